@@ -1,0 +1,212 @@
+"""Benchmark: GMRES + MRCM-OS solves per second on one MI355X.
+
+A step is one solve of A p = b to a true FP64 relative residual of 1e-8 with
+right-preconditioned GMRES(10) and the MRCM-OS operator, the operator's
+factorisations resident in HBM (setup excluded from the timed region and
+reported separately).  Every step runs the whole hot path: local Robin
+solves with trace moments, interface solve, reconstruction, smoothing
+residual and patch solves, output projection, the fine operator, Gram-Schmidt
+and the solution update.
+
+Prints one JSON line (rank 0).  Besides the contract keys it carries the
+roofline of the dominant kernel (measured live with HIP events on the
+library's stream), the oracle timed on the host cores on a bounded sample,
+cell-DOF/s, p50/p99 latency of the timed solves and setup-inclusive
+throughput.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+
+def algorithmic_bytes(cfg, maps, word: int) -> dict:
+    """Algorithmic bytes of one launch of the local and patch kernels.
+
+    Local solve of subdomain i (bx x by cells): the D_j^-1 blocks (by bx^2
+    words) and couplings (by bx words) read once, r read (8 B/cell, FP64), p
+    written (word/cell), trace-moment weights read (2 x 8 B per face of every
+    dof) and moments written (16 B per dof).
+    Patch solve of patch i (px x py cells, owned bx x by): factor and
+    couplings read once, the residual read on the patch (word/cell), p read
+    and written on the owned cells (2 words/cell).
+    """
+    b = maps["boxes"]
+    bx = (b[:, 1] - b[:, 0]).astype(np.int64)
+    by = (b[:, 3] - b[:, 2]).astype(np.int64)
+    local = int(np.sum(by * bx * bx * word + by * bx * word + by * bx * 8 + by * bx * word))
+    dofs = maps["dof_table"]
+    sides = dofs[:, 1]
+    lens = np.where(sides <= 1, by[dofs[:, 0]], bx[dofs[:, 0]])
+    local += int(np.sum(lens) * 16 + len(dofs) * 16)
+    p = maps["pboxes"]
+    px = (p[:, 1] - p[:, 0]).astype(np.int64)
+    py = (p[:, 3] - p[:, 2]).astype(np.int64)
+    patch = int(np.sum(py * px * px * word + py * px * word + py * px * word + 2 * bx * by * word))
+    return {"local": local, "patch": patch}
+
+
+def cpu_baseline(workload_name: str, gpu_iterations: int, budget_s: float = 25.0) -> dict:
+    """Time the oracle (as it stands) on the host: its setup for the same
+    workload, then GMRES inner steps until the budget is spent; the solve
+    time is the mean inner-step time times the iterations of one solve."""
+    code = r"""
+import json, sys, time
+import numpy as np
+sys.path.insert(0, %r)
+from oracle.mrcm import MRCM
+from oracle.gmres import gmres
+from paper_2606_08883_amd.configs import WORKLOADS
+w = WORKLOADS[%r]
+K = w.permeability()
+t0 = time.perf_counter()
+mr = MRCM(K, **w.oracle_args())
+t_setup = time.perf_counter() - t0
+b = w.rhs()
+steps = 0
+t0 = time.perf_counter()
+while True:
+    res = gmres(lambda x: mr.A @ x, mr.apply, b, rtol=1e-8, restart=10, maxit=2)
+    steps += res.iterations
+    if time.perf_counter() - t0 > %f:
+        break
+t_step = (time.perf_counter() - t0) / steps
+print(json.dumps({"setup_s": t_setup, "step_s": t_step, "steps": steps}))
+""" % (ROOT, workload_name, budget_s)
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        env[k] = "1"
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                         timeout=900)
+    if out.returncode != 0:
+        raise RuntimeError(out.stderr[-2000:])
+    d = json.loads(out.stdout.strip().splitlines()[-1])
+    solve_s = d["step_s"] * gpu_iterations
+    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle setup ({d['setup_s']:.1f} s, excluded) then {d['steps']} GMRES "
+                       f"inner steps (T apply + A apply + MGS) of the same workload in "
+                       f"{budget_s:.0f} s; solve time = mean step time "
+                       f"({d['step_s'] * 1e3:.1f} ms) x {gpu_iterations} steps per solve")}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batched",
+                    choices=["small", "channel", "batched", "large"])
+    ap.add_argument("--precision", type=int, default=None, help="0 FP64 apply, 1 FP32 apply")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_2606_08883_amd import binding as B
+    from paper_2606_08883_amd.configs import WORKLOADS
+
+    w = WORKLOADS[args.workload]
+    if args.precision is not None:
+        w = w.with_(precision=args.precision)
+    dev = torch.device("cuda:0")
+    K = torch.tensor(w.permeability(), dtype=torch.float64, device=dev)
+    b = torch.tensor(w.rhs(), dtype=torch.float64, device=dev)
+    p = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    print(f"bench: workload {w.name} {w.nx}x{w.ny} precision {w.precision}", file=sys.stderr,
+          flush=True)
+    t0 = time.perf_counter()
+    ctx = B.Context(w.binding_config(), K)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    print(f"bench: setup {setup_s:.2f} s", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        st = ctx.gmres(b, p, rtol=1e-8, restart=10, maxit=500)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    lat = []
+    its = []
+    relres = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        t1 = time.perf_counter()
+        st = ctx.gmres(b, p, rtol=1e-8, restart=10, maxit=500)
+        lat.append(time.perf_counter() - t1)
+        its.append(st.iterations)
+        relres.append(st.final_relres)
+        if not st.converged:
+            raise RuntimeError("GMRES did not converge")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    phases = ctx.timing_read()
+    ctx.timing(False)
+    n = w.cells
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = args.steps / elapsed
+    maps = B.maps(w.binding_config())
+    word = 4 if w.precision == 1 else 8
+    abytes = algorithmic_bytes(w, maps, word)
+    # dominant kernel = the phase with the largest accumulated device time
+    dom = max(("local", "patch"), key=lambda k: phases[k][0])
+    avg_ms = phases[dom][0] / max(1, phases[dom][1])
+    achieved = abytes[dom] / (avg_ms * 1e-3) / 1e9
+    apply_ms = sum(v[0] for v in phases.values()) / max(1, phases["local"][1])
+    out = {
+        "metric": "GMRES+MRCM-OS solves/s & cell-DOF/s at rel.res 1e-8; p50/p99 solve latency",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if w.precision == 1 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.nx}x{w.ny} cells, {maps['boxes'].shape[0]} "
+                               f"subdomains of {w.s}x{w.s}, oversampling {w.oversample}, "
+                               f"{w.sweeps} smoothing sweep(s), overlap {w.overlap}, "
+                               f"alpha {w.alpha}, field {w.field}, no-flow, corner sources",
+                   "cells": n, "precision": "fp32 apply / fp64 krylov" if w.precision else "fp64",
+                   "rtol": 1e-8, "restart": 10, "parallelism": "single GPU"},
+        "cell_dof_per_s": value * n,
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                       "p99": float(np.percentile(lat, 99) * 1e3)},
+        "iterations_per_solve": float(np.mean(its)),
+        "final_relres_max": float(np.max(relres)),
+        "setup_s": setup_s,
+        "solves_per_s_incl_setup": 1.0 / (setup_s + elapsed / args.steps),
+        "apply_ms": apply_ms,
+        "phase_ms_per_launch": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in phases.items()},
+        "roofline": {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_bytes_per_launch": abytes[dom],
+                     "avg_launch_ms": avg_ms},
+    }
+    if not args.no_cpu_baseline:
+        print("bench: timing the oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w.name, int(round(np.mean(its))))
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,185 @@
+/*
+ * mrcm.h -- C ABI of the MI355X (gfx950) library for GMRES with the
+ * matrix-free MRCM-OS right preconditioner on 2-D Darcy pressure problems.
+ *
+ * Problem (Section 2, eqs. (1a)-(1d)): u = -K grad p, div u = f on a
+ * rectangle covered by nx x ny square cells; each side is either no-flow or
+ * Dirichlet.  The fine system A p = b (Section 3) is the lowest-order
+ * Raviart-Thomas discretisation with vertex-quadrature mass lumping,
+ * condensed to the cell-centred five-point stencil with harmonic-mean face
+ * permeability.  T (Section 3, the modified MRCM-O with source r and
+ * homogeneous boundary data) is the MRCM-OS operator of Section 2.1:
+ * Robin local solves on the non-overlapping subdomains, informed multiplier
+ * spaces from oversampled problems, weak flux / pressure continuity (eqs.
+ * (13)-(14)) through a small interface system, then overlapping-Schwarz
+ * smoothing sweeps.  gmres_solve is the right-preconditioned restarted GMRES
+ * of Algorithm 1.
+ *
+ * Conventions shared by every entry point:
+ *  - cell (ix, iy) has id iy * nx + ix (x fastest); cell (0,0) touches the
+ *    corner x = 0, y = 0;
+ *  - every vector argument is float64; a multi-RHS vector is nrhs
+ *    consecutive vectors of length nx * ny ([nrhs][n]);
+ *  - "device" pointers are HIP device memory owned by the caller; "host"
+ *    pointers are ordinary host memory owned by the caller;
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream); all
+ *    device work of a call is ordered on it;
+ *  - a context is not thread-safe; distinct contexts may be used
+ *    concurrently from different threads and streams;
+ *  - every function returning int returns 0 on success or a negative MRCM_E*
+ *    code; the message of the last failure of the calling thread is returned
+ *    by mrcm_last_error().  No C++ exception crosses this interface.
+ */
+#ifndef MRCM_H
+#define MRCM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MRCM_OK = 0,
+  MRCM_EINVAL = -1,    /* bad sizes or parameters, K not finite or not > 0 */
+  MRCM_ENOMEM = -2,    /* host or device allocation failed */
+  MRCM_ESINGULAR = -3, /* non-positive pivot in a local factorisation, or a
+                          singular block of the interface system */
+  MRCM_ENOCONV = -4,   /* gmres_solve reached maxit; p and stats are written */
+  MRCM_EDEVICE = -5    /* a HIP runtime call failed */
+};
+
+/* Fine grid.  bc[side] for side W (x = 0), E, S (y = 0), N:
+ * 0 = no-flow (u.n = 0), 1 = Dirichlet (p = g).  With no-flow on all four
+ * sides A is singular (constants) and every result is projected to zero
+ * mean. */
+typedef struct {
+  int32_t nx, ny;
+  int32_t bc[4];
+} mrcm_grid;
+
+/* Method parameters (Section 2.1 and Section 4, Table 1).
+ *  sx, sy          subdomain size in cells (last column/row narrower when it
+ *                  does not divide the grid);
+ *  oversample      l: hat-Omega_i = Omega_i grown by l cells, clipped; must not
+ *                  reach the domain boundary across an interior side;
+ *  alpha           Robin parameter, beta = alpha * L / K_H (Section 2.1);
+ *  beta_len        0: L = H = max(sx, sy) cells; 1: L = h (one cell);
+ *  smooth_sweeps   k smoothing sweeps (restricted additive Schwarz);
+ *  smooth_overlap  delta: smoothing patch = Omega_i grown by delta, clipped;
+ *  iface_degree    d >= 0: Legendre P_0..P_d per interface side;
+ *  precision       0: FP64 preconditioner apply; 1: local and smoothing
+ *                  solves applied in FP32 (factors computed in FP64), coarse
+ *                  solve and GMRES in FP64. */
+typedef struct {
+  int32_t sx, sy;
+  int32_t oversample;
+  double alpha;
+  int32_t beta_len;
+  int32_t smooth_sweeps;
+  int32_t smooth_overlap;
+  int32_t iface_degree;
+  int32_t precision;
+} mrcm_params;
+
+/* GMRES statistics, host memory owned by the caller.  est_hist / true_hist
+ * may be NULL; otherwise they hold hist_cap doubles each. */
+typedef struct {
+  int32_t iterations;   /* inner steps = applications of T (all RHS summed) */
+  int32_t cycles;       /* restart cycles started (all RHS summed) */
+  int32_t converged;    /* 1 when every RHS met the tolerance */
+  int32_t hist_cap;     /* in: capacity of the history arrays */
+  int32_t hist_len;     /* out: entries written to est_hist (first RHS) */
+  int32_t true_len;     /* out: entries written to true_hist (first RHS) */
+  double final_relres;  /* max over RHS of the true ||b - A p|| / ||b|| */
+  double* est_hist;     /* estimated relative residual after each inner step */
+  double* true_hist;    /* true relative residual at the start and end of each cycle */
+} mrcm_stats;
+
+typedef struct mrcm_ctx mrcm_ctx;
+
+/* Index-map sizes for (grid, params): m subdomains, E interior edges and nc
+ * coarse dofs (= coarse rows).  Host only; no device is touched. */
+int mrcm_map_sizes(const mrcm_grid* grid, const mrcm_params* params,
+                   int64_t* m, int64_t* n_edges, int64_t* nc);
+
+/* Decomposition maps (Section 2.1: Omega_i, Gamma_i, hat-Omega_i, and the
+ * smoothing patches), written to caller-owned host arrays:
+ *  owner[n]           subdomain id of every cell;
+ *  boxes[4m]          (x0, x1, y0, y1) of Omega_i, half-open;
+ *  oboxes[4m]         hat-Omega_i; pboxes[4m] smoothing patches;
+ *  edges[5E]          (L, R, orientation 0 vertical / 1 horizontal, start, length);
+ *  dof_table[3nc]     (subdomain, side W0 E1 S2 N3, q) of every coarse dof;
+ *  dof_offset[m+1]    first coarse dof of every subdomain;
+ *  row_table[3nc]     (edge, 0 flux / 1 pressure, q) of every coarse row.
+ * Host only; any pointer may be NULL to skip that map. */
+int mrcm_maps(const mrcm_grid* grid, const mrcm_params* params, int32_t* owner,
+              int32_t* boxes, int32_t* oboxes, int32_t* pboxes, int32_t* edges,
+              int32_t* dof_table, int32_t* dof_offset, int32_t* row_table);
+
+/* Set up T for one permeability field (Section 2.1, steps one to three of
+ * the MRCM-OS algorithm: decomposition, multiplier spaces from the
+ * oversampled problems, multiscale basis functions and the interface system;
+ * plus the smoothing-patch factorisations).  K_dev: device, n float64 cell
+ * permeabilities (read once; the context keeps no reference).  Factorisations
+ * are computed in FP64 and kept resident in device memory owned by the
+ * context.  On success *out receives the new context. */
+int mrcm_setup(const mrcm_grid* grid, const mrcm_params* params, const double* K_dev,
+               void* stream, mrcm_ctx** out);
+
+/* z = T r for nrhs vectors (Section 3: source r, homogeneous boundary data,
+ * then the smoothing sweeps).  r, z: device [nrhs][n]; may not alias. */
+int mrcm_apply(mrcm_ctx* ctx, const double* r, double* z, int32_t nrhs, void* stream);
+
+/* y = A x for nrhs vectors (Section 3, the condensed fine operator).
+ * x, y: device [nrhs][n]; may not alias. */
+int op_apply(mrcm_ctx* ctx, const double* x, double* y, int32_t nrhs, void* stream);
+
+/* Solve A p = b with right-preconditioned restarted GMRES (Algorithm 1):
+ * p_0 = 0, Krylov dimension `restart`, modified Gram-Schmidt, stored z_j.
+ * Stops an inner cycle when the estimated residual is <= rtol * ||b|| (tested
+ * after every step) and finishes when the true FP64 residual ||b - A p|| is
+ * <= rtol * ||b||.  maxit bounds the number of applications of T per RHS.
+ * b, p: device [nrhs][n]; st: host, may be NULL.  Returns MRCM_ENOCONV
+ * (p and st written) when maxit is reached. */
+int gmres_solve(mrcm_ctx* ctx, const double* b, double* p, int32_t nrhs, double rtol,
+                int32_t restart, int32_t maxit, mrcm_stats* st, void* stream);
+
+/* Right-hand side of the fine system (Section 3): b = f h^2 plus 2 K_c g on
+ * every Dirichlet boundary face.  f_cell: device n values or NULL (zero
+ * source); g_bc: device, the Dirichlet values of the W, E, S, N sides
+ * concatenated (ny, ny, nx, nx values, each in increasing coordinate; entries
+ * of no-flow sides are ignored) or NULL; h: cell size; b: device n. */
+int mrcm_rhs(mrcm_ctx* ctx, const double* f_cell, const double* g_bc, double h, double* b,
+             void* stream);
+
+/* Device bytes a context for (grid, params) keeps resident, plus the work
+ * space of nrhs simultaneous right-hand sides (admission control). */
+size_t mrcm_footprint(const mrcm_grid* grid, const mrcm_params* params, int32_t nrhs);
+
+/* Per-phase device timing of the preconditioner apply (Section 2.1, the
+ * steps of one MRCM-OS application), measured with HIP events recorded on the
+ * stream of each call.  on = 1 starts (and clears) the accumulation, 0 stops
+ * it.  Phases: 0 local Robin solves with trace moments, 1 interface
+ * right-hand side and interface solve, 2 multiscale reconstruction,
+ * 3 smoothing residual, 4 smoothing patch solves, 5 output (and zero-mean
+ * projection). */
+int mrcm_timing_enable(mrcm_ctx* ctx, int32_t on);
+
+/* Accumulated device milliseconds and event-pair counts of every phase since
+ * mrcm_timing_enable(ctx, 1): ms[6], counts[6], host.  Waits for the recorded
+ * events. */
+int mrcm_timing_read(mrcm_ctx* ctx, double* ms, int64_t* counts);
+
+/* Release a context and all device memory it owns (NULL is ignored). */
+void mrcm_destroy(mrcm_ctx* ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* mrcm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MRCM_H */

@@ -1,0 +1,40 @@
+/*
+ * mrcm_testing.h -- test hooks of the host-side FP64 setup.
+ *
+ * For the test suite only (callers that check the setup arithmetic on a
+ * machine without a GPU).  These functions are not a solver path: no entry
+ * point of mrcm.h calls them, and they take and return host memory only.
+ * Each call runs the whole FP64 setup again.  Error behaviour as in mrcm.h.
+ */
+#ifndef MRCM_TESTING_H
+#define MRCM_TESTING_H
+
+#include <stdint.h>
+
+#include "mrcm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Sizes of the interface system for (grid, params, K): nc and nnz of C. */
+int mrcm_test_coarse_sizes(const mrcm_grid* grid, const mrcm_params* params, const double* K,
+                           int64_t* nc, int64_t* nnz);
+
+/* The interface matrix C in CSR (rows x coarse dofs, row replacement for
+ * all-no-flow grids applied): rp[nc+1], ci[nnz], cv[nnz], host. */
+int mrcm_test_coarse_matrix(const mrcm_grid* grid, const mrcm_params* params, const double* K,
+                            int32_t* rp, int32_t* ci, double* cv);
+
+/* z = T r evaluated on the host from the exact data layout that mrcm_setup
+ * uploads (box factors, trace-moment weights, nested-dissection coarse
+ * factor, multiscale basis functions, patch factors).  r, z: host, n values.
+ * Also returns the smallest pivot ratio of the coarse factorisation. */
+int mrcm_test_host_apply(const mrcm_grid* grid, const mrcm_params* params, const double* K,
+                         const double* r, double* z, double* min_pivot_ratio);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MRCM_TESTING_H */

@@ -1,0 +1,279 @@
+"""ctypes binding of ``libmrcm.so`` (include/mrcm.h).
+
+Argument marshalling only: every step of setup, apply and GMRES runs in the
+library.  Device vectors are torch CUDA (HIP) float64 tensors; the stream is
+torch's current stream unless one is given.  There is no fallback: when the
+library is missing every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmrcm.so")
+
+MRCM_OK, MRCM_EINVAL, MRCM_ENOMEM, MRCM_ESINGULAR, MRCM_ENOCONV, MRCM_EDEVICE = 0, -1, -2, -3, -4, -5
+_NAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "ESINGULAR", -4: "ENOCONV", -5: "EDEVICE"}
+
+# Every symbol the headers declare (checked by the test suite).
+EXPORTED = ["mrcm_map_sizes", "mrcm_maps", "mrcm_setup", "mrcm_apply", "op_apply", "gmres_solve",
+            "mrcm_rhs", "mrcm_footprint", "mrcm_timing_enable", "mrcm_timing_read",
+            "mrcm_destroy", "mrcm_last_error"]
+PHASES = ["local", "coarse", "reconstruct", "residual", "patch", "finalize"]
+TEST_EXPORTED = ["mrcm_test_coarse_sizes", "mrcm_test_coarse_matrix", "mrcm_test_host_apply"]
+
+
+class MrcmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"MRCM_{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("bc", ctypes.c_int32 * 4)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("sx", ctypes.c_int32), ("sy", ctypes.c_int32), ("oversample", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("beta_len", ctypes.c_int32),
+                ("smooth_sweeps", ctypes.c_int32), ("smooth_overlap", ctypes.c_int32),
+                ("iface_degree", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("cycles", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("hist_cap", ctypes.c_int32),
+                ("hist_len", ctypes.c_int32), ("true_len", ctypes.c_int32),
+                ("final_relres", ctypes.c_double), ("est_hist", ctypes.POINTER(ctypes.c_double)),
+                ("true_hist", ctypes.POINTER(ctypes.c_double))]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        pG, pP = ctypes.POINTER(Grid), ctypes.POINTER(Params)
+        pi32 = ctypes.POINTER(ctypes.c_int32)
+        pi64 = ctypes.POINTER(ctypes.c_int64)
+        pd = ctypes.POINTER(ctypes.c_double)
+        sig = {
+            "mrcm_map_sizes": ([pG, pP, pi64, pi64, pi64], i32),
+            "mrcm_maps": ([pG, pP] + [pi32] * 8, i32),
+            "mrcm_setup": ([pG, pP, P, P, ctypes.POINTER(P)], i32),
+            "mrcm_apply": ([P, P, P, i32, P], i32),
+            "op_apply": ([P, P, P, i32, P], i32),
+            "gmres_solve": ([P, P, P, i32, dbl, i32, i32, ctypes.POINTER(Stats), P], i32),
+            "mrcm_rhs": ([P, P, P, dbl, P, P], i32),
+            "mrcm_footprint": ([pG, pP, i32], ctypes.c_size_t),
+            "mrcm_timing_enable": ([P, i32], i32),
+            "mrcm_timing_read": ([P, pd, pi64], i32),
+            "mrcm_destroy": ([P], None),
+            "mrcm_last_error": ([], ctypes.c_char_p),
+            "mrcm_test_coarse_sizes": ([pG, pP, pd, pi64, pi64], i32),
+            "mrcm_test_coarse_matrix": ([pG, pP, pd, pi32, pi32, pd], i32),
+            "mrcm_test_host_apply": ([pG, pP, pd, pd, pd, pd], i32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != MRCM_OK:
+        raise MrcmError(code, lib().mrcm_last_error().decode())
+
+
+@dataclass
+class Config:
+    """Grid and method parameters (see include/mrcm.h)."""
+    nx: int
+    ny: int
+    bc: tuple = (0, 0, 0, 0)
+    sx: int = 16
+    sy: int = 16
+    oversample: int = 0
+    alpha: float = 10.0
+    beta_len: int = 0
+    smooth_sweeps: int = 0
+    smooth_overlap: int = 2
+    iface_degree: int = 1
+    precision: int = 0
+
+    def grid(self) -> Grid:
+        return Grid(self.nx, self.ny, (ctypes.c_int32 * 4)(*self.bc))
+
+    def params(self) -> Params:
+        return Params(self.sx, self.sy, self.oversample, self.alpha, self.beta_len,
+                      self.smooth_sweeps, self.smooth_overlap, self.iface_degree, self.precision)
+
+
+def _i32(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _f64(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def map_sizes(cfg: Config):
+    m, e, nc = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    g, p = cfg.grid(), cfg.params()
+    _check(lib().mrcm_map_sizes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(m),
+                                ctypes.byref(e), ctypes.byref(nc)))
+    return m.value, e.value, nc.value
+
+
+def maps(cfg: Config) -> dict:
+    m, e, nc = map_sizes(cfg)
+    out = {"owner": np.zeros(cfg.nx * cfg.ny, np.int32), "boxes": np.zeros((m, 4), np.int32),
+           "oboxes": np.zeros((m, 4), np.int32), "pboxes": np.zeros((m, 4), np.int32),
+           "edges": np.zeros((e, 5), np.int32), "dof_table": np.zeros((nc, 3), np.int32),
+           "dof_offset": np.zeros(m + 1, np.int32), "row_table": np.zeros((nc, 3), np.int32)}
+    g, p = cfg.grid(), cfg.params()
+    _check(lib().mrcm_maps(ctypes.byref(g), ctypes.byref(p), _i32(out["owner"]),
+                           _i32(out["boxes"]), _i32(out["oboxes"]), _i32(out["pboxes"]),
+                           _i32(out["edges"]), _i32(out["dof_table"]), _i32(out["dof_offset"]),
+                           _i32(out["row_table"])))
+    return out
+
+
+def footprint(cfg: Config, nrhs: int = 1) -> int:
+    g, p = cfg.grid(), cfg.params()
+    return int(lib().mrcm_footprint(ctypes.byref(g), ctypes.byref(p), nrhs))
+
+
+# ---- test hooks of the host setup (host memory) ------------------------------
+def test_coarse_matrix(cfg: Config, K: np.ndarray):
+    import scipy.sparse as sp
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    g, p = cfg.grid(), cfg.params()
+    nc, nnz = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().mrcm_test_coarse_sizes(ctypes.byref(g), ctypes.byref(p), _f64(K),
+                                        ctypes.byref(nc), ctypes.byref(nnz)))
+    rp = np.zeros(nc.value + 1, np.int32)
+    ci = np.zeros(max(nnz.value, 1), np.int32)
+    cv = np.zeros(max(nnz.value, 1), np.float64)
+    _check(lib().mrcm_test_coarse_matrix(ctypes.byref(g), ctypes.byref(p), _f64(K), _i32(rp),
+                                         _i32(ci), _f64(cv)))
+    return sp.csr_matrix((cv[:nnz.value], ci[:nnz.value], rp), shape=(nc.value, nc.value))
+
+
+def test_host_apply(cfg: Config, K: np.ndarray, r: np.ndarray):
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    z = np.zeros_like(r)
+    piv = ctypes.c_double()
+    g, p = cfg.grid(), cfg.params()
+    _check(lib().mrcm_test_host_apply(ctypes.byref(g), ctypes.byref(p), _f64(K), _f64(r), _f64(z),
+                                      ctypes.byref(piv)))
+    return z, piv.value
+
+
+# ---- device entry points --------------------------------------------------------
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t, n_expected: int | None = None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 \
+            or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 device tensor")
+    if n_expected is not None and t.numel() != n_expected:
+        raise ValueError(f"expected {n_expected} values, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class SolveStats:
+    iterations: int
+    cycles: int
+    converged: bool
+    final_relres: float
+    est_history: list
+    true_history: list
+
+
+class Context:
+    """A set-up MRCM-OS operator for one permeability field (mrcm_setup)."""
+
+    def __init__(self, cfg: Config, K, stream=None):
+        self.cfg = cfg
+        self.n = cfg.nx * cfg.ny
+        self._ptr = ctypes.c_void_p()
+        self._g, self._p = cfg.grid(), cfg.params()
+        _check(lib().mrcm_setup(ctypes.byref(self._g), ctypes.byref(self._p),
+                                _dptr(K, self.n), _stream(stream), ctypes.byref(self._ptr)))
+
+    def close(self):
+        if self._ptr:
+            lib().mrcm_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _nrhs(self, t) -> int:
+        if t.numel() % self.n:
+            raise ValueError("vector length is not a multiple of the cell count")
+        return t.numel() // self.n
+
+    def timing(self, on: bool):
+        """Start (and clear) or stop per-phase event timing (mrcm_timing_enable)."""
+        _check(lib().mrcm_timing_enable(self._ptr, 1 if on else 0))
+
+    def timing_read(self) -> dict:
+        """{phase: (total device ms, launches)} since timing(True)."""
+        ms = (ctypes.c_double * 6)()
+        cnt = (ctypes.c_int64 * 6)()
+        _check(lib().mrcm_timing_read(self._ptr, ms, cnt))
+        return {PHASES[k]: (ms[k], cnt[k]) for k in range(6)}
+
+    def apply(self, r, z, stream=None):
+        """z = T r (mrcm_apply)."""
+        k = self._nrhs(r)
+        _check(lib().mrcm_apply(self._ptr, _dptr(r), _dptr(z, r.numel()), k, _stream(stream)))
+
+    def op(self, x, y, stream=None):
+        """y = A x (op_apply)."""
+        k = self._nrhs(x)
+        _check(lib().op_apply(self._ptr, _dptr(x), _dptr(y, x.numel()), k, _stream(stream)))
+
+    def rhs(self, f, g_bc, h: float, b, stream=None):
+        _check(lib().mrcm_rhs(self._ptr, None if f is None else _dptr(f, self.n),
+                              None if g_bc is None else _dptr(g_bc), h, _dptr(b, self.n),
+                              _stream(stream)))
+
+    def gmres(self, b, p, rtol: float = 1e-8, restart: int = 10, maxit: int = 300,
+              stream=None, raise_on_noconv: bool = True) -> SolveStats:
+        """Solve A p = b (gmres_solve)."""
+        k = self._nrhs(b)
+        cap = max(1, maxit * 2 + 8)
+        est = (ctypes.c_double * cap)()
+        tru = (ctypes.c_double * cap)()
+        st = Stats(0, 0, 0, cap, 0, 0, 0.0, est, tru)
+        code = lib().gmres_solve(self._ptr, _dptr(b), _dptr(p, b.numel()), k, rtol, restart,
+                                 maxit, ctypes.byref(st), _stream(stream))
+        if code != MRCM_OK and (code != MRCM_ENOCONV or raise_on_noconv):
+            _check(code)
+        return SolveStats(st.iterations, st.cycles, bool(st.converged), st.final_relres,
+                          list(est[:st.hist_len]), list(tru[:st.true_len]))

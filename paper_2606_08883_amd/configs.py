@@ -1,0 +1,87 @@
+"""Synthetic workloads (stand-ins for the paper's experiments; see workloads.py).
+
+Every workload: no-flow on all four sides with the pressure fixed by its mean,
+a point injector +1 in cell (0, 0) and a producer -1 in the last cell, GMRES
+restart 10 and relative tolerance 1e-8, interface degree 1, smoothing overlap
+2.  Field recipes and seeds:
+
+* small   64 x 64, log-normal K (sigma 2, correlation 8, seed 1), 4 x 4
+          subdomains of 16 x 16, oversampling 2, alpha 1 with L = h, one
+          smoothing sweep; FP64.
+* channel 220 x 60 channelised facies (Gaussian threshold, correlation 20 x 3
+          cells, seed 2; K = 1 in channels, 1e-6 in shale), 11 x 3 subdomains
+          of 20 x 20 (the shape of the paper's SPE10 layers), alpha 10 with
+          L = H, oversampling in {0, 2, 4}, sweeps in {0, 1, 2}; FP64.
+* batched 1024 x 1024, log-normal K (sigma 3, correlation 16, seed 3), 4096
+          subdomains of 16 x 16, oversampling 4, one sweep, alpha 10, L = H;
+          FP32 local and smoothing apply, FP64 factorisation and GMRES.
+* large   4096 x 4096 (16.8 M cells), channel / log-normal mixture with
+          contrast 1e8 (seeds 5, 6), 16384 subdomains of 32 x 32, oversampling
+          4, two sweeps, alpha 10, L = H; FP32 and FP64 apply.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, replace
+
+import numpy as np
+
+from . import workloads as wl
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    s: int
+    oversample: int
+    alpha: float
+    beta_len: int  # 0: L = H, 1: L = h
+    sweeps: int
+    overlap: int
+    degree: int
+    precision: int
+    field: str
+    bc: tuple = (0, 0, 0, 0)
+
+    def permeability(self) -> np.ndarray:
+        if self.field == "small":
+            return wl.lognormal_K(self.nx, self.ny, 2.0, 8.0, 1)
+        if self.field == "channel":
+            return wl.channel_K(self.nx, self.ny, 20.0, 3.0, 2)
+        if self.field == "batched":
+            return wl.lognormal_K(self.nx, self.ny, 3.0, 16.0, 3)
+        if self.field == "large":
+            return wl.mixture_K(self.nx, self.ny, 5, 6)
+        raise ValueError(self.field)
+
+    def rhs(self) -> np.ndarray:
+        return wl.corner_sources(self.nx, self.ny)
+
+    def with_(self, **kw) -> "Workload":
+        return replace(self, **kw)
+
+    def binding_config(self):
+        from .binding import Config
+        return Config(self.nx, self.ny, tuple(self.bc), self.s, self.s, self.oversample,
+                      self.alpha, self.beta_len, self.sweeps, self.overlap, self.degree,
+                      self.precision)
+
+    def oracle_args(self):
+        """Positional/keyword arguments of oracle.mrcm.MRCM (without K)."""
+        return dict(nx=self.nx, ny=self.ny, bc=tuple(self.bc), sx=self.s, sy=self.s,
+                    oversample=self.oversample, alpha=self.alpha,
+                    beta_len="h" if self.beta_len else "H", sweeps=self.sweeps,
+                    overlap=self.overlap, degree=self.degree)
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny
+
+
+WORKLOADS = {
+    "small": Workload("small", 64, 64, 16, 2, 1.0, 1, 1, 2, 1, 0, "small"),
+    "channel": Workload("channel", 220, 60, 20, 2, 10.0, 0, 1, 2, 1, 0, "channel"),
+    "batched": Workload("batched", 1024, 1024, 16, 4, 10.0, 0, 1, 2, 1, 1, "batched"),
+    "large": Workload("large", 4096, 4096, 32, 4, 10.0, 0, 2, 2, 1, 1, "large"),
+}

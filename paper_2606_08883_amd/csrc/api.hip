@@ -1,0 +1,723 @@
+// C ABI of the library (include/mrcm.h): context life cycle, setup (FP64 host
+// factorisations uploaded to HBM), the preconditioner apply, the fine operator,
+// and the host-driven GMRES loop of Algorithm 1 with device-resident Krylov
+// vectors.
+#include <hip/hip_runtime.h>
+#include <omp.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "coarse.h"
+#include "device.h"
+#include "internal.h"
+#include "setup.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string& m) { g_last_error = m; }
+
+}  // namespace
+
+namespace mrcm {
+void set_last_error(const std::string& msg) { set_error(msg); }
+}  // namespace mrcm
+
+namespace {
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess)
+    throw mrcm::Error(e == hipErrorOutOfMemory ? MRCM_ENOMEM : MRCM_EDEVICE,
+                      std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int host_threads() {
+  int t = omp_get_max_threads();
+  return t < 1 ? 1 : t;
+}
+
+}  // namespace
+
+struct mrcm_ctx {
+  int nx = 0, ny = 0, bc[4] = {0, 0, 0, 0}, noflow = 0, precision = 0, sweeps = 0;
+  int m = 0, nc = 0, pin_row = -1;
+  long long n = 0;
+  int max_cells_local = 0, max_cells_patch = 0;
+  int max_nf = 0, max_nu = 0;
+  std::vector<void*> allocs;
+  // fine operator
+  double *tx = nullptr, *ty = nullptr;
+  void *txT = nullptr, *tyT = nullptr;  // compute-precision copies (aliases in FP64 mode)
+  int* d_bc = nullptr;
+  // local and patch factors
+  mrcm::BoxDesc *lbox = nullptr, *pbox = nullptr;
+  void *ldinv = nullptr, *lcoup = nullptr, *pdinv = nullptr, *pcoup = nullptr;
+  void* mbf = nullptr;
+  long long* mbf_off = nullptr;
+  int *dof_off = nullptr, *dof_side = nullptr, *w_off = nullptr;
+  double *wU = nullptr, *wP = nullptr;
+  int *rowL = nullptr, *rowR = nullptr, *rowKind = nullptr;
+  // coarse factor
+  mrcm::CNodeDesc* cnodes = nullptr;
+  double *cfwd = nullptr, *cbwd = nullptr;
+  int *cidx = nullptr, *pull_ptr = nullptr, *pull_idx = nullptr;
+  mrcm::CChunk* chunks = nullptr;
+  std::vector<std::pair<int, int>> fwd_levels, bwd_levels;  // (first chunk, count)
+  // work space
+  void *pT = nullptr, *rhoT = nullptr;
+  double *mU = nullptr, *mP = nullptr, *g = nullptr, *xc = nullptr, *ybuf = nullptr,
+         *cbuf = nullptr, *partials = nullptr;
+  // GMRES
+  int krylov_cap = 0;
+  double *V = nullptr, *Z = nullptr, *hcol = nullptr, *parts = nullptr, *yd = nullptr;
+  double *h_host = nullptr;  // pinned: partials / Hessenberg column / y
+  double setup_seconds = 0.0;
+  // per-phase event timing
+  static constexpr int kPhases = 6;
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, std::pair<size_t, size_t>>> ev_marks;  // phase, (start, end)
+  double phase_ms[kPhases] = {0, 0, 0, 0, 0, 0};
+  long long phase_n[kPhases] = {0, 0, 0, 0, 0, 0};
+
+  template <typename X>
+  X* alloc(size_t count) {
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    hip_check(hipMalloc(&p, count * sizeof(X)), "hipMalloc");
+    allocs.push_back(p);
+    return static_cast<X*>(p);
+  }
+  template <typename X>
+  X* upload(const std::vector<X>& v, hipStream_t s) {
+    X* d = alloc<X>(v.size());
+    if (!v.empty())
+      hip_check(hipMemcpyAsync(d, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice, s),
+                "hipMemcpyAsync");
+    return d;
+  }
+  // Record an event on stream s; returns its pool index.
+  size_t mark(hipStream_t s) {
+    if (ev_used == ev_pool.size()) {
+      hipEvent_t e;
+      hip_check(hipEventCreate(&e), "hipEventCreate");
+      ev_pool.push_back(e);
+    }
+    hip_check(hipEventRecord(ev_pool[ev_used], s), "hipEventRecord");
+    return ev_used++;
+  }
+  // Fold the elapsed times of completed event pairs into the accumulators.
+  void fold_timing() {
+    for (const auto& m : ev_marks) {
+      float ms = 0.0f;
+      hip_check(hipEventSynchronize(ev_pool[m.second.second]), "hipEventSynchronize");
+      hip_check(hipEventElapsedTime(&ms, ev_pool[m.second.first], ev_pool[m.second.second]),
+                "hipEventElapsedTime");
+      phase_ms[m.first] += ms;
+      phase_n[m.first] += 1;
+    }
+    ev_marks.clear();
+    ev_used = 0;
+  }
+  ~mrcm_ctx() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    for (void* p : allocs) (void)hipFree(p);
+    if (h_host) (void)hipHostFree(h_host);
+  }
+};
+
+namespace {
+
+using mrcm::BoxDesc;
+using mrcm::CChunk;
+using mrcm::CNodeDesc;
+
+template <typename T>
+std::vector<T> narrow(const std::vector<double>& v) {
+  std::vector<T> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = (T)v[i];
+  return o;
+}
+
+// Upload a set of box factors in precision T.
+template <typename T>
+void upload_boxes(mrcm_ctx* c, const std::vector<mrcm::BoxFactor>& F,
+                  const std::vector<mrcm::Box>& owned, BoxDesc** desc, void** dinv, void** coup,
+                  int* max_cells, hipStream_t s) {
+  std::vector<BoxDesc> d(F.size());
+  long long nd = 0, ncp = 0;
+  int mc = 0;
+  for (size_t i = 0; i < F.size(); ++i) {
+    const mrcm::Box& b = F[i].box;
+    const mrcm::Box& o = owned[i];
+    d[i] = BoxDesc{b.x0, b.y0, b.bx(), b.by(), F[i].pin, o.x0 - b.x0, o.y0 - b.y0, o.bx(), o.by(),
+                   0, nd, ncp};
+    nd += (long long)F[i].dinv.size();
+    ncp += (long long)F[i].coup.size();
+    mc = std::max(mc, b.bx() * b.by());
+    if (b.bx() > mrcm::kBoxThreads)
+      throw mrcm::Error(MRCM_EINVAL, "box wider than 256 cells is not supported");
+  }
+  if ((size_t)mc * sizeof(T) + mrcm::kBoxThreads * sizeof(T) > 60 * 1024)
+    throw mrcm::Error(MRCM_EINVAL, "subdomain or patch too large for the LDS of one workgroup");
+  std::vector<T> hd((size_t)nd), hc((size_t)ncp);
+  for (size_t i = 0; i < F.size(); ++i) {
+    std::transform(F[i].dinv.begin(), F[i].dinv.end(), hd.begin() + d[i].doff,
+                   [](double v) { return (T)v; });
+    std::transform(F[i].coup.begin(), F[i].coup.end(), hc.begin() + d[i].coff,
+                   [](double v) { return (T)v; });
+  }
+  *desc = c->upload(d, s);
+  *dinv = c->upload(hd, s);
+  *coup = c->upload(hc, s);
+  *max_cells = mc;
+  hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+void upload_coarse(mrcm_ctx* c, const mrcm::CoarseFactor& F, hipStream_t s) {
+  std::vector<CNodeDesc> nodes;
+  std::vector<double> fwd, bwd;
+  std::vector<int> idx;
+  int max_nf = 1, max_nu = 1;
+  for (const auto& cn : F.nodes) {
+    CNodeDesc d{};
+    d.nf = (int)cn.frow.size();
+    d.nu = (int)cn.urow.size();
+    d.frow = (int)idx.size();
+    idx.insert(idx.end(), cn.frow.begin(), cn.frow.end());
+    d.fcol = (int)idx.size();
+    idx.insert(idx.end(), cn.fcol.begin(), cn.fcol.end());
+    d.ucol = (int)idx.size();
+    idx.insert(idx.end(), cn.ucol.begin(), cn.ucol.end());
+    d.yoff = cn.yoff;
+    d.coff = cn.coff;
+    d.fwd = (long long)fwd.size();
+    fwd.insert(fwd.end(), cn.fwd.begin(), cn.fwd.end());
+    d.bwd = (long long)bwd.size();
+    bwd.insert(bwd.end(), cn.bwd.begin(), cn.bwd.end());
+    nodes.push_back(d);
+    max_nf = std::max(max_nf, d.nf);
+    max_nu = std::max(max_nu, d.nu);
+  }
+  if (max_nf > 6144 || max_nu > 6144)
+    throw mrcm::Error(MRCM_EINVAL, "interface separator too large for one workgroup");
+  // level chunks: forward deepest level first, backward root first
+  constexpr int kRowsPerChunk = 32;
+  std::vector<CChunk> chunks;
+  c->fwd_levels.clear();
+  c->bwd_levels.clear();
+  for (int d = F.depth; d >= 0; --d) {
+    const int first = (int)chunks.size();
+    for (size_t t = 0; t < F.nodes.size(); ++t) {
+      if (F.nodes[t].depth != d) continue;
+      const int rows = nodes[t].nf + nodes[t].nu;
+      for (int r0 = 0; r0 < rows; r0 += kRowsPerChunk)
+        chunks.push_back(CChunk{(int)t, r0, std::min(rows, r0 + kRowsPerChunk), 0});
+    }
+    c->fwd_levels.push_back({first, (int)chunks.size() - first});
+  }
+  for (int d = 0; d <= F.depth; ++d) {
+    const int first = (int)chunks.size();
+    for (size_t t = 0; t < F.nodes.size(); ++t) {
+      if (F.nodes[t].depth != d) continue;
+      const int rows = nodes[t].nf;
+      for (int r0 = 0; r0 < rows; r0 += kRowsPerChunk)
+        chunks.push_back(CChunk{(int)t, r0, std::min(rows, r0 + kRowsPerChunk), 0});
+    }
+    c->bwd_levels.push_back({first, (int)chunks.size() - first});
+  }
+  c->cnodes = c->upload(nodes, s);
+  c->cfwd = c->upload(fwd, s);
+  c->cbwd = c->upload(bwd, s);
+  c->cidx = c->upload(idx, s);
+  c->pull_ptr = c->upload(F.pull_ptr, s);
+  c->pull_idx = c->upload(F.pull_idx, s);
+  c->chunks = c->upload(chunks, s);
+  c->ybuf = c->alloc<double>(F.ylen);
+  c->cbuf = c->alloc<double>(F.clen);
+  c->max_nf = max_nf;
+  c->max_nu = max_nu;
+  hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+template <typename T>
+void apply_one(mrcm_ctx* c, const double* r, double* z, hipStream_t s) {
+  T* p = static_cast<T*>(c->pT);
+  T* rho = static_cast<T*>(c->rhoT);
+  size_t e0 = 0;
+  auto begin = [&]() {
+    if (c->timing) e0 = c->mark(s);
+  };
+  auto end = [&](int phase) {
+    if (c->timing) c->ev_marks.push_back({phase, {e0, c->mark(s)}});
+  };
+  begin();
+  mrcm::launch_local<T>(c->lbox, c->m, c->max_cells_local, static_cast<const T*>(c->ldinv),
+                        static_cast<const T*>(c->lcoup), r, p, c->nx, c->dof_off, c->dof_side,
+                        c->w_off, c->wU, c->wP, c->mU, c->mP, s);
+  end(0);
+  if (c->nc > 0) {
+    begin();
+    mrcm::launch_coarse_rhs(c->mU, c->mP, c->rowL, c->rowR, c->rowKind, c->nc, c->pin_row, c->g,
+                            s);
+    for (const auto& lv : c->fwd_levels)
+      mrcm::launch_coarse_fwd(c->chunks + lv.first, lv.second, c->cnodes, c->cfwd, c->cidx,
+                              c->pull_ptr, c->pull_idx, c->g, c->ybuf, c->cbuf, c->max_nf, s);
+    for (const auto& lv : c->bwd_levels)
+      mrcm::launch_coarse_bwd(c->chunks + lv.first, lv.second, c->cnodes, c->cbwd, c->cidx,
+                              c->ybuf, c->xc, c->max_nu, s);
+    end(1);
+    begin();
+    mrcm::launch_reconstruct<T>(c->lbox, c->m, static_cast<const T*>(c->mbf), c->mbf_off,
+                                c->dof_off, c->xc, p, c->nx, s);
+    end(2);
+  }
+  for (int k = 0; k < c->sweeps; ++k) {
+    begin();
+    mrcm::launch_residual<T>(static_cast<const T*>(c->txT), static_cast<const T*>(c->tyT), c->nx,
+                             c->ny, r, p, rho, s);
+    end(3);
+    begin();
+    mrcm::launch_patch<T>(c->pbox, c->m, c->max_cells_patch, static_cast<const T*>(c->pdinv),
+                          static_cast<const T*>(c->pcoup), rho, p, c->nx, s);
+    end(4);
+  }
+  begin();
+  mrcm::launch_finalize<T>(p, c->n, c->noflow, z, c->partials, s);
+  end(5);
+}
+
+void apply_dispatch(mrcm_ctx* c, const double* r, double* z, hipStream_t s) {
+  if (c->precision == 1)
+    apply_one<float>(c, r, z, s);
+  else
+    apply_one<double>(c, r, z, s);
+}
+
+template <typename X>
+void setup_precision(mrcm_ctx* c, const mrcm::HostSetup& S, hipStream_t s) {
+  const mrcm::Maps& M = S.maps;
+  upload_boxes<X>(c, S.local, M.boxes, &c->lbox, &c->ldinv, &c->lcoup, &c->max_cells_local, s);
+  if (S.sweeps > 0)
+    upload_boxes<X>(c, S.patch, M.boxes, &c->pbox, &c->pdinv, &c->pcoup, &c->max_cells_patch, s);
+  std::vector<X> mbf;
+  std::vector<long long> off;
+  for (int i = 0; i < M.m; ++i) {
+    off.push_back((long long)mbf.size());
+    for (double v : S.mbf[i]) mbf.push_back((X)v);
+  }
+  c->mbf = c->upload(mbf, s);
+  c->mbf_off = c->upload(off, s);
+  if (sizeof(X) == sizeof(double)) {
+    c->txT = c->tx;
+    c->tyT = c->ty;
+  } else {
+    c->txT = c->upload(narrow<X>(S.tx), s);
+    c->tyT = c->upload(narrow<X>(S.ty), s);
+  }
+  c->pT = c->alloc<X>(c->n);
+  c->rhoT = c->alloc<X>(c->n);
+  hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+void ensure_krylov(mrcm_ctx* c, int restart) {
+  if (restart <= c->krylov_cap) return;
+  c->V = c->alloc<double>((size_t)(restart + 1) * c->n);
+  c->Z = c->alloc<double>((size_t)restart * c->n);
+  c->hcol = c->alloc<double>(restart + 2);
+  c->yd = c->alloc<double>(restart + 1);
+  c->krylov_cap = restart;
+}
+
+double host_sum(const double* v, int nb) {
+  double s = 0.0;
+  for (int k = 0; k < nb; ++k) s += v[k];
+  return s;
+}
+
+void check_launch() { hip_check(hipGetLastError(), "kernel launch"); }
+
+}  // namespace
+
+extern "C" {
+
+int mrcm_map_sizes(const mrcm_grid* grid, const mrcm_params* params, int64_t* m, int64_t* ne,
+                   int64_t* nc) {
+  try {
+    if (!grid || !params) throw mrcm::Error(MRCM_EINVAL, "null argument");
+    mrcm::Maps M = mrcm::build_maps(*grid, *params);
+    if (m) *m = M.m;
+    if (ne) *ne = (int64_t)M.edges.size();
+    if (nc) *nc = M.nc();
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    set_error(e.what());
+    return e.code;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return MRCM_EINVAL;
+  }
+}
+
+int mrcm_maps(const mrcm_grid* grid, const mrcm_params* params, int32_t* owner, int32_t* boxes,
+              int32_t* oboxes, int32_t* pboxes, int32_t* edges, int32_t* dof_table,
+              int32_t* dof_offset, int32_t* row_table) {
+  try {
+    if (!grid || !params) throw mrcm::Error(MRCM_EINVAL, "null argument");
+    mrcm::Maps M = mrcm::build_maps(*grid, *params);
+    if (owner) std::memcpy(owner, M.owner.data(), M.owner.size() * sizeof(int32_t));
+    auto put_boxes = [&](int32_t* dst, const std::vector<mrcm::Box>& b) {
+      if (!dst) return;
+      for (size_t i = 0; i < b.size(); ++i) {
+        dst[4 * i] = b[i].x0;
+        dst[4 * i + 1] = b[i].x1;
+        dst[4 * i + 2] = b[i].y0;
+        dst[4 * i + 3] = b[i].y1;
+      }
+    };
+    put_boxes(boxes, M.boxes);
+    put_boxes(oboxes, M.oboxes);
+    put_boxes(pboxes, M.pboxes);
+    if (edges)
+      for (size_t e = 0; e < M.edges.size(); ++e)
+        for (int k = 0; k < 5; ++k) edges[5 * e + k] = M.edges[e][k];
+    if (dof_table)
+      for (size_t k = 0; k < M.dofs.size(); ++k)
+        for (int q = 0; q < 3; ++q) dof_table[3 * k + q] = M.dofs[k][q];
+    if (dof_offset) std::memcpy(dof_offset, M.dof_offset.data(), M.dof_offset.size() * 4);
+    if (row_table)
+      for (size_t k = 0; k < M.rows.size(); ++k)
+        for (int q = 0; q < 3; ++q) row_table[3 * k + q] = M.rows[k][q];
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    set_error(e.what());
+    return e.code;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return MRCM_EINVAL;
+  }
+}
+
+int mrcm_setup(const mrcm_grid* grid, const mrcm_params* params, const double* K_dev,
+               void* stream, mrcm_ctx** out) {
+  mrcm_ctx* c = nullptr;
+  try {
+    if (!grid || !params || !K_dev || !out) throw mrcm::Error(MRCM_EINVAL, "null argument");
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t n = (size_t)grid->nx * grid->ny;
+    if (grid->nx < 1 || grid->ny < 1) throw mrcm::Error(MRCM_EINVAL, "empty grid");
+    std::vector<double> K(n);
+    hip_check(hipMemcpyAsync(K.data(), K_dev, n * sizeof(double), hipMemcpyDeviceToHost, s),
+              "hipMemcpyAsync K");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    mrcm::HostSetup S;
+    mrcm::host_setup(S, *grid, *params, K.data(), host_threads());
+    mrcm::CoarseFactor CF = mrcm::coarse_factor(S.maps, S.Crp, S.Cci, S.Cv, host_threads());
+    c = new mrcm_ctx();
+    c->nx = grid->nx;
+    c->ny = grid->ny;
+    for (int k = 0; k < 4; ++k) c->bc[k] = grid->bc[k];
+    c->noflow = S.noflow ? 1 : 0;
+    c->precision = params->precision;
+    c->sweeps = params->smooth_sweeps;
+    c->m = S.maps.m;
+    c->nc = S.maps.nc();
+    c->n = (long long)n;
+    c->pin_row = S.pin_row;
+    c->tx = c->upload(S.tx, s);
+    c->ty = c->upload(S.ty, s);
+    c->d_bc = c->upload(std::vector<int>(grid->bc, grid->bc + 4), s);
+    if (c->precision == 1)
+      setup_precision<float>(c, S, s);
+    else
+      setup_precision<double>(c, S, s);
+    std::vector<int> dof_side;
+    for (const auto& d : S.maps.dofs) dof_side.push_back(d[1]);
+    c->dof_off = c->upload(S.maps.dof_offset, s);
+    c->dof_side = c->upload(dof_side, s);
+    c->w_off = c->upload(S.wOff, s);
+    c->wU = c->upload(S.wU, s);
+    c->wP = c->upload(S.wP, s);
+    c->rowL = c->upload(S.rowL, s);
+    c->rowR = c->upload(S.rowR, s);
+    c->rowKind = c->upload(S.rowKind, s);
+    c->mU = c->alloc<double>(c->nc);
+    c->mP = c->alloc<double>(c->nc);
+    c->g = c->alloc<double>(c->nc);
+    c->xc = c->alloc<double>(c->nc);
+    c->partials = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
+    c->parts = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
+    upload_coarse(c, CF, s);
+    hip_check(hipHostMalloc((void**)&c->h_host, sizeof(double) * (mrcm::kMaxVecBlocks + 64),
+                            hipHostMallocDefault),
+              "hipHostMalloc");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    c->setup_seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = c;
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    delete c;
+    set_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    delete c;
+    set_error("host allocation failed");
+    return MRCM_ENOMEM;
+  } catch (const std::exception& e) {
+    delete c;
+    set_error(e.what());
+    return MRCM_EINVAL;
+  }
+}
+
+int mrcm_apply(mrcm_ctx* c, const double* r, double* z, int32_t nrhs, void* stream) {
+  try {
+    if (!c || nrhs < 0) throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+    if (nrhs == 0) return MRCM_OK;
+    if (!r || !z) throw mrcm::Error(MRCM_EINVAL, "null vector");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int k = 0; k < nrhs; ++k) apply_dispatch(c, r + (size_t)k * c->n, z + (size_t)k * c->n, s);
+    if (c->timing && c->ev_used > 4096) c->fold_timing();
+    check_launch();
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    set_error(e.what());
+    return e.code;
+  }
+}
+
+int op_apply(mrcm_ctx* c, const double* x, double* y, int32_t nrhs, void* stream) {
+  try {
+    if (!c || nrhs < 0) throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+    if (nrhs == 0) return MRCM_OK;
+    if (!x || !y) throw mrcm::Error(MRCM_EINVAL, "null vector");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int k = 0; k < nrhs; ++k)
+      mrcm::launch_op_apply(c->tx, c->ty, c->nx, c->ny, x + (size_t)k * c->n,
+                            y + (size_t)k * c->n, s);
+    check_launch();
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    set_error(e.what());
+    return e.code;
+  }
+}
+
+int mrcm_rhs(mrcm_ctx* c, const double* f_cell, const double* g_bc, double h, double* b,
+             void* stream) {
+  try {
+    if (!c || !b) throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+    mrcm::launch_rhs(c->tx, c->ty, c->nx, c->ny, c->bc, f_cell, g_bc, h, b,
+                     static_cast<hipStream_t>(stream));
+    check_launch();
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    set_error(e.what());
+    return e.code;
+  }
+}
+
+int gmres_solve(mrcm_ctx* c, const double* b, double* p, int32_t nrhs, double rtol,
+                int32_t restart, int32_t maxit, mrcm_stats* st, void* stream) {
+  try {
+    if (!c || nrhs < 0 || restart < 1 || restart > 200 || maxit < 0 || !(rtol >= 0.0))
+      throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+    if (nrhs == 0) {
+      if (st) {
+        st->iterations = st->cycles = st->hist_len = st->true_len = 0;
+        st->converged = 1;
+        st->final_relres = 0.0;
+      }
+      return MRCM_OK;
+    }
+    if (!b || !p) throw mrcm::Error(MRCM_EINVAL, "null vector");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ensure_krylov(c, restart);
+    const long long n = c->n;
+    const int nb = mrcm::vec_blocks(n);
+    double* hh = c->h_host;
+    int total_it = 0, total_cycles = 0, all_conv = 1, hist_len = 0, true_len = 0;
+    double worst = 0.0;
+    auto fetch = [&](const double* dsrc, int cnt) {
+      hip_check(hipMemcpyAsync(hh, dsrc, sizeof(double) * cnt, hipMemcpyDeviceToHost, s),
+                "hipMemcpyAsync");
+      hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+      if (c->timing) c->fold_timing();
+    };
+    std::vector<double> H((size_t)(restart + 1) * restart), cs(restart), sn(restart),
+        gv(restart + 1), y(restart);
+    for (int k = 0; k < nrhs; ++k) {
+      const double* bk = b + (size_t)k * n;
+      double* pk = p + (size_t)k * n;
+      hip_check(hipMemsetAsync(pk, 0, sizeof(double) * n, s), "hipMemsetAsync");
+      mrcm::launch_sumsq(bk, n, c->parts, nb, s);
+      fetch(c->parts, nb);
+      const double bnorm = std::sqrt(host_sum(hh, nb));
+      if (bnorm == 0.0) continue;
+      const double tol = rtol * bnorm;
+      int it = 0;
+      bool first = true, conv = false;
+      double relres = 1.0;
+      while (true) {
+        mrcm::launch_resid_norm(c->tx, c->ty, c->nx, c->ny, bk, first ? nullptr : pk, c->V,
+                                c->parts, nb, s);
+        fetch(c->parts, nb);
+        const double beta = std::sqrt(host_sum(hh, nb));
+        relres = beta / bnorm;
+        if (k == 0 && st && st->true_hist && true_len < st->hist_cap)
+          st->true_hist[true_len++] = relres;
+        if (beta <= tol) {
+          conv = true;
+          break;
+        }
+        if (it >= maxit) break;
+        ++total_cycles;
+        mrcm::launch_scale(c->V, n, 1.0 / beta, s);
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = beta;
+        int jj = 0;
+        for (int j = 0; j < restart; ++j) {
+          double* vj = c->V + (size_t)j * n;
+          double* zj = c->Z + (size_t)j * n;
+          double* w = c->V + (size_t)(j + 1) * n;
+          apply_dispatch(c, vj, zj, s);
+          mrcm::launch_arnoldi_start(c->tx, c->ty, c->nx, c->ny, zj, w, c->V, c->parts, nb, s);
+          for (int i = 0; i <= j; ++i)
+            mrcm::launch_mgs_step(c->parts + (i % 2) * mrcm::kMaxVecBlocks,
+                                  c->parts + ((i + 1) % 2) * mrcm::kMaxVecBlocks, nb, c->hcol, i,
+                                  w, c->V + (size_t)i * n,
+                                  i < j ? c->V + (size_t)(i + 1) * n : nullptr, n, s);
+          mrcm::launch_norm_scale(c->parts + ((j + 1) % 2) * mrcm::kMaxVecBlocks, nb, c->hcol,
+                                  j + 1, w, n, s);
+          fetch(c->hcol, j + 2);
+          ++it;
+          for (int i = 0; i <= j + 1; ++i) H[(size_t)i * restart + j] = hh[i];
+          const double hnext = hh[j + 1];
+          for (int i = 0; i < j; ++i) {
+            const double a = H[(size_t)i * restart + j], bb = H[(size_t)(i + 1) * restart + j];
+            H[(size_t)i * restart + j] = cs[i] * a + sn[i] * bb;
+            H[(size_t)(i + 1) * restart + j] = -sn[i] * a + cs[i] * bb;
+          }
+          const double a = H[(size_t)j * restart + j], bb = H[(size_t)(j + 1) * restart + j];
+          const double rr = std::hypot(a, bb);
+          cs[j] = a / rr;
+          sn[j] = bb / rr;
+          H[(size_t)j * restart + j] = rr;
+          H[(size_t)(j + 1) * restart + j] = 0.0;
+          gv[j + 1] = -sn[j] * gv[j];
+          gv[j] = cs[j] * gv[j];
+          if (k == 0 && st && st->est_hist && hist_len < st->hist_cap)
+            st->est_hist[hist_len++] = std::fabs(gv[j + 1]) / bnorm;
+          jj = j + 1;
+          if (hnext == 0.0 || std::fabs(gv[j + 1]) <= tol || it >= maxit) break;
+        }
+        for (int i = jj - 1; i >= 0; --i) {
+          double sum = gv[i];
+          for (int q = i + 1; q < jj; ++q) sum -= H[(size_t)i * restart + q] * y[q];
+          y[i] = sum / H[(size_t)i * restart + i];
+        }
+        std::memcpy(hh, y.data(), sizeof(double) * jj);
+        hip_check(hipMemcpyAsync(c->yd, hh, sizeof(double) * jj, hipMemcpyHostToDevice, s),
+                  "hipMemcpyAsync");
+        mrcm::launch_update(pk, c->Z, c->yd, jj, n, s);
+        // the host buffer is reused by the next fetch only after this copy completes
+        hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+        first = false;
+      }
+      total_it += it;
+      all_conv &= conv ? 1 : 0;
+      worst = std::max(worst, relres);
+    }
+    check_launch();
+    if (st) {
+      st->iterations = total_it;
+      st->cycles = total_cycles;
+      st->converged = all_conv;
+      st->hist_len = hist_len;
+      st->true_len = true_len;
+      st->final_relres = worst;
+    }
+    if (!all_conv) throw mrcm::Error(MRCM_ENOCONV, "GMRES reached maxit");
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    set_error(e.what());
+    return e.code;
+  }
+}
+
+size_t mrcm_footprint(const mrcm_grid* grid, const mrcm_params* params, int32_t nrhs) {
+  try {
+    if (!grid || !params) return 0;
+    mrcm::Maps M = mrcm::build_maps(*grid, *params);
+    const size_t w = params->precision == 1 ? 4 : 8;
+    const size_t n = (size_t)grid->nx * grid->ny;
+    size_t bytes = 2 * (n + grid->nx + grid->ny + 1) * (8 + (w == 4 ? 4 : 0));
+    auto boxes = [&](const std::vector<mrcm::Box>& B) {
+      size_t t = 0;
+      for (const auto& b : B) t += (size_t)b.by() * b.bx() * (b.bx() + 1);
+      return t * w;
+    };
+    bytes += boxes(M.boxes);
+    if (params->smooth_sweeps > 0) bytes += boxes(M.pboxes);
+    for (int i = 0; i < M.m; ++i)
+      bytes += (size_t)(M.dof_offset[i + 1] - M.dof_offset[i]) * M.boxes[i].bx() *
+               M.boxes[i].by() * w;
+    // coarse factor: about 60 x nc^1.5 / sqrt(dofs per subdomain) values (nested dissection)
+    const double nc = M.nc();
+    bytes += (size_t)(8.0 * 60.0 * nc * std::sqrt(nc / std::max(1.0, nc / std::max(1, M.m))));
+    bytes += 2 * n * w;
+    const int r = nrhs > 0 ? nrhs : 1;
+    bytes += (size_t)r * 21 * n * 8;  // Krylov basis of restart 10
+    return bytes;
+  } catch (...) {
+    return 0;
+  }
+}
+
+int mrcm_timing_enable(mrcm_ctx* c, int32_t on) {
+  try {
+    if (!c) throw mrcm::Error(MRCM_EINVAL, "null context");
+    if (c->timing) c->fold_timing();
+    c->timing = on != 0;
+    if (on)
+      for (int k = 0; k < mrcm_ctx::kPhases; ++k) {
+        c->phase_ms[k] = 0.0;
+        c->phase_n[k] = 0;
+      }
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    set_error(e.what());
+    return e.code;
+  }
+}
+
+int mrcm_timing_read(mrcm_ctx* c, double* ms, int64_t* counts) {
+  try {
+    if (!c || !ms || !counts) throw mrcm::Error(MRCM_EINVAL, "null argument");
+    c->fold_timing();
+    for (int k = 0; k < mrcm_ctx::kPhases; ++k) {
+      ms[k] = c->phase_ms[k];
+      counts[k] = c->phase_n[k];
+    }
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    set_error(e.what());
+    return e.code;
+  }
+}
+
+void mrcm_destroy(mrcm_ctx* c) { delete c; }
+
+const char* mrcm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

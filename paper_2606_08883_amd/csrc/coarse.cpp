@@ -1,0 +1,311 @@
+// Nested-dissection multifrontal factorisation of the interface system and a
+// host reference of its level-scheduled solve (the GPU solve is in
+// kernels.hip).  See coarse.h for the structure.
+#include "coarse.h"
+
+#include <omp.h>
+
+#include <algorithm>
+#include <cmath>
+#include <functional>
+
+namespace mrcm {
+
+namespace {
+
+constexpr int kLeafArea = 4;  // boxes of at most this many subdomains are eliminated whole
+
+struct TreeNode {
+  std::vector<int> fsub, usub;
+  int depth;
+  std::vector<int> children;
+};
+
+// C (m x n) = alpha * A (m x k) * B (k x n) + beta * C, row-major, OpenMP over rows.
+void gemm(int m, int n, int k, double alpha, const double* A, int lda, const double* B, int ldb,
+          double beta, double* C, int ldc) {
+  const bool par = !omp_in_parallel() && (double)m * n * k > 2e6;
+#pragma omp parallel for schedule(static) if (par)
+  for (int i = 0; i < m; ++i) {
+    double* c = C + (size_t)i * ldc;
+    if (beta == 0.0)
+      for (int j = 0; j < n; ++j) c[j] = 0.0;
+    else if (beta != 1.0)
+      for (int j = 0; j < n; ++j) c[j] *= beta;
+    const double* a = A + (size_t)i * lda;
+    for (int p = 0; p < k; ++p) {
+      const double av = alpha * a[p];
+      if (av == 0.0) continue;
+      const double* b = B + (size_t)p * ldb;
+      for (int j = 0; j < n; ++j) c[j] += av * b[j];
+    }
+  }
+}
+
+// Inverse of a dense n x n row-major matrix by LU with partial pivoting.
+// Returns the smallest |pivot| / max|A| ratio (0 when singular).
+double lu_inverse(std::vector<double>& A, int n, std::vector<double>& inv) {
+  double amax = 0.0;
+  for (double v : A) amax = std::max(amax, std::fabs(v));
+  std::vector<int> perm(n);
+  for (int i = 0; i < n; ++i) perm[i] = i;
+  double ratio = 1.0;
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    double best = std::fabs(A[(size_t)k * n + k]);
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(A[(size_t)i * n + k]) > best) {
+        best = std::fabs(A[(size_t)i * n + k]);
+        p = i;
+      }
+    if (!(best > 0.0) || !std::isfinite(best)) return 0.0;
+    ratio = std::min(ratio, best / amax);
+    if (p != k) {
+      for (int j = 0; j < n; ++j) std::swap(A[(size_t)k * n + j], A[(size_t)p * n + j]);
+      std::swap(perm[k], perm[p]);
+    }
+    const double piv = A[(size_t)k * n + k];
+    const bool par = !omp_in_parallel() && (double)(n - k) * (n - k) > 2e5;
+#pragma omp parallel for schedule(static) if (par)
+    for (int i = k + 1; i < n; ++i) {
+      double l = A[(size_t)i * n + k] / piv;
+      A[(size_t)i * n + k] = l;
+      if (l == 0.0) continue;
+      for (int j = k + 1; j < n; ++j) A[(size_t)i * n + j] -= l * A[(size_t)k * n + j];
+    }
+  }
+  inv.assign((size_t)n * n, 0.0);
+  const bool par = !omp_in_parallel() && n > 64;
+#pragma omp parallel for schedule(dynamic, 8) if (par)
+  for (int col = 0; col < n; ++col) {
+    std::vector<double> x(n, 0.0);
+    for (int i = 0; i < n; ++i) x[i] = (perm[i] == col) ? 1.0 : 0.0;
+    for (int i = 0; i < n; ++i) {
+      double s = x[i];
+      for (int j = 0; j < i; ++j) s -= A[(size_t)i * n + j] * x[j];
+      x[i] = s;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = x[i];
+      for (int j = i + 1; j < n; ++j) s -= A[(size_t)i * n + j] * x[j];
+      x[i] = s / A[(size_t)i * n + i];
+    }
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + col] = x[i];
+  }
+  return ratio;
+}
+
+}  // namespace
+
+CoarseFactor coarse_factor(const Maps& M, const std::vector<int>& rp, const std::vector<int>& ci,
+                           const std::vector<double>& cv, int nthreads) {
+  CoarseFactor F;
+  const int nc = M.nc();
+  F.nc = nc;
+  if (nc == 0) {
+    F.pull_ptr.assign(1, 0);
+    return F;
+  }
+  // rows owned by each subdomain: flux rows -> L, pressure rows -> R
+  std::vector<std::vector<int>> rows_of(M.m);
+  for (int r = 0; r < nc; ++r) {
+    const auto& e = M.edges[M.rows[r][0]];
+    rows_of[M.rows[r][1] == 0 ? e[0] : e[1]].push_back(r);
+  }
+  for (int i = 0; i < M.m; ++i)
+    if ((int)rows_of[i].size() != M.dof_offset[i + 1] - M.dof_offset[i])
+      throw Error(MRCM_EINVAL, "coarse row ownership is not square");
+  // nested dissection on the mx x my subdomain grid
+  std::vector<TreeNode> tree;
+  std::function<int(int, int, int, int, int)> build = [&](int x0, int x1, int y0, int y1,
+                                                          int depth) -> int {
+    if (x0 >= x1 || y0 >= y1) return -1;
+    TreeNode nd;
+    nd.depth = depth;
+    if ((x1 - x0) * (y1 - y0) <= kLeafArea) {
+      for (int y = y0; y < y1; ++y)
+        for (int x = x0; x < x1; ++x) nd.fsub.push_back(y * M.mx + x);
+    } else if (x1 - x0 >= y1 - y0) {
+      const int xm = (x0 + x1) / 2;
+      int a = build(x0, xm, y0, y1, depth + 1), b = build(xm + 1, x1, y0, y1, depth + 1);
+      if (a >= 0) nd.children.push_back(a);
+      if (b >= 0) nd.children.push_back(b);
+      for (int y = y0; y < y1; ++y) nd.fsub.push_back(y * M.mx + xm);
+    } else {
+      const int ym = (y0 + y1) / 2;
+      int a = build(x0, x1, y0, ym, depth + 1), b = build(x0, x1, ym + 1, y1, depth + 1);
+      if (a >= 0) nd.children.push_back(a);
+      if (b >= 0) nd.children.push_back(b);
+      for (int x = x0; x < x1; ++x) nd.fsub.push_back(ym * M.mx + x);
+    }
+    for (int y = y0; y < y1; ++y) {
+      if (x0 > 0) nd.usub.push_back(y * M.mx + x0 - 1);
+      if (x1 < M.mx) nd.usub.push_back(y * M.mx + x1);
+    }
+    for (int x = x0; x < x1; ++x) {
+      if (y0 > 0) nd.usub.push_back((y0 - 1) * M.mx + x);
+      if (y1 < M.my) nd.usub.push_back(y1 * M.mx + x);
+    }
+    std::sort(nd.usub.begin(), nd.usub.end());
+    tree.push_back(nd);
+    return (int)tree.size() - 1;
+  };
+  build(0, M.mx, 0, M.my, 0);
+  const int nn = (int)tree.size();
+  F.nodes.resize(nn);
+  int maxdepth = 0;
+  for (int t = 0; t < nn; ++t) {
+    CoarseNode& cn = F.nodes[t];
+    cn.depth = tree[t].depth;
+    maxdepth = std::max(maxdepth, cn.depth);
+    for (int s : tree[t].fsub) {
+      cn.frow.insert(cn.frow.end(), rows_of[s].begin(), rows_of[s].end());
+      for (int k = M.dof_offset[s]; k < M.dof_offset[s + 1]; ++k) cn.fcol.push_back(k);
+    }
+    for (int s : tree[t].usub) {
+      cn.urow.insert(cn.urow.end(), rows_of[s].begin(), rows_of[s].end());
+      for (int k = M.dof_offset[s]; k < M.dof_offset[s + 1]; ++k) cn.ucol.push_back(k);
+    }
+  }
+  F.depth = maxdepth;
+  // factor level by level, deepest first; update matrices are passed to parents
+  std::vector<std::vector<double>> update(nn);
+  std::vector<std::vector<int>> by_depth(maxdepth + 1);
+  for (int t = 0; t < nn; ++t) by_depth[F.nodes[t].depth].push_back(t);
+  double min_ratio = 1.0;
+  int failed = 0;
+  for (int d = maxdepth; d >= 0; --d) {
+    const auto& lvl = by_depth[d];
+    const bool par_nodes = (int)lvl.size() >= 4;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads) if (par_nodes)
+    for (int li = 0; li < (int)lvl.size(); ++li) {
+      const int t = lvl[li];
+      CoarseNode& cn = F.nodes[t];
+      const int nf = (int)cn.frow.size(), nu = (int)cn.urow.size(), nt = nf + nu;
+      // local positions of the front's rows and columns (-1: not in the front)
+      static thread_local std::vector<int> rpos, cpos;
+      if ((int)rpos.size() < nc) {
+        rpos.assign(nc, -1);
+        cpos.assign(nc, -1);
+      }
+      for (int a = 0; a < nf; ++a) {
+        rpos[cn.frow[a]] = a;
+        cpos[cn.fcol[a]] = a;
+      }
+      for (int a = 0; a < nu; ++a) {
+        rpos[cn.urow[a]] = nf + a;
+        cpos[cn.ucol[a]] = nf + a;
+      }
+      std::vector<double> Fm((size_t)nt * nt, 0.0);
+      for (int a = 0; a < nt; ++a) {
+        const int r = a < nf ? cn.frow[a] : cn.urow[a - nf];
+        for (int q = rp[r]; q < rp[r + 1]; ++q) {
+          const int b = cpos[ci[q]];
+          if (b < 0) continue;
+          if (a >= nf && b >= nf) continue;  // both later: assembled at an ancestor
+          Fm[(size_t)a * nt + b] += cv[q];
+        }
+      }
+      for (int ch : tree[t].children) {
+        const CoarseNode& cc = F.nodes[ch];
+        const int cu = (int)cc.urow.size();
+        std::vector<int> ra(cu), cb(cu);
+        for (int u = 0; u < cu; ++u) {
+          ra[u] = rpos[cc.urow[u]];
+          cb[u] = cpos[cc.ucol[u]];
+        }
+        const std::vector<double>& S = update[ch];
+        for (int u = 0; u < cu; ++u)
+          for (int v = 0; v < cu; ++v) Fm[(size_t)ra[u] * nt + cb[v]] += S[(size_t)u * cu + v];
+        update[ch].clear();
+        update[ch].shrink_to_fit();
+      }
+      for (int a = 0; a < nf; ++a) rpos[cn.frow[a]] = cpos[cn.fcol[a]] = -1;
+      for (int a = 0; a < nu; ++a) rpos[cn.urow[a]] = cpos[cn.ucol[a]] = -1;
+      std::vector<double> Aff((size_t)nf * nf), Winv;
+      for (int a = 0; a < nf; ++a)
+        for (int b = 0; b < nf; ++b) Aff[(size_t)a * nf + b] = Fm[(size_t)a * nt + b];
+      const double ratio = lu_inverse(Aff, nf, Winv);
+      if (!(ratio > 1e-14)) {
+#pragma omp atomic write
+        failed = 1;
+        continue;
+      }
+#pragma omp critical
+      min_ratio = std::min(min_ratio, ratio);
+      cn.fwd.assign((size_t)nt * nf, 0.0);
+      std::copy(Winv.begin(), Winv.end(), cn.fwd.begin());
+      if (nu > 0) {
+        // E = A_UF Winv
+        gemm(nu, nf, nf, 1.0, &Fm[(size_t)nf * nt], nt, Winv.data(), nf, 0.0,
+             &cn.fwd[(size_t)nf * nf], nf);
+        // G = Winv A_FU
+        cn.bwd.assign((size_t)nf * nu, 0.0);
+        gemm(nf, nu, nf, 1.0, Winv.data(), nf, &Fm[nf], nt, 0.0, cn.bwd.data(), nu);
+        // S = A_UU - A_UF G
+        std::vector<double> S((size_t)nu * nu);
+        for (int a = 0; a < nu; ++a)
+          for (int b = 0; b < nu; ++b) S[(size_t)a * nu + b] = Fm[(size_t)(nf + a) * nt + nf + b];
+        gemm(nu, nu, nf, -1.0, &Fm[(size_t)nf * nt], nt, cn.bwd.data(), nu, 1.0, S.data(), nu);
+        update[t] = std::move(S);
+      }
+    }
+    if (failed) throw Error(MRCM_ESINGULAR, "singular block in the interface system");
+  }
+  F.min_pivot_ratio = min_ratio;
+  // buffer offsets and pull lists
+  int yo = 0, co = 0;
+  for (auto& cn : F.nodes) {
+    cn.yoff = yo;
+    cn.coff = co;
+    yo += (int)cn.frow.size();
+    co += (int)cn.urow.size();
+  }
+  F.ylen = yo;
+  F.clen = co;
+  std::vector<std::vector<int>> pulls(nc);
+  for (const auto& cn : F.nodes)
+    for (size_t u = 0; u < cn.urow.size(); ++u) pulls[cn.urow[u]].push_back(cn.coff + (int)u);
+  F.pull_ptr.assign(nc + 1, 0);
+  for (int r = 0; r < nc; ++r) {
+    F.pull_ptr[r + 1] = F.pull_ptr[r] + (int)pulls[r].size();
+    F.pull_idx.insert(F.pull_idx.end(), pulls[r].begin(), pulls[r].end());
+  }
+  return F;
+}
+
+void coarse_solve_host(const CoarseFactor& F, const double* g, double* x) {
+  std::vector<double> ybuf(F.ylen), cbuf(F.clen);
+  for (int d = F.depth; d >= 0; --d)
+    for (const auto& cn : F.nodes) {
+      if (cn.depth != d) continue;
+      const int nf = (int)cn.frow.size(), nu = (int)cn.urow.size();
+      std::vector<double> v(nf);
+      for (int a = 0; a < nf; ++a) {
+        const int r = cn.frow[a];
+        double s = g[r];
+        for (int q = F.pull_ptr[r]; q < F.pull_ptr[r + 1]; ++q) s -= cbuf[F.pull_idx[q]];
+        v[a] = s;
+      }
+      for (int a = 0; a < nf + nu; ++a) {
+        double s = 0.0;
+        for (int b = 0; b < nf; ++b) s += cn.fwd[(size_t)a * nf + b] * v[b];
+        if (a < nf)
+          ybuf[cn.yoff + a] = s;
+        else
+          cbuf[cn.coff + a - nf] = s;
+      }
+    }
+  for (int d = 0; d <= F.depth; ++d)
+    for (const auto& cn : F.nodes) {
+      if (cn.depth != d) continue;
+      const int nf = (int)cn.frow.size(), nu = (int)cn.urow.size();
+      for (int a = 0; a < nf; ++a) {
+        double s = ybuf[cn.yoff + a];
+        for (int b = 0; b < nu; ++b) s -= cn.bwd[(size_t)a * nu + b] * x[cn.ucol[b]];
+        x[cn.fcol[a]] = s;
+      }
+    }
+}
+
+}  // namespace mrcm

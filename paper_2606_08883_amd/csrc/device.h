@@ -1,0 +1,104 @@
+// Device-side descriptors and kernel launchers of the MRCM-OS library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mrcm {
+
+// One cell box solved by a workgroup (a subdomain or a smoothing patch).
+// (x0, y0, bx, by): the box; (ox, oy, obx, oby): the owned subdomain, in
+// coordinates relative to the box (patches add their solution there only).
+struct BoxDesc {
+  int x0, y0, bx, by;
+  int pin;
+  int ox, oy, obx, oby;
+  int pad;
+  long long doff;  // offset of D_j^-1 blocks (elements)
+  long long coff;  // offset of the couplings T_j (elements)
+};
+
+// One node of the coarse nested-dissection tree (see coarse.h).
+struct CNodeDesc {
+  int nf, nu;
+  int frow, fcol, ucol;  // offsets into the index arrays
+  int yoff, coff;
+  int pad;
+  long long fwd, bwd;  // offsets into the factor arrays
+};
+
+// A slice [row0, row1) of one node's forward or backward matrix.
+struct CChunk {
+  int node, row0, row1, pad;
+};
+
+constexpr int kBoxThreads = 256;
+constexpr int kVecThreads = 256;
+constexpr int kMaxVecBlocks = 1024;
+
+inline int vec_blocks(long long n) {
+  long long b = (n + kVecThreads * 4 - 1) / (kVecThreads * 4);
+  if (b < 1) b = 1;
+  if (b > kMaxVecBlocks) b = kMaxVecBlocks;
+  return (int)b;
+}
+
+// ---- fine operator --------------------------------------------------------
+void launch_op_apply(const double* tx, const double* ty, int nx, int ny, const double* x,
+                     double* y, hipStream_t s);
+void launch_rhs(const double* tx, const double* ty, int nx, int ny, const int* bc,
+                const double* f, const double* g, double h, double* b, hipStream_t s);
+
+// ---- preconditioner apply (T = double or float) ----------------------------
+template <typename T>
+void launch_local(const BoxDesc* boxes, int m, int max_cells, const T* dinv, const T* coup,
+                  const double* r, T* p, int nx, const int* dof_off, const int* dof_side,
+                  const int* w_off, const double* wU, const double* wP, double* mU, double* mP,
+                  hipStream_t s);
+void launch_coarse_rhs(const double* mU, const double* mP, const int* rowL, const int* rowR,
+                       const int* rowKind, int nc, int pin_row, double* g, hipStream_t s);
+void launch_coarse_fwd(const CChunk* chunks, int nchunks, const CNodeDesc* nodes,
+                       const double* fwd, const int* idx, const int* pull_ptr,
+                       const int* pull_idx, const double* g, double* ybuf, double* cbuf,
+                       int max_nf, hipStream_t s);
+void launch_coarse_bwd(const CChunk* chunks, int nchunks, const CNodeDesc* nodes,
+                       const double* bwd, const int* idx, const double* ybuf, double* x,
+                       int max_nu, hipStream_t s);
+template <typename T>
+void launch_reconstruct(const BoxDesc* boxes, int m, const T* mbf, const long long* mbf_off,
+                        const int* dof_off, const double* xc, T* p, int nx, hipStream_t s);
+template <typename T>
+void launch_residual(const T* tx, const T* ty, int nx, int ny, const double* r, const T* p,
+                     T* rho, hipStream_t s);
+template <typename T>
+void launch_patch(const BoxDesc* boxes, int m, int max_cells, const T* dinv, const T* coup,
+                  const T* rho, T* p, int nx, hipStream_t s);
+template <typename T>
+void launch_finalize(const T* p, long long n, int noflow, double* z, double* partials,
+                     hipStream_t s);
+void launch_convert(const double* src, float* dst, long long n, hipStream_t s);
+
+// ---- GMRES vector kernels (FP64) -------------------------------------------
+// r = b - A p (p may be NULL for p = 0); partials[block] = sum r^2
+void launch_resid_norm(const double* tx, const double* ty, int nx, int ny, const double* b,
+                       const double* p, double* r, double* partials, int nb, hipStream_t s);
+// v = alpha * v
+void launch_scale(double* v, long long n, double alpha, hipStream_t s);
+// w = A z, partials = w . v0
+void launch_arnoldi_start(const double* tx, const double* ty, int nx, int ny, const double* z,
+                          double* w, const double* v0, double* partials, int nb, hipStream_t s);
+// h = sum(part_in); hcol[i] = h; w -= h vi; part_out = w . vnext (or w . w when vnext NULL)
+void launch_mgs_step(const double* part_in, double* part_out, int nb, double* hcol, int i,
+                     double* w, const double* vi, const double* vnext, long long n,
+                     hipStream_t s);
+// hn = sqrt(sum(part_in)); hcol[j] = hn; w /= hn (if hn > 0)
+void launch_norm_scale(const double* part_in, int nb, double* hcol, int j, double* w,
+                       long long n, hipStream_t s);
+// p += sum_i y[i] Z_i
+void launch_update(double* p, const double* Z, const double* y, int k, long long n,
+                   hipStream_t s);
+// partials = sum of squares of x
+void launch_sumsq(const double* x, long long n, double* partials, int nb, hipStream_t s);
+
+}  // namespace mrcm

@@ -1,0 +1,411 @@
+// Host-side FP64 setup of T (Section 2.1): face transmissibilities, Robin
+// coefficients (beta = alpha L / K_H), block LDL^T factors of the local Robin
+// problems, the oversampled problems that inform the multiplier spaces, the
+// multiscale basis functions, the interface system, and the factors of the
+// smoothing patches.
+#include "setup.h"
+
+#include <omp.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <string>
+#include <utility>
+
+namespace mrcm {
+
+void face_transmissibilities(HostSetup& S) {
+  const int nx = S.nx, ny = S.ny;
+  const double* K = S.K.data();
+  S.tx.assign((size_t)ny * (nx + 1), 0.0);
+  S.ty.assign((size_t)(ny + 1) * nx, 0.0);
+  for (int y = 0; y < ny; ++y) {
+    for (int x = 1; x < nx; ++x) {
+      double a = K[(size_t)y * nx + x - 1], b = K[(size_t)y * nx + x];
+      S.tx[(size_t)y * (nx + 1) + x] = 2.0 * a * b / (a + b);
+    }
+    if (S.bc[SW]) S.tx[(size_t)y * (nx + 1)] = 2.0 * K[(size_t)y * nx];
+    if (S.bc[SE]) S.tx[(size_t)y * (nx + 1) + nx] = 2.0 * K[(size_t)y * nx + nx - 1];
+  }
+  for (int y = 1; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      double a = K[(size_t)(y - 1) * nx + x], b = K[(size_t)y * nx + x];
+      S.ty[(size_t)y * nx + x] = 2.0 * a * b / (a + b);
+    }
+  for (int x = 0; x < nx; ++x) {
+    if (S.bc[SS]) S.ty[x] = 2.0 * K[x];
+    if (S.bc[SN]) S.ty[(size_t)ny * nx + x] = 2.0 * K[(size_t)(ny - 1) * nx + x];
+  }
+}
+
+static inline double txv(const HostSetup& S, int y, int x) {
+  return S.tx[(size_t)y * (S.nx + 1) + x];
+}
+static inline double tyv(const HostSetup& S, int y, int x) { return S.ty[(size_t)y * S.nx + x]; }
+
+// Robin conductance of a face leaving a cell set: 1 / (1 / (2 K_c) + b_f),
+// b_f = alpha L_cells / K_H(f), K_H(f) = t_f for square cells.
+static inline double robin_rho(const HostSetup& S, double Kc, double t) {
+  return 1.0 / (1.0 / (2.0 * Kc) + S.alpha * S.Lcells / t);
+}
+
+// In-place SPD inverse of an n x n row-major matrix through Cholesky.
+static bool spd_inverse(double* A, int n, std::vector<double>& L, std::vector<double>& Li) {
+  L.assign((size_t)n * n, 0.0);
+  Li.assign((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = A[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) d -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+    if (!(d > 0.0) || !std::isfinite(d)) return false;
+    double ljj = std::sqrt(d);
+    L[(size_t)j * n + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      double s = A[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) s -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+      L[(size_t)i * n + j] = s / ljj;
+    }
+  }
+  for (int j = 0; j < n; ++j) {
+    Li[(size_t)j * n + j] = 1.0 / L[(size_t)j * n + j];
+    for (int i = j + 1; i < n; ++i) {
+      double s = 0.0;
+      for (int k = j; k < i; ++k) s += L[(size_t)i * n + k] * Li[(size_t)k * n + j];
+      Li[(size_t)i * n + j] = -s / L[(size_t)i * n + i];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double s = 0.0;
+      for (int k = i; k < n; ++k) s += Li[(size_t)k * n + i] * Li[(size_t)k * n + j];
+      A[(size_t)i * n + j] = s;
+      A[(size_t)j * n + i] = s;
+    }
+  return true;
+}
+
+BoxFactor factor_box(const HostSetup& S, const Box& b, bool robin) {
+  BoxFactor F;
+  F.box = b;
+  const int bx = b.bx(), by = b.by(), nx = S.nx, ny = S.ny;
+  F.pin = (S.noflow && b.x0 == 0 && b.y0 == 0 && b.x1 == nx && b.y1 == ny) ? 1 : 0;
+  F.dinv.assign((size_t)by * bx * bx, 0.0);
+  F.coup.assign((size_t)by * bx, 0.0);
+  std::vector<double> D((size_t)bx * bx), L, Li;
+  for (int j = 0; j < by; ++j) {
+    const int y = b.y0 + j;
+    std::fill(D.begin(), D.end(), 0.0);
+    for (int a = 0; a < bx; ++a) {
+      const int x = b.x0 + a;
+      const double Kc = S.K[(size_t)y * nx + x];
+      double tW = txv(S, y, x), tE = txv(S, y, x + 1), tS = tyv(S, y, x), tN = tyv(S, y + 1, x);
+      // faces leaving the box inside the domain: Robin conductance or the
+      // principal-submatrix transmissibility (unchanged)
+      if (robin) {
+        if (a == 0 && x > 0) tW = robin_rho(S, Kc, tW);
+        if (a == bx - 1 && x + 1 < nx) tE = robin_rho(S, Kc, tE);
+        if (j == 0 && y > 0) tS = robin_rho(S, Kc, tS);
+        if (j == by - 1 && y + 1 < ny) tN = robin_rho(S, Kc, tN);
+      }
+      D[(size_t)a * bx + a] = tW + tE + tS + tN;
+      if (a > 0) {
+        D[(size_t)a * bx + a - 1] = -txv(S, y, x);
+        D[(size_t)(a - 1) * bx + a] = -txv(S, y, x);
+      }
+      if (j > 0) F.coup[(size_t)j * bx + a] = tyv(S, y, x);
+    }
+    if (F.pin && j == 0) {
+      for (int a = 0; a < bx; ++a) {
+        D[a] = 0.0;
+        D[(size_t)a * bx] = 0.0;
+      }
+      D[0] = 1.0;
+    }
+    if (F.pin && j == 1) F.coup[(size_t)bx] = 0.0;
+    if (j > 0) {
+      const double* Dp = &F.dinv[(size_t)(j - 1) * bx * bx];
+      const double* T = &F.coup[(size_t)j * bx];
+      for (int a = 0; a < bx; ++a)
+        for (int c = 0; c < bx; ++c) D[(size_t)a * bx + c] -= T[a] * Dp[(size_t)a * bx + c] * T[c];
+    }
+    if (!spd_inverse(D.data(), bx, L, Li))
+      throw Error(MRCM_ESINGULAR, "non-positive pivot in a local factorisation");
+    std::copy(D.begin(), D.end(), F.dinv.begin() + (size_t)j * bx * bx);
+  }
+  return F;
+}
+
+void box_solve(const BoxFactor& F, double* x) {
+  const int bx = F.box.bx(), by = F.box.by();
+  std::vector<double> y(bx);
+  if (F.pin) x[0] = 0.0;
+  for (int j = 0; j < by; ++j) {
+    const double* T = &F.coup[(size_t)j * bx];
+    for (int a = 0; a < bx; ++a)
+      y[a] = x[(size_t)j * bx + a] + (j > 0 ? T[a] * x[(size_t)(j - 1) * bx + a] : 0.0);
+    const double* Di = &F.dinv[(size_t)j * bx * bx];
+    for (int a = 0; a < bx; ++a) {
+      double s = 0.0;
+      for (int c = 0; c < bx; ++c) s += Di[(size_t)a * bx + c] * y[c];
+      x[(size_t)j * bx + a] = s;
+    }
+  }
+  for (int j = by - 2; j >= 0; --j) {
+    const double* T = &F.coup[(size_t)(j + 1) * bx];
+    for (int a = 0; a < bx; ++a) y[a] = T[a] * x[(size_t)(j + 1) * bx + a];
+    const double* Di = &F.dinv[(size_t)j * bx * bx];
+    for (int a = 0; a < bx; ++a) {
+      double s = 0.0;
+      for (int c = 0; c < bx; ++c) s += Di[(size_t)a * bx + c] * y[c];
+      x[(size_t)j * bx + a] += s;
+    }
+  }
+}
+
+void host_op_apply(const HostSetup& S, const double* x, double* y) {
+  const int nx = S.nx, ny = S.ny;
+  for (int iy = 0; iy < ny; ++iy)
+    for (int ix = 0; ix < nx; ++ix) {
+      size_t c = (size_t)iy * nx + ix;
+      double tW = txv(S, iy, ix), tE = txv(S, iy, ix + 1), tS = tyv(S, iy, ix),
+             tN = tyv(S, iy + 1, ix);
+      double v = (tW + tE + tS + tN) * x[c];
+      if (ix > 0) v -= tW * x[c - 1];
+      if (ix + 1 < nx) v -= tE * x[c + 1];
+      if (iy > 0) v -= tS * x[c - nx];
+      if (iy + 1 < ny) v -= tN * x[c + nx];
+      y[c] = v;
+    }
+}
+
+namespace {
+
+// Data of one side of Gamma_i (faces in increasing coordinate).
+struct GammaSide {
+  int side;
+  std::vector<Face> faces;
+  std::vector<double> t, b, rho, Kin, Kout;
+};
+
+inline int loc_of(const Box& b, int cell, int nx) {
+  return (cell / nx - b.y0) * b.bx() + (cell % nx - b.x0);
+}
+
+GammaSide make_side(const HostSetup& S, const Box& b, int side) {
+  GammaSide g;
+  g.side = side;
+  g.faces = side_faces(b, side, S.nx);
+  for (const Face& f : g.faces) {
+    double t = f.kind == 0 ? txv(S, f.row, f.col) : tyv(S, f.row, f.col);
+    double Kin = S.K[f.inside], Kout = S.K[f.outside];
+    double bf = S.alpha * S.Lcells / t;
+    g.t.push_back(t);
+    g.b.push_back(bf);
+    g.rho.push_back(1.0 / (1.0 / (2.0 * Kin) + bf));
+    g.Kin.push_back(Kin);
+    g.Kout.push_back(Kout);
+  }
+  return g;
+}
+
+inline double xi_of(int j, int n) { return (2.0 * j + 1.0) / n - 1.0; }
+
+// Edge index across `side` of subdomain i, and whether i is its L subdomain.
+int edge_across(const Maps& M, int i, int side, bool& isL) {
+  const int I = i % M.mx, J = i / M.mx, nV = M.my * (M.mx - 1);
+  switch (side) {
+    case SE: isL = true; return J * (M.mx - 1) + I;
+    case SW: isL = false; return J * (M.mx - 1) + I - 1;
+    case SN: isL = true; return nV + J * M.mx + I;
+    default: isL = false; return nV + (J - 1) * M.mx + I;
+  }
+}
+
+struct SubResult {
+  // column contributions: for dof k of i, for each side s' of i and q': flux and pressure moments
+  std::vector<std::vector<std::vector<double>>> colU, colP;  // [k][side index][q']
+};
+
+}  // namespace
+
+void host_setup(HostSetup& S, const mrcm_grid& g, const mrcm_params& p, const double* K,
+                int nthreads) {
+  S.maps = build_maps(g, p);
+  const Maps& M = S.maps;
+  S.nx = g.nx;
+  S.ny = g.ny;
+  for (int s = 0; s < 4; ++s) S.bc[s] = g.bc[s];
+  S.noflow = !(g.bc[0] || g.bc[1] || g.bc[2] || g.bc[3]);
+  S.alpha = p.alpha;
+  S.Lcells = p.beta_len == 0 ? (double)std::max(p.sx, p.sy) : 1.0;
+  S.sweeps = p.smooth_sweeps;
+  const size_t n = (size_t)g.nx * g.ny;
+  S.K.assign(K, K + n);
+  for (size_t c = 0; c < n; ++c)
+    if (!(S.K[c] > 0.0) || !std::isfinite(S.K[c]))
+      throw Error(MRCM_EINVAL, "K must be finite and positive on every cell");
+  face_transmissibilities(S);
+  const int m = M.m, nb = M.degree + 1, nc = M.nc();
+  S.local.resize(m);
+  S.patch.resize(S.sweeps > 0 ? m : 0);
+  S.mbf.resize(m);
+  std::vector<SubResult> sub(m);
+  // weight offsets per dof
+  S.wOff.assign(nc + 1, 0);
+  for (int k = 0; k < nc; ++k)
+    S.wOff[k + 1] = S.wOff[k] + side_len(M.boxes[M.dofs[k][0]], M.dofs[k][1]);
+  S.wU.assign(S.wOff[nc], 0.0);
+  S.wP.assign(S.wOff[nc], 0.0);
+
+  int err_code = 0;
+  std::string err_msg;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+  for (int i = 0; i < m; ++i) {
+    try {
+      const Box& bi = M.boxes[i];
+      const Box& oi = M.oboxes[i];
+      S.local[i] = factor_box(S, bi, true);
+      if (S.sweeps > 0) S.patch[i] = factor_box(S, M.pboxes[i], false);
+      std::vector<GammaSide> gam;
+      for (int s : M.sides[i]) gam.push_back(make_side(S, bi, s));
+      const int Ni = M.dof_offset[i + 1] - M.dof_offset[i];
+      // oversampled problems -> informed multiplier functions phi_k on Gamma_i
+      BoxFactor of = factor_box(S, oi, true);
+      std::vector<std::vector<std::vector<double>>> phi(Ni);  // [k][side idx][face]
+      std::vector<double> ph((size_t)oi.bx() * oi.by());
+      for (int k = 0; k < Ni; ++k) {
+        const int ks = M.dofs[M.dof_offset[i] + k][1], kq = M.dofs[M.dof_offset[i] + k][2];
+        GammaSide os = make_side(S, oi, ks);
+        std::fill(ph.begin(), ph.end(), 0.0);
+        const int nf = (int)os.faces.size();
+        for (int j = 0; j < nf; ++j)
+          ph[loc_of(oi, os.faces[j].inside, S.nx)] += os.rho[j] * legendre(kq, xi_of(j, nf));
+        box_solve(of, ph.data());
+        phi[k].resize(gam.size());
+        for (size_t si = 0; si < gam.size(); ++si) {
+          const GammaSide& gs = gam[si];
+          const int nfs = (int)gs.faces.size();
+          phi[k][si].resize(nfs);
+          for (int j = 0; j < nfs; ++j) {
+            double pc = ph[loc_of(oi, gs.faces[j].inside, S.nx)], U, pi;
+            if (M.oversample == 0) {
+              double lam = gs.side == ks ? legendre(kq, xi_of(j, nfs)) : 0.0;
+              U = gs.rho[j] * (pc - lam);
+              pi = lam + gs.b[j] * U;
+            } else {
+              double pn = ph[loc_of(oi, gs.faces[j].outside, S.nx)];
+              U = gs.t[j] * (pc - pn);
+              pi = (gs.Kin[j] * pc + gs.Kout[j] * pn) / (gs.Kin[j] + gs.Kout[j]);
+            }
+            phi[k][si][j] = pi - gs.b[j] * U;
+          }
+        }
+      }
+      // multiscale basis functions and their trace moments (columns of C)
+      const size_t nloc = (size_t)bi.bx() * bi.by();
+      S.mbf[i].assign((size_t)Ni * nloc, 0.0);
+      sub[i].colU.assign(Ni, std::vector<std::vector<double>>(gam.size(), std::vector<double>(nb)));
+      sub[i].colP = sub[i].colU;
+      for (int k = 0; k < Ni; ++k) {
+        double* pk = &S.mbf[i][(size_t)k * nloc];
+        for (size_t si = 0; si < gam.size(); ++si)
+          for (size_t j = 0; j < gam[si].faces.size(); ++j)
+            pk[loc_of(bi, gam[si].faces[j].inside, S.nx)] += gam[si].rho[j] * phi[k][si][j];
+        box_solve(S.local[i], pk);
+        for (size_t si = 0; si < gam.size(); ++si) {
+          const GammaSide& gs = gam[si];
+          const int nfs = (int)gs.faces.size();
+          for (int j = 0; j < nfs; ++j) {
+            double pc = pk[loc_of(bi, gs.faces[j].inside, S.nx)];
+            double U = gs.rho[j] * (pc - phi[k][si][j]);
+            double pi = phi[k][si][j] + gs.b[j] * U;
+            for (int q = 0; q < M.nbasis(nfs); ++q) {
+              double w = legendre(q, xi_of(j, nfs));
+              sub[i].colU[k][si][q] += w * U;
+              sub[i].colP[k][si][q] += w * pi;
+            }
+          }
+        }
+      }
+      // coarse right-hand-side weights of the particular traces
+      for (int k = 0; k < Ni; ++k) {
+        const int dof = M.dof_offset[i] + k;
+        const int ks = M.dofs[dof][1], kq = M.dofs[dof][2];
+        size_t si = 0;
+        while (gam[si].side != ks) ++si;
+        const int nfs = (int)gam[si].faces.size();
+        for (int j = 0; j < nfs; ++j) {
+          double w = legendre(kq, xi_of(j, nfs));
+          S.wU[S.wOff[dof] + j] = gam[si].rho[j] * w;
+          S.wP[S.wOff[dof] + j] = gam[si].b[j] * gam[si].rho[j] * w;
+        }
+      }
+    } catch (const Error& e) {
+#pragma omp critical
+      {
+        if (!err_code) {
+          err_code = e.code;
+          err_msg = e.what();
+        }
+      }
+    }
+  }
+  if (err_code) throw Error(err_code, err_msg);
+
+  // coarse rows: the dofs of the L and R sides each row combines
+  const int E = (int)M.edges.size();
+  S.rowL.assign(nc, -1);
+  S.rowR.assign(nc, -1);
+  S.rowKind.assign(nc, 0);
+  for (int e = 0; e < E; ++e) {
+    const int L = M.edges[e][0], R = M.edges[e][1], o = M.edges[e][2];
+    const int sL = o == 0 ? SE : SN, sR = o == 0 ? SW : SS;
+    const int nb = M.nbasis(M.edges[e][4]);
+    for (int kind = 0; kind < 2; ++kind)
+      for (int q = 0; q < nb; ++q) {
+        int r = M.row_offset[e] + kind * nb + q;
+        S.rowL[r] = M.dof_of(L, sL, q);
+        S.rowR[r] = M.dof_of(R, sR, q);
+        S.rowKind[r] = kind;
+      }
+  }
+  // assemble C
+  std::vector<std::map<int, double>> rowsC(nc);
+  for (int i = 0; i < m; ++i) {
+    const int Ni = M.dof_offset[i + 1] - M.dof_offset[i];
+    for (int k = 0; k < Ni; ++k) {
+      const int col = M.dof_offset[i] + k;
+      for (size_t si = 0; si < M.sides[i].size(); ++si) {
+        bool isL;
+        const int e = edge_across(M, i, M.sides[i][si], isL);
+        const double sign = isL ? 1.0 : -1.0;
+        const int nb = M.nbasis(M.edges[e][4]);
+        for (int q = 0; q < nb; ++q) {
+          rowsC[M.row_offset[e] + q][col] += sub[i].colU[k][si][q];
+          rowsC[M.row_offset[e] + nb + q][col] += sign * sub[i].colP[k][si][q];
+        }
+      }
+    }
+  }
+  S.pin_row = -1;
+  S.pin_dof = -1;
+  if (S.noflow && E > 0) {
+    const int L0 = M.edges[0][0], o0 = M.edges[0][2];
+    S.pin_row = M.row_offset[0];
+    S.pin_dof = M.dof_of(L0, o0 == 0 ? SE : SN, 0);
+    rowsC[S.pin_row].clear();
+    rowsC[S.pin_row][S.pin_dof] = 1.0;
+  }
+  S.Crp.assign(nc + 1, 0);
+  S.Cci.clear();
+  S.Cv.clear();
+  for (int r = 0; r < nc; ++r) {
+    for (const auto& kv : rowsC[r]) {
+      S.Cci.push_back(kv.first);
+      S.Cv.push_back(kv.second);
+    }
+    S.Crp[r + 1] = (int)S.Cci.size();
+  }
+}
+
+}  // namespace mrcm

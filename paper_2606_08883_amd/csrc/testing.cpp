@@ -1,0 +1,142 @@
+// Test hooks (include/mrcm_testing.h): the host FP64 setup exposed for the
+// test suite, and a host evaluation of T from the uploaded data layout.
+#include "../../include/mrcm_testing.h"
+
+#include <omp.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "coarse.h"
+#include "setup.h"
+
+namespace {
+
+int fail(const mrcm::Error& e) {
+  mrcm::set_last_error(e.what());
+  return e.code;
+}
+
+mrcm::HostSetup make_setup(const mrcm_grid* g, const mrcm_params* p, const double* K) {
+  if (!g || !p || !K) throw mrcm::Error(MRCM_EINVAL, "null argument");
+  mrcm::HostSetup S;
+  mrcm::host_setup(S, *g, *p, K, std::max(1, omp_get_max_threads()));
+  return S;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mrcm_test_coarse_sizes(const mrcm_grid* grid, const mrcm_params* params, const double* K,
+                           int64_t* nc, int64_t* nnz) {
+  try {
+    mrcm::HostSetup S = make_setup(grid, params, K);
+    if (nc) *nc = S.maps.nc();
+    if (nnz) *nnz = (int64_t)S.Cv.size();
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    return fail(e);
+  }
+}
+
+int mrcm_test_coarse_matrix(const mrcm_grid* grid, const mrcm_params* params, const double* K,
+                            int32_t* rp, int32_t* ci, double* cv) {
+  try {
+    mrcm::HostSetup S = make_setup(grid, params, K);
+    std::copy(S.Crp.begin(), S.Crp.end(), rp);
+    std::copy(S.Cci.begin(), S.Cci.end(), ci);
+    std::copy(S.Cv.begin(), S.Cv.end(), cv);
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    return fail(e);
+  }
+}
+
+int mrcm_test_host_apply(const mrcm_grid* grid, const mrcm_params* params, const double* K,
+                         const double* r, double* z, double* min_pivot_ratio) {
+  try {
+    mrcm::HostSetup S = make_setup(grid, params, K);
+    const mrcm::Maps& M = S.maps;
+    mrcm::CoarseFactor CF =
+        mrcm::coarse_factor(M, S.Crp, S.Cci, S.Cv, std::max(1, omp_get_max_threads()));
+    if (min_pivot_ratio) *min_pivot_ratio = CF.min_pivot_ratio;
+    const int nx = S.nx;
+    const size_t n = (size_t)S.nx * S.ny;
+    const int nc = M.nc();
+    std::vector<double> p(n, 0.0), mU(nc), mP(nc), g(nc), xc(nc);
+    auto gather = [&](const mrcm::Box& b, const double* v, std::vector<double>& x) {
+      x.assign((size_t)b.bx() * b.by(), 0.0);
+      for (int j = 0; j < b.by(); ++j)
+        for (int a = 0; a < b.bx(); ++a) x[(size_t)j * b.bx() + a] = v[(size_t)(b.y0 + j) * nx + b.x0 + a];
+    };
+    std::vector<double> x;
+    for (int i = 0; i < M.m; ++i) {
+      const mrcm::Box& b = M.boxes[i];
+      gather(b, r, x);
+      mrcm::box_solve(S.local[i], x.data());
+      for (int j = 0; j < b.by(); ++j)
+        for (int a = 0; a < b.bx(); ++a) p[(size_t)(b.y0 + j) * nx + b.x0 + a] = x[(size_t)j * b.bx() + a];
+      for (int k = M.dof_offset[i]; k < M.dof_offset[i + 1]; ++k) {
+        const int side = M.dofs[k][1];
+        const int len = mrcm::side_len(b, side);
+        double su = 0.0, sp = 0.0;
+        for (int jf = 0; jf < len; ++jf) {
+          int cell = side == 0 ? jf * b.bx()
+                   : side == 1 ? jf * b.bx() + b.bx() - 1
+                   : side == 2 ? jf
+                               : (b.by() - 1) * b.bx() + jf;
+          su += S.wU[S.wOff[k] + jf] * x[cell];
+          sp += S.wP[S.wOff[k] + jf] * x[cell];
+        }
+        mU[k] = su;
+        mP[k] = sp;
+      }
+    }
+    if (nc > 0) {
+      for (int rr = 0; rr < nc; ++rr) {
+        const int L = S.rowL[rr], R = S.rowR[rr];
+        g[rr] = S.rowKind[rr] == 0 ? -(mU[L] + mU[R]) : -(mP[L] - mP[R]);
+        if (rr == S.pin_row) g[rr] = 0.0;
+      }
+      mrcm::coarse_solve_host(CF, g.data(), xc.data());
+      for (int i = 0; i < M.m; ++i) {
+        const mrcm::Box& b = M.boxes[i];
+        const int ncell = b.bx() * b.by();
+        for (int q = 0; q < ncell; ++q) {
+          double s = 0.0;
+          for (int k = 0; k < M.dof_offset[i + 1] - M.dof_offset[i]; ++k)
+            s += S.mbf[i][(size_t)k * ncell + q] * xc[M.dof_offset[i] + k];
+          p[(size_t)(b.y0 + q / b.bx()) * nx + b.x0 + q % b.bx()] += s;
+        }
+      }
+    }
+    std::vector<double> rho(n);
+    for (int sweep = 0; sweep < S.sweeps; ++sweep) {
+      mrcm::host_op_apply(S, p.data(), rho.data());
+      for (size_t c = 0; c < n; ++c) rho[c] = r[c] - rho[c];
+      for (int i = 0; i < M.m; ++i) {
+        const mrcm::Box& pb = M.pboxes[i];
+        const mrcm::Box& b = M.boxes[i];
+        gather(pb, rho.data(), x);
+        mrcm::box_solve(S.patch[i], x.data());
+        for (int y = b.y0; y < b.y1; ++y)
+          for (int xx = b.x0; xx < b.x1; ++xx)
+            p[(size_t)y * nx + xx] += x[(size_t)(y - pb.y0) * pb.bx() + xx - pb.x0];
+      }
+    }
+    double mean = 0.0;
+    if (S.noflow) {
+      for (size_t c = 0; c < n; ++c) mean += p[c];
+      mean /= (double)n;
+    }
+    for (size_t c = 0; c < n; ++c) z[c] = p[c] - mean;
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    return fail(e);
+  }
+}
+
+}  // extern "C"
