@@ -45,7 +45,7 @@ enum {
   MRCM_EINVAL = -1,    /* bad sizes or parameters, K not finite or not > 0 */
   MRCM_ENOMEM = -2,    /* host or device allocation failed */
   MRCM_ESINGULAR = -3, /* non-positive pivot in a local factorisation, or a
-                          singular block of the interface system */
+                          zero pivot in the interface system */
   MRCM_ENOCONV = -4,   /* gmres_solve reached maxit; p and stats are written */
   MRCM_EDEVICE = -5    /* a HIP runtime call failed */
 };
@@ -171,6 +171,22 @@ int mrcm_timing_enable(mrcm_ctx* ctx, int32_t on);
  * mrcm_timing_enable(ctx, 1): ms[6], counts[6], host.  Waits for the recorded
  * events. */
 int mrcm_timing_read(mrcm_ctx* ctx, double* ms, int64_t* counts);
+
+/* Scalar facts about a set-up context, by `what`:
+ *  MRCM_Q_SETUP_SECONDS   wall time of mrcm_setup;
+ *  MRCM_Q_DEVICE_BYTES    device memory the context holds;
+ *  MRCM_Q_COARSE_PIVOT    smallest |pivot| / max|row| met while factorising the
+ *                         row-equilibrated interface system (its conditioning);
+ *  MRCM_Q_COARSE_LEVELS   levels of the nested-dissection interface solve;
+ *  MRCM_Q_COARSE_DOFS     interface unknowns nc. */
+enum {
+  MRCM_Q_SETUP_SECONDS = 0,
+  MRCM_Q_DEVICE_BYTES = 1,
+  MRCM_Q_COARSE_PIVOT = 2,
+  MRCM_Q_COARSE_LEVELS = 3,
+  MRCM_Q_COARSE_DOFS = 4
+};
+int mrcm_query(mrcm_ctx* ctx, int32_t what, double* value);
 
 /* Release a context and all device memory it owns (NULL is ignored). */
 void mrcm_destroy(mrcm_ctx* ctx);

@@ -22,7 +22,9 @@ _NAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "ESINGULAR", -4: "ENOCONV", -5: "EDEVI
 # Every symbol the headers declare (checked by the test suite).
 EXPORTED = ["mrcm_map_sizes", "mrcm_maps", "mrcm_setup", "mrcm_apply", "op_apply", "gmres_solve",
             "mrcm_rhs", "mrcm_footprint", "mrcm_timing_enable", "mrcm_timing_read",
-            "mrcm_destroy", "mrcm_last_error"]
+            "mrcm_query", "mrcm_destroy", "mrcm_last_error"]
+QUERIES = {"setup_seconds": 0, "device_bytes": 1, "coarse_pivot": 2, "coarse_levels": 3,
+           "coarse_dofs": 4}
 PHASES = ["local", "coarse", "reconstruct", "residual", "patch", "finalize"]
 TEST_EXPORTED = ["mrcm_test_coarse_sizes", "mrcm_test_coarse_matrix", "mrcm_test_host_apply"]
 
@@ -78,6 +80,7 @@ def lib() -> ctypes.CDLL:
             "mrcm_footprint": ([pG, pP, i32], ctypes.c_size_t),
             "mrcm_timing_enable": ([P, i32], i32),
             "mrcm_timing_read": ([P, pd, pi64], i32),
+            "mrcm_query": ([P, i32, pd], i32),
             "mrcm_destroy": ([P], None),
             "mrcm_last_error": ([], ctypes.c_char_p),
             "mrcm_test_coarse_sizes": ([pG, pP, pd, pi64, pi64], i32),
@@ -236,6 +239,12 @@ class Context:
         if t.numel() % self.n:
             raise ValueError("vector length is not a multiple of the cell count")
         return t.numel() // self.n
+
+    def query(self, what: str) -> float:
+        """mrcm_query: setup_seconds, device_bytes, coarse_pivot, coarse_levels, coarse_dofs."""
+        v = ctypes.c_double()
+        _check(lib().mrcm_query(self._ptr, QUERIES[what], ctypes.byref(v)))
+        return v.value
 
     def timing(self, on: bool):
         """Start (and clear) or stop per-phase event timing (mrcm_timing_enable)."""

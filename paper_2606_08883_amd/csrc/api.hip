@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -48,7 +49,7 @@ struct mrcm_ctx {
   int nx = 0, ny = 0, bc[4] = {0, 0, 0, 0}, noflow = 0, precision = 0, sweeps = 0;
   int m = 0, nc = 0, pin_row = -1;
   long long n = 0;
-  int max_cells_local = 0, max_cells_patch = 0;
+  int max_cells_local = 0, max_cells_patch = 0, max_bx_local = 0, max_bx_patch = 0;
   int max_nf = 0, max_nu = 0;
   std::vector<void*> allocs;
   // fine operator
@@ -66,7 +67,9 @@ struct mrcm_ctx {
   // coarse factor
   mrcm::CNodeDesc* cnodes = nullptr;
   double *cfwd = nullptr, *cbwd = nullptr;
-  int *cidx = nullptr, *pull_ptr = nullptr, *pull_idx = nullptr;
+  int *cidx = nullptr, *nd_row = nullptr, *slots = nullptr;
+  double* nd_scale = nullptr;
+  int maxp = 4;
   mrcm::CChunk* chunks = nullptr;
   std::vector<std::pair<int, int>> fwd_levels, bwd_levels;  // (first chunk, count)
   // work space
@@ -78,14 +81,30 @@ struct mrcm_ctx {
   double *V = nullptr, *Z = nullptr, *hcol = nullptr, *parts = nullptr, *yd = nullptr;
   double *h_host = nullptr;  // pinned: partials / Hessenberg column / y
   double setup_seconds = 0.0;
+  double coarse_pivot = 1.0;
+  int coarse_levels = 0;
+  size_t device_bytes = 0;
   // per-phase event timing
   static constexpr int kPhases = 6;
+  using Mark = std::pair<int, std::pair<hipEvent_t, hipEvent_t>>;  // phase, (start, end)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  std::vector<std::pair<int, std::pair<size_t, size_t>>> ev_marks;  // phase, (start, end)
+  std::vector<Mark> ev_marks;
   double phase_ms[kPhases] = {0, 0, 0, 0, 0, 0};
   long long phase_n[kPhases] = {0, 0, 0, 0, 0, 0};
+  // One captured Arnoldi step (T apply, A z, Gram-Schmidt, normalisation) per
+  // Krylov index; events recorded inside it belong to the graph.
+  struct StepGraph {
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipEvent_t> owned;
+    std::vector<Mark> marks;
+  };
+  bool use_graphs = true;
+  std::vector<StepGraph> graphs;
+  StepGraph* capturing = nullptr;
+  hipStream_t ws = nullptr;  // context stream for GMRES (graphs cannot capture the null stream)
+  hipEvent_t ws_in = nullptr;
 
   template <typename X>
   X* alloc(size_t count) {
@@ -93,6 +112,7 @@ struct mrcm_ctx {
     if (count == 0) count = 1;
     hip_check(hipMalloc(&p, count * sizeof(X)), "hipMalloc");
     allocs.push_back(p);
+    device_bytes += count * sizeof(X);
     return static_cast<X*>(p);
   }
   template <typename X>
@@ -103,30 +123,51 @@ struct mrcm_ctx {
                 "hipMemcpyAsync");
     return d;
   }
-  // Record an event on stream s; returns its pool index.
-  size_t mark(hipStream_t s) {
-    if (ev_used == ev_pool.size()) {
-      hipEvent_t e;
+  // Record an event on stream s (a graph node while capturing).
+  hipEvent_t mark(hipStream_t s) {
+    hipEvent_t e;
+    if (capturing) {
       hip_check(hipEventCreate(&e), "hipEventCreate");
-      ev_pool.push_back(e);
+      capturing->owned.push_back(e);
+    } else {
+      if (ev_used == ev_pool.size()) {
+        hip_check(hipEventCreate(&e), "hipEventCreate");
+        ev_pool.push_back(e);
+      }
+      e = ev_pool[ev_used++];
     }
-    hip_check(hipEventRecord(ev_pool[ev_used], s), "hipEventRecord");
-    return ev_used++;
+    hip_check(hipEventRecord(e, s), "hipEventRecord");
+    return e;
   }
-  // Fold the elapsed times of completed event pairs into the accumulators.
-  void fold_timing() {
-    for (const auto& m : ev_marks) {
+  void add_mark(int phase, hipEvent_t a, hipEvent_t b) {
+    (capturing ? capturing->marks : ev_marks).push_back({phase, {a, b}});
+  }
+  void fold(const std::vector<Mark>& marks) {
+    for (const auto& m : marks) {
       float ms = 0.0f;
-      hip_check(hipEventSynchronize(ev_pool[m.second.second]), "hipEventSynchronize");
-      hip_check(hipEventElapsedTime(&ms, ev_pool[m.second.first], ev_pool[m.second.second]),
-                "hipEventElapsedTime");
+      hip_check(hipEventSynchronize(m.second.second), "hipEventSynchronize");
+      hip_check(hipEventElapsedTime(&ms, m.second.first, m.second.second), "hipEventElapsedTime");
       phase_ms[m.first] += ms;
       phase_n[m.first] += 1;
     }
+  }
+  // Fold the elapsed times of completed eager event pairs into the accumulators.
+  void fold_timing() {
+    fold(ev_marks);
     ev_marks.clear();
     ev_used = 0;
   }
+  void drop_graphs() {
+    for (auto& g : graphs) {
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      for (hipEvent_t e : g.owned) (void)hipEventDestroy(e);
+    }
+    graphs.clear();
+  }
   ~mrcm_ctx() {
+    drop_graphs();
+    if (ws) (void)hipStreamDestroy(ws);
+    if (ws_in) (void)hipEventDestroy(ws_in);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
     if (h_host) (void)hipHostFree(h_host);
@@ -150,10 +191,10 @@ std::vector<T> narrow(const std::vector<double>& v) {
 template <typename T>
 void upload_boxes(mrcm_ctx* c, const std::vector<mrcm::BoxFactor>& F,
                   const std::vector<mrcm::Box>& owned, BoxDesc** desc, void** dinv, void** coup,
-                  int* max_cells, hipStream_t s) {
+                  int* max_cells, int* max_bx, hipStream_t s) {
   std::vector<BoxDesc> d(F.size());
   long long nd = 0, ncp = 0;
-  int mc = 0;
+  int mc = 0, mb = 0;
   for (size_t i = 0; i < F.size(); ++i) {
     const mrcm::Box& b = F[i].box;
     const mrcm::Box& o = owned[i];
@@ -162,10 +203,11 @@ void upload_boxes(mrcm_ctx* c, const std::vector<mrcm::BoxFactor>& F,
     nd += (long long)F[i].dinv.size();
     ncp += (long long)F[i].coup.size();
     mc = std::max(mc, b.bx() * b.by());
-    if (b.bx() > mrcm::kBoxThreads)
-      throw mrcm::Error(MRCM_EINVAL, "box wider than 256 cells is not supported");
+    mb = std::max(mb, b.bx());
   }
-  if ((size_t)mc * sizeof(T) + mrcm::kBoxThreads * sizeof(T) > 60 * 1024)
+  if (mb > 64)
+    throw mrcm::Error(MRCM_EINVAL, "subdomains and smoothing patches must be at most 64 cells wide");
+  if (mrcm::box_lds_bytes(mb, mc, sizeof(T)) > 64 * 1024)
     throw mrcm::Error(MRCM_EINVAL, "subdomain or patch too large for the LDS of one workgroup");
   std::vector<T> hd((size_t)nd), hc((size_t)ncp);
   for (size_t i = 0; i < F.size(); ++i) {
@@ -178,6 +220,7 @@ void upload_boxes(mrcm_ctx* c, const std::vector<mrcm::BoxFactor>& F,
   *dinv = c->upload(hd, s);
   *coup = c->upload(hc, s);
   *max_cells = mc;
+  *max_bx = mb;
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
@@ -209,7 +252,7 @@ void upload_coarse(mrcm_ctx* c, const mrcm::CoarseFactor& F, hipStream_t s) {
   if (max_nf > 6144 || max_nu > 6144)
     throw mrcm::Error(MRCM_EINVAL, "interface separator too large for one workgroup");
   // level chunks: forward deepest level first, backward root first
-  constexpr int kRowsPerChunk = 32;
+  constexpr int kRowsPerChunk = 16;
   std::vector<CChunk> chunks;
   c->fwd_levels.clear();
   c->bwd_levels.clear();
@@ -237,8 +280,10 @@ void upload_coarse(mrcm_ctx* c, const mrcm::CoarseFactor& F, hipStream_t s) {
   c->cfwd = c->upload(fwd, s);
   c->cbwd = c->upload(bwd, s);
   c->cidx = c->upload(idx, s);
-  c->pull_ptr = c->upload(F.pull_ptr, s);
-  c->pull_idx = c->upload(F.pull_idx, s);
+  c->nd_row = c->upload(F.nd_row, s);
+  c->nd_scale = c->upload(F.nd_scale, s);
+  c->slots = c->upload(F.slots, s);
+  c->maxp = F.maxp;
   c->chunks = c->upload(chunks, s);
   c->ybuf = c->alloc<double>(F.ylen);
   c->cbuf = c->alloc<double>(F.clen);
@@ -251,25 +296,26 @@ template <typename T>
 void apply_one(mrcm_ctx* c, const double* r, double* z, hipStream_t s) {
   T* p = static_cast<T*>(c->pT);
   T* rho = static_cast<T*>(c->rhoT);
-  size_t e0 = 0;
+  hipEvent_t e0 = nullptr;
   auto begin = [&]() {
     if (c->timing) e0 = c->mark(s);
   };
   auto end = [&](int phase) {
-    if (c->timing) c->ev_marks.push_back({phase, {e0, c->mark(s)}});
+    if (c->timing) c->add_mark(phase, e0, c->mark(s));
   };
   begin();
-  mrcm::launch_local<T>(c->lbox, c->m, c->max_cells_local, static_cast<const T*>(c->ldinv),
+  mrcm::launch_local<T>(c->lbox, c->m, c->max_cells_local, c->max_bx_local,
+                        static_cast<const T*>(c->ldinv),
                         static_cast<const T*>(c->lcoup), r, p, c->nx, c->dof_off, c->dof_side,
                         c->w_off, c->wU, c->wP, c->mU, c->mP, s);
   end(0);
   if (c->nc > 0) {
     begin();
-    mrcm::launch_coarse_rhs(c->mU, c->mP, c->rowL, c->rowR, c->rowKind, c->nc, c->pin_row, c->g,
-                            s);
+    mrcm::launch_coarse_rhs(c->nd_row, c->nd_scale, c->rowL, c->rowR, c->rowKind, c->pin_row,
+                            c->mU, c->mP, c->g, c->nc, s);
     for (const auto& lv : c->fwd_levels)
-      mrcm::launch_coarse_fwd(c->chunks + lv.first, lv.second, c->cnodes, c->cfwd, c->cidx,
-                              c->pull_ptr, c->pull_idx, c->g, c->ybuf, c->cbuf, c->max_nf, s);
+      mrcm::launch_coarse_fwd(c->chunks + lv.first, lv.second, c->cnodes, c->cfwd, c->g,
+                              c->slots, c->maxp, c->ybuf, c->cbuf, c->max_nf, s);
     for (const auto& lv : c->bwd_levels)
       mrcm::launch_coarse_bwd(c->chunks + lv.first, lv.second, c->cnodes, c->cbwd, c->cidx,
                               c->ybuf, c->xc, c->max_nu, s);
@@ -285,7 +331,8 @@ void apply_one(mrcm_ctx* c, const double* r, double* z, hipStream_t s) {
                              c->ny, r, p, rho, s);
     end(3);
     begin();
-    mrcm::launch_patch<T>(c->pbox, c->m, c->max_cells_patch, static_cast<const T*>(c->pdinv),
+    mrcm::launch_patch<T>(c->pbox, c->m, c->max_cells_patch, c->max_bx_patch,
+                          static_cast<const T*>(c->pdinv),
                           static_cast<const T*>(c->pcoup), rho, p, c->nx, s);
     end(4);
   }
@@ -304,9 +351,11 @@ void apply_dispatch(mrcm_ctx* c, const double* r, double* z, hipStream_t s) {
 template <typename X>
 void setup_precision(mrcm_ctx* c, const mrcm::HostSetup& S, hipStream_t s) {
   const mrcm::Maps& M = S.maps;
-  upload_boxes<X>(c, S.local, M.boxes, &c->lbox, &c->ldinv, &c->lcoup, &c->max_cells_local, s);
+  upload_boxes<X>(c, S.local, M.boxes, &c->lbox, &c->ldinv, &c->lcoup, &c->max_cells_local,
+                  &c->max_bx_local, s);
   if (S.sweeps > 0)
-    upload_boxes<X>(c, S.patch, M.boxes, &c->pbox, &c->pdinv, &c->pcoup, &c->max_cells_patch, s);
+    upload_boxes<X>(c, S.patch, M.boxes, &c->pbox, &c->pdinv, &c->pcoup, &c->max_cells_patch,
+                    &c->max_bx_patch, s);
   std::vector<X> mbf;
   std::vector<long long> off;
   for (int i = 0; i < M.m; ++i) {
@@ -329,11 +378,80 @@ void setup_precision(mrcm_ctx* c, const mrcm::HostSetup& S, hipStream_t s) {
 
 void ensure_krylov(mrcm_ctx* c, int restart) {
   if (restart <= c->krylov_cap) return;
+  c->drop_graphs();
   c->V = c->alloc<double>((size_t)(restart + 1) * c->n);
   c->Z = c->alloc<double>((size_t)restart * c->n);
   c->hcol = c->alloc<double>(restart + 2);
   c->yd = c->alloc<double>(restart + 1);
   c->krylov_cap = restart;
+}
+
+// One Arnoldi step of Algorithm 1: z_j = T v_j, w = A z_j, modified
+// Gram-Schmidt against v_0..v_j, h_{j+1,j} = ||w||, v_{j+1} = w / h_{j+1,j}.
+// The Hessenberg column is left in c->hcol (j + 2 values).
+void arnoldi_step(mrcm_ctx* c, int j, int nb, hipStream_t s) {
+  const long long n = c->n;
+  double* vj = c->V + (size_t)j * n;
+  double* zj = c->Z + (size_t)j * n;
+  double* w = c->V + (size_t)(j + 1) * n;
+  apply_dispatch(c, vj, zj, s);
+  mrcm::launch_arnoldi_start(c->tx, c->ty, c->nx, c->ny, zj, w, c->V, c->parts, nb, s);
+  for (int i = 0; i <= j; ++i)
+    mrcm::launch_mgs_step(c->parts + (i % 2) * mrcm::kMaxVecBlocks,
+                          c->parts + ((i + 1) % 2) * mrcm::kMaxVecBlocks, nb, c->hcol, i, w,
+                          c->V + (size_t)i * n, i < j ? c->V + (size_t)(i + 1) * n : nullptr, n,
+                          s);
+  mrcm::launch_norm_scale(c->parts + ((j + 1) % 2) * mrcm::kMaxVecBlocks, nb, c->hcol, j + 1, w,
+                          n, s);
+}
+
+// The captured graph of Arnoldi step j (captured on first use); nullptr when
+// capture is unavailable or timing is on, in which case the caller launches
+// eagerly.
+mrcm_ctx::StepGraph* step_graph(mrcm_ctx* c, int j, int nb) {
+  // Per-phase timing reads events recorded between eager launches; events
+  // recorded as graph nodes cannot be queried for elapsed time.
+  if (!c->use_graphs || c->timing) return nullptr;
+  if ((int)c->graphs.size() < c->krylov_cap) c->graphs.resize(c->krylov_cap);
+  mrcm_ctx::StepGraph& g = c->graphs[j];
+  if (g.exec) return &g;
+  hipGraph_t graph = nullptr;
+  if (hipStreamBeginCapture(c->ws, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    c->use_graphs = false;
+    return nullptr;
+  }
+  c->capturing = &g;
+  bool ok = true;
+  try {
+    arnoldi_step(c, j, nb, c->ws);
+  } catch (const mrcm::Error&) {
+    ok = false;  // an operation this runtime cannot capture: run eagerly from now on
+  }
+  c->capturing = nullptr;
+  if (!ok) {
+    (void)hipStreamEndCapture(c->ws, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    for (hipEvent_t e : g.owned) (void)hipEventDestroy(e);
+    g.owned.clear();
+    g.marks.clear();
+    c->use_graphs = false;
+    return nullptr;
+  }
+  hipError_t e1 = hipStreamEndCapture(c->ws, &graph);
+  hipError_t e2 = e1 == hipSuccess ? hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) : e1;
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e2 != hipSuccess) {
+    (void)hipGetLastError();
+    g.exec = nullptr;
+    for (hipEvent_t e : g.owned) (void)hipEventDestroy(e);
+    g.owned.clear();
+    g.marks.clear();
+    c->use_graphs = false;
+    return nullptr;
+  }
+  return &g;
 }
 
 double host_sum(const double* v, int nb) {
@@ -456,9 +574,15 @@ int mrcm_setup(const mrcm_grid* grid, const mrcm_params* params, const double* K
     c->partials = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
     c->parts = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
     upload_coarse(c, CF, s);
+    c->coarse_pivot = CF.min_pivot_ratio;
+    c->coarse_levels = CF.nodes.empty() ? 0 : CF.depth + 1;
     hip_check(hipHostMalloc((void**)&c->h_host, sizeof(double) * (mrcm::kMaxVecBlocks + 64),
                             hipHostMallocDefault),
               "hipHostMalloc");
+    hip_check(hipStreamCreateWithFlags(&c->ws, hipStreamNonBlocking), "hipStreamCreate");
+    hip_check(hipEventCreateWithFlags(&c->ws_in, hipEventDisableTiming), "hipEventCreate");
+    const char* ge = std::getenv("MRCM_GRAPHS");
+    c->use_graphs = !(ge && ge[0] == '0');
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     c->setup_seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -540,8 +664,12 @@ int gmres_solve(mrcm_ctx* c, const double* b, double* p, int32_t nrhs, double rt
       return MRCM_OK;
     }
     if (!b || !p) throw mrcm::Error(MRCM_EINVAL, "null vector");
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipStream_t cs_ = static_cast<hipStream_t>(stream);
     ensure_krylov(c, restart);
+    // all GMRES work runs on the context stream, ordered after the caller's
+    hip_check(hipEventRecord(c->ws_in, cs_), "hipEventRecord");
+    hip_check(hipStreamWaitEvent(c->ws, c->ws_in, 0), "hipStreamWaitEvent");
+    hipStream_t s = c->ws;
     const long long n = c->n;
     const int nb = mrcm::vec_blocks(n);
     double* hh = c->h_host;
@@ -587,19 +715,13 @@ int gmres_solve(mrcm_ctx* c, const double* b, double* p, int32_t nrhs, double rt
         gv[0] = beta;
         int jj = 0;
         for (int j = 0; j < restart; ++j) {
-          double* vj = c->V + (size_t)j * n;
-          double* zj = c->Z + (size_t)j * n;
-          double* w = c->V + (size_t)(j + 1) * n;
-          apply_dispatch(c, vj, zj, s);
-          mrcm::launch_arnoldi_start(c->tx, c->ty, c->nx, c->ny, zj, w, c->V, c->parts, nb, s);
-          for (int i = 0; i <= j; ++i)
-            mrcm::launch_mgs_step(c->parts + (i % 2) * mrcm::kMaxVecBlocks,
-                                  c->parts + ((i + 1) % 2) * mrcm::kMaxVecBlocks, nb, c->hcol, i,
-                                  w, c->V + (size_t)i * n,
-                                  i < j ? c->V + (size_t)(i + 1) * n : nullptr, n, s);
-          mrcm::launch_norm_scale(c->parts + ((j + 1) % 2) * mrcm::kMaxVecBlocks, nb, c->hcol,
-                                  j + 1, w, n, s);
+          mrcm_ctx::StepGraph* sg = step_graph(c, j, nb);
+          if (sg)
+            hip_check(hipGraphLaunch(sg->exec, s), "hipGraphLaunch");
+          else
+            arnoldi_step(c, j, nb, s);
           fetch(c->hcol, j + 2);
+          if (sg && c->timing) c->fold(sg->marks);
           ++it;
           for (int i = 0; i <= j + 1; ++i) H[(size_t)i * restart + j] = hh[i];
           const double hnext = hh[j + 1];
@@ -688,6 +810,7 @@ int mrcm_timing_enable(mrcm_ctx* c, int32_t on) {
   try {
     if (!c) throw mrcm::Error(MRCM_EINVAL, "null context");
     if (c->timing) c->fold_timing();
+    if ((on != 0) != c->timing) c->drop_graphs();
     c->timing = on != 0;
     if (on)
       for (int k = 0; k < mrcm_ctx::kPhases; ++k) {
@@ -708,6 +831,24 @@ int mrcm_timing_read(mrcm_ctx* c, double* ms, int64_t* counts) {
     for (int k = 0; k < mrcm_ctx::kPhases; ++k) {
       ms[k] = c->phase_ms[k];
       counts[k] = c->phase_n[k];
+    }
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    set_error(e.what());
+    return e.code;
+  }
+}
+
+int mrcm_query(mrcm_ctx* c, int32_t what, double* value) {
+  try {
+    if (!c || !value) throw mrcm::Error(MRCM_EINVAL, "null argument");
+    switch (what) {
+      case MRCM_Q_SETUP_SECONDS: *value = c->setup_seconds; break;
+      case MRCM_Q_DEVICE_BYTES: *value = (double)c->device_bytes; break;
+      case MRCM_Q_COARSE_PIVOT: *value = c->coarse_pivot; break;
+      case MRCM_Q_COARSE_LEVELS: *value = c->coarse_levels; break;
+      case MRCM_Q_COARSE_DOFS: *value = c->nc; break;
+      default: throw mrcm::Error(MRCM_EINVAL, "unknown query");
     }
     return MRCM_OK;
   } catch (const mrcm::Error& e) {

@@ -13,7 +13,7 @@ namespace mrcm {
 
 namespace {
 
-constexpr int kLeafArea = 4;  // boxes of at most this many subdomains are eliminated whole
+constexpr int kLeafArea = 16;  // boxes of at most this many subdomains are eliminated whole
 
 struct TreeNode {
   std::vector<int> fsub, usub;
@@ -102,10 +102,7 @@ CoarseFactor coarse_factor(const Maps& M, const std::vector<int>& rp, const std:
   CoarseFactor F;
   const int nc = M.nc();
   F.nc = nc;
-  if (nc == 0) {
-    F.pull_ptr.assign(1, 0);
-    return F;
-  }
+  if (nc == 0) return F;
   // rows owned by each subdomain: flux rows -> L, pressure rows -> R
   std::vector<std::vector<int>> rows_of(M.m);
   for (int r = 0; r < nc; ++r) {
@@ -168,6 +165,18 @@ CoarseFactor coarse_factor(const Maps& M, const std::vector<int>& rp, const std:
     }
   }
   F.depth = maxdepth;
+  // row equilibration: every row of C scaled to unit max-norm (the solve scales
+  // g the same way), so pivot tests do not depend on the units of flux and
+  // pressure rows, which differ by the permeability contrast
+  F.rscale.assign(nc, 1.0);
+  std::vector<double> cvs(cv);
+  for (int r = 0; r < nc; ++r) {
+    double mx = 0.0;
+    for (int q = rp[r]; q < rp[r + 1]; ++q) mx = std::max(mx, std::fabs(cv[q]));
+    if (!(mx > 0.0)) throw Error(MRCM_ESINGULAR, "zero row in the interface system");
+    F.rscale[r] = 1.0 / mx;
+    for (int q = rp[r]; q < rp[r + 1]; ++q) cvs[q] = cv[q] * F.rscale[r];
+  }
   // factor level by level, deepest first; update matrices are passed to parents
   std::vector<std::vector<double>> update(nn);
   std::vector<std::vector<int>> by_depth(maxdepth + 1);
@@ -203,7 +212,7 @@ CoarseFactor coarse_factor(const Maps& M, const std::vector<int>& rp, const std:
           const int b = cpos[ci[q]];
           if (b < 0) continue;
           if (a >= nf && b >= nf) continue;  // both later: assembled at an ancestor
-          Fm[(size_t)a * nt + b] += cv[q];
+          Fm[(size_t)a * nt + b] += cvs[q];
         }
       }
       for (int ch : tree[t].children) {
@@ -226,7 +235,7 @@ CoarseFactor coarse_factor(const Maps& M, const std::vector<int>& rp, const std:
       for (int a = 0; a < nf; ++a)
         for (int b = 0; b < nf; ++b) Aff[(size_t)a * nf + b] = Fm[(size_t)a * nt + b];
       const double ratio = lu_inverse(Aff, nf, Winv);
-      if (!(ratio > 1e-14)) {
+      if (!(ratio > 0.0)) {  // exact zero or non-finite pivot
 #pragma omp atomic write
         failed = 1;
         continue;
@@ -266,15 +275,23 @@ CoarseFactor coarse_factor(const Maps& M, const std::vector<int>& rp, const std:
   std::vector<std::vector<int>> pulls(nc);
   for (const auto& cn : F.nodes)
     for (size_t u = 0; u < cn.urow.size(); ++u) pulls[cn.urow[u]].push_back(cn.coff + (int)u);
-  F.pull_ptr.assign(nc + 1, 0);
-  for (int r = 0; r < nc; ++r) {
-    F.pull_ptr[r + 1] = F.pull_ptr[r] + (int)pulls[r].size();
-    F.pull_idx.insert(F.pull_idx.end(), pulls[r].begin(), pulls[r].end());
-  }
+  size_t mp = 1;
+  for (const auto& pl : pulls) mp = std::max(mp, pl.size());
+  F.maxp = (int)((mp + 3) / 4 * 4);
+  F.nd_row.assign(nc, -1);
+  F.nd_scale.assign(nc, 1.0);
+  F.slots.assign((size_t)nc * F.maxp, -1);
+  for (const auto& cn : F.nodes)
+    for (size_t a = 0; a < cn.frow.size(); ++a) {
+      const int t = cn.yoff + (int)a, r = cn.frow[a];
+      F.nd_row[t] = r;
+      F.nd_scale[t] = F.rscale[r];
+      for (size_t u = 0; u < pulls[r].size(); ++u) F.slots[(size_t)t * F.maxp + u] = pulls[r][u];
+    }
   return F;
 }
 
-void coarse_solve_host(const CoarseFactor& F, const double* g, double* x) {
+void coarse_solve_host(const CoarseFactor& F, const double* g_nd, double* x) {
   std::vector<double> ybuf(F.ylen), cbuf(F.clen);
   for (int d = F.depth; d >= 0; --d)
     for (const auto& cn : F.nodes) {
@@ -282,9 +299,12 @@ void coarse_solve_host(const CoarseFactor& F, const double* g, double* x) {
       const int nf = (int)cn.frow.size(), nu = (int)cn.urow.size();
       std::vector<double> v(nf);
       for (int a = 0; a < nf; ++a) {
-        const int r = cn.frow[a];
-        double s = g[r];
-        for (int q = F.pull_ptr[r]; q < F.pull_ptr[r + 1]; ++q) s -= cbuf[F.pull_idx[q]];
+        const size_t t = (size_t)cn.yoff + a;
+        double s = g_nd[t];
+        for (int u = 0; u < F.maxp; ++u) {
+          const int q = F.slots[t * F.maxp + u];
+          if (q >= 0) s -= cbuf[q];
+        }
         v[a] = s;
       }
       for (int a = 0; a < nf + nu; ++a) {

@@ -34,8 +34,16 @@ struct CoarseNode {
 struct CoarseFactor {
   int nc = 0, depth = 0, ylen = 0, clen = 0;
   std::vector<CoarseNode> nodes;  // post-order
-  // for every coarse row, the contribution slots (in cbuf) to subtract, fixed order
-  std::vector<int> pull_ptr, pull_idx;
+  // Tree order: position t = yoff_n + a holds the a-th separator row of node
+  // n.  nd_row[t] is that row; slots[t * maxp + u] (u < maxp) are the
+  // contribution slots (in cbuf) to subtract from it, in a fixed order,
+  // padded with -1.
+  std::vector<int> nd_row;
+  // Row equilibration: the factor is of diag(rscale) C; g_nd[t] must be
+  // multiplied by nd_scale[t] = rscale[nd_row[t]].
+  std::vector<double> rscale, nd_scale;
+  int maxp = 4;
+  std::vector<int> slots;
   double min_pivot_ratio = 1.0;
 };
 
@@ -43,6 +51,8 @@ struct CoarseFactor {
 CoarseFactor coarse_factor(const Maps& M, const std::vector<int>& rp, const std::vector<int>& ci,
                            const std::vector<double>& cv, int nthreads);
 // Host reference of the level-scheduled solve (used to check the factor).
-void coarse_solve_host(const CoarseFactor& F, const double* g, double* x);
+// g_nd: the scaled right-hand side in tree order
+// (g_nd[t] = nd_scale[t] * g[nd_row[t]]).
+void coarse_solve_host(const CoarseFactor& F, const double* g_nd, double* x);
 
 }  // namespace mrcm

@@ -51,17 +51,25 @@ void launch_rhs(const double* tx, const double* ty, int nx, int ny, const int* b
                 const double* f, const double* g, double h, double* b, hipStream_t s);
 
 // ---- preconditioner apply (T = double or float) ----------------------------
+// Boxes are solved by lane groups of 16, 32 or 64 lanes (>= the widest box,
+// at most 64 cells wide); LDS per workgroup: box_lds_bytes() (all ones when a
+// single group exceeds 64 KB).
+size_t box_lds_bytes(int max_bx, int max_cells, size_t word);
 template <typename T>
-void launch_local(const BoxDesc* boxes, int m, int max_cells, const T* dinv, const T* coup,
-                  const double* r, T* p, int nx, const int* dof_off, const int* dof_side,
-                  const int* w_off, const double* wU, const double* wP, double* mU, double* mP,
-                  hipStream_t s);
-void launch_coarse_rhs(const double* mU, const double* mP, const int* rowL, const int* rowR,
-                       const int* rowKind, int nc, int pin_row, double* g, hipStream_t s);
+void launch_local(const BoxDesc* boxes, int m, int max_cells, int max_bx, const T* dinv,
+                  const T* coup, const double* r, T* p, int nx, const int* dof_off,
+                  const int* dof_side, const int* w_off, const double* wU, const double* wP,
+                  double* mU, double* mP, hipStream_t s);
+// Interface right-hand side from the trace moments, in tree order, times
+// the row equilibration scales.
+void launch_coarse_rhs(const int* nd_row, const double* nd_scale, const int* rowL,
+                       const int* rowR, const int* rowKind, int pin_row, const double* mU,
+                       const double* mP, double* g_nd, int nc, hipStream_t s);
+// One forward level of the interface solve (slots: padded contribution lists,
+// maxp a multiple of 4).
 void launch_coarse_fwd(const CChunk* chunks, int nchunks, const CNodeDesc* nodes,
-                       const double* fwd, const int* idx, const int* pull_ptr,
-                       const int* pull_idx, const double* g, double* ybuf, double* cbuf,
-                       int max_nf, hipStream_t s);
+                       const double* fwd, const double* g_nd, const int* slots, int maxp,
+                       double* ybuf, double* cbuf, int max_nf, hipStream_t s);
 void launch_coarse_bwd(const CChunk* chunks, int nchunks, const CNodeDesc* nodes,
                        const double* bwd, const int* idx, const double* ybuf, double* x,
                        int max_nu, hipStream_t s);
@@ -72,8 +80,8 @@ template <typename T>
 void launch_residual(const T* tx, const T* ty, int nx, int ny, const double* r, const T* p,
                      T* rho, hipStream_t s);
 template <typename T>
-void launch_patch(const BoxDesc* boxes, int m, int max_cells, const T* dinv, const T* coup,
-                  const T* rho, T* p, int nx, hipStream_t s);
+void launch_patch(const BoxDesc* boxes, int m, int max_cells, int max_bx, const T* dinv,
+                  const T* coup, const T* rho, T* p, int nx, hipStream_t s);
 template <typename T>
 void launch_finalize(const T* p, long long n, int noflow, double* z, double* partials,
                      hipStream_t s);

@@ -82,154 +82,227 @@ __global__ void k_rhs(const double* __restrict__ tx, const double* __restrict__ 
   }
 }
 
-// Block LDL^T solve of one box held in LDS (x: by rows of bx values).
-//   forward  u_j = D_j^-1 (x_j + T_j u_{j-1})
-//   backward x_j = u_j + D_j^-1 (T_{j+1} x_{j+1})
-// GEMV mapping: thread t handles row r = t % bx of D_j^-1 over the columns
-// c = g, g + G, ... with g = t / bx and G = blockDim / bx groups; D_j^-1 is
-// symmetric, so D[c * bx + r] is read with consecutive r in consecutive
-// lanes (coalesced).  The G partial sums are reduced through LDS.
-template <typename T>
-__device__ void ldl_box_solve(T* x, T* part, const T* __restrict__ Dinv,
-                              const T* __restrict__ coup, int bx, int by) {
-  const int t = threadIdx.x;
-  const int G = blockDim.x / bx;
-  const int r = t % bx, g = t / bx;
-  const bool act = g < G;
-  for (int j = 0; j < by; ++j) {
-    if (j > 0 && t < bx) x[j * bx + t] += coup[j * bx + t] * x[(j - 1) * bx + t];
-    __syncthreads();
-    T acc = T(0);
-    if (act) {
-      const T* D = Dinv + (long long)j * bx * bx;
-      for (int c = g; c < bx; c += G) acc += D[c * bx + r] * x[j * bx + c];
-      part[g * bx + r] = acc;
-    }
-    __syncthreads();
-    if (t < bx) {
-      T s = T(0);
-      for (int q = 0; q < G; ++q) s += part[q * bx + t];
-      x[j * bx + t] = s;
-    }
-    __syncthreads();
+// Block LDL^T solve of one cell box by one group of GS lanes of a wave
+// (GS = 16, 32 or 64 >= bx; 64 / GS boxes per wave).  Lane r owns cell
+// column r of every cell row j:
+//   forward  u_j = D_j^-1 (b_j + T_j u_{j-1}),
+//   backward x_j = u_j + D_j^-1 (T_{j+1} x_{j+1}).
+// The elementwise coupling terms stay in the lane; the GEMV needs the whole
+// vector, which the group broadcasts through its slot ys[0..bx) of LDS.  Lane
+// r reads column r of the symmetric D_j^-1, i.e. D[c * bx + r] for every c, so
+// each load instruction is contiguous across the group; the next block is
+// prefetched into registers while the current one is used.  All exchange is
+// wave-local (no workgroup barrier).  us holds b on entry, x on exit
+// (by rows of bx, LDS).
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+
+template <typename T, int NB>
+__device__ __forceinline__ void load_cols(T (&dst)[NB], const T* __restrict__ D, int bx, int r,
+                                          bool act) {
+#pragma unroll
+  for (int c = 0; c < NB; ++c) dst[c] = (act && c < bx) ? D[c * bx + r] : T(0);
+}
+
+template <typename T, int NB>
+__device__ __forceinline__ T group_dot(const T (&col)[NB], const T* ys, int bx) {
+  T acc = T(0);
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+    if (c < bx) acc += col[c] * ys[c];
+  return acc;
+}
+
+// Forward step j with the columns of D_j^-1 in cur; prefetches D_{j+1} into nxt.
+template <typename T, int NB>
+__device__ __forceinline__ void fwd_step(int j, T (&cur)[NB], T (&nxt)[NB], T* us, T* ys,
+                                         const T* __restrict__ Dinv,
+                                         const T* __restrict__ coup, int bx, int by, int r,
+                                         bool act, T& u_prev) {
+  if (j + 1 < by) load_cols<T, NB>(nxt, Dinv + (long long)(j + 1) * bx * bx, bx, r, act);
+  if (act) ys[r] = us[j * bx + r] + (j > 0 ? coup[j * bx + r] * u_prev : T(0));
+  wave_sync();
+  const T acc = group_dot<T, NB>(cur, ys, bx);
+  wave_sync();
+  if (act) us[j * bx + r] = acc;
+  u_prev = acc;
+}
+
+// Backward step j with the columns of D_j^-1 in cur; prefetches D_{j-1} into nxt.
+template <typename T, int NB>
+__device__ __forceinline__ void bwd_step(int j, T (&cur)[NB], T (&nxt)[NB], T* us, T* ys,
+                                         const T* __restrict__ Dinv,
+                                         const T* __restrict__ coup, int bx, int r, bool act,
+                                         T& x_next) {
+  if (j > 0) load_cols<T, NB>(nxt, Dinv + (long long)(j - 1) * bx * bx, bx, r, act);
+  if (act) ys[r] = coup[(j + 1) * bx + r] * x_next;
+  wave_sync();
+  const T acc = group_dot<T, NB>(cur, ys, bx);
+  wave_sync();
+  T xj = T(0);
+  if (act) {
+    xj = us[j * bx + r] + acc;
+    us[j * bx + r] = xj;
   }
-  for (int j = by - 2; j >= 0; --j) {
-    T acc = T(0);
-    if (act) {
-      const T* D = Dinv + (long long)j * bx * bx;
-      const T* cp = coup + (j + 1) * bx;
-      const T* xn = x + (j + 1) * bx;
-      for (int c = g; c < bx; c += G) acc += D[c * bx + r] * (cp[c] * xn[c]);
-      part[g * bx + r] = acc;
-    }
-    __syncthreads();
-    if (t < bx) {
-      T s = T(0);
-      for (int q = 0; q < G; ++q) s += part[q * bx + t];
-      x[j * bx + t] += s;
-    }
-    __syncthreads();
+  x_next = xj;
+}
+
+template <typename T, int NB>
+__device__ void box_solve_rows(T* us, T* ys, const T* __restrict__ Dinv,
+                               const T* __restrict__ coup, int bx, int by, int r, bool act) {
+  T A[NB], Bf[NB];
+  load_cols<T, NB>(A, Dinv, bx, r, act);
+  T u_prev = T(0);
+  for (int j = 0; j < by; j += 2) {
+    fwd_step<T, NB>(j, A, Bf, us, ys, Dinv, coup, bx, by, r, act, u_prev);
+    if (j + 1 < by) fwd_step<T, NB>(j + 1, Bf, A, us, ys, Dinv, coup, bx, by, r, act, u_prev);
+  }
+  if (by < 2) return;
+  T x_next = u_prev;
+  load_cols<T, NB>(A, Dinv + (long long)(by - 2) * bx * bx, bx, r, act);
+  for (int j = by - 2; j >= 0; j -= 2) {
+    bwd_step<T, NB>(j, A, Bf, us, ys, Dinv, coup, bx, r, act, x_next);
+    if (j - 1 >= 0) bwd_step<T, NB>(j - 1, Bf, A, us, ys, Dinv, coup, bx, r, act, x_next);
   }
 }
 
-// Local Robin particular solves p_{i,r} = A_i^-1 r[Omega_i] (one workgroup per
-// subdomain) fused with the trace moments of the coarse right-hand side:
-// mU[k] = sum_j wU[k][j] p(face cell j), mP[k] likewise, for every coarse dof k
-// = (i, side, q) of the subdomain.
-template <typename T>
+// Local Robin particular solves p_{i,r} = A_i^-1 r[Omega_i], one lane group
+// per subdomain, fused with the trace moments of the coarse right-hand side:
+// mU[k] = sum_j wU[k][j] p(face cell j), mP[k] likewise, for every coarse dof
+// k = (i, side, q) of the subdomain (one lane per dof, FP64 sums).
+template <typename T, int NB, int GS = (NB <= 16 ? 16 : NB <= 32 ? 32 : 64)>
 __global__ void __launch_bounds__(kBoxThreads)
-    k_local(const BoxDesc* __restrict__ boxes, const T* __restrict__ dinv,
-            const T* __restrict__ coup, const double* __restrict__ r, T* __restrict__ p, int nx,
+    k_local(const BoxDesc* __restrict__ boxes, int m, int cell_stride,
+            const T* __restrict__ dinv, const T* __restrict__ coup,
+            const double* __restrict__ r, T* __restrict__ p, int nx,
             const int* __restrict__ dof_off, const int* __restrict__ dof_side,
             const int* __restrict__ w_off, const double* __restrict__ wU,
             const double* __restrict__ wP, double* __restrict__ mU, double* __restrict__ mP) {
   extern __shared__ __align__(16) char smem_raw[];
-  const BoxDesc d = boxes[blockIdx.x];
-  const int bx = d.bx, by = d.by, ncell = bx * by;
-  T* part = reinterpret_cast<T*>(smem_raw);
-  T* x = part + kBoxThreads;
-  for (int q = threadIdx.x; q < ncell; q += blockDim.x) {
-    const int a = q % bx, j = q / bx;
-    x[q] = (T)r[(long long)(d.y0 + j) * nx + d.x0 + a];
-  }
-  __syncthreads();
-  if (d.pin && threadIdx.x == 0) x[0] = T(0);
-  __syncthreads();
-  ldl_box_solve<T>(x, part, dinv + d.doff, coup + d.coff, bx, by);
-  for (int q = threadIdx.x; q < ncell; q += blockDim.x) {
-    const int a = q % bx, j = q / bx;
-    p[(long long)(d.y0 + j) * nx + d.x0 + a] = x[q];
-  }
-  const int i = blockIdx.x;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int k = dof_off[i] + wid; k < dof_off[i + 1]; k += nw) {
+  const int groups = blockDim.x / GS;
+  const int grp = threadIdx.x / GS, lane = threadIdx.x % GS;
+  const int i = blockIdx.x * groups + grp;
+  T* ys = reinterpret_cast<T*>(smem_raw) + grp * GS;
+  T* us = reinterpret_cast<T*>(smem_raw) + blockDim.x + (long long)grp * cell_stride;
+  if (i >= m) return;  // whole group leaves together
+  const BoxDesc d = boxes[i];
+  const int bx = d.bx, by = d.by;
+  const bool act = lane < bx;
+  if (act)
+    for (int j = 0; j < by; ++j) us[j * bx + lane] = (T)r[(long long)(d.y0 + j) * nx + d.x0 + lane];
+  wave_sync();
+  if (d.pin && lane == 0) us[0] = T(0);
+  wave_sync();
+  box_solve_rows<T, NB>(us, ys, dinv + d.doff, coup + d.coff, bx, by, lane, act);
+  wave_sync();
+  if (act)
+    for (int j = 0; j < by; ++j) p[(long long)(d.y0 + j) * nx + d.x0 + lane] = us[j * bx + lane];
+  for (int k = dof_off[i] + lane; k < dof_off[i + 1]; k += GS) {
     const int side = dof_side[k];
     const int len = (side <= 1) ? by : bx;
+    const double* wu = wU + w_off[k];
+    const double* wp = wP + w_off[k];
     double su = 0.0, sp = 0.0;
-    for (int jf = lane; jf < len; jf += 64) {
-      int cell;
-      if (side == 0) cell = jf * bx;
-      else if (side == 1) cell = jf * bx + bx - 1;
-      else if (side == 2) cell = jf;
-      else cell = (by - 1) * bx + jf;
-      const double v = (double)x[cell];
-      su += wU[w_off[k] + jf] * v;
-      sp += wP[w_off[k] + jf] * v;
+    for (int jf = 0; jf < len; ++jf) {
+      const int cell = side == 0 ? jf * bx
+                     : side == 1 ? jf * bx + bx - 1
+                     : side == 2 ? jf
+                                 : (by - 1) * bx + jf;
+      const double v = (double)us[cell];
+      su += wu[jf] * v;
+      sp += wp[jf] * v;
     }
-    su = wave_sum(su);
-    sp = wave_sum(sp);
-    if (lane == 0) {
-      mU[k] = su;
-      mP[k] = sp;
+    mU[k] = su;
+    mP[k] = sp;
+  }
+}
+
+// Interface right-hand side in tree order: g_nd[t] for the coarse row
+// nd_row[t] is minus the row functional of the particular traces (a flux row
+// adds the two sides' moments, a pressure row subtracts them), times the
+// row's equilibration scale; the replaced row of an all-no-flow grid gets zero.
+__global__ void k_coarse_rhs(const int* __restrict__ nd_row, const double* __restrict__ nd_scale,
+                             const int* __restrict__ rowL, const int* __restrict__ rowR,
+                             const int* __restrict__ rowKind, int pin_row,
+                             const double* __restrict__ mU, const double* __restrict__ mP,
+                             double* __restrict__ g_nd, int nc) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nc) return;
+  const int row = nd_row[t];
+  const int L = rowL[row], R = rowR[row];
+  const double v = rowKind[row] == 0 ? -(mU[L] + mU[R]) : -(mP[L] - mP[R]);
+  g_nd[t] = row == pin_row ? 0.0 : nd_scale[t] * v;
+}
+
+// Rows [row0, row1) of an (rows x ncol) row-major matrix times the LDS vector
+// vec, one wave per group of four rows; lane 0 hands each result to
+// emit(row, value).  The column loop is unrolled eight deep, so a wave has up
+// to 32 loads in flight before it waits.
+template <typename Emit>
+__device__ __forceinline__ void gemv_rows(const double* __restrict__ M, int ncol, int row0,
+                                          int row1, const double* vec, Emit emit) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int r = row0 + 4 * wid; r < row1; r += 4 * nw) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    const int nrow = row1 - r < 4 ? row1 - r : 4;
+    for (int b0 = lane; b0 < ncol; b0 += 64 * 8) {
+      double m[4][8], x[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int b = b0 + 64 * q;
+        const bool in = b < ncol;
+        x[q] = in ? vec[b] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          m[u][q] = (in && u < nrow) ? M[(long long)(r + u) * ncol + b] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s[u] += m[u][q] * x[q];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double t = wave_sum(s[u]);
+      if (lane == 0 && u < nrow) emit(r + u, t);
     }
   }
 }
 
-// Coarse right-hand side: minus the flux and pressure row functionals of the
-// particular traces (flux rows add the two sides, pressure rows subtract).
-__global__ void k_coarse_rhs(const double* __restrict__ mU, const double* __restrict__ mP,
-                             const int* __restrict__ rowL, const int* __restrict__ rowR,
-                             const int* __restrict__ rowKind, int nc, int pin_row,
-                             double* __restrict__ g) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nc) return;
-  const int L = rowL[r], R = rowR[r];
-  double v = rowKind[r] == 0 ? -(mU[L] + mU[R]) : -(mP[L] - mP[R]);
-  g[r] = (r == pin_row) ? 0.0 : v;
-}
-
-// Forward level of the coarse solve: gather v = g_F - contributions of
-// descendants (fixed order), then rows [row0, row1) of [W; E] v.
+// Forward level of the coarse solve: v = g_F - contributions of descendants
+// (fixed order, slots read four at a time), then rows [row0, row1) of
+// [W; E] v: y_F for the separator rows, c_n for the bordering rows.
 __global__ void __launch_bounds__(kVecThreads)
     k_coarse_fwd(const CChunk* __restrict__ chunks, const CNodeDesc* __restrict__ nodes,
-                 const double* __restrict__ fwd, const int* __restrict__ idx,
-                 const int* __restrict__ pull_ptr, const int* __restrict__ pull_idx,
-                 const double* __restrict__ g, double* __restrict__ ybuf,
+                 const double* __restrict__ fwd, const double* __restrict__ g_nd,
+                 const int* __restrict__ slots, int maxp, double* __restrict__ ybuf,
                  double* __restrict__ cbuf) {
   extern __shared__ double v[];
   const CChunk ch = chunks[blockIdx.x];
   const CNodeDesc nd = nodes[ch.node];
   const int nf = nd.nf;
   for (int a = threadIdx.x; a < nf; a += blockDim.x) {
-    const int row = idx[nd.frow + a];
-    double s = g[row];
-    for (int q = pull_ptr[row]; q < pull_ptr[row + 1]; ++q) s -= cbuf[pull_idx[q]];
+    const long long t = (long long)nd.yoff + a;
+    double s = g_nd[t];
+    const int4* sl = reinterpret_cast<const int4*>(slots + t * maxp);
+    for (int u = 0; u < maxp / 4; ++u) {
+      const int4 q = sl[u];
+      const double c0 = q.x >= 0 ? cbuf[q.x] : 0.0, c1 = q.y >= 0 ? cbuf[q.y] : 0.0;
+      const double c2 = q.z >= 0 ? cbuf[q.z] : 0.0, c3 = q.w >= 0 ? cbuf[q.w] : 0.0;
+      s -= c0;
+      s -= c1;
+      s -= c2;
+      s -= c3;
+    }
     v[a] = s;
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int row = ch.row0 + wid; row < ch.row1; row += nw) {
-    const double* M = fwd + nd.fwd + (long long)row * nf;
-    double s = 0.0;
-    for (int b = lane; b < nf; b += 64) s += M[b] * v[b];
-    s = wave_sum(s);
-    if (lane == 0) {
-      if (row < nf)
-        ybuf[nd.yoff + row] = s;
-      else
-        cbuf[nd.coff + row - nf] = s;
-    }
-  }
+  const int yoff = nd.yoff, coff = nd.coff;
+  gemv_rows(fwd + nd.fwd, nf, ch.row0, ch.row1, v, [&](int row, double val) {
+    if (row < nf)
+      ybuf[yoff + row] = val;
+    else
+      cbuf[coff + row - nf] = val;
+  });
 }
 
 // Backward level: x_F = y_F - G x_U for rows [row0, row1).
@@ -240,20 +313,18 @@ __global__ void __launch_bounds__(kVecThreads)
   extern __shared__ double xu[];
   const CChunk ch = chunks[blockIdx.x];
   const CNodeDesc nd = nodes[ch.node];
-  const int nf = nd.nf, nu = nd.nu;
+  const int nu = nd.nu;
   for (int b = threadIdx.x; b < nu; b += blockDim.x) xu[b] = x[idx[nd.ucol + b]];
   __syncthreads();
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int row = ch.row0 + wid; row < ch.row1; row += nw) {
-    double s = 0.0;
-    if (nu > 0) {
-      const double* M = bwd + nd.bwd + (long long)row * nu;
-      for (int b = lane; b < nu; b += 64) s += M[b] * xu[b];
-      s = wave_sum(s);
-    }
-    if (lane == 0) x[idx[nd.fcol + row]] = ybuf[nd.yoff + row] - s;
+  const int yoff = nd.yoff, fcol = nd.fcol;
+  if (nu == 0) {
+    for (int row = ch.row0 + threadIdx.x; row < ch.row1; row += blockDim.x)
+      x[idx[fcol + row]] = ybuf[yoff + row];
+    return;
   }
-  (void)nf;
+  gemv_rows(bwd + nd.bwd, nu, ch.row0, ch.row1, xu, [&](int row, double val) {
+    x[idx[fcol + row]] = ybuf[yoff + row] - val;
+  });
 }
 
 // p[Omega_i] += P_i x_i (multiscale reconstruction), one workgroup per subdomain.
@@ -291,31 +362,36 @@ __global__ void __launch_bounds__(kVecThreads)
   }
 }
 
-// Restricted additive Schwarz: solve A[S_i] e = rho[S_i] on patch i and add
-// e on the owned subdomain Omega_i (each cell is written by one patch only).
-template <typename T>
+// Restricted additive Schwarz: solve A[S_i] e = rho[S_i] on patch i (one
+// lane group per patch) and add e on the owned subdomain Omega_i (each cell
+// is written by one patch only).
+template <typename T, int NB, int GS = (NB <= 16 ? 16 : NB <= 32 ? 32 : 64)>
 __global__ void __launch_bounds__(kBoxThreads)
-    k_patch(const BoxDesc* __restrict__ boxes, const T* __restrict__ dinv,
-            const T* __restrict__ coup, const T* __restrict__ rho, T* __restrict__ p, int nx) {
+    k_patch(const BoxDesc* __restrict__ boxes, int m, int cell_stride,
+            const T* __restrict__ dinv, const T* __restrict__ coup, const T* __restrict__ rho,
+            T* __restrict__ p, int nx) {
   extern __shared__ __align__(16) char smem_raw[];
-  const BoxDesc d = boxes[blockIdx.x];
-  const int bx = d.bx, by = d.by, ncell = bx * by;
-  T* part = reinterpret_cast<T*>(smem_raw);
-  T* x = part + kBoxThreads;
-  for (int q = threadIdx.x; q < ncell; q += blockDim.x) {
-    const int a = q % bx, j = q / bx;
-    x[q] = rho[(long long)(d.y0 + j) * nx + d.x0 + a];
-  }
-  __syncthreads();
-  if (d.pin && threadIdx.x == 0) x[0] = T(0);
-  __syncthreads();
-  ldl_box_solve<T>(x, part, dinv + d.doff, coup + d.coff, bx, by);
-  const int oc = d.obx * d.oby;
-  for (int q = threadIdx.x; q < oc; q += blockDim.x) {
-    const int a = q % d.obx, j = q / d.obx;
-    const long long c = (long long)(d.y0 + d.oy + j) * nx + d.x0 + d.ox + a;
-    p[c] += x[(d.oy + j) * bx + d.ox + a];
-  }
+  const int groups = blockDim.x / GS;
+  const int grp = threadIdx.x / GS, lane = threadIdx.x % GS;
+  const int i = blockIdx.x * groups + grp;
+  T* ys = reinterpret_cast<T*>(smem_raw) + grp * GS;
+  T* us = reinterpret_cast<T*>(smem_raw) + blockDim.x + (long long)grp * cell_stride;
+  if (i >= m) return;
+  const BoxDesc d = boxes[i];
+  const int bx = d.bx, by = d.by;
+  const bool act = lane < bx;
+  if (act)
+    for (int j = 0; j < by; ++j) us[j * bx + lane] = rho[(long long)(d.y0 + j) * nx + d.x0 + lane];
+  wave_sync();
+  if (d.pin && lane == 0) us[0] = T(0);
+  wave_sync();
+  box_solve_rows<T, NB>(us, ys, dinv + d.doff, coup + d.coff, bx, by, lane, act);
+  wave_sync();
+  if (lane >= d.ox && lane < d.ox + d.obx)
+    for (int j = 0; j < d.oby; ++j) {
+      const long long c = (long long)(d.y0 + d.oy + j) * nx + d.x0 + lane;
+      p[c] += us[(d.oy + j) * bx + lane];
+    }
 }
 
 template <typename T>
@@ -467,31 +543,68 @@ void launch_rhs(const double* tx, const double* ty, int nx, int ny, const int* b
                      bc[1], bc[2], bc[3], f, g, h, b);
 }
 
-template <typename T>
-void launch_local(const BoxDesc* boxes, int m, int max_cells, const T* dinv, const T* coup,
-                  const double* r, T* p, int nx, const int* dof_off, const int* dof_side,
-                  const int* w_off, const double* wU, const double* wP, double* mU, double* mP,
-                  hipStream_t s) {
-  const size_t shm = sizeof(T) * (size_t)(kBoxThreads + max_cells);
-  hipLaunchKernelGGL(k_local<T>, dim3(m), dim3(kBoxThreads), shm, s, boxes, dinv, coup, r, p, nx,
-                     dof_off, dof_side, w_off, wU, wP, mU, mP);
+// Column-buffer width (registers) and lane-group size for boxes up to max_bx
+// cells wide.
+inline int col_width(int max_bx) {
+  return max_bx <= 16 ? 16 : max_bx <= 24 ? 24 : max_bx <= 32 ? 32 : max_bx <= 40 ? 40
+       : max_bx <= 48 ? 48 : 64;
+}
+inline int group_size(int max_bx) { return max_bx <= 16 ? 16 : max_bx <= 32 ? 32 : 64; }
+
+// Lane groups per workgroup: up to 256 threads, fewer when the boxes' LDS
+// would exceed 64 KB (0 when even one group does not fit).
+int box_groups(int max_bx, int max_cells, size_t word) {
+  const int gs = group_size(max_bx);
+  for (int groups = kBoxThreads / gs; groups >= 1; groups /= 2)
+    if (word * ((size_t)groups * gs + (size_t)groups * max_cells) <= 64 * 1024) return groups;
+  return 0;
 }
 
-void launch_coarse_rhs(const double* mU, const double* mP, const int* rowL, const int* rowR,
-                       const int* rowKind, int nc, int pin_row, double* g, hipStream_t s) {
+size_t box_lds_bytes(int max_bx, int max_cells, size_t word) {
+  const int groups = box_groups(max_bx, max_cells, word);
+  const int gs = group_size(max_bx);
+  return groups ? word * ((size_t)groups * gs + (size_t)groups * max_cells) : ~(size_t)0;
+}
+
+#define MRCM_BOX_DISPATCH(KERNEL, T, max_bx, ...)                                         \
+  do {                                                                                   \
+    switch (col_width(max_bx)) {                                                         \
+      case 16: hipLaunchKernelGGL((KERNEL<T, 16>), __VA_ARGS__); break;                  \
+      case 24: hipLaunchKernelGGL((KERNEL<T, 24>), __VA_ARGS__); break;                  \
+      case 32: hipLaunchKernelGGL((KERNEL<T, 32>), __VA_ARGS__); break;                  \
+      case 40: hipLaunchKernelGGL((KERNEL<T, 40>), __VA_ARGS__); break;                  \
+      case 48: hipLaunchKernelGGL((KERNEL<T, 48>), __VA_ARGS__); break;                  \
+      default: hipLaunchKernelGGL((KERNEL<T, 64>), __VA_ARGS__); break;                  \
+    }                                                                                    \
+  } while (0)
+
+template <typename T>
+void launch_local(const BoxDesc* boxes, int m, int max_cells, int max_bx, const T* dinv,
+                  const T* coup, const double* r, T* p, int nx, const int* dof_off,
+                  const int* dof_side, const int* w_off, const double* wU, const double* wP,
+                  double* mU, double* mP, hipStream_t s) {
+  const int groups = box_groups(max_bx, max_cells, sizeof(T));
+  const size_t shm = box_lds_bytes(max_bx, max_cells, sizeof(T));
+  const dim3 grid((m + groups - 1) / groups), block(groups * group_size(max_bx));
+  MRCM_BOX_DISPATCH(k_local, T, max_bx, grid, block, shm, s, boxes, m, max_cells,
+                    dinv, coup, r, p, nx, dof_off, dof_side, w_off, wU, wP, mU, mP);
+}
+
+void launch_coarse_rhs(const int* nd_row, const double* nd_scale, const int* rowL,
+                       const int* rowR, const int* rowKind, int pin_row, const double* mU,
+                       const double* mP, double* g_nd, int nc, hipStream_t s) {
   if (nc <= 0) return;
-  hipLaunchKernelGGL(k_coarse_rhs, dim3((nc + 255) / 256), dim3(256), 0, s, mU, mP, rowL, rowR,
-                     rowKind, nc, pin_row, g);
+  hipLaunchKernelGGL(k_coarse_rhs, dim3((nc + 255) / 256), dim3(256), 0, s, nd_row, nd_scale,
+                     rowL, rowR, rowKind, pin_row, mU, mP, g_nd, nc);
 }
 
 void launch_coarse_fwd(const CChunk* chunks, int nchunks, const CNodeDesc* nodes,
-                       const double* fwd, const int* idx, const int* pull_ptr,
-                       const int* pull_idx, const double* g, double* ybuf, double* cbuf,
-                       int max_nf, hipStream_t s) {
+                       const double* fwd, const double* g_nd, const int* slots, int maxp,
+                       double* ybuf, double* cbuf, int max_nf, hipStream_t s) {
   if (nchunks <= 0) return;
   hipLaunchKernelGGL(k_coarse_fwd, dim3(nchunks), dim3(kVecThreads),
-                     sizeof(double) * (size_t)max_nf, s, chunks, nodes, fwd, idx, pull_ptr,
-                     pull_idx, g, ybuf, cbuf);
+                     sizeof(double) * (size_t)max_nf, s, chunks, nodes, fwd, g_nd, slots, maxp,
+                     ybuf, cbuf);
 }
 
 void launch_coarse_bwd(const CChunk* chunks, int nchunks, const CNodeDesc* nodes,
@@ -519,11 +632,13 @@ void launch_residual(const T* tx, const T* ty, int nx, int ny, const double* r, 
 }
 
 template <typename T>
-void launch_patch(const BoxDesc* boxes, int m, int max_cells, const T* dinv, const T* coup,
-                  const T* rho, T* p, int nx, hipStream_t s) {
-  const size_t shm = sizeof(T) * (size_t)(kBoxThreads + max_cells);
-  hipLaunchKernelGGL(k_patch<T>, dim3(m), dim3(kBoxThreads), shm, s, boxes, dinv, coup, rho, p,
-                     nx);
+void launch_patch(const BoxDesc* boxes, int m, int max_cells, int max_bx, const T* dinv,
+                  const T* coup, const T* rho, T* p, int nx, hipStream_t s) {
+  const int groups = box_groups(max_bx, max_cells, sizeof(T));
+  const size_t shm = box_lds_bytes(max_bx, max_cells, sizeof(T));
+  const dim3 grid((m + groups - 1) / groups), block(groups * group_size(max_bx));
+  MRCM_BOX_DISPATCH(k_patch, T, max_bx, grid, block, shm, s, boxes, m, max_cells,
+                    dinv, coup, rho, p, nx);
 }
 
 template <typename T>
@@ -577,15 +692,15 @@ void launch_sumsq(const double* x, long long n, double* partials, int nb, hipStr
 }
 
 #define MRCM_INSTANTIATE(T)                                                                    \
-  template void launch_local<T>(const BoxDesc*, int, int, const T*, const T*, const double*, T*, \
-                                int, const int*, const int*, const int*, const double*,          \
+  template void launch_local<T>(const BoxDesc*, int, int, int, const T*, const T*, const double*, \
+                                T*, int, const int*, const int*, const int*, const double*,      \
                                 const double*, double*, double*, hipStream_t);                   \
   template void launch_reconstruct<T>(const BoxDesc*, int, const T*, const long long*,          \
                                       const int*, const double*, T*, int, hipStream_t);         \
   template void launch_residual<T>(const T*, const T*, int, int, const double*, const T*, T*,   \
                                    hipStream_t);                                                \
-  template void launch_patch<T>(const BoxDesc*, int, int, const T*, const T*, const T*, T*, int, \
-                                hipStream_t);                                                   \
+  template void launch_patch<T>(const BoxDesc*, int, int, int, const T*, const T*, const T*, T*, \
+                                int, hipStream_t);                                              \
   template void launch_finalize<T>(const T*, long long, int, double*, double*, hipStream_t);
 
 MRCM_INSTANTIATE(double)

@@ -101,7 +101,9 @@ int mrcm_test_host_apply(const mrcm_grid* grid, const mrcm_params* params, const
         g[rr] = S.rowKind[rr] == 0 ? -(mU[L] + mU[R]) : -(mP[L] - mP[R]);
         if (rr == S.pin_row) g[rr] = 0.0;
       }
-      mrcm::coarse_solve_host(CF, g.data(), xc.data());
+      std::vector<double> gnd(nc);
+      for (int q = 0; q < nc; ++q) gnd[q] = CF.nd_scale[q] * g[CF.nd_row[q]];
+      mrcm::coarse_solve_host(CF, gnd.data(), xc.data());
       for (int i = 0; i < M.m; ++i) {
         const mrcm::Box& b = M.boxes[i];
         const int ncell = b.bx() * b.by();
