@@ -31,21 +31,32 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 
 
-def algorithmic_bytes(cfg, maps, word: int) -> dict:
-    """Algorithmic bytes of one launch of the local and patch kernels.
+def words(precision: int) -> tuple:
+    """(work-vector word, factor storage word) in bytes of a precision mode."""
+    return (4 if precision == 1 else 8), (8 if precision == 0 else 4)
+
+
+DTYPES = {0: "f64", 1: "f32", 2: "f32-storage/f64-arith"}
+PRECISION_NAMES = {0: "fp64", 1: "fp32 local/smoothing apply, fp64 interface + krylov",
+                   2: "fp32 factor storage with fp64 arithmetic, fp64 interface + krylov"}
+
+
+def algorithmic_bytes(cfg, maps, tw: int, sw: int) -> dict:
+    """Algorithmic bytes of one launch of the local and patch kernels
+    (tw: bytes of a work-vector word, sw: bytes of a stored factor word).
 
     Local solve of subdomain i (bx x by cells): the D_j^-1 blocks (by bx^2
     words) and couplings (by bx words) read once, r read (8 B/cell, FP64), p
-    written (word/cell), trace-moment weights read (2 x 8 B per face of every
+    written (tw/cell), trace-moment weights read (2 x 8 B per face of every
     dof) and moments written (16 B per dof).
     Patch solve of patch i (px x py cells, owned bx x by): factor and
-    couplings read once, the residual read on the patch (word/cell), p read
-    and written on the owned cells (2 words/cell).
+    couplings read once, the residual read on the patch (tw/cell), p read
+    and written on the owned cells (2 tw/cell).
     """
     b = maps["boxes"]
     bx = (b[:, 1] - b[:, 0]).astype(np.int64)
     by = (b[:, 3] - b[:, 2]).astype(np.int64)
-    local = int(np.sum(by * bx * bx * word + by * bx * word + by * bx * 8 + by * bx * word))
+    local = int(np.sum(by * bx * bx * sw + by * bx * sw + by * bx * 8 + by * bx * tw))
     dofs = maps["dof_table"]
     sides = dofs[:, 1]
     lens = np.where(sides <= 1, by[dofs[:, 0]], bx[dofs[:, 0]])
@@ -53,7 +64,7 @@ def algorithmic_bytes(cfg, maps, word: int) -> dict:
     p = maps["pboxes"]
     px = (p[:, 1] - p[:, 0]).astype(np.int64)
     py = (p[:, 3] - p[:, 2]).astype(np.int64)
-    patch = int(np.sum(py * px * px * word + py * px * word + py * px * word + 2 * bx * by * word))
+    patch = int(np.sum(py * px * px * sw + py * px * sw + py * px * tw + 2 * bx * by * tw))
     return {"local": local, "patch": patch}
 
 
@@ -122,15 +133,14 @@ def apply_only(args, w, ctx, b, setup_s) -> int:
     phases = ctx.timing_read()
     ctx.timing(False)
     maps = B.maps(w.binding_config())
-    word = 4 if w.precision == 1 else 8
-    abytes = algorithmic_bytes(w, maps, word)
+    abytes = algorithmic_bytes(w, maps, *words(w.precision))
     dom = max(("local", "patch"), key=lambda k: phases[k][0])
     avg_ms = phases[dom][0] / max(1, phases[dom][1])
     achieved = abytes[dom] / (avg_ms * 1e-3) / 1e9
     out = {"metric": "MRCM-OS preconditioner applications/s", "value": args.steps / elapsed,
            "unit": "applies/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
-           "dtype": "f32" if w.precision == 1 else "f64", "data": "synthetic",
+           "dtype": DTYPES[w.precision], "data": "synthetic",
            "config": {"workload": w.name, "cells": w.cells, "subdomains": int(maps["boxes"].shape[0])},
            "setup_s": setup_s,
            "device_gb": ctx.query("device_bytes") / 1e9,
@@ -152,7 +162,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batched",
                     choices=["small", "channel", "batched", "large"])
-    ap.add_argument("--precision", type=int, default=None, help="0 FP64 apply, 1 FP32 apply")
+    ap.add_argument("--precision", type=int, default=None, help="0 FP64 apply, 1 FP32 apply, 2 FP32-stored factors with FP64 arithmetic")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apply-only", action="store_true",
                     help="time preconditioner applications T r instead of solves")
@@ -215,8 +225,7 @@ def main() -> int:
     ms_per_step = 1e3 * elapsed / args.steps
     value = args.steps / elapsed
     maps = B.maps(w.binding_config())
-    word = 4 if w.precision == 1 else 8
-    abytes = algorithmic_bytes(w, maps, word)
+    abytes = algorithmic_bytes(w, maps, *words(w.precision))
     # dominant kernel = the phase with the largest accumulated device time
     dom = max(("local", "patch"), key=lambda k: phases[k][0])
     avg_ms = phases[dom][0] / max(1, phases[dom][1])
@@ -233,13 +242,13 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if w.precision == 1 else "f64",
+        "dtype": DTYPES[w.precision],
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.nx}x{w.ny} cells, {maps['boxes'].shape[0]} "
                                f"subdomains of {w.s}x{w.s}, oversampling {w.oversample}, "
                                f"{w.sweeps} smoothing sweep(s), overlap {w.overlap}, "
                                f"alpha {w.alpha}, field {w.field}, no-flow, corner sources",
-                   "cells": n, "precision": "fp32 apply / fp64 krylov" if w.precision else "fp64",
+                   "cells": n, "precision": PRECISION_NAMES[w.precision],
                    "rtol": 1e-8, "restart": 10, "parallelism": "single GPU"},
         "cell_dof_per_s": value * n,
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),

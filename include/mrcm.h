@@ -69,9 +69,13 @@ typedef struct {
  *  smooth_sweeps   k smoothing sweeps (restricted additive Schwarz);
  *  smooth_overlap  delta: smoothing patch = Omega_i grown by delta, clipped;
  *  iface_degree    d >= 0: Legendre P_0..P_d per interface side;
- *  precision       0: FP64 preconditioner apply; 1: local and smoothing
- *                  solves applied in FP32 (factors computed in FP64), coarse
- *                  solve and GMRES in FP64. */
+ *  precision       0: FP64 preconditioner apply;
+ *                  1: local and smoothing solves applied in FP32 (factors
+ *                  computed in FP64, stored and applied in FP32, FP32
+ *                  accumulation);
+ *                  2: factors stored in FP32 (half the bytes), applied with
+ *                  FP64 arithmetic and FP64 work vectors;
+ *                  the interface solve and GMRES are FP64 in every mode. */
 typedef struct {
   int32_t sx, sy;
   int32_t oversample;

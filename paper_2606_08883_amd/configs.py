@@ -14,10 +14,12 @@ restart 10 and relative tolerance 1e-8, interface degree 1, smoothing overlap
           L = H, oversampling in {0, 2, 4}, sweeps in {0, 1, 2}; FP64.
 * batched 1024 x 1024, log-normal K (sigma 3, correlation 16, seed 3), 4096
           subdomains of 16 x 16, oversampling 4, one sweep, alpha 10, L = H;
-          FP32 local and smoothing apply, FP64 factorisation and GMRES.
+          local and smoothing factors stored in FP32 and applied in FP64
+          arithmetic, FP64 factorisation, interface solve and GMRES.
 * large   4096 x 4096 (16.8 M cells), channel / log-normal mixture with
           contrast 1e8 (seeds 5, 6), 16384 subdomains of 32 x 32, oversampling
-          4, two sweeps, alpha 10, L = H; FP32 and FP64 apply.
+          4, two sweeps, alpha 10, L = H; FP32-stored factors with FP64
+          arithmetic (FP64 and FP32 apply for comparison).
 """
 from __future__ import annotations
 
@@ -82,6 +84,6 @@ class Workload:
 WORKLOADS = {
     "small": Workload("small", 64, 64, 16, 2, 1.0, 1, 1, 2, 1, 0, "small"),
     "channel": Workload("channel", 220, 60, 20, 2, 10.0, 0, 1, 2, 1, 0, "channel"),
-    "batched": Workload("batched", 1024, 1024, 16, 4, 10.0, 0, 1, 2, 1, 1, "batched"),
-    "large": Workload("large", 4096, 4096, 32, 4, 10.0, 0, 2, 2, 1, 1, "large"),
+    "batched": Workload("batched", 1024, 1024, 16, 4, 10.0, 0, 1, 2, 1, 2, "batched"),
+    "large": Workload("large", 4096, 4096, 32, 4, 10.0, 0, 2, 2, 1, 2, "large"),
 }

@@ -50,6 +50,7 @@ struct mrcm_ctx {
   int m = 0, nc = 0, pin_row = -1;
   long long n = 0;
   int max_cells_local = 0, max_cells_patch = 0, max_bx_local = 0, max_bx_patch = 0;
+  int max_bs_local = 0, max_bs_patch = 0;
   int max_nf = 0, max_nu = 0;
   std::vector<void*> allocs;
   // fine operator
@@ -191,28 +192,35 @@ std::vector<T> narrow(const std::vector<double>& v) {
 template <typename T>
 void upload_boxes(mrcm_ctx* c, const std::vector<mrcm::BoxFactor>& F,
                   const std::vector<mrcm::Box>& owned, BoxDesc** desc, void** dinv, void** coup,
-                  int* max_cells, int* max_bx, hipStream_t s) {
+                  int* max_cells, int* max_bx, int* max_bs, hipStream_t s) {
+  // D_j^-1 blocks are stored with a stride rounded up to 16 bytes and every
+  // box starts 16-byte aligned, so the blocks can be staged with vector loads.
+  constexpr long long epv = 16 / sizeof(T);
   std::vector<BoxDesc> d(F.size());
   long long nd = 0, ncp = 0;
-  int mc = 0, mb = 0;
+  int mc = 0, mb = 0, ms = 0;
   for (size_t i = 0; i < F.size(); ++i) {
     const mrcm::Box& b = F[i].box;
     const mrcm::Box& o = owned[i];
+    const int bs = (int)(((long long)b.bx() * b.bx() + epv - 1) / epv * epv);
     d[i] = BoxDesc{b.x0, b.y0, b.bx(), b.by(), F[i].pin, o.x0 - b.x0, o.y0 - b.y0, o.bx(), o.by(),
-                   0, nd, ncp};
-    nd += (long long)F[i].dinv.size();
+                   bs, nd, ncp};
+    nd += (long long)bs * b.by();
     ncp += (long long)F[i].coup.size();
     mc = std::max(mc, b.bx() * b.by());
     mb = std::max(mb, b.bx());
+    ms = std::max(ms, bs);
   }
   if (mb > 64)
     throw mrcm::Error(MRCM_EINVAL, "subdomains and smoothing patches must be at most 64 cells wide");
-  if (mrcm::box_lds_bytes(mb, mc, sizeof(T)) > 64 * 1024)
+  if (mrcm::box_lds_bytes(mb, mc, ms, sizeof(double), sizeof(T)) > 64 * 1024)
     throw mrcm::Error(MRCM_EINVAL, "subdomain or patch too large for the LDS of one workgroup");
-  std::vector<T> hd((size_t)nd), hc((size_t)ncp);
+  std::vector<T> hd((size_t)nd, T(0)), hc((size_t)ncp);
   for (size_t i = 0; i < F.size(); ++i) {
-    std::transform(F[i].dinv.begin(), F[i].dinv.end(), hd.begin() + d[i].doff,
-                   [](double v) { return (T)v; });
+    const size_t bb = (size_t)d[i].bx * d[i].bx;
+    for (int j = 0; j < d[i].by; ++j)
+      std::transform(F[i].dinv.begin() + j * bb, F[i].dinv.begin() + (j + 1) * bb,
+                     hd.begin() + d[i].doff + (size_t)j * d[i].bs, [](double v) { return (T)v; });
     std::transform(F[i].coup.begin(), F[i].coup.end(), hc.begin() + d[i].coff,
                    [](double v) { return (T)v; });
   }
@@ -221,6 +229,7 @@ void upload_boxes(mrcm_ctx* c, const std::vector<mrcm::BoxFactor>& F,
   *coup = c->upload(hc, s);
   *max_cells = mc;
   *max_bx = mb;
+  *max_bs = ms;
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
@@ -292,7 +301,9 @@ void upload_coarse(mrcm_ctx* c, const mrcm::CoarseFactor& F, hipStream_t s) {
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
-template <typename T>
+// One application of T with arithmetic / work-vector type T and factor
+// storage type S.
+template <typename T, typename S>
 void apply_one(mrcm_ctx* c, const double* r, double* z, hipStream_t s) {
   T* p = static_cast<T*>(c->pT);
   T* rho = static_cast<T*>(c->rhoT);
@@ -304,10 +315,10 @@ void apply_one(mrcm_ctx* c, const double* r, double* z, hipStream_t s) {
     if (c->timing) c->add_mark(phase, e0, c->mark(s));
   };
   begin();
-  mrcm::launch_local<T>(c->lbox, c->m, c->max_cells_local, c->max_bx_local,
-                        static_cast<const T*>(c->ldinv),
-                        static_cast<const T*>(c->lcoup), r, p, c->nx, c->dof_off, c->dof_side,
-                        c->w_off, c->wU, c->wP, c->mU, c->mP, s);
+  mrcm::launch_local<T, S>(c->lbox, c->m, c->max_cells_local, c->max_bx_local,
+                           c->max_bs_local, static_cast<const S*>(c->ldinv),
+                           static_cast<const S*>(c->lcoup), r, p, c->nx, c->dof_off,
+                           c->dof_side, c->w_off, c->wU, c->wP, c->mU, c->mP, s);
   end(0);
   if (c->nc > 0) {
     begin();
@@ -321,8 +332,8 @@ void apply_one(mrcm_ctx* c, const double* r, double* z, hipStream_t s) {
                               c->ybuf, c->xc, c->max_nu, s);
     end(1);
     begin();
-    mrcm::launch_reconstruct<T>(c->lbox, c->m, static_cast<const T*>(c->mbf), c->mbf_off,
-                                c->dof_off, c->xc, p, c->nx, s);
+    mrcm::launch_reconstruct<T, S>(c->lbox, c->m, static_cast<const S*>(c->mbf), c->mbf_off,
+                                   c->dof_off, c->xc, p, c->nx, s);
     end(2);
   }
   for (int k = 0; k < c->sweeps; ++k) {
@@ -331,9 +342,9 @@ void apply_one(mrcm_ctx* c, const double* r, double* z, hipStream_t s) {
                              c->ny, r, p, rho, s);
     end(3);
     begin();
-    mrcm::launch_patch<T>(c->pbox, c->m, c->max_cells_patch, c->max_bx_patch,
-                          static_cast<const T*>(c->pdinv),
-                          static_cast<const T*>(c->pcoup), rho, p, c->nx, s);
+    mrcm::launch_patch<T, S>(c->pbox, c->m, c->max_cells_patch, c->max_bx_patch,
+                             c->max_bs_patch, static_cast<const S*>(c->pdinv),
+                             static_cast<const S*>(c->pcoup), rho, p, c->nx, s);
     end(4);
   }
   begin();
@@ -343,19 +354,22 @@ void apply_one(mrcm_ctx* c, const double* r, double* z, hipStream_t s) {
 
 void apply_dispatch(mrcm_ctx* c, const double* r, double* z, hipStream_t s) {
   if (c->precision == 1)
-    apply_one<float>(c, r, z, s);
+    apply_one<float, float>(c, r, z, s);
+  else if (c->precision == 2)
+    apply_one<double, float>(c, r, z, s);
   else
-    apply_one<double>(c, r, z, s);
+    apply_one<double, double>(c, r, z, s);
 }
 
-template <typename X>
+// Upload factors in storage type X and allocate work vectors of type W.
+template <typename W, typename X>
 void setup_precision(mrcm_ctx* c, const mrcm::HostSetup& S, hipStream_t s) {
   const mrcm::Maps& M = S.maps;
   upload_boxes<X>(c, S.local, M.boxes, &c->lbox, &c->ldinv, &c->lcoup, &c->max_cells_local,
-                  &c->max_bx_local, s);
+                  &c->max_bx_local, &c->max_bs_local, s);
   if (S.sweeps > 0)
     upload_boxes<X>(c, S.patch, M.boxes, &c->pbox, &c->pdinv, &c->pcoup, &c->max_cells_patch,
-                    &c->max_bx_patch, s);
+                    &c->max_bx_patch, &c->max_bs_patch, s);
   std::vector<X> mbf;
   std::vector<long long> off;
   for (int i = 0; i < M.m; ++i) {
@@ -364,15 +378,15 @@ void setup_precision(mrcm_ctx* c, const mrcm::HostSetup& S, hipStream_t s) {
   }
   c->mbf = c->upload(mbf, s);
   c->mbf_off = c->upload(off, s);
-  if (sizeof(X) == sizeof(double)) {
+  if (sizeof(W) == sizeof(double)) {
     c->txT = c->tx;
     c->tyT = c->ty;
   } else {
-    c->txT = c->upload(narrow<X>(S.tx), s);
-    c->tyT = c->upload(narrow<X>(S.ty), s);
+    c->txT = c->upload(narrow<W>(S.tx), s);
+    c->tyT = c->upload(narrow<W>(S.ty), s);
   }
-  c->pT = c->alloc<X>(c->n);
-  c->rhoT = c->alloc<X>(c->n);
+  c->pT = c->alloc<W>(c->n);
+  c->rhoT = c->alloc<W>(c->n);
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
@@ -554,9 +568,11 @@ int mrcm_setup(const mrcm_grid* grid, const mrcm_params* params, const double* K
     c->ty = c->upload(S.ty, s);
     c->d_bc = c->upload(std::vector<int>(grid->bc, grid->bc + 4), s);
     if (c->precision == 1)
-      setup_precision<float>(c, S, s);
+      setup_precision<float, float>(c, S, s);
+    else if (c->precision == 2)
+      setup_precision<double, float>(c, S, s);
     else
-      setup_precision<double>(c, S, s);
+      setup_precision<double, double>(c, S, s);
     std::vector<int> dof_side;
     for (const auto& d : S.maps.dofs) dof_side.push_back(d[1]);
     c->dof_off = c->upload(S.maps.dof_offset, s);
@@ -781,7 +797,7 @@ size_t mrcm_footprint(const mrcm_grid* grid, const mrcm_params* params, int32_t 
   try {
     if (!grid || !params) return 0;
     mrcm::Maps M = mrcm::build_maps(*grid, *params);
-    const size_t w = params->precision == 1 ? 4 : 8;
+    const size_t w = params->precision == 0 ? 8 : 4;
     const size_t n = (size_t)grid->nx * grid->ny;
     size_t bytes = 2 * (n + grid->nx + grid->ny + 1) * (8 + (w == 4 ? 4 : 0));
     auto boxes = [&](const std::vector<mrcm::Box>& B) {

@@ -14,8 +14,8 @@ struct BoxDesc {
   int x0, y0, bx, by;
   int pin;
   int ox, oy, obx, oby;
-  int pad;
-  long long doff;  // offset of D_j^-1 blocks (elements)
+  int bs;          // stride between D_j^-1 blocks: bx * bx rounded up to 16 bytes
+  long long doff;  // offset of the first D_j^-1 block (elements, 16-byte aligned)
   long long coff;  // offset of the couplings T_j (elements)
 };
 
@@ -50,16 +50,17 @@ void launch_op_apply(const double* tx, const double* ty, int nx, int ny, const d
 void launch_rhs(const double* tx, const double* ty, int nx, int ny, const int* bc,
                 const double* f, const double* g, double h, double* b, hipStream_t s);
 
-// ---- preconditioner apply (T = double or float) ----------------------------
+// ---- preconditioner apply (arithmetic T, factor storage S) ------------------
 // Boxes are solved by lane groups of 16, 32 or 64 lanes (>= the widest box,
 // at most 64 cells wide); LDS per workgroup: box_lds_bytes() (all ones when a
-// single group exceeds 64 KB).
-size_t box_lds_bytes(int max_bx, int max_cells, size_t word);
-template <typename T>
-void launch_local(const BoxDesc* boxes, int m, int max_cells, int max_bx, const T* dinv,
-                  const T* coup, const double* r, T* p, int nx, const int* dof_off,
-                  const int* dof_side, const int* w_off, const double* wU, const double* wP,
-                  double* mU, double* mP, hipStream_t s);
+// single group exceeds 64 KB).  max_bs: the largest block stride; t, w: bytes
+// of the arithmetic type T and of the factor storage type S.
+size_t box_lds_bytes(int max_bx, int max_cells, int max_bs, size_t t, size_t w);
+template <typename T, typename S>
+void launch_local(const BoxDesc* boxes, int m, int max_cells, int max_bx, int max_bs,
+                  const S* dinv, const S* coup, const double* r, T* p, int nx,
+                  const int* dof_off, const int* dof_side, const int* w_off, const double* wU,
+                  const double* wP, double* mU, double* mP, hipStream_t s);
 // Interface right-hand side from the trace moments, in tree order, times
 // the row equilibration scales.
 void launch_coarse_rhs(const int* nd_row, const double* nd_scale, const int* rowL,
@@ -73,15 +74,15 @@ void launch_coarse_fwd(const CChunk* chunks, int nchunks, const CNodeDesc* nodes
 void launch_coarse_bwd(const CChunk* chunks, int nchunks, const CNodeDesc* nodes,
                        const double* bwd, const int* idx, const double* ybuf, double* x,
                        int max_nu, hipStream_t s);
-template <typename T>
-void launch_reconstruct(const BoxDesc* boxes, int m, const T* mbf, const long long* mbf_off,
+template <typename T, typename S>
+void launch_reconstruct(const BoxDesc* boxes, int m, const S* mbf, const long long* mbf_off,
                         const int* dof_off, const double* xc, T* p, int nx, hipStream_t s);
 template <typename T>
 void launch_residual(const T* tx, const T* ty, int nx, int ny, const double* r, const T* p,
                      T* rho, hipStream_t s);
-template <typename T>
-void launch_patch(const BoxDesc* boxes, int m, int max_cells, int max_bx, const T* dinv,
-                  const T* coup, const T* rho, T* p, int nx, hipStream_t s);
+template <typename T, typename S>
+void launch_patch(const BoxDesc* boxes, int m, int max_cells, int max_bx, int max_bs,
+                  const S* dinv, const S* coup, const T* rho, T* p, int nx, hipStream_t s);
 template <typename T>
 void launch_finalize(const T* p, long long n, int noflow, double* z, double* partials,
                      hipStream_t s);

@@ -96,93 +96,135 @@ __global__ void k_rhs(const double* __restrict__ tx, const double* __restrict__ 
 // (by rows of bx, LDS).
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
-template <typename T, int NB>
-__device__ __forceinline__ void load_cols(T (&dst)[NB], const T* __restrict__ D, int bx, int r,
-                                          bool act) {
+// 16-byte native vector type of a word type (clang vector extension, kept in
+// registers by the optimiser).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using type = f32x4; };
+template <> struct Vec16<double> { using type = f64x2; };
+
+// Staging of one D_j^-1 block (bstride words, 16-byte aligned, contiguous)
+// through registers into an LDS buffer by all GS lanes of the group.  Indices
+// past the block are clamped to its last vector (the load and the store then
+// repeat that vector with identical data), which keeps the register array
+// statically indexed.
+template <typename V, int GS, int MAXV>
+__device__ __forceinline__ void stage_load(V (&reg)[MAXV], const void* __restrict__ src, int nvec,
+                                           int lane) {
+  const V* s = reinterpret_cast<const V*>(src);
 #pragma unroll
-  for (int c = 0; c < NB; ++c) dst[c] = (act && c < bx) ? D[c * bx + r] : T(0);
+  for (int k = 0; k < MAXV; ++k) {
+    const int q = k * GS + lane;
+    reg[k] = s[q < nvec ? q : nvec - 1];
+  }
 }
 
-template <typename T, int NB>
-__device__ __forceinline__ T group_dot(const T (&col)[NB], const T* ys, int bx) {
+template <typename V, int GS, int MAXV>
+__device__ __forceinline__ void stage_store(const V (&reg)[MAXV], void* dst, int nvec, int lane) {
+  V* d = reinterpret_cast<V*>(dst);
+#pragma unroll
+  for (int k = 0; k < MAXV; ++k) {
+    const int q = k * GS + lane;
+    d[q < nvec ? q : nvec - 1] = reg[k];
+  }
+}
+
+// acc = sum_c D[c * bx + r] ys[c]: lane r's column of the LDS block (symmetric,
+// so it is row r) against the broadcast vector.
+template <typename T, typename S, int NB>
+__device__ __forceinline__ T lds_dot(const S* D, const T* ys, int bx, int r) {
   T acc = T(0);
 #pragma unroll
   for (int c = 0; c < NB; ++c)
-    if (c < bx) acc += col[c] * ys[c];
+    if (c < bx) acc += (T)D[c * bx + r] * ys[c];
   return acc;
 }
 
-// Forward step j with the columns of D_j^-1 in cur; prefetches D_{j+1} into nxt.
-template <typename T, int NB>
-__device__ __forceinline__ void fwd_step(int j, T (&cur)[NB], T (&nxt)[NB], T* us, T* ys,
-                                         const T* __restrict__ Dinv,
-                                         const T* __restrict__ coup, int bx, int by, int r,
-                                         bool act, T& u_prev) {
-  if (j + 1 < by) load_cols<T, NB>(nxt, Dinv + (long long)(j + 1) * bx * bx, bx, r, act);
-  if (act) ys[r] = us[j * bx + r] + (j > 0 ? coup[j * bx + r] * u_prev : T(0));
+// Block LDL^T solve of one box by a group of GS lanes; lane r owns cell column
+// r of every cell row j (see the comment above wave_sync):
+//   forward  u_j = D_j^-1 (b_j + T_j u_{j-1}),
+//   backward x_j = u_j + D_j^-1 (T_{j+1} x_{j+1}).
+// Each D_j^-1 block is loaded one step ahead with 16-byte vector loads spread
+// over the whole group and staged into one of two LDS buffers (Db), so the
+// global loads of step j+1 are in flight while step j reads the other
+// buffer.  us holds b on entry, x on exit (by rows of bx words, LDS).  S is
+// the storage type of the factors, T the arithmetic and vector type (FP32
+// factors may be applied in FP64 arithmetic).
+template <typename T, typename S, int NB, int GS, int MAXV>
+__device__ __forceinline__ void box_solve_rows(T* us, T* ys, S* Db, const S* __restrict__ Dinv,
+                                               const S* __restrict__ coup, int bx, int by,
+                                               int bstride, int r, bool act) {
+  using V = typename Vec16<S>::type;
+  constexpr int EPV = 16 / sizeof(S);
+  const int nvec = bstride / EPV;
+  V reg[MAXV];
+  stage_load<V, GS, MAXV>(reg, Dinv, nvec, r);
+  stage_store<V, GS, MAXV>(reg, Db, nvec, r);
   wave_sync();
-  const T acc = group_dot<T, NB>(cur, ys, bx);
-  wave_sync();
-  if (act) us[j * bx + r] = acc;
-  u_prev = acc;
-}
-
-// Backward step j with the columns of D_j^-1 in cur; prefetches D_{j-1} into nxt.
-template <typename T, int NB>
-__device__ __forceinline__ void bwd_step(int j, T (&cur)[NB], T (&nxt)[NB], T* us, T* ys,
-                                         const T* __restrict__ Dinv,
-                                         const T* __restrict__ coup, int bx, int r, bool act,
-                                         T& x_next) {
-  if (j > 0) load_cols<T, NB>(nxt, Dinv + (long long)(j - 1) * bx * bx, bx, r, act);
-  if (act) ys[r] = coup[(j + 1) * bx + r] * x_next;
-  wave_sync();
-  const T acc = group_dot<T, NB>(cur, ys, bx);
-  wave_sync();
-  T xj = T(0);
-  if (act) {
-    xj = us[j * bx + r] + acc;
-    us[j * bx + r] = xj;
-  }
-  x_next = xj;
-}
-
-template <typename T, int NB>
-__device__ void box_solve_rows(T* us, T* ys, const T* __restrict__ Dinv,
-                               const T* __restrict__ coup, int bx, int by, int r, bool act) {
-  T A[NB], Bf[NB];
-  load_cols<T, NB>(A, Dinv, bx, r, act);
   T u_prev = T(0);
-  for (int j = 0; j < by; j += 2) {
-    fwd_step<T, NB>(j, A, Bf, us, ys, Dinv, coup, bx, by, r, act, u_prev);
-    if (j + 1 < by) fwd_step<T, NB>(j + 1, Bf, A, us, ys, Dinv, coup, bx, by, r, act, u_prev);
+  for (int j = 0; j < by; ++j) {
+    if (j + 1 < by) stage_load<V, GS, MAXV>(reg, Dinv + (long long)(j + 1) * bstride, nvec, r);
+    if (act) ys[r] = us[j * bx + r] + (j > 0 ? (T)coup[j * bx + r] * u_prev : T(0));
+    wave_sync();
+    const T acc = lds_dot<T, S, NB>(Db + (j & 1) * bstride, ys, bx, r);
+    wave_sync();
+    if (act) us[j * bx + r] = acc;
+    u_prev = acc;
+    if (j + 1 < by) stage_store<V, GS, MAXV>(reg, Db + ((j + 1) & 1) * bstride, nvec, r);
+    wave_sync();
   }
   if (by < 2) return;
   T x_next = u_prev;
-  load_cols<T, NB>(A, Dinv + (long long)(by - 2) * bx * bx, bx, r, act);
-  for (int j = by - 2; j >= 0; j -= 2) {
-    bwd_step<T, NB>(j, A, Bf, us, ys, Dinv, coup, bx, r, act, x_next);
-    if (j - 1 >= 0) bwd_step<T, NB>(j - 1, Bf, A, us, ys, Dinv, coup, bx, r, act, x_next);
+  stage_load<V, GS, MAXV>(reg, Dinv + (long long)(by - 2) * bstride, nvec, r);
+  stage_store<V, GS, MAXV>(reg, Db, nvec, r);
+  wave_sync();
+  int buf = 0;
+  for (int j = by - 2; j >= 0; --j) {
+    if (j > 0) stage_load<V, GS, MAXV>(reg, Dinv + (long long)(j - 1) * bstride, nvec, r);
+    if (act) ys[r] = (T)coup[(j + 1) * bx + r] * x_next;
+    wave_sync();
+    const T acc = lds_dot<T, S, NB>(Db + buf * bstride, ys, bx, r);
+    wave_sync();
+    T xj = T(0);
+    if (act) {
+      xj = us[j * bx + r] + acc;
+      us[j * bx + r] = xj;
+    }
+    x_next = xj;
+    if (j > 0) stage_store<V, GS, MAXV>(reg, Db + (buf ^ 1) * bstride, nvec, r);
+    buf ^= 1;
+    wave_sync();
   }
+}
+
+// Vectors per lane needed to stage the widest block of a launch.
+template <typename T, int NB, int GS>
+constexpr int stage_vectors() {
+  return ((NB * NB + 16 / (int)sizeof(T) - 1) / (16 / (int)sizeof(T)) + GS - 1) / GS;
 }
 
 // Local Robin particular solves p_{i,r} = A_i^-1 r[Omega_i], one lane group
 // per subdomain, fused with the trace moments of the coarse right-hand side:
 // mU[k] = sum_j wU[k][j] p(face cell j), mP[k] likewise, for every coarse dof
 // k = (i, side, q) of the subdomain (one lane per dof, FP64 sums).
-template <typename T, int NB, int GS = (NB <= 16 ? 16 : NB <= 32 ? 32 : 64)>
+template <typename T, typename S, int NB, int GS = (NB <= 16 ? 16 : NB <= 32 ? 32 : 64)>
 __global__ void __launch_bounds__(kBoxThreads)
-    k_local(const BoxDesc* __restrict__ boxes, int m, int cell_stride,
-            const T* __restrict__ dinv, const T* __restrict__ coup,
+    k_local(const BoxDesc* __restrict__ boxes, int m, int group_bytes, int blk_stride,
+            const S* __restrict__ dinv, const S* __restrict__ coup,
             const double* __restrict__ r, T* __restrict__ p, int nx,
             const int* __restrict__ dof_off, const int* __restrict__ dof_side,
             const int* __restrict__ w_off, const double* __restrict__ wU,
             const double* __restrict__ wP, double* __restrict__ mU, double* __restrict__ mP) {
   extern __shared__ __align__(16) char smem_raw[];
-  const int groups = blockDim.x / GS;
   const int grp = threadIdx.x / GS, lane = threadIdx.x % GS;
-  const int i = blockIdx.x * groups + grp;
-  T* ys = reinterpret_cast<T*>(smem_raw) + grp * GS;
-  T* us = reinterpret_cast<T*>(smem_raw) + blockDim.x + (long long)grp * cell_stride;
+  const int i = blockIdx.x * (blockDim.x / GS) + grp;
+  // per group: ys[GS] (T) | Db[2 * max block stride] (S) | us[max cells] (T),
+  // every part 16-byte aligned
+  char* base = smem_raw + (long long)grp * group_bytes;
+  T* ys = reinterpret_cast<T*>(base);
+  S* Db = reinterpret_cast<S*>(base + GS * sizeof(T));
+  T* us = reinterpret_cast<T*>(base + GS * sizeof(T) + 2 * (long long)blk_stride * sizeof(S));
   if (i >= m) return;  // whole group leaves together
   const BoxDesc d = boxes[i];
   const int bx = d.bx, by = d.by;
@@ -192,7 +234,9 @@ __global__ void __launch_bounds__(kBoxThreads)
   wave_sync();
   if (d.pin && lane == 0) us[0] = T(0);
   wave_sync();
-  box_solve_rows<T, NB>(us, ys, dinv + d.doff, coup + d.coff, bx, by, lane, act);
+  box_solve_rows<T, S, NB, GS, stage_vectors<S, NB, GS>()>(us, ys, Db, dinv + d.doff,
+                                                          coup + d.coff, bx, by, d.bs, lane,
+                                                          act);
   wave_sync();
   if (act)
     for (int j = 0; j < by; ++j) p[(long long)(d.y0 + j) * nx + d.x0 + lane] = us[j * bx + lane];
@@ -328,9 +372,9 @@ __global__ void __launch_bounds__(kVecThreads)
 }
 
 // p[Omega_i] += P_i x_i (multiscale reconstruction), one workgroup per subdomain.
-template <typename T>
+template <typename T, typename S>
 __global__ void __launch_bounds__(kBoxThreads)
-    k_reconstruct(const BoxDesc* __restrict__ boxes, const T* __restrict__ mbf,
+    k_reconstruct(const BoxDesc* __restrict__ boxes, const S* __restrict__ mbf,
                   const long long* __restrict__ mbf_off, const int* __restrict__ dof_off,
                   const double* __restrict__ xc, T* __restrict__ p, int nx) {
   __shared__ T xs[64];
@@ -339,12 +383,12 @@ __global__ void __launch_bounds__(kBoxThreads)
   const int k0 = dof_off[i], nk = dof_off[i + 1] - k0, ncell = d.bx * d.by;
   for (int k = threadIdx.x; k < nk; k += blockDim.x) xs[k] = (T)xc[k0 + k];
   __syncthreads();
-  const T* P = mbf + mbf_off[i];
+  const S* P = mbf + mbf_off[i];
   for (int q = threadIdx.x; q < ncell; q += blockDim.x) {
     const int a = q % d.bx, j = q / d.bx;
     const long long c = (long long)(d.y0 + j) * nx + d.x0 + a;
     T s = p[c];
-    for (int k = 0; k < nk; ++k) s += P[(long long)k * ncell + q] * xs[k];
+    for (int k = 0; k < nk; ++k) s += (T)P[(long long)k * ncell + q] * xs[k];
     p[c] = s;
   }
 }
@@ -365,17 +409,20 @@ __global__ void __launch_bounds__(kVecThreads)
 // Restricted additive Schwarz: solve A[S_i] e = rho[S_i] on patch i (one
 // lane group per patch) and add e on the owned subdomain Omega_i (each cell
 // is written by one patch only).
-template <typename T, int NB, int GS = (NB <= 16 ? 16 : NB <= 32 ? 32 : 64)>
+template <typename T, typename S, int NB, int GS = (NB <= 16 ? 16 : NB <= 32 ? 32 : 64)>
 __global__ void __launch_bounds__(kBoxThreads)
-    k_patch(const BoxDesc* __restrict__ boxes, int m, int cell_stride,
-            const T* __restrict__ dinv, const T* __restrict__ coup, const T* __restrict__ rho,
+    k_patch(const BoxDesc* __restrict__ boxes, int m, int group_bytes, int blk_stride,
+            const S* __restrict__ dinv, const S* __restrict__ coup, const T* __restrict__ rho,
             T* __restrict__ p, int nx) {
   extern __shared__ __align__(16) char smem_raw[];
-  const int groups = blockDim.x / GS;
   const int grp = threadIdx.x / GS, lane = threadIdx.x % GS;
-  const int i = blockIdx.x * groups + grp;
-  T* ys = reinterpret_cast<T*>(smem_raw) + grp * GS;
-  T* us = reinterpret_cast<T*>(smem_raw) + blockDim.x + (long long)grp * cell_stride;
+  const int i = blockIdx.x * (blockDim.x / GS) + grp;
+  // per group: ys[GS] (T) | Db[2 * max block stride] (S) | us[max cells] (T),
+  // every part 16-byte aligned
+  char* base = smem_raw + (long long)grp * group_bytes;
+  T* ys = reinterpret_cast<T*>(base);
+  S* Db = reinterpret_cast<S*>(base + GS * sizeof(T));
+  T* us = reinterpret_cast<T*>(base + GS * sizeof(T) + 2 * (long long)blk_stride * sizeof(S));
   if (i >= m) return;
   const BoxDesc d = boxes[i];
   const int bx = d.bx, by = d.by;
@@ -385,7 +432,9 @@ __global__ void __launch_bounds__(kBoxThreads)
   wave_sync();
   if (d.pin && lane == 0) us[0] = T(0);
   wave_sync();
-  box_solve_rows<T, NB>(us, ys, dinv + d.doff, coup + d.coff, bx, by, lane, act);
+  box_solve_rows<T, S, NB, GS, stage_vectors<S, NB, GS>()>(us, ys, Db, dinv + d.doff,
+                                                          coup + d.coff, bx, by, d.bs, lane,
+                                                          act);
   wave_sync();
   if (lane >= d.ox && lane < d.ox + d.obx)
     for (int j = 0; j < d.oby; ++j) {
@@ -551,42 +600,49 @@ inline int col_width(int max_bx) {
 }
 inline int group_size(int max_bx) { return max_bx <= 16 ? 16 : max_bx <= 32 ? 32 : 64; }
 
+// LDS bytes of one lane group: broadcast slot and box (arithmetic words t),
+// two staged blocks (storage words w), rounded to 16 bytes.
+inline size_t group_bytes(int max_bx, int max_cells, int max_bs, size_t t, size_t w) {
+  const size_t b = (size_t)group_size(max_bx) * t + 2 * (size_t)max_bs * w + (size_t)max_cells * t;
+  return (b + 15) / 16 * 16;
+}
+
 // Lane groups per workgroup: up to 256 threads, fewer when the boxes' LDS
 // would exceed 64 KB (0 when even one group does not fit).
-int box_groups(int max_bx, int max_cells, size_t word) {
+int box_groups(int max_bx, int max_cells, int max_bs, size_t t, size_t w) {
   const int gs = group_size(max_bx);
   for (int groups = kBoxThreads / gs; groups >= 1; groups /= 2)
-    if (word * ((size_t)groups * gs + (size_t)groups * max_cells) <= 64 * 1024) return groups;
+    if (groups * group_bytes(max_bx, max_cells, max_bs, t, w) <= 64 * 1024) return groups;
   return 0;
 }
 
-size_t box_lds_bytes(int max_bx, int max_cells, size_t word) {
-  const int groups = box_groups(max_bx, max_cells, word);
-  const int gs = group_size(max_bx);
-  return groups ? word * ((size_t)groups * gs + (size_t)groups * max_cells) : ~(size_t)0;
+size_t box_lds_bytes(int max_bx, int max_cells, int max_bs, size_t t, size_t w) {
+  const int groups = box_groups(max_bx, max_cells, max_bs, t, w);
+  return groups ? groups * group_bytes(max_bx, max_cells, max_bs, t, w) : ~(size_t)0;
 }
 
-#define MRCM_BOX_DISPATCH(KERNEL, T, max_bx, ...)                                         \
+#define MRCM_BOX_DISPATCH(KERNEL, T, S, max_bx, ...)                                      \
   do {                                                                                   \
     switch (col_width(max_bx)) {                                                         \
-      case 16: hipLaunchKernelGGL((KERNEL<T, 16>), __VA_ARGS__); break;                  \
-      case 24: hipLaunchKernelGGL((KERNEL<T, 24>), __VA_ARGS__); break;                  \
-      case 32: hipLaunchKernelGGL((KERNEL<T, 32>), __VA_ARGS__); break;                  \
-      case 40: hipLaunchKernelGGL((KERNEL<T, 40>), __VA_ARGS__); break;                  \
-      case 48: hipLaunchKernelGGL((KERNEL<T, 48>), __VA_ARGS__); break;                  \
-      default: hipLaunchKernelGGL((KERNEL<T, 64>), __VA_ARGS__); break;                  \
+      case 16: hipLaunchKernelGGL((KERNEL<T, S, 16>), __VA_ARGS__); break;               \
+      case 24: hipLaunchKernelGGL((KERNEL<T, S, 24>), __VA_ARGS__); break;               \
+      case 32: hipLaunchKernelGGL((KERNEL<T, S, 32>), __VA_ARGS__); break;               \
+      case 40: hipLaunchKernelGGL((KERNEL<T, S, 40>), __VA_ARGS__); break;               \
+      case 48: hipLaunchKernelGGL((KERNEL<T, S, 48>), __VA_ARGS__); break;               \
+      default: hipLaunchKernelGGL((KERNEL<T, S, 64>), __VA_ARGS__); break;               \
     }                                                                                    \
   } while (0)
 
-template <typename T>
-void launch_local(const BoxDesc* boxes, int m, int max_cells, int max_bx, const T* dinv,
-                  const T* coup, const double* r, T* p, int nx, const int* dof_off,
-                  const int* dof_side, const int* w_off, const double* wU, const double* wP,
-                  double* mU, double* mP, hipStream_t s) {
-  const int groups = box_groups(max_bx, max_cells, sizeof(T));
-  const size_t shm = box_lds_bytes(max_bx, max_cells, sizeof(T));
+template <typename T, typename S>
+void launch_local(const BoxDesc* boxes, int m, int max_cells, int max_bx, int max_bs,
+                  const S* dinv, const S* coup, const double* r, T* p, int nx,
+                  const int* dof_off, const int* dof_side, const int* w_off, const double* wU,
+                  const double* wP, double* mU, double* mP, hipStream_t s) {
+  const int groups = box_groups(max_bx, max_cells, max_bs, sizeof(T), sizeof(S));
+  const size_t shm = box_lds_bytes(max_bx, max_cells, max_bs, sizeof(T), sizeof(S));
+  const int gb = (int)group_bytes(max_bx, max_cells, max_bs, sizeof(T), sizeof(S));
   const dim3 grid((m + groups - 1) / groups), block(groups * group_size(max_bx));
-  MRCM_BOX_DISPATCH(k_local, T, max_bx, grid, block, shm, s, boxes, m, max_cells,
+  MRCM_BOX_DISPATCH(k_local, T, S, max_bx, grid, block, shm, s, boxes, m, gb, max_bs,
                     dinv, coup, r, p, nx, dof_off, dof_side, w_off, wU, wP, mU, mP);
 }
 
@@ -616,11 +672,11 @@ void launch_coarse_bwd(const CChunk* chunks, int nchunks, const CNodeDesc* nodes
                      idx, ybuf, x);
 }
 
-template <typename T>
-void launch_reconstruct(const BoxDesc* boxes, int m, const T* mbf, const long long* mbf_off,
+template <typename T, typename S>
+void launch_reconstruct(const BoxDesc* boxes, int m, const S* mbf, const long long* mbf_off,
                         const int* dof_off, const double* xc, T* p, int nx, hipStream_t s) {
-  hipLaunchKernelGGL(k_reconstruct<T>, dim3(m), dim3(kBoxThreads), 0, s, boxes, mbf, mbf_off,
-                     dof_off, xc, p, nx);
+  hipLaunchKernelGGL((k_reconstruct<T, S>), dim3(m), dim3(kBoxThreads), 0, s, boxes, mbf,
+                     mbf_off, dof_off, xc, p, nx);
 }
 
 template <typename T>
@@ -631,13 +687,14 @@ void launch_residual(const T* tx, const T* ty, int nx, int ny, const double* r, 
                      r, p, rho);
 }
 
-template <typename T>
-void launch_patch(const BoxDesc* boxes, int m, int max_cells, int max_bx, const T* dinv,
-                  const T* coup, const T* rho, T* p, int nx, hipStream_t s) {
-  const int groups = box_groups(max_bx, max_cells, sizeof(T));
-  const size_t shm = box_lds_bytes(max_bx, max_cells, sizeof(T));
+template <typename T, typename S>
+void launch_patch(const BoxDesc* boxes, int m, int max_cells, int max_bx, int max_bs,
+                  const S* dinv, const S* coup, const T* rho, T* p, int nx, hipStream_t s) {
+  const int groups = box_groups(max_bx, max_cells, max_bs, sizeof(T), sizeof(S));
+  const size_t shm = box_lds_bytes(max_bx, max_cells, max_bs, sizeof(T), sizeof(S));
+  const int gb = (int)group_bytes(max_bx, max_cells, max_bs, sizeof(T), sizeof(S));
   const dim3 grid((m + groups - 1) / groups), block(groups * group_size(max_bx));
-  MRCM_BOX_DISPATCH(k_patch, T, max_bx, grid, block, shm, s, boxes, m, max_cells,
+  MRCM_BOX_DISPATCH(k_patch, T, S, max_bx, grid, block, shm, s, boxes, m, gb, max_bs,
                     dinv, coup, rho, p, nx);
 }
 
@@ -691,19 +748,23 @@ void launch_sumsq(const double* x, long long n, double* partials, int nb, hipStr
   hipLaunchKernelGGL(k_sumsq, dim3(nb), dim3(kVecThreads), 0, s, x, n, partials);
 }
 
-#define MRCM_INSTANTIATE(T)                                                                    \
-  template void launch_local<T>(const BoxDesc*, int, int, int, const T*, const T*, const double*, \
-                                T*, int, const int*, const int*, const int*, const double*,      \
-                                const double*, double*, double*, hipStream_t);                   \
-  template void launch_reconstruct<T>(const BoxDesc*, int, const T*, const long long*,          \
-                                      const int*, const double*, T*, int, hipStream_t);         \
+#define MRCM_INSTANTIATE_TS(T, S)                                                              \
+  template void launch_local<T, S>(const BoxDesc*, int, int, int, int, const S*, const S*,     \
+                                   const double*, T*, int, const int*, const int*, const int*,   \
+                                   const double*, const double*, double*, double*, hipStream_t); \
+  template void launch_reconstruct<T, S>(const BoxDesc*, int, const S*, const long long*,       \
+                                         const int*, const double*, T*, int, hipStream_t);      \
+  template void launch_patch<T, S>(const BoxDesc*, int, int, int, int, const S*, const S*,     \
+                                   const T*, T*, int, hipStream_t);
+#define MRCM_INSTANTIATE_T(T)                                                                  \
   template void launch_residual<T>(const T*, const T*, int, int, const double*, const T*, T*,   \
                                    hipStream_t);                                                \
-  template void launch_patch<T>(const BoxDesc*, int, int, int, const T*, const T*, const T*, T*, \
-                                int, hipStream_t);                                              \
   template void launch_finalize<T>(const T*, long long, int, double*, double*, hipStream_t);
 
-MRCM_INSTANTIATE(double)
-MRCM_INSTANTIATE(float)
+MRCM_INSTANTIATE_TS(double, double)
+MRCM_INSTANTIATE_TS(float, float)
+MRCM_INSTANTIATE_TS(double, float)
+MRCM_INSTANTIATE_T(double)
+MRCM_INSTANTIATE_T(float)
 
 }  // namespace mrcm

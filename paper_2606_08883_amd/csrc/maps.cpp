@@ -33,7 +33,7 @@ Maps build_maps(const mrcm_grid& g, const mrcm_params& p) {
   if (g.nx < 1 || g.ny < 1 || p.sx < 1 || p.sy < 1 || p.oversample < 0 ||
       p.smooth_overlap < 0 || p.smooth_sweeps < 0 || p.iface_degree < 0 ||
       p.iface_degree > 8 || !(p.alpha > 0.0) || (p.beta_len != 0 && p.beta_len != 1) ||
-      (p.precision != 0 && p.precision != 1))
+      p.precision < 0 || p.precision > 2)
     throw Error(MRCM_EINVAL, "invalid grid or method parameters");
   for (int s = 0; s < 4; ++s)
     if (g.bc[s] != 0 && g.bc[s] != 1) throw Error(MRCM_EINVAL, "bc must be 0 or 1");

@@ -6,7 +6,8 @@ interface system is ill-conditioned (cond(C) ~ 1e9 - 1e12), so no two FP64
 implementations that sum in different orders agree to 1e-10; there the gate
 for T is the first-order forward-error bound cond(C) * 2^-53 (with C the
 oracle's own interface matrix), and never below 1e-10.
-Mixed precision (FP32 local and smoothing solves) is gated at 1e-7 on final
+Mixed precision (mode 1: FP32 local and smoothing solves; mode 2: FP32-stored
+factors applied in FP64 arithmetic) is gated at 1e-7 on final
 solutions driven to the tightest relative residual the FP64 problem reaches
 (1e-10 here: the no-flow point-source problems stall near 1e-11 in FP64),
 and its GMRES must reach the FP64 tolerance on the true residual.
@@ -176,10 +177,13 @@ def test_gmres_estimates_channel(dev):
     assert np.allclose(st.est_history, ref.est_history, rtol=1e-6, atol=1e-12)
 
 
-@pytest.mark.parametrize("name,w", [("small-mixed", WORKLOADS["small"].with_(precision=1)),
-                                    ("lognormal-256-mixed",
-                                     WORKLOADS["batched"].with_(nx=256, ny=256))],
-                         ids=["small-mixed", "lognormal-256-mixed"])
+MIXED = [("small-f32", WORKLOADS["small"].with_(precision=1)),
+         ("small-f32s", WORKLOADS["small"].with_(precision=2)),
+         ("lognormal-256-f32", WORKLOADS["batched"].with_(nx=256, ny=256, precision=1)),
+         ("lognormal-256-f32s", WORKLOADS["batched"].with_(nx=256, ny=256, precision=2))]
+
+
+@pytest.mark.parametrize("name,w", MIXED, ids=[m[0] for m in MIXED])
 def test_mixed_precision(dev, name, w):
     print(f"mixed precision {name}", flush=True)
     K = w.permeability() if w.nx == WORKLOADS[w.field].nx else \
