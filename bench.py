@@ -17,6 +17,7 @@ throughput.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import subprocess
@@ -29,6 +30,37 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+CSRC = os.path.join(ROOT, "paper_2606_08883_amd", "csrc")
+
+
+def kernel_source_hash() -> str:
+    """First 16 hex digits of the sha256 of the kernel sources."""
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "device.h"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel: str, workload: str, precision: int):
+    """HBM bytes per launch of a kernel from the committed PMC summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or None when
+    no summary covers this kernel, workload and precision or the kernel
+    sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if (kv.get("kernel") != kernel or kv.get("workload") != workload
+            or kv.get("precision") != str(precision)
+            or kv.get("source_sha256_16") != kernel_source_hash()):
+        return None
+    return int(kv["traffic_bytes_per_launch"])
 
 
 def words(precision: int) -> tuple:
@@ -149,7 +181,9 @@ def apply_only(args, w, ctx, b, setup_s) -> int:
            "algorithmic_bytes_per_launch": abytes,
            "roofline": {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                        "traffic": None, "avg_launch_ms": avg_ms}}
+                        "traffic": recorded_traffic(f"k_{dom}", f"{w.name}{w.nx}",
+                                                    w.precision),
+                        "traffic_unit": "bytes per launch", "avg_launch_ms": avg_ms}}
     print(json.dumps(out), flush=True)
     ctx.close()
     return 0
@@ -166,13 +200,28 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apply-only", action="store_true",
                     help="time preconditioner applications T r instead of solves")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run device-to-device copies of MIB MiB (the known-size "
+                         "kernel that scales the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the solver runs on a single device, with no "
+              "multi-GPU mode; run it with --gpus 1", file=sys.stderr)
         return 2
 
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(max(1, args.steps)):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8,
+                          "copies": max(1, args.steps)}), flush=True)
+        return 0
 
     from paper_2606_08883_amd import binding as B
     from paper_2606_08883_amd.configs import WORKLOADS
@@ -261,7 +310,9 @@ def main() -> int:
         "phase_ms_per_launch": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in phases.items()},
         "roofline": {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "algorithmic_bytes_per_launch": abytes[dom],
+                     "traffic": recorded_traffic(f"k_{dom}", f"{w.name}{w.nx}", w.precision),
+                     "traffic_unit": "bytes per launch",
+                     "algorithmic_bytes_per_launch": abytes[dom],
                      "avg_launch_ms": avg_ms},
     }
     if not args.no_cpu_baseline:
