@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 MAP_CASES = [(64, 64, (0, 0, 0, 0), 16, 2, 2, 1), (220, 60, (0, 0, 0, 0), 20, 4, 2, 1),
              (52, 39, (1, 0, 1, 0), 12, 2, 3, 0), (34, 18, (1, 1, 0, 0), 8, 1, 1, 2),
              (1024, 1024, (0, 0, 0, 0), 16, 4, 2, 1), (25, 20, (0, 0, 0, 0), 7, 3, 2, 1),
-             (16, 16, (0, 0, 0, 0), 16, 0, 2, 1)]
+             (16, 16, (0, 0, 0, 0), 16, 0, 2, 1), (4096, 4096, (0, 0, 0, 0), 32, 4, 2, 1)]
 
 
 @pytest.mark.parametrize("nx,ny,bc,s,l,d,deg", MAP_CASES)
