@@ -47,10 +47,9 @@ int host_threads() {
 
 struct mrcm_ctx {
   int nx = 0, ny = 0, bc[4] = {0, 0, 0, 0}, noflow = 0, precision = 0, sweeps = 0;
-  int m = 0, nc = 0, pin_row = -1;
+  int m = 0, nc = 0;
   long long n = 0;
   int max_cells_local = 0, max_cells_patch = 0, max_bx_local = 0, max_bx_patch = 0;
-  int max_bs_local = 0, max_bs_patch = 0;
   int max_nf = 0, max_nu = 0;
   std::vector<void*> allocs;
   // fine operator
@@ -64,19 +63,20 @@ struct mrcm_ctx {
   long long* mbf_off = nullptr;
   int *dof_off = nullptr, *dof_side = nullptr, *w_off = nullptr;
   double *wU = nullptr, *wP = nullptr;
-  int *rowL = nullptr, *rowR = nullptr, *rowKind = nullptr;
   // coarse factor
-  mrcm::CNodeDesc* cnodes = nullptr;
   double *cfwd = nullptr, *cbwd = nullptr;
-  int *cidx = nullptr, *nd_row = nullptr, *slots = nullptr;
-  double* nd_scale = nullptr;
-  int maxp = 4;
+  int* cidx = nullptr;
+  int4* gsrc = nullptr;        // per tree position: mU / mP indices L, R and the row kind
+  double* gscale = nullptr;    // per tree position: row equilibration scale
+  int* cdest = nullptr;        // contribution row -> slot in contrib
+  double* contrib = nullptr;   // maxp slots per tree position (zero where unused)
+  double* g_nd = nullptr;      // interface right-hand side in tree order
+  int maxp = 4, np = 0;
   mrcm::CChunk* chunks = nullptr;
   std::vector<std::pair<int, int>> fwd_levels, bwd_levels;  // (first chunk, count)
   // work space
   void *pT = nullptr, *rhoT = nullptr;
-  double *mU = nullptr, *mP = nullptr, *g = nullptr, *xc = nullptr, *ybuf = nullptr,
-         *cbuf = nullptr, *partials = nullptr;
+  double *mU = nullptr, *mP = nullptr, *xc = nullptr, *ybuf = nullptr, *partials = nullptr;
   // GMRES
   int krylov_cap = 0;
   double *V = nullptr, *Z = nullptr, *hcol = nullptr, *parts = nullptr, *yd = nullptr;
@@ -179,7 +179,6 @@ namespace {
 
 using mrcm::BoxDesc;
 using mrcm::CChunk;
-using mrcm::CNodeDesc;
 
 template <typename T>
 std::vector<T> narrow(const std::vector<double>& v) {
@@ -188,17 +187,18 @@ std::vector<T> narrow(const std::vector<double>& v) {
   return o;
 }
 
-// Upload a set of box factors in precision T.
+// Upload a set of box factors in precision T: every box's D_j^-1 blocks
+// (row-major) with a block stride rounded up to 16 bytes (every box starts
+// 16-byte aligned, so the blocks can be staged with vector loads), then its
+// couplings.
 template <typename T>
 void upload_boxes(mrcm_ctx* c, const std::vector<mrcm::BoxFactor>& F,
                   const std::vector<mrcm::Box>& owned, BoxDesc** desc, void** dinv, void** coup,
-                  int* max_cells, int* max_bx, int* max_bs, hipStream_t s) {
-  // D_j^-1 blocks are stored with a stride rounded up to 16 bytes and every
-  // box starts 16-byte aligned, so the blocks can be staged with vector loads.
+                  int* max_cells, int* max_bx, hipStream_t s) {
   constexpr long long epv = 16 / sizeof(T);
   std::vector<BoxDesc> d(F.size());
   long long nd = 0, ncp = 0;
-  int mc = 0, mb = 0, ms = 0;
+  int mc = 0, mb = 0;
   for (size_t i = 0; i < F.size(); ++i) {
     const mrcm::Box& b = F[i].box;
     const mrcm::Box& o = owned[i];
@@ -209,11 +209,10 @@ void upload_boxes(mrcm_ctx* c, const std::vector<mrcm::BoxFactor>& F,
     ncp += (long long)F[i].coup.size();
     mc = std::max(mc, b.bx() * b.by());
     mb = std::max(mb, b.bx());
-    ms = std::max(ms, bs);
   }
   if (mb > 64)
     throw mrcm::Error(MRCM_EINVAL, "subdomains and smoothing patches must be at most 64 cells wide");
-  if (mrcm::box_lds_bytes(mb, mc, ms, sizeof(double), sizeof(T)) > 64 * 1024)
+  if (mrcm::box_lds_bytes(mb, mc, sizeof(double), sizeof(T)) > 64 * 1024)
     throw mrcm::Error(MRCM_EINVAL, "subdomain or patch too large for the LDS of one workgroup");
   std::vector<T> hd((size_t)nd, T(0)), hc((size_t)ncp);
   for (size_t i = 0; i < F.size(); ++i) {
@@ -229,73 +228,97 @@ void upload_boxes(mrcm_ctx* c, const std::vector<mrcm::BoxFactor>& F,
   *coup = c->upload(hc, s);
   *max_cells = mc;
   *max_bx = mb;
-  *max_bs = ms;
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
-void upload_coarse(mrcm_ctx* c, const mrcm::CoarseFactor& F, hipStream_t s) {
-  std::vector<CNodeDesc> nodes;
+// Upload the nested-dissection factor of the interface system and the data
+// of its level-scheduled solve: chunk descriptors (16 rows each), the
+// right-hand-side sources of every
+// tree position, and the contribution slots by destination (the inverse of
+// the factor's slot lists; slot u of every position contiguous, so that a
+// node reads its rows' contributions in slot order with coalesced loads).
+void upload_coarse(mrcm_ctx* c, const mrcm::CoarseFactor& F, const mrcm::HostSetup& S,
+                   hipStream_t s) {
+  const int nn = (int)F.nodes.size();
   std::vector<double> fwd, bwd;
   std::vector<int> idx;
+  std::vector<long long> fwd_off(nn), bwd_off(nn);
+  std::vector<int> fcol_off(nn), ucol_off(nn);
   int max_nf = 1, max_nu = 1;
-  for (const auto& cn : F.nodes) {
-    CNodeDesc d{};
-    d.nf = (int)cn.frow.size();
-    d.nu = (int)cn.urow.size();
-    d.frow = (int)idx.size();
-    idx.insert(idx.end(), cn.frow.begin(), cn.frow.end());
-    d.fcol = (int)idx.size();
+  for (int t = 0; t < nn; ++t) {
+    const auto& cn = F.nodes[t];
+    fcol_off[t] = (int)idx.size();
     idx.insert(idx.end(), cn.fcol.begin(), cn.fcol.end());
-    d.ucol = (int)idx.size();
+    ucol_off[t] = (int)idx.size();
     idx.insert(idx.end(), cn.ucol.begin(), cn.ucol.end());
-    d.yoff = cn.yoff;
-    d.coff = cn.coff;
-    d.fwd = (long long)fwd.size();
+    fwd_off[t] = (long long)fwd.size();
     fwd.insert(fwd.end(), cn.fwd.begin(), cn.fwd.end());
-    d.bwd = (long long)bwd.size();
+    bwd_off[t] = (long long)bwd.size();
     bwd.insert(bwd.end(), cn.bwd.begin(), cn.bwd.end());
-    nodes.push_back(d);
-    max_nf = std::max(max_nf, d.nf);
-    max_nu = std::max(max_nu, d.nu);
+    max_nf = std::max(max_nf, (int)cn.frow.size());
+    max_nu = std::max(max_nu, (int)cn.urow.size());
   }
   if (max_nf > 6144 || max_nu > 6144)
     throw mrcm::Error(MRCM_EINVAL, "interface separator too large for one workgroup");
-  // level chunks: forward deepest level first, backward root first
-  constexpr int kRowsPerChunk = 16;
+  // 16 rows per chunk: one group of four rows per wave
+  auto slice_rows = [](int) { return 16; };
   std::vector<CChunk> chunks;
   c->fwd_levels.clear();
   c->bwd_levels.clear();
   for (int d = F.depth; d >= 0; --d) {
     const int first = (int)chunks.size();
-    for (size_t t = 0; t < F.nodes.size(); ++t) {
-      if (F.nodes[t].depth != d) continue;
-      const int rows = nodes[t].nf + nodes[t].nu;
-      for (int r0 = 0; r0 < rows; r0 += kRowsPerChunk)
-        chunks.push_back(CChunk{(int)t, r0, std::min(rows, r0 + kRowsPerChunk), 0});
+    for (int t = 0; t < nn; ++t) {
+      const auto& cn = F.nodes[t];
+      if (cn.depth != d) continue;
+      const int nf = (int)cn.frow.size(), nu = (int)cn.urow.size(), rows = nf + nu;
+      const int step = slice_rows(nf);
+      for (int r0 = 0; r0 < rows; r0 += step)
+        chunks.push_back(CChunk{r0, std::min(rows, r0 + step), nf, nu, cn.yoff, cn.coff,
+                                fcol_off[t], ucol_off[t], fwd_off[t]});
     }
     c->fwd_levels.push_back({first, (int)chunks.size() - first});
   }
   for (int d = 0; d <= F.depth; ++d) {
     const int first = (int)chunks.size();
-    for (size_t t = 0; t < F.nodes.size(); ++t) {
-      if (F.nodes[t].depth != d) continue;
-      const int rows = nodes[t].nf;
-      for (int r0 = 0; r0 < rows; r0 += kRowsPerChunk)
-        chunks.push_back(CChunk{(int)t, r0, std::min(rows, r0 + kRowsPerChunk), 0});
+    for (int t = 0; t < nn; ++t) {
+      const auto& cn = F.nodes[t];
+      if (cn.depth != d) continue;
+      const int nf = (int)cn.frow.size(), nu = (int)cn.urow.size();
+      const int step = nu > 0 ? slice_rows(nu) : std::max(nf, 1);
+      for (int r0 = 0; r0 < nf; r0 += step)
+        chunks.push_back(CChunk{r0, std::min(nf, r0 + step), nf, nu, cn.yoff, cn.coff,
+                                fcol_off[t], ucol_off[t], bwd_off[t]});
     }
     c->bwd_levels.push_back({first, (int)chunks.size() - first});
   }
-  c->cnodes = c->upload(nodes, s);
+  // right-hand-side sources and contribution destinations by tree position
+  const int np = F.ylen;
+  std::vector<int4> gsrc(np);
+  for (int t = 0; t < np; ++t) {
+    const int row = F.nd_row[t];
+    const int kind = row == S.pin_row ? 2 : S.rowKind[row];
+    gsrc[t] = make_int4(S.rowL[row], S.rowR[row], kind, 0);
+  }
+  std::vector<int> cdest(std::max(F.clen, 1), 0);
+  for (int t = 0; t < np; ++t)
+    for (int u = 0; u < F.maxp; ++u) {
+      const int q = F.slots[(size_t)t * F.maxp + u];
+      if (q >= 0) cdest[q] = u * np + t;
+    }
   c->cfwd = c->upload(fwd, s);
   c->cbwd = c->upload(bwd, s);
   c->cidx = c->upload(idx, s);
-  c->nd_row = c->upload(F.nd_row, s);
-  c->nd_scale = c->upload(F.nd_scale, s);
-  c->slots = c->upload(F.slots, s);
+  c->gsrc = c->upload(gsrc, s);
+  c->gscale = c->upload(F.nd_scale, s);
+  c->cdest = c->upload(cdest, s);
   c->maxp = F.maxp;
+  c->np = np;
+  c->g_nd = c->alloc<double>(std::max(np, 1));
+  c->contrib = c->alloc<double>((size_t)np * F.maxp);
+  hip_check(hipMemsetAsync(c->contrib, 0, sizeof(double) * (size_t)np * F.maxp, s),
+            "hipMemsetAsync");
   c->chunks = c->upload(chunks, s);
   c->ybuf = c->alloc<double>(F.ylen);
-  c->cbuf = c->alloc<double>(F.clen);
   c->max_nf = max_nf;
   c->max_nu = max_nu;
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
@@ -316,20 +339,19 @@ void apply_one(mrcm_ctx* c, const double* r, double* z, hipStream_t s) {
   };
   begin();
   mrcm::launch_local<T, S>(c->lbox, c->m, c->max_cells_local, c->max_bx_local,
-                           c->max_bs_local, static_cast<const S*>(c->ldinv),
+                           static_cast<const S*>(c->ldinv),
                            static_cast<const S*>(c->lcoup), r, p, c->nx, c->dof_off,
                            c->dof_side, c->w_off, c->wU, c->wP, c->mU, c->mP, s);
   end(0);
   if (c->nc > 0) {
     begin();
-    mrcm::launch_coarse_rhs(c->nd_row, c->nd_scale, c->rowL, c->rowR, c->rowKind, c->pin_row,
-                            c->mU, c->mP, c->g, c->nc, s);
+    mrcm::launch_coarse_rhs(c->gsrc, c->gscale, c->mU, c->mP, c->g_nd, c->np, s);
     for (const auto& lv : c->fwd_levels)
-      mrcm::launch_coarse_fwd(c->chunks + lv.first, lv.second, c->cnodes, c->cfwd, c->g,
-                              c->slots, c->maxp, c->ybuf, c->cbuf, c->max_nf, s);
+      mrcm::launch_coarse_fwd(c->chunks + lv.first, lv.second, c->cfwd, c->g_nd, c->contrib,
+                              c->maxp, c->np, c->cdest, c->ybuf, c->max_nf, s);
     for (const auto& lv : c->bwd_levels)
-      mrcm::launch_coarse_bwd(c->chunks + lv.first, lv.second, c->cnodes, c->cbwd, c->cidx,
-                              c->ybuf, c->xc, c->max_nu, s);
+      mrcm::launch_coarse_bwd(c->chunks + lv.first, lv.second, c->cbwd, c->cidx, c->ybuf,
+                              c->xc, c->max_nu, s);
     end(1);
     begin();
     mrcm::launch_reconstruct<T, S>(c->lbox, c->m, static_cast<const S*>(c->mbf), c->mbf_off,
@@ -343,7 +365,7 @@ void apply_one(mrcm_ctx* c, const double* r, double* z, hipStream_t s) {
     end(3);
     begin();
     mrcm::launch_patch<T, S>(c->pbox, c->m, c->max_cells_patch, c->max_bx_patch,
-                             c->max_bs_patch, static_cast<const S*>(c->pdinv),
+                             static_cast<const S*>(c->pdinv),
                              static_cast<const S*>(c->pcoup), rho, p, c->nx, s);
     end(4);
   }
@@ -366,10 +388,10 @@ template <typename W, typename X>
 void setup_precision(mrcm_ctx* c, const mrcm::HostSetup& S, hipStream_t s) {
   const mrcm::Maps& M = S.maps;
   upload_boxes<X>(c, S.local, M.boxes, &c->lbox, &c->ldinv, &c->lcoup, &c->max_cells_local,
-                  &c->max_bx_local, &c->max_bs_local, s);
+                  &c->max_bx_local, s);
   if (S.sweeps > 0)
     upload_boxes<X>(c, S.patch, M.boxes, &c->pbox, &c->pdinv, &c->pcoup, &c->max_cells_patch,
-                    &c->max_bx_patch, &c->max_bs_patch, s);
+                    &c->max_bx_patch, s);
   std::vector<X> mbf;
   std::vector<long long> off;
   for (int i = 0; i < M.m; ++i) {
@@ -563,7 +585,6 @@ int mrcm_setup(const mrcm_grid* grid, const mrcm_params* params, const double* K
     c->m = S.maps.m;
     c->nc = S.maps.nc();
     c->n = (long long)n;
-    c->pin_row = S.pin_row;
     c->tx = c->upload(S.tx, s);
     c->ty = c->upload(S.ty, s);
     c->d_bc = c->upload(std::vector<int>(grid->bc, grid->bc + 4), s);
@@ -580,16 +601,12 @@ int mrcm_setup(const mrcm_grid* grid, const mrcm_params* params, const double* K
     c->w_off = c->upload(S.wOff, s);
     c->wU = c->upload(S.wU, s);
     c->wP = c->upload(S.wP, s);
-    c->rowL = c->upload(S.rowL, s);
-    c->rowR = c->upload(S.rowR, s);
-    c->rowKind = c->upload(S.rowKind, s);
     c->mU = c->alloc<double>(c->nc);
     c->mP = c->alloc<double>(c->nc);
-    c->g = c->alloc<double>(c->nc);
     c->xc = c->alloc<double>(c->nc);
     c->partials = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
     c->parts = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
-    upload_coarse(c, CF, s);
+    if (c->nc > 0) upload_coarse(c, CF, S, s);
     c->coarse_pivot = CF.min_pivot_ratio;
     c->coarse_levels = CF.nodes.empty() ? 0 : CF.depth + 1;
     hip_check(hipHostMalloc((void**)&c->h_host, sizeof(double) * (mrcm::kMaxVecBlocks + 64),

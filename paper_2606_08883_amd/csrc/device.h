@@ -19,18 +19,16 @@ struct BoxDesc {
   long long coff;  // offset of the couplings T_j (elements)
 };
 
-// One node of the coarse nested-dissection tree (see coarse.h).
-struct CNodeDesc {
-  int nf, nu;
-  int frow, fcol, ucol;  // offsets into the index arrays
-  int yoff, coff;
-  int pad;
-  long long fwd, bwd;  // offsets into the factor arrays
-};
-
-// A slice [row0, row1) of one node's forward or backward matrix.
+// A chunk of one level of the interface solve: rows [row0, row1) of one
+// node's forward ([W; E], (nf + nu) x nf) or backward (G, nf x nu) matrix,
+// with the node's sizes and offsets copied in so that a workgroup needs one
+// descriptor load: mat, the matrix offset; yoff, the node's first tree
+// position (its y_F rows); coff, its first contribution row; fcol, ucol,
+// offsets of its separator and border dof lists in the index array.
 struct CChunk {
-  int node, row0, row1, pad;
+  int row0, row1, nf, nu;
+  int yoff, coff, fcol, ucol;
+  long long mat;
 };
 
 constexpr int kBoxThreads = 256;
@@ -53,27 +51,28 @@ void launch_rhs(const double* tx, const double* ty, int nx, int ny, const int* b
 // ---- preconditioner apply (arithmetic T, factor storage S) ------------------
 // Boxes are solved by lane groups of 16, 32 or 64 lanes (>= the widest box,
 // at most 64 cells wide); LDS per workgroup: box_lds_bytes() (all ones when a
-// single group exceeds 64 KB).  max_bs: the largest block stride; t, w: bytes
-// of the arithmetic type T and of the factor storage type S.
-size_t box_lds_bytes(int max_bx, int max_cells, int max_bs, size_t t, size_t w);
+// single group exceeds 64 KB).  t, w: bytes of the arithmetic type T and of
+// the factor storage type S.
+size_t box_lds_bytes(int max_bx, int max_cells, size_t t, size_t w);
 template <typename T, typename S>
-void launch_local(const BoxDesc* boxes, int m, int max_cells, int max_bx, int max_bs,
-                  const S* dinv, const S* coup, const double* r, T* p, int nx,
-                  const int* dof_off, const int* dof_side, const int* w_off, const double* wU,
-                  const double* wP, double* mU, double* mP, hipStream_t s);
-// Interface right-hand side from the trace moments, in tree order, times
-// the row equilibration scales.
-void launch_coarse_rhs(const int* nd_row, const double* nd_scale, const int* rowL,
-                       const int* rowR, const int* rowKind, int pin_row, const double* mU,
-                       const double* mP, double* g_nd, int nc, hipStream_t s);
-// One forward level of the interface solve (slots: padded contribution lists,
-// maxp a multiple of 4).
-void launch_coarse_fwd(const CChunk* chunks, int nchunks, const CNodeDesc* nodes,
-                       const double* fwd, const double* g_nd, const int* slots, int maxp,
-                       double* ybuf, double* cbuf, int max_nf, hipStream_t s);
-void launch_coarse_bwd(const CChunk* chunks, int nchunks, const CNodeDesc* nodes,
-                       const double* bwd, const int* idx, const double* ybuf, double* x,
-                       int max_nu, hipStream_t s);
+void launch_local(const BoxDesc* boxes, int m, int max_cells, int max_bx, const S* dinv,
+                  const S* coup, const double* r, T* p, int nx, const int* dof_off,
+                  const int* dof_side, const int* w_off, const double* wU, const double* wP,
+                  double* mU, double* mP, hipStream_t s);
+// Interface solve: the right-hand side g_nd in tree order (np positions;
+// gsrc[t] = {L, R, kind, 0} names the trace moments of the row at tree
+// position t and its kind, gscale[t] its equilibration scale), then one
+// launch per tree level, forward levels leaves first, backward levels root
+// first.  contrib (maxp slots per tree position, slot u of position t at
+// u * np + t, zero where unused) receives the descendants' contributions at
+// cdest; max_nf / max_nu bound the LDS vector.
+void launch_coarse_rhs(const int4* gsrc, const double* gscale, const double* mU,
+                       const double* mP, double* g_nd, int np, hipStream_t s);
+void launch_coarse_fwd(const CChunk* chunks, int nchunks, const double* fwd, const double* g_nd,
+                       double* contrib, int maxp, int np, const int* cdest, double* ybuf,
+                       int max_nf, hipStream_t s);
+void launch_coarse_bwd(const CChunk* chunks, int nchunks, const double* bwd, const int* idx,
+                       const double* ybuf, double* x, int max_nu, hipStream_t s);
 template <typename T, typename S>
 void launch_reconstruct(const BoxDesc* boxes, int m, const S* mbf, const long long* mbf_off,
                         const int* dof_off, const double* xc, T* p, int nx, hipStream_t s);
@@ -81,8 +80,8 @@ template <typename T>
 void launch_residual(const T* tx, const T* ty, int nx, int ny, const double* r, const T* p,
                      T* rho, hipStream_t s);
 template <typename T, typename S>
-void launch_patch(const BoxDesc* boxes, int m, int max_cells, int max_bx, int max_bs,
-                  const S* dinv, const S* coup, const T* rho, T* p, int nx, hipStream_t s);
+void launch_patch(const BoxDesc* boxes, int m, int max_cells, int max_bx, const S* dinv,
+                  const S* coup, const T* rho, T* p, int nx, hipStream_t s);
 template <typename T>
 void launch_finalize(const T* p, long long n, int noflow, double* z, double* partials,
                      hipStream_t s);

@@ -82,18 +82,14 @@ __global__ void k_rhs(const double* __restrict__ tx, const double* __restrict__ 
   }
 }
 
-// Block LDL^T solve of one cell box by one group of GS lanes of a wave
-// (GS = 16, 32 or 64 >= bx; 64 / GS boxes per wave).  Lane r owns cell
-// column r of every cell row j:
+// ---- batched box solves ---------------------------------------------------
+// One lane group of GS lanes (GS = 16, 32 or 64 >= the box width bx, 64 / GS
+// boxes per wave) solves one cell box with the block LDL^T factor of its cell
+// rows.  Lane r owns cell column r of every row j:
 //   forward  u_j = D_j^-1 (b_j + T_j u_{j-1}),
 //   backward x_j = u_j + D_j^-1 (T_{j+1} x_{j+1}).
-// The elementwise coupling terms stay in the lane; the GEMV needs the whole
-// vector, which the group broadcasts through its slot ys[0..bx) of LDS.  Lane
-// r reads column r of the symmetric D_j^-1, i.e. D[c * bx + r] for every c, so
-// each load instruction is contiguous across the group; the next block is
-// prefetched into registers while the current one is used.  All exchange is
-// wave-local (no workgroup barrier).  us holds b on entry, x on exit
-// (by rows of bx, LDS).
+// All exchange between the lanes of a group goes through the group's slot of
+// LDS and is wave-local (no workgroup barrier).
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
 // 16-byte native vector type of a word type (clang vector extension, kept in
@@ -104,11 +100,22 @@ template <typename T> struct Vec16;
 template <> struct Vec16<float> { using type = f32x4; };
 template <> struct Vec16<double> { using type = f64x2; };
 
-// Staging of one D_j^-1 block (bstride words, 16-byte aligned, contiguous)
-// through registers into an LDS buffer by all GS lanes of the group.  Indices
-// past the block are clamped to its last vector (the load and the store then
-// repeat that vector with identical data), which keeps the register array
-// statically indexed.
+// Vectors per lane that stage the largest block of an NB-wide launch.
+template <typename S, int NB, int GS>
+constexpr int stage_vectors() {
+  return ((NB * NB + 16 / (int)sizeof(S) - 1) / (16 / (int)sizeof(S)) + GS - 1) / GS;
+}
+
+// Blocks in flight per group: as many as 64 VGPRs hold (4 per 16-byte
+// vector), between 2 and 4.
+template <int MAXV>
+constexpr int prefetch_depth() {
+  return 16 * MAXV <= 64 ? 4 : 12 * MAXV <= 64 ? 3 : 2;
+}
+
+// Issue the loads of one block (nvec 16-byte vectors) into registers, spread
+// over the group.  Indices past the block repeat its last vector, which
+// keeps the register array statically indexed.
 template <typename V, int GS, int MAXV>
 __device__ __forceinline__ void stage_load(V (&reg)[MAXV], const void* __restrict__ src, int nvec,
                                            int lane) {
@@ -120,6 +127,8 @@ __device__ __forceinline__ void stage_load(V (&reg)[MAXV], const void* __restric
   }
 }
 
+// Store a staged block into an LDS buffer (the clamped indices store the
+// repeated last vector again, with identical data).
 template <typename V, int GS, int MAXV>
 __device__ __forceinline__ void stage_store(const V (&reg)[MAXV], void* dst, int nvec, int lane) {
   V* d = reinterpret_cast<V*>(dst);
@@ -130,87 +139,203 @@ __device__ __forceinline__ void stage_store(const V (&reg)[MAXV], void* dst, int
   }
 }
 
+// Make v opaque to the optimiser at this point, so that addresses derived
+// from it are recomputed here instead of being hoisted out of the row loop
+// into registers for the whole kernel.
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // acc = sum_c D[c * bx + r] ys[c]: lane r's column of the LDS block (symmetric,
-// so it is row r) against the broadcast vector.
+// so it is row r) against the broadcast vector; each LDS read instruction is
+// contiguous across the group.  r < bx; rows c >= bx read row bx - 1 of the
+// block and meet ys[c] = 0, so every read is unconditional and inside the
+// block.
 template <typename T, typename S, int NB>
 __device__ __forceinline__ T lds_dot(const S* D, const T* ys, int bx, int r) {
   T acc = T(0);
+  const S* col = D + opaque(r);
+  const int n = opaque(bx);
 #pragma unroll
-  for (int c = 0; c < NB; ++c)
-    if (c < bx) acc += (T)D[c * bx + r] * ys[c];
+  for (int c = 0; c < NB; ++c) acc += (T)col[(c < n ? c : n - 1) * n] * ys[c];
   return acc;
 }
 
-// Block LDL^T solve of one box by a group of GS lanes; lane r owns cell column
-// r of every cell row j (see the comment above wave_sync):
-//   forward  u_j = D_j^-1 (b_j + T_j u_{j-1}),
-//   backward x_j = u_j + D_j^-1 (T_{j+1} x_{j+1}).
-// Each D_j^-1 block is loaded one step ahead with 16-byte vector loads spread
-// over the whole group and staged into one of two LDS buffers (Db), so the
-// global loads of step j+1 are in flight while step j reads the other
-// buffer.  us holds b on entry, x on exit (by rows of bx words, LDS).  S is
-// the storage type of the factors, T the arithmetic and vector type (FP32
-// factors may be applied in FP64 arithmetic).
-template <typename T, typename S, int NB, int GS, int MAXV>
-__device__ __forceinline__ void box_solve_rows(T* us, T* ys, S* Db, const S* __restrict__ Dinv,
-                                               const S* __restrict__ coup, int bx, int by,
-                                               int bstride, int r, bool act) {
+// Largest value of v over the 64 lanes of the wave, as a wave-uniform value.
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+// One sweep over the block rows of the boxes of a wave.  Group step s uses
+// block blk(s) of its Dinv, staged into LDS buffer s & 1; the loads of block
+// s + DEPTH are issued at step s into the register set that block s has just
+// left, so every block has DEPTH - 1 steps to arrive before it is stored to
+// LDS.  The boxes of a wave have different heights, so the wave runs nmax
+// steps (the wave's largest count, rounded up to a multiple of DEPTH); a
+// group's steps past its own nsteps re-load its last block and are told
+// valid = false.  No load is conditional, so the compiler can count the
+// loads in flight exactly and waits only for the block it stores.
+template <typename S, int NB, int GS, int MAXV, int DEPTH, typename Blk, typename Step>
+__device__ __forceinline__ void pipelined_sweep(int nsteps, int nmax, Blk blk, Step step, S* Db,
+                                                int lds_blk, const S* __restrict__ Dinv,
+                                                int bstride, int lane) {
   using V = typename Vec16<S>::type;
   constexpr int EPV = 16 / sizeof(S);
   const int nvec = bstride / EPV;
-  V reg[MAXV];
-  stage_load<V, GS, MAXV>(reg, Dinv, nvec, r);
-  stage_store<V, GS, MAXV>(reg, Db, nvec, r);
+  const int last = nsteps > 0 ? nsteps - 1 : 0;
+  auto src = [&](int s) {
+    const int b = blk(s < last ? s : last);
+    return Dinv + (long long)(b > 0 ? b : 0) * bstride;
+  };
+  V reg[DEPTH][MAXV];
+#pragma unroll
+  for (int u = 0; u < DEPTH; ++u) stage_load<V, GS, MAXV>(reg[u], src(u), nvec, lane);
+  stage_store<V, GS, MAXV>(reg[0], Db, nvec, lane);
   wave_sync();
-  T u_prev = T(0);
-  for (int j = 0; j < by; ++j) {
-    if (j + 1 < by) stage_load<V, GS, MAXV>(reg, Dinv + (long long)(j + 1) * bstride, nvec, r);
-    if (act) ys[r] = us[j * bx + r] + (j > 0 ? (T)coup[j * bx + r] * u_prev : T(0));
-    wave_sync();
-    const T acc = lds_dot<T, S, NB>(Db + (j & 1) * bstride, ys, bx, r);
-    wave_sync();
-    if (act) us[j * bx + r] = acc;
-    u_prev = acc;
-    if (j + 1 < by) stage_store<V, GS, MAXV>(reg, Db + ((j + 1) & 1) * bstride, nvec, r);
-    wave_sync();
-  }
-  if (by < 2) return;
-  T x_next = u_prev;
-  stage_load<V, GS, MAXV>(reg, Dinv + (long long)(by - 2) * bstride, nvec, r);
-  stage_store<V, GS, MAXV>(reg, Db, nvec, r);
-  wave_sync();
-  int buf = 0;
-  for (int j = by - 2; j >= 0; --j) {
-    if (j > 0) stage_load<V, GS, MAXV>(reg, Dinv + (long long)(j - 1) * bstride, nvec, r);
-    if (act) ys[r] = (T)coup[(j + 1) * bx + r] * x_next;
-    wave_sync();
-    const T acc = lds_dot<T, S, NB>(Db + buf * bstride, ys, bx, r);
-    wave_sync();
-    T xj = T(0);
-    if (act) {
-      xj = us[j * bx + r] + acc;
-      us[j * bx + r] = xj;
+  for (int s0 = 0; s0 < nmax; s0 += DEPTH) {
+#pragma unroll
+    for (int u = 0; u < DEPTH; ++u) {
+      const int s = s0 + u;
+      stage_load<V, GS, MAXV>(reg[u], src(s + DEPTH), nvec, lane);
+      step(s, Db + (s & 1) * lds_blk, s < nsteps);
+      stage_store<V, GS, MAXV>(reg[(u + 1) % DEPTH], Db + ((s + 1) & 1) * lds_blk, nvec, lane);
+      wave_sync();
     }
-    x_next = xj;
-    if (j > 0) stage_store<V, GS, MAXV>(reg, Db + (buf ^ 1) * bstride, nvec, r);
-    buf ^= 1;
-    wave_sync();
   }
 }
 
-// Vectors per lane needed to stage the widest block of a launch.
-template <typename T, int NB, int GS>
-constexpr int stage_vectors() {
-  return ((NB * NB + 16 / (int)sizeof(T) - 1) / (16 / (int)sizeof(T)) + GS - 1) / GS;
+// Steps a wave runs for the largest of n over its groups: rounded up to a
+// multiple of DEPTH.
+template <int DEPTH>
+__device__ __forceinline__ int wave_steps(int n) {
+  const int m = wave_max(n);
+  return (m + DEPTH - 1) / DEPTH * DEPTH;
 }
+
+// Block LDL^T solve of one box by a group; us holds b on entry and x on exit
+// (by rows of bx words, LDS); cp holds the couplings T_j (LDS).  S is the
+// storage type of the factors, T the arithmetic and vector type (FP32
+// factors may be applied in FP64 arithmetic).  Lanes at or past bx (and
+// whole groups with live = false) take part in every step but read only
+// inside the box and write nothing; they set their broadcast slot to zero.
+template <typename T, typename S, int NB, int GS>
+__device__ __forceinline__ void box_solve(T* us, T* ys, S* Db, int lds_blk, const S* cp,
+                                          const S* __restrict__ Dinv, int bx, int by,
+                                          int bstride, int r, bool live) {
+  constexpr int MAXV = stage_vectors<S, NB, GS>();
+  constexpr int DEPTH = prefetch_depth<MAXV>();
+  const bool act = live && r < bx;
+  const int rc = r < bx ? r : bx - 1;
+  T carry = T(0);
+  pipelined_sweep<S, NB, GS, MAXV, DEPTH>(
+      live ? by : 0, wave_steps<DEPTH>(live ? by : 0), [](int s) { return s; },
+      [&](int s, const S* D, bool valid) {
+        const int j = s < by ? s : by - 1;
+        const T y = us[j * bx + rc] + (j > 0 ? (T)cp[j * bx + rc] * carry : T(0));
+        const bool w = act && valid;
+        ys[r] = w ? y : T(0);
+        wave_sync();
+        const T acc = lds_dot<T, S, NB>(D, ys, bx, rc);
+        wave_sync();
+        if (w) us[j * bx + r] = acc;
+        carry = w ? acc : carry;
+      },
+      Db, lds_blk, Dinv, bstride, r);
+  // carry = x_{by-1} = u_{by-1}
+  const int nb = live && by > 1 ? by - 1 : 0;
+  pipelined_sweep<S, NB, GS, MAXV, DEPTH>(
+      nb, wave_steps<DEPTH>(nb), [by](int s) { return by - 2 - s; },
+      [&](int s, const S* D, bool valid) {
+        int j = by - 2 - s;
+        j = j < 0 ? 0 : j;
+        const int jn = j + 1 < by ? j + 1 : by - 1;
+        const bool w = act && valid;
+        ys[r] = w ? (T)cp[jn * bx + rc] * carry : T(0);
+        wave_sync();
+        const T acc = lds_dot<T, S, NB>(D, ys, bx, rc);
+        wave_sync();
+        const T xj = us[j * bx + rc] + acc;
+        if (w) us[j * bx + r] = xj;
+        carry = w ? xj : carry;
+      },
+      Db, lds_blk, Dinv, bstride, r);
+}
+
+// Copy rows [0, by) of a box (bx cells wide, lane r: column r) from a global
+// grid vector into LDS, eight rows of loads in flight at a time.  Loads are
+// unconditional (row and column clamped into the box); the wave runs the
+// rows of its tallest box.
+template <typename T, typename G>
+__device__ __forceinline__ void rows_to_lds(T* dst, const G* __restrict__ src, long long origin,
+                                            int nx, int bx, int by, int lane, bool live) {
+  const int rows = wave_max(live ? by : 0);
+  const int col = lane < bx ? lane : bx - 1;
+  const bool act = live && lane < bx;
+  for (int j0 = 0; j0 < rows; j0 += 8) {
+    G v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + u < by ? j0 + u : by - 1;
+      v[u] = src[origin + (long long)j * nx + col];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (act && j0 + u < by) dst[(j0 + u) * bx + lane] = (T)v[u];
+  }
+}
+
+// Copy count (>= 1) contiguous words from global memory into LDS with the
+// whole group, eight unconditional loads in flight per lane at a time.
+template <typename S, int GS>
+__device__ __forceinline__ void words_to_lds(S* dst, const S* __restrict__ src, int count,
+                                             int lane, bool live) {
+  const int total = wave_max(live ? count : 0);
+  for (int q0 = 0; q0 < total; q0 += 8 * GS) {
+    S v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = q0 + u * GS + lane;
+      v[u] = src[q < count ? q : count - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = q0 + u * GS + lane;
+      if (live && q < count) dst[q] = v[u];
+    }
+  }
+}
+
+// LDS slot of one lane group:
+//   ys[GS] (T) | Db[2 * lds_blk] (S) | cp[max cells] (S) | us[max cells] (T),
+// every part 16-byte aligned; lds_blk (the block stride) and cp_words (the
+// coupling area) are multiples of 16 bytes.
+template <typename T, typename S, int GS>
+struct BoxSlot {
+  T* ys;
+  S* Db;
+  S* cp;
+  T* us;
+  __device__ BoxSlot(char* base, int lds_blk, int cp_words) {
+    ys = reinterpret_cast<T*>(base);
+    Db = reinterpret_cast<S*>(base + GS * sizeof(T));
+    cp = reinterpret_cast<S*>(base + GS * sizeof(T) + 2 * (long long)lds_blk * sizeof(S));
+    us = reinterpret_cast<T*>(base + GS * sizeof(T) +
+                              (2 * (long long)lds_blk + cp_words) * sizeof(S));
+  }
+};
 
 // Local Robin particular solves p_{i,r} = A_i^-1 r[Omega_i], one lane group
 // per subdomain, fused with the trace moments of the coarse right-hand side:
 // mU[k] = sum_j wU[k][j] p(face cell j), mP[k] likewise, for every coarse dof
-// k = (i, side, q) of the subdomain (one lane per dof, FP64 sums).
+// k = (i, side, q) of the subdomain (one lane per dof, FP64 sums).  Groups
+// past the last subdomain (live = false) run along on the last one and write
+// nothing.
 template <typename T, typename S, int NB, int GS = (NB <= 16 ? 16 : NB <= 32 ? 32 : 64)>
 __global__ void __launch_bounds__(kBoxThreads)
-    k_local(const BoxDesc* __restrict__ boxes, int m, int group_bytes, int blk_stride,
+    k_local(const BoxDesc* __restrict__ boxes, int m, int group_bytes, int lds_blk, int cp_words,
             const S* __restrict__ dinv, const S* __restrict__ coup,
             const double* __restrict__ r, T* __restrict__ p, int nx,
             const int* __restrict__ dof_off, const int* __restrict__ dof_side,
@@ -218,157 +343,212 @@ __global__ void __launch_bounds__(kBoxThreads)
             const double* __restrict__ wP, double* __restrict__ mU, double* __restrict__ mP) {
   extern __shared__ __align__(16) char smem_raw[];
   const int grp = threadIdx.x / GS, lane = threadIdx.x % GS;
-  const int i = blockIdx.x * (blockDim.x / GS) + grp;
-  // per group: ys[GS] (T) | Db[2 * max block stride] (S) | us[max cells] (T),
-  // every part 16-byte aligned
-  char* base = smem_raw + (long long)grp * group_bytes;
-  T* ys = reinterpret_cast<T*>(base);
-  S* Db = reinterpret_cast<S*>(base + GS * sizeof(T));
-  T* us = reinterpret_cast<T*>(base + GS * sizeof(T) + 2 * (long long)blk_stride * sizeof(S));
-  if (i >= m) return;  // whole group leaves together
+  const int i0 = blockIdx.x * (blockDim.x / GS) + grp;
+  const bool live = i0 < m;
+  const int i = live ? i0 : m - 1;
+  BoxSlot<T, S, GS> L(smem_raw + (long long)grp * group_bytes, lds_blk, cp_words);
   const BoxDesc d = boxes[i];
   const int bx = d.bx, by = d.by;
-  const bool act = lane < bx;
+  const bool act = live && lane < bx;
+  const long long origin = (long long)d.y0 * nx + d.x0;
+  rows_to_lds(L.us, r, origin, nx, bx, by, lane, live);
+  words_to_lds<S, GS>(L.cp, coup + d.coff, bx * by, lane, live);
+  wave_sync();
+  if (live && d.pin && lane == 0) L.us[0] = T(0);
+  wave_sync();
+  box_solve<T, S, NB, GS>(L.us, L.ys, L.Db, lds_blk, L.cp, dinv + d.doff, bx, by, d.bs, lane,
+                          live);
+  wave_sync();
   if (act)
-    for (int j = 0; j < by; ++j) us[j * bx + lane] = (T)r[(long long)(d.y0 + j) * nx + d.x0 + lane];
-  wave_sync();
-  if (d.pin && lane == 0) us[0] = T(0);
-  wave_sync();
-  box_solve_rows<T, S, NB, GS, stage_vectors<S, NB, GS>()>(us, ys, Db, dinv + d.doff,
-                                                          coup + d.coff, bx, by, d.bs, lane,
-                                                          act);
-  wave_sync();
-  if (act)
-    for (int j = 0; j < by; ++j) p[(long long)(d.y0 + j) * nx + d.x0 + lane] = us[j * bx + lane];
+    for (int j = 0; j < by; ++j) p[origin + (long long)j * nx + lane] = L.us[j * bx + lane];
+  if (!live) return;
   for (int k = dof_off[i] + lane; k < dof_off[i + 1]; k += GS) {
     const int side = dof_side[k];
     const int len = (side <= 1) ? by : bx;
     const double* wu = wU + w_off[k];
     const double* wp = wP + w_off[k];
     double su = 0.0, sp = 0.0;
-    for (int jf = 0; jf < len; ++jf) {
-      const int cell = side == 0 ? jf * bx
-                     : side == 1 ? jf * bx + bx - 1
-                     : side == 2 ? jf
-                                 : (by - 1) * bx + jf;
-      const double v = (double)us[cell];
-      su += wu[jf] * v;
-      sp += wp[jf] * v;
+    for (int j0 = 0; j0 < len; j0 += 8) {
+      double a[8], b[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int jf = j0 + u < len ? j0 + u : len - 1;
+        a[u] = wu[jf];
+        b[u] = wp[jf];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int jf = j0 + u;
+        if (jf < len) {
+          const int cell = side == 0 ? jf * bx
+                         : side == 1 ? jf * bx + bx - 1
+                         : side == 2 ? jf
+                                     : (by - 1) * bx + jf;
+          const double v = (double)L.us[cell];
+          su += a[u] * v;
+          sp += b[u] * v;
+        }
+      }
     }
     mU[k] = su;
     mP[k] = sp;
   }
 }
 
-// Interface right-hand side in tree order: g_nd[t] for the coarse row
-// nd_row[t] is minus the row functional of the particular traces (a flux row
-// adds the two sides' moments, a pressure row subtracts them), times the
-// row's equilibration scale; the replaced row of an all-no-flow grid gets zero.
-__global__ void k_coarse_rhs(const int* __restrict__ nd_row, const double* __restrict__ nd_scale,
-                             const int* __restrict__ rowL, const int* __restrict__ rowR,
-                             const int* __restrict__ rowKind, int pin_row,
+// Interface right-hand side in tree order: for tree position t, gsrc[t] =
+// {L, R, kind}: kind 0 a flux row, g = -(mU[L] + mU[R]); 1 a pressure row,
+// g = -(mP[L] - mP[R]); 2 the replaced row of an all-no-flow grid, g = 0;
+// times the row's equilibration scale gscale[t].
+__global__ void k_coarse_rhs(const int4* __restrict__ gsrc, const double* __restrict__ gscale,
                              const double* __restrict__ mU, const double* __restrict__ mP,
-                             double* __restrict__ g_nd, int nc) {
+                             double* __restrict__ g_nd, int np) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nc) return;
-  const int row = nd_row[t];
-  const int L = rowL[row], R = rowR[row];
-  const double v = rowKind[row] == 0 ? -(mU[L] + mU[R]) : -(mP[L] - mP[R]);
-  g_nd[t] = row == pin_row ? 0.0 : nd_scale[t] * v;
+  if (t >= np) return;
+  const int4 src = gsrc[t];
+  const double v = src.z == 0 ? -(mU[src.x] + mU[src.y]) : -(mP[src.x] - mP[src.y]);
+  g_nd[t] = src.z == 2 ? 0.0 : gscale[t] * v;
 }
 
-// Rows [row0, row1) of an (rows x ncol) row-major matrix times the LDS vector
-// vec, one wave per group of four rows; lane 0 hands each result to
-// emit(row, value).  The column loop is unrolled eight deep, so a wave has up
-// to 32 loads in flight before it waits.
-template <typename Emit>
-__device__ __forceinline__ void gemv_rows(const double* __restrict__ M, int ncol, int row0,
-                                          int row1, const double* vec, Emit emit) {
+// ---- interface solve (level-scheduled nested dissection) -------------------
+// One launch per tree level and direction; a workgroup takes one chunk, rows
+// [row0, row1) of one node's matrix (see device.h).  Each wave takes groups
+// of four rows (wave w: rows row0 + 4 w + 16 k); lanes stride the columns
+// eight deep, so a wave has 32 matrix loads in flight.  The first group's
+// loads are issued before the right-hand side is gathered, so their latency
+// overlaps the gather.
+
+// Issue the loads of one 4 x (8 x 64) tile: rows r .. r + 3 (clipped at
+// row1), columns b0 + 64 q (clipped at ncol); missing entries read as zero.
+__device__ __forceinline__ void load_tile(double (&m)[4][8], const double* __restrict__ M,
+                                          int ncol, int r, int row1, int b0) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int b = b0 + 64 * q;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      m[u][q] = (b < ncol && r + u < row1) ? M[(long long)(r + u) * ncol + b] : 0.0;
+  }
+}
+
+// s[u] += sum_q m[u][q] vec[b0 + 64 q] (vector in LDS).
+__device__ __forceinline__ void fma_tile(double (&s)[4], const double (&m)[4][8],
+                                         const double* vec, int ncol, int b0) {
+  double x[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) x[q] = b0 + 64 * q < ncol ? vec[b0 + 64 * q] : 0.0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s[u] += m[u][q] * x[q];
+}
+
+// Rows [row0, row1) of M (row-major, ncol columns) times the LDS vector; the
+// tile m holds this wave's first tile (rows row0 + 4 wid, columns lane ..),
+// and pre(row0 + 4 wid) has already been called.  For every later group of
+// four rows r .. r + 3, pre(r) is called first (lane u may fetch what it
+// needs for row r + u); then emit(r + u, value) runs in lane u.
+template <typename Pre, typename Emit>
+__device__ __forceinline__ void gemv_chunk(const double* __restrict__ M, int ncol, int row0,
+                                           int row1, const double* vec, double (&m)[4][8],
+                                           Pre pre, Emit emit) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int r = row0 + 4 * wid; r < row1; r += 4 * nw) {
+    const bool first = r == row0 + 4 * wid;
+    if (!first) pre(r);
     double s[4] = {0.0, 0.0, 0.0, 0.0};
-    const int nrow = row1 - r < 4 ? row1 - r : 4;
-    for (int b0 = lane; b0 < ncol; b0 += 64 * 8) {
-      double m[4][8], x[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int b = b0 + 64 * q;
-        const bool in = b < ncol;
-        x[q] = in ? vec[b] : 0.0;
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          m[u][q] = (in && u < nrow) ? M[(long long)(r + u) * ncol + b] : 0.0;
-      }
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) s[u] += m[u][q] * x[q];
+    fma_tile(s, m, vec, ncol, lane);
+    for (int b0 = lane + 64 * 8; b0 < ncol; b0 += 64 * 8) {
+      load_tile(m, M, ncol, r, row1, b0);
+      fma_tile(s, m, vec, ncol, b0);
     }
+    if (r + 4 * nw < row1) load_tile(m, M, ncol, r + 4 * nw, row1, lane);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const double t = wave_sum(s[u]);
-      if (lane == 0 && u < nrow) emit(r + u, t);
+      if (lane == u && r + u < row1) emit(r + u, t);
     }
   }
 }
 
-// Forward level of the coarse solve: v = g_F - contributions of descendants
-// (fixed order, slots read four at a time), then rows [row0, row1) of
-// [W; E] v: y_F for the separator rows, c_n for the bordering rows.
+// Forward level: for the separator rows a of the chunk's node (tree
+// positions t = yoff + a),
+//   v[a] = g_nd[t] - (contributions of the descendants, in slot order),
+// with the contributions by destination in contrib[u * np + t] (slot u,
+// zero where unused).  Then rows of [W; E] v: y_F into ybuf, each c_n row
+// into its destination slot cdest[coff + row - nf].
 __global__ void __launch_bounds__(kVecThreads)
-    k_coarse_fwd(const CChunk* __restrict__ chunks, const CNodeDesc* __restrict__ nodes,
-                 const double* __restrict__ fwd, const double* __restrict__ g_nd,
-                 const int* __restrict__ slots, int maxp, double* __restrict__ ybuf,
-                 double* __restrict__ cbuf) {
+    k_coarse_fwd(const CChunk* __restrict__ chunks, const double* __restrict__ fwd,
+                 const double* __restrict__ g_nd, double* __restrict__ contrib, int maxp, int np,
+                 const int* __restrict__ cdest, double* __restrict__ ybuf) {
   extern __shared__ double v[];
   const CChunk ch = chunks[blockIdx.x];
-  const CNodeDesc nd = nodes[ch.node];
-  const int nf = nd.nf;
+  const int nf = ch.nf;
+  const double* M = fwd + ch.mat;
+  const int yoff = ch.yoff, coff = ch.coff;
+  int dst = -1;
+  auto pre = [&](int r) {
+    const int lane = threadIdx.x & 63, row = r + lane;
+    dst = (lane < 4 && row >= nf && row < ch.row1) ? cdest[coff + row - nf] : -1;
+  };
+  double m[4][8];
+  const int rw = ch.row0 + 4 * (threadIdx.x >> 6);
+  load_tile(m, M, nf, rw, ch.row1, threadIdx.x & 63);
+  pre(rw);
   for (int a = threadIdx.x; a < nf; a += blockDim.x) {
-    const long long t = (long long)nd.yoff + a;
+    const long long t = (long long)yoff + a;
     double s = g_nd[t];
-    const int4* sl = reinterpret_cast<const int4*>(slots + t * maxp);
-    for (int u = 0; u < maxp / 4; ++u) {
-      const int4 q = sl[u];
-      const double c0 = q.x >= 0 ? cbuf[q.x] : 0.0, c1 = q.y >= 0 ? cbuf[q.y] : 0.0;
-      const double c2 = q.z >= 0 ? cbuf[q.z] : 0.0, c3 = q.w >= 0 ? cbuf[q.w] : 0.0;
-      s -= c0;
-      s -= c1;
-      s -= c2;
-      s -= c3;
+    for (int u0 = 0; u0 < maxp; u0 += 8) {
+      double c[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        c[k] = u0 + k < maxp ? contrib[(long long)(u0 + k) * np + t] : 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (u0 + k < maxp) s -= c[k];
     }
     v[a] = s;
   }
   __syncthreads();
-  const int yoff = nd.yoff, coff = nd.coff;
-  gemv_rows(fwd + nd.fwd, nf, ch.row0, ch.row1, v, [&](int row, double val) {
+  gemv_chunk(M, nf, ch.row0, ch.row1, v, m, pre, [&](int row, double val) {
     if (row < nf)
       ybuf[yoff + row] = val;
     else
-      cbuf[coff + row - nf] = val;
+      contrib[dst] = val;
   });
 }
 
-// Backward level: x_F = y_F - G x_U for rows [row0, row1).
+// Backward level: x_F = y_F - G x_U for the chunk's rows (x_U gathered
+// through idx[ucol ..], x_F scattered through idx[fcol ..]).
 __global__ void __launch_bounds__(kVecThreads)
-    k_coarse_bwd(const CChunk* __restrict__ chunks, const CNodeDesc* __restrict__ nodes,
-                 const double* __restrict__ bwd, const int* __restrict__ idx,
-                 const double* __restrict__ ybuf, double* __restrict__ x) {
+    k_coarse_bwd(const CChunk* __restrict__ chunks, const double* __restrict__ bwd,
+                 const int* __restrict__ idx, const double* __restrict__ ybuf,
+                 double* __restrict__ x) {
   extern __shared__ double xu[];
   const CChunk ch = chunks[blockIdx.x];
-  const CNodeDesc nd = nodes[ch.node];
-  const int nu = nd.nu;
-  for (int b = threadIdx.x; b < nu; b += blockDim.x) xu[b] = x[idx[nd.ucol + b]];
-  __syncthreads();
-  const int yoff = nd.yoff, fcol = nd.fcol;
+  const int nu = ch.nu;
+  const double* M = bwd + ch.mat;
+  const int yoff = ch.yoff, fcol = ch.fcol;
   if (nu == 0) {
     for (int row = ch.row0 + threadIdx.x; row < ch.row1; row += blockDim.x)
       x[idx[fcol + row]] = ybuf[yoff + row];
     return;
   }
-  gemv_rows(bwd + nd.bwd, nu, ch.row0, ch.row1, xu, [&](int row, double val) {
-    x[idx[fcol + row]] = ybuf[yoff + row] - val;
-  });
+  int dst = 0;
+  double y = 0.0;
+  auto pre = [&](int r) {
+    const int lane = threadIdx.x & 63, row = r + lane;
+    if (lane < 4 && row < ch.row1) {
+      dst = idx[fcol + row];
+      y = ybuf[yoff + row];
+    }
+  };
+  double m[4][8];
+  const int rw = ch.row0 + 4 * (threadIdx.x >> 6);
+  load_tile(m, M, nu, rw, ch.row1, threadIdx.x & 63);
+  pre(rw);
+  for (int b = threadIdx.x; b < nu; b += blockDim.x) xu[b] = x[idx[ch.ucol + b]];
+  __syncthreads();
+  gemv_chunk(M, nu, ch.row0, ch.row1, xu, m, pre, [&](int, double val) { x[dst] = y - val; });
 }
 
 // p[Omega_i] += P_i x_i (multiscale reconstruction), one workgroup per subdomain.
@@ -408,39 +588,47 @@ __global__ void __launch_bounds__(kVecThreads)
 
 // Restricted additive Schwarz: solve A[S_i] e = rho[S_i] on patch i (one
 // lane group per patch) and add e on the owned subdomain Omega_i (each cell
-// is written by one patch only).
+// is written by one patch only).  Groups past the last patch run along on
+// the last one and write nothing.
 template <typename T, typename S, int NB, int GS = (NB <= 16 ? 16 : NB <= 32 ? 32 : 64)>
 __global__ void __launch_bounds__(kBoxThreads)
-    k_patch(const BoxDesc* __restrict__ boxes, int m, int group_bytes, int blk_stride,
+    k_patch(const BoxDesc* __restrict__ boxes, int m, int group_bytes, int lds_blk, int cp_words,
             const S* __restrict__ dinv, const S* __restrict__ coup, const T* __restrict__ rho,
             T* __restrict__ p, int nx) {
   extern __shared__ __align__(16) char smem_raw[];
   const int grp = threadIdx.x / GS, lane = threadIdx.x % GS;
-  const int i = blockIdx.x * (blockDim.x / GS) + grp;
-  // per group: ys[GS] (T) | Db[2 * max block stride] (S) | us[max cells] (T),
-  // every part 16-byte aligned
-  char* base = smem_raw + (long long)grp * group_bytes;
-  T* ys = reinterpret_cast<T*>(base);
-  S* Db = reinterpret_cast<S*>(base + GS * sizeof(T));
-  T* us = reinterpret_cast<T*>(base + GS * sizeof(T) + 2 * (long long)blk_stride * sizeof(S));
-  if (i >= m) return;
+  const int i0 = blockIdx.x * (blockDim.x / GS) + grp;
+  const bool live = i0 < m;
+  const int i = live ? i0 : m - 1;
+  BoxSlot<T, S, GS> L(smem_raw + (long long)grp * group_bytes, lds_blk, cp_words);
   const BoxDesc d = boxes[i];
   const int bx = d.bx, by = d.by;
-  const bool act = lane < bx;
-  if (act)
-    for (int j = 0; j < by; ++j) us[j * bx + lane] = rho[(long long)(d.y0 + j) * nx + d.x0 + lane];
+  const long long origin = (long long)d.y0 * nx + d.x0;
+  rows_to_lds(L.us, rho, origin, nx, bx, by, lane, live);
+  words_to_lds<S, GS>(L.cp, coup + d.coff, bx * by, lane, live);
   wave_sync();
-  if (d.pin && lane == 0) us[0] = T(0);
+  if (live && d.pin && lane == 0) L.us[0] = T(0);
   wave_sync();
-  box_solve_rows<T, S, NB, GS, stage_vectors<S, NB, GS>()>(us, ys, Db, dinv + d.doff,
-                                                          coup + d.coff, bx, by, d.bs, lane,
-                                                          act);
+  box_solve<T, S, NB, GS>(L.us, L.ys, L.Db, lds_blk, L.cp, dinv + d.doff, bx, by, d.bs, lane,
+                          live);
   wave_sync();
-  if (lane >= d.ox && lane < d.ox + d.obx)
-    for (int j = 0; j < d.oby; ++j) {
-      const long long c = (long long)(d.y0 + d.oy + j) * nx + d.x0 + lane;
-      p[c] += us[(d.oy + j) * bx + lane];
+  // p += e on the owned cells, eight rows of read-modify-write in flight
+  const bool own = live && lane >= d.ox && lane < d.ox + d.obx;
+  const int col = own ? lane : d.ox;
+  const long long o2 = origin + (long long)d.oy * nx;
+  const int rows = wave_max(live ? d.oby : 0);
+  for (int j0 = 0; j0 < rows; j0 += 8) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + u < d.oby ? j0 + u : d.oby - 1;
+      v[u] = p[o2 + (long long)j * nx + col];
     }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (own && j0 + u < d.oby)
+        p[o2 + (long long)(j0 + u) * nx + lane] = v[u] + L.us[(d.oy + j0 + u) * bx + lane];
+  }
 }
 
 template <typename T>
@@ -599,28 +787,35 @@ inline int col_width(int max_bx) {
        : max_bx <= 48 ? 48 : 64;
 }
 inline int group_size(int max_bx) { return max_bx <= 16 ? 16 : max_bx <= 32 ? 32 : 64; }
-
+// Words of S in 16 bytes; x rounded up to a multiple of them.
+inline int round16(long long x, size_t w) {
+  const long long e = 16 / (long long)w;
+  return (int)((x + e - 1) / e * e);
+}
 // LDS bytes of one lane group: broadcast slot and box (arithmetic words t),
-// two staged blocks (storage words w), rounded to 16 bytes.
-inline size_t group_bytes(int max_bx, int max_cells, int max_bs, size_t t, size_t w) {
-  const size_t b = (size_t)group_size(max_bx) * t + 2 * (size_t)max_bs * w + (size_t)max_cells * t;
+// two expanded blocks and the couplings (storage words w), rounded to 16
+// bytes.
+// LDS words of one staged block: the largest block, rounded up to 16 bytes.
+inline int lds_block_words(int max_bx, size_t w) { return round16((long long)max_bx * max_bx, w); }
+inline size_t group_bytes(int max_bx, int max_cells, size_t t, size_t w) {
+  const size_t b = (size_t)group_size(max_bx) * t +
+                   (2 * (size_t)lds_block_words(max_bx, w) +
+                    (size_t)round16(max_cells, w)) * w +
+                   (size_t)max_cells * t;
   return (b + 15) / 16 * 16;
 }
-
 // Lane groups per workgroup: up to 256 threads, fewer when the boxes' LDS
 // would exceed 64 KB (0 when even one group does not fit).
-int box_groups(int max_bx, int max_cells, int max_bs, size_t t, size_t w) {
+int box_groups(int max_bx, int max_cells, size_t t, size_t w) {
   const int gs = group_size(max_bx);
   for (int groups = kBoxThreads / gs; groups >= 1; groups /= 2)
-    if (groups * group_bytes(max_bx, max_cells, max_bs, t, w) <= 64 * 1024) return groups;
+    if (groups * group_bytes(max_bx, max_cells, t, w) <= 64 * 1024) return groups;
   return 0;
 }
-
-size_t box_lds_bytes(int max_bx, int max_cells, int max_bs, size_t t, size_t w) {
-  const int groups = box_groups(max_bx, max_cells, max_bs, t, w);
-  return groups ? groups * group_bytes(max_bx, max_cells, max_bs, t, w) : ~(size_t)0;
+size_t box_lds_bytes(int max_bx, int max_cells, size_t t, size_t w) {
+  const int groups = box_groups(max_bx, max_cells, t, w);
+  return groups ? groups * group_bytes(max_bx, max_cells, t, w) : ~(size_t)0;
 }
-
 #define MRCM_BOX_DISPATCH(KERNEL, T, S, max_bx, ...)                                      \
   do {                                                                                   \
     switch (col_width(max_bx)) {                                                         \
@@ -632,46 +827,42 @@ size_t box_lds_bytes(int max_bx, int max_cells, int max_bs, size_t t, size_t w) 
       default: hipLaunchKernelGGL((KERNEL<T, S, 64>), __VA_ARGS__); break;               \
     }                                                                                    \
   } while (0)
-
 template <typename T, typename S>
-void launch_local(const BoxDesc* boxes, int m, int max_cells, int max_bx, int max_bs,
-                  const S* dinv, const S* coup, const double* r, T* p, int nx,
-                  const int* dof_off, const int* dof_side, const int* w_off, const double* wU,
-                  const double* wP, double* mU, double* mP, hipStream_t s) {
-  const int groups = box_groups(max_bx, max_cells, max_bs, sizeof(T), sizeof(S));
-  const size_t shm = box_lds_bytes(max_bx, max_cells, max_bs, sizeof(T), sizeof(S));
-  const int gb = (int)group_bytes(max_bx, max_cells, max_bs, sizeof(T), sizeof(S));
+void launch_local(const BoxDesc* boxes, int m, int max_cells, int max_bx, const S* dinv,
+                  const S* coup, const double* r, T* p, int nx, const int* dof_off,
+                  const int* dof_side, const int* w_off, const double* wU, const double* wP,
+                  double* mU, double* mP, hipStream_t s) {
+  const int groups = box_groups(max_bx, max_cells, sizeof(T), sizeof(S));
+  const size_t shm = box_lds_bytes(max_bx, max_cells, sizeof(T), sizeof(S));
+  const int gb = (int)group_bytes(max_bx, max_cells, sizeof(T), sizeof(S));
+  const int lds_blk = lds_block_words(max_bx, sizeof(S));
+  const int cp_words = round16(max_cells, sizeof(S));
   const dim3 grid((m + groups - 1) / groups), block(groups * group_size(max_bx));
-  MRCM_BOX_DISPATCH(k_local, T, S, max_bx, grid, block, shm, s, boxes, m, gb, max_bs,
+  MRCM_BOX_DISPATCH(k_local, T, S, max_bx, grid, block, shm, s, boxes, m, gb, lds_blk, cp_words,
                     dinv, coup, r, p, nx, dof_off, dof_side, w_off, wU, wP, mU, mP);
 }
 
-void launch_coarse_rhs(const int* nd_row, const double* nd_scale, const int* rowL,
-                       const int* rowR, const int* rowKind, int pin_row, const double* mU,
-                       const double* mP, double* g_nd, int nc, hipStream_t s) {
-  if (nc <= 0) return;
-  hipLaunchKernelGGL(k_coarse_rhs, dim3((nc + 255) / 256), dim3(256), 0, s, nd_row, nd_scale,
-                     rowL, rowR, rowKind, pin_row, mU, mP, g_nd, nc);
+void launch_coarse_rhs(const int4* gsrc, const double* gscale, const double* mU,
+                       const double* mP, double* g_nd, int np, hipStream_t s) {
+  if (np <= 0) return;
+  hipLaunchKernelGGL(k_coarse_rhs, dim3((np + 255) / 256), dim3(256), 0, s, gsrc, gscale, mU, mP,
+                     g_nd, np);
 }
-
-void launch_coarse_fwd(const CChunk* chunks, int nchunks, const CNodeDesc* nodes,
-                       const double* fwd, const double* g_nd, const int* slots, int maxp,
-                       double* ybuf, double* cbuf, int max_nf, hipStream_t s) {
+void launch_coarse_fwd(const CChunk* chunks, int nchunks, const double* fwd, const double* g_nd,
+                       double* contrib, int maxp, int np, const int* cdest, double* ybuf,
+                       int max_nf, hipStream_t s) {
   if (nchunks <= 0) return;
   hipLaunchKernelGGL(k_coarse_fwd, dim3(nchunks), dim3(kVecThreads),
-                     sizeof(double) * (size_t)max_nf, s, chunks, nodes, fwd, g_nd, slots, maxp,
-                     ybuf, cbuf);
+                     sizeof(double) * (size_t)(max_nf > 0 ? max_nf : 1), s, chunks, fwd, g_nd,
+                     contrib, maxp, np, cdest, ybuf);
 }
-
-void launch_coarse_bwd(const CChunk* chunks, int nchunks, const CNodeDesc* nodes,
-                       const double* bwd, const int* idx, const double* ybuf, double* x,
-                       int max_nu, hipStream_t s) {
+void launch_coarse_bwd(const CChunk* chunks, int nchunks, const double* bwd, const int* idx,
+                       const double* ybuf, double* x, int max_nu, hipStream_t s) {
   if (nchunks <= 0) return;
   hipLaunchKernelGGL(k_coarse_bwd, dim3(nchunks), dim3(kVecThreads),
-                     sizeof(double) * (size_t)(max_nu > 0 ? max_nu : 1), s, chunks, nodes, bwd,
-                     idx, ybuf, x);
+                     sizeof(double) * (size_t)(max_nu > 0 ? max_nu : 1), s, chunks, bwd, idx,
+                     ybuf, x);
 }
-
 template <typename T, typename S>
 void launch_reconstruct(const BoxDesc* boxes, int m, const S* mbf, const long long* mbf_off,
                         const int* dof_off, const double* xc, T* p, int nx, hipStream_t s) {
@@ -688,13 +879,15 @@ void launch_residual(const T* tx, const T* ty, int nx, int ny, const double* r, 
 }
 
 template <typename T, typename S>
-void launch_patch(const BoxDesc* boxes, int m, int max_cells, int max_bx, int max_bs,
-                  const S* dinv, const S* coup, const T* rho, T* p, int nx, hipStream_t s) {
-  const int groups = box_groups(max_bx, max_cells, max_bs, sizeof(T), sizeof(S));
-  const size_t shm = box_lds_bytes(max_bx, max_cells, max_bs, sizeof(T), sizeof(S));
-  const int gb = (int)group_bytes(max_bx, max_cells, max_bs, sizeof(T), sizeof(S));
+void launch_patch(const BoxDesc* boxes, int m, int max_cells, int max_bx, const S* dinv,
+                  const S* coup, const T* rho, T* p, int nx, hipStream_t s) {
+  const int groups = box_groups(max_bx, max_cells, sizeof(T), sizeof(S));
+  const size_t shm = box_lds_bytes(max_bx, max_cells, sizeof(T), sizeof(S));
+  const int gb = (int)group_bytes(max_bx, max_cells, sizeof(T), sizeof(S));
+  const int lds_blk = lds_block_words(max_bx, sizeof(S));
+  const int cp_words = round16(max_cells, sizeof(S));
   const dim3 grid((m + groups - 1) / groups), block(groups * group_size(max_bx));
-  MRCM_BOX_DISPATCH(k_patch, T, S, max_bx, grid, block, shm, s, boxes, m, gb, max_bs,
+  MRCM_BOX_DISPATCH(k_patch, T, S, max_bx, grid, block, shm, s, boxes, m, gb, lds_blk, cp_words,
                     dinv, coup, rho, p, nx);
 }
 
@@ -749,12 +942,12 @@ void launch_sumsq(const double* x, long long n, double* partials, int nb, hipStr
 }
 
 #define MRCM_INSTANTIATE_TS(T, S)                                                              \
-  template void launch_local<T, S>(const BoxDesc*, int, int, int, int, const S*, const S*,     \
+  template void launch_local<T, S>(const BoxDesc*, int, int, int, const S*, const S*,          \
                                    const double*, T*, int, const int*, const int*, const int*,   \
                                    const double*, const double*, double*, double*, hipStream_t); \
   template void launch_reconstruct<T, S>(const BoxDesc*, int, const S*, const long long*,       \
                                          const int*, const double*, T*, int, hipStream_t);      \
-  template void launch_patch<T, S>(const BoxDesc*, int, int, int, int, const S*, const S*,     \
+  template void launch_patch<T, S>(const BoxDesc*, int, int, int, const S*, const S*,          \
                                    const T*, T*, int, hipStream_t);
 #define MRCM_INSTANTIATE_T(T)                                                                  \
   template void launch_residual<T>(const T*, const T*, int, int, const double*, const T*, T*,   \
