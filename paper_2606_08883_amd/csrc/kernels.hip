@@ -29,26 +29,46 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 // Sum of nb partials, identical order in every block.
+// Elements a thread handles per round of a grid-stride loop: the loads of a
+// round are all issued (indices clamped into range) before any is used, so
+// they are in flight together; a thread still visits its elements in
+// increasing order, so the reductions keep one fixed order.
+constexpr int kRound = 4;
+
 __device__ __forceinline__ double reduce_partials(const double* part, int nb, double* red) {
   double v = 0.0;
-  for (int k = threadIdx.x; k < nb; k += blockDim.x) v += part[k];
+  for (int k0 = threadIdx.x; k0 < nb; k0 += kRound * blockDim.x) {
+    double a[kRound];
+#pragma unroll
+    for (int u = 0; u < kRound; ++u) {
+      const int k = k0 + u * blockDim.x;
+      a[u] = part[k < nb ? k : nb - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kRound; ++u)
+      if (k0 + u * (int)blockDim.x < nb) v += a[u];
+  }
   return block_sum(v, red);
 }
 
 // y_c = sum_f t_f (x_c - x_c') over the four faces; boundary faces carry the
-// Dirichlet half-transmissibility (coupled to zero) or zero.
+// Dirichlet half-transmissibility (coupled to zero) or zero.  Branch-free:
+// missing neighbours are read at the cell itself and meet a zero
+// coefficient, so all loads are unconditional.
 template <typename T>
 __device__ __forceinline__ T stencil(const T* __restrict__ tx, const T* __restrict__ ty, int nx,
                                      int ny, int ix, int iy, const T* __restrict__ x) {
   const long long c = (long long)iy * nx + ix;
-  const T tW = tx[(long long)iy * (nx + 1) + ix], tE = tx[(long long)iy * (nx + 1) + ix + 1];
-  const T tS = ty[(long long)iy * nx + ix], tN = ty[(long long)(iy + 1) * nx + ix];
+  const long long fx = (long long)iy * (nx + 1) + ix;
+  const T tW = tx[fx], tE = tx[fx + 1], tS = ty[c], tN = ty[c + nx];
   const T xc = x[c];
+  const T xw = x[ix > 0 ? c - 1 : c], xe = x[ix + 1 < nx ? c + 1 : c];
+  const T xs = x[iy > 0 ? c - nx : c], xn = x[iy + 1 < ny ? c + nx : c];
   T v = (tW + tE + tS + tN) * xc;
-  if (ix > 0) v -= tW * x[c - 1];
-  if (ix + 1 < nx) v -= tE * x[c + 1];
-  if (iy > 0) v -= tS * x[c - nx];
-  if (iy + 1 < ny) v -= tN * x[c + nx];
+  v -= (ix > 0 ? tW : T(0)) * xw;
+  v -= (ix + 1 < nx ? tE : T(0)) * xe;
+  v -= (iy > 0 ? tS : T(0)) * xs;
+  v -= (iy + 1 < ny ? tN : T(0)) * xn;
   return v;
 }
 
@@ -635,24 +655,51 @@ template <typename T>
 __global__ void __launch_bounds__(kVecThreads)
     k_sum(const T* __restrict__ p, long long n, double* __restrict__ partials) {
   __shared__ double red[kVecThreads / 64];
+  const long long st = (long long)gridDim.x * blockDim.x;
   double s = 0.0;
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
-       c += (long long)gridDim.x * blockDim.x)
-    s += (double)p[c];
+  for (long long c0 = blockIdx.x * (long long)blockDim.x + threadIdx.x; c0 < n;
+       c0 += kRound * st) {
+    T a[kRound];
+#pragma unroll
+    for (int u = 0; u < kRound; ++u) {
+      const long long c = c0 + u * st;
+      a[u] = p[c < n ? c : n - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kRound; ++u)
+      if (c0 + u * st < n) s += (double)a[u];
+  }
   s = block_sum(s, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-// z = p - mean(p) (no-flow) or z = p, in FP64.
+// z = p - mean(p) (no-flow) or z = p, in FP64.  First round loaded before
+// the reduction, as in k_mgs_step.
 template <typename T>
 __global__ void __launch_bounds__(kVecThreads)
     k_finalize(const T* __restrict__ p, long long n, const double* __restrict__ partials, int nb,
                double* __restrict__ z) {
   __shared__ double red[kVecThreads / 64];
+  const long long st = (long long)gridDim.x * blockDim.x;
+  T a[kRound];
+  auto load = [&](long long c0) {
+#pragma unroll
+    for (int u = 0; u < kRound; ++u) {
+      const long long c = c0 + u * st;
+      a[u] = p[c < n ? c : n - 1];
+    }
+  };
+  const long long start = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  load(start);
   const double mean = partials ? reduce_partials(partials, nb, red) / (double)n : 0.0;
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
-       c += (long long)gridDim.x * blockDim.x)
-    z[c] = (double)p[c] - mean;
+  for (long long c0 = start; c0 < n; c0 += kRound * st) {
+    if (c0 != start) load(c0);
+#pragma unroll
+    for (int u = 0; u < kRound; ++u) {
+      const long long c = c0 + u * st;
+      if (c < n) z[c] = (double)a[u] - mean;
+    }
+  }
 }
 
 __global__ void k_convert(const double* __restrict__ s, float* __restrict__ d, long long n) {
@@ -662,19 +709,33 @@ __global__ void k_convert(const double* __restrict__ s, float* __restrict__ d, l
 }
 
 // ---- GMRES -----------------------------------------------------------------
+// (Grid-stride loops in rounds of kRound elements, see reduce_partials.)
+
+// r = b - A p (b when p is null), partial sums of r^2.
 __global__ void __launch_bounds__(kVecThreads)
     k_resid_norm(const double* __restrict__ tx, const double* __restrict__ ty, int nx, int ny,
                  const double* __restrict__ b, const double* __restrict__ p,
                  double* __restrict__ r, double* __restrict__ partials) {
   __shared__ double red[kVecThreads / 64];
-  const long long n = (long long)nx * ny;
+  const long long n = (long long)nx * ny, st = (long long)gridDim.x * blockDim.x;
   double s = 0.0;
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
-       c += (long long)gridDim.x * blockDim.x) {
-    const int iy = (int)(c / nx), ix = (int)(c - (long long)iy * nx);
-    const double v = p ? b[c] - stencil(tx, ty, nx, ny, ix, iy, p) : b[c];
-    r[c] = v;
-    s += v * v;
+  for (long long c0 = blockIdx.x * (long long)blockDim.x + threadIdx.x; c0 < n;
+       c0 += kRound * st) {
+    double v[kRound];
+#pragma unroll
+    for (int u = 0; u < kRound; ++u) {
+      const long long c = c0 + u * st, q = c < n ? c : n - 1;
+      const int iy = (int)(q / nx), ix = (int)(q - (long long)iy * nx);
+      v[u] = p ? b[q] - stencil(tx, ty, nx, ny, ix, iy, p) : b[q];
+    }
+#pragma unroll
+    for (int u = 0; u < kRound; ++u) {
+      const long long c = c0 + u * st;
+      if (c < n) {
+        r[c] = v[u];
+        s += v[u] * v[u];
+      }
+    }
   }
   s = block_sum(s, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
@@ -686,73 +747,151 @@ __global__ void k_scale(double* __restrict__ v, long long n, double alpha) {
     v[c] *= alpha;
 }
 
+// w = A z, partial sums of w . v0.
 __global__ void __launch_bounds__(kVecThreads)
     k_arnoldi_start(const double* __restrict__ tx, const double* __restrict__ ty, int nx, int ny,
                     const double* __restrict__ z, double* __restrict__ w,
                     const double* __restrict__ v0, double* __restrict__ partials) {
   __shared__ double red[kVecThreads / 64];
-  const long long n = (long long)nx * ny;
+  const long long n = (long long)nx * ny, st = (long long)gridDim.x * blockDim.x;
   double s = 0.0;
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
-       c += (long long)gridDim.x * blockDim.x) {
-    const int iy = (int)(c / nx), ix = (int)(c - (long long)iy * nx);
-    const double v = stencil(tx, ty, nx, ny, ix, iy, z);
-    w[c] = v;
-    s += v * v0[c];
+  for (long long c0 = blockIdx.x * (long long)blockDim.x + threadIdx.x; c0 < n;
+       c0 += kRound * st) {
+    double v[kRound], o[kRound];
+#pragma unroll
+    for (int u = 0; u < kRound; ++u) {
+      const long long c = c0 + u * st, q = c < n ? c : n - 1;
+      const int iy = (int)(q / nx), ix = (int)(q - (long long)iy * nx);
+      v[u] = stencil(tx, ty, nx, ny, ix, iy, z);
+      o[u] = v0[q];
+    }
+#pragma unroll
+    for (int u = 0; u < kRound; ++u) {
+      const long long c = c0 + u * st;
+      if (c < n) {
+        w[c] = v[u];
+        s += v[u] * o[u];
+      }
+    }
   }
   s = block_sum(s, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// h = sum(part_in) (= w . v_i); hcol[i] = h; w -= h v_i; partial sums of
+// w . v_next, or of w . w when vnext is null.  The vectors' loads do not
+// depend on h: every thread issues its first round before the reduction
+// that forms h (outside any loop, so its barriers are met by all threads),
+// then finishes its remaining rounds.
 __global__ void __launch_bounds__(kVecThreads)
     k_mgs_step(const double* __restrict__ part_in, double* __restrict__ part_out, int nb,
                double* __restrict__ hcol, int i, double* __restrict__ w,
                const double* __restrict__ vi, const double* __restrict__ vnext, long long n) {
   __shared__ double red[kVecThreads / 64];
-  const double h = reduce_partials(part_in, nb, red);
+  const bool self = vnext == nullptr;
+  const double* vn = self ? vi : vnext;
+  const long long st = (long long)gridDim.x * blockDim.x;
+  double a[kRound], b[kRound], d[kRound];
+  auto load = [&](long long c0) {
+#pragma unroll
+    for (int u = 0; u < kRound; ++u) {
+      const long long c = c0 + u * st, q = c < n ? c : n - 1;
+      a[u] = w[q];
+      b[u] = vi[q];
+      d[u] = vn[q];
+    }
+  };
+  double s = 0.0, h = 0.0;
+  auto use = [&](long long c0) {
+#pragma unroll
+    for (int u = 0; u < kRound; ++u) {
+      const long long c = c0 + u * st;
+      if (c < n) {
+        const double v = a[u] - h * b[u];
+        w[c] = v;
+        s += v * (self ? v : d[u]);
+      }
+    }
+  };
+  const long long start = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  load(start);
+  h = reduce_partials(part_in, nb, red);
   if (blockIdx.x == 0 && threadIdx.x == 0) hcol[i] = h;
-  double s = 0.0;
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
-       c += (long long)gridDim.x * blockDim.x) {
-    const double v = w[c] - h * vi[c];
-    w[c] = v;
-    s += v * (vnext ? vnext[c] : v);
+  use(start);
+  for (long long c0 = start + kRound * st; c0 < n; c0 += kRound * st) {
+    load(c0);
+    use(c0);
   }
   s = block_sum(s, red);
   if (threadIdx.x == 0) part_out[blockIdx.x] = s;
 }
 
+// hn = sqrt(sum(part_in)); hcol[j] = hn; w /= hn (if hn > 0).  First round
+// loaded before the reduction, as in k_mgs_step.
 __global__ void __launch_bounds__(kVecThreads)
     k_norm_scale(const double* __restrict__ part_in, int nb, double* __restrict__ hcol, int j,
                  double* __restrict__ w, long long n) {
   __shared__ double red[kVecThreads / 64];
+  const long long st = (long long)gridDim.x * blockDim.x;
+  double a[kRound];
+  auto load = [&](long long c0) {
+#pragma unroll
+    for (int u = 0; u < kRound; ++u) {
+      const long long c = c0 + u * st;
+      a[u] = w[c < n ? c : n - 1];
+    }
+  };
+  const long long start = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  load(start);
   const double hn = sqrt(reduce_partials(part_in, nb, red));
   if (blockIdx.x == 0 && threadIdx.x == 0) hcol[j] = hn;
-  if (hn > 0.0) {
-    const double inv = 1.0 / hn;
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
-         c += (long long)gridDim.x * blockDim.x)
-      w[c] *= inv;
+  if (!(hn > 0.0)) return;
+  const double inv = 1.0 / hn;
+  for (long long c0 = start; c0 < n; c0 += kRound * st) {
+    if (c0 != start) load(c0);
+#pragma unroll
+    for (int u = 0; u < kRound; ++u) {
+      const long long c = c0 + u * st;
+      if (c < n) w[c] = a[u] * inv;
+    }
   }
 }
 
+// p += sum_{i < k} y_i Z_i (k <= kMaxUpdate per launch).
+constexpr int kMaxUpdate = 16;
 __global__ void k_update(double* __restrict__ p, const double* __restrict__ Z,
                          const double* __restrict__ y, int k, long long n) {
   for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
        c += (long long)gridDim.x * blockDim.x) {
+    double z[kMaxUpdate];
+#pragma unroll
+    for (int i = 0; i < kMaxUpdate; ++i) z[i] = Z[(long long)(i < k ? i : 0) * n + c];
     double s = p[c];
-    for (int i = 0; i < k; ++i) s += y[i] * Z[(long long)i * n + c];
+#pragma unroll
+    for (int i = 0; i < kMaxUpdate; ++i)
+      if (i < k) s += y[i] * z[i];
     p[c] = s;
   }
 }
 
+// partial sums of x^2.
 __global__ void __launch_bounds__(kVecThreads)
     k_sumsq(const double* __restrict__ x, long long n, double* __restrict__ partials) {
   __shared__ double red[kVecThreads / 64];
+  const long long st = (long long)gridDim.x * blockDim.x;
   double s = 0.0;
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
-       c += (long long)gridDim.x * blockDim.x)
-    s += x[c] * x[c];
+  for (long long c0 = blockIdx.x * (long long)blockDim.x + threadIdx.x; c0 < n;
+       c0 += kRound * st) {
+    double a[kRound];
+#pragma unroll
+    for (int u = 0; u < kRound; ++u) {
+      const long long c = c0 + u * st;
+      a[u] = x[c < n ? c : n - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kRound; ++u)
+      if (c0 + u * st < n) s += a[u] * a[u];
+  }
   s = block_sum(s, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
@@ -934,7 +1073,10 @@ void launch_norm_scale(const double* part_in, int nb, double* hcol, int j, doubl
 
 void launch_update(double* p, const double* Z, const double* y, int k, long long n,
                    hipStream_t s) {
-  hipLaunchKernelGGL(k_update, dim3(grid_for(n)), dim3(kVecThreads), 0, s, p, Z, y, k, n);
+  // in slices of kMaxUpdate vectors: p is updated in the same order
+  for (int i0 = 0; i0 < k; i0 += kMaxUpdate)
+    hipLaunchKernelGGL(k_update, dim3(grid_for(n)), dim3(kVecThreads), 0, s, p, Z + (long long)i0 * n,
+                       y + i0, k - i0 < kMaxUpdate ? k - i0 : kMaxUpdate, n);
 }
 
 void launch_sumsq(const double* x, long long n, double* partials, int nb, hipStream_t s) {
