@@ -187,8 +187,20 @@ std::vector<T> narrow(const std::vector<double>& v) {
   return o;
 }
 
-// Upload a set of box factors in precision T: every box's D_j^-1 blocks
-// (row-major) with a block stride rounded up to 16 bytes (every box starts
+// Store the symmetric n x n block D (row-major) by quads of rows
+// (quad_block_words, device.h): word (q n + r) 4 + i = D(4 q + i, r).
+template <typename T>
+void quad_block(const double* D, int n, T* out) {
+  for (int q = 0; q < (n + 3) / 4; ++q)
+    for (int r = 0; r < n; ++r)
+      for (int i = 0; i < 4; ++i) {
+        const int c = 4 * q + i;
+        out[((size_t)q * n + r) * 4 + i] = c < n ? (T)D[(size_t)c * n + r] : T(0);
+      }
+}
+
+// Upload a set of box factors in precision T: every box's D_j^-1 blocks,
+// by quads of rows, with a block stride rounded up to 16 bytes (every box starts
 // 16-byte aligned, so the blocks can be staged with vector loads), then its
 // couplings.
 template <typename T>
@@ -202,7 +214,7 @@ void upload_boxes(mrcm_ctx* c, const std::vector<mrcm::BoxFactor>& F,
   for (size_t i = 0; i < F.size(); ++i) {
     const mrcm::Box& b = F[i].box;
     const mrcm::Box& o = owned[i];
-    const int bs = (int)(((long long)b.bx() * b.bx() + epv - 1) / epv * epv);
+    const int bs = (int)((mrcm::quad_block_words(b.bx()) + epv - 1) / epv * epv);
     d[i] = BoxDesc{b.x0, b.y0, b.bx(), b.by(), F[i].pin, o.x0 - b.x0, o.y0 - b.y0, o.bx(), o.by(),
                    bs, nd, ncp};
     nd += (long long)bs * b.by();
@@ -216,10 +228,10 @@ void upload_boxes(mrcm_ctx* c, const std::vector<mrcm::BoxFactor>& F,
     throw mrcm::Error(MRCM_EINVAL, "subdomain or patch too large for the LDS of one workgroup");
   std::vector<T> hd((size_t)nd, T(0)), hc((size_t)ncp);
   for (size_t i = 0; i < F.size(); ++i) {
-    const size_t bb = (size_t)d[i].bx * d[i].bx;
+    const int n = d[i].bx;
+    const size_t bb = (size_t)n * n;
     for (int j = 0; j < d[i].by; ++j)
-      std::transform(F[i].dinv.begin() + j * bb, F[i].dinv.begin() + (j + 1) * bb,
-                     hd.begin() + d[i].doff + (size_t)j * d[i].bs, [](double v) { return (T)v; });
+      quad_block(F[i].dinv.data() + j * bb, n, hd.data() + d[i].doff + (size_t)j * d[i].bs);
     std::transform(F[i].coup.begin(), F[i].coup.end(), hc.begin() + d[i].coff,
                    [](double v) { return (T)v; });
   }

@@ -14,7 +14,7 @@ struct BoxDesc {
   int x0, y0, bx, by;
   int pin;
   int ox, oy, obx, oby;
-  int bs;          // stride between D_j^-1 blocks: bx * bx rounded up to 16 bytes
+  int bs;          // stride between D_j^-1 blocks (words, a multiple of 16 bytes)
   long long doff;  // offset of the first D_j^-1 block (elements, 16-byte aligned)
   long long coff;  // offset of the couplings T_j (elements)
 };
@@ -30,6 +30,12 @@ struct CChunk {
   int yoff, coff, fcol, ucol;
   long long mat;
 };
+
+// Layout of one D_j^-1 block (bx x bx, symmetric) in memory: by quads of
+// rows.  With nq = ceil(bx / 4), word (q * bx + r) * 4 + i holds D(4 q + i, r)
+// (zero for 4 q + i >= bx), so the lane that owns column r finds the four
+// entries of a row quad in 16 contiguous bytes (32 for FP64).
+__host__ __device__ constexpr int quad_block_words(int n) { return ((n + 3) / 4) * 4 * n; }
 
 constexpr int kBoxThreads = 256;
 constexpr int kVecThreads = 256;

@@ -120,10 +120,12 @@ template <typename T> struct Vec16;
 template <> struct Vec16<float> { using type = f32x4; };
 template <> struct Vec16<double> { using type = f64x2; };
 
-// Vectors per lane that stage the largest block of an NB-wide launch.
+// Vectors per lane that stage the largest block of an NB-wide launch (see
+// quad_block_words in device.h).
 template <typename S, int NB, int GS>
 constexpr int stage_vectors() {
-  return ((NB * NB + 16 / (int)sizeof(S) - 1) / (16 / (int)sizeof(S)) + GS - 1) / GS;
+  return ((quad_block_words(NB) + 16 / (int)sizeof(S) - 1) / (16 / (int)sizeof(S)) + GS - 1) /
+         GS;
 }
 
 // Blocks in flight per group: as many as 64 VGPRs hold (4 per 16-byte
@@ -167,19 +169,46 @@ __device__ __forceinline__ int opaque(int v) {
   return v;
 }
 
-// acc = sum_c D[c * bx + r] ys[c]: lane r's column of the LDS block (symmetric,
-// so it is row r) against the broadcast vector; each LDS read instruction is
-// contiguous across the group.  r < bx; rows c >= bx read row bx - 1 of the
-// block and meet ys[c] = 0, so every read is unconditional and inside the
-// block.
+// Four consecutive words of type S (16 or 32 bytes, 16-byte aligned) and of
+// the arithmetic type T, read with 16-byte LDS loads.
+template <typename S>
+__device__ __forceinline__ void load_quad(const S* p, S (&q)[4]) {
+  if constexpr (sizeof(S) == 4) {
+    const f32x4 v = *reinterpret_cast<const f32x4*>(p);
+    q[0] = v[0], q[1] = v[1], q[2] = v[2], q[3] = v[3];
+  } else {
+    const f64x2 v0 = *reinterpret_cast<const f64x2*>(p);
+    const f64x2 v1 = *reinterpret_cast<const f64x2*>(p + 2);
+    q[0] = v0[0], q[1] = v0[1], q[2] = v1[0], q[3] = v1[1];
+  }
+}
+
+// acc = sum_c D(c, r) ys[c]: lane r's column of the symmetric block (its row
+// r) against the broadcast vector.  The block is stored by quads of rows
+// (see quad_block_words in device.h): lane r's entries for rows 4q .. 4q + 3
+// are the four contiguous words at (q * bx + r) * 4, so each quad is one
+// 16-byte read (two for FP64), contiguous across the group.  Quads past the
+// block re-read its last quad and meet ys[c] = 0 (c >= bx), so every read is
+// unconditional and inside the block; four partial sums shorten the chain
+// of dependent additions.
 template <typename T, typename S, int NB>
 __device__ __forceinline__ T lds_dot(const S* D, const T* ys, int bx, int r) {
-  T acc = T(0);
-  const S* col = D + opaque(r);
   const int n = opaque(bx);
+  const int nq = (n + 3) >> 2;
+  const S* col = D + 4 * opaque(r);
+  T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
 #pragma unroll
-  for (int c = 0; c < NB; ++c) acc += (T)col[(c < n ? c : n - 1) * n] * ys[c];
-  return acc;
+  for (int q = 0; q < NB / 4; ++q) {
+    S d[4];
+    T y[4];
+    load_quad(col + (long long)(q < nq ? q : nq - 1) * 4 * n, d);
+    load_quad(ys + 4 * q, y);
+    a0 += (T)d[0] * y[0];
+    a1 += (T)d[1] * y[1];
+    a2 += (T)d[2] * y[2];
+    a3 += (T)d[3] * y[3];
+  }
+  return (a0 + a1) + (a2 + a3);
 }
 
 // Largest value of v over the 64 lanes of the wave, as a wave-uniform value.
@@ -935,7 +964,7 @@ inline int round16(long long x, size_t w) {
 // two expanded blocks and the couplings (storage words w), rounded to 16
 // bytes.
 // LDS words of one staged block: the largest block, rounded up to 16 bytes.
-inline int lds_block_words(int max_bx, size_t w) { return round16((long long)max_bx * max_bx, w); }
+inline int lds_block_words(int max_bx, size_t w) { return round16(quad_block_words(max_bx), w); }
 inline size_t group_bytes(int max_bx, int max_cells, size_t t, size_t w) {
   const size_t b = (size_t)group_size(max_bx) * t +
                    (2 * (size_t)lds_block_words(max_bx, w) +
