@@ -201,8 +201,9 @@ def main() -> int:
     ap.add_argument("--apply-only", action="store_true",
                     help="time preconditioner applications T r instead of solves")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="only run device-to-device copies of MIB MiB (the known-size "
-                         "kernel that scales the FETCH_SIZE / WRITE_SIZE counters)")
+                    help="only run device-to-device copies of MIB MiB, as a runtime copy and "
+                         "as an elementwise kernel (known-size kernels that scale the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the solver runs on a single device, with no "
@@ -218,6 +219,7 @@ def main() -> int:
         torch.cuda.synchronize()
         for _ in range(max(1, args.steps)):
             dst.copy_(src)
+            torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8,
                           "copies": max(1, args.steps)}), flush=True)
