@@ -136,6 +136,29 @@ int mrcm_setup(const mrcm_grid* grid, const mrcm_params* params, const double* K
  * then the smoothing sweeps).  r, z: device [nrhs][n]; may not alias. */
 int mrcm_apply(mrcm_ctx* ctx, const double* r, double* z, int32_t nrhs, void* stream);
 
+/* z_i = T_i r_i for n set-up contexts at once (Section 3, as mrcm_apply,
+ * for several permeability fields or grids): every context's applications
+ * run on its own stream after the work already queued on `stream`, so the
+ * contexts' kernels overlap on the device, and `stream` waits for all of
+ * them.  ctx[i], r[i], z[i], nrhs[i]: host arrays of n entries; r[i], z[i]:
+ * device [nrhs[i]][n_i] of context i.  A context may appear once per call.
+ * Results are those of mrcm_apply, bit for bit. */
+int mrcm_apply_many(mrcm_ctx* const* ctx, int32_t n, const double* const* r, double* const* z,
+                    const int32_t* nrhs, void* stream);
+
+/* Device allocator for the contexts set up after this call (not part of the
+ * method: memory plumbing, so that a caller such as a framework's caching
+ * allocator owns the device memory).  alloc(bytes, stream) returns device
+ * memory of at least `bytes` bytes, 256-byte aligned, or NULL (mrcm_setup
+ * then fails with MRCM_ENOMEM); release(ptr, stream) returns it.  `stream`
+ * is the stream the context was set up on.  A context frees its memory in
+ * mrcm_destroy with the pair it was created with, after draining its own
+ * stream and its setup stream.  Passing NULL for either restores
+ * hipMalloc / hipFree.  Process-wide; safe to call from any thread. */
+typedef void* (*mrcm_alloc_fn)(size_t bytes, void* stream);
+typedef void (*mrcm_free_fn)(void* ptr, void* stream);
+void mrcm_set_allocator(mrcm_alloc_fn alloc, mrcm_free_fn release);
+
 /* y = A x for nrhs vectors (Section 3, the condensed fine operator).
  * x, y: device [nrhs][n]; may not alias. */
 int op_apply(mrcm_ctx* ctx, const double* x, double* y, int32_t nrhs, void* stream);

@@ -20,9 +20,10 @@ MRCM_OK, MRCM_EINVAL, MRCM_ENOMEM, MRCM_ESINGULAR, MRCM_ENOCONV, MRCM_EDEVICE = 
 _NAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "ESINGULAR", -4: "ENOCONV", -5: "EDEVICE"}
 
 # Every symbol the headers declare (checked by the test suite).
-EXPORTED = ["mrcm_map_sizes", "mrcm_maps", "mrcm_setup", "mrcm_apply", "op_apply", "gmres_solve",
-            "mrcm_rhs", "mrcm_footprint", "mrcm_timing_enable", "mrcm_timing_read",
-            "mrcm_query", "mrcm_destroy", "mrcm_last_error"]
+EXPORTED = ["mrcm_map_sizes", "mrcm_maps", "mrcm_setup", "mrcm_apply", "mrcm_apply_many",
+            "op_apply", "gmres_solve", "mrcm_rhs", "mrcm_footprint", "mrcm_timing_enable",
+            "mrcm_timing_read", "mrcm_query", "mrcm_set_allocator", "mrcm_destroy",
+            "mrcm_last_error"]
 QUERIES = {"setup_seconds": 0, "device_bytes": 1, "coarse_pivot": 2, "coarse_levels": 3,
            "coarse_dofs": 4}
 PHASES = ["local", "coarse", "reconstruct", "residual", "patch", "finalize"]
@@ -44,6 +45,10 @@ class Params(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("beta_len", ctypes.c_int32),
                 ("smooth_sweeps", ctypes.c_int32), ("smooth_overlap", ctypes.c_int32),
                 ("iface_degree", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class Stats(ctypes.Structure):
@@ -74,6 +79,9 @@ def lib() -> ctypes.CDLL:
             "mrcm_maps": ([pG, pP] + [pi32] * 8, i32),
             "mrcm_setup": ([pG, pP, P, P, ctypes.POINTER(P)], i32),
             "mrcm_apply": ([P, P, P, i32, P], i32),
+            "mrcm_apply_many": ([ctypes.POINTER(P), i32, ctypes.POINTER(P), ctypes.POINTER(P),
+                                 pi32, P], i32),
+            "mrcm_set_allocator": ([ALLOC_FN, FREE_FN], None),
             "op_apply": ([P, P, P, i32, P], i32),
             "gmres_solve": ([P, P, P, i32, dbl, i32, i32, ctypes.POINTER(Stats), P], i32),
             "mrcm_rhs": ([P, P, P, dbl, P, P], i32),
@@ -187,6 +195,62 @@ def test_host_apply(cfg: Config, K: np.ndarray, r: np.ndarray):
 
 
 # ---- device entry points --------------------------------------------------------
+_allocator = None  # the callback objects in use (kept alive while installed)
+
+
+def set_allocator(alloc=None, release=None):
+    """mrcm_set_allocator: alloc(nbytes, stream_handle) -> device pointer (int),
+    release(ptr, stream_handle); None restores hipMalloc / hipFree.  Contexts
+    set up while a pair is installed allocate through it; close them before
+    installing another pair or letting the callables go."""
+    global _allocator
+    if alloc is None or release is None:
+        lib().mrcm_set_allocator(ALLOC_FN(), FREE_FN())
+        _allocator = None
+        return
+
+    def _a(nbytes, stream):
+        try:
+            return int(alloc(int(nbytes), stream))
+        except Exception:
+            return 0
+
+    def _f(ptr, stream):
+        try:
+            release(int(ptr), stream)
+        except Exception:
+            pass
+
+    pair = (ALLOC_FN(_a), FREE_FN(_f))
+    lib().mrcm_set_allocator(*pair)
+    _allocator = pair
+
+
+def torch_allocator(device: int = 0):
+    """(alloc, release) that take device memory from torch's caching
+    allocator on the stream the library names."""
+    import torch
+
+    def alloc(nbytes, stream):
+        return torch.cuda.caching_allocator_alloc(nbytes, device, stream or 0)
+
+    def release(ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return alloc, release
+
+
+def apply_many(contexts, rs, zs, stream=None):
+    """z_i = T_i r_i for several contexts in one call (mrcm_apply_many)."""
+    n = len(contexts)
+    if not (len(rs) == len(zs) == n):
+        raise ValueError("contexts, rs and zs must have the same length")
+    P = ctypes.c_void_p
+    ctx = (P * n)(*[c._ptr for c in contexts])
+    rp = (P * n)(*[_dptr(r) for r in rs])
+    zp = (P * n)(*[_dptr(z, r.numel()) for r, z in zip(rs, zs)])
+    k = (ctypes.c_int32 * n)(*[c._nrhs(r) for c, r in zip(contexts, rs)])
+    _check(lib().mrcm_apply_many(ctx, n, rp, zp, k, _stream(stream)))
 def _stream(stream):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream

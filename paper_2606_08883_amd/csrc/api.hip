@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -42,6 +43,13 @@ int host_threads() {
   int t = omp_get_max_threads();
   return t < 1 ? 1 : t;
 }
+
+// Process-wide device allocator (mrcm_set_allocator); a context keeps the
+// pair it was created with, so its memory is always freed by the matching
+// function.
+std::mutex g_alloc_mutex;
+mrcm_alloc_fn g_alloc = nullptr;
+mrcm_free_fn g_free = nullptr;
 
 }  // namespace
 
@@ -105,15 +113,26 @@ struct mrcm_ctx {
   std::vector<StepGraph> graphs;
   StepGraph* capturing = nullptr;
   hipStream_t ws = nullptr;  // context stream for GMRES (graphs cannot capture the null stream)
-  hipEvent_t ws_in = nullptr;
+  hipEvent_t ws_in = nullptr, ws_out = nullptr;
 
+  // allocator of this context (null: hipMalloc / hipFree) and the stream
+  // its callbacks are given
+  mrcm_alloc_fn alloc_fn = nullptr;
+  mrcm_free_fn free_fn = nullptr;
+  hipStream_t alloc_stream = nullptr;
   template <typename X>
   X* alloc(size_t count) {
     void* p = nullptr;
     if (count == 0) count = 1;
-    hip_check(hipMalloc(&p, count * sizeof(X)), "hipMalloc");
+    const size_t bytes = (count * sizeof(X) + 255) / 256 * 256;
+    if (alloc_fn) {
+      p = alloc_fn(bytes, alloc_stream);
+      if (!p) throw mrcm::Error(MRCM_ENOMEM, "allocator callback returned NULL");
+    } else {
+      hip_check(hipMalloc(&p, bytes), "hipMalloc");
+    }
     allocs.push_back(p);
-    device_bytes += count * sizeof(X);
+    device_bytes += bytes;
     return static_cast<X*>(p);
   }
   template <typename X>
@@ -166,11 +185,19 @@ struct mrcm_ctx {
     graphs.clear();
   }
   ~mrcm_ctx() {
+    if (ws) (void)hipStreamSynchronize(ws);
+    if (alloc_stream) (void)hipStreamSynchronize(alloc_stream);
     drop_graphs();
     if (ws) (void)hipStreamDestroy(ws);
     if (ws_in) (void)hipEventDestroy(ws_in);
+    if (ws_out) (void)hipEventDestroy(ws_out);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-    for (void* p : allocs) (void)hipFree(p);
+    for (void* p : allocs) {
+      if (free_fn)
+        free_fn(p, alloc_stream);
+      else
+        (void)hipFree(p);
+    }
     if (h_host) (void)hipHostFree(h_host);
   }
 };
@@ -588,6 +615,12 @@ int mrcm_setup(const mrcm_grid* grid, const mrcm_params* params, const double* K
     mrcm::host_setup(S, *grid, *params, K.data(), host_threads());
     mrcm::CoarseFactor CF = mrcm::coarse_factor(S.maps, S.Crp, S.Cci, S.Cv, host_threads());
     c = new mrcm_ctx();
+    {
+      std::lock_guard<std::mutex> lock(g_alloc_mutex);
+      c->alloc_fn = g_alloc;
+      c->free_fn = g_free;
+    }
+    c->alloc_stream = s;
     c->nx = grid->nx;
     c->ny = grid->ny;
     for (int k = 0; k < 4; ++k) c->bc[k] = grid->bc[k];
@@ -626,6 +659,7 @@ int mrcm_setup(const mrcm_grid* grid, const mrcm_params* params, const double* K
               "hipHostMalloc");
     hip_check(hipStreamCreateWithFlags(&c->ws, hipStreamNonBlocking), "hipStreamCreate");
     hip_check(hipEventCreateWithFlags(&c->ws_in, hipEventDisableTiming), "hipEventCreate");
+    hip_check(hipEventCreateWithFlags(&c->ws_out, hipEventDisableTiming), "hipEventCreate");
     const char* ge = std::getenv("MRCM_GRAPHS");
     c->use_graphs = !(ge && ge[0] == '0');
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
@@ -661,6 +695,50 @@ int mrcm_apply(mrcm_ctx* c, const double* r, double* z, int32_t nrhs, void* stre
   } catch (const mrcm::Error& e) {
     set_error(e.what());
     return e.code;
+  }
+}
+
+int mrcm_apply_many(mrcm_ctx* const* ctx, int32_t n, const double* const* r, double* const* z,
+                    const int32_t* nrhs, void* stream) {
+  try {
+    if (n < 0 || (n > 0 && (!ctx || !r || !z || !nrhs)))
+      throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+    for (int i = 0; i < n; ++i) {
+      if (!ctx[i] || nrhs[i] < 0) throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+      if (nrhs[i] > 0 && (!r[i] || !z[i])) throw mrcm::Error(MRCM_EINVAL, "null vector");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // every context's applications run on its own stream after the work the
+    // caller's stream holds, and the caller's stream waits for all of them
+    for (int i = 0; i < n; ++i) {
+      mrcm_ctx* c = ctx[i];
+      if (nrhs[i] == 0) continue;
+      hip_check(hipEventRecord(c->ws_in, s), "hipEventRecord");
+      hip_check(hipStreamWaitEvent(c->ws, c->ws_in, 0), "hipStreamWaitEvent");
+      for (int k = 0; k < nrhs[i]; ++k)
+        apply_dispatch(c, r[i] + (size_t)k * c->n, z[i] + (size_t)k * c->n, c->ws);
+      hip_check(hipEventRecord(c->ws_out, c->ws), "hipEventRecord");
+    }
+    for (int i = 0; i < n; ++i)
+      if (nrhs[i] > 0) hip_check(hipStreamWaitEvent(s, ctx[i]->ws_out, 0), "hipStreamWaitEvent");
+    for (int i = 0; i < n; ++i)
+      if (ctx[i]->timing && ctx[i]->ev_used > 4096) ctx[i]->fold_timing();
+    check_launch();
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    set_error(e.what());
+    return e.code;
+  }
+}
+
+void mrcm_set_allocator(mrcm_alloc_fn alloc, mrcm_free_fn release) {
+  std::lock_guard<std::mutex> lock(g_alloc_mutex);
+  if (alloc && release) {
+    g_alloc = alloc;
+    g_free = release;
+  } else {
+    g_alloc = nullptr;
+    g_free = nullptr;
   }
 }
 

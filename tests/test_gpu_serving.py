@@ -1,0 +1,134 @@
+"""GPU tests of the serving path and of the batch and allocator entry points.
+
+* Requests of mixed grid sizes served together (in flight at once, each on
+  its own stream) give answers bit-identical to the same requests served one
+  at a time, and every answer meets the tolerance on the true residual.
+* A served request in FP64 (precision 0) matches the oracle's GMRES solution
+  (iterations within +-1, solution within the FP64 gate).
+* mrcm_apply_many over several contexts equals mrcm_apply on each, bit for bit.
+* Contexts set up with a caller allocator (torch's caching allocator through
+  mrcm_set_allocator) allocate through it and compute the same T r.
+"""
+import numpy as np
+import pytest
+
+from oracle.discretization import assemble
+from oracle.gmres import gmres
+from oracle.mrcm import MRCM
+from paper_2606_08883_amd import binding as B
+from paper_2606_08883_amd import serving as S
+from paper_2606_08883_amd import workloads as wl
+from tests._gates import t_gate
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    B.lib()
+    return torch.device("cuda:0")
+
+
+def _requests():
+    reqs = [S.Request(0, 128, 1.5, 1000, 2000, 3, 0.0), S.Request(1, 256, 2.5, 1001, 2001, 3, 0.0),
+            S.Request(2, 128, 3.0, 1002, 2002, 3, 0.0), S.Request(3, 256, 1.0, 1003, 2003, 3, 0.0)]
+    return [S.make_payload(r) for r in reqs]
+
+
+def test_mix_equals_alone(dev):
+    print("serving: 4 requests alone, then together", flush=True)
+    reqs = _requests()
+    alone = S.Server(S.gpu_solver(), max_active=1).run(reqs, realtime=False)
+    mix_server = S.Server(S.gpu_solver(), max_active=4)
+    mix = mix_server.run(reqs, realtime=False)
+    assert mix_server.peak_active >= 2
+    for a, m, r in zip(alone, mix, reqs):
+        A = assemble(r.K, r.n, r.n, (0, 0, 0, 0))
+        rel = [np.linalg.norm(r.B[k] - A @ m.p[k]) / np.linalg.norm(r.B[k]) for k in range(r.nrhs)]
+        print(f"  request {r.rid} ({r.n}^2): its {m.iterations}, max relres {max(rel):.2e}, "
+              f"identical {np.array_equal(a.p, m.p)}", flush=True)
+        assert m.converged and a.converged
+        assert a.iterations == m.iterations
+        assert np.array_equal(a.p, m.p)
+        assert max(rel) <= 1e-8 * (1 + 1e-6)
+
+
+def test_served_request_matches_oracle(dev):
+    r = S.make_payload(S.Request(0, 128, 2.0, 1000, 2000, 2, 0.0))
+    params = dict(precision=0)
+    res = S.Server(S.gpu_solver(params), max_active=1).run([r], realtime=False)[0]
+    p = dict(S.SERVE_PARAMS, **params)
+    mr = MRCM(r.K, nx=r.n, ny=r.n, bc=(0, 0, 0, 0), sx=p["s"], sy=p["s"],
+              oversample=p["oversample"], alpha=p["alpha"],
+              beta_len="h" if p["beta_len"] else "H", sweeps=p["sweeps"], overlap=p["overlap"],
+              degree=p["degree"])
+    gate = t_gate(mr)
+    its = 0
+    for k in range(r.nrhs):
+        ref = gmres(lambda x: mr.A @ x, mr.apply, r.B[k], rtol=1e-8, restart=10, maxit=500)
+        err = np.linalg.norm(res.p[k] - ref.p) / np.linalg.norm(ref.p)
+        print(f"  rhs {k}: oracle its {ref.iterations}, rel L2 {err:.2e} (gate {gate:.1e})",
+              flush=True)
+        assert err <= gate
+        its += ref.iterations
+    assert abs(res.iterations - its) <= r.nrhs
+
+
+def test_apply_many_equals_apply(dev):
+    cfgs = [S.config_for(128), S.config_for(256), S.config_for(128, dict(precision=0))]
+    Ks = [wl.lognormal_K(c.nx, c.ny, 2.0, 16.0, 40 + i) for i, c in enumerate(cfgs)]
+    ctxs = [B.Context(c, torch.tensor(K, dtype=torch.float64, device=dev)) for c, K in zip(cfgs, Ks)]
+    rs = [torch.tensor(np.stack([wl.random_vector(c.nx * c.ny, 50 + i + 7 * k, zero_mean=True)
+                                 for k in range(2)]), dtype=torch.float64, device=dev).contiguous()
+          for i, c in enumerate(cfgs)]
+    zs = [torch.empty_like(r) for r in rs]
+    B.apply_many(ctxs, rs, zs)
+    torch.cuda.synchronize()
+    for c, r, z in zip(ctxs, rs, zs):
+        z1 = torch.empty_like(r)
+        c.apply(r, z1)
+        torch.cuda.synchronize()
+        assert torch.equal(z, z1)
+    for c in ctxs:
+        c.close()
+
+
+def test_caller_allocator(dev):
+    cfg = S.config_for(128)
+    K = torch.tensor(wl.lognormal_K(128, 128, 2.0, 16.0, 60), dtype=torch.float64, device=dev)
+    r = torch.tensor(wl.random_vector(128 * 128, 61, zero_mean=True), dtype=torch.float64,
+                     device=dev)
+    ref_ctx = B.Context(cfg, K)
+    z0 = torch.empty_like(r)
+    ref_ctx.apply(r, z0)
+    torch.cuda.synchronize()
+    ref_ctx.close()
+    calls = {"alloc": 0, "free": 0, "bytes": 0}
+    ta, tf = B.torch_allocator(0)
+
+    def alloc(nbytes, stream):
+        calls["alloc"] += 1
+        calls["bytes"] += nbytes
+        return ta(nbytes, stream)
+
+    def release(ptr, stream):
+        calls["free"] += 1
+        tf(ptr, stream)
+
+    B.set_allocator(alloc, release)
+    try:
+        ctx = B.Context(cfg, K)
+        z1 = torch.empty_like(r)
+        ctx.apply(r, z1)
+        torch.cuda.synchronize()
+        held = ctx.query("device_bytes")
+        ctx.close()
+    finally:
+        B.set_allocator(None, None)
+    print(f"  allocator calls {calls}, context bytes {held:.0f}", flush=True)
+    assert calls["alloc"] > 0 and calls["alloc"] == calls["free"]
+    assert calls["bytes"] == held
+    assert torch.equal(z0, z1)

@@ -26,6 +26,7 @@ def _declared():
     for h in ("mrcm.h", "mrcm_testing.h"):
         txt = open(os.path.join(ROOT, "include", h)).read()
         txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        txt = re.sub(r"^\s*typedef[^;]*;", "", txt, flags=re.M)  # function-pointer types
         names += re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", txt, re.M)
     return sorted(set(names))
 
