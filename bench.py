@@ -233,6 +233,42 @@ def serve(args) -> int:
     return 0
 
 
+def multi_rhs(args, w, ctx) -> dict:
+    """Throughput of one gmres call on nrhs injector/producer right-hand sides
+    (seeded cell pairs) on the same context, with 1 lane and with several
+    lanes in flight at once; each right-hand side's solution is the same bit
+    for bit either way (checked here)."""
+    import torch
+
+    from paper_2606_08883_amd import workloads as wl
+
+    b = torch.tensor(wl.random_pairs(w.nx, w.ny, args.nrhs, 2024), dtype=torch.float64,
+                     device="cuda:0").contiguous()
+    out = {"nrhs": args.nrhs, "rhs": "injector/producer cell pairs, seed 2024"}
+    ref = None
+    for lanes in (1, args.lanes):
+        ctx.set_lanes(lanes)
+        p = torch.zeros_like(b)
+        ctx.gmres(b, p, rtol=1e-8, restart=10, maxit=500)  # warm-up: lanes, graphs
+        torch.cuda.synchronize()
+        reps = 2
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st = ctx.gmres(b, p, rtol=1e-8, restart=10, maxit=500)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        if ref is None:
+            ref = p.clone()
+        elif not torch.equal(ref, p):
+            raise RuntimeError("lanes changed a solution")
+        out[f"lanes_{lanes}"] = {"solves_per_s": args.nrhs / dt, "ms_per_call": 1e3 * dt,
+                                 "iterations_per_solve": st.iterations / args.nrhs}
+        print(f"bench: {args.nrhs} rhs on {lanes} lane(s): {args.nrhs / dt:.1f} solves/s",
+              file=sys.stderr, flush=True)
+    ctx.set_lanes(4)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,6 +278,10 @@ def main() -> int:
                     choices=["small", "channel", "batched", "large"])
     ap.add_argument("--precision", type=int, default=None, help="0 FP64 apply, 1 FP32 apply, 2 FP32-stored factors with FP64 arithmetic")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--nrhs", type=int, default=8,
+                    help="right-hand sides of the extra multi-RHS measurement (0: skip)")
+    ap.add_argument("--lanes", type=int, default=4,
+                    help="right-hand sides in flight at once in the multi-RHS measurement")
     ap.add_argument("--apply-only", action="store_true",
                     help="time preconditioner applications T r instead of solves")
     ap.add_argument("--serve", action="store_true",
@@ -325,6 +365,7 @@ def main() -> int:
     torch.cuda.synchronize()
     phases = ctx.timing_read()
     ctx.timing(False)
+    multi = multi_rhs(args, w, ctx) if args.nrhs > 0 else None
     n = w.cells
     ms_per_step = 1e3 * elapsed / args.steps
     value = args.steps / elapsed
@@ -370,6 +411,8 @@ def main() -> int:
                      "algorithmic_bytes_per_launch": abytes[dom],
                      "avg_launch_ms": avg_ms},
     }
+    if multi:
+        out["multi_rhs"] = multi
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w.name, int(round(np.mean(its))))

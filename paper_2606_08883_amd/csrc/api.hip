@@ -77,18 +77,10 @@ struct mrcm_ctx {
   int4* gsrc = nullptr;        // per tree position: mU / mP indices L, R and the row kind
   double* gscale = nullptr;    // per tree position: row equilibration scale
   int* cdest = nullptr;        // contribution row -> slot in contrib
-  double* contrib = nullptr;   // maxp slots per tree position (zero where unused)
-  double* g_nd = nullptr;      // interface right-hand side in tree order
   int maxp = 4, np = 0;
   mrcm::CChunk* chunks = nullptr;
   std::vector<std::pair<int, int>> fwd_levels, bwd_levels;  // (first chunk, count)
-  // work space
-  void *pT = nullptr, *rhoT = nullptr;
-  double *mU = nullptr, *mP = nullptr, *xc = nullptr, *ybuf = nullptr, *partials = nullptr;
-  // GMRES
-  int krylov_cap = 0;
-  double *V = nullptr, *Z = nullptr, *hcol = nullptr, *parts = nullptr, *yd = nullptr;
-  double *h_host = nullptr;  // pinned: partials / Hessenberg column / y
+  size_t tsize = 8;  // bytes of the arithmetic / work-vector type
   double setup_seconds = 0.0;
   double coarse_pivot = 1.0;
   int coarse_levels = 0;
@@ -109,12 +101,26 @@ struct mrcm_ctx {
     std::vector<hipEvent_t> owned;
     std::vector<Mark> marks;
   };
+  // The work space of one application of T and of one right-hand side of
+  // GMRES: lanes run concurrently on their own streams and share the
+  // factorisations.  Lane 0 runs on the context stream.
+  struct Lane {
+    hipStream_t st = nullptr;
+    void *pT = nullptr, *rhoT = nullptr;
+    double *mU = nullptr, *mP = nullptr, *xc = nullptr, *ybuf = nullptr, *g_nd = nullptr;
+    double *contrib = nullptr;  // maxp slots per tree position (zero where unused)
+    double *partials = nullptr;
+    int krylov_cap = 0;
+    double *V = nullptr, *Z = nullptr, *hcol = nullptr, *parts = nullptr, *yd = nullptr;
+    double *h_fetch = nullptr, *h_y = nullptr;  // pinned host buffers
+    std::vector<StepGraph> graphs;
+  };
+  std::vector<Lane> lanes;
+  int max_lanes = 4;
   bool use_graphs = true;
-  std::vector<StepGraph> graphs;
   StepGraph* capturing = nullptr;
-  hipStream_t ws = nullptr;  // context stream for GMRES (graphs cannot capture the null stream)
+  hipStream_t ws = nullptr;  // context stream = lane 0's (graphs cannot capture the null stream)
   hipEvent_t ws_in = nullptr, ws_out = nullptr;
-
   // allocator of this context (null: hipMalloc / hipFree) and the stream
   // its callbacks are given
   mrcm_alloc_fn alloc_fn = nullptr;
@@ -177,18 +183,23 @@ struct mrcm_ctx {
     ev_marks.clear();
     ev_used = 0;
   }
-  void drop_graphs() {
-    for (auto& g : graphs) {
+  void drop_graphs(Lane& L) {
+    for (auto& g : L.graphs) {
       if (g.exec) (void)hipGraphExecDestroy(g.exec);
       for (hipEvent_t e : g.owned) (void)hipEventDestroy(e);
     }
-    graphs.clear();
+    L.graphs.clear();
   }
   ~mrcm_ctx() {
-    if (ws) (void)hipStreamSynchronize(ws);
+    for (auto& L : lanes)
+      if (L.st) (void)hipStreamSynchronize(L.st);
     if (alloc_stream) (void)hipStreamSynchronize(alloc_stream);
-    drop_graphs();
-    if (ws) (void)hipStreamDestroy(ws);
+    for (auto& L : lanes) {
+      drop_graphs(L);
+      if (L.st) (void)hipStreamDestroy(L.st);
+      if (L.h_fetch) (void)hipHostFree(L.h_fetch);
+      if (L.h_y) (void)hipHostFree(L.h_y);
+    }
     if (ws_in) (void)hipEventDestroy(ws_in);
     if (ws_out) (void)hipEventDestroy(ws_out);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
@@ -198,7 +209,6 @@ struct mrcm_ctx {
       else
         (void)hipFree(p);
     }
-    if (h_host) (void)hipHostFree(h_host);
   }
 };
 
@@ -352,12 +362,7 @@ void upload_coarse(mrcm_ctx* c, const mrcm::CoarseFactor& F, const mrcm::HostSet
   c->cdest = c->upload(cdest, s);
   c->maxp = F.maxp;
   c->np = np;
-  c->g_nd = c->alloc<double>(std::max(np, 1));
-  c->contrib = c->alloc<double>((size_t)np * F.maxp);
-  hip_check(hipMemsetAsync(c->contrib, 0, sizeof(double) * (size_t)np * F.maxp, s),
-            "hipMemsetAsync");
   c->chunks = c->upload(chunks, s);
-  c->ybuf = c->alloc<double>(F.ylen);
   c->max_nf = max_nf;
   c->max_nu = max_nu;
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
@@ -366,9 +371,9 @@ void upload_coarse(mrcm_ctx* c, const mrcm::CoarseFactor& F, const mrcm::HostSet
 // One application of T with arithmetic / work-vector type T and factor
 // storage type S.
 template <typename T, typename S>
-void apply_one(mrcm_ctx* c, const double* r, double* z, hipStream_t s) {
-  T* p = static_cast<T*>(c->pT);
-  T* rho = static_cast<T*>(c->rhoT);
+void apply_one(mrcm_ctx* c, mrcm_ctx::Lane& L, const double* r, double* z, hipStream_t s) {
+  T* p = static_cast<T*>(L.pT);
+  T* rho = static_cast<T*>(L.rhoT);
   hipEvent_t e0 = nullptr;
   auto begin = [&]() {
     if (c->timing) e0 = c->mark(s);
@@ -380,21 +385,21 @@ void apply_one(mrcm_ctx* c, const double* r, double* z, hipStream_t s) {
   mrcm::launch_local<T, S>(c->lbox, c->m, c->max_cells_local, c->max_bx_local,
                            static_cast<const S*>(c->ldinv),
                            static_cast<const S*>(c->lcoup), r, p, c->nx, c->dof_off,
-                           c->dof_side, c->w_off, c->wU, c->wP, c->mU, c->mP, s);
+                           c->dof_side, c->w_off, c->wU, c->wP, L.mU, L.mP, s);
   end(0);
   if (c->nc > 0) {
     begin();
-    mrcm::launch_coarse_rhs(c->gsrc, c->gscale, c->mU, c->mP, c->g_nd, c->np, s);
+    mrcm::launch_coarse_rhs(c->gsrc, c->gscale, L.mU, L.mP, L.g_nd, c->np, s);
     for (const auto& lv : c->fwd_levels)
-      mrcm::launch_coarse_fwd(c->chunks + lv.first, lv.second, c->cfwd, c->g_nd, c->contrib,
-                              c->maxp, c->np, c->cdest, c->ybuf, c->max_nf, s);
+      mrcm::launch_coarse_fwd(c->chunks + lv.first, lv.second, c->cfwd, L.g_nd, L.contrib,
+                              c->maxp, c->np, c->cdest, L.ybuf, c->max_nf, s);
     for (const auto& lv : c->bwd_levels)
-      mrcm::launch_coarse_bwd(c->chunks + lv.first, lv.second, c->cbwd, c->cidx, c->ybuf,
-                              c->xc, c->max_nu, s);
+      mrcm::launch_coarse_bwd(c->chunks + lv.first, lv.second, c->cbwd, c->cidx, L.ybuf,
+                              L.xc, c->max_nu, s);
     end(1);
     begin();
     mrcm::launch_reconstruct<T, S>(c->lbox, c->m, static_cast<const S*>(c->mbf), c->mbf_off,
-                                   c->dof_off, c->xc, p, c->nx, s);
+                                   c->dof_off, L.xc, p, c->nx, s);
     end(2);
   }
   for (int k = 0; k < c->sweeps; ++k) {
@@ -409,17 +414,49 @@ void apply_one(mrcm_ctx* c, const double* r, double* z, hipStream_t s) {
     end(4);
   }
   begin();
-  mrcm::launch_finalize<T>(p, c->n, c->noflow, z, c->partials, s);
+  mrcm::launch_finalize<T>(p, c->n, c->noflow, z, L.partials, s);
   end(5);
 }
 
-void apply_dispatch(mrcm_ctx* c, const double* r, double* z, hipStream_t s) {
+void apply_dispatch(mrcm_ctx* c, mrcm_ctx::Lane& L, const double* r, double* z, hipStream_t s) {
   if (c->precision == 1)
-    apply_one<float, float>(c, r, z, s);
+    apply_one<float, float>(c, L, r, z, s);
   else if (c->precision == 2)
-    apply_one<double, float>(c, r, z, s);
+    apply_one<double, float>(c, L, r, z, s);
   else
-    apply_one<double, double>(c, r, z, s);
+    apply_one<double, double>(c, L, r, z, s);
+}
+
+// Work space of one lane (its stream is set by the caller).
+void make_lane(mrcm_ctx* c, mrcm_ctx::Lane& L, hipStream_t s) {
+  const size_t nc = std::max(c->nc, 1), np = std::max(c->np, 1);
+  L.pT = c->alloc<char>(c->tsize * c->n);
+  L.rhoT = c->alloc<char>(c->tsize * c->n);
+  L.mU = c->alloc<double>(nc);
+  L.mP = c->alloc<double>(nc);
+  L.xc = c->alloc<double>(nc);
+  L.g_nd = c->alloc<double>(np);
+  L.ybuf = c->alloc<double>(np);
+  L.contrib = c->alloc<double>(np * c->maxp);
+  hip_check(hipMemsetAsync(L.contrib, 0, sizeof(double) * np * c->maxp, s), "hipMemsetAsync");
+  L.partials = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
+  L.parts = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
+  hip_check(hipHostMalloc((void**)&L.h_fetch, sizeof(double) * (mrcm::kMaxVecBlocks + 256),
+                          hipHostMallocDefault),
+            "hipHostMalloc");
+  hip_check(hipHostMalloc((void**)&L.h_y, sizeof(double) * 256, hipHostMallocDefault),
+            "hipHostMalloc");
+}
+
+// Lanes 0 .. count - 1 exist (new lanes get their own non-blocking stream).
+void ensure_lanes(mrcm_ctx* c, int count) {
+  while ((int)c->lanes.size() < count) {
+    c->lanes.emplace_back();
+    mrcm_ctx::Lane& L = c->lanes.back();
+    hip_check(hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking), "hipStreamCreate");
+    make_lane(c, L, L.st);
+    hip_check(hipStreamSynchronize(L.st), "hipStreamSynchronize");
+  }
 }
 
 // Upload factors in storage type X and allocate work vectors of type W.
@@ -446,52 +483,51 @@ void setup_precision(mrcm_ctx* c, const mrcm::HostSetup& S, hipStream_t s) {
     c->txT = c->upload(narrow<W>(S.tx), s);
     c->tyT = c->upload(narrow<W>(S.ty), s);
   }
-  c->pT = c->alloc<W>(c->n);
-  c->rhoT = c->alloc<W>(c->n);
+  c->tsize = sizeof(W);
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
-void ensure_krylov(mrcm_ctx* c, int restart) {
-  if (restart <= c->krylov_cap) return;
-  c->drop_graphs();
-  c->V = c->alloc<double>((size_t)(restart + 1) * c->n);
-  c->Z = c->alloc<double>((size_t)restart * c->n);
-  c->hcol = c->alloc<double>(restart + 2);
-  c->yd = c->alloc<double>(restart + 1);
-  c->krylov_cap = restart;
+void ensure_krylov(mrcm_ctx* c, mrcm_ctx::Lane& L, int restart) {
+  if (restart <= L.krylov_cap) return;
+  c->drop_graphs(L);
+  L.V = c->alloc<double>((size_t)(restart + 1) * c->n);
+  L.Z = c->alloc<double>((size_t)restart * c->n);
+  L.hcol = c->alloc<double>(restart + 2);
+  L.yd = c->alloc<double>(restart + 1);
+  L.krylov_cap = restart;
 }
 
 // One Arnoldi step of Algorithm 1: z_j = T v_j, w = A z_j, modified
 // Gram-Schmidt against v_0..v_j, h_{j+1,j} = ||w||, v_{j+1} = w / h_{j+1,j}.
-// The Hessenberg column is left in c->hcol (j + 2 values).
-void arnoldi_step(mrcm_ctx* c, int j, int nb, hipStream_t s) {
+// The Hessenberg column is left in L.hcol (j + 2 values).
+void arnoldi_step(mrcm_ctx* c, mrcm_ctx::Lane& L, int j, int nb, hipStream_t s) {
   const long long n = c->n;
-  double* vj = c->V + (size_t)j * n;
-  double* zj = c->Z + (size_t)j * n;
-  double* w = c->V + (size_t)(j + 1) * n;
-  apply_dispatch(c, vj, zj, s);
-  mrcm::launch_arnoldi_start(c->tx, c->ty, c->nx, c->ny, zj, w, c->V, c->parts, nb, s);
+  double* vj = L.V + (size_t)j * n;
+  double* zj = L.Z + (size_t)j * n;
+  double* w = L.V + (size_t)(j + 1) * n;
+  apply_dispatch(c, L, vj, zj, s);
+  mrcm::launch_arnoldi_start(c->tx, c->ty, c->nx, c->ny, zj, w, L.V, L.parts, nb, s);
   for (int i = 0; i <= j; ++i)
-    mrcm::launch_mgs_step(c->parts + (i % 2) * mrcm::kMaxVecBlocks,
-                          c->parts + ((i + 1) % 2) * mrcm::kMaxVecBlocks, nb, c->hcol, i, w,
-                          c->V + (size_t)i * n, i < j ? c->V + (size_t)(i + 1) * n : nullptr, n,
+    mrcm::launch_mgs_step(L.parts + (i % 2) * mrcm::kMaxVecBlocks,
+                          L.parts + ((i + 1) % 2) * mrcm::kMaxVecBlocks, nb, L.hcol, i, w,
+                          L.V + (size_t)i * n, i < j ? L.V + (size_t)(i + 1) * n : nullptr, n,
                           s);
-  mrcm::launch_norm_scale(c->parts + ((j + 1) % 2) * mrcm::kMaxVecBlocks, nb, c->hcol, j + 1, w,
+  mrcm::launch_norm_scale(L.parts + ((j + 1) % 2) * mrcm::kMaxVecBlocks, nb, L.hcol, j + 1, w,
                           n, s);
 }
 
-// The captured graph of Arnoldi step j (captured on first use); nullptr when
-// capture is unavailable or timing is on, in which case the caller launches
-// eagerly.
-mrcm_ctx::StepGraph* step_graph(mrcm_ctx* c, int j, int nb) {
+// The captured graph of Arnoldi step j of a lane (captured on first use, on
+// the lane's stream); nullptr when capture is unavailable or timing is on,
+// in which case the caller launches eagerly.
+mrcm_ctx::StepGraph* step_graph(mrcm_ctx* c, mrcm_ctx::Lane& L, int j, int nb) {
   // Per-phase timing reads events recorded between eager launches; events
   // recorded as graph nodes cannot be queried for elapsed time.
   if (!c->use_graphs || c->timing) return nullptr;
-  if ((int)c->graphs.size() < c->krylov_cap) c->graphs.resize(c->krylov_cap);
-  mrcm_ctx::StepGraph& g = c->graphs[j];
+  if ((int)L.graphs.size() < L.krylov_cap) L.graphs.resize(L.krylov_cap);
+  mrcm_ctx::StepGraph& g = L.graphs[j];
   if (g.exec) return &g;
   hipGraph_t graph = nullptr;
-  if (hipStreamBeginCapture(c->ws, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+  if (hipStreamBeginCapture(L.st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     (void)hipGetLastError();
     c->use_graphs = false;
     return nullptr;
@@ -499,13 +535,13 @@ mrcm_ctx::StepGraph* step_graph(mrcm_ctx* c, int j, int nb) {
   c->capturing = &g;
   bool ok = true;
   try {
-    arnoldi_step(c, j, nb, c->ws);
+    arnoldi_step(c, L, j, nb, L.st);
   } catch (const mrcm::Error&) {
     ok = false;  // an operation this runtime cannot capture: run eagerly from now on
   }
   c->capturing = nullptr;
   if (!ok) {
-    (void)hipStreamEndCapture(c->ws, &graph);
+    (void)hipStreamEndCapture(L.st, &graph);
     if (graph) (void)hipGraphDestroy(graph);
     (void)hipGetLastError();
     for (hipEvent_t e : g.owned) (void)hipEventDestroy(e);
@@ -514,7 +550,7 @@ mrcm_ctx::StepGraph* step_graph(mrcm_ctx* c, int j, int nb) {
     c->use_graphs = false;
     return nullptr;
   }
-  hipError_t e1 = hipStreamEndCapture(c->ws, &graph);
+  hipError_t e1 = hipStreamEndCapture(L.st, &graph);
   hipError_t e2 = e1 == hipSuccess ? hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) : e1;
   if (graph) (void)hipGraphDestroy(graph);
   if (e2 != hipSuccess) {
@@ -646,18 +682,13 @@ int mrcm_setup(const mrcm_grid* grid, const mrcm_params* params, const double* K
     c->w_off = c->upload(S.wOff, s);
     c->wU = c->upload(S.wU, s);
     c->wP = c->upload(S.wP, s);
-    c->mU = c->alloc<double>(c->nc);
-    c->mP = c->alloc<double>(c->nc);
-    c->xc = c->alloc<double>(c->nc);
-    c->partials = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
-    c->parts = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
     if (c->nc > 0) upload_coarse(c, CF, S, s);
     c->coarse_pivot = CF.min_pivot_ratio;
     c->coarse_levels = CF.nodes.empty() ? 0 : CF.depth + 1;
-    hip_check(hipHostMalloc((void**)&c->h_host, sizeof(double) * (mrcm::kMaxVecBlocks + 64),
-                            hipHostMallocDefault),
-              "hipHostMalloc");
     hip_check(hipStreamCreateWithFlags(&c->ws, hipStreamNonBlocking), "hipStreamCreate");
+    c->lanes.resize(1);
+    c->lanes[0].st = c->ws;
+    make_lane(c, c->lanes[0], s);
     hip_check(hipEventCreateWithFlags(&c->ws_in, hipEventDisableTiming), "hipEventCreate");
     hip_check(hipEventCreateWithFlags(&c->ws_out, hipEventDisableTiming), "hipEventCreate");
     const char* ge = std::getenv("MRCM_GRAPHS");
@@ -688,7 +719,8 @@ int mrcm_apply(mrcm_ctx* c, const double* r, double* z, int32_t nrhs, void* stre
     if (nrhs == 0) return MRCM_OK;
     if (!r || !z) throw mrcm::Error(MRCM_EINVAL, "null vector");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int k = 0; k < nrhs; ++k) apply_dispatch(c, r + (size_t)k * c->n, z + (size_t)k * c->n, s);
+    for (int k = 0; k < nrhs; ++k)
+      apply_dispatch(c, c->lanes[0], r + (size_t)k * c->n, z + (size_t)k * c->n, s);
     if (c->timing && c->ev_used > 4096) c->fold_timing();
     check_launch();
     return MRCM_OK;
@@ -716,7 +748,7 @@ int mrcm_apply_many(mrcm_ctx* const* ctx, int32_t n, const double* const* r, dou
       hip_check(hipEventRecord(c->ws_in, s), "hipEventRecord");
       hip_check(hipStreamWaitEvent(c->ws, c->ws_in, 0), "hipStreamWaitEvent");
       for (int k = 0; k < nrhs[i]; ++k)
-        apply_dispatch(c, r[i] + (size_t)k * c->n, z[i] + (size_t)k * c->n, c->ws);
+        apply_dispatch(c, c->lanes[0], r[i] + (size_t)k * c->n, z[i] + (size_t)k * c->n, c->ws);
       hip_check(hipEventRecord(c->ws_out, c->ws), "hipEventRecord");
     }
     for (int i = 0; i < n; ++i)
@@ -788,100 +820,166 @@ int gmres_solve(mrcm_ctx* c, const double* b, double* p, int32_t nrhs, double rt
     }
     if (!b || !p) throw mrcm::Error(MRCM_EINVAL, "null vector");
     hipStream_t cs_ = static_cast<hipStream_t>(stream);
-    ensure_krylov(c, restart);
-    // all GMRES work runs on the context stream, ordered after the caller's
+    // Up to max_lanes right-hand sides are in flight, each on its own lane
+    // (work space, Krylov space, stream, captured steps), all ordered after
+    // the work the caller's stream holds.  One host thread drives them round
+    // robin: every state change launches the lane's next work and an
+    // asynchronous copy of the scalars the host needs next, so while the
+    // host serves one lane the others compute.  A right-hand side runs the
+    // same kernels in the same order whatever the number of lanes.
+    const int nl = c->timing ? 1 : std::max(1, std::min<int>(nrhs, c->max_lanes));
+    ensure_lanes(c, nl);
     hip_check(hipEventRecord(c->ws_in, cs_), "hipEventRecord");
-    hip_check(hipStreamWaitEvent(c->ws, c->ws_in, 0), "hipStreamWaitEvent");
-    hipStream_t s = c->ws;
+    for (int l = 0; l < nl; ++l) {
+      ensure_krylov(c, c->lanes[l], restart);
+      hip_check(hipStreamWaitEvent(c->lanes[l].st, c->ws_in, 0), "hipStreamWaitEvent");
+    }
     const long long n = c->n;
     const int nb = mrcm::vec_blocks(n);
-    double* hh = c->h_host;
     int total_it = 0, total_cycles = 0, all_conv = 1, hist_len = 0, true_len = 0;
     double worst = 0.0;
-    auto fetch = [&](const double* dsrc, int cnt) {
-      hip_check(hipMemcpyAsync(hh, dsrc, sizeof(double) * cnt, hipMemcpyDeviceToHost, s),
-                "hipMemcpyAsync");
-      hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-      if (c->timing) c->fold_timing();
+    enum Phase { kNormB, kBeta, kStep, kIdle };
+    struct Run {
+      int k = -1;
+      Phase phase = kIdle;
+      double bnorm = 0.0, tol = 0.0, relres = 1.0;
+      int it = 0, j = 0;
+      bool conv = false;
+      std::vector<double> H, cs, sn, gv, y;
     };
-    std::vector<double> H((size_t)(restart + 1) * restart), cs(restart), sn(restart),
-        gv(restart + 1), y(restart);
-    for (int k = 0; k < nrhs; ++k) {
-      const double* bk = b + (size_t)k * n;
-      double* pk = p + (size_t)k * n;
-      hip_check(hipMemsetAsync(pk, 0, sizeof(double) * n, s), "hipMemsetAsync");
-      mrcm::launch_sumsq(bk, n, c->parts, nb, s);
-      fetch(c->parts, nb);
-      const double bnorm = std::sqrt(host_sum(hh, nb));
-      if (bnorm == 0.0) continue;
-      const double tol = rtol * bnorm;
-      int it = 0;
-      bool first = true, conv = false;
-      double relres = 1.0;
-      while (true) {
-        mrcm::launch_resid_norm(c->tx, c->ty, c->nx, c->ny, bk, first ? nullptr : pk, c->V,
-                                c->parts, nb, s);
-        fetch(c->parts, nb);
-        const double beta = std::sqrt(host_sum(hh, nb));
-        relres = beta / bnorm;
-        if (k == 0 && st && st->true_hist && true_len < st->hist_cap)
-          st->true_hist[true_len++] = relres;
-        if (beta <= tol) {
-          conv = true;
-          break;
+    std::vector<Run> runs(nl);
+    auto fetch = [&](mrcm_ctx::Lane& L, const double* src, int cnt) {
+      hip_check(hipMemcpyAsync(L.h_fetch, src, sizeof(double) * cnt, hipMemcpyDeviceToHost, L.st),
+                "hipMemcpyAsync");
+    };
+    auto launch_step = [&](mrcm_ctx::Lane& L, int j) {
+      mrcm_ctx::StepGraph* sg = step_graph(c, L, j, nb);
+      if (sg)
+        hip_check(hipGraphLaunch(sg->exec, L.st), "hipGraphLaunch");
+      else
+        arnoldi_step(c, L, j, nb, L.st);
+      fetch(L, L.hcol, j + 2);
+    };
+    auto finish = [&](Run& R) {
+      total_it += R.it;
+      all_conv &= R.conv ? 1 : 0;
+      worst = std::max(worst, R.relres);
+      R.phase = kIdle;
+      R.k = -1;
+    };
+    int next = 0;
+    auto start = [&](Run& R, mrcm_ctx::Lane& L) {
+      R = Run();
+      R.k = next++;
+      R.H.assign((size_t)(restart + 1) * restart, 0.0);
+      R.cs.assign(restart, 0.0);
+      R.sn.assign(restart, 0.0);
+      R.gv.assign(restart + 1, 0.0);
+      R.y.assign(restart, 0.0);
+      double* pk = p + (size_t)R.k * n;
+      hip_check(hipMemsetAsync(pk, 0, sizeof(double) * n, L.st), "hipMemsetAsync");
+      mrcm::launch_sumsq(b + (size_t)R.k * n, n, L.parts, nb, L.st);
+      fetch(L, L.parts, nb);
+      R.phase = kNormB;
+    };
+    // Consume the lane's fetched scalars and launch its next work.
+    auto advance = [&](Run& R, mrcm_ctx::Lane& L) {
+      const double* bk = b + (size_t)R.k * n;
+      double* pk = p + (size_t)R.k * n;
+      const double* hh = L.h_fetch;
+      if (c->timing) c->fold_timing();
+      if (R.phase == kNormB) {
+        R.bnorm = std::sqrt(host_sum(hh, nb));
+        if (R.bnorm == 0.0) {  // p = 0 is exact
+          R.conv = true;
+          R.relres = 0.0;
+          finish(R);
+          return;
         }
-        if (it >= maxit) break;
-        ++total_cycles;
-        mrcm::launch_scale(c->V, n, 1.0 / beta, s);
-        std::fill(H.begin(), H.end(), 0.0);
-        std::fill(gv.begin(), gv.end(), 0.0);
-        gv[0] = beta;
-        int jj = 0;
-        for (int j = 0; j < restart; ++j) {
-          mrcm_ctx::StepGraph* sg = step_graph(c, j, nb);
-          if (sg)
-            hip_check(hipGraphLaunch(sg->exec, s), "hipGraphLaunch");
-          else
-            arnoldi_step(c, j, nb, s);
-          fetch(c->hcol, j + 2);
-          if (sg && c->timing) c->fold(sg->marks);
-          ++it;
-          for (int i = 0; i <= j + 1; ++i) H[(size_t)i * restart + j] = hh[i];
-          const double hnext = hh[j + 1];
-          for (int i = 0; i < j; ++i) {
-            const double a = H[(size_t)i * restart + j], bb = H[(size_t)(i + 1) * restart + j];
-            H[(size_t)i * restart + j] = cs[i] * a + sn[i] * bb;
-            H[(size_t)(i + 1) * restart + j] = -sn[i] * a + cs[i] * bb;
-          }
-          const double a = H[(size_t)j * restart + j], bb = H[(size_t)(j + 1) * restart + j];
-          const double rr = std::hypot(a, bb);
-          cs[j] = a / rr;
-          sn[j] = bb / rr;
-          H[(size_t)j * restart + j] = rr;
-          H[(size_t)(j + 1) * restart + j] = 0.0;
-          gv[j + 1] = -sn[j] * gv[j];
-          gv[j] = cs[j] * gv[j];
-          if (k == 0 && st && st->est_hist && hist_len < st->hist_cap)
-            st->est_hist[hist_len++] = std::fabs(gv[j + 1]) / bnorm;
-          jj = j + 1;
-          if (hnext == 0.0 || std::fabs(gv[j + 1]) <= tol || it >= maxit) break;
-        }
-        for (int i = jj - 1; i >= 0; --i) {
-          double sum = gv[i];
-          for (int q = i + 1; q < jj; ++q) sum -= H[(size_t)i * restart + q] * y[q];
-          y[i] = sum / H[(size_t)i * restart + i];
-        }
-        std::memcpy(hh, y.data(), sizeof(double) * jj);
-        hip_check(hipMemcpyAsync(c->yd, hh, sizeof(double) * jj, hipMemcpyHostToDevice, s),
-                  "hipMemcpyAsync");
-        mrcm::launch_update(pk, c->Z, c->yd, jj, n, s);
-        // the host buffer is reused by the next fetch only after this copy completes
-        hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-        first = false;
+        R.tol = rtol * R.bnorm;
+        mrcm::launch_resid_norm(c->tx, c->ty, c->nx, c->ny, bk, nullptr, L.V, L.parts, nb, L.st);
+        fetch(L, L.parts, nb);
+        R.phase = kBeta;
+        return;
       }
-      total_it += it;
-      all_conv &= conv ? 1 : 0;
-      worst = std::max(worst, relres);
+      if (R.phase == kBeta) {
+        const double beta = std::sqrt(host_sum(hh, nb));
+        R.relres = beta / R.bnorm;
+        if (R.k == 0 && st && st->true_hist && true_len < st->hist_cap)
+          st->true_hist[true_len++] = R.relres;
+        if (beta <= R.tol) {
+          R.conv = true;
+          finish(R);
+          return;
+        }
+        if (R.it >= maxit) {
+          finish(R);
+          return;
+        }
+        ++total_cycles;
+        mrcm::launch_scale(L.V, n, 1.0 / beta, L.st);
+        std::fill(R.H.begin(), R.H.end(), 0.0);
+        std::fill(R.gv.begin(), R.gv.end(), 0.0);
+        R.gv[0] = beta;
+        R.j = 0;
+        launch_step(L, 0);
+        R.phase = kStep;
+        return;
+      }
+      // kStep: Givens rotation of the new Hessenberg column (Algorithm 1)
+      const int j = R.j;
+      std::vector<double>& H = R.H;
+      ++R.it;
+      for (int i = 0; i <= j + 1; ++i) H[(size_t)i * restart + j] = hh[i];
+      const double hnext = hh[j + 1];
+      for (int i = 0; i < j; ++i) {
+        const double a = H[(size_t)i * restart + j], bb = H[(size_t)(i + 1) * restart + j];
+        H[(size_t)i * restart + j] = R.cs[i] * a + R.sn[i] * bb;
+        H[(size_t)(i + 1) * restart + j] = -R.sn[i] * a + R.cs[i] * bb;
+      }
+      const double a = H[(size_t)j * restart + j], bb = H[(size_t)(j + 1) * restart + j];
+      const double rr = std::hypot(a, bb);
+      R.cs[j] = a / rr;
+      R.sn[j] = bb / rr;
+      H[(size_t)j * restart + j] = rr;
+      H[(size_t)(j + 1) * restart + j] = 0.0;
+      R.gv[j + 1] = -R.sn[j] * R.gv[j];
+      R.gv[j] = R.cs[j] * R.gv[j];
+      if (R.k == 0 && st && st->est_hist && hist_len < st->hist_cap)
+        st->est_hist[hist_len++] = std::fabs(R.gv[j + 1]) / R.bnorm;
+      const int jj = j + 1;
+      if (!(hnext == 0.0 || std::fabs(R.gv[j + 1]) <= R.tol || R.it >= maxit || jj == restart)) {
+        R.j = jj;
+        launch_step(L, jj);
+        return;
+      }
+      // end of the cycle: y = H^-1 g, p += Z y, true residual
+      for (int i = jj - 1; i >= 0; --i) {
+        double sum = R.gv[i];
+        for (int q = i + 1; q < jj; ++q) sum -= H[(size_t)i * restart + q] * R.y[q];
+        R.y[i] = sum / H[(size_t)i * restart + i];
+      }
+      std::memcpy(L.h_y, R.y.data(), sizeof(double) * jj);
+      hip_check(hipMemcpyAsync(L.yd, L.h_y, sizeof(double) * jj, hipMemcpyHostToDevice, L.st),
+                "hipMemcpyAsync");
+      mrcm::launch_update(pk, L.Z, L.yd, jj, n, L.st);
+      mrcm::launch_resid_norm(c->tx, c->ty, c->nx, c->ny, bk, pk, L.V, L.parts, nb, L.st);
+      fetch(L, L.parts, nb);
+      R.phase = kBeta;
+    };
+    for (int l = 0; l < nl && next < nrhs; ++l) start(runs[l], c->lanes[l]);
+    for (;;) {
+      bool busy = false;
+      for (int l = 0; l < nl; ++l) {
+        Run& R = runs[l];
+        if (R.phase == kIdle) continue;
+        busy = true;
+        mrcm_ctx::Lane& L = c->lanes[l];
+        hip_check(hipStreamSynchronize(L.st), "hipStreamSynchronize");
+        advance(R, L);
+        if (R.phase == kIdle && next < nrhs) start(R, L);
+      }
+      if (!busy) break;
     }
     check_launch();
     if (st) {
@@ -893,6 +991,17 @@ int gmres_solve(mrcm_ctx* c, const double* b, double* p, int32_t nrhs, double rt
       st->final_relres = worst;
     }
     if (!all_conv) throw mrcm::Error(MRCM_ENOCONV, "GMRES reached maxit");
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    set_error(e.what());
+    return e.code;
+  }
+}
+
+int mrcm_set_lanes(mrcm_ctx* c, int32_t lanes) {
+  try {
+    if (!c || lanes < 1 || lanes > 64) throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+    c->max_lanes = lanes;
     return MRCM_OK;
   } catch (const mrcm::Error& e) {
     set_error(e.what());
@@ -922,7 +1031,9 @@ size_t mrcm_footprint(const mrcm_grid* grid, const mrcm_params* params, int32_t 
     bytes += (size_t)(8.0 * 60.0 * nc * std::sqrt(nc / std::max(1.0, nc / std::max(1, M.m))));
     bytes += 2 * n * w;
     const int r = nrhs > 0 ? nrhs : 1;
-    bytes += (size_t)r * 21 * n * 8;  // Krylov basis of restart 10
+    // per lane: Krylov basis and stored z_j of restart 10, apply work space
+    bytes += (size_t)r * (21 * n * 8 + 2 * n * w + 3 * (size_t)(nc + 1) * 8 +
+                          (2 + 4) * (size_t)(nc + 1) * 8);
     return bytes;
   } catch (...) {
     return 0;
@@ -933,7 +1044,8 @@ int mrcm_timing_enable(mrcm_ctx* c, int32_t on) {
   try {
     if (!c) throw mrcm::Error(MRCM_EINVAL, "null context");
     if (c->timing) c->fold_timing();
-    if ((on != 0) != c->timing) c->drop_graphs();
+    if ((on != 0) != c->timing)
+      for (auto& L : c->lanes) c->drop_graphs(L);
     c->timing = on != 0;
     if (on)
       for (int k = 0; k < mrcm_ctx::kPhases; ++k) {

@@ -104,9 +104,12 @@ def config_for(n: int, params: dict | None = None):
                   p["sweeps"], p["overlap"], p["degree"], p["precision"])
 
 
+LANES = 4  # right-hand sides of one request solved at once (mrcm_set_lanes)
+
+
 def footprint_of(req: Request, params: dict | None = None) -> int:
     from .binding import footprint
-    return footprint(config_for(req.n, params), req.nrhs)
+    return footprint(config_for(req.n, params), min(req.nrhs, LANES))
 
 
 def gpu_solver(params: dict | None = None, rtol: float = 1e-8, restart: int = 10,
@@ -126,6 +129,7 @@ def gpu_solver(params: dict | None = None, rtol: float = 1e-8, restart: int = 10
             B = torch.tensor(req.B, dtype=torch.float64, device=dev).contiguous()
             t0 = time.perf_counter()
             ctx = Context(config_for(req.n, params), K, stream=stream)
+            ctx.set_lanes(LANES)
             stream.synchronize()
             t1 = time.perf_counter()
             P = torch.zeros_like(B)

@@ -8,6 +8,9 @@
 * mrcm_apply_many over several contexts equals mrcm_apply on each, bit for bit.
 * Contexts set up with a caller allocator (torch's caching allocator through
   mrcm_set_allocator) allocate through it and compute the same T r.
+* gmres_solve advancing several right-hand sides at once (lanes) gives the
+  solutions and iteration counts of one lane, bit for bit, and of each
+  right-hand side solved on its own.
 """
 import numpy as np
 import pytest
@@ -132,3 +135,36 @@ def test_caller_allocator(dev):
     assert calls["alloc"] > 0 and calls["alloc"] == calls["free"]
     assert calls["bytes"] == held
     assert torch.equal(z0, z1)
+
+
+@pytest.mark.parametrize("precision,n,nrhs,lanes", [(2, 256, 6, 4), (0, 128, 3, 2)])
+def test_lanes_equal_one_lane(dev, precision, n, nrhs, lanes):
+    print(f"lanes: {n}^2 precision {precision}, {nrhs} rhs on 1 and {lanes} lanes", flush=True)
+    cfg = S.config_for(n, dict(precision=precision))
+    K = torch.tensor(wl.lognormal_K(n, n, 2.0, 16.0, 70), dtype=torch.float64, device=dev)
+    b = torch.tensor(wl.random_pairs(n, n, nrhs, 71), dtype=torch.float64, device=dev).contiguous()
+    ctx = B.Context(cfg, K)
+    ctx.set_lanes(1)
+    p1 = torch.zeros_like(b)
+    s1 = ctx.gmres(b, p1, rtol=1e-8, restart=10, maxit=500)
+    ctx.set_lanes(lanes)
+    pl = torch.full_like(b, 7.0)   # the solve must overwrite what p holds
+    sl = ctx.gmres(b, pl, rtol=1e-8, restart=10, maxit=500)
+    torch.cuda.synchronize()
+    print(f"  iterations {s1.iterations} / {sl.iterations}, cycles {s1.cycles} / {sl.cycles}",
+          flush=True)
+    assert s1.converged and sl.converged
+    assert (s1.iterations, s1.cycles) == (sl.iterations, sl.cycles)
+    assert s1.final_relres == sl.final_relres
+    assert s1.est_history == sl.est_history and s1.true_history == sl.true_history
+    assert torch.equal(p1, pl)
+    its = 0
+    for k in range(nrhs):
+        pk = torch.zeros_like(b[k])
+        sk = ctx.gmres(b[k].contiguous(), pk, rtol=1e-8, restart=10, maxit=500)
+        its += sk.iterations
+        assert torch.equal(pk, pl[k])
+    assert its == sl.iterations
+    with pytest.raises(B.MrcmError):
+        ctx.set_lanes(0)
+    ctx.close()
