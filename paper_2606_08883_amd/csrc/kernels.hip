@@ -112,53 +112,25 @@ __global__ void k_rhs(const double* __restrict__ tx, const double* __restrict__ 
 // LDS and is wave-local (no workgroup barrier).
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
-// 16-byte native vector type of a word type (clang vector extension, kept in
-// registers by the optimiser).
+// Four consecutive words of a factor block (16 bytes of FP32 or 32 bytes of
+// FP64), as native vectors the optimiser keeps in registers.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
-template <typename T> struct Vec16;
-template <> struct Vec16<float> { using type = f32x4; };
-template <> struct Vec16<double> { using type = f64x2; };
-
-// Vectors per lane that stage the largest block of an NB-wide launch (see
-// quad_block_words in device.h).
-template <typename S, int NB, int GS>
-constexpr int stage_vectors() {
-  return ((quad_block_words(NB) + 16 / (int)sizeof(S) - 1) / (16 / (int)sizeof(S)) + GS - 1) /
-         GS;
+template <typename S> struct Quad;
+template <> struct Quad<float> {
+  f32x4 v;
+  __device__ float operator[](int i) const { return v[i]; }
+};
+template <> struct Quad<double> {
+  f64x2 lo, hi;
+  __device__ double operator[](int i) const { return i < 2 ? lo[i] : hi[i - 2]; }
+};
+__device__ __forceinline__ void load_quad(Quad<float>& q, const float* p) {
+  q.v = *reinterpret_cast<const f32x4*>(p);
 }
-
-// Blocks in flight per group: as many as 64 VGPRs hold (4 per 16-byte
-// vector), between 2 and 4.
-template <int MAXV>
-constexpr int prefetch_depth() {
-  return 16 * MAXV <= 64 ? 4 : 12 * MAXV <= 64 ? 3 : 2;
-}
-
-// Issue the loads of one block (nvec 16-byte vectors) into registers, spread
-// over the group.  Indices past the block repeat its last vector, which
-// keeps the register array statically indexed.
-template <typename V, int GS, int MAXV>
-__device__ __forceinline__ void stage_load(V (&reg)[MAXV], const void* __restrict__ src, int nvec,
-                                           int lane) {
-  const V* s = reinterpret_cast<const V*>(src);
-#pragma unroll
-  for (int k = 0; k < MAXV; ++k) {
-    const int q = k * GS + lane;
-    reg[k] = s[q < nvec ? q : nvec - 1];
-  }
-}
-
-// Store a staged block into an LDS buffer (the clamped indices store the
-// repeated last vector again, with identical data).
-template <typename V, int GS, int MAXV>
-__device__ __forceinline__ void stage_store(const V (&reg)[MAXV], void* dst, int nvec, int lane) {
-  V* d = reinterpret_cast<V*>(dst);
-#pragma unroll
-  for (int k = 0; k < MAXV; ++k) {
-    const int q = k * GS + lane;
-    d[q < nvec ? q : nvec - 1] = reg[k];
-  }
+__device__ __forceinline__ void load_quad(Quad<double>& q, const double* p) {
+  q.lo = *reinterpret_cast<const f64x2*>(p);
+  q.hi = *reinterpret_cast<const f64x2*>(p + 2);
 }
 
 // Make v opaque to the optimiser at this point, so that addresses derived
@@ -169,44 +141,48 @@ __device__ __forceinline__ int opaque(int v) {
   return v;
 }
 
-// Four consecutive words of type S (16 or 32 bytes, 16-byte aligned) and of
-// the arithmetic type T, read with 16-byte LDS loads.
-template <typename S>
-__device__ __forceinline__ void load_quad(const S* p, S (&q)[4]) {
-  if constexpr (sizeof(S) == 4) {
-    const f32x4 v = *reinterpret_cast<const f32x4*>(p);
-    q[0] = v[0], q[1] = v[1], q[2] = v[2], q[3] = v[3];
-  } else {
-    const f64x2 v0 = *reinterpret_cast<const f64x2*>(p);
-    const f64x2 v1 = *reinterpret_cast<const f64x2*>(p + 2);
-    q[0] = v0[0], q[1] = v0[1], q[2] = v1[0], q[3] = v1[1];
-  }
+// Blocks in flight per lane: as many as about 96 VGPRs of quads hold (NQ
+// quads of 4 words each per block), between 2 and 6.
+template <typename S, int NQ>
+constexpr int reg_depth() {
+  constexpr int per_block = NQ * 4 * (int)sizeof(S) / 4;
+  constexpr int d = 96 / per_block;
+  return d < 2 ? 2 : d > 6 ? 6 : d;
 }
 
-// acc = sum_c D(c, r) ys[c]: lane r's column of the symmetric block (its row
-// r) against the broadcast vector.  The block is stored by quads of rows
-// (see quad_block_words in device.h): lane r's entries for rows 4q .. 4q + 3
-// are the four contiguous words at (q * bx + r) * 4, so each quad is one
-// 16-byte read (two for FP64), contiguous across the group.  Quads past the
-// block re-read its last quad and meet ys[c] = 0 (c >= bx), so every read is
-// unconditional and inside the block; four partial sums shorten the chain
-// of dependent additions.
-template <typename T, typename S, int NB>
-__device__ __forceinline__ T lds_dot(const S* D, const T* ys, int bx, int r) {
-  const int n = opaque(bx);
-  const int nq = (n + 3) >> 2;
-  const S* col = D + 4 * opaque(r);
+// Lane r's part of one block: the quads of its row r (= column r, the block
+// is symmetric), rows 4q .. 4q + 3 at words (q * bx + r) * 4 of the block (see
+// quad_block_words in device.h), so lanes read contiguous 16-byte pieces.
+// Quads past the block (q >= nq) re-read its last quad; they meet zeros in
+// the broadcast vector.
+template <typename S, int NQ>
+__device__ __forceinline__ void load_row(Quad<S> (&d)[NQ], const S* __restrict__ blk, int bx,
+                                         int nq) {
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) load_quad(d[q], blk + (long long)(q < nq ? q : nq - 1) * 4 * bx);
+}
+
+// acc = sum_c D(c, r) ys[c] with lane r's quads in registers and the
+// broadcast vector ys in LDS (entries past the box are zero); four partial
+// sums shorten the chain of dependent additions.
+template <typename T, typename S, int NQ>
+__device__ __forceinline__ T row_dot(const Quad<S> (&d)[NQ], const T* ys) {
   T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
 #pragma unroll
-  for (int q = 0; q < NB / 4; ++q) {
-    S d[4];
+  for (int q = 0; q < NQ; ++q) {
     T y[4];
-    load_quad(col + (long long)(q < nq ? q : nq - 1) * 4 * n, d);
-    load_quad(ys + 4 * q, y);
-    a0 += (T)d[0] * y[0];
-    a1 += (T)d[1] * y[1];
-    a2 += (T)d[2] * y[2];
-    a3 += (T)d[3] * y[3];
+    if constexpr (sizeof(T) == 4) {
+      const f32x4 v = *reinterpret_cast<const f32x4*>(ys + 4 * q);
+      y[0] = v[0], y[1] = v[1], y[2] = v[2], y[3] = v[3];
+    } else {
+      const f64x2 v0 = *reinterpret_cast<const f64x2*>(ys + 4 * q);
+      const f64x2 v1 = *reinterpret_cast<const f64x2*>(ys + 4 * q + 2);
+      y[0] = v0[0], y[1] = v0[1], y[2] = v1[0], y[3] = v1[1];
+    }
+    a0 += (T)d[q][0] * y[0];
+    a1 += (T)d[q][1] * y[1];
+    a2 += (T)d[q][2] * y[2];
+    a3 += (T)d[q][3] * y[3];
   }
   return (a0 + a1) + (a2 + a3);
 }
@@ -218,40 +194,33 @@ __device__ __forceinline__ int wave_max(int v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
 
-// One sweep over the block rows of the boxes of a wave.  Group step s uses
-// block blk(s) of its Dinv, staged into LDS buffer s & 1; the loads of block
-// s + DEPTH are issued at step s into the register set that block s has just
-// left, so every block has DEPTH - 1 steps to arrive before it is stored to
-// LDS.  The boxes of a wave have different heights, so the wave runs nmax
-// steps (the wave's largest count, rounded up to a multiple of DEPTH); a
-// group's steps past its own nsteps re-load its last block and are told
-// valid = false.  No load is conditional, so the compiler can count the
-// loads in flight exactly and waits only for the block it stores.
-template <typename S, int NB, int GS, int MAXV, int DEPTH, typename Blk, typename Step>
-__device__ __forceinline__ void pipelined_sweep(int nsteps, int nmax, Blk blk, Step step, S* Db,
-                                                int lds_blk, const S* __restrict__ Dinv,
-                                                int bstride, int lane) {
-  using V = typename Vec16<S>::type;
-  constexpr int EPV = 16 / sizeof(S);
-  const int nvec = bstride / EPV;
+// One sweep over the block rows of the boxes of a wave.  Step s uses block
+// blk(s), whose quads were loaded into register set s % DEPTH at step
+// s - DEPTH; right after its use the set is refilled with block s + DEPTH,
+// so every block has DEPTH - 1 steps to arrive.  The boxes of a wave have
+// different heights, so the wave runs nmax steps (its largest count, rounded
+// up to a multiple of DEPTH); a group's steps past its own nsteps re-load its
+// last block and are told valid = false.  No load is conditional, so the
+// compiler counts the loads in flight exactly and waits only for the block
+// a step uses.
+template <typename S, int NQ, int DEPTH, typename Blk, typename Step>
+__device__ __forceinline__ void pipelined_sweep(int nsteps, int nmax, Blk blk, Step step,
+                                                const S* __restrict__ Dinv, int bstride,
+                                                int bx, int nq, int r) {
   const int last = nsteps > 0 ? nsteps - 1 : 0;
   auto src = [&](int s) {
     const int b = blk(s < last ? s : last);
-    return Dinv + (long long)(b > 0 ? b : 0) * bstride;
+    return Dinv + (long long)(b > 0 ? b : 0) * bstride + 4 * opaque(r);
   };
-  V reg[DEPTH][MAXV];
+  Quad<S> reg[DEPTH][NQ];
 #pragma unroll
-  for (int u = 0; u < DEPTH; ++u) stage_load<V, GS, MAXV>(reg[u], src(u), nvec, lane);
-  stage_store<V, GS, MAXV>(reg[0], Db, nvec, lane);
-  wave_sync();
+  for (int u = 0; u < DEPTH; ++u) load_row<S, NQ>(reg[u], src(u), bx, nq);
   for (int s0 = 0; s0 < nmax; s0 += DEPTH) {
 #pragma unroll
     for (int u = 0; u < DEPTH; ++u) {
       const int s = s0 + u;
-      stage_load<V, GS, MAXV>(reg[u], src(s + DEPTH), nvec, lane);
-      step(s, Db + (s & 1) * lds_blk, s < nsteps);
-      stage_store<V, GS, MAXV>(reg[(u + 1) % DEPTH], Db + ((s + 1) & 1) * lds_blk, nvec, lane);
-      wave_sync();
+      step(s, reg[u], s < nsteps);
+      load_row<S, NQ>(reg[u], src(s + DEPTH), bx, nq);
     }
   }
 }
@@ -265,52 +234,53 @@ __device__ __forceinline__ int wave_steps(int n) {
 }
 
 // Block LDL^T solve of one box by a group; us holds b on entry and x on exit
-// (by rows of bx words, LDS); cp holds the couplings T_j (LDS).  S is the
-// storage type of the factors, T the arithmetic and vector type (FP32
-// factors may be applied in FP64 arithmetic).  Lanes at or past bx (and
-// whole groups with live = false) take part in every step but read only
-// inside the box and write nothing; they set their broadcast slot to zero.
+// (by rows of bx words, LDS); cp holds the couplings T_j (LDS); ys is the
+// group's broadcast slot.  S is the storage type of the factors, T the
+// arithmetic and vector type (FP32 factors may be applied in FP64
+// arithmetic).  Lanes at or past bx (and whole groups with live = false)
+// take part in every step but read only inside the box and write nothing;
+// they set their broadcast entry to zero.
 template <typename T, typename S, int NB, int GS>
-__device__ __forceinline__ void box_solve(T* us, T* ys, S* Db, int lds_blk, const S* cp,
-                                          const S* __restrict__ Dinv, int bx, int by,
-                                          int bstride, int r, bool live) {
-  constexpr int MAXV = stage_vectors<S, NB, GS>();
-  constexpr int DEPTH = prefetch_depth<MAXV>();
+__device__ __forceinline__ void box_solve(T* us, T* ys, const S* cp, const S* __restrict__ Dinv,
+                                          int bx, int by, int bstride, int r, bool live) {
+  constexpr int NQ = NB / 4;
+  constexpr int DEPTH = reg_depth<S, NQ>();
   const bool act = live && r < bx;
   const int rc = r < bx ? r : bx - 1;
+  const int nq = (bx + 3) >> 2;
   T carry = T(0);
-  pipelined_sweep<S, NB, GS, MAXV, DEPTH>(
+  pipelined_sweep<S, NQ, DEPTH>(
       live ? by : 0, wave_steps<DEPTH>(live ? by : 0), [](int s) { return s; },
-      [&](int s, const S* D, bool valid) {
+      [&](int s, const Quad<S>(&d)[NQ], bool valid) {
         const int j = s < by ? s : by - 1;
         const T y = us[j * bx + rc] + (j > 0 ? (T)cp[j * bx + rc] * carry : T(0));
         const bool w = act && valid;
         ys[r] = w ? y : T(0);
         wave_sync();
-        const T acc = lds_dot<T, S, NB>(D, ys, bx, rc);
+        const T acc = row_dot<T, S, NQ>(d, ys);
         wave_sync();
         if (w) us[j * bx + r] = acc;
         carry = w ? acc : carry;
       },
-      Db, lds_blk, Dinv, bstride, r);
+      Dinv, bstride, bx, nq, rc);
   // carry = x_{by-1} = u_{by-1}
   const int nb = live && by > 1 ? by - 1 : 0;
-  pipelined_sweep<S, NB, GS, MAXV, DEPTH>(
+  pipelined_sweep<S, NQ, DEPTH>(
       nb, wave_steps<DEPTH>(nb), [by](int s) { return by - 2 - s; },
-      [&](int s, const S* D, bool valid) {
+      [&](int s, const Quad<S>(&d)[NQ], bool valid) {
         int j = by - 2 - s;
         j = j < 0 ? 0 : j;
         const int jn = j + 1 < by ? j + 1 : by - 1;
         const bool w = act && valid;
         ys[r] = w ? (T)cp[jn * bx + rc] * carry : T(0);
         wave_sync();
-        const T acc = lds_dot<T, S, NB>(D, ys, bx, rc);
+        const T acc = row_dot<T, S, NQ>(d, ys);
         wave_sync();
         const T xj = us[j * bx + rc] + acc;
         if (w) us[j * bx + r] = xj;
         carry = w ? xj : carry;
       },
-      Db, lds_blk, Dinv, bstride, r);
+      Dinv, bstride, bx, nq, rc);
 }
 
 // Copy rows [0, by) of a box (bx cells wide, lane r: column r) from a global
@@ -358,21 +328,18 @@ __device__ __forceinline__ void words_to_lds(S* dst, const S* __restrict__ src, 
 }
 
 // LDS slot of one lane group:
-//   ys[GS] (T) | Db[2 * lds_blk] (S) | cp[max cells] (S) | us[max cells] (T),
-// every part 16-byte aligned; lds_blk (the block stride) and cp_words (the
-// coupling area) are multiples of 16 bytes.
+//   ys[GS] (T) | cp[max cells] (S) | us[max cells] (T),
+// every part 16-byte aligned; cp_words (the coupling area) is a multiple of
+// 16 bytes.
 template <typename T, typename S, int GS>
 struct BoxSlot {
   T* ys;
-  S* Db;
   S* cp;
   T* us;
-  __device__ BoxSlot(char* base, int lds_blk, int cp_words) {
+  __device__ BoxSlot(char* base, int cp_words) {
     ys = reinterpret_cast<T*>(base);
-    Db = reinterpret_cast<S*>(base + GS * sizeof(T));
-    cp = reinterpret_cast<S*>(base + GS * sizeof(T) + 2 * (long long)lds_blk * sizeof(S));
-    us = reinterpret_cast<T*>(base + GS * sizeof(T) +
-                              (2 * (long long)lds_blk + cp_words) * sizeof(S));
+    cp = reinterpret_cast<S*>(base + GS * sizeof(T));
+    us = reinterpret_cast<T*>(base + GS * sizeof(T) + (long long)cp_words * sizeof(S));
   }
 };
 
@@ -384,7 +351,7 @@ struct BoxSlot {
 // nothing.
 template <typename T, typename S, int NB, int GS = (NB <= 16 ? 16 : NB <= 32 ? 32 : 64)>
 __global__ void __launch_bounds__(kBoxThreads)
-    k_local(const BoxDesc* __restrict__ boxes, int m, int group_bytes, int lds_blk, int cp_words,
+    k_local(const BoxDesc* __restrict__ boxes, int m, int group_bytes, int cp_words,
             const S* __restrict__ dinv, const S* __restrict__ coup,
             const double* __restrict__ r, T* __restrict__ p, int nx,
             const int* __restrict__ dof_off, const int* __restrict__ dof_side,
@@ -395,7 +362,7 @@ __global__ void __launch_bounds__(kBoxThreads)
   const int i0 = blockIdx.x * (blockDim.x / GS) + grp;
   const bool live = i0 < m;
   const int i = live ? i0 : m - 1;
-  BoxSlot<T, S, GS> L(smem_raw + (long long)grp * group_bytes, lds_blk, cp_words);
+  BoxSlot<T, S, GS> L(smem_raw + (long long)grp * group_bytes, cp_words);
   const BoxDesc d = boxes[i];
   const int bx = d.bx, by = d.by;
   const bool act = live && lane < bx;
@@ -405,8 +372,7 @@ __global__ void __launch_bounds__(kBoxThreads)
   wave_sync();
   if (live && d.pin && lane == 0) L.us[0] = T(0);
   wave_sync();
-  box_solve<T, S, NB, GS>(L.us, L.ys, L.Db, lds_blk, L.cp, dinv + d.doff, bx, by, d.bs, lane,
-                          live);
+  box_solve<T, S, NB, GS>(L.us, L.ys, L.cp, dinv + d.doff, bx, by, d.bs, lane, live);
   wave_sync();
   if (act)
     for (int j = 0; j < by; ++j) p[origin + (long long)j * nx + lane] = L.us[j * bx + lane];
@@ -641,7 +607,7 @@ __global__ void __launch_bounds__(kVecThreads)
 // the last one and write nothing.
 template <typename T, typename S, int NB, int GS = (NB <= 16 ? 16 : NB <= 32 ? 32 : 64)>
 __global__ void __launch_bounds__(kBoxThreads)
-    k_patch(const BoxDesc* __restrict__ boxes, int m, int group_bytes, int lds_blk, int cp_words,
+    k_patch(const BoxDesc* __restrict__ boxes, int m, int group_bytes, int cp_words,
             const S* __restrict__ dinv, const S* __restrict__ coup, const T* __restrict__ rho,
             T* __restrict__ p, int nx) {
   extern __shared__ __align__(16) char smem_raw[];
@@ -649,7 +615,7 @@ __global__ void __launch_bounds__(kBoxThreads)
   const int i0 = blockIdx.x * (blockDim.x / GS) + grp;
   const bool live = i0 < m;
   const int i = live ? i0 : m - 1;
-  BoxSlot<T, S, GS> L(smem_raw + (long long)grp * group_bytes, lds_blk, cp_words);
+  BoxSlot<T, S, GS> L(smem_raw + (long long)grp * group_bytes, cp_words);
   const BoxDesc d = boxes[i];
   const int bx = d.bx, by = d.by;
   const long long origin = (long long)d.y0 * nx + d.x0;
@@ -658,8 +624,7 @@ __global__ void __launch_bounds__(kBoxThreads)
   wave_sync();
   if (live && d.pin && lane == 0) L.us[0] = T(0);
   wave_sync();
-  box_solve<T, S, NB, GS>(L.us, L.ys, L.Db, lds_blk, L.cp, dinv + d.doff, bx, by, d.bs, lane,
-                          live);
+  box_solve<T, S, NB, GS>(L.us, L.ys, L.cp, dinv + d.doff, bx, by, d.bs, lane, live);
   wave_sync();
   // p += e on the owned cells, eight rows of read-modify-write in flight
   const bool own = live && lane >= d.ox && lane < d.ox + d.obx;
@@ -960,15 +925,10 @@ inline int round16(long long x, size_t w) {
   const long long e = 16 / (long long)w;
   return (int)((x + e - 1) / e * e);
 }
-// LDS bytes of one lane group: broadcast slot and box (arithmetic words t),
-// two expanded blocks and the couplings (storage words w), rounded to 16
-// bytes.
-// LDS words of one staged block: the largest block, rounded up to 16 bytes.
-inline int lds_block_words(int max_bx, size_t w) { return round16(quad_block_words(max_bx), w); }
+// LDS bytes of one lane group: broadcast slot and box (arithmetic words t)
+// and the couplings (storage words w), rounded to 16 bytes.
 inline size_t group_bytes(int max_bx, int max_cells, size_t t, size_t w) {
-  const size_t b = (size_t)group_size(max_bx) * t +
-                   (2 * (size_t)lds_block_words(max_bx, w) +
-                    (size_t)round16(max_cells, w)) * w +
+  const size_t b = (size_t)group_size(max_bx) * t + (size_t)round16(max_cells, w) * w +
                    (size_t)max_cells * t;
   return (b + 15) / 16 * 16;
 }
@@ -1003,10 +963,9 @@ void launch_local(const BoxDesc* boxes, int m, int max_cells, int max_bx, const 
   const int groups = box_groups(max_bx, max_cells, sizeof(T), sizeof(S));
   const size_t shm = box_lds_bytes(max_bx, max_cells, sizeof(T), sizeof(S));
   const int gb = (int)group_bytes(max_bx, max_cells, sizeof(T), sizeof(S));
-  const int lds_blk = lds_block_words(max_bx, sizeof(S));
   const int cp_words = round16(max_cells, sizeof(S));
   const dim3 grid((m + groups - 1) / groups), block(groups * group_size(max_bx));
-  MRCM_BOX_DISPATCH(k_local, T, S, max_bx, grid, block, shm, s, boxes, m, gb, lds_blk, cp_words,
+  MRCM_BOX_DISPATCH(k_local, T, S, max_bx, grid, block, shm, s, boxes, m, gb, cp_words,
                     dinv, coup, r, p, nx, dof_off, dof_side, w_off, wU, wP, mU, mP);
 }
 
@@ -1052,10 +1011,9 @@ void launch_patch(const BoxDesc* boxes, int m, int max_cells, int max_bx, const 
   const int groups = box_groups(max_bx, max_cells, sizeof(T), sizeof(S));
   const size_t shm = box_lds_bytes(max_bx, max_cells, sizeof(T), sizeof(S));
   const int gb = (int)group_bytes(max_bx, max_cells, sizeof(T), sizeof(S));
-  const int lds_blk = lds_block_words(max_bx, sizeof(S));
   const int cp_words = round16(max_cells, sizeof(S));
   const dim3 grid((m + groups - 1) / groups), block(groups * group_size(max_bx));
-  MRCM_BOX_DISPATCH(k_patch, T, S, max_bx, grid, block, shm, s, boxes, m, gb, lds_blk, cp_words,
+  MRCM_BOX_DISPATCH(k_patch, T, S, max_bx, grid, block, shm, s, boxes, m, gb, cp_words,
                     dinv, coup, rho, p, nx);
 }
 
