@@ -235,9 +235,10 @@ def serve(args) -> int:
 
 def multi_rhs(args, w, ctx) -> dict:
     """Throughput of one gmres call on nrhs injector/producer right-hand sides
-    (seeded cell pairs) on the same context, with 1 lane and with several
-    lanes in flight at once; each right-hand side's solution is the same bit
-    for bit either way (checked here)."""
+    (seeded cell pairs) on the same context, one at a time and with several in
+    flight: lanes (streams) x width (right-hand sides sharing one
+    multi-column application of T per step).  Each right-hand side's solution
+    is the same bit for bit in every arrangement (checked here)."""
     import torch
 
     from paper_2606_08883_amd import workloads as wl
@@ -246,8 +247,9 @@ def multi_rhs(args, w, ctx) -> dict:
                      device="cuda:0").contiguous()
     out = {"nrhs": args.nrhs, "rhs": "injector/producer cell pairs, seed 2024"}
     ref = None
-    for lanes in (1, args.lanes):
+    for lanes, width in ((1, 1), (4, 1), (1, 8), (2, 4)):
         ctx.set_lanes(lanes)
+        ctx.set_batch(width)
         p = torch.zeros_like(b)
         ctx.gmres(b, p, rtol=1e-8, restart=10, maxit=500)  # warm-up: lanes, graphs
         torch.cuda.synchronize()
@@ -260,12 +262,14 @@ def multi_rhs(args, w, ctx) -> dict:
         if ref is None:
             ref = p.clone()
         elif not torch.equal(ref, p):
-            raise RuntimeError("lanes changed a solution")
-        out[f"lanes_{lanes}"] = {"solves_per_s": args.nrhs / dt, "ms_per_call": 1e3 * dt,
-                                 "iterations_per_solve": st.iterations / args.nrhs}
-        print(f"bench: {args.nrhs} rhs on {lanes} lane(s): {args.nrhs / dt:.1f} solves/s",
-              file=sys.stderr, flush=True)
+            raise RuntimeError("lanes or batch width changed a solution")
+        out[f"lanes_{lanes}_width_{width}"] = {
+            "solves_per_s": args.nrhs / dt, "ms_per_call": 1e3 * dt,
+            "iterations_per_solve": st.iterations / args.nrhs}
+        print(f"bench: {args.nrhs} rhs on {lanes} lane(s) of width {width}: "
+              f"{args.nrhs / dt:.1f} solves/s", file=sys.stderr, flush=True)
     ctx.set_lanes(4)
+    ctx.set_batch(4)
     return out
 
 
@@ -280,8 +284,6 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--nrhs", type=int, default=8,
                     help="right-hand sides of the extra multi-RHS measurement (0: skip)")
-    ap.add_argument("--lanes", type=int, default=4,
-                    help="right-hand sides in flight at once in the multi-RHS measurement")
     ap.add_argument("--apply-only", action="store_true",
                     help="time preconditioner applications T r instead of solves")
     ap.add_argument("--serve", action="store_true",

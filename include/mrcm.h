@@ -170,22 +170,28 @@ int op_apply(mrcm_ctx* ctx, const double* x, double* y, int32_t nrhs, void* stre
  * <= rtol * ||b||.  maxit bounds the number of applications of T per RHS.
  * b, p: device [nrhs][n]; st: host, may be NULL.  Returns MRCM_ENOCONV
  * (p and st written) when maxit is reached.
- * Up to mrcm_set_lanes(ctx, ...) right-hand sides (4 by default) are solved
- * at once, each with its own work space, Krylov space and stream, ordered
- * after the work `stream` holds; the device work of all of them has finished
- * when the call returns.  Each right-hand side runs the same kernels in the
- * same order whatever the number of lanes, so p is identical bit for bit to
- * the one-lane result.  st->iterations and st->cycles sum over the right-hand
+ * Up to lanes x width right-hand sides (mrcm_set_lanes, mrcm_set_batch) are
+ * solved at once, each with its own Krylov space, ordered after the work
+ * `stream` holds; the device work of all of them has finished when the call
+ * returns.  Each right-hand side runs the same arithmetic in the same order
+ * whatever the lanes and width, so p is identical bit for bit to the
+ * one-at-a-time result.  st->iterations and st->cycles sum over the right-hand
  * sides, st->final_relres is the largest, the histories are those of the
  * first. */
 int gmres_solve(mrcm_ctx* ctx, const double* b, double* p, int32_t nrhs, double rtol,
                 int32_t restart, int32_t maxit, mrcm_stats* st, void* stream);
 
-/* Right-hand sides gmres_solve may advance at once on this context (1..64;
- * 4 after mrcm_setup).  Lanes beyond the first are created, with their
+/* Lanes (streams) gmres_solve may use at once on this context (1..64; 4
+ * after mrcm_setup).  Lanes beyond the first are created, with their
  * streams and device work space, by the first solve that uses them and kept
  * until mrcm_destroy.  While mrcm_timing_enable is on, solves use one lane. */
 int mrcm_set_lanes(mrcm_ctx* ctx, int32_t lanes);
+
+/* Right-hand sides one lane of gmres_solve advances together (1..8; 4 after
+ * mrcm_setup): each step applies T to all of them in one multi-column
+ * application (as mrcm_apply with nrhs > 1), so up to lanes x width
+ * right-hand sides are in flight.  Results do not depend on it. */
+int mrcm_set_batch(mrcm_ctx* ctx, int32_t width);
 
 /* Right-hand side of the fine system (Section 3): b = f h^2 plus 2 K_c g on
  * every Dirichlet boundary face.  f_cell: device n values or NULL (zero
@@ -196,8 +202,8 @@ int mrcm_rhs(mrcm_ctx* ctx, const double* f_cell, const double* g_bc, double h, 
              void* stream);
 
 /* Device bytes a context for (grid, params) keeps resident, plus the work
- * space of nrhs lanes of gmres_solve with restart 10 (admission control;
- * a solve of k right-hand sides uses min(k, lanes) lanes). */
+ * space of nrhs right-hand sides in flight in gmres_solve with restart 10
+ * (one lane each; admission control). */
 size_t mrcm_footprint(const mrcm_grid* grid, const mrcm_params* params, int32_t nrhs);
 
 /* Per-phase device timing of the preconditioner apply (Section 2.1, the

@@ -22,7 +22,8 @@ _NAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "ESINGULAR", -4: "ENOCONV", -5: "EDEVI
 # Every symbol the headers declare (checked by the test suite).
 EXPORTED = ["mrcm_map_sizes", "mrcm_maps", "mrcm_setup", "mrcm_apply", "mrcm_apply_many",
             "op_apply", "gmres_solve", "mrcm_rhs", "mrcm_footprint", "mrcm_timing_enable",
-            "mrcm_timing_read", "mrcm_query", "mrcm_set_allocator", "mrcm_set_lanes", "mrcm_destroy",
+            "mrcm_timing_read", "mrcm_query", "mrcm_set_allocator", "mrcm_set_lanes", "mrcm_set_batch",
+            "mrcm_destroy",
             "mrcm_last_error"]
 QUERIES = {"setup_seconds": 0, "device_bytes": 1, "coarse_pivot": 2, "coarse_levels": 3,
            "coarse_dofs": 4}
@@ -86,6 +87,7 @@ def lib() -> ctypes.CDLL:
             "gmres_solve": ([P, P, P, i32, dbl, i32, i32, ctypes.POINTER(Stats), P], i32),
             "mrcm_rhs": ([P, P, P, dbl, P, P], i32),
             "mrcm_set_lanes": ([P, i32], i32),
+            "mrcm_set_batch": ([P, i32], i32),
             "mrcm_footprint": ([pG, pP, i32], ctypes.c_size_t),
             "mrcm_timing_enable": ([P, i32], i32),
             "mrcm_timing_read": ([P, pd, pi64], i32),
@@ -340,6 +342,10 @@ class Context:
     def set_lanes(self, lanes: int) -> None:
         """mrcm_set_lanes: right-hand sides one gmres call advances at once."""
         _check(lib().mrcm_set_lanes(self._ptr, lanes))
+
+    def set_batch(self, width: int) -> None:
+        """mrcm_set_batch: right-hand sides one lane advances together."""
+        _check(lib().mrcm_set_batch(self._ptr, width))
 
     def gmres(self, b, p, rtol: float = 1e-8, restart: int = 10, maxit: int = 300,
               stream=None, raise_on_noconv: bool = True) -> SolveStats:

@@ -101,22 +101,39 @@ struct mrcm_ctx {
     std::vector<hipEvent_t> owned;
     std::vector<Mark> marks;
   };
-  // The work space of one application of T and of one right-hand side of
-  // GMRES: lanes run concurrently on their own streams and share the
-  // factorisations.  Lane 0 runs on the context stream.
+  // Work space of the multi-RHS applications (kMaxRhs columns), allocated on
+  // first use: the columns' p, rho and patch scratch (arithmetic type), and
+  // the interface-solve vectors of all columns, column k at k * nc / k * np.
+  struct Batch {
+    bool ready = false;
+    void *p[mrcm::kMaxRhs] = {}, *rho[mrcm::kMaxRhs] = {}, *e[mrcm::kMaxRhs] = {};
+    double *mU = nullptr, *mP = nullptr, *xc = nullptr, *g_nd = nullptr, *ybuf = nullptr;
+    double *contrib = nullptr, *partials = nullptr;
+  };
+  // One right-hand side in flight in GMRES: its Krylov space (V, Z), the
+  // Hessenberg column and reduction partials, and pinned host buffers.
+  struct Slot {
+    int krylov_cap = 0;
+    double *V = nullptr, *Z = nullptr, *hcol = nullptr, *parts = nullptr, *yd = nullptr;
+    double *h_fetch = nullptr, *h_y = nullptr;
+  };
+  // A lane: a stream with the work space of one-column and multi-column
+  // applications of T and the slots it advances together (one multi-column
+  // application per step for all of them).  Lanes run concurrently and share
+  // the factorisations.  Lane 0 runs on the context stream.
   struct Lane {
     hipStream_t st = nullptr;
     void *pT = nullptr, *rhoT = nullptr;
     double *mU = nullptr, *mP = nullptr, *xc = nullptr, *ybuf = nullptr, *g_nd = nullptr;
     double *contrib = nullptr;  // maxp slots per tree position (zero where unused)
     double *partials = nullptr;
-    int krylov_cap = 0;
-    double *V = nullptr, *Z = nullptr, *hcol = nullptr, *parts = nullptr, *yd = nullptr;
-    double *h_fetch = nullptr, *h_y = nullptr;  // pinned host buffers
-    std::vector<StepGraph> graphs;
+    Batch batch;
+    std::vector<Slot> slots;
+    std::vector<StepGraph> graphs;  // captured steps of slot 0 (lanes of one slot)
   };
   std::vector<Lane> lanes;
-  int max_lanes = 4;
+  int max_lanes = 4, batch_width = 4;
+  long long patch_cells = 0;  // cells of all smoothing patches (scratch of one column)
   bool use_graphs = true;
   StepGraph* capturing = nullptr;
   hipStream_t ws = nullptr;  // context stream = lane 0's (graphs cannot capture the null stream)
@@ -197,8 +214,10 @@ struct mrcm_ctx {
     for (auto& L : lanes) {
       drop_graphs(L);
       if (L.st) (void)hipStreamDestroy(L.st);
-      if (L.h_fetch) (void)hipHostFree(L.h_fetch);
-      if (L.h_y) (void)hipHostFree(L.h_y);
+      for (auto& S : L.slots) {
+        if (S.h_fetch) (void)hipHostFree(S.h_fetch);
+        if (S.h_y) (void)hipHostFree(S.h_y);
+      }
     }
     if (ws_in) (void)hipEventDestroy(ws_in);
     if (ws_out) (void)hipEventDestroy(ws_out);
@@ -427,6 +446,120 @@ void apply_dispatch(mrcm_ctx* c, mrcm_ctx::Lane& L, const double* r, double* z, 
     apply_one<double, double>(c, L, r, z, s);
 }
 
+void ensure_batch(mrcm_ctx* c, mrcm_ctx::Lane& L, hipStream_t s) {
+  mrcm_ctx::Batch& B = L.batch;
+  if (B.ready) return;
+  const size_t K = mrcm::kMaxRhs, nc = std::max(c->nc, 1), np = std::max(c->np, 1);
+  for (size_t k = 0; k < K; ++k) {
+    B.p[k] = c->alloc<char>(c->tsize * c->n);
+    B.rho[k] = c->alloc<char>(c->tsize * c->n);
+    B.e[k] = c->sweeps > 0 ? c->alloc<char>(c->tsize * std::max(c->patch_cells, 1LL)) : nullptr;
+  }
+  B.mU = c->alloc<double>(K * nc);
+  B.mP = c->alloc<double>(K * nc);
+  B.xc = c->alloc<double>(K * nc);
+  B.g_nd = c->alloc<double>(K * np);
+  B.ybuf = c->alloc<double>(K * np);
+  B.contrib = c->alloc<double>(K * np * c->maxp);
+  hip_check(hipMemsetAsync(B.contrib, 0, sizeof(double) * K * np * c->maxp, s), "hipMemsetAsync");
+  B.partials = c->alloc<double>(K * mrcm::kMaxVecBlocks);
+  B.ready = true;
+}
+
+// z_k = T r_k for k columns (k = 2, 4 or 8) with the multi-RHS launches; the
+// same steps and per-column arithmetic as apply_one.
+template <typename T, typename S>
+void apply_k(mrcm_ctx* c, mrcm_ctx::Batch& B, int k, const double* const* r, double* const* z,
+             hipStream_t s) {
+  T *p[mrcm::kMaxRhs], *rho[mrcm::kMaxRhs], *e[mrcm::kMaxRhs];
+  for (int i = 0; i < mrcm::kMaxRhs; ++i) {
+    p[i] = static_cast<T*>(B.p[i]);
+    rho[i] = static_cast<T*>(B.rho[i]);
+    e[i] = static_cast<T*>(B.e[i]);
+  }
+  hipEvent_t e0 = nullptr;
+  auto begin = [&]() {
+    if (c->timing) e0 = c->mark(s);
+  };
+  auto end = [&](int phase) {
+    if (c->timing) c->add_mark(phase, e0, c->mark(s));
+  };
+  begin();
+  mrcm::launch_local_k<T, S>(k, c->lbox, c->m, c->max_cells_local, c->max_bx_local,
+                             static_cast<const S*>(c->ldinv), static_cast<const S*>(c->lcoup), r,
+                             p, c->nx, c->dof_off, c->dof_side, c->w_off, c->wU, c->wP, B.mU,
+                             B.mP, c->nc, s);
+  end(0);
+  if (c->nc > 0) {
+    begin();
+    mrcm::launch_coarse_rhs_k(k, c->gsrc, c->gscale, B.mU, B.mP, B.g_nd, c->np, c->nc, s);
+    for (const auto& lv : c->fwd_levels)
+      mrcm::launch_coarse_fwd_k(k, c->chunks + lv.first, lv.second, c->cfwd, B.g_nd, B.contrib,
+                                c->maxp, c->np, c->cdest, B.ybuf, c->max_nf, s);
+    for (const auto& lv : c->bwd_levels)
+      mrcm::launch_coarse_bwd_k(k, c->chunks + lv.first, lv.second, c->cbwd, c->cidx, B.ybuf,
+                                B.xc, c->max_nu, c->np, c->nc, s);
+    end(1);
+    begin();
+    mrcm::launch_reconstruct_k<T, S>(k, c->lbox, c->m, static_cast<const S*>(c->mbf), c->mbf_off,
+                                     c->dof_off, B.xc, c->nc, p, c->nx, s);
+    end(2);
+  }
+  for (int sw = 0; sw < c->sweeps; ++sw) {
+    begin();
+    mrcm::launch_residual_k<T>(k, static_cast<const T*>(c->txT), static_cast<const T*>(c->tyT),
+                               c->nx, c->ny, r, p, rho, s);
+    end(3);
+    begin();
+    mrcm::launch_patch_k<T, S>(k, c->pbox, c->m, c->max_cells_patch, c->max_bx_patch,
+                               static_cast<const S*>(c->pdinv), static_cast<const S*>(c->pcoup),
+                               rho, p, e, c->nx, s);
+    end(4);
+  }
+  begin();
+  mrcm::launch_finalize_k<T>(k, p, c->n, c->noflow, z, B.partials, s);
+  end(5);
+}
+
+// z_k = T r_k for nrhs columns, with a lane's work space: multi-RHS
+// launches of 8, 4 and 2 columns, a last single column with the one-RHS
+// launches.
+void apply_columns(mrcm_ctx* c, mrcm_ctx::Lane& L, const double* const* r, double* const* z,
+                   int nrhs, hipStream_t s) {
+  int k0 = 0;
+  while (k0 < nrhs) {
+    const int rem = nrhs - k0;
+    const int k = rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
+    if (k == 1) {
+      apply_dispatch(c, L, r[k0], z[k0], s);
+    } else {
+      ensure_batch(c, L, s);
+      if (c->precision == 1)
+        apply_k<float, float>(c, L.batch, k, r + k0, z + k0, s);
+      else if (c->precision == 2)
+        apply_k<double, float>(c, L.batch, k, r + k0, z + k0, s);
+      else
+        apply_k<double, double>(c, L.batch, k, r + k0, z + k0, s);
+    }
+    k0 += k;
+  }
+}
+
+// Slots 0 .. count - 1 of a lane exist (reduction partials and pinned host
+// buffers; the Krylov space is sized by ensure_krylov).
+void ensure_slots(mrcm_ctx* c, mrcm_ctx::Lane& L, int count) {
+  while ((int)L.slots.size() < count) {
+    L.slots.emplace_back();
+    mrcm_ctx::Slot& S = L.slots.back();
+    S.parts = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
+    hip_check(hipHostMalloc((void**)&S.h_fetch, sizeof(double) * (mrcm::kMaxVecBlocks + 256),
+                            hipHostMallocDefault),
+              "hipHostMalloc");
+    hip_check(hipHostMalloc((void**)&S.h_y, sizeof(double) * 256, hipHostMallocDefault),
+              "hipHostMalloc");
+  }
+}
+
 // Work space of one lane (its stream is set by the caller).
 void make_lane(mrcm_ctx* c, mrcm_ctx::Lane& L, hipStream_t s) {
   const size_t nc = std::max(c->nc, 1), np = std::max(c->np, 1);
@@ -440,12 +573,7 @@ void make_lane(mrcm_ctx* c, mrcm_ctx::Lane& L, hipStream_t s) {
   L.contrib = c->alloc<double>(np * c->maxp);
   hip_check(hipMemsetAsync(L.contrib, 0, sizeof(double) * np * c->maxp, s), "hipMemsetAsync");
   L.partials = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
-  L.parts = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
-  hip_check(hipHostMalloc((void**)&L.h_fetch, sizeof(double) * (mrcm::kMaxVecBlocks + 256),
-                          hipHostMallocDefault),
-            "hipHostMalloc");
-  hip_check(hipHostMalloc((void**)&L.h_y, sizeof(double) * 256, hipHostMallocDefault),
-            "hipHostMalloc");
+  ensure_slots(c, L, 1);
 }
 
 // Lanes 0 .. count - 1 exist (new lanes get their own non-blocking stream).
@@ -468,6 +596,8 @@ void setup_precision(mrcm_ctx* c, const mrcm::HostSetup& S, hipStream_t s) {
   if (S.sweeps > 0)
     upload_boxes<X>(c, S.patch, M.boxes, &c->pbox, &c->pdinv, &c->pcoup, &c->max_cells_patch,
                     &c->max_bx_patch, s);
+  c->patch_cells = 0;
+  for (const auto& f : S.patch) c->patch_cells += (long long)f.coup.size();
   std::vector<X> mbf;
   std::vector<long long> off;
   for (int i = 0; i < M.m; ++i) {
@@ -487,33 +617,39 @@ void setup_precision(mrcm_ctx* c, const mrcm::HostSetup& S, hipStream_t s) {
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
-void ensure_krylov(mrcm_ctx* c, mrcm_ctx::Lane& L, int restart) {
-  if (restart <= L.krylov_cap) return;
-  c->drop_graphs(L);
-  L.V = c->alloc<double>((size_t)(restart + 1) * c->n);
-  L.Z = c->alloc<double>((size_t)restart * c->n);
-  L.hcol = c->alloc<double>(restart + 2);
-  L.yd = c->alloc<double>(restart + 1);
-  L.krylov_cap = restart;
+void ensure_krylov(mrcm_ctx* c, mrcm_ctx::Lane& L, mrcm_ctx::Slot& S, int restart) {
+  if (restart <= S.krylov_cap) return;
+  if (&S == &L.slots[0]) c->drop_graphs(L);
+  S.V = c->alloc<double>((size_t)(restart + 1) * c->n);
+  S.Z = c->alloc<double>((size_t)restart * c->n);
+  S.hcol = c->alloc<double>(restart + 2);
+  S.yd = c->alloc<double>(restart + 1);
+  S.krylov_cap = restart;
 }
 
-// One Arnoldi step of Algorithm 1: z_j = T v_j, w = A z_j, modified
-// Gram-Schmidt against v_0..v_j, h_{j+1,j} = ||w||, v_{j+1} = w / h_{j+1,j}.
-// The Hessenberg column is left in L.hcol (j + 2 values).
-void arnoldi_step(mrcm_ctx* c, mrcm_ctx::Lane& L, int j, int nb, hipStream_t s) {
+// The rest of Arnoldi step j of a slot after z_j = T v_j: w = A z_j,
+// modified Gram-Schmidt against v_0..v_j, h_{j+1,j} = ||w||, v_{j+1} =
+// w / h_{j+1,j}; the Hessenberg column is left in S.hcol (j + 2 values).
+void arnoldi_tail(mrcm_ctx* c, mrcm_ctx::Slot& S, int j, int nb, hipStream_t s) {
   const long long n = c->n;
-  double* vj = L.V + (size_t)j * n;
-  double* zj = L.Z + (size_t)j * n;
-  double* w = L.V + (size_t)(j + 1) * n;
-  apply_dispatch(c, L, vj, zj, s);
-  mrcm::launch_arnoldi_start(c->tx, c->ty, c->nx, c->ny, zj, w, L.V, L.parts, nb, s);
+  double* zj = S.Z + (size_t)j * n;
+  double* w = S.V + (size_t)(j + 1) * n;
+  mrcm::launch_arnoldi_start(c->tx, c->ty, c->nx, c->ny, zj, w, S.V, S.parts, nb, s);
   for (int i = 0; i <= j; ++i)
-    mrcm::launch_mgs_step(L.parts + (i % 2) * mrcm::kMaxVecBlocks,
-                          L.parts + ((i + 1) % 2) * mrcm::kMaxVecBlocks, nb, L.hcol, i, w,
-                          L.V + (size_t)i * n, i < j ? L.V + (size_t)(i + 1) * n : nullptr, n,
+    mrcm::launch_mgs_step(S.parts + (i % 2) * mrcm::kMaxVecBlocks,
+                          S.parts + ((i + 1) % 2) * mrcm::kMaxVecBlocks, nb, S.hcol, i, w,
+                          S.V + (size_t)i * n, i < j ? S.V + (size_t)(i + 1) * n : nullptr, n,
                           s);
-  mrcm::launch_norm_scale(L.parts + ((j + 1) % 2) * mrcm::kMaxVecBlocks, nb, L.hcol, j + 1, w,
+  mrcm::launch_norm_scale(S.parts + ((j + 1) % 2) * mrcm::kMaxVecBlocks, nb, S.hcol, j + 1, w,
                           n, s);
+}
+
+// One Arnoldi step of Algorithm 1 for slot 0 of a lane: z_j = T v_j, then
+// the tail.
+void arnoldi_step(mrcm_ctx* c, mrcm_ctx::Lane& L, int j, int nb, hipStream_t s) {
+  mrcm_ctx::Slot& S = L.slots[0];
+  apply_dispatch(c, L, S.V + (size_t)j * c->n, S.Z + (size_t)j * c->n, s);
+  arnoldi_tail(c, S, j, nb, s);
 }
 
 // The captured graph of Arnoldi step j of a lane (captured on first use, on
@@ -523,7 +659,7 @@ mrcm_ctx::StepGraph* step_graph(mrcm_ctx* c, mrcm_ctx::Lane& L, int j, int nb) {
   // Per-phase timing reads events recorded between eager launches; events
   // recorded as graph nodes cannot be queried for elapsed time.
   if (!c->use_graphs || c->timing) return nullptr;
-  if ((int)L.graphs.size() < L.krylov_cap) L.graphs.resize(L.krylov_cap);
+  if ((int)L.graphs.size() < L.slots[0].krylov_cap) L.graphs.resize(L.slots[0].krylov_cap);
   mrcm_ctx::StepGraph& g = L.graphs[j];
   if (g.exec) return &g;
   hipGraph_t graph = nullptr;
@@ -719,8 +855,13 @@ int mrcm_apply(mrcm_ctx* c, const double* r, double* z, int32_t nrhs, void* stre
     if (nrhs == 0) return MRCM_OK;
     if (!r || !z) throw mrcm::Error(MRCM_EINVAL, "null vector");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int k = 0; k < nrhs; ++k)
-      apply_dispatch(c, c->lanes[0], r + (size_t)k * c->n, z + (size_t)k * c->n, s);
+    std::vector<const double*> rk(nrhs);
+    std::vector<double*> zk(nrhs);
+    for (int k = 0; k < nrhs; ++k) {
+      rk[k] = r + (size_t)k * c->n;
+      zk[k] = z + (size_t)k * c->n;
+    }
+    apply_columns(c, c->lanes[0], rk.data(), zk.data(), nrhs, s);
     if (c->timing && c->ev_used > 4096) c->fold_timing();
     check_launch();
     return MRCM_OK;
@@ -747,8 +888,13 @@ int mrcm_apply_many(mrcm_ctx* const* ctx, int32_t n, const double* const* r, dou
       if (nrhs[i] == 0) continue;
       hip_check(hipEventRecord(c->ws_in, s), "hipEventRecord");
       hip_check(hipStreamWaitEvent(c->ws, c->ws_in, 0), "hipStreamWaitEvent");
-      for (int k = 0; k < nrhs[i]; ++k)
-        apply_dispatch(c, c->lanes[0], r[i] + (size_t)k * c->n, z[i] + (size_t)k * c->n, c->ws);
+      std::vector<const double*> rk(nrhs[i]);
+      std::vector<double*> zk(nrhs[i]);
+      for (int k = 0; k < nrhs[i]; ++k) {
+        rk[k] = r[i] + (size_t)k * c->n;
+        zk[k] = z[i] + (size_t)k * c->n;
+      }
+      apply_columns(c, c->lanes[0], rk.data(), zk.data(), nrhs[i], c->ws);
       hip_check(hipEventRecord(c->ws_out, c->ws), "hipEventRecord");
     }
     for (int i = 0; i < n; ++i)
@@ -820,45 +966,48 @@ int gmres_solve(mrcm_ctx* c, const double* b, double* p, int32_t nrhs, double rt
     }
     if (!b || !p) throw mrcm::Error(MRCM_EINVAL, "null vector");
     hipStream_t cs_ = static_cast<hipStream_t>(stream);
-    // Up to max_lanes right-hand sides are in flight, each on its own lane
-    // (work space, Krylov space, stream, captured steps), all ordered after
-    // the work the caller's stream holds.  One host thread drives them round
-    // robin: every state change launches the lane's next work and an
-    // asynchronous copy of the scalars the host needs next, so while the
-    // host serves one lane the others compute.  A right-hand side runs the
-    // same kernels in the same order whatever the number of lanes.
-    const int nl = c->timing ? 1 : std::max(1, std::min<int>(nrhs, c->max_lanes));
+    // Right-hand sides in flight: nl lanes (streams) of w slots each, all
+    // ordered after the work the caller's stream holds.  A lane advances its
+    // slots in ticks: one multi-column application of T for every slot that
+    // is on an Arnoldi step, then each slot's Gram-Schmidt and the copies of
+    // the scalars the host needs; one synchronisation per tick, after which
+    // the host advances every slot (Givens rotations, restarts, the next
+    // right-hand side).  One host thread serves the lanes round robin, so
+    // while it serves one the others compute.  A right-hand side runs the
+    // same kernels in the same order (and the multi-column applications give
+    // the one-column results bit for bit) whatever the lanes and widths.
+    const int w = std::max(1, std::min<int>(nrhs, c->batch_width));
+    const int nl = c->timing ? 1
+                             : std::max(1, std::min<int>((nrhs + w - 1) / w, c->max_lanes));
     ensure_lanes(c, nl);
     hip_check(hipEventRecord(c->ws_in, cs_), "hipEventRecord");
     for (int l = 0; l < nl; ++l) {
-      ensure_krylov(c, c->lanes[l], restart);
-      hip_check(hipStreamWaitEvent(c->lanes[l].st, c->ws_in, 0), "hipStreamWaitEvent");
+      mrcm_ctx::Lane& L = c->lanes[l];
+      ensure_slots(c, L, w);
+      for (int q = 0; q < w; ++q) ensure_krylov(c, L, L.slots[q], restart);
+      hip_check(hipStreamWaitEvent(L.st, c->ws_in, 0), "hipStreamWaitEvent");
     }
     const long long n = c->n;
     const int nb = mrcm::vec_blocks(n);
     int total_it = 0, total_cycles = 0, all_conv = 1, hist_len = 0, true_len = 0;
     double worst = 0.0;
+    // kNormB / kBeta / kStep: waiting for the scalars of ||b||, of a true
+    // residual, of Arnoldi step j; kIdle: no right-hand side.  step = the
+    // slot takes part in the lane's next multi-column application.
     enum Phase { kNormB, kBeta, kStep, kIdle };
     struct Run {
       int k = -1;
       Phase phase = kIdle;
+      bool step = false;
       double bnorm = 0.0, tol = 0.0, relres = 1.0;
       int it = 0, j = 0;
       bool conv = false;
       std::vector<double> H, cs, sn, gv, y;
     };
-    std::vector<Run> runs(nl);
-    auto fetch = [&](mrcm_ctx::Lane& L, const double* src, int cnt) {
-      hip_check(hipMemcpyAsync(L.h_fetch, src, sizeof(double) * cnt, hipMemcpyDeviceToHost, L.st),
+    std::vector<std::vector<Run>> runs(nl, std::vector<Run>(w));
+    auto fetch = [&](mrcm_ctx::Lane& L, mrcm_ctx::Slot& S, const double* src, int cnt) {
+      hip_check(hipMemcpyAsync(S.h_fetch, src, sizeof(double) * cnt, hipMemcpyDeviceToHost, L.st),
                 "hipMemcpyAsync");
-    };
-    auto launch_step = [&](mrcm_ctx::Lane& L, int j) {
-      mrcm_ctx::StepGraph* sg = step_graph(c, L, j, nb);
-      if (sg)
-        hip_check(hipGraphLaunch(sg->exec, L.st), "hipGraphLaunch");
-      else
-        arnoldi_step(c, L, j, nb, L.st);
-      fetch(L, L.hcol, j + 2);
     };
     auto finish = [&](Run& R) {
       total_it += R.it;
@@ -868,7 +1017,7 @@ int gmres_solve(mrcm_ctx* c, const double* b, double* p, int32_t nrhs, double rt
       R.k = -1;
     };
     int next = 0;
-    auto start = [&](Run& R, mrcm_ctx::Lane& L) {
+    auto start = [&](Run& R, mrcm_ctx::Lane& L, mrcm_ctx::Slot& S) {
       R = Run();
       R.k = next++;
       R.H.assign((size_t)(restart + 1) * restart, 0.0);
@@ -878,16 +1027,16 @@ int gmres_solve(mrcm_ctx* c, const double* b, double* p, int32_t nrhs, double rt
       R.y.assign(restart, 0.0);
       double* pk = p + (size_t)R.k * n;
       hip_check(hipMemsetAsync(pk, 0, sizeof(double) * n, L.st), "hipMemsetAsync");
-      mrcm::launch_sumsq(b + (size_t)R.k * n, n, L.parts, nb, L.st);
-      fetch(L, L.parts, nb);
+      mrcm::launch_sumsq(b + (size_t)R.k * n, n, S.parts, nb, L.st);
+      fetch(L, S, S.parts, nb);
       R.phase = kNormB;
     };
-    // Consume the lane's fetched scalars and launch its next work.
-    auto advance = [&](Run& R, mrcm_ctx::Lane& L) {
+    // Consume a slot's fetched scalars and launch its next work other than
+    // the application of T (R.step asks for that).
+    auto advance = [&](Run& R, mrcm_ctx::Lane& L, mrcm_ctx::Slot& S) {
       const double* bk = b + (size_t)R.k * n;
       double* pk = p + (size_t)R.k * n;
-      const double* hh = L.h_fetch;
-      if (c->timing) c->fold_timing();
+      const double* hh = S.h_fetch;
       if (R.phase == kNormB) {
         R.bnorm = std::sqrt(host_sum(hh, nb));
         if (R.bnorm == 0.0) {  // p = 0 is exact
@@ -897,8 +1046,8 @@ int gmres_solve(mrcm_ctx* c, const double* b, double* p, int32_t nrhs, double rt
           return;
         }
         R.tol = rtol * R.bnorm;
-        mrcm::launch_resid_norm(c->tx, c->ty, c->nx, c->ny, bk, nullptr, L.V, L.parts, nb, L.st);
-        fetch(L, L.parts, nb);
+        mrcm::launch_resid_norm(c->tx, c->ty, c->nx, c->ny, bk, nullptr, S.V, S.parts, nb, L.st);
+        fetch(L, S, S.parts, nb);
         R.phase = kBeta;
         return;
       }
@@ -917,12 +1066,12 @@ int gmres_solve(mrcm_ctx* c, const double* b, double* p, int32_t nrhs, double rt
           return;
         }
         ++total_cycles;
-        mrcm::launch_scale(L.V, n, 1.0 / beta, L.st);
+        mrcm::launch_scale(S.V, n, 1.0 / beta, L.st);
         std::fill(R.H.begin(), R.H.end(), 0.0);
         std::fill(R.gv.begin(), R.gv.end(), 0.0);
         R.gv[0] = beta;
         R.j = 0;
-        launch_step(L, 0);
+        R.step = true;
         R.phase = kStep;
         return;
       }
@@ -950,7 +1099,7 @@ int gmres_solve(mrcm_ctx* c, const double* b, double* p, int32_t nrhs, double rt
       const int jj = j + 1;
       if (!(hnext == 0.0 || std::fabs(R.gv[j + 1]) <= R.tol || R.it >= maxit || jj == restart)) {
         R.j = jj;
-        launch_step(L, jj);
+        R.step = true;
         return;
       }
       // end of the cycle: y = H^-1 g, p += Z y, true residual
@@ -959,25 +1108,72 @@ int gmres_solve(mrcm_ctx* c, const double* b, double* p, int32_t nrhs, double rt
         for (int q = i + 1; q < jj; ++q) sum -= H[(size_t)i * restart + q] * R.y[q];
         R.y[i] = sum / H[(size_t)i * restart + i];
       }
-      std::memcpy(L.h_y, R.y.data(), sizeof(double) * jj);
-      hip_check(hipMemcpyAsync(L.yd, L.h_y, sizeof(double) * jj, hipMemcpyHostToDevice, L.st),
+      std::memcpy(S.h_y, R.y.data(), sizeof(double) * jj);
+      hip_check(hipMemcpyAsync(S.yd, S.h_y, sizeof(double) * jj, hipMemcpyHostToDevice, L.st),
                 "hipMemcpyAsync");
-      mrcm::launch_update(pk, L.Z, L.yd, jj, n, L.st);
-      mrcm::launch_resid_norm(c->tx, c->ty, c->nx, c->ny, bk, pk, L.V, L.parts, nb, L.st);
-      fetch(L, L.parts, nb);
+      mrcm::launch_update(pk, S.Z, S.yd, jj, n, L.st);
+      mrcm::launch_resid_norm(c->tx, c->ty, c->nx, c->ny, bk, pk, S.V, S.parts, nb, L.st);
+      fetch(L, S, S.parts, nb);
       R.phase = kBeta;
     };
-    for (int l = 0; l < nl && next < nrhs; ++l) start(runs[l], c->lanes[l]);
+    // The lane's Arnoldi steps of this tick: one application of T for all
+    // stepping slots (a captured step when the lane has one slot), then
+    // each slot's tail and the copy of its Hessenberg column.
+    std::vector<const double*> vr(w);
+    std::vector<double*> zr(w);
+    auto launch_steps = [&](int l) {
+      mrcm_ctx::Lane& L = c->lanes[l];
+      int cnt = 0;
+      for (int q = 0; q < w; ++q) {
+        Run& R = runs[l][q];
+        if (!R.step) continue;
+        mrcm_ctx::Slot& S = L.slots[q];
+        vr[cnt] = S.V + (size_t)R.j * n;
+        zr[cnt] = S.Z + (size_t)R.j * n;
+        ++cnt;
+      }
+      if (cnt == 0) return;
+      if (w == 1) {
+        Run& R = runs[l][0];
+        mrcm_ctx::StepGraph* sg = step_graph(c, L, R.j, nb);
+        if (sg)
+          hip_check(hipGraphLaunch(sg->exec, L.st), "hipGraphLaunch");
+        else
+          arnoldi_step(c, L, R.j, nb, L.st);
+        fetch(L, L.slots[0], L.slots[0].hcol, R.j + 2);
+        R.step = false;
+        return;
+      }
+      apply_columns(c, L, vr.data(), zr.data(), cnt, L.st);
+      for (int q = 0; q < w; ++q) {
+        Run& R = runs[l][q];
+        if (!R.step) continue;
+        mrcm_ctx::Slot& S = L.slots[q];
+        arnoldi_tail(c, S, R.j, nb, L.st);
+        fetch(L, S, S.hcol, R.j + 2);
+        R.step = false;
+      }
+    };
+    for (int l = 0; l < nl; ++l) {
+      for (int q = 0; q < w && next < nrhs; ++q) start(runs[l][q], c->lanes[l], c->lanes[l].slots[q]);
+    }
     for (;;) {
       bool busy = false;
       for (int l = 0; l < nl; ++l) {
-        Run& R = runs[l];
-        if (R.phase == kIdle) continue;
-        busy = true;
         mrcm_ctx::Lane& L = c->lanes[l];
+        bool live = false;
+        for (const Run& R : runs[l]) live |= R.phase != kIdle;
+        if (!live) continue;
+        busy = true;
         hip_check(hipStreamSynchronize(L.st), "hipStreamSynchronize");
-        advance(R, L);
-        if (R.phase == kIdle && next < nrhs) start(R, L);
+        if (c->timing) c->fold_timing();
+        for (int q = 0; q < w; ++q) {
+          Run& R = runs[l][q];
+          if (R.phase == kIdle) continue;
+          advance(R, L, L.slots[q]);
+          if (R.phase == kIdle && next < nrhs) start(R, L, L.slots[q]);
+        }
+        launch_steps(l);
       }
       if (!busy) break;
     }
@@ -991,6 +1187,17 @@ int gmres_solve(mrcm_ctx* c, const double* b, double* p, int32_t nrhs, double rt
       st->final_relres = worst;
     }
     if (!all_conv) throw mrcm::Error(MRCM_ENOCONV, "GMRES reached maxit");
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    set_error(e.what());
+    return e.code;
+  }
+}
+
+int mrcm_set_batch(mrcm_ctx* c, int32_t width) {
+  try {
+    if (!c || width < 1 || width > mrcm::kMaxRhs) throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+    c->batch_width = width;
     return MRCM_OK;
   } catch (const mrcm::Error& e) {
     set_error(e.what());
@@ -1031,8 +1238,12 @@ size_t mrcm_footprint(const mrcm_grid* grid, const mrcm_params* params, int32_t 
     bytes += (size_t)(8.0 * 60.0 * nc * std::sqrt(nc / std::max(1.0, nc / std::max(1, M.m))));
     bytes += 2 * n * w;
     const int r = nrhs > 0 ? nrhs : 1;
-    // per lane: Krylov basis and stored z_j of restart 10, apply work space
-    bytes += (size_t)r * (21 * n * 8 + 2 * n * w + 3 * (size_t)(nc + 1) * 8 +
+    // per right-hand side in flight: Krylov basis and stored z_j of restart
+    // 10, apply work space (p, rho, patch scratch, interface vectors)
+    size_t pcells = 0;
+    if (params->smooth_sweeps > 0)
+      for (const auto& b : M.pboxes) pcells += (size_t)b.bx() * b.by();
+    bytes += (size_t)r * (21 * n * 8 + 2 * n * w + pcells * w + 3 * (size_t)(nc + 1) * 8 +
                           (2 + 4) * (size_t)(nc + 1) * 8);
     return bytes;
   } catch (...) {

@@ -40,6 +40,7 @@ __host__ __device__ constexpr int quad_block_words(int n) { return ((n + 3) / 4)
 constexpr int kBoxThreads = 256;
 constexpr int kVecThreads = 256;
 constexpr int kMaxVecBlocks = 1024;
+constexpr int kMaxRhs = 8;  // right-hand sides of one multi-RHS launch
 
 inline int vec_blocks(long long n) {
   long long b = (n + kVecThreads * 4 - 1) / (kVecThreads * 4);
@@ -92,6 +93,41 @@ template <typename T>
 void launch_finalize(const T* p, long long n, int noflow, double* z, double* partials,
                      hipStream_t s);
 void launch_convert(const double* src, float* dst, long long n, hipStream_t s);
+
+// ---- the same steps for K right-hand sides per launch (K = 2, 4 or 8) ------
+// Per-RHS vectors are given by host arrays of K base pointers; the per-RHS
+// work vectors of the interface solve are K consecutive blocks (mU, mP, xc:
+// k * nc; g_nd, ybuf: k * np; contrib: k * maxp * np).  e: per-RHS scratch
+// of the smoothing patches (sum of the patches' cells each, patch i at its
+// coupling offset).  Results equal K one-RHS launches bit for bit.
+size_t box_lds_bytes_k(int k, int max_bx, int max_cells, size_t t, size_t w);
+template <typename T, typename S>
+void launch_local_k(int k, const BoxDesc* boxes, int m, int max_cells, int max_bx, const S* dinv,
+                    const S* coup, const double* const* r, T* const* p, int nx,
+                    const int* dof_off, const int* dof_side, const int* w_off, const double* wU,
+                    const double* wP, double* mU, double* mP, int nc, hipStream_t s);
+void launch_coarse_rhs_k(int k, const int4* gsrc, const double* gscale, const double* mU,
+                         const double* mP, double* g_nd, int np, int nc, hipStream_t s);
+void launch_coarse_fwd_k(int k, const CChunk* chunks, int nchunks, const double* fwd,
+                         const double* g_nd, double* contrib, int maxp, int np, const int* cdest,
+                         double* ybuf, int max_nf, hipStream_t s);
+void launch_coarse_bwd_k(int k, const CChunk* chunks, int nchunks, const double* bwd,
+                         const int* idx, const double* ybuf, double* x, int max_nu, int np, int nc,
+                         hipStream_t s);
+template <typename T, typename S>
+void launch_reconstruct_k(int k, const BoxDesc* boxes, int m, const S* mbf,
+                          const long long* mbf_off, const int* dof_off, const double* xc, int nc,
+                          T* const* p, int nx, hipStream_t s);
+template <typename T>
+void launch_residual_k(int k, const T* tx, const T* ty, int nx, int ny, const double* const* r,
+                       const T* const* p, T* const* rho, hipStream_t s);
+template <typename T, typename S>
+void launch_patch_k(int k, const BoxDesc* boxes, int m, int max_cells, int max_bx, const S* dinv,
+                    const S* coup, const T* const* rho, T* const* p, T* const* e, int nx,
+                    hipStream_t s);
+template <typename T>
+void launch_finalize_k(int k, const T* const* p, long long n, int noflow, double* const* z,
+                       double* partials, hipStream_t s);
 
 // ---- GMRES vector kernels (FP64) -------------------------------------------
 // r = b - A p (p may be NULL for p = 0); partials[block] = sum r^2

@@ -4,6 +4,7 @@
 // fused Arnoldi vector kernels of GMRES.  Every reduction has a fixed order,
 // so results are bit-identical from run to run.
 #include "device.h"
+#include "internal.h"
 
 namespace mrcm {
 
@@ -112,6 +113,12 @@ __global__ void k_rhs(const double* __restrict__ tx, const double* __restrict__ 
 // LDS and is wave-local (no workgroup barrier).
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
+// a * b + c with one rounding, spelled out so that the one-RHS and the
+// multi-RHS kernels round every step the same way whatever the optimiser
+// would contract.
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // Four consecutive words of a factor block (16 bytes of FP32 or 32 bytes of
 // FP64), as native vectors the optimiser keeps in registers.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -179,10 +186,10 @@ __device__ __forceinline__ T row_dot(const Quad<S> (&d)[NQ], const T* ys) {
       const f64x2 v1 = *reinterpret_cast<const f64x2*>(ys + 4 * q + 2);
       y[0] = v0[0], y[1] = v0[1], y[2] = v1[0], y[3] = v1[1];
     }
-    a0 += (T)d[q][0] * y[0];
-    a1 += (T)d[q][1] * y[1];
-    a2 += (T)d[q][2] * y[2];
-    a3 += (T)d[q][3] * y[3];
+    a0 = fmat((T)d[q][0], y[0], a0);
+    a1 = fmat((T)d[q][1], y[1], a1);
+    a2 = fmat((T)d[q][2], y[2], a2);
+    a3 = fmat((T)d[q][3], y[3], a3);
   }
   return (a0 + a1) + (a2 + a3);
 }
@@ -253,7 +260,8 @@ __device__ __forceinline__ void box_solve(T* us, T* ys, const S* cp, const S* __
       live ? by : 0, wave_steps<DEPTH>(live ? by : 0), [](int s) { return s; },
       [&](int s, const Quad<S>(&d)[NQ], bool valid) {
         const int j = s < by ? s : by - 1;
-        const T y = us[j * bx + rc] + (j > 0 ? (T)cp[j * bx + rc] * carry : T(0));
+        const T uj = us[j * bx + rc];
+        const T y = j > 0 ? fmat((T)cp[j * bx + rc], carry, uj) : uj;
         const bool w = act && valid;
         ys[r] = w ? y : T(0);
         wave_sync();
@@ -400,8 +408,8 @@ __global__ void __launch_bounds__(kBoxThreads)
                          : side == 2 ? jf
                                      : (by - 1) * bx + jf;
           const double v = (double)L.us[cell];
-          su += a[u] * v;
-          sp += b[u] * v;
+          su = fmat(a[u], v, su);
+          sp = fmat(b[u], v, sp);
         }
       }
     }
@@ -454,7 +462,7 @@ __device__ __forceinline__ void fma_tile(double (&s)[4], const double (&m)[4][8]
 #pragma unroll
   for (int q = 0; q < 8; ++q)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) s[u] += m[u][q] * x[q];
+    for (int u = 0; u < 4; ++u) s[u] = fmat(m[u][q], x[q], s[u]);
 }
 
 // Rows [row0, row1) of M (row-major, ncol columns) times the LDS vector; the
@@ -583,7 +591,7 @@ __global__ void __launch_bounds__(kBoxThreads)
     const int a = q % d.bx, j = q / d.bx;
     const long long c = (long long)(d.y0 + j) * nx + d.x0 + a;
     T s = p[c];
-    for (int k = 0; k < nk; ++k) s += (T)P[(long long)k * ncell + q] * xs[k];
+    for (int k = 0; k < nk; ++k) s = fmat((T)P[(long long)k * ncell + q], xs[k], s);
     p[c] = s;
   }
 }
@@ -890,6 +898,614 @@ __global__ void __launch_bounds__(kVecThreads)
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// ---- several right-hand sides per launch ----------------------------------
+// The kernels below apply T to K <= kMaxRhs right-hand sides at once (vectors
+// given by per-RHS base pointers).  Every per-RHS sum runs in the order of
+// the one-RHS kernels above, so the results are those of K separate
+// applications, bit for bit; what the K columns share is each load of a
+// factor quad, an MBF entry or an interface-matrix tile, and each step of
+// the row recurrence of a box.
+
+template <typename T>
+struct RhsPtrs {
+  T* v[kMaxRhs];
+};
+
+// Blocks in flight per lane for K right-hand sides: about 64 VGPRs of quads
+// (the K columns need their own registers), between 2 and 4.
+template <typename S, int NQ, int K>
+constexpr int reg_depth_k() {
+  constexpr int per_block = NQ * 4 * (int)sizeof(S) / 4;
+  constexpr int d = (K == 1 ? 96 : 64) / per_block;
+  return d < 2 ? 2 : d > 4 ? 4 : d;
+}
+
+// acc[k] = sum_c D(c, r) ys[k][c] for the K broadcast vectors ys[k * GS ..]:
+// each factor quad is converted once and used for every column; per column,
+// the four partial sums of row_dot.  The broadcast reads run one quad ahead
+// of the arithmetic, and a scheduling barrier after each quad keeps the
+// compiler from hoisting all NQ x K reads at once (which would need more
+// registers than a lane has).
+template <typename T, int K, int GS>
+__device__ __forceinline__ void load_ys(T (&y)[K][4], const T* ys, int q) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const T* yk = ys + k * GS + 4 * q;
+    if constexpr (sizeof(T) == 4) {
+      const f32x4 v = *reinterpret_cast<const f32x4*>(yk);
+      y[k][0] = v[0], y[k][1] = v[1], y[k][2] = v[2], y[k][3] = v[3];
+    } else {
+      const f64x2 v0 = *reinterpret_cast<const f64x2*>(yk);
+      const f64x2 v1 = *reinterpret_cast<const f64x2*>(yk + 2);
+      y[k][0] = v0[0], y[k][1] = v0[1], y[k][2] = v1[0], y[k][3] = v1[1];
+    }
+  }
+}
+
+template <typename T, typename S, int NQ, int K, int GS>
+__device__ __forceinline__ void row_dot_k(const Quad<S> (&d)[NQ], const T* ys, T (&acc)[K]) {
+  T a[K][4];
+#pragma unroll
+  for (int k = 0; k < K; ++k) a[k][0] = a[k][1] = a[k][2] = a[k][3] = T(0);
+  T y[2][K][4];
+  load_ys<T, K, GS>(y[0], ys, 0);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    if (q + 1 < NQ) load_ys<T, K, GS>(y[(q + 1) & 1], ys, q + 1);
+    const T d0 = (T)d[q][0], d1 = (T)d[q][1], d2 = (T)d[q][2], d3 = (T)d[q][3];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      a[k][0] = fmat(d0, y[q & 1][k][0], a[k][0]);
+      a[k][1] = fmat(d1, y[q & 1][k][1], a[k][1]);
+      a[k][2] = fmat(d2, y[q & 1][k][2], a[k][2]);
+      a[k][3] = fmat(d3, y[q & 1][k][3], a[k][3]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = (a[k][0] + a[k][1]) + (a[k][2] + a[k][3]);
+}
+
+// Completes this work-item's global stores before its later loads and makes
+// them visible to the group (workgroup scope: waits only, no cache flush).
+__device__ __forceinline__ void group_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+}
+
+// Block LDL^T solves of one box for K right-hand sides by a group (the
+// recurrence of box_solve, K columns per step).  Row j of right-hand side k
+// is read at in[k] + j * istride (lane r: column r); the solution is built
+// in place at work[k] + j * wstride: the forward pass leaves u_j there and
+// the backward pass overwrites it with x_j.  The next step's rows are loaded
+// one step ahead.  ys[K][GS] is the group's broadcast slot (LDS), cp the
+// couplings (LDS); pin zeroes b_0 in column 0 (a box fixed at its first
+// cell).
+template <typename T, typename S, int NB, int GS, int K, typename In>
+__device__ __forceinline__ void box_solve_k(const In* const (&in)[K], long long istride,
+                                            T* const (&work)[K], long long wstride, T* ys,
+                                            const S* cp, const S* __restrict__ Dinv, int bx,
+                                            int by, int bstride, int r, bool live, bool pin) {
+  constexpr int NQ = NB / 4;
+  constexpr int DEPTH = reg_depth_k<S, NQ, K>();
+  const bool act = live && r < bx;
+  const int rc = r < bx ? r : bx - 1;
+  const int nq = (bx + 3) >> 2;
+  T carry[K], nxt[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) carry[k] = T(0);
+  auto in_row = [&](int s) {
+    const long long off = (long long)(s < by ? s : by - 1) * istride + rc;
+#pragma unroll
+    for (int k = 0; k < K; ++k) nxt[k] = (T)in[k][off];
+  };
+  in_row(0);
+  pipelined_sweep<S, NQ, DEPTH>(
+      live ? by : 0, wave_steps<DEPTH>(live ? by : 0), [](int s) { return s; },
+      [&](int s, const Quad<S>(&d)[NQ], bool valid) {
+        const int j = s < by ? s : by - 1;
+        const bool w = act && valid;
+        T b[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) b[k] = (pin && j == 0 && rc == 0) ? T(0) : nxt[k];
+        in_row(s + 1);
+        const T cj = (T)cp[j * bx + rc];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const T y = j > 0 ? fmat(cj, carry[k], b[k]) : b[k];
+          ys[k * GS + r] = w ? y : T(0);
+        }
+        wave_sync();
+        T acc[K];
+        row_dot_k<T, S, NQ, K, GS>(d, ys, acc);
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          if (w) work[k][(long long)j * wstride + r] = acc[k];
+          carry[k] = w ? acc[k] : carry[k];
+        }
+      },
+      Dinv, bstride, bx, nq, rc);
+  group_fence();
+  // carry = x_{by-1} = u_{by-1}
+  const int nb = live && by > 1 ? by - 1 : 0;
+  auto u_row = [&](int s) {
+    int j = by - 2 - s;
+    j = j < 0 ? 0 : j;
+#pragma unroll
+    for (int k = 0; k < K; ++k) nxt[k] = work[k][(long long)j * wstride + rc];
+  };
+  u_row(0);
+  pipelined_sweep<S, NQ, DEPTH>(
+      nb, wave_steps<DEPTH>(nb), [by](int s) { return by - 2 - s; },
+      [&](int s, const Quad<S>(&d)[NQ], bool valid) {
+        int j = by - 2 - s;
+        j = j < 0 ? 0 : j;
+        const int jn = j + 1 < by ? j + 1 : by - 1;
+        const bool w = act && valid;
+        T u[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) u[k] = nxt[k];
+        u_row(s + 1);
+        const T cj = (T)cp[jn * bx + rc];
+#pragma unroll
+        for (int k = 0; k < K; ++k) ys[k * GS + r] = w ? cj * carry[k] : T(0);
+        wave_sync();
+        T acc[K];
+        row_dot_k<T, S, NQ, K, GS>(d, ys, acc);
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const T xj = u[k] + acc[k];
+          if (w) work[k][(long long)j * wstride + r] = xj;
+          carry[k] = w ? xj : carry[k];
+        }
+      },
+      Dinv, bstride, bx, nq, rc);
+  group_fence();
+}
+
+// LDS slot of one lane group for K right-hand sides:
+//   ys[K][GS] (T) | cp[max cells] (S).
+template <typename T, typename S, int GS, int K>
+struct BoxSlotK {
+  T* ys;
+  S* cp;
+  __device__ BoxSlotK(char* base) {
+    ys = reinterpret_cast<T*>(base);
+    cp = reinterpret_cast<S*>(base + K * GS * sizeof(T));
+  }
+};
+
+// k_local for K right-hand sides: p_k[Omega_i] = A_i^-1 r_k[Omega_i] (solved
+// in place in p_k) and the trace moments of every coarse dof of the
+// subdomain for every k (mU[k * nc + dof], mP likewise).
+template <typename T, typename S, int NB, int K, int GS = (NB <= 16 ? 16 : NB <= 32 ? 32 : 64)>
+__global__ void __launch_bounds__(kBoxThreads)
+    k_local_k(const BoxDesc* __restrict__ boxes, int m, int group_bytes,
+              const S* __restrict__ dinv, const S* __restrict__ coup, RhsPtrs<const double> r,
+              RhsPtrs<T> p, int nx, const int* __restrict__ dof_off,
+              const int* __restrict__ dof_side, const int* __restrict__ w_off,
+              const double* __restrict__ wU, const double* __restrict__ wP,
+              double* __restrict__ mU, double* __restrict__ mP, int nc) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int grp = threadIdx.x / GS, lane = threadIdx.x % GS;
+  const int i0 = blockIdx.x * (blockDim.x / GS) + grp;
+  const bool live = i0 < m;
+  const int i = live ? i0 : m - 1;
+  BoxSlotK<T, S, GS, K> L(smem_raw + (long long)grp * group_bytes);
+  const BoxDesc d = boxes[i];
+  const int bx = d.bx, by = d.by;
+  const long long origin = (long long)d.y0 * nx + d.x0;
+  const double* in[K];
+  T* work[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    in[k] = r.v[k] + origin;
+    work[k] = p.v[k] + origin;
+  }
+  words_to_lds<S, GS>(L.cp, coup + d.coff, bx * by, lane, live);
+  wave_sync();
+  box_solve_k<T, S, NB, GS, K, double>(in, nx, work, nx, L.ys, L.cp, dinv + d.doff, bx, by,
+                                       d.bs, lane, live, live && d.pin);
+  if (!live) return;
+  for (int kd = dof_off[i] + lane; kd < dof_off[i + 1]; kd += GS) {
+    const int side = dof_side[kd];
+    const int len = (side <= 1) ? by : bx;
+    const double* wu = wU + w_off[kd];
+    const double* wp = wP + w_off[kd];
+    double su[K], sp[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) su[k] = sp[k] = 0.0;
+    for (int j0 = 0; j0 < len; j0 += 8) {
+      double a8[8], b8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int jf = j0 + u < len ? j0 + u : len - 1;
+        a8[u] = wu[jf];
+        b8[u] = wp[jf];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int jf = j0 + u;
+        if (jf < len) {
+          const int row = side == 0 ? jf : side == 1 ? jf : side == 2 ? 0 : by - 1;
+          const int col = side == 0 ? 0 : side == 1 ? bx - 1 : jf;
+          const long long c = (long long)row * nx + col;
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const double v = (double)work[k][c];
+            su[k] = fmat(a8[u], v, su[k]);
+            sp[k] = fmat(b8[u], v, sp[k]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      mU[(long long)k * nc + kd] = su[k];
+      mP[(long long)k * nc + kd] = sp[k];
+    }
+  }
+}
+
+// k_patch for K right-hand sides: e_k = A[S_i]^-1 rho_k[S_i], built in the
+// patch's slice of the scratch vectors (offset coff, row stride bx), then
+// p_k += e_k on the owned cells.
+template <typename T, typename S, int NB, int K, int GS = (NB <= 16 ? 16 : NB <= 32 ? 32 : 64)>
+__global__ void __launch_bounds__(kBoxThreads)
+    k_patch_k(const BoxDesc* __restrict__ boxes, int m, int group_bytes,
+              const S* __restrict__ dinv, const S* __restrict__ coup, RhsPtrs<const T> rho,
+              RhsPtrs<T> p, RhsPtrs<T> e, int nx) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int grp = threadIdx.x / GS, lane = threadIdx.x % GS;
+  const int i0 = blockIdx.x * (blockDim.x / GS) + grp;
+  const bool live = i0 < m;
+  const int i = live ? i0 : m - 1;
+  BoxSlotK<T, S, GS, K> L(smem_raw + (long long)grp * group_bytes);
+  const BoxDesc d = boxes[i];
+  const int bx = d.bx, by = d.by;
+  const long long origin = (long long)d.y0 * nx + d.x0;
+  const T* in[K];
+  T* work[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    in[k] = rho.v[k] + origin;
+    work[k] = e.v[k] + d.coff;
+  }
+  words_to_lds<S, GS>(L.cp, coup + d.coff, bx * by, lane, live);
+  wave_sync();
+  box_solve_k<T, S, NB, GS, K, T>(in, nx, work, bx, L.ys, L.cp, dinv + d.doff, bx, by, d.bs,
+                                  lane, live, live && d.pin);
+  // p += e on the owned cells, eight rows of read-modify-write in flight
+  const bool own = live && lane >= d.ox && lane < d.ox + d.obx;
+  const int col = own ? lane : d.ox;
+  const long long o2 = origin + (long long)d.oy * nx;
+  const int rows = wave_max(live ? d.oby : 0);
+#pragma unroll 1
+  for (int k = 0; k < K; ++k) {
+    T* pk = p.v[k];
+    const T* ek = work[k] + (long long)d.oy * bx;
+    for (int j0 = 0; j0 < rows; j0 += 8) {
+      T v[8], ev[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = j0 + u < d.oby ? j0 + u : d.oby - 1;
+        v[u] = pk[o2 + (long long)j * nx + col];
+        ev[u] = ek[(long long)j * bx + col];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (own && j0 + u < d.oby) pk[o2 + (long long)(j0 + u) * nx + lane] = v[u] + ev[u];
+    }
+  }
+}
+
+// Interface right-hand sides of K columns (blockIdx.y = column; vectors of
+// column k at offset k * nc / k * np).
+__global__ void k_coarse_rhs_k(const int4* __restrict__ gsrc, const double* __restrict__ gscale,
+                               const double* __restrict__ mU, const double* __restrict__ mP,
+                               double* __restrict__ g_nd, int np, int nc) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= np) return;
+  const long long ko = (long long)blockIdx.y * nc;
+  const int4 src = gsrc[t];
+  const double v = src.z == 0 ? -(mU[ko + src.x] + mU[ko + src.y])
+                              : -(mP[ko + src.x] - mP[ko + src.y]);
+  g_nd[(long long)blockIdx.y * np + t] = src.z == 2 ? 0.0 : gscale[t] * v;
+}
+
+// s[u][k] += sum_q m[u][q] vec_k[b0 + 64 q] for the K columns vec + k * ld
+// (LDS): per (u, k) the order of fma_tile.  One column at a time (a
+// scheduling barrier after each keeps the LDS reads of later columns from
+// being hoisted into registers).
+template <int K>
+__device__ __forceinline__ void fma_tile_k(double (&s)[4][K], const double (&m)[4][8],
+                                           const double* vec, int ld, int ncol, int b0) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double x[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) x[q] = b0 + 64 * q < ncol ? vec[k * ld + b0 + 64 * q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s[u][k] = fmat(m[u][q], x[q], s[u][k]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Sums of N values (a power of two, 2..64) over the 64 lanes of the wave, all
+// at once: at the exchange with lane ^ off (off = 32, 16, ..., 1) a lane
+// keeps half of its values, and the sum of each kept value is its own plus
+// the partner's, so every value meets the pairs of wave_sum in the same order
+// (each result is bit-identical to wave_sum of that value) with 2N - 1 + 6 -
+// log2 N exchanges instead of 6 N.  Afterwards v[0] in lane l is the sum of
+// value butterfly_index<N>(l).
+template <int N>
+__device__ __forceinline__ int butterfly_index(int lane) {
+  int idx = 0, n = N;
+#pragma unroll
+  for (int off = 32; off > 0 && n > 1; off >>= 1) {
+    n >>= 1;
+    if (lane & off) idx += n;
+  }
+  return idx;
+}
+template <int N>
+__device__ __forceinline__ void butterfly_sum(double (&v)[N], int lane) {
+#pragma unroll
+  for (int st = 0; st < 6; ++st) {
+    const int off = 32 >> st;
+    const int n = N >> st;  // values still held (compile-time after unrolling)
+    if (n > 1) {
+      const int half = n >> 1;
+      const bool upper = (lane & off) != 0;
+#pragma unroll
+      for (int i = 0; i < N / 2; ++i)
+        if (i < half) {
+          const double send = upper ? v[i] : v[i + half];
+          const double keep = upper ? v[i + half] : v[i];
+          v[i] = keep + __shfl_xor(send, off, 64);
+        }
+    } else {
+      v[0] += __shfl_xor(v[0], off, 64);
+    }
+  }
+}
+
+// gemv_chunk for K columns of the LDS matrix vec (column k at vec + k * ld).
+// After the butterfly, lane l holds output (row r + u_l, column k_l) with
+// u_l * K + k_l = butterfly_index(l); pre(row, k) runs in every lane for its
+// own output before that group's tile loads, and emit(row, k, value) in one
+// lane per output.
+template <int K, typename Pre, typename Emit>
+__device__ __forceinline__ void gemv_chunk_k(const double* __restrict__ M, int ncol, int row0,
+                                             int row1, const double* vec, int ld,
+                                             double (&m)[4][8], Pre pre, Emit emit) {
+  constexpr int N = 4 * K;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int bi = butterfly_index<N>(lane);
+  const int ul = bi / K, kl = bi % K;
+  const bool emitter = (lane & (64 / N - 1)) == 0;
+  for (int r = row0 + 4 * wid; r < row1; r += 4 * nw) {
+    const bool first = r == row0 + 4 * wid;
+    if (!first) pre(r + ul, kl);
+    double s[4][K];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < K; ++k) s[u][k] = 0.0;
+    fma_tile_k<K>(s, m, vec, ld, ncol, lane);
+    for (int b0 = lane + 64 * 8; b0 < ncol; b0 += 64 * 8) {
+      load_tile(m, M, ncol, r, row1, b0);
+      fma_tile_k<K>(s, m, vec, ld, ncol, b0);
+    }
+    if (r + 4 * nw < row1) load_tile(m, M, ncol, r + 4 * nw, row1, lane);
+    double v[N];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < K; ++k) v[u * K + k] = s[u][k];
+    butterfly_sum<N>(v, lane);
+    if (emitter && r + ul < row1) emit(r + ul, kl, v[0]);
+  }
+}
+
+// k_coarse_fwd for K columns (column k of g_nd, contrib and ybuf at offsets
+// k * np, k * maxp * np and k * np).
+template <int K>
+__global__ void __launch_bounds__(kVecThreads)
+    k_coarse_fwd_k(const CChunk* __restrict__ chunks, const double* __restrict__ fwd,
+                   const double* __restrict__ g_nd, double* __restrict__ contrib, int maxp,
+                   int np, const int* __restrict__ cdest, double* __restrict__ ybuf) {
+  extern __shared__ double v[];
+  const CChunk ch = chunks[blockIdx.x];
+  const int nf = ch.nf;
+  const double* M = fwd + ch.mat;
+  const int yoff = ch.yoff, coff = ch.coff;
+  const long long cstride = (long long)maxp * np;
+  int dst = -1;
+  auto pre = [&](int row, int) {
+    dst = (row >= nf && row < ch.row1) ? cdest[coff + row - nf] : -1;
+  };
+  double m[4][8];
+  const int rw = ch.row0 + 4 * (threadIdx.x >> 6);
+  load_tile(m, M, nf, rw, ch.row1, threadIdx.x & 63);
+  {
+    const int bi = butterfly_index<4 * K>(threadIdx.x & 63);
+    pre(rw + bi / K, bi % K);
+  }
+  for (int e = threadIdx.x; e < nf * K; e += blockDim.x) {
+    const int k = e / nf, a = e - k * nf;
+    const long long t = (long long)yoff + a;
+    double s = g_nd[(long long)k * np + t];
+    const double* ck = contrib + k * cstride;
+    for (int u0 = 0; u0 < maxp; u0 += 8) {
+      double c[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) c[q] = u0 + q < maxp ? ck[(long long)(u0 + q) * np + t] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (u0 + q < maxp) s -= c[q];
+    }
+    v[k * nf + a] = s;
+  }
+  __syncthreads();
+  gemv_chunk_k<K>(M, nf, ch.row0, ch.row1, v, nf, m, pre, [&](int row, int k, double val) {
+    if (row < nf)
+      ybuf[(long long)k * np + yoff + row] = val;
+    else
+      contrib[k * cstride + dst] = val;
+  });
+}
+
+// k_coarse_bwd for K columns (column k of ybuf and x at offsets k * np and
+// k * nc).
+template <int K>
+__global__ void __launch_bounds__(kVecThreads)
+    k_coarse_bwd_k(const CChunk* __restrict__ chunks, const double* __restrict__ bwd,
+                   const int* __restrict__ idx, const double* __restrict__ ybuf,
+                   double* __restrict__ x, int np, int nc) {
+  extern __shared__ double xu[];
+  const CChunk ch = chunks[blockIdx.x];
+  const int nu = ch.nu;
+  const double* M = bwd + ch.mat;
+  const int yoff = ch.yoff, fcol = ch.fcol;
+  if (nu == 0) {
+    for (int e = threadIdx.x; e < (ch.row1 - ch.row0) * K; e += blockDim.x) {
+      const int k = e / (ch.row1 - ch.row0), row = ch.row0 + e - k * (ch.row1 - ch.row0);
+      x[(long long)k * nc + idx[fcol + row]] = ybuf[(long long)k * np + yoff + row];
+    }
+    return;
+  }
+  int dst = 0;
+  double y = 0.0;
+  auto pre = [&](int row, int k) {
+    if (row < ch.row1) {
+      dst = idx[fcol + row];
+      y = ybuf[(long long)k * np + yoff + row];
+    }
+  };
+  double m[4][8];
+  const int rw = ch.row0 + 4 * (threadIdx.x >> 6);
+  load_tile(m, M, nu, rw, ch.row1, threadIdx.x & 63);
+  {
+    const int bi = butterfly_index<4 * K>(threadIdx.x & 63);
+    pre(rw + bi / K, bi % K);
+  }
+  for (int e = threadIdx.x; e < nu * K; e += blockDim.x) {
+    const int k = e / nu, b = e - k * nu;
+    xu[k * nu + b] = x[(long long)k * nc + idx[ch.ucol + b]];
+  }
+  __syncthreads();
+  gemv_chunk_k<K>(M, nu, ch.row0, ch.row1, xu, nu, m, pre,
+                  [&](int, int k, double val) { x[(long long)k * nc + dst] = y - val; });
+}
+
+// k_reconstruct for K columns: p_k[Omega_i] += P_i x_i^k, each MBF entry
+// loaded once for all k.
+template <typename T, typename S, int K>
+__global__ void __launch_bounds__(kBoxThreads)
+    k_reconstruct_k(const BoxDesc* __restrict__ boxes, const S* __restrict__ mbf,
+                    const long long* __restrict__ mbf_off, const int* __restrict__ dof_off,
+                    const double* __restrict__ xc, int nc, RhsPtrs<T> p, int nx) {
+  __shared__ T xs[K][64];
+  const int i = blockIdx.x;
+  const BoxDesc d = boxes[i];
+  const int k0 = dof_off[i], nk = dof_off[i + 1] - k0, ncell = d.bx * d.by;
+  for (int e = threadIdx.x; e < nk * K; e += blockDim.x) {
+    const int k = e / nk, j = e - k * nk;
+    xs[k][j] = (T)xc[(long long)k * nc + k0 + j];
+  }
+  __syncthreads();
+  const S* P = mbf + mbf_off[i];
+  for (int q = threadIdx.x; q < ncell; q += blockDim.x) {
+    const int a = q % d.bx, j = q / d.bx;
+    const long long c = (long long)(d.y0 + j) * nx + d.x0 + a;
+    T s[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k] = p.v[k][c];
+    for (int j2 = 0; j2 < nk; ++j2) {
+      const T pv = (T)P[(long long)j2 * ncell + q];
+#pragma unroll
+      for (int k = 0; k < K; ++k) s[k] = fmat(pv, xs[k][j2], s[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) p.v[k][c] = s[k];
+  }
+}
+
+// Smoothing residuals rho_k = r_k - A p_k (blockIdx.y = k).
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+    k_residual_k(const T* __restrict__ tx, const T* __restrict__ ty, int nx, int ny,
+                 RhsPtrs<const double> r, RhsPtrs<const T> p, RhsPtrs<T> rho) {
+  const long long n = (long long)nx * ny;
+  const double* rk = r.v[blockIdx.y];
+  const T* pk = p.v[blockIdx.y];
+  T* ok = rho.v[blockIdx.y];
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
+       c += (long long)gridDim.x * blockDim.x) {
+    const int iy = (int)(c / nx), ix = (int)(c - (long long)iy * nx);
+    ok[c] = (T)rk[c] - stencil(tx, ty, nx, ny, ix, iy, pk);
+  }
+}
+
+// k_sum for K vectors (blockIdx.y = k; partials of k at k * kMaxVecBlocks).
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+    k_sum_k(RhsPtrs<const T> p, long long n, double* __restrict__ partials) {
+  __shared__ double red[kVecThreads / 64];
+  const T* pk = p.v[blockIdx.y];
+  const long long st = (long long)gridDim.x * blockDim.x;
+  double s = 0.0;
+  for (long long c0 = blockIdx.x * (long long)blockDim.x + threadIdx.x; c0 < n;
+       c0 += kRound * st) {
+    T a[kRound];
+#pragma unroll
+    for (int u = 0; u < kRound; ++u) {
+      const long long c = c0 + u * st;
+      a[u] = pk[c < n ? c : n - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kRound; ++u)
+      if (c0 + u * st < n) s += (double)a[u];
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) partials[(long long)blockIdx.y * kMaxVecBlocks + blockIdx.x] = s;
+}
+
+// k_finalize for K vectors (blockIdx.y = k).
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+    k_finalize_k(RhsPtrs<const T> p, long long n, const double* __restrict__ partials, int nb,
+                 RhsPtrs<double> z) {
+  __shared__ double red[kVecThreads / 64];
+  const T* pk = p.v[blockIdx.y];
+  double* zk = z.v[blockIdx.y];
+  const double* part = partials ? partials + (long long)blockIdx.y * kMaxVecBlocks : nullptr;
+  const long long st = (long long)gridDim.x * blockDim.x;
+  T a[kRound];
+  auto load = [&](long long c0) {
+#pragma unroll
+    for (int u = 0; u < kRound; ++u) {
+      const long long c = c0 + u * st;
+      a[u] = pk[c < n ? c : n - 1];
+    }
+  };
+  const long long start = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  load(start);
+  const double mean = part ? reduce_partials(part, nb, red) / (double)n : 0.0;
+  for (long long c0 = start; c0 < n; c0 += kRound * st) {
+    if (c0 != start) load(c0);
+#pragma unroll
+    for (int u = 0; u < kRound; ++u) {
+      const long long c = c0 + u * st;
+      if (c < n) zk[c] = (double)a[u] - mean;
+    }
+  }
+}
+
 inline int grid_for(long long n) {
   long long b = (n + kVecThreads - 1) / kVecThreads;
   if (b > 4096) b = 4096;
@@ -975,18 +1591,24 @@ void launch_coarse_rhs(const int4* gsrc, const double* gscale, const double* mU,
   hipLaunchKernelGGL(k_coarse_rhs, dim3((np + 255) / 256), dim3(256), 0, s, gsrc, gscale, mU, mP,
                      g_nd, np);
 }
+// Threads per chunk of an interface level: levels with many chunks (the
+// lower ones, small fronts) take one wave per chunk, so that about a dozen
+// chunks are resident per compute unit and the level runs in one round;
+// levels with few, large chunks take four waves per chunk.
+static int coarse_threads(int nchunks) { return nchunks >= 1024 ? 64 : kVecThreads; }
+
 void launch_coarse_fwd(const CChunk* chunks, int nchunks, const double* fwd, const double* g_nd,
                        double* contrib, int maxp, int np, const int* cdest, double* ybuf,
                        int max_nf, hipStream_t s) {
   if (nchunks <= 0) return;
-  hipLaunchKernelGGL(k_coarse_fwd, dim3(nchunks), dim3(kVecThreads),
+  hipLaunchKernelGGL(k_coarse_fwd, dim3(nchunks), dim3(coarse_threads(nchunks)),
                      sizeof(double) * (size_t)(max_nf > 0 ? max_nf : 1), s, chunks, fwd, g_nd,
                      contrib, maxp, np, cdest, ybuf);
 }
 void launch_coarse_bwd(const CChunk* chunks, int nchunks, const double* bwd, const int* idx,
                        const double* ybuf, double* x, int max_nu, hipStream_t s) {
   if (nchunks <= 0) return;
-  hipLaunchKernelGGL(k_coarse_bwd, dim3(nchunks), dim3(kVecThreads),
+  hipLaunchKernelGGL(k_coarse_bwd, dim3(nchunks), dim3(coarse_threads(nchunks)),
                      sizeof(double) * (size_t)(max_nu > 0 ? max_nu : 1), s, chunks, bwd, idx,
                      ybuf, x);
 }
@@ -1015,6 +1637,209 @@ void launch_patch(const BoxDesc* boxes, int m, int max_cells, int max_bx, const 
   const dim3 grid((m + groups - 1) / groups), block(groups * group_size(max_bx));
   MRCM_BOX_DISPATCH(k_patch, T, S, max_bx, grid, block, shm, s, boxes, m, gb, cp_words,
                     dinv, coup, rho, p, nx);
+}
+
+// ---- K right-hand sides per launch ----
+namespace {
+template <typename T>
+RhsPtrs<T> rhs_ptrs(int k, T* const* v) {
+  RhsPtrs<T> out{};
+  for (int i = 0; i < k; ++i) out.v[i] = v[i];
+  return out;
+}
+void check_k(int k) {
+  if (k != 2 && k != 4 && k != 8)
+    throw Error(MRCM_EINVAL, "multi-RHS launch of unsupported width");
+}
+inline size_t group_bytes_k(int k, int max_bx, int max_cells, size_t t, size_t w) {
+  const size_t b = (size_t)k * group_size(max_bx) * t + (size_t)round16(max_cells, w) * w;
+  return (b + 15) / 16 * 16;
+}
+int box_groups_k(int k, int max_bx, int max_cells, size_t t, size_t w) {
+  const int gs = group_size(max_bx);
+  for (int groups = kBoxThreads / gs; groups >= 1; groups /= 2)
+    if (groups * group_bytes_k(k, max_bx, max_cells, t, w) <= 64 * 1024) return groups;
+  return 0;
+}
+}  // namespace
+
+size_t box_lds_bytes_k(int k, int max_bx, int max_cells, size_t t, size_t w) {
+  const int groups = box_groups_k(k, max_bx, max_cells, t, w);
+  return groups ? groups * group_bytes_k(k, max_bx, max_cells, t, w) : ~(size_t)0;
+}
+
+// Right-hand sides one box launch takes at most, by column width: what the
+// lane's registers hold without spilling (quads in flight, four partial sums
+// and the rows of every column); 1 = the one-RHS kernels, once per column.
+inline int box_width_k(int nb, size_t w) {
+  if (w == 8) return nb <= 16 ? 4 : nb <= 48 ? 2 : 1;
+  return nb <= 16 ? 8 : nb <= 32 ? 4 : nb <= 48 ? 2 : 1;
+}
+
+#define MRCM_BOX_DISPATCH_K(KERNEL, T, S, nb, kk, ...)                                  \
+  do {                                                                                 \
+    if (nb == 16 && kk == 8) hipLaunchKernelGGL((KERNEL<T, S, 16, 8>), __VA_ARGS__);   \
+    else if (nb == 16 && kk == 4) hipLaunchKernelGGL((KERNEL<T, S, 16, 4>), __VA_ARGS__); \
+    else if (nb == 16) hipLaunchKernelGGL((KERNEL<T, S, 16, 2>), __VA_ARGS__);         \
+    else if (nb == 24 && kk == 4) hipLaunchKernelGGL((KERNEL<T, S, 24, 4>), __VA_ARGS__); \
+    else if (nb == 24) hipLaunchKernelGGL((KERNEL<T, S, 24, 2>), __VA_ARGS__);         \
+    else if (nb == 32 && kk == 4) hipLaunchKernelGGL((KERNEL<T, S, 32, 4>), __VA_ARGS__); \
+    else if (nb == 32) hipLaunchKernelGGL((KERNEL<T, S, 32, 2>), __VA_ARGS__);         \
+    else if (nb == 40) hipLaunchKernelGGL((KERNEL<T, S, 40, 2>), __VA_ARGS__);         \
+    else hipLaunchKernelGGL((KERNEL<T, S, 48, 2>), __VA_ARGS__);                       \
+  } while (0)
+#define MRCM_K_DISPATCH(k, CALL) \
+  do {                           \
+    if ((k) == 2) {              \
+      constexpr int K = 2;       \
+      CALL;                      \
+    } else if ((k) == 4) {       \
+      constexpr int K = 4;       \
+      CALL;                      \
+    } else {                     \
+      constexpr int K = 8;       \
+      CALL;                      \
+    }                            \
+  } while (0)
+
+template <typename T, typename S>
+void launch_local_k(int k, const BoxDesc* boxes, int m, int max_cells, int max_bx, const S* dinv,
+                    const S* coup, const double* const* r, T* const* p, int nx,
+                    const int* dof_off, const int* dof_side, const int* w_off, const double* wU,
+                    const double* wP, double* mU, double* mP, int nc, hipStream_t s) {
+  check_k(k);
+  const int nb = col_width(max_bx), kk = std::min(k, box_width_k(nb, sizeof(S)));
+  for (int k0 = 0; k0 < k; k0 += kk) {
+    double* u = mU + (long long)k0 * nc;
+    double* v = mP + (long long)k0 * nc;
+    if (kk == 1) {
+      launch_local<T, S>(boxes, m, max_cells, max_bx, dinv, coup, r[k0], p[k0], nx, dof_off,
+                         dof_side, w_off, wU, wP, u, v, s);
+      continue;
+    }
+    const int groups = box_groups_k(kk, max_bx, max_cells, sizeof(T), sizeof(S));
+    const size_t shm = box_lds_bytes_k(kk, max_bx, max_cells, sizeof(T), sizeof(S));
+    const int gb = (int)group_bytes_k(kk, max_bx, max_cells, sizeof(T), sizeof(S));
+    const dim3 grid((m + groups - 1) / groups), block(groups * group_size(max_bx));
+    const RhsPtrs<const double> rp = rhs_ptrs(kk, r + k0);
+    const RhsPtrs<T> pp = rhs_ptrs(kk, p + k0);
+    MRCM_BOX_DISPATCH_K(k_local_k, T, S, nb, kk, grid, block, shm, s, boxes, m, gb, dinv, coup,
+                        rp, pp, nx, dof_off, dof_side, w_off, wU, wP, u, v, nc);
+  }
+}
+
+void launch_coarse_rhs_k(int k, const int4* gsrc, const double* gscale, const double* mU,
+                         const double* mP, double* g_nd, int np, int nc, hipStream_t s) {
+  check_k(k);
+  if (np <= 0) return;
+  hipLaunchKernelGGL(k_coarse_rhs_k, dim3((np + 255) / 256, k), dim3(256), 0, s, gsrc, gscale,
+                     mU, mP, g_nd, np, nc);
+}
+
+// Columns go in groups of at most 4 (wider ones spill registers) whose LDS
+// vector (group width x the largest front) fits in 64 KB.
+static int coarse_width(int k, int max_dim) {
+  int w = k < 4 ? k : 4;
+  while (w > 1 && (size_t)w * (max_dim > 0 ? max_dim : 1) * sizeof(double) > 64 * 1024) w /= 2;
+  return w;
+}
+
+void launch_coarse_fwd_k(int k, const CChunk* chunks, int nchunks, const double* fwd,
+                         const double* g_nd, double* contrib, int maxp, int np, const int* cdest,
+                         double* ybuf, int max_nf, hipStream_t s) {
+  check_k(k);
+  if (nchunks <= 0) return;
+  const int w = coarse_width(k, max_nf);
+  for (int k0 = 0; k0 < k; k0 += w) {
+    const double* g = g_nd + (long long)k0 * np;
+    double* c = contrib + (long long)k0 * maxp * np;
+    double* y = ybuf + (long long)k0 * np;
+    const size_t shm = sizeof(double) * (size_t)w * (max_nf > 0 ? max_nf : 1);
+    if (w == 1)
+      hipLaunchKernelGGL(k_coarse_fwd, dim3(nchunks), dim3(coarse_threads(nchunks)), shm, s, chunks, fwd, g,
+                         c, maxp, np, cdest, y);
+    else if (w == 2)
+      hipLaunchKernelGGL(k_coarse_fwd_k<2>, dim3(nchunks), dim3(coarse_threads(nchunks)), shm, s, chunks, fwd,
+                         g, c, maxp, np, cdest, y);
+    else
+      hipLaunchKernelGGL(k_coarse_fwd_k<4>, dim3(nchunks), dim3(coarse_threads(nchunks)), shm, s, chunks, fwd,
+                         g, c, maxp, np, cdest, y);
+  }
+}
+
+void launch_coarse_bwd_k(int k, const CChunk* chunks, int nchunks, const double* bwd,
+                         const int* idx, const double* ybuf, double* x, int max_nu, int np, int nc,
+                         hipStream_t s) {
+  check_k(k);
+  if (nchunks <= 0) return;
+  const int w = coarse_width(k, max_nu);
+  for (int k0 = 0; k0 < k; k0 += w) {
+    const double* y = ybuf + (long long)k0 * np;
+    double* xk = x + (long long)k0 * nc;
+    const size_t shm = sizeof(double) * (size_t)w * (max_nu > 0 ? max_nu : 1);
+    if (w == 1)
+      hipLaunchKernelGGL(k_coarse_bwd, dim3(nchunks), dim3(coarse_threads(nchunks)), shm, s, chunks, bwd, idx,
+                         y, xk);
+    else if (w == 2)
+      hipLaunchKernelGGL(k_coarse_bwd_k<2>, dim3(nchunks), dim3(coarse_threads(nchunks)), shm, s, chunks, bwd,
+                         idx, y, xk, np, nc);
+    else
+      hipLaunchKernelGGL(k_coarse_bwd_k<4>, dim3(nchunks), dim3(coarse_threads(nchunks)), shm, s, chunks, bwd,
+                         idx, y, xk, np, nc);
+  }
+}
+
+template <typename T, typename S>
+void launch_reconstruct_k(int k, const BoxDesc* boxes, int m, const S* mbf,
+                          const long long* mbf_off, const int* dof_off, const double* xc, int nc,
+                          T* const* p, int nx, hipStream_t s) {
+  check_k(k);
+  const RhsPtrs<T> pp = rhs_ptrs(k, p);
+  MRCM_K_DISPATCH(k, hipLaunchKernelGGL((k_reconstruct_k<T, S, K>), dim3(m), dim3(kBoxThreads), 0,
+                                        s, boxes, mbf, mbf_off, dof_off, xc, nc, pp, nx));
+}
+
+template <typename T>
+void launch_residual_k(int k, const T* tx, const T* ty, int nx, int ny, const double* const* r,
+                       const T* const* p, T* const* rho, hipStream_t s) {
+  check_k(k);
+  const long long n = (long long)nx * ny;
+  hipLaunchKernelGGL(k_residual_k<T>, dim3(grid_for(n), k), dim3(kVecThreads), 0, s, tx, ty, nx,
+                     ny, rhs_ptrs(k, r), rhs_ptrs(k, p), rhs_ptrs(k, rho));
+}
+
+template <typename T, typename S>
+void launch_patch_k(int k, const BoxDesc* boxes, int m, int max_cells, int max_bx, const S* dinv,
+                    const S* coup, const T* const* rho, T* const* p, T* const* e, int nx,
+                    hipStream_t s) {
+  check_k(k);
+  const int nb = col_width(max_bx), kk = std::min(k, box_width_k(nb, sizeof(S)));
+  for (int k0 = 0; k0 < k; k0 += kk) {
+    if (kk == 1) {
+      launch_patch<T, S>(boxes, m, max_cells, max_bx, dinv, coup, rho[k0], p[k0], nx, s);
+      continue;
+    }
+    const int groups = box_groups_k(kk, max_bx, max_cells, sizeof(T), sizeof(S));
+    const size_t shm = box_lds_bytes_k(kk, max_bx, max_cells, sizeof(T), sizeof(S));
+    const int gb = (int)group_bytes_k(kk, max_bx, max_cells, sizeof(T), sizeof(S));
+    const dim3 grid((m + groups - 1) / groups), block(groups * group_size(max_bx));
+    const RhsPtrs<const T> rp = rhs_ptrs(kk, rho + k0);
+    const RhsPtrs<T> pp = rhs_ptrs(kk, p + k0), ep = rhs_ptrs(kk, e + k0);
+    MRCM_BOX_DISPATCH_K(k_patch_k, T, S, nb, kk, grid, block, shm, s, boxes, m, gb, dinv, coup,
+                        rp, pp, ep, nx);
+  }
+}
+
+template <typename T>
+void launch_finalize_k(int k, const T* const* p, long long n, int noflow, double* const* z,
+                       double* partials, hipStream_t s) {
+  check_k(k);
+  const int nb = vec_blocks(n);
+  const RhsPtrs<const T> pp = rhs_ptrs(k, p);
+  if (noflow)
+    hipLaunchKernelGGL(k_sum_k<T>, dim3(nb, k), dim3(kVecThreads), 0, s, pp, n, partials);
+  hipLaunchKernelGGL(k_finalize_k<T>, dim3(nb, k), dim3(kVecThreads), 0, s, pp, n,
+                     noflow ? partials : (const double*)nullptr, nb, rhs_ptrs(k, z));
 }
 
 template <typename T>
@@ -1077,11 +1902,24 @@ void launch_sumsq(const double* x, long long n, double* partials, int nb, hipStr
   template void launch_reconstruct<T, S>(const BoxDesc*, int, const S*, const long long*,       \
                                          const int*, const double*, T*, int, hipStream_t);      \
   template void launch_patch<T, S>(const BoxDesc*, int, int, int, const S*, const S*,          \
-                                   const T*, T*, int, hipStream_t);
+                                   const T*, T*, int, hipStream_t);                              \
+  template void launch_local_k<T, S>(int, const BoxDesc*, int, int, int, const S*, const S*,    \
+                                     const double* const*, T* const*, int, const int*,          \
+                                     const int*, const int*, const double*, const double*,      \
+                                     double*, double*, int, hipStream_t);                       \
+  template void launch_reconstruct_k<T, S>(int, const BoxDesc*, int, const S*,                  \
+                                           const long long*, const int*, const double*, int,    \
+                                           T* const*, int, hipStream_t);                        \
+  template void launch_patch_k<T, S>(int, const BoxDesc*, int, int, int, const S*, const S*,    \
+                                     const T* const*, T* const*, T* const*, int, hipStream_t);
 #define MRCM_INSTANTIATE_T(T)                                                                  \
   template void launch_residual<T>(const T*, const T*, int, int, const double*, const T*, T*,   \
                                    hipStream_t);                                                \
-  template void launch_finalize<T>(const T*, long long, int, double*, double*, hipStream_t);
+  template void launch_finalize<T>(const T*, long long, int, double*, double*, hipStream_t);    \
+  template void launch_residual_k<T>(int, const T*, const T*, int, int, const double* const*,   \
+                                     const T* const*, T* const*, hipStream_t);                  \
+  template void launch_finalize_k<T>(int, const T* const*, long long, int, double* const*,      \
+                                     double*, hipStream_t);
 
 MRCM_INSTANTIATE_TS(double, double)
 MRCM_INSTANTIATE_TS(float, float)

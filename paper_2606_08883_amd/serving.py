@@ -104,12 +104,12 @@ def config_for(n: int, params: dict | None = None):
                   p["sweeps"], p["overlap"], p["degree"], p["precision"])
 
 
-LANES = 4  # right-hand sides of one request solved at once (mrcm_set_lanes)
+LANES, WIDTH = 4, 4  # lanes and right-hand sides per lane of a request (mrcm_set_lanes/_batch)
 
 
 def footprint_of(req: Request, params: dict | None = None) -> int:
     from .binding import footprint
-    return footprint(config_for(req.n, params), min(req.nrhs, LANES))
+    return footprint(config_for(req.n, params), min(req.nrhs, LANES * WIDTH))
 
 
 def gpu_solver(params: dict | None = None, rtol: float = 1e-8, restart: int = 10,
@@ -130,6 +130,7 @@ def gpu_solver(params: dict | None = None, rtol: float = 1e-8, restart: int = 10
             t0 = time.perf_counter()
             ctx = Context(config_for(req.n, params), K, stream=stream)
             ctx.set_lanes(LANES)
+            ctx.set_batch(WIDTH)
             stream.synchronize()
             t1 = time.perf_counter()
             P = torch.zeros_like(B)

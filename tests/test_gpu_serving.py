@@ -8,7 +8,8 @@
 * mrcm_apply_many over several contexts equals mrcm_apply on each, bit for bit.
 * Contexts set up with a caller allocator (torch's caching allocator through
   mrcm_set_allocator) allocate through it and compute the same T r.
-* gmres_solve advancing several right-hand sides at once (lanes) gives the
+* gmres_solve advancing several right-hand sides at once (lanes, and
+  several slots per lane sharing multi-column applications of T) gives the
   solutions and iteration counts of one lane, bit for bit, and of each
   right-hand side solved on its own.
 """
@@ -137,9 +138,12 @@ def test_caller_allocator(dev):
     assert torch.equal(z0, z1)
 
 
-@pytest.mark.parametrize("precision,n,nrhs,lanes", [(2, 256, 6, 4), (0, 128, 3, 2)])
-def test_lanes_equal_one_lane(dev, precision, n, nrhs, lanes):
-    print(f"lanes: {n}^2 precision {precision}, {nrhs} rhs on 1 and {lanes} lanes", flush=True)
+@pytest.mark.parametrize("precision,n,nrhs,lanes,width",
+                         [(2, 256, 6, 4, 1), (0, 128, 3, 2, 1), (2, 256, 7, 1, 8), (2, 256, 9, 2, 4),
+                          (1, 128, 5, 2, 2), (0, 128, 4, 1, 4)])
+def test_lanes_equal_one_lane(dev, precision, n, nrhs, lanes, width):
+    print(f"lanes: {n}^2 precision {precision}, {nrhs} rhs on 1 lane and on {lanes} lanes of "
+          f"width {width}", flush=True)
     cfg = S.config_for(n, dict(precision=precision))
     K = torch.tensor(wl.lognormal_K(n, n, 2.0, 16.0, 70), dtype=torch.float64, device=dev)
     b = torch.tensor(wl.random_pairs(n, n, nrhs, 71), dtype=torch.float64, device=dev).contiguous()
@@ -148,6 +152,7 @@ def test_lanes_equal_one_lane(dev, precision, n, nrhs, lanes):
     p1 = torch.zeros_like(b)
     s1 = ctx.gmres(b, p1, rtol=1e-8, restart=10, maxit=500)
     ctx.set_lanes(lanes)
+    ctx.set_batch(width)
     pl = torch.full_like(b, 7.0)   # the solve must overwrite what p holds
     sl = ctx.gmres(b, pl, rtol=1e-8, restart=10, maxit=500)
     torch.cuda.synchronize()
@@ -167,4 +172,6 @@ def test_lanes_equal_one_lane(dev, precision, n, nrhs, lanes):
     assert its == sl.iterations
     with pytest.raises(B.MrcmError):
         ctx.set_lanes(0)
+    with pytest.raises(B.MrcmError):
+        ctx.set_batch(9)
     ctx.close()
