@@ -194,6 +194,7 @@ def serve(args) -> int:
     0.8 of it; request latency from arrival to answer (setup included)."""
     from paper_2606_08883_amd import serving as S
 
+    # a set-up takes the host cores divided among the set-ups in progress
     B = S.gpu_solver(keep=False)
     warm = S.make_payload(S.Request(0, 128, 2.0, 999, 1999, 2, 0.0))
     S.Server(B, max_active=1).run([warm], realtime=False)

@@ -193,6 +193,12 @@ int mrcm_set_lanes(mrcm_ctx* ctx, int32_t lanes);
  * right-hand sides are in flight.  Results do not depend on it. */
 int mrcm_set_batch(mrcm_ctx* ctx, int32_t width);
 
+/* Host threads the calling thread's later mrcm_setup calls use for the
+ * host part of the set-up (0: OpenMP's default, all of them).  A server that
+ * sets up several contexts at once on different threads gives each a share
+ * of the cores instead of letting every set-up spread over all of them. */
+int mrcm_set_host_threads(int32_t threads);
+
 /* Right-hand side of the fine system (Section 3): b = f h^2 plus 2 K_c g on
  * every Dirichlet boundary face.  f_cell: device n values or NULL (zero
  * source); g_bc: device, the Dirichlet values of the W, E, S, N sides

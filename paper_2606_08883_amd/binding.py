@@ -23,6 +23,7 @@ _NAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "ESINGULAR", -4: "ENOCONV", -5: "EDEVI
 EXPORTED = ["mrcm_map_sizes", "mrcm_maps", "mrcm_setup", "mrcm_apply", "mrcm_apply_many",
             "op_apply", "gmres_solve", "mrcm_rhs", "mrcm_footprint", "mrcm_timing_enable",
             "mrcm_timing_read", "mrcm_query", "mrcm_set_allocator", "mrcm_set_lanes", "mrcm_set_batch",
+            "mrcm_set_host_threads",
             "mrcm_destroy",
             "mrcm_last_error"]
 QUERIES = {"setup_seconds": 0, "device_bytes": 1, "coarse_pivot": 2, "coarse_levels": 3,
@@ -88,6 +89,7 @@ def lib() -> ctypes.CDLL:
             "mrcm_rhs": ([P, P, P, dbl, P, P], i32),
             "mrcm_set_lanes": ([P, i32], i32),
             "mrcm_set_batch": ([P, i32], i32),
+            "mrcm_set_host_threads": ([i32], i32),
             "mrcm_footprint": ([pG, pP, i32], ctypes.c_size_t),
             "mrcm_timing_enable": ([P, i32], i32),
             "mrcm_timing_read": ([P, pd, pi64], i32),
@@ -163,6 +165,11 @@ def maps(cfg: Config) -> dict:
                            _i32(out["edges"]), _i32(out["dof_table"]), _i32(out["dof_offset"]),
                            _i32(out["row_table"])))
     return out
+
+
+def set_host_threads(threads: int) -> None:
+    """mrcm_set_host_threads: host threads of this thread's later set-ups."""
+    _check(lib().mrcm_set_host_threads(threads))
 
 
 def footprint(cfg: Config, nrhs: int = 1) -> int:

@@ -39,8 +39,12 @@ void hip_check(hipError_t e, const char* what) {
                       std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Host threads of the calling thread's set-ups (mrcm_set_host_threads; 0 =
+// OpenMP's default).
+thread_local int t_host_threads = 0;
+
 int host_threads() {
-  int t = omp_get_max_threads();
+  int t = t_host_threads > 0 ? t_host_threads : omp_get_max_threads();
   return t < 1 ? 1 : t;
 }
 
@@ -1192,6 +1196,15 @@ int gmres_solve(mrcm_ctx* c, const double* b, double* p, int32_t nrhs, double rt
     set_error(e.what());
     return e.code;
   }
+}
+
+int mrcm_set_host_threads(int32_t threads) {
+  if (threads < 0) {
+    set_error("invalid argument");
+    return MRCM_EINVAL;
+  }
+  t_host_threads = threads;
+  return MRCM_OK;
 }
 
 int mrcm_set_batch(mrcm_ctx* c, int32_t width) {

@@ -112,34 +112,63 @@ def footprint_of(req: Request, params: dict | None = None) -> int:
     return footprint(config_for(req.n, params), min(req.nrhs, LANES * WIDTH))
 
 
+def host_cores() -> int:
+    """Cores this process may use: OMP_NUM_THREADS when set, else all."""
+    import os
+    try:
+        return max(1, int(os.environ.get("OMP_NUM_THREADS", "")))
+    except ValueError:
+        return max(1, os.cpu_count() or 1)
+
+
 def gpu_solver(params: dict | None = None, rtol: float = 1e-8, restart: int = 10,
-               maxit: int = 500, keep: bool = True, device: int = 0):
+               maxit: int = 500, keep: bool = True, device: int = 0,
+               setup_threads: int | None = None):
     """Solve function of the library: set up the request's context on its
     own stream, solve its right-hand sides, copy the answer to the host and
-    release everything."""
+    release everything.  setup_threads: host threads of each set-up; None
+    (the default) divides the host cores among the set-ups in progress when
+    a set-up starts (all of them when it runs alone); 0 = all cores always."""
     import torch
 
-    from .binding import Context
+    from .binding import Context, set_host_threads
+
+    cores = host_cores()
+    lock = threading.Lock()
+    setups = [0]  # set-ups in progress
 
     def solve(req: Request) -> dict:
-        dev = torch.device("cuda", device)
-        stream = torch.cuda.Stream(device=dev)
-        with torch.cuda.stream(stream):
-            K = torch.tensor(req.K, dtype=torch.float64, device=dev)
-            B = torch.tensor(req.B, dtype=torch.float64, device=dev).contiguous()
-            t0 = time.perf_counter()
-            ctx = Context(config_for(req.n, params), K, stream=stream)
-            ctx.set_lanes(LANES)
-            ctx.set_batch(WIDTH)
-            stream.synchronize()
-            t1 = time.perf_counter()
-            P = torch.zeros_like(B)
-            st = ctx.gmres(B, P, rtol=rtol, restart=restart, maxit=maxit, stream=stream,
-                           raise_on_noconv=False)
-            stream.synchronize()
-            t2 = time.perf_counter()
-            p = P.cpu().numpy() if keep else None
-            ctx.close()
+        with lock:
+            setups[0] += 1
+            share = max(1, cores // setups[0])
+        set_host_threads(share if setup_threads is None else setup_threads)
+        in_setup = True
+        try:
+            dev = torch.device("cuda", device)
+            stream = torch.cuda.Stream(device=dev)
+            with torch.cuda.stream(stream):
+                K = torch.tensor(req.K, dtype=torch.float64, device=dev)
+                B = torch.tensor(req.B, dtype=torch.float64, device=dev).contiguous()
+                t0 = time.perf_counter()
+                ctx = Context(config_for(req.n, params), K, stream=stream)
+                ctx.set_lanes(LANES)
+                ctx.set_batch(WIDTH)
+                stream.synchronize()
+                t1 = time.perf_counter()
+                with lock:
+                    setups[0] -= 1
+                in_setup = False
+                P = torch.zeros_like(B)
+                st = ctx.gmres(B, P, rtol=rtol, restart=restart, maxit=maxit, stream=stream,
+                               raise_on_noconv=False)
+                stream.synchronize()
+                t2 = time.perf_counter()
+                p = P.cpu().numpy() if keep else None
+                ctx.close()
+        finally:
+            if in_setup:
+                with lock:
+                    setups[0] -= 1
         return dict(iterations=st.iterations, converged=st.converged,
                     final_relres=st.final_relres, setup_s=t1 - t0, solve_s=t2 - t1, p=p)
 

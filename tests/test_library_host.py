@@ -118,3 +118,12 @@ def test_host_setup_rejects_bad_permeability():
     K[5] = np.inf
     with pytest.raises(B.MrcmError):
         B.test_host_apply(cfg, K, np.zeros(256))
+
+
+def test_set_host_threads():
+    """mrcm_set_host_threads is per calling thread and rejects negative counts
+    (host only; no device is touched)."""
+    B.set_host_threads(2)
+    B.set_host_threads(0)
+    with pytest.raises(B.MrcmError):
+        B.set_host_threads(-1)
