@@ -283,7 +283,8 @@ void upload_boxes(mrcm_ctx* c, const std::vector<mrcm::BoxFactor>& F,
     mb = std::max(mb, b.bx());
   }
   if (mb > 64)
-    throw mrcm::Error(MRCM_EINVAL, "subdomains and smoothing patches must be at most 64 cells wide");
+    throw mrcm::Error(MRCM_EINVAL,
+                      "subdomains and smoothing patches must be at most 64 cells wide");
   if (mrcm::box_lds_bytes(mb, mc, sizeof(double), sizeof(T)) > 64 * 1024)
     throw mrcm::Error(MRCM_EINVAL, "subdomain or patch too large for the LDS of one workgroup");
   std::vector<T> hd((size_t)nd, T(0)), hc((size_t)ncp);
@@ -1159,7 +1160,8 @@ int gmres_solve(mrcm_ctx* c, const double* b, double* p, int32_t nrhs, double rt
       }
     };
     for (int l = 0; l < nl; ++l) {
-      for (int q = 0; q < w && next < nrhs; ++q) start(runs[l][q], c->lanes[l], c->lanes[l].slots[q]);
+      for (int q = 0; q < w && next < nrhs; ++q)
+        start(runs[l][q], c->lanes[l], c->lanes[l].slots[q]);
     }
     for (;;) {
       bool busy = false;
@@ -1209,7 +1211,8 @@ int mrcm_set_host_threads(int32_t threads) {
 
 int mrcm_set_batch(mrcm_ctx* c, int32_t width) {
   try {
-    if (!c || width < 1 || width > mrcm::kMaxRhs) throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+    if (!c || width < 1 || width > mrcm::kMaxRhs)
+      throw mrcm::Error(MRCM_EINVAL, "invalid argument");
     c->batch_width = width;
     return MRCM_OK;
   } catch (const mrcm::Error& e) {

@@ -116,8 +116,12 @@ __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 // a * b + c with one rounding, spelled out so that the one-RHS and the
 // multi-RHS kernels round every step the same way whatever the optimiser
 // would contract.
-__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmat(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+__device__ __forceinline__ double fmat(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
 
 // Four consecutive words of a factor block (16 bytes of FP32 or 32 bytes of
 // FP64), as native vectors the optimiser keeps in registers.
@@ -1755,15 +1759,15 @@ void launch_coarse_fwd_k(int k, const CChunk* chunks, int nchunks, const double*
     double* c = contrib + (long long)k0 * maxp * np;
     double* y = ybuf + (long long)k0 * np;
     const size_t shm = sizeof(double) * (size_t)w * (max_nf > 0 ? max_nf : 1);
+    const dim3 grid(nchunks), block(coarse_threads(nchunks));
     if (w == 1)
-      hipLaunchKernelGGL(k_coarse_fwd, dim3(nchunks), dim3(coarse_threads(nchunks)), shm, s, chunks, fwd, g,
-                         c, maxp, np, cdest, y);
+      hipLaunchKernelGGL(k_coarse_fwd, grid, block, shm, s, chunks, fwd, g, c, maxp, np, cdest, y);
     else if (w == 2)
-      hipLaunchKernelGGL(k_coarse_fwd_k<2>, dim3(nchunks), dim3(coarse_threads(nchunks)), shm, s, chunks, fwd,
-                         g, c, maxp, np, cdest, y);
+      hipLaunchKernelGGL(k_coarse_fwd_k<2>, grid, block, shm, s, chunks, fwd, g, c, maxp, np, cdest,
+                         y);
     else
-      hipLaunchKernelGGL(k_coarse_fwd_k<4>, dim3(nchunks), dim3(coarse_threads(nchunks)), shm, s, chunks, fwd,
-                         g, c, maxp, np, cdest, y);
+      hipLaunchKernelGGL(k_coarse_fwd_k<4>, grid, block, shm, s, chunks, fwd, g, c, maxp, np, cdest,
+                         y);
   }
 }
 
@@ -1777,15 +1781,13 @@ void launch_coarse_bwd_k(int k, const CChunk* chunks, int nchunks, const double*
     const double* y = ybuf + (long long)k0 * np;
     double* xk = x + (long long)k0 * nc;
     const size_t shm = sizeof(double) * (size_t)w * (max_nu > 0 ? max_nu : 1);
+    const dim3 grid(nchunks), block(coarse_threads(nchunks));
     if (w == 1)
-      hipLaunchKernelGGL(k_coarse_bwd, dim3(nchunks), dim3(coarse_threads(nchunks)), shm, s, chunks, bwd, idx,
-                         y, xk);
+      hipLaunchKernelGGL(k_coarse_bwd, grid, block, shm, s, chunks, bwd, idx, y, xk);
     else if (w == 2)
-      hipLaunchKernelGGL(k_coarse_bwd_k<2>, dim3(nchunks), dim3(coarse_threads(nchunks)), shm, s, chunks, bwd,
-                         idx, y, xk, np, nc);
+      hipLaunchKernelGGL(k_coarse_bwd_k<2>, grid, block, shm, s, chunks, bwd, idx, y, xk, np, nc);
     else
-      hipLaunchKernelGGL(k_coarse_bwd_k<4>, dim3(nchunks), dim3(coarse_threads(nchunks)), shm, s, chunks, bwd,
-                         idx, y, xk, np, nc);
+      hipLaunchKernelGGL(k_coarse_bwd_k<4>, grid, block, shm, s, chunks, bwd, idx, y, xk, np, nc);
   }
 }
 
@@ -1887,8 +1889,8 @@ void launch_update(double* p, const double* Z, const double* y, int k, long long
                    hipStream_t s) {
   // in slices of kMaxUpdate vectors: p is updated in the same order
   for (int i0 = 0; i0 < k; i0 += kMaxUpdate)
-    hipLaunchKernelGGL(k_update, dim3(grid_for(n)), dim3(kVecThreads), 0, s, p, Z + (long long)i0 * n,
-                       y + i0, k - i0 < kMaxUpdate ? k - i0 : kMaxUpdate, n);
+    hipLaunchKernelGGL(k_update, dim3(grid_for(n)), dim3(kVecThreads), 0, s, p,
+                       Z + (long long)i0 * n, y + i0, k - i0 < kMaxUpdate ? k - i0 : kMaxUpdate, n);
 }
 
 void launch_sumsq(const double* x, long long n, double* partials, int nb, hipStream_t s) {

@@ -70,7 +70,8 @@ int mrcm_test_host_apply(const mrcm_grid* grid, const mrcm_params* params, const
     auto gather = [&](const mrcm::Box& b, const double* v, std::vector<double>& x) {
       x.assign((size_t)b.bx() * b.by(), 0.0);
       for (int j = 0; j < b.by(); ++j)
-        for (int a = 0; a < b.bx(); ++a) x[(size_t)j * b.bx() + a] = v[(size_t)(b.y0 + j) * nx + b.x0 + a];
+        for (int a = 0; a < b.bx(); ++a)
+          x[(size_t)j * b.bx() + a] = v[(size_t)(b.y0 + j) * nx + b.x0 + a];
     };
     std::vector<double> x;
     for (int i = 0; i < M.m; ++i) {
@@ -78,7 +79,8 @@ int mrcm_test_host_apply(const mrcm_grid* grid, const mrcm_params* params, const
       gather(b, r, x);
       mrcm::box_solve(S.local[i], x.data());
       for (int j = 0; j < b.by(); ++j)
-        for (int a = 0; a < b.bx(); ++a) p[(size_t)(b.y0 + j) * nx + b.x0 + a] = x[(size_t)j * b.bx() + a];
+        for (int a = 0; a < b.bx(); ++a)
+          p[(size_t)(b.y0 + j) * nx + b.x0 + a] = x[(size_t)j * b.bx() + a];
       for (int k = M.dof_offset[i]; k < M.dof_offset[i + 1]; ++k) {
         const int side = M.dofs[k][1];
         const int len = mrcm::side_len(b, side);
