@@ -194,21 +194,24 @@ def serve(args) -> int:
     0.8 of it; request latency from arrival to answer (setup included)."""
     from paper_2606_08883_amd import serving as S
 
+    params = None if args.precision is None else dict(precision=args.precision)
+    prec = S.SERVE_PARAMS["precision"] if args.precision is None else args.precision
+    fp = (lambda r: S.footprint_of(r, params))
     # a set-up takes the host cores divided among the set-ups in progress
-    B = S.gpu_solver(keep=False)
+    B = S.gpu_solver(params, keep=False)
     warm = S.make_payload(S.Request(0, 128, 2.0, 999, 1999, 2, 0.0))
     S.Server(B, max_active=1).run([warm], realtime=False)
     burst = [S.make_payload(r) for r in S.make_requests(max(4, args.requests // 2), rate=None,
                                                           seed=5)]
     print(f"bench: serving burst of {len(burst)} requests", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    res = S.Server(B, max_active=args.max_active).run(burst, realtime=False)
+    res = S.Server(B, max_active=args.max_active, footprint=fp).run(burst, realtime=False)
     cap = len(res) / (time.perf_counter() - t0)
     rate = 0.8 * cap
     reqs = [S.make_payload(r) for r in S.make_requests(args.requests, rate=rate, seed=4)]
     print(f"bench: capacity {cap:.2f} requests/s; Poisson stream of {len(reqs)} at "
           f"{rate:.2f}/s", file=sys.stderr, flush=True)
-    server = S.Server(B, max_active=args.max_active)
+    server = S.Server(B, max_active=args.max_active, footprint=fp)
     t0 = time.perf_counter()
     res = server.run(reqs)
     wall = time.perf_counter() - t0
@@ -219,7 +222,7 @@ def serve(args) -> int:
     out = {"metric": "GMRES+MRCM-OS solves/s & cell-DOF/s at rel.res 1e-8; p50/p99 solve latency",
            "value": sm["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": len(reqs),
            "warmup": 1, "ms_per_step": 1e3 * wall / len(reqs), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": DTYPES[2], "data": "synthetic",
+           "scaling": "weak", "vs_baseline": None, "dtype": DTYPES[prec], "data": "synthetic",
            "config": {"workload": f"serving: {len(reqs)} requests, grids {sizes} (uniform), "
                                   f"log-normal sigma U[1,3] corr. 16, 8 injector/producer "
                                   f"pairs each, Poisson arrivals at 0.8 x closed-loop capacity "
