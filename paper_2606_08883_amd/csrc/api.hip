@@ -162,6 +162,19 @@ struct mrcm_ctx {
     device_bytes += bytes;
     return static_cast<X*>(p);
   }
+  // Free an allocation of this context before mrcm_destroy (set-up
+  // temporaries); the caller has drained the streams that used it.
+  void release(void* p, size_t count_bytes) {
+    auto it = std::find(allocs.begin(), allocs.end(), p);
+    if (it == allocs.end()) return;
+    allocs.erase(it);
+    const size_t bytes = ((count_bytes ? count_bytes : 1) + 255) / 256 * 256;
+    device_bytes -= bytes;
+    if (free_fn)
+      free_fn(p, alloc_stream);
+    else
+      (void)hipFree(p);
+  }
   template <typename X>
   X* upload(const std::vector<X>& v, hipStream_t s) {
     X* d = alloc<X>(v.size());
@@ -245,63 +258,6 @@ std::vector<T> narrow(const std::vector<double>& v) {
   std::vector<T> o(v.size());
   for (size_t i = 0; i < v.size(); ++i) o[i] = (T)v[i];
   return o;
-}
-
-// Store the symmetric n x n block D (row-major) by quads of rows
-// (quad_block_words, device.h): word (q n + r) 4 + i = D(4 q + i, r).
-template <typename T>
-void quad_block(const double* D, int n, T* out) {
-  for (int q = 0; q < (n + 3) / 4; ++q)
-    for (int r = 0; r < n; ++r)
-      for (int i = 0; i < 4; ++i) {
-        const int c = 4 * q + i;
-        out[((size_t)q * n + r) * 4 + i] = c < n ? (T)D[(size_t)c * n + r] : T(0);
-      }
-}
-
-// Upload a set of box factors in precision T: every box's D_j^-1 blocks,
-// by quads of rows, with a block stride rounded up to 16 bytes (every box starts
-// 16-byte aligned, so the blocks can be staged with vector loads), then its
-// couplings.
-template <typename T>
-void upload_boxes(mrcm_ctx* c, const std::vector<mrcm::BoxFactor>& F,
-                  const std::vector<mrcm::Box>& owned, BoxDesc** desc, void** dinv, void** coup,
-                  int* max_cells, int* max_bx, hipStream_t s) {
-  constexpr long long epv = 16 / sizeof(T);
-  std::vector<BoxDesc> d(F.size());
-  long long nd = 0, ncp = 0;
-  int mc = 0, mb = 0;
-  for (size_t i = 0; i < F.size(); ++i) {
-    const mrcm::Box& b = F[i].box;
-    const mrcm::Box& o = owned[i];
-    const int bs = (int)((mrcm::quad_block_words(b.bx()) + epv - 1) / epv * epv);
-    d[i] = BoxDesc{b.x0, b.y0, b.bx(), b.by(), F[i].pin, o.x0 - b.x0, o.y0 - b.y0, o.bx(), o.by(),
-                   bs, nd, ncp};
-    nd += (long long)bs * b.by();
-    ncp += (long long)F[i].coup.size();
-    mc = std::max(mc, b.bx() * b.by());
-    mb = std::max(mb, b.bx());
-  }
-  if (mb > 64)
-    throw mrcm::Error(MRCM_EINVAL,
-                      "subdomains and smoothing patches must be at most 64 cells wide");
-  if (mrcm::box_lds_bytes(mb, mc, sizeof(double), sizeof(T)) > 64 * 1024)
-    throw mrcm::Error(MRCM_EINVAL, "subdomain or patch too large for the LDS of one workgroup");
-  std::vector<T> hd((size_t)nd, T(0)), hc((size_t)ncp);
-  for (size_t i = 0; i < F.size(); ++i) {
-    const int n = d[i].bx;
-    const size_t bb = (size_t)n * n;
-    for (int j = 0; j < d[i].by; ++j)
-      quad_block(F[i].dinv.data() + j * bb, n, hd.data() + d[i].doff + (size_t)j * d[i].bs);
-    std::transform(F[i].coup.begin(), F[i].coup.end(), hc.begin() + d[i].coff,
-                   [](double v) { return (T)v; });
-  }
-  *desc = c->upload(d, s);
-  *dinv = c->upload(hd, s);
-  *coup = c->upload(hc, s);
-  *max_cells = mc;
-  *max_bx = mb;
-  hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
 // Upload the nested-dissection factor of the interface system and the data
@@ -592,25 +548,105 @@ void ensure_lanes(mrcm_ctx* c, int count) {
   }
 }
 
-// Upload factors in storage type X and allocate work vectors of type W.
+// Set-up of the boxes on the device (storage type X, arithmetic W): factor
+// the subdomain, patch and oversampled boxes, solve the oversampled problems
+// for phi and the MBF problems for the MBFs and their moments.  Fills the
+// context's box descriptors, factors, MBFs and work-vector copies of the
+// transmissibilities, and returns the moments (colU, colP; layout of
+// T.col_off) for the interface system.
 template <typename W, typename X>
-void setup_precision(mrcm_ctx* c, const mrcm::HostSetup& S, hipStream_t s) {
+void device_setup(mrcm_ctx* c, mrcm::HostSetup& S, const double* K_dev, hipStream_t s,
+                  std::vector<double>& colU, std::vector<double>& colP,
+                  std::vector<long long>& col_off) {
   const mrcm::Maps& M = S.maps;
-  upload_boxes<X>(c, S.local, M.boxes, &c->lbox, &c->ldinv, &c->lcoup, &c->max_cells_local,
-                  &c->max_bx_local, s);
-  if (S.sweeps > 0)
-    upload_boxes<X>(c, S.patch, M.boxes, &c->pbox, &c->pdinv, &c->pcoup, &c->max_cells_patch,
-                    &c->max_bx_patch, s);
-  c->patch_cells = 0;
-  for (const auto& f : S.patch) c->patch_cells += (long long)f.coup.size();
-  std::vector<X> mbf;
-  std::vector<long long> off;
-  for (int i = 0; i < M.m; ++i) {
-    off.push_back((long long)mbf.size());
-    for (double v : S.mbf[i]) mbf.push_back((X)v);
+  mrcm::DeviceTables T;
+  mrcm::device_tables(S, (int)(16 / sizeof(X)), T);
+  const int m = M.m, nb = M.degree + 1;
+  auto check_boxes = [&](int max_bx, int max_cells) {
+    if (max_bx > 64)
+      throw mrcm::Error(MRCM_EINVAL,
+                        "subdomains and smoothing patches must be at most 64 cells wide");
+    if (mrcm::box_lds_bytes(max_bx, max_cells, sizeof(W), sizeof(X)) > 64 * 1024)
+      throw mrcm::Error(MRCM_EINVAL, "subdomain or patch too large for the LDS of one workgroup");
+  };
+  auto descs = [&](const std::vector<mrcm::FactorJob>& jobs, const std::vector<mrcm::Box>& own,
+                   int* max_cells, int* max_bx) {
+    std::vector<mrcm::BoxDesc> d(jobs.size());
+    int mc = 0, mb = 0;
+    for (size_t i = 0; i < jobs.size(); ++i) {
+      const mrcm::FactorJob& j = jobs[i];
+      const mrcm::Box& o = own[i];
+      d[i] = mrcm::BoxDesc{j.x0, j.y0, j.bx, j.by, j.pin, o.x0 - j.x0, o.y0 - j.y0, o.bx(),
+                           o.by(), j.bs, j.doffS, j.coffS};
+      mc = std::max(mc, j.bx * j.by);
+      mb = std::max(mb, j.bx);
+    }
+    check_boxes(mb, mc);
+    *max_cells = mc;
+    *max_bx = mb;
+    return d;
+  };
+  c->lbox = c->upload(descs(T.local_jobs, M.boxes, &c->max_cells_local, &c->max_bx_local), s);
+  c->ldinv = c->alloc<X>(T.ldinv_len);
+  c->lcoup = c->alloc<X>(T.lcoup_len);
+  if (S.sweeps > 0) {
+    c->pbox = c->upload(descs(T.patch_jobs, M.boxes, &c->max_cells_patch, &c->max_bx_patch), s);
+    c->pdinv = c->alloc<X>(T.pdinv_len);
+    c->pcoup = c->alloc<X>(T.pcoup_len);
   }
-  c->mbf = c->upload(mbf, s);
-  c->mbf_off = c->upload(off, s);
+  if (T.max_over > 64) throw mrcm::Error(MRCM_EINVAL, "oversampled boxes must be at most 64 cells wide");
+  c->mbf = c->alloc<X>(T.mbf_off[m]);
+  c->mbf_off = c->upload(std::vector<long long>(T.mbf_off.begin(), T.mbf_off.end() - 1), s);
+  // set-up temporaries
+  std::vector<std::pair<void*, size_t>> temps;
+  auto temp_upload = [&](const auto& v) {
+    auto* d = c->upload(v, s);
+    temps.push_back({(void*)d, v.size() * sizeof(v[0])});
+    return d;
+  };
+  auto temp_alloc = [&](size_t count, auto* tag) {
+    using Y = std::remove_pointer_t<decltype(tag)>;
+    Y* d = c->alloc<Y>(count);
+    temps.push_back({(void*)d, count * sizeof(Y)});
+    return d;
+  };
+  double* buf = temp_alloc((size_t)T.buf_len, (double*)nullptr);
+  double* dU = temp_alloc((size_t)std::max(T.col_off[m], 1LL), (double*)nullptr);
+  double* dP = temp_alloc((size_t)std::max(T.col_off[m], 1LL), (double*)nullptr);
+  int* status = temp_upload(std::vector<int>{0});
+  const mrcm::FactorJob* lj = temp_upload(T.local_jobs);
+  const mrcm::FactorJob* oj = temp_upload(T.over_jobs);
+  const mrcm::SubJob* sj = temp_upload(T.subs);
+  const mrcm::OverRhs* rh = temp_upload(T.rhs.empty() ? std::vector<mrcm::OverRhs>(1) : T.rhs);
+  const mrcm::GamFace* gm = temp_upload(T.gam.empty() ? std::vector<mrcm::GamFace>(1) : T.gam);
+  const int* dside = temp_upload(T.dof_side.empty() ? std::vector<int>(1) : T.dof_side);
+  const int* dq = temp_upload(T.dof_q.empty() ? std::vector<int>(1) : T.dof_q);
+  const double aL = S.alpha * S.Lcells;
+  X* ld = static_cast<X*>(c->ldinv);
+  X* lcp = static_cast<X*>(c->lcoup);
+  mrcm::launch_factor_boxes<X>(lj, m, T.max_local, K_dev, c->tx, c->ty, c->nx, c->ny, aL, ld, lcp,
+                               buf, buf, status, s);
+  if (S.sweeps > 0) {
+    const mrcm::FactorJob* pj = temp_upload(T.patch_jobs);
+    mrcm::launch_factor_boxes<X>(pj, m, T.max_patch, K_dev, c->tx, c->ty, c->nx, c->ny, aL,
+                                 static_cast<X*>(c->pdinv), static_cast<X*>(c->pcoup), buf, buf,
+                                 status, s);
+  }
+  mrcm::launch_factor_boxes<X>(oj, m, T.max_over, K_dev, c->tx, c->ty, c->nx, c->ny, aL, ld, lcp,
+                               buf, buf, status, s);
+  mrcm::launch_over_phi(sj, m, rh, gm, dside, dq, M.oversample == 0 ? 1 : 0, buf, s);
+  mrcm::launch_mbf<X>(sj, m, gm, nb, buf, static_cast<X*>(c->mbf), dU, dP, s);
+  hip_check(hipGetLastError(), "set-up kernel launch");
+  colU.resize((size_t)T.col_off[m]);
+  colP.resize((size_t)T.col_off[m]);
+  int bad = 0;
+  if (T.col_off[m] > 0) {
+    hip_check(hipMemcpyAsync(colU.data(), dU, sizeof(double) * colU.size(), hipMemcpyDeviceToHost,
+                             s), "hipMemcpyAsync");
+    hip_check(hipMemcpyAsync(colP.data(), dP, sizeof(double) * colP.size(), hipMemcpyDeviceToHost,
+                             s), "hipMemcpyAsync");
+  }
+  hip_check(hipMemcpyAsync(&bad, status, sizeof(int), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
   if (sizeof(W) == sizeof(double)) {
     c->txT = c->tx;
     c->tyT = c->ty;
@@ -619,7 +655,11 @@ void setup_precision(mrcm_ctx* c, const mrcm::HostSetup& S, hipStream_t s) {
     c->tyT = c->upload(narrow<W>(S.ty), s);
   }
   c->tsize = sizeof(W);
+  c->patch_cells = T.pcoup_len;
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+  for (auto& t : temps) c->release(t.first, t.second);
+  if (bad) throw mrcm::Error(MRCM_ESINGULAR, "non-positive pivot in a local factorisation");
+  col_off = T.col_off;
 }
 
 void ensure_krylov(mrcm_ctx* c, mrcm_ctx::Lane& L, mrcm_ctx::Slot& S, int restart) {
@@ -789,8 +829,7 @@ int mrcm_setup(const mrcm_grid* grid, const mrcm_params* params, const double* K
               "hipMemcpyAsync K");
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     mrcm::HostSetup S;
-    mrcm::host_setup(S, *grid, *params, K.data(), host_threads());
-    mrcm::CoarseFactor CF = mrcm::coarse_factor(S.maps, S.Crp, S.Cci, S.Cv, host_threads());
+    mrcm::host_prepare(S, *grid, *params, K.data());
     c = new mrcm_ctx();
     {
       std::lock_guard<std::mutex> lock(g_alloc_mutex);
@@ -810,12 +849,18 @@ int mrcm_setup(const mrcm_grid* grid, const mrcm_params* params, const double* K
     c->tx = c->upload(S.tx, s);
     c->ty = c->upload(S.ty, s);
     c->d_bc = c->upload(std::vector<int>(grid->bc, grid->bc + 4), s);
+    // boxes on the device; the interface system from their moments on the
+    // host
+    std::vector<double> colU, colP;
+    std::vector<long long> col_off;
     if (c->precision == 1)
-      setup_precision<float, float>(c, S, s);
+      device_setup<float, float>(c, S, K_dev, s, colU, colP, col_off);
     else if (c->precision == 2)
-      setup_precision<double, float>(c, S, s);
+      device_setup<double, float>(c, S, K_dev, s, colU, colP, col_off);
     else
-      setup_precision<double, double>(c, S, s);
+      device_setup<double, double>(c, S, K_dev, s, colU, colP, col_off);
+    mrcm::assemble_coarse(S, colU.data(), colP.data(), col_off);
+    mrcm::CoarseFactor CF = mrcm::coarse_factor(S.maps, S.Crp, S.Cci, S.Cv, host_threads());
     std::vector<int> dof_side;
     for (const auto& d : S.maps.dofs) dof_side.push_back(d[1]);
     c->dof_off = c->upload(S.maps.dof_offset, s);

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "setup_jobs.h"
+
 namespace mrcm {
 
 // One cell box solved by a workgroup (a subdomain or a smoothing patch).
@@ -128,6 +130,23 @@ void launch_patch_k(int k, const BoxDesc* boxes, int m, int max_cells, int max_b
 template <typename T>
 void launch_finalize_k(int k, const T* const* p, long long n, int noflow, double* const* z,
                        double* partials, hipStream_t s);
+
+// ---- set-up on the device (FP64; one wave per box or subdomain) ------------
+// Factor the boxes of `jobs` (LDS: two maxn x maxn blocks); status[0] = 1
+// after a non-positive pivot.
+template <typename S>
+void launch_factor_boxes(const FactorJob* jobs, int njobs, int maxn, const double* K,
+                         const double* tx, const double* ty, int nx, int ny, double aL, S* dS,
+                         S* cS, double* d64, double* c64, int* status, hipStream_t s);
+// Oversampled problems and phi of every subdomain (buf: FP64 work buffer that
+// the SubJob offsets index).
+void launch_over_phi(const SubJob* subs, int m, const OverRhs* rhs, const GamFace* gam,
+                     const int* dof_side, const int* dof_q, int over0, double* buf,
+                     hipStream_t s);
+// MBFs of every subdomain into mbf (storage type) and their moments.
+template <typename S>
+void launch_mbf(const SubJob* subs, int m, const GamFace* gam, int nb, double* buf, S* mbf,
+                double* colU, double* colP, hipStream_t s);
 
 // ---- GMRES vector kernels (FP64) -------------------------------------------
 // r = b - A p (p may be NULL for p = 0); partials[block] = sum r^2

@@ -228,8 +228,7 @@ struct SubResult {
 
 }  // namespace
 
-void host_setup(HostSetup& S, const mrcm_grid& g, const mrcm_params& p, const double* K,
-                int nthreads) {
+void host_prepare(HostSetup& S, const mrcm_grid& g, const mrcm_params& p, const double* K) {
   S.maps = build_maps(g, p);
   const Maps& M = S.maps;
   S.nx = g.nx;
@@ -245,17 +244,219 @@ void host_setup(HostSetup& S, const mrcm_grid& g, const mrcm_params& p, const do
     if (!(S.K[c] > 0.0) || !std::isfinite(S.K[c]))
       throw Error(MRCM_EINVAL, "K must be finite and positive on every cell");
   face_transmissibilities(S);
-  const int m = M.m, nb = M.degree + 1, nc = M.nc();
-  S.local.resize(m);
-  S.patch.resize(S.sweeps > 0 ? m : 0);
-  S.mbf.resize(m);
-  std::vector<SubResult> sub(m);
-  // weight offsets per dof
+  const int m = M.m, nc = M.nc();
+  // coarse right-hand-side weights of the particular traces, per dof k =
+  // (i, side, q) over the faces of that side: wU = rho P_q(xi), wP = b wU
   S.wOff.assign(nc + 1, 0);
   for (int k = 0; k < nc; ++k)
     S.wOff[k + 1] = S.wOff[k] + side_len(M.boxes[M.dofs[k][0]], M.dofs[k][1]);
   S.wU.assign(S.wOff[nc], 0.0);
   S.wP.assign(S.wOff[nc], 0.0);
+  for (int i = 0; i < m; ++i)
+    for (int dof = M.dof_offset[i]; dof < M.dof_offset[i + 1]; ++dof) {
+      const int ks = M.dofs[dof][1], kq = M.dofs[dof][2];
+      const GammaSide gs = make_side(S, M.boxes[i], ks);
+      const int nfs = (int)gs.faces.size();
+      for (int j = 0; j < nfs; ++j) {
+        const double w = legendre(kq, xi_of(j, nfs));
+        S.wU[S.wOff[dof] + j] = gs.rho[j] * w;
+        S.wP[S.wOff[dof] + j] = gs.b[j] * gs.rho[j] * w;
+      }
+    }
+  // coarse rows: the dofs of the L and R sides each row combines
+  const int E = (int)M.edges.size();
+  S.rowL.assign(nc, -1);
+  S.rowR.assign(nc, -1);
+  S.rowKind.assign(nc, 0);
+  for (int e = 0; e < E; ++e) {
+    const int L = M.edges[e][0], R = M.edges[e][1], o = M.edges[e][2];
+    const int sL = o == 0 ? SE : SN, sR = o == 0 ? SW : SS;
+    const int nb = M.nbasis(M.edges[e][4]);
+    for (int kind = 0; kind < 2; ++kind)
+      for (int q = 0; q < nb; ++q) {
+        int r = M.row_offset[e] + kind * nb + q;
+        S.rowL[r] = M.dof_of(L, sL, q);
+        S.rowR[r] = M.dof_of(R, sR, q);
+        S.rowKind[r] = kind;
+      }
+  }
+}
+
+// Words of one row block in the quad layout of the apply kernels: ceil(n / 4)
+// quads of rows times n columns times 4.
+static long long quad_words(int n) { return (long long)((n + 3) / 4) * 4 * n; }
+
+void device_tables(const HostSetup& S, int epv, DeviceTables& T) {
+  const Maps& M = S.maps;
+  const int m = M.m, nb = M.degree + 1, nx = S.nx, ny = S.ny;
+  auto whole = [&](const Box& b) {
+    return S.noflow && b.x0 == 0 && b.y0 == 0 && b.x1 == nx && b.y1 == ny;
+  };
+  auto qstride = [&](const Box& b) {
+    const long long w = quad_words(b.bx());
+    return (int)((w + epv - 1) / epv * epv);
+  };
+  T = DeviceTables();
+  T.mbf_off.assign(m + 1, 0);
+  T.col_off.assign(m + 1, 0);
+  long long buf = 0;
+  for (int i = 0; i < m; ++i) {
+    const Box& bi = M.boxes[i];
+    const Box& oi = M.oboxes[i];
+    const int ni = M.dof_offset[i + 1] - M.dof_offset[i];
+    const int ns = (int)M.sides[i].size();
+    const long long lc = (long long)bi.bx() * bi.by(), oc = (long long)oi.bx() * oi.by();
+    T.max_local = std::max(T.max_local, bi.bx());
+    T.max_over = std::max(T.max_over, oi.bx());
+    // factor jobs: subdomain box (storage type for the apply, FP64 for the
+    // MBF solves), patch (storage type), oversampled box (FP64)
+    FactorJob lj{bi.x0, bi.y0, bi.bx(), bi.by(), 1, whole(bi) ? 1 : 0, qstride(bi), 0,
+                 T.ldinv_len, T.lcoup_len, buf, buf + lc * bi.bx()};
+    T.ldinv_len += (long long)lj.bs * bi.by();
+    T.lcoup_len += lc;
+    SubJob sj{};
+    sj.l64 = buf;
+    sj.lc64 = buf + lc * bi.bx();
+    buf += lc * bi.bx() + lc;
+    T.local_jobs.push_back(lj);
+    if (S.sweeps > 0) {
+      const Box& pb = M.pboxes[i];
+      T.max_patch = std::max(T.max_patch, pb.bx());
+      FactorJob pj{pb.x0, pb.y0, pb.bx(), pb.by(), 0, whole(pb) ? 1 : 0, qstride(pb), 0,
+                   T.pdinv_len, T.pcoup_len, -1, -1};
+      T.pdinv_len += (long long)pj.bs * pb.by();
+      T.pcoup_len += (long long)pb.bx() * pb.by();
+      T.patch_jobs.push_back(pj);
+    }
+    FactorJob oj{oi.x0, oi.y0, oi.bx(), oi.by(), 1, whole(oi) ? 1 : 0, 0, 0, -1, -1, buf,
+                 buf + oc * oi.bx()};
+    sj.o64 = buf;
+    sj.oc64 = buf + oc * oi.bx();
+    buf += oc * oi.bx() + oc;
+    T.over_jobs.push_back(oj);
+    // per-subdomain work: scratch, phi, MBF and moment offsets
+    sj.lbx = bi.bx();
+    sj.lby = bi.by();
+    sj.lpin = lj.pin;
+    sj.obx = oi.bx();
+    sj.oby = oi.by();
+    sj.opin = oj.pin;
+    sj.ni = ni;
+    sj.nsides = ns;
+    sj.dof0 = M.dof_offset[i];
+    sj.lscr = buf;
+    buf += ni * lc;
+    sj.oscr = buf;
+    buf += ni * oc;
+    // Robin data of the oversampled problems: P_q on side ks of the
+    // oversampled box, times the face conductance
+    sj.rhs0 = (int)T.rhs.size();
+    for (int k = 0; k < ni; ++k) {
+      const int dof = M.dof_offset[i] + k;
+      const int ks = M.dofs[dof][1], kq = M.dofs[dof][2];
+      const std::vector<Face> fs = side_faces(oi, ks, nx);
+      const int nf = (int)fs.size();
+      for (int j = 0; j < nf; ++j) {
+        const Face& f = fs[j];
+        const double t = f.kind == 0 ? txv(S, f.row, f.col) : tyv(S, f.row, f.col);
+        const double rho = robin_rho(S, S.K[f.inside], t);
+        T.rhs.push_back(OverRhs{k, loc_of(oi, f.inside, nx), rho * legendre(kq, xi_of(j, nf))});
+      }
+    }
+    sj.rhs1 = (int)T.rhs.size();
+    // faces of Gamma_i, side by side in the order of M.sides[i]
+    sj.gam0 = (int)T.gam.size();
+    for (int si = 0; si < ns; ++si) {
+      const GammaSide gs = make_side(S, bi, M.sides[i][si]);
+      const int nfs = (int)gs.faces.size();
+      for (int j = 0; j < nfs; ++j) {
+        const Face& f = gs.faces[j];
+        GamFace g{};
+        g.ocin = loc_of(oi, f.inside, nx);
+        g.ocout = M.oversample == 0 ? -1 : loc_of(oi, f.outside, nx);
+        g.lcin = loc_of(bi, f.inside, nx);
+        g.si = si;
+        g.side = gs.side;
+        g.j = j;
+        g.nfs = nfs;
+        g.rho = gs.rho[j];
+        g.b = gs.b[j];
+        g.t = gs.t[j];
+        g.Kin = gs.Kin[j];
+        g.Kout = gs.Kout[j];
+        T.gam.push_back(g);
+      }
+    }
+    sj.gam1 = (int)T.gam.size();
+    sj.phi = buf;
+    buf += (long long)ni * (sj.gam1 - sj.gam0);
+    T.mbf_off[i + 1] = T.mbf_off[i] + ni * lc;
+    T.col_off[i + 1] = T.col_off[i] + (long long)ni * ns * nb;
+    sj.mbf = T.mbf_off[i];
+    sj.col = T.col_off[i];
+    T.subs.push_back(sj);
+  }
+  T.buf_len = buf;
+  for (const auto& d : M.dofs) {
+    T.dof_side.push_back(d[1]);
+    T.dof_q.push_back(d[2]);
+  }
+}
+
+void assemble_coarse(HostSetup& S, const double* colU, const double* colP,
+                     const std::vector<long long>& col_off) {
+  const Maps& M = S.maps;
+  const int m = M.m, nc = M.nc(), nbm = M.degree + 1;
+  const int E = (int)M.edges.size();
+  std::vector<std::map<int, double>> rowsC(nc);
+  for (int i = 0; i < m; ++i) {
+    const int Ni = M.dof_offset[i + 1] - M.dof_offset[i];
+    const int ns = (int)M.sides[i].size();
+    for (int k = 0; k < Ni; ++k) {
+      const int col = M.dof_offset[i] + k;
+      for (int si = 0; si < ns; ++si) {
+        bool isL;
+        const int e = edge_across(M, i, M.sides[i][si], isL);
+        const double sign = isL ? 1.0 : -1.0;
+        const int nb = M.nbasis(M.edges[e][4]);
+        const long long base = col_off[i] + ((long long)k * ns + si) * nbm;
+        for (int q = 0; q < nb; ++q) {
+          rowsC[M.row_offset[e] + q][col] += colU[base + q];
+          rowsC[M.row_offset[e] + nb + q][col] += sign * colP[base + q];
+        }
+      }
+    }
+  }
+  S.pin_row = -1;
+  S.pin_dof = -1;
+  if (S.noflow && E > 0) {
+    const int L0 = M.edges[0][0], o0 = M.edges[0][2];
+    S.pin_row = M.row_offset[0];
+    S.pin_dof = M.dof_of(L0, o0 == 0 ? SE : SN, 0);
+    rowsC[S.pin_row].clear();
+    rowsC[S.pin_row][S.pin_dof] = 1.0;
+  }
+  S.Crp.assign(nc + 1, 0);
+  S.Cci.clear();
+  S.Cv.clear();
+  for (int r = 0; r < nc; ++r) {
+    for (const auto& kv : rowsC[r]) {
+      S.Cci.push_back(kv.first);
+      S.Cv.push_back(kv.second);
+    }
+    S.Crp[r + 1] = (int)S.Cci.size();
+  }
+}
+
+void host_setup(HostSetup& S, const mrcm_grid& g, const mrcm_params& p, const double* K,
+                int nthreads) {
+  host_prepare(S, g, p, K);
+  const Maps& M = S.maps;
+  const int m = M.m, nb = M.degree + 1;
+  S.local.resize(m);
+  S.patch.resize(S.sweeps > 0 ? m : 0);
+  S.mbf.resize(m);
+  std::vector<SubResult> sub(m);
 
   int err_code = 0;
   std::string err_msg;
@@ -327,19 +528,6 @@ void host_setup(HostSetup& S, const mrcm_grid& g, const mrcm_params& p, const do
           }
         }
       }
-      // coarse right-hand-side weights of the particular traces
-      for (int k = 0; k < Ni; ++k) {
-        const int dof = M.dof_offset[i] + k;
-        const int ks = M.dofs[dof][1], kq = M.dofs[dof][2];
-        size_t si = 0;
-        while (gam[si].side != ks) ++si;
-        const int nfs = (int)gam[si].faces.size();
-        for (int j = 0; j < nfs; ++j) {
-          double w = legendre(kq, xi_of(j, nfs));
-          S.wU[S.wOff[dof] + j] = gam[si].rho[j] * w;
-          S.wP[S.wOff[dof] + j] = gam[si].b[j] * gam[si].rho[j] * w;
-        }
-      }
     } catch (const Error& e) {
 #pragma omp critical
       {
@@ -351,61 +539,22 @@ void host_setup(HostSetup& S, const mrcm_grid& g, const mrcm_params& p, const do
     }
   }
   if (err_code) throw Error(err_code, err_msg);
-
-  // coarse rows: the dofs of the L and R sides each row combines
-  const int E = (int)M.edges.size();
-  S.rowL.assign(nc, -1);
-  S.rowR.assign(nc, -1);
-  S.rowKind.assign(nc, 0);
-  for (int e = 0; e < E; ++e) {
-    const int L = M.edges[e][0], R = M.edges[e][1], o = M.edges[e][2];
-    const int sL = o == 0 ? SE : SN, sR = o == 0 ? SW : SS;
-    const int nb = M.nbasis(M.edges[e][4]);
-    for (int kind = 0; kind < 2; ++kind)
-      for (int q = 0; q < nb; ++q) {
-        int r = M.row_offset[e] + kind * nb + q;
-        S.rowL[r] = M.dof_of(L, sL, q);
-        S.rowR[r] = M.dof_of(R, sR, q);
-        S.rowKind[r] = kind;
-      }
-  }
-  // assemble C
-  std::vector<std::map<int, double>> rowsC(nc);
+  std::vector<long long> col_off(m + 1, 0);
+  for (int i = 0; i < m; ++i)
+    col_off[i + 1] = col_off[i] + (long long)(M.dof_offset[i + 1] - M.dof_offset[i]) *
+                                      (long long)M.sides[i].size() * nb;
+  std::vector<double> cu((size_t)col_off[m]), cp((size_t)col_off[m]);
   for (int i = 0; i < m; ++i) {
-    const int Ni = M.dof_offset[i + 1] - M.dof_offset[i];
-    for (int k = 0; k < Ni; ++k) {
-      const int col = M.dof_offset[i] + k;
-      for (size_t si = 0; si < M.sides[i].size(); ++si) {
-        bool isL;
-        const int e = edge_across(M, i, M.sides[i][si], isL);
-        const double sign = isL ? 1.0 : -1.0;
-        const int nb = M.nbasis(M.edges[e][4]);
+    const int ns = (int)M.sides[i].size();
+    for (size_t k = 0; k < sub[i].colU.size(); ++k)
+      for (int si = 0; si < ns; ++si)
         for (int q = 0; q < nb; ++q) {
-          rowsC[M.row_offset[e] + q][col] += sub[i].colU[k][si][q];
-          rowsC[M.row_offset[e] + nb + q][col] += sign * sub[i].colP[k][si][q];
+          const size_t at = (size_t)col_off[i] + ((size_t)k * ns + si) * nb + q;
+          cu[at] = sub[i].colU[k][si][q];
+          cp[at] = sub[i].colP[k][si][q];
         }
-      }
-    }
   }
-  S.pin_row = -1;
-  S.pin_dof = -1;
-  if (S.noflow && E > 0) {
-    const int L0 = M.edges[0][0], o0 = M.edges[0][2];
-    S.pin_row = M.row_offset[0];
-    S.pin_dof = M.dof_of(L0, o0 == 0 ? SE : SN, 0);
-    rowsC[S.pin_row].clear();
-    rowsC[S.pin_row][S.pin_dof] = 1.0;
-  }
-  S.Crp.assign(nc + 1, 0);
-  S.Cci.clear();
-  S.Cv.clear();
-  for (int r = 0; r < nc; ++r) {
-    for (const auto& kv : rowsC[r]) {
-      S.Cci.push_back(kv.first);
-      S.Cv.push_back(kv.second);
-    }
-    S.Crp[r + 1] = (int)S.Cci.size();
-  }
+  assemble_coarse(S, cu.data(), cp.data(), col_off);
 }
 
 }  // namespace mrcm

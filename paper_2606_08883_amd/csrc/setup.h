@@ -4,6 +4,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "setup_jobs.h"
 
 namespace mrcm {
 
@@ -46,6 +47,33 @@ struct HostSetup {
   std::vector<int> Crp, Cci;
   std::vector<double> Cv;
 };
+
+// Work lists of the set-up on the device (built on the host from the maps,
+// transmissibilities and K; O(perimeter) per subdomain).  Offsets: FP64 work
+// buffer `buf` (factors and couplings of subdomain and oversampled boxes,
+// scratch vectors, phi), storage-type factor arrays (local: doffS/coffS of
+// local_jobs; patch: of patch_jobs), MBF array and moment array.
+struct DeviceTables {
+  std::vector<FactorJob> local_jobs, patch_jobs, over_jobs;
+  std::vector<SubJob> subs;
+  std::vector<OverRhs> rhs;
+  std::vector<GamFace> gam;
+  std::vector<int> dof_side, dof_q;
+  std::vector<long long> mbf_off, col_off;  // m + 1 entries
+  long long buf_len = 0, ldinv_len = 0, lcoup_len = 0, pdinv_len = 0, pcoup_len = 0;
+  int max_local = 0, max_patch = 0, max_over = 0;  // widest box of each kind
+};
+// epv: storage-type words per 16 bytes (4 for FP32, 2 for FP64).
+void device_tables(const HostSetup& S, int epv, DeviceTables& T);
+
+// Everything of the set-up but the box numerics: maps, transmissibilities,
+// the right-hand-side weights and the row maps of the interface system.
+void host_prepare(HostSetup& S, const mrcm_grid& g, const mrcm_params& p, const double* K);
+// The interface system C from the moments of the MBFs: colU / colP of
+// subdomain i, dof k, side index si, mode q at col_off[i] + (k * nsides_i +
+// si) * (degree + 1) + q.
+void assemble_coarse(HostSetup& S, const double* colU, const double* colP,
+                     const std::vector<long long>& col_off);
 
 void face_transmissibilities(HostSetup& S);
 BoxFactor factor_box(const HostSetup& S, const Box& b, bool robin);

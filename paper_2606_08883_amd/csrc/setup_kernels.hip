@@ -1,0 +1,311 @@
+// HIP kernels of the set-up of T (Section 2.1), FP64, one wave per box or
+// subdomain:
+//  - k_factor_boxes: block LDL^T factorisation of a cell box by cell rows
+//    with explicit inverses of the row blocks (Gauss-Jordan in LDS);
+//  - k_over_phi: the oversampled Robin problems with Legendre data on each
+//    side of the oversampled box, and the informed multiplier functions phi
+//    on the faces of Gamma_i;
+//  - k_mbf: the multiscale basis functions (local Robin problems with the
+//    phi data) and their flux and pressure moments on Gamma_i (the columns
+//    of the interface system).
+#include "device.h"
+#include "setup_jobs.h"
+
+namespace mrcm {
+
+namespace {
+
+__device__ __forceinline__ void wsync() { __builtin_amdgcn_wave_barrier(); }
+
+// Stores of this work-item complete before its later loads, and the wave's
+// stores are visible to the wave (workgroup scope: waits only).
+__device__ __forceinline__ void wfence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+
+// Robin conductance of a face leaving a cell box: 1 / (1 / (2 K_c) + b_f),
+// b_f = alpha L / t_f.
+__device__ __forceinline__ double robin(double Kc, double t, double aL) {
+  return 1.0 / (1.0 / (2.0 * Kc) + aL / t);
+}
+
+// Legendre polynomial P_q at xi (three-term recurrence) and the face
+// parameter xi_j = (2 j + 1) / n - 1.
+__device__ __forceinline__ double legendre_d(int q, double xi) {
+  double pm = 1.0, p = xi;
+  if (q == 0) return 1.0;
+  for (int k = 1; k < q; ++k) {
+    const double pn = ((2.0 * k + 1.0) * xi * p - k * pm) / (k + 1.0);
+    pm = p;
+    p = pn;
+  }
+  return p;
+}
+__device__ __forceinline__ double xi_d(int j, int n) { return (2.0 * j + 1.0) / n - 1.0; }
+
+// Block LDL^T factor of a box with cell rows as blocks (the form the apply
+// kernels use): D_0 = A_0, D_j = A_j - T_j D_{j-1}^-1 T_j, stored as D_j^-1.
+// A_j is the tridiagonal matrix of row j (Robin conductances on the box's
+// faces inside the domain when robin, else the principal submatrix of A),
+// T_j the vertical transmissibilities between rows j - 1 and j.  The inverse
+// of each row block is taken in place by Gauss-Jordan elimination (the
+// blocks are symmetric positive definite, so no pivoting); a non-positive
+// pivot sets status[0] = 1.  LDS: two blocks and two vectors of maxn.
+template <typename S>
+__global__ void __launch_bounds__(64)
+    k_factor_boxes(const FactorJob* __restrict__ jobs, int maxn, const double* __restrict__ K,
+                   const double* __restrict__ tx, const double* __restrict__ ty, int nx, int ny,
+                   double aL, S* __restrict__ dS, S* __restrict__ cS, double* __restrict__ d64,
+                   double* __restrict__ c64, int* __restrict__ status) {
+  extern __shared__ double sm[];
+  const FactorJob J = jobs[blockIdx.x];
+  const int n = J.bx, lane = threadIdx.x;
+  double* D = sm;
+  double* P = sm + (long long)maxn * maxn;
+  double* C = sm + 2LL * maxn * maxn;
+  double* T = C + maxn;
+  for (int j = 0; j < J.by; ++j) {
+    const int y = J.y0 + j;
+    for (int e = lane; e < n * n; e += 64) D[e] = 0.0;
+    wsync();
+    for (int a = lane; a < n; a += 64) {
+      const int x = J.x0 + a;
+      const long long c = (long long)y * nx + x;
+      const long long fx = (long long)y * (nx + 1) + x;
+      const double Kc = K[c];
+      double tW = tx[fx], tE = tx[fx + 1], tS = ty[c], tN = ty[c + nx];
+      if (J.robin) {
+        if (a == 0 && x > 0) tW = robin(Kc, tW, aL);
+        if (a == n - 1 && x + 1 < nx) tE = robin(Kc, tE, aL);
+        if (j == 0 && y > 0) tS = robin(Kc, tS, aL);
+        if (j == J.by - 1 && y + 1 < ny) tN = robin(Kc, tN, aL);
+      }
+      D[a * n + a] = tW + tE + tS + tN;
+      if (a > 0) {
+        D[a * n + a - 1] = -tx[fx];
+        D[(a - 1) * n + a] = -tx[fx];
+      }
+      double tc = j > 0 ? ty[c] : 0.0;
+      if (J.pin && j == 1 && a == 0) tc = 0.0;
+      T[a] = tc;
+      if (J.coffS >= 0) cS[J.coffS + (long long)j * n + a] = (S)tc;
+      if (J.c64 >= 0) c64[J.c64 + (long long)j * n + a] = tc;
+    }
+    wsync();
+    if (J.pin && j == 0) {
+      for (int a = lane; a < n; a += 64) {
+        D[a] = 0.0;
+        D[a * n] = 0.0;
+      }
+      wsync();
+      if (lane == 0) D[0] = 1.0;
+      wsync();
+    }
+    if (j > 0) {
+      for (int e = lane; e < n * n; e += 64) {
+        const int a = e / n, b = e - a * n;
+        D[e] -= T[a] * P[e] * T[b];
+      }
+      wsync();
+    }
+    for (int k = 0; k < n; ++k) {
+      const double p = D[k * n + k];
+      if (!(p > 0.0) || !isfinite(p)) {  // the same value in every lane
+        if (lane == 0) status[0] = 1;
+        return;
+      }
+      for (int i = lane; i < n; i += 64) C[i] = D[i * n + k];
+      wsync();
+      const double inv = 1.0 / p;
+      for (int b = lane; b < n; b += 64) D[k * n + b] = b == k ? inv : D[k * n + b] * inv;
+      wsync();
+      for (int e = lane; e < n * n; e += 64) {
+        const int i = e / n, b = e - i * n;
+        if (i != k) D[e] = b == k ? -C[i] * inv : D[e] - C[i] * D[k * n + b];
+      }
+      wsync();
+    }
+    if (J.d64 >= 0)
+      for (int e = lane; e < n * n; e += 64) d64[J.d64 + (long long)j * n * n + e] = D[e];
+    if (J.doffS >= 0) {
+      // quad layout: word (q n + r) 4 + i holds D(4 q + i, r), zero past the block
+      const int nq = (n + 3) >> 2;
+      for (int w = lane; w < J.bs; w += 64) {
+        const int q = w / (4 * n), r = (w >> 2) % n, row = 4 * q + (w & 3);
+        dS[J.doffS + (long long)j * J.bs + w] = (q < nq && row < n) ? (S)D[row * n + r] : S(0);
+      }
+    }
+    double* t = P;
+    P = D;
+    D = t;
+  }
+}
+
+// x = A_box^-1 x for one box with its FP64 factor (row-major inverse blocks
+// and couplings), lane r owning column r; ys is an LDS vector of 64.
+__device__ void box_solve64(double* x, int bx, int by, const double* __restrict__ Dinv,
+                            const double* __restrict__ coup, int pin, int lane, double* ys) {
+  const bool act = lane < bx;
+  if (pin && lane == 0) x[0] = 0.0;
+  wfence();
+  for (int j = 0; j < by; ++j) {
+    if (act)
+      ys[lane] = x[(long long)j * bx + lane] +
+                 (j > 0 ? coup[(long long)j * bx + lane] * x[(long long)(j - 1) * bx + lane] : 0.0);
+    wsync();
+    if (act) {
+      const double* Di = Dinv + (long long)j * bx * bx + (long long)lane * bx;
+      double s = 0.0;
+      for (int c = 0; c < bx; ++c) s += Di[c] * ys[c];
+      x[(long long)j * bx + lane] = s;
+    }
+    wsync();
+  }
+  for (int j = by - 2; j >= 0; --j) {
+    if (act) ys[lane] = coup[(long long)(j + 1) * bx + lane] * x[(long long)(j + 1) * bx + lane];
+    wsync();
+    if (act) {
+      const double* Di = Dinv + (long long)j * bx * bx + (long long)lane * bx;
+      double s = 0.0;
+      for (int c = 0; c < bx; ++c) s += Di[c] * ys[c];
+      x[(long long)j * bx + lane] += s;
+    }
+    wsync();
+  }
+  wfence();
+}
+
+// Oversampled problems of one subdomain (one right-hand side per local dof:
+// its Legendre function as Robin data on its side of the oversampled box)
+// and the informed functions phi on the faces of Gamma_i:
+//   phi = pi - b U, with U, pi the flux and pressure of the oversampled
+//   solution across the face (from the cells on both sides, or from the
+//   Robin data when the oversampled box is the subdomain box).
+__global__ void __launch_bounds__(64)
+    k_over_phi(const SubJob* __restrict__ subs, const OverRhs* __restrict__ rhs,
+               const GamFace* __restrict__ gam, const int* __restrict__ dof_side,
+               const int* __restrict__ dof_q, int over0, double* __restrict__ buf) {
+  __shared__ double ys[64];
+  const SubJob J = subs[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int ncell = J.obx * J.oby;
+  double* X = buf + J.oscr;
+  for (long long e = lane; e < (long long)J.ni * ncell; e += 64) X[e] = 0.0;
+  wfence();
+  for (int e = J.rhs0 + lane; e < J.rhs1; e += 64) {
+    const OverRhs R = rhs[e];
+    X[(long long)R.k * ncell + R.cell] += R.val;
+  }
+  wfence();
+  for (int k = 0; k < J.ni; ++k)
+    box_solve64(X + (long long)k * ncell, J.obx, J.oby, buf + J.o64, buf + J.oc64, J.opin, lane,
+                ys);
+  const int ng = J.gam1 - J.gam0;
+  for (int e = lane; e < J.ni * ng; e += 64) {
+    const int k = e / ng, f = e - k * ng;
+    const GamFace G = gam[J.gam0 + f];
+    const double pc = X[(long long)k * ncell + G.ocin];
+    double U, pi;
+    if (over0) {
+      const int dk = J.dof0 + k;
+      const double lam = G.side == dof_side[dk] ? legendre_d(dof_q[dk], xi_d(G.j, G.nfs)) : 0.0;
+      U = G.rho * (pc - lam);
+      pi = lam + G.b * U;
+    } else {
+      const double pn = X[(long long)k * ncell + G.ocout];
+      U = G.t * (pc - pn);
+      pi = (G.Kin * pc + G.Kout * pn) / (G.Kin + G.Kout);
+    }
+    buf[J.phi + (long long)k * ng + f] = pi - G.b * U;
+  }
+}
+
+// Multiscale basis functions of one subdomain: p_k = A_i^-1 (sum over the
+// faces of Gamma_i of rho phi_k at the inside cell), stored as the MBF
+// columns (storage type), and their moments on every side si and mode q:
+//   colU = sum_j P_q(xi_j) U_j,  colP = sum_j P_q(xi_j) pi_j,
+//   U = rho (p - phi), pi = phi + b U.
+template <typename S>
+__global__ void __launch_bounds__(64)
+    k_mbf(const SubJob* __restrict__ subs, const GamFace* __restrict__ gam, int nb,
+          double* __restrict__ buf, S* __restrict__ mbf, double* __restrict__ colU,
+          double* __restrict__ colP) {
+  __shared__ double ys[64];
+  const SubJob J = subs[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int ncell = J.lbx * J.lby, ng = J.gam1 - J.gam0;
+  double* X = buf + J.lscr;
+  for (long long e = lane; e < (long long)J.ni * ncell; e += 64) X[e] = 0.0;
+  wfence();
+  // faces in order per right-hand side (a corner cell has two faces)
+  for (int k = lane; k < J.ni; k += 64)
+    for (int f = 0; f < ng; ++f) {
+      const GamFace G = gam[J.gam0 + f];
+      X[(long long)k * ncell + G.lcin] += G.rho * buf[J.phi + (long long)k * ng + f];
+    }
+  wfence();
+  for (int k = 0; k < J.ni; ++k)
+    box_solve64(X + (long long)k * ncell, J.lbx, J.lby, buf + J.l64, buf + J.lc64, J.lpin, lane,
+                ys);
+  for (long long e = lane; e < (long long)J.ni * ncell; e += 64) mbf[J.mbf + e] = (S)X[e];
+  const int nt = J.ni * J.nsides * nb;
+  for (int e = lane; e < nt; e += 64) {
+    const int k = e / (J.nsides * nb), rem = e - k * (J.nsides * nb);
+    const int si = rem / nb, q = rem - si * nb;
+    double su = 0.0, sp = 0.0;
+    for (int f = 0; f < ng; ++f) {
+      const GamFace G = gam[J.gam0 + f];
+      if (G.si != si || q >= (nb < G.nfs ? nb : G.nfs)) continue;
+      const double pc = X[(long long)k * ncell + G.lcin];
+      const double phi = buf[J.phi + (long long)k * ng + f];
+      const double U = G.rho * (pc - phi);
+      const double pi = phi + G.b * U;
+      const double w = legendre_d(q, xi_d(G.j, G.nfs));
+      su += w * U;
+      sp += w * pi;
+    }
+    colU[J.col + e] = su;
+    colP[J.col + e] = sp;
+  }
+}
+
+}  // namespace
+
+template <typename S>
+void launch_factor_boxes(const FactorJob* jobs, int njobs, int maxn, const double* K,
+                         const double* tx, const double* ty, int nx, int ny, double aL, S* dS,
+                         S* cS, double* d64, double* c64, int* status, hipStream_t s) {
+  if (njobs <= 0) return;
+  const size_t shm = sizeof(double) * (2 * (size_t)maxn * maxn + 2 * (size_t)maxn);
+  if (shm > 64 * 1024)  // boxes wider than 62 cells: ask for the larger LDS of gfx950
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_factor_boxes<S>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL(k_factor_boxes<S>, dim3(njobs), dim3(64), shm, s, jobs, maxn, K, tx, ty, nx,
+                     ny, aL, dS, cS, d64, c64, status);
+}
+
+void launch_over_phi(const SubJob* subs, int m, const OverRhs* rhs, const GamFace* gam,
+                     const int* dof_side, const int* dof_q, int over0, double* buf,
+                     hipStream_t s) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_over_phi, dim3(m), dim3(64), 0, s, subs, rhs, gam, dof_side, dof_q, over0,
+                     buf);
+}
+
+template <typename S>
+void launch_mbf(const SubJob* subs, int m, const GamFace* gam, int nb, double* buf, S* mbf,
+                double* colU, double* colP, hipStream_t s) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_mbf<S>, dim3(m), dim3(64), 0, s, subs, gam, nb, buf, mbf, colU, colP);
+}
+
+template void launch_factor_boxes<float>(const FactorJob*, int, int, const double*, const double*,
+                                         const double*, int, int, double, float*, float*, double*,
+                                         double*, int*, hipStream_t);
+template void launch_factor_boxes<double>(const FactorJob*, int, int, const double*,
+                                          const double*, const double*, int, int, double,
+                                          double*, double*, double*, double*, int*, hipStream_t);
+template void launch_mbf<float>(const SubJob*, int, const GamFace*, int, double*, float*, double*,
+                                double*, hipStream_t);
+template void launch_mbf<double>(const SubJob*, int, const GamFace*, int, double*, double*,
+                                 double*, double*, hipStream_t);
+
+}  // namespace mrcm

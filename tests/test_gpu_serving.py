@@ -110,16 +110,20 @@ def test_caller_allocator(dev):
     ref_ctx.apply(r, z0)
     torch.cuda.synchronize()
     ref_ctx.close()
-    calls = {"alloc": 0, "free": 0, "bytes": 0}
+    calls = {"alloc": 0, "free": 0, "live": 0}
+    sizes = {}
     ta, tf = B.torch_allocator(0)
 
     def alloc(nbytes, stream):
         calls["alloc"] += 1
-        calls["bytes"] += nbytes
-        return ta(nbytes, stream)
+        calls["live"] += nbytes
+        ptr = ta(nbytes, stream)
+        sizes[ptr] = nbytes
+        return ptr
 
     def release(ptr, stream):
         calls["free"] += 1
+        calls["live"] -= sizes.pop(ptr)
         tf(ptr, stream)
 
     B.set_allocator(alloc, release)
@@ -129,12 +133,13 @@ def test_caller_allocator(dev):
         ctx.apply(r, z1)
         torch.cuda.synchronize()
         held = ctx.query("device_bytes")
+        live = calls["live"]   # set-up temporaries are already released
         ctx.close()
     finally:
         B.set_allocator(None, None)
     print(f"  allocator calls {calls}, context bytes {held:.0f}", flush=True)
-    assert calls["alloc"] > 0 and calls["alloc"] == calls["free"]
-    assert calls["bytes"] == held
+    assert calls["alloc"] > 0 and calls["alloc"] == calls["free"] and calls["live"] == 0
+    assert live == held
     assert torch.equal(z0, z1)
 
 
