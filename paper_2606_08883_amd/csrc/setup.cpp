@@ -20,6 +20,7 @@ void face_transmissibilities(HostSetup& S) {
   const double* K = S.K.data();
   S.tx.assign((size_t)ny * (nx + 1), 0.0);
   S.ty.assign((size_t)(ny + 1) * nx, 0.0);
+#pragma omp parallel for schedule(static)
   for (int y = 0; y < ny; ++y) {
     for (int x = 1; x < nx; ++x) {
       double a = K[(size_t)y * nx + x - 1], b = K[(size_t)y * nx + x];
@@ -28,6 +29,7 @@ void face_transmissibilities(HostSetup& S) {
     if (S.bc[SW]) S.tx[(size_t)y * (nx + 1)] = 2.0 * K[(size_t)y * nx];
     if (S.bc[SE]) S.tx[(size_t)y * (nx + 1) + nx] = 2.0 * K[(size_t)y * nx + nx - 1];
   }
+#pragma omp parallel for schedule(static)
   for (int y = 1; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
       double a = K[(size_t)(y - 1) * nx + x], b = K[(size_t)y * nx + x];
@@ -240,9 +242,11 @@ void host_prepare(HostSetup& S, const mrcm_grid& g, const mrcm_params& p, const 
   S.sweeps = p.smooth_sweeps;
   const size_t n = (size_t)g.nx * g.ny;
   S.K.assign(K, K + n);
-  for (size_t c = 0; c < n; ++c)
-    if (!(S.K[c] > 0.0) || !std::isfinite(S.K[c]))
-      throw Error(MRCM_EINVAL, "K must be finite and positive on every cell");
+  long long bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : bad)
+  for (long long c = 0; c < (long long)n; ++c)
+    if (!(S.K[c] > 0.0) || !std::isfinite(S.K[c])) ++bad;
+  if (bad) throw Error(MRCM_EINVAL, "K must be finite and positive on every cell");
   face_transmissibilities(S);
   const int m = M.m, nc = M.nc();
   // coarse right-hand-side weights of the particular traces, per dof k =
@@ -252,6 +256,7 @@ void host_prepare(HostSetup& S, const mrcm_grid& g, const mrcm_params& p, const 
     S.wOff[k + 1] = S.wOff[k] + side_len(M.boxes[M.dofs[k][0]], M.dofs[k][1]);
   S.wU.assign(S.wOff[nc], 0.0);
   S.wP.assign(S.wOff[nc], 0.0);
+#pragma omp parallel for schedule(dynamic, 64)
   for (int i = 0; i < m; ++i)
     for (int dof = M.dof_offset[i]; dof < M.dof_offset[i + 1]; ++dof) {
       const int ks = M.dofs[dof][1], kq = M.dofs[dof][2];
@@ -296,61 +301,43 @@ void device_tables(const HostSetup& S, int epv, DeviceTables& T) {
     const long long w = quad_words(b.bx());
     return (int)((w + epv - 1) / epv * epv);
   };
-  T = DeviceTables();
-  T.mbf_off.assign(m + 1, 0);
-  T.col_off.assign(m + 1, 0);
-  long long buf = 0;
+  // per subdomain (in parallel): the jobs with sizes only, the Robin data of
+  // its oversampled problems and its faces of Gamma_i
+  struct Part {
+    FactorJob lj, pj, oj;
+    SubJob sj;
+    std::vector<OverRhs> rhs;
+    std::vector<GamFace> gam;
+  };
+  std::vector<Part> part(m);
+#pragma omp parallel for schedule(dynamic, 64)
   for (int i = 0; i < m; ++i) {
+    Part& P = part[i];
     const Box& bi = M.boxes[i];
     const Box& oi = M.oboxes[i];
     const int ni = M.dof_offset[i + 1] - M.dof_offset[i];
     const int ns = (int)M.sides[i].size();
-    const long long lc = (long long)bi.bx() * bi.by(), oc = (long long)oi.bx() * oi.by();
-    T.max_local = std::max(T.max_local, bi.bx());
-    T.max_over = std::max(T.max_over, oi.bx());
-    // factor jobs: subdomain box (storage type for the apply, FP64 for the
-    // MBF solves), patch (storage type), oversampled box (FP64)
-    FactorJob lj{bi.x0, bi.y0, bi.bx(), bi.by(), 1, whole(bi) ? 1 : 0, qstride(bi), 0,
-                 T.ldinv_len, T.lcoup_len, buf, buf + lc * bi.bx()};
-    T.ldinv_len += (long long)lj.bs * bi.by();
-    T.lcoup_len += lc;
-    SubJob sj{};
-    sj.l64 = buf;
-    sj.lc64 = buf + lc * bi.bx();
-    buf += lc * bi.bx() + lc;
-    T.local_jobs.push_back(lj);
+    P.lj = FactorJob{bi.x0, bi.y0, bi.bx(), bi.by(), 1, whole(bi) ? 1 : 0, qstride(bi), 0,
+                     0, 0, 0, 0};
     if (S.sweeps > 0) {
       const Box& pb = M.pboxes[i];
-      T.max_patch = std::max(T.max_patch, pb.bx());
-      FactorJob pj{pb.x0, pb.y0, pb.bx(), pb.by(), 0, whole(pb) ? 1 : 0, qstride(pb), 0,
-                   T.pdinv_len, T.pcoup_len, -1, -1};
-      T.pdinv_len += (long long)pj.bs * pb.by();
-      T.pcoup_len += (long long)pb.bx() * pb.by();
-      T.patch_jobs.push_back(pj);
+      P.pj = FactorJob{pb.x0, pb.y0, pb.bx(), pb.by(), 0, whole(pb) ? 1 : 0, qstride(pb), 0,
+                       0, 0, -1, -1};
     }
-    FactorJob oj{oi.x0, oi.y0, oi.bx(), oi.by(), 1, whole(oi) ? 1 : 0, 0, 0, -1, -1, buf,
-                 buf + oc * oi.bx()};
-    sj.o64 = buf;
-    sj.oc64 = buf + oc * oi.bx();
-    buf += oc * oi.bx() + oc;
-    T.over_jobs.push_back(oj);
-    // per-subdomain work: scratch, phi, MBF and moment offsets
+    P.oj = FactorJob{oi.x0, oi.y0, oi.bx(), oi.by(), 1, whole(oi) ? 1 : 0, 0, 0, -1, -1, 0, 0};
+    SubJob& sj = P.sj;
+    sj = SubJob{};
     sj.lbx = bi.bx();
     sj.lby = bi.by();
-    sj.lpin = lj.pin;
+    sj.lpin = P.lj.pin;
     sj.obx = oi.bx();
     sj.oby = oi.by();
-    sj.opin = oj.pin;
+    sj.opin = P.oj.pin;
     sj.ni = ni;
     sj.nsides = ns;
     sj.dof0 = M.dof_offset[i];
-    sj.lscr = buf;
-    buf += ni * lc;
-    sj.oscr = buf;
-    buf += ni * oc;
     // Robin data of the oversampled problems: P_q on side ks of the
     // oversampled box, times the face conductance
-    sj.rhs0 = (int)T.rhs.size();
     for (int k = 0; k < ni; ++k) {
       const int dof = M.dof_offset[i] + k;
       const int ks = M.dofs[dof][1], kq = M.dofs[dof][2];
@@ -360,12 +347,10 @@ void device_tables(const HostSetup& S, int epv, DeviceTables& T) {
         const Face& f = fs[j];
         const double t = f.kind == 0 ? txv(S, f.row, f.col) : tyv(S, f.row, f.col);
         const double rho = robin_rho(S, S.K[f.inside], t);
-        T.rhs.push_back(OverRhs{k, loc_of(oi, f.inside, nx), rho * legendre(kq, xi_of(j, nf))});
+        P.rhs.push_back(OverRhs{k, loc_of(oi, f.inside, nx), rho * legendre(kq, xi_of(j, nf))});
       }
     }
-    sj.rhs1 = (int)T.rhs.size();
     // faces of Gamma_i, side by side in the order of M.sides[i]
-    sj.gam0 = (int)T.gam.size();
     for (int si = 0; si < ns; ++si) {
       const GammaSide gs = make_side(S, bi, M.sides[i][si]);
       const int nfs = (int)gs.faces.size();
@@ -384,14 +369,66 @@ void device_tables(const HostSetup& S, int epv, DeviceTables& T) {
         g.t = gs.t[j];
         g.Kin = gs.Kin[j];
         g.Kout = gs.Kout[j];
-        T.gam.push_back(g);
+        P.gam.push_back(g);
       }
     }
+  }
+  // offsets, in subdomain order
+  T = DeviceTables();
+  T.mbf_off.assign(m + 1, 0);
+  T.col_off.assign(m + 1, 0);
+  size_t nrhs = 0, ngam = 0;
+  for (const Part& P : part) {
+    nrhs += P.rhs.size();
+    ngam += P.gam.size();
+  }
+  T.rhs.reserve(nrhs);
+  T.gam.reserve(ngam);
+  long long buf = 0;
+  for (int i = 0; i < m; ++i) {
+    Part& P = part[i];
+    SubJob& sj = P.sj;
+    const long long lc = (long long)sj.lbx * sj.lby, oc = (long long)sj.obx * sj.oby;
+    T.max_local = std::max(T.max_local, sj.lbx);
+    T.max_over = std::max(T.max_over, sj.obx);
+    P.lj.doffS = T.ldinv_len;
+    P.lj.coffS = T.lcoup_len;
+    P.lj.d64 = buf;
+    P.lj.c64 = buf + lc * sj.lbx;
+    T.ldinv_len += (long long)P.lj.bs * sj.lby;
+    T.lcoup_len += lc;
+    sj.l64 = P.lj.d64;
+    sj.lc64 = P.lj.c64;
+    buf += lc * sj.lbx + lc;
+    T.local_jobs.push_back(P.lj);
+    if (S.sweeps > 0) {
+      T.max_patch = std::max(T.max_patch, P.pj.bx);
+      P.pj.doffS = T.pdinv_len;
+      P.pj.coffS = T.pcoup_len;
+      T.pdinv_len += (long long)P.pj.bs * P.pj.by;
+      T.pcoup_len += (long long)P.pj.bx * P.pj.by;
+      T.patch_jobs.push_back(P.pj);
+    }
+    P.oj.d64 = buf;
+    P.oj.c64 = buf + oc * sj.obx;
+    sj.o64 = P.oj.d64;
+    sj.oc64 = P.oj.c64;
+    buf += oc * sj.obx + oc;
+    T.over_jobs.push_back(P.oj);
+    sj.lscr = buf;
+    buf += sj.ni * lc;
+    sj.oscr = buf;
+    buf += sj.ni * oc;
+    sj.rhs0 = (int)T.rhs.size();
+    T.rhs.insert(T.rhs.end(), P.rhs.begin(), P.rhs.end());
+    sj.rhs1 = (int)T.rhs.size();
+    sj.gam0 = (int)T.gam.size();
+    T.gam.insert(T.gam.end(), P.gam.begin(), P.gam.end());
     sj.gam1 = (int)T.gam.size();
     sj.phi = buf;
-    buf += (long long)ni * (sj.gam1 - sj.gam0);
-    T.mbf_off[i + 1] = T.mbf_off[i] + ni * lc;
-    T.col_off[i + 1] = T.col_off[i] + (long long)ni * ns * nb;
+    buf += (long long)sj.ni * (sj.gam1 - sj.gam0);
+    T.mbf_off[i + 1] = T.mbf_off[i] + sj.ni * lc;
+    T.col_off[i + 1] = T.col_off[i] + (long long)sj.ni * sj.nsides * nb;
     sj.mbf = T.mbf_off[i];
     sj.col = T.col_off[i];
     T.subs.push_back(sj);
@@ -405,27 +442,22 @@ void device_tables(const HostSetup& S, int epv, DeviceTables& T) {
 
 void assemble_coarse(HostSetup& S, const double* colU, const double* colP,
                      const std::vector<long long>& col_off) {
+  // Row (e, kind, q) of C couples the dofs of the two subdomains of edge e,
+  // L (left / lower) before R: C[r][(L, k)] = colU_L[k][side of L facing
+  // e][q] (flux rows) or colP_L[...] (pressure rows); R's entries likewise,
+  // with a minus sign on its pressure moments.
   const Maps& M = S.maps;
-  const int m = M.m, nc = M.nc(), nbm = M.degree + 1;
+  const int nc = M.nc(), nbm = M.degree + 1;
   const int E = (int)M.edges.size();
-  std::vector<std::map<int, double>> rowsC(nc);
-  for (int i = 0; i < m; ++i) {
-    const int Ni = M.dof_offset[i + 1] - M.dof_offset[i];
-    const int ns = (int)M.sides[i].size();
-    for (int k = 0; k < Ni; ++k) {
-      const int col = M.dof_offset[i] + k;
-      for (int si = 0; si < ns; ++si) {
-        bool isL;
-        const int e = edge_across(M, i, M.sides[i][si], isL);
-        const double sign = isL ? 1.0 : -1.0;
-        const int nb = M.nbasis(M.edges[e][4]);
-        const long long base = col_off[i] + ((long long)k * ns + si) * nbm;
-        for (int q = 0; q < nb; ++q) {
-          rowsC[M.row_offset[e] + q][col] += colU[base + q];
-          rowsC[M.row_offset[e] + nb + q][col] += sign * colP[base + q];
-        }
-      }
-    }
+  auto side_index = [&](int i, int side) {
+    const auto& sd = M.sides[i];
+    return (int)(std::find(sd.begin(), sd.end(), side) - sd.begin());
+  };
+  S.Crp.assign(nc + 1, 0);
+  for (int e = 0; e < E; ++e) {
+    const int L = M.edges[e][0], R = M.edges[e][1];
+    const int w = (M.dof_offset[L + 1] - M.dof_offset[L]) + (M.dof_offset[R + 1] - M.dof_offset[R]);
+    for (int r = M.row_offset[e]; r < M.row_offset[e + 1]; ++r) S.Crp[r + 1] = w;
   }
   S.pin_row = -1;
   S.pin_dof = -1;
@@ -433,18 +465,37 @@ void assemble_coarse(HostSetup& S, const double* colU, const double* colP,
     const int L0 = M.edges[0][0], o0 = M.edges[0][2];
     S.pin_row = M.row_offset[0];
     S.pin_dof = M.dof_of(L0, o0 == 0 ? SE : SN, 0);
-    rowsC[S.pin_row].clear();
-    rowsC[S.pin_row][S.pin_dof] = 1.0;
+    S.Crp[S.pin_row + 1] = 1;
   }
-  S.Crp.assign(nc + 1, 0);
-  S.Cci.clear();
-  S.Cv.clear();
-  for (int r = 0; r < nc; ++r) {
-    for (const auto& kv : rowsC[r]) {
-      S.Cci.push_back(kv.first);
-      S.Cv.push_back(kv.second);
-    }
-    S.Crp[r + 1] = (int)S.Cci.size();
+  for (int r = 0; r < nc; ++r) S.Crp[r + 1] += S.Crp[r];
+  S.Cci.assign(S.Crp[nc], 0);
+  S.Cv.assign(S.Crp[nc], 0.0);
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < E; ++e) {
+    const int L = M.edges[e][0], R = M.edges[e][1], o = M.edges[e][2];
+    const int sl = side_index(L, o == 0 ? SE : SN), sr = side_index(R, o == 0 ? SW : SS);
+    const int nsl = (int)M.sides[L].size(), nsr = (int)M.sides[R].size();
+    const int nb = M.nbasis(M.edges[e][4]);
+    for (int kind = 0; kind < 2; ++kind)
+      for (int q = 0; q < nb; ++q) {
+        const int r = M.row_offset[e] + kind * nb + q;
+        int at = S.Crp[r];
+        if (r == S.pin_row) {
+          S.Cci[at] = S.pin_dof;
+          S.Cv[at] = 1.0;
+          continue;
+        }
+        const double* src = kind == 0 ? colU : colP;
+        for (int k = 0; k < M.dof_offset[L + 1] - M.dof_offset[L]; ++k, ++at) {
+          S.Cci[at] = M.dof_offset[L] + k;
+          S.Cv[at] = src[col_off[L] + ((long long)k * nsl + sl) * nbm + q];
+        }
+        const double sign = kind == 0 ? 1.0 : -1.0;
+        for (int k = 0; k < M.dof_offset[R + 1] - M.dof_offset[R]; ++k, ++at) {
+          S.Cci[at] = M.dof_offset[R] + k;
+          S.Cv[at] = sign * src[col_off[R] + ((long long)k * nsr + sr) * nbm + q];
+        }
+      }
   }
 }
 
