@@ -33,12 +33,6 @@ struct CChunk {
   long long mat;
 };
 
-// Layout of one D_j^-1 block (bx x bx, symmetric) in memory: by quads of
-// rows.  With nq = ceil(bx / 4), word (q * bx + r) * 4 + i holds D(4 q + i, r)
-// (zero for 4 q + i >= bx), so the lane that owns column r finds the four
-// entries of a row quad in 16 contiguous bytes (32 for FP64).
-__host__ __device__ constexpr int quad_block_words(int n) { return ((n + 3) / 4) * 4 * n; }
-
 constexpr int kBoxThreads = 256;
 constexpr int kVecThreads = 256;
 constexpr int kMaxVecBlocks = 1024;

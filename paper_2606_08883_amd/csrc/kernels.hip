@@ -109,8 +109,12 @@ __global__ void k_rhs(const double* __restrict__ tx, const double* __restrict__ 
 // rows.  Lane r owns cell column r of every row j:
 //   forward  u_j = D_j^-1 (b_j + T_j u_{j-1}),
 //   backward x_j = u_j + D_j^-1 (T_{j+1} x_{j+1}).
-// All exchange between the lanes of a group goes through the group's slot of
-// LDS and is wave-local (no workgroup barrier).
+// The blocks are symmetric and stored as half blocks (setup_jobs.h): lane r
+// loads the entries D(r, r + k), k = 0 .. NB / 2, of each block and fetches
+// D(r, r - k) = D(r - k, r) from the registers of lane r - k.  All exchange
+// between the lanes of a group is wave-local (no workgroup barrier): the
+// vector of a step goes through the group's slot of LDS, the mirrored
+// entries through cross-lane permutes.
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
 // a * b + c with one rounding, spelled out so that the one-RHS and the
@@ -152,50 +156,111 @@ __device__ __forceinline__ int opaque(int v) {
   return v;
 }
 
-// Blocks in flight per lane: as many as about 96 VGPRs of quads hold (NQ
-// quads of 4 words each per block), between 2 and 6.
-template <typename S, int NQ>
+// Shape of the half blocks of a launch of column width NB: rows 0 .. H, the
+// first K0 of them single words, the others NH quads.
+template <int NB>
+struct Half {
+  static constexpr int H = NB / 2;
+  static constexpr int K0 = half_k0(NB);
+  static constexpr int NH = half_quads(NB);
+};
+
+// A lane's rows of one half block.  row(k) is entry D(r, r + k) of lane r
+// (k a constant after unrolling).
+template <typename S, int NB>
+struct HalfRow {
+  Quad<S> q[Half<NB>::NH];
+  S h[Half<NB>::K0 > 0 ? Half<NB>::K0 : 1];
+  __device__ S row(int k) const {
+    constexpr int K0 = Half<NB>::K0;
+    return k < K0 ? h[k] : q[(k - K0) >> 2][(k - K0) & 3];
+  }
+};
+
+// Blocks in flight per lane: as many as about 48 VGPRs of rows hold, between
+// 2 and 6 (more would cost waves per SIMD: a sweep over 48, 64, 80 and 96
+// found 48 and 64 equal, 96 a third slower on 36-wide patches).
+template <typename S, int NB>
 constexpr int reg_depth() {
-  constexpr int per_block = NQ * 4 * (int)sizeof(S) / 4;
-  constexpr int d = 96 / per_block;
+  constexpr int per_block = half_rows(NB) * (int)sizeof(S) / 4;
+  constexpr int d = 48 / per_block;
   return d < 2 ? 2 : d > 6 ? 6 : d;
 }
 
-// Lane r's part of one block: the quads of its row r (= column r, the block
-// is symmetric), rows 4q .. 4q + 3 at words (q * bx + r) * 4 of the block (see
-// quad_block_words in device.h), so lanes read contiguous 16-byte pieces.
-// Quads past the block (q >= nq) re-read its last quad; they meet zeros in
-// the broadcast vector.
-template <typename S, int NQ>
-__device__ __forceinline__ void load_row(Quad<S> (&d)[NQ], const S* __restrict__ blk, int bx,
-                                         int nq) {
+// Lane rc's rows of one block of a box n cells wide: the quads at words
+// (q n + rc) 4, the single words at 4 NH n + k n + rc, so the group reads
+// contiguous pieces.
+template <typename S, int NB>
+__device__ __forceinline__ void load_half(HalfRow<S, NB>& d, const S* __restrict__ blk, int n,
+                                          int rc) {
+  constexpr int NH = Half<NB>::NH, K0 = Half<NB>::K0;
+  const S* p = blk + 4 * rc;
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) load_quad(d[q], blk + (long long)(q < nq ? q : nq - 1) * 4 * bx);
+  for (int q = 0; q < NH; ++q) load_quad(d.q[q], p + (long long)q * 4 * n);
+  const S* t = blk + (long long)4 * NH * n + rc;
+#pragma unroll
+  for (int k = 0; k < K0; ++k) d.h[k] = t[(long long)k * n];
 }
 
-// acc = sum_c D(c, r) ys[c] with lane r's quads in registers and the
-// broadcast vector ys in LDS (entries past the box are zero); four partial
-// sums shorten the chain of dependent additions.
-template <typename T, typename S, int NQ>
-__device__ __forceinline__ T row_dot(const Quad<S> (&d)[NQ], const T* ys) {
-  T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+// Value v of the lane whose byte address (4 x lane index) is addr.
+__device__ __forceinline__ float lane_fetch(int addr, float v) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_fetch(int addr, double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)b);
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Byte addresses of the lanes that hold D(rc, rc - k), k = 1 .. H: lane
+// (rc - k) mod n of the group starting at lane g0 (lane g0 for k > n, where
+// every lane holds a zero row), one byte each, four to a word.
+template <int H>
+__device__ __forceinline__ void mirror_lanes(int (&src)[(H + 3) / 4], int g0, int rc, int n) {
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    T y[4];
-    if constexpr (sizeof(T) == 4) {
-      const f32x4 v = *reinterpret_cast<const f32x4*>(ys + 4 * q);
-      y[0] = v[0], y[1] = v[1], y[2] = v[2], y[3] = v[3];
-    } else {
-      const f64x2 v0 = *reinterpret_cast<const f64x2*>(ys + 4 * q);
-      const f64x2 v1 = *reinterpret_cast<const f64x2*>(ys + 4 * q + 2);
-      y[0] = v0[0], y[1] = v0[1], y[2] = v1[0], y[3] = v1[1];
-    }
-    a0 = fmat((T)d[q][0], y[0], a0);
-    a1 = fmat((T)d[q][1], y[1], a1);
-    a2 = fmat((T)d[q][2], y[2], a2);
-    a3 = fmat((T)d[q][3], y[3], a3);
+  for (int w = 0; w < (H + 3) / 4; ++w) src[w] = 0;
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    int c = rc - k;
+    c = c < 0 ? c + n : c;
+    c = c < 0 ? 0 : c;
+    src[(k - 1) >> 2] |= (4 * (g0 + c)) << (8 * ((k - 1) & 3));
   }
-  return (a0 + a1) + (a2 + a3);
+}
+
+// The mirrored entries rot[k - 1] = D(rc, rc - k) of one block.  The packed
+// addresses are unpacked at each use (opaque keeps the optimiser from
+// holding all H of them in registers across the sweep).
+template <typename S, int NB>
+__device__ __forceinline__ void mirror_rows(S (&rot)[Half<NB>::H], const HalfRow<S, NB>& d,
+                                            const int (&src)[(Half<NB>::H + 3) / 4]) {
+  int w[(Half<NB>::H + 3) / 4];
+#pragma unroll
+  for (int i = 0; i < (Half<NB>::H + 3) / 4; ++i) w[i] = opaque(src[i]);
+#pragma unroll
+  for (int k = 1; k <= Half<NB>::H; ++k)
+    rot[k - 1] = lane_fetch((w[(k - 1) >> 2] >> (8 * ((k - 1) & 3))) & 255, d.row(k));
+}
+
+// acc = sum_c D(rc, c) v[c]: the lane's rows k against vo[k] = v[(rc + k)
+// mod n], the mirrored entries against vr[-k] = v[(rc - k) mod n] (vo and vr
+// point into the group's doubled copy of v); four partial sums shorten the
+// chain of dependent additions.
+template <typename T, typename S, int NB>
+__device__ __forceinline__ T half_dot(const HalfRow<S, NB>& d, const S (&rot)[Half<NB>::H],
+                                      const T* vo, const T* vr) {
+  constexpr int NH = Half<NB>::NH, K0 = Half<NB>::K0, H = Half<NB>::H;
+  T a[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int q = 0; q < NH; ++q)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = fmat((T)d.q[q][i], vo[K0 + 4 * q + i], a[i]);
+#pragma unroll
+  for (int k = 0; k < K0; ++k) a[k] = fmat((T)d.h[k], vo[k], a[k]);
+#pragma unroll
+  for (int k = 1; k <= H; ++k) a[(k - 1) & 3] = fmat((T)rot[k - 1], vr[-k], a[(k - 1) & 3]);
+  return (a[0] + a[1]) + (a[2] + a[3]);
 }
 
 // Largest value of v over the 64 lanes of the wave, as a wave-uniform value.
@@ -206,7 +271,7 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 // One sweep over the block rows of the boxes of a wave.  Step s uses block
-// blk(s), whose quads were loaded into register set s % DEPTH at step
+// blk(s), whose rows were loaded into register set s % DEPTH at step
 // s - DEPTH; right after its use the set is refilled with block s + DEPTH,
 // so every block has DEPTH - 1 steps to arrive.  The boxes of a wave have
 // different heights, so the wave runs nmax steps (its largest count, rounded
@@ -214,24 +279,24 @@ __device__ __forceinline__ int wave_max(int v) {
 // last block and are told valid = false.  No load is conditional, so the
 // compiler counts the loads in flight exactly and waits only for the block
 // a step uses.
-template <typename S, int NQ, int DEPTH, typename Blk, typename Step>
+template <typename S, int NB, int DEPTH, typename Blk, typename Step>
 __device__ __forceinline__ void pipelined_sweep(int nsteps, int nmax, Blk blk, Step step,
                                                 const S* __restrict__ Dinv, int bstride,
-                                                int bx, int nq, int r) {
+                                                int n, int r) {
   const int last = nsteps > 0 ? nsteps - 1 : 0;
   auto src = [&](int s) {
     const int b = blk(s < last ? s : last);
-    return Dinv + (long long)(b > 0 ? b : 0) * bstride + 4 * opaque(r);
+    return Dinv + (long long)(b > 0 ? b : 0) * bstride;
   };
-  Quad<S> reg[DEPTH][NQ];
+  HalfRow<S, NB> reg[DEPTH];
 #pragma unroll
-  for (int u = 0; u < DEPTH; ++u) load_row<S, NQ>(reg[u], src(u), bx, nq);
+  for (int u = 0; u < DEPTH; ++u) load_half<S, NB>(reg[u], src(u), n, opaque(r));
   for (int s0 = 0; s0 < nmax; s0 += DEPTH) {
 #pragma unroll
     for (int u = 0; u < DEPTH; ++u) {
       const int s = s0 + u;
       step(s, reg[u], s < nsteps);
-      load_row<S, NQ>(reg[u], src(s + DEPTH), bx, nq);
+      load_half<S, NB>(reg[u], src(s + DEPTH), n, opaque(r));
     }
   }
 }
@@ -244,55 +309,76 @@ __device__ __forceinline__ int wave_steps(int n) {
   return (m + DEPTH - 1) / DEPTH * DEPTH;
 }
 
+// Words of the group's copy of the step vector for column width NB and group
+// size GS: v at [H, H + n) and again at [H + n, H + 2 n), zeros around it
+// (the lane's rows past the box meet finite values).
+template <int NB, int GS>
+constexpr int vec_words() { return (NB / 2 + 2 * GS + 3) / 4 * 4; }
+
+// Zero the group's vector slots (count words) before the first step.
+template <typename T, int GS>
+__device__ __forceinline__ void zero_slots(T* v, int count, int lane) {
+  for (int i = lane; i < count; i += GS) v[i] = T(0);
+}
+
 // Block LDL^T solve of one box by a group; us holds b on entry and x on exit
-// (by rows of bx words, LDS); cp holds the couplings T_j (LDS); ys is the
-// group's broadcast slot.  S is the storage type of the factors, T the
-// arithmetic and vector type (FP32 factors may be applied in FP64
-// arithmetic).  Lanes at or past bx (and whole groups with live = false)
-// take part in every step but read only inside the box and write nothing;
-// they set their broadcast entry to zero.
+// (by rows of bx words, LDS); cp holds the couplings T_j (LDS); vv is the
+// group's vector slot (vec_words, zeroed); g0 the group's first lane in the
+// wave.  S is the storage type of the factors, T the arithmetic and vector
+// type (FP32 factors may be applied in FP64 arithmetic).  Lanes at or past
+// bx (and whole groups with live = false) take part in every step but read
+// only inside the box and write nothing outside their slot.
 template <typename T, typename S, int NB, int GS>
-__device__ __forceinline__ void box_solve(T* us, T* ys, const S* cp, const S* __restrict__ Dinv,
-                                          int bx, int by, int bstride, int r, bool live) {
-  constexpr int NQ = NB / 4;
-  constexpr int DEPTH = reg_depth<S, NQ>();
+__device__ __forceinline__ void box_solve(T* us, T* vv, const S* cp, const S* __restrict__ Dinv,
+                                          int bx, int by, int bstride, int r, int g0,
+                                          bool live) {
+  constexpr int H = Half<NB>::H;
+  constexpr int DEPTH = reg_depth<S, NB>();
   const bool act = live && r < bx;
   const int rc = r < bx ? r : bx - 1;
-  const int nq = (bx + 3) >> 2;
+  int src[(H + 3) / 4];
+  mirror_lanes<H>(src, g0, rc, bx);
+  const T* vo = vv + H + rc;
+  const T* vr = vv + H + rc + bx;
   T carry = T(0);
-  pipelined_sweep<S, NQ, DEPTH>(
+  pipelined_sweep<S, NB, DEPTH>(
       live ? by : 0, wave_steps<DEPTH>(live ? by : 0), [](int s) { return s; },
-      [&](int s, const Quad<S>(&d)[NQ], bool valid) {
+      [&](int s, const HalfRow<S, NB>& d, bool valid) {
+        S rot[H];
+        mirror_rows<S, NB>(rot, d, src);
         const int j = s < by ? s : by - 1;
         const T uj = us[j * bx + rc];
         const T y = j > 0 ? fmat((T)cp[j * bx + rc], carry, uj) : uj;
         const bool w = act && valid;
-        ys[r] = w ? y : T(0);
+        if (r < bx) vv[H + r] = vv[H + bx + r] = w ? y : T(0);
         wave_sync();
-        const T acc = row_dot<T, S, NQ>(d, ys);
+        const T acc = half_dot<T, S, NB>(d, rot, vo, vr);
         wave_sync();
         if (w) us[j * bx + r] = acc;
         carry = w ? acc : carry;
       },
-      Dinv, bstride, bx, nq, rc);
+      Dinv, bstride, bx, rc);
   // carry = x_{by-1} = u_{by-1}
   const int nb = live && by > 1 ? by - 1 : 0;
-  pipelined_sweep<S, NQ, DEPTH>(
+  pipelined_sweep<S, NB, DEPTH>(
       nb, wave_steps<DEPTH>(nb), [by](int s) { return by - 2 - s; },
-      [&](int s, const Quad<S>(&d)[NQ], bool valid) {
+      [&](int s, const HalfRow<S, NB>& d, bool valid) {
+        S rot[H];
+        mirror_rows<S, NB>(rot, d, src);
         int j = by - 2 - s;
         j = j < 0 ? 0 : j;
         const int jn = j + 1 < by ? j + 1 : by - 1;
         const bool w = act && valid;
-        ys[r] = w ? (T)cp[jn * bx + rc] * carry : T(0);
+        const T y = (T)cp[jn * bx + rc] * carry;
+        if (r < bx) vv[H + r] = vv[H + bx + r] = w ? y : T(0);
         wave_sync();
-        const T acc = row_dot<T, S, NQ>(d, ys);
+        const T acc = half_dot<T, S, NB>(d, rot, vo, vr);
         wave_sync();
         const T xj = us[j * bx + rc] + acc;
         if (w) us[j * bx + r] = xj;
         carry = w ? xj : carry;
       },
-      Dinv, bstride, bx, nq, rc);
+      Dinv, bstride, bx, rc);
 }
 
 // Copy rows [0, by) of a box (bx cells wide, lane r: column r) from a global
@@ -340,18 +426,19 @@ __device__ __forceinline__ void words_to_lds(S* dst, const S* __restrict__ src, 
 }
 
 // LDS slot of one lane group:
-//   ys[GS] (T) | cp[max cells] (S) | us[max cells] (T),
+//   vv[vec_words] (T) | cp[max cells] (S) | us[max cells] (T),
 // every part 16-byte aligned; cp_words (the coupling area) is a multiple of
 // 16 bytes.
-template <typename T, typename S, int GS>
+template <typename T, typename S, int NB, int GS>
 struct BoxSlot {
-  T* ys;
+  T* vv;
   S* cp;
   T* us;
   __device__ BoxSlot(char* base, int cp_words) {
-    ys = reinterpret_cast<T*>(base);
-    cp = reinterpret_cast<S*>(base + GS * sizeof(T));
-    us = reinterpret_cast<T*>(base + GS * sizeof(T) + (long long)cp_words * sizeof(S));
+    constexpr int VW = vec_words<NB, GS>();
+    vv = reinterpret_cast<T*>(base);
+    cp = reinterpret_cast<S*>(base + VW * sizeof(T));
+    us = reinterpret_cast<T*>(base + VW * sizeof(T) + (long long)cp_words * sizeof(S));
   }
 };
 
@@ -374,17 +461,19 @@ __global__ void __launch_bounds__(kBoxThreads)
   const int i0 = blockIdx.x * (blockDim.x / GS) + grp;
   const bool live = i0 < m;
   const int i = live ? i0 : m - 1;
-  BoxSlot<T, S, GS> L(smem_raw + (long long)grp * group_bytes, cp_words);
+  BoxSlot<T, S, NB, GS> L(smem_raw + (long long)grp * group_bytes, cp_words);
   const BoxDesc d = boxes[i];
   const int bx = d.bx, by = d.by;
   const bool act = live && lane < bx;
   const long long origin = (long long)d.y0 * nx + d.x0;
   rows_to_lds(L.us, r, origin, nx, bx, by, lane, live);
   words_to_lds<S, GS>(L.cp, coup + d.coff, bx * by, lane, live);
+  zero_slots<T, GS>(L.vv, vec_words<NB, GS>(), lane);
   wave_sync();
   if (live && d.pin && lane == 0) L.us[0] = T(0);
   wave_sync();
-  box_solve<T, S, NB, GS>(L.us, L.ys, L.cp, dinv + d.doff, bx, by, d.bs, lane, live);
+  box_solve<T, S, NB, GS>(L.us, L.vv, L.cp, dinv + d.doff, bx, by, d.bs, lane,
+                         (threadIdx.x & 63) - lane, live);
   wave_sync();
   if (act)
     for (int j = 0; j < by; ++j) p[origin + (long long)j * nx + lane] = L.us[j * bx + lane];
@@ -627,16 +716,18 @@ __global__ void __launch_bounds__(kBoxThreads)
   const int i0 = blockIdx.x * (blockDim.x / GS) + grp;
   const bool live = i0 < m;
   const int i = live ? i0 : m - 1;
-  BoxSlot<T, S, GS> L(smem_raw + (long long)grp * group_bytes, cp_words);
+  BoxSlot<T, S, NB, GS> L(smem_raw + (long long)grp * group_bytes, cp_words);
   const BoxDesc d = boxes[i];
   const int bx = d.bx, by = d.by;
   const long long origin = (long long)d.y0 * nx + d.x0;
   rows_to_lds(L.us, rho, origin, nx, bx, by, lane, live);
   words_to_lds<S, GS>(L.cp, coup + d.coff, bx * by, lane, live);
+  zero_slots<T, GS>(L.vv, vec_words<NB, GS>(), lane);
   wave_sync();
   if (live && d.pin && lane == 0) L.us[0] = T(0);
   wave_sync();
-  box_solve<T, S, NB, GS>(L.us, L.ys, L.cp, dinv + d.doff, bx, by, d.bs, lane, live);
+  box_solve<T, S, NB, GS>(L.us, L.vv, L.cp, dinv + d.doff, bx, by, d.bs, lane,
+                         (threadIdx.x & 63) - lane, live);
   wave_sync();
   // p += e on the owned cells, eight rows of read-modify-write in flight
   const bool own = live && lane >= d.ox && lane < d.ox + d.obx;
@@ -915,56 +1006,53 @@ struct RhsPtrs {
   T* v[kMaxRhs];
 };
 
-// Blocks in flight per lane for K right-hand sides: about 64 VGPRs of quads
+// Blocks in flight per lane for K right-hand sides: about 64 VGPRs of rows
 // (the K columns need their own registers), between 2 and 4.
-template <typename S, int NQ, int K>
+template <typename S, int NB, int K>
 constexpr int reg_depth_k() {
-  constexpr int per_block = NQ * 4 * (int)sizeof(S) / 4;
+  constexpr int per_block = half_rows(NB) * (int)sizeof(S) / 4;
   constexpr int d = (K == 1 ? 96 : 64) / per_block;
   return d < 2 ? 2 : d > 4 ? 4 : d;
 }
 
-// acc[k] = sum_c D(c, r) ys[k][c] for the K broadcast vectors ys[k * GS ..]:
-// each factor quad is converted once and used for every column; per column,
-// the four partial sums of row_dot.  The broadcast reads run one quad ahead
-// of the arithmetic, and a scheduling barrier after each quad keeps the
-// compiler from hoisting all NQ x K reads at once (which would need more
-// registers than a lane has).
-template <typename T, int K, int GS>
-__device__ __forceinline__ void load_ys(T (&y)[K][4], const T* ys, int q) {
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const T* yk = ys + k * GS + 4 * q;
-    if constexpr (sizeof(T) == 4) {
-      const f32x4 v = *reinterpret_cast<const f32x4*>(yk);
-      y[k][0] = v[0], y[k][1] = v[1], y[k][2] = v[2], y[k][3] = v[3];
-    } else {
-      const f64x2 v0 = *reinterpret_cast<const f64x2*>(yk);
-      const f64x2 v1 = *reinterpret_cast<const f64x2*>(yk + 2);
-      y[k][0] = v0[0], y[k][1] = v0[1], y[k][2] = v1[0], y[k][3] = v1[1];
-    }
-  }
-}
-
-template <typename T, typename S, int NQ, int K, int GS>
-__device__ __forceinline__ void row_dot_k(const Quad<S> (&d)[NQ], const T* ys, T (&acc)[K]) {
+// acc[k] = sum_c D(rc, c) v_k[c] for the K vectors of the group (column k's
+// doubled copy at vo / vr + k * VW): each factor entry is converted once and
+// used for every column; per column, the order of half_dot.  A scheduling
+// barrier after each group of four entries keeps the compiler from hoisting
+// all the vector reads at once (which would need more registers than a lane
+// has).
+template <typename T, typename S, int NB, int K, int VW>
+__device__ __forceinline__ void half_dot_k(const HalfRow<S, NB>& d, const S (&rot)[Half<NB>::H],
+                                           const T* vo, const T* vr, T (&acc)[K]) {
+  constexpr int NH = Half<NB>::NH, K0 = Half<NB>::K0, H = Half<NB>::H;
   T a[K][4];
 #pragma unroll
   for (int k = 0; k < K; ++k) a[k][0] = a[k][1] = a[k][2] = a[k][3] = T(0);
-  T y[2][K][4];
-  load_ys<T, K, GS>(y[0], ys, 0);
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    if (q + 1 < NQ) load_ys<T, K, GS>(y[(q + 1) & 1], ys, q + 1);
-    const T d0 = (T)d[q][0], d1 = (T)d[q][1], d2 = (T)d[q][2], d3 = (T)d[q][3];
+  for (int q = 0; q < NH; ++q) {
+    const T dq[4] = {(T)d.q[q][0], (T)d.q[q][1], (T)d.q[q][2], (T)d.q[q][3]};
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      a[k][0] = fmat(d0, y[q & 1][k][0], a[k][0]);
-      a[k][1] = fmat(d1, y[q & 1][k][1], a[k][1]);
-      a[k][2] = fmat(d2, y[q & 1][k][2], a[k][2]);
-      a[k][3] = fmat(d3, y[q & 1][k][3], a[k][3]);
-    }
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[k][i] = fmat(dq[i], vo[k * VW + K0 + 4 * q + i], a[k][i]);
     __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int e = 0; e < K0; ++e) {
+    const T de = (T)d.h[e];
+#pragma unroll
+    for (int k = 0; k < K; ++k) a[k][e] = fmat(de, vo[k * VW + e], a[k][e]);
+  }
+#pragma unroll
+  for (int g = 1; g <= H; g += 4) {
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int e = g; e < g + 4 && e <= H; ++e) {
+      const T de = (T)rot[e - 1];
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        a[k][(e - 1) & 3] = fmat(de, vr[k * VW - e], a[k][(e - 1) & 3]);
+    }
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = (a[k][0] + a[k][1]) + (a[k][2] + a[k][3]);
@@ -981,19 +1069,23 @@ __device__ __forceinline__ void group_fence() {
 // is read at in[k] + j * istride (lane r: column r); the solution is built
 // in place at work[k] + j * wstride: the forward pass leaves u_j there and
 // the backward pass overwrites it with x_j.  The next step's rows are loaded
-// one step ahead.  ys[K][GS] is the group's broadcast slot (LDS), cp the
-// couplings (LDS); pin zeroes b_0 in column 0 (a box fixed at its first
-// cell).
+// one step ahead.  vv holds the group's K vector slots (vec_words each,
+// zeroed), cp the couplings (LDS); g0 is the group's first lane in the wave;
+// pin zeroes b_0 in column 0 (a box fixed at its first cell).
 template <typename T, typename S, int NB, int GS, int K, typename In>
 __device__ __forceinline__ void box_solve_k(const In* const (&in)[K], long long istride,
-                                            T* const (&work)[K], long long wstride, T* ys,
+                                            T* const (&work)[K], long long wstride, T* vv,
                                             const S* cp, const S* __restrict__ Dinv, int bx,
-                                            int by, int bstride, int r, bool live, bool pin) {
-  constexpr int NQ = NB / 4;
-  constexpr int DEPTH = reg_depth_k<S, NQ, K>();
+                                            int by, int bstride, int r, int g0, bool live,
+                                            bool pin) {
+  constexpr int H = Half<NB>::H, VW = vec_words<NB, GS>();
+  constexpr int DEPTH = reg_depth_k<S, NB, K>();
   const bool act = live && r < bx;
   const int rc = r < bx ? r : bx - 1;
-  const int nq = (bx + 3) >> 2;
+  int src[(H + 3) / 4];
+  mirror_lanes<H>(src, g0, rc, bx);
+  const T* vo = vv + H + rc;
+  const T* vr = vv + H + rc + bx;
   T carry[K], nxt[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) carry[k] = T(0);
@@ -1003,9 +1095,11 @@ __device__ __forceinline__ void box_solve_k(const In* const (&in)[K], long long 
     for (int k = 0; k < K; ++k) nxt[k] = (T)in[k][off];
   };
   in_row(0);
-  pipelined_sweep<S, NQ, DEPTH>(
+  pipelined_sweep<S, NB, DEPTH>(
       live ? by : 0, wave_steps<DEPTH>(live ? by : 0), [](int s) { return s; },
-      [&](int s, const Quad<S>(&d)[NQ], bool valid) {
+      [&](int s, const HalfRow<S, NB>& d, bool valid) {
+        S rot[H];
+        mirror_rows<S, NB>(rot, d, src);
         const int j = s < by ? s : by - 1;
         const bool w = act && valid;
         T b[K];
@@ -1013,14 +1107,15 @@ __device__ __forceinline__ void box_solve_k(const In* const (&in)[K], long long 
         for (int k = 0; k < K; ++k) b[k] = (pin && j == 0 && rc == 0) ? T(0) : nxt[k];
         in_row(s + 1);
         const T cj = (T)cp[j * bx + rc];
+        if (r < bx)
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const T y = j > 0 ? fmat(cj, carry[k], b[k]) : b[k];
-          ys[k * GS + r] = w ? y : T(0);
-        }
+          for (int k = 0; k < K; ++k) {
+            const T y = j > 0 ? fmat(cj, carry[k], b[k]) : b[k];
+            vv[k * VW + H + r] = vv[k * VW + H + bx + r] = w ? y : T(0);
+          }
         wave_sync();
         T acc[K];
-        row_dot_k<T, S, NQ, K, GS>(d, ys, acc);
+        half_dot_k<T, S, NB, K, VW>(d, rot, vo, vr, acc);
         wave_sync();
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -1028,7 +1123,7 @@ __device__ __forceinline__ void box_solve_k(const In* const (&in)[K], long long 
           carry[k] = w ? acc[k] : carry[k];
         }
       },
-      Dinv, bstride, bx, nq, rc);
+      Dinv, bstride, bx, rc);
   group_fence();
   // carry = x_{by-1} = u_{by-1}
   const int nb = live && by > 1 ? by - 1 : 0;
@@ -1039,9 +1134,11 @@ __device__ __forceinline__ void box_solve_k(const In* const (&in)[K], long long 
     for (int k = 0; k < K; ++k) nxt[k] = work[k][(long long)j * wstride + rc];
   };
   u_row(0);
-  pipelined_sweep<S, NQ, DEPTH>(
+  pipelined_sweep<S, NB, DEPTH>(
       nb, wave_steps<DEPTH>(nb), [by](int s) { return by - 2 - s; },
-      [&](int s, const Quad<S>(&d)[NQ], bool valid) {
+      [&](int s, const HalfRow<S, NB>& d, bool valid) {
+        S rot[H];
+        mirror_rows<S, NB>(rot, d, src);
         int j = by - 2 - s;
         j = j < 0 ? 0 : j;
         const int jn = j + 1 < by ? j + 1 : by - 1;
@@ -1051,11 +1148,13 @@ __device__ __forceinline__ void box_solve_k(const In* const (&in)[K], long long 
         for (int k = 0; k < K; ++k) u[k] = nxt[k];
         u_row(s + 1);
         const T cj = (T)cp[jn * bx + rc];
+        if (r < bx)
 #pragma unroll
-        for (int k = 0; k < K; ++k) ys[k * GS + r] = w ? cj * carry[k] : T(0);
+          for (int k = 0; k < K; ++k)
+            vv[k * VW + H + r] = vv[k * VW + H + bx + r] = w ? cj * carry[k] : T(0);
         wave_sync();
         T acc[K];
-        row_dot_k<T, S, NQ, K, GS>(d, ys, acc);
+        half_dot_k<T, S, NB, K, VW>(d, rot, vo, vr, acc);
         wave_sync();
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -1064,19 +1163,19 @@ __device__ __forceinline__ void box_solve_k(const In* const (&in)[K], long long 
           carry[k] = w ? xj : carry[k];
         }
       },
-      Dinv, bstride, bx, nq, rc);
+      Dinv, bstride, bx, rc);
   group_fence();
 }
 
 // LDS slot of one lane group for K right-hand sides:
-//   ys[K][GS] (T) | cp[max cells] (S).
-template <typename T, typename S, int GS, int K>
+//   vv[K][vec_words] (T) | cp[max cells] (S).
+template <typename T, typename S, int NB, int GS, int K>
 struct BoxSlotK {
-  T* ys;
+  T* vv;
   S* cp;
   __device__ BoxSlotK(char* base) {
-    ys = reinterpret_cast<T*>(base);
-    cp = reinterpret_cast<S*>(base + K * GS * sizeof(T));
+    vv = reinterpret_cast<T*>(base);
+    cp = reinterpret_cast<S*>(base + K * vec_words<NB, GS>() * sizeof(T));
   }
 };
 
@@ -1096,7 +1195,7 @@ __global__ void __launch_bounds__(kBoxThreads)
   const int i0 = blockIdx.x * (blockDim.x / GS) + grp;
   const bool live = i0 < m;
   const int i = live ? i0 : m - 1;
-  BoxSlotK<T, S, GS, K> L(smem_raw + (long long)grp * group_bytes);
+  BoxSlotK<T, S, NB, GS, K> L(smem_raw + (long long)grp * group_bytes);
   const BoxDesc d = boxes[i];
   const int bx = d.bx, by = d.by;
   const long long origin = (long long)d.y0 * nx + d.x0;
@@ -1108,9 +1207,11 @@ __global__ void __launch_bounds__(kBoxThreads)
     work[k] = p.v[k] + origin;
   }
   words_to_lds<S, GS>(L.cp, coup + d.coff, bx * by, lane, live);
+  zero_slots<T, GS>(L.vv, K * vec_words<NB, GS>(), lane);
   wave_sync();
-  box_solve_k<T, S, NB, GS, K, double>(in, nx, work, nx, L.ys, L.cp, dinv + d.doff, bx, by,
-                                       d.bs, lane, live, live && d.pin);
+  box_solve_k<T, S, NB, GS, K, double>(in, nx, work, nx, L.vv, L.cp, dinv + d.doff, bx, by,
+                                       d.bs, lane, (threadIdx.x & 63) - lane, live,
+                                       live && d.pin);
   if (!live) return;
   for (int kd = dof_off[i] + lane; kd < dof_off[i + 1]; kd += GS) {
     const int side = dof_side[kd];
@@ -1165,7 +1266,7 @@ __global__ void __launch_bounds__(kBoxThreads)
   const int i0 = blockIdx.x * (blockDim.x / GS) + grp;
   const bool live = i0 < m;
   const int i = live ? i0 : m - 1;
-  BoxSlotK<T, S, GS, K> L(smem_raw + (long long)grp * group_bytes);
+  BoxSlotK<T, S, NB, GS, K> L(smem_raw + (long long)grp * group_bytes);
   const BoxDesc d = boxes[i];
   const int bx = d.bx, by = d.by;
   const long long origin = (long long)d.y0 * nx + d.x0;
@@ -1177,9 +1278,10 @@ __global__ void __launch_bounds__(kBoxThreads)
     work[k] = e.v[k] + d.coff;
   }
   words_to_lds<S, GS>(L.cp, coup + d.coff, bx * by, lane, live);
+  zero_slots<T, GS>(L.vv, K * vec_words<NB, GS>(), lane);
   wave_sync();
-  box_solve_k<T, S, NB, GS, K, T>(in, nx, work, bx, L.ys, L.cp, dinv + d.doff, bx, by, d.bs,
-                                  lane, live, live && d.pin);
+  box_solve_k<T, S, NB, GS, K, T>(in, nx, work, bx, L.vv, L.cp, dinv + d.doff, bx, by, d.bs,
+                                  lane, (threadIdx.x & 63) - lane, live, live && d.pin);
   // p += e on the owned cells, eight rows of read-modify-write in flight
   const bool own = live && lane >= d.ox && lane < d.ox + d.obx;
   const int col = own ? lane : d.ox;
@@ -1535,11 +1637,12 @@ void launch_rhs(const double* tx, const double* ty, int nx, int ny, const int* b
 
 // Column-buffer width (registers) and lane-group size for boxes up to max_bx
 // cells wide.
-inline int col_width(int max_bx) {
-  return max_bx <= 16 ? 16 : max_bx <= 24 ? 24 : max_bx <= 32 ? 32 : max_bx <= 40 ? 40
-       : max_bx <= 48 ? 48 : 64;
-}
+inline int col_width(int max_bx) { return box_cols(max_bx); }
 inline int group_size(int max_bx) { return max_bx <= 16 ? 16 : max_bx <= 32 ? 32 : 64; }
+// Words of a group's vector slot (vec_words of the kernels).
+inline int vec_slot_words(int max_bx) {
+  return (col_width(max_bx) / 2 + 2 * group_size(max_bx) + 3) / 4 * 4;
+}
 // Words of S in 16 bytes; x rounded up to a multiple of them.
 inline int round16(long long x, size_t w) {
   const long long e = 16 / (long long)w;
@@ -1548,7 +1651,7 @@ inline int round16(long long x, size_t w) {
 // LDS bytes of one lane group: broadcast slot and box (arithmetic words t)
 // and the couplings (storage words w), rounded to 16 bytes.
 inline size_t group_bytes(int max_bx, int max_cells, size_t t, size_t w) {
-  const size_t b = (size_t)group_size(max_bx) * t + (size_t)round16(max_cells, w) * w +
+  const size_t b = (size_t)vec_slot_words(max_bx) * t + (size_t)round16(max_cells, w) * w +
                    (size_t)max_cells * t;
   return (b + 15) / 16 * 16;
 }
@@ -1568,8 +1671,10 @@ size_t box_lds_bytes(int max_bx, int max_cells, size_t t, size_t w) {
   do {                                                                                   \
     switch (col_width(max_bx)) {                                                         \
       case 16: hipLaunchKernelGGL((KERNEL<T, S, 16>), __VA_ARGS__); break;               \
+      case 20: hipLaunchKernelGGL((KERNEL<T, S, 20>), __VA_ARGS__); break;               \
       case 24: hipLaunchKernelGGL((KERNEL<T, S, 24>), __VA_ARGS__); break;               \
       case 32: hipLaunchKernelGGL((KERNEL<T, S, 32>), __VA_ARGS__); break;               \
+      case 36: hipLaunchKernelGGL((KERNEL<T, S, 36>), __VA_ARGS__); break;               \
       case 40: hipLaunchKernelGGL((KERNEL<T, S, 40>), __VA_ARGS__); break;               \
       case 48: hipLaunchKernelGGL((KERNEL<T, S, 48>), __VA_ARGS__); break;               \
       default: hipLaunchKernelGGL((KERNEL<T, S, 64>), __VA_ARGS__); break;               \
@@ -1656,7 +1761,7 @@ void check_k(int k) {
     throw Error(MRCM_EINVAL, "multi-RHS launch of unsupported width");
 }
 inline size_t group_bytes_k(int k, int max_bx, int max_cells, size_t t, size_t w) {
-  const size_t b = (size_t)k * group_size(max_bx) * t + (size_t)round16(max_cells, w) * w;
+  const size_t b = (size_t)k * vec_slot_words(max_bx) * t + (size_t)round16(max_cells, w) * w;
   return (b + 15) / 16 * 16;
 }
 int box_groups_k(int k, int max_bx, int max_cells, size_t t, size_t w) {
@@ -1685,10 +1790,13 @@ inline int box_width_k(int nb, size_t w) {
     if (nb == 16 && kk == 8) hipLaunchKernelGGL((KERNEL<T, S, 16, 8>), __VA_ARGS__);   \
     else if (nb == 16 && kk == 4) hipLaunchKernelGGL((KERNEL<T, S, 16, 4>), __VA_ARGS__); \
     else if (nb == 16) hipLaunchKernelGGL((KERNEL<T, S, 16, 2>), __VA_ARGS__);         \
+    else if (nb == 20 && kk == 4) hipLaunchKernelGGL((KERNEL<T, S, 20, 4>), __VA_ARGS__); \
+    else if (nb == 20) hipLaunchKernelGGL((KERNEL<T, S, 20, 2>), __VA_ARGS__);         \
     else if (nb == 24 && kk == 4) hipLaunchKernelGGL((KERNEL<T, S, 24, 4>), __VA_ARGS__); \
     else if (nb == 24) hipLaunchKernelGGL((KERNEL<T, S, 24, 2>), __VA_ARGS__);         \
     else if (nb == 32 && kk == 4) hipLaunchKernelGGL((KERNEL<T, S, 32, 4>), __VA_ARGS__); \
     else if (nb == 32) hipLaunchKernelGGL((KERNEL<T, S, 32, 2>), __VA_ARGS__);         \
+    else if (nb == 36) hipLaunchKernelGGL((KERNEL<T, S, 36, 2>), __VA_ARGS__);         \
     else if (nb == 40) hipLaunchKernelGGL((KERNEL<T, S, 40, 2>), __VA_ARGS__);         \
     else hipLaunchKernelGGL((KERNEL<T, S, 48, 2>), __VA_ARGS__);                       \
   } while (0)

@@ -287,18 +287,22 @@ void host_prepare(HostSetup& S, const mrcm_grid& g, const mrcm_params& p, const 
   }
 }
 
-// Words of one row block in the quad layout of the apply kernels: ceil(n / 4)
-// quads of rows times n columns times 4.
-static long long quad_words(int n) { return (long long)((n + 3) / 4) * 4 * n; }
-
 void device_tables(const HostSetup& S, int epv, DeviceTables& T) {
   const Maps& M = S.maps;
   const int m = M.m, nb = M.degree + 1, nx = S.nx, ny = S.ny;
   auto whole = [&](const Box& b) {
     return S.noflow && b.x0 == 0 && b.y0 == 0 && b.x1 == nx && b.y1 == ny;
   };
-  auto qstride = [&](const Box& b) {
-    const long long w = quad_words(b.bx());
+  // column widths of the local and patch launches, which fix the half-block
+  // layout of their factors
+  int lmax = 1, pmax = 1;
+  for (int i = 0; i < m; ++i) {
+    lmax = std::max(lmax, M.boxes[i].bx());
+    if (S.sweeps > 0) pmax = std::max(pmax, M.pboxes[i].bx());
+  }
+  const int lcols = box_cols(lmax), pcols = box_cols(pmax);
+  auto hstride = [&](const Box& b, int cols) {
+    const long long w = half_block_words(b.bx(), cols);
     return (int)((w + epv - 1) / epv * epv);
   };
   // per subdomain (in parallel): the jobs with sizes only, the Robin data of
@@ -317,12 +321,12 @@ void device_tables(const HostSetup& S, int epv, DeviceTables& T) {
     const Box& oi = M.oboxes[i];
     const int ni = M.dof_offset[i + 1] - M.dof_offset[i];
     const int ns = (int)M.sides[i].size();
-    P.lj = FactorJob{bi.x0, bi.y0, bi.bx(), bi.by(), 1, whole(bi) ? 1 : 0, qstride(bi), 0,
-                     0, 0, 0, 0};
+    P.lj = FactorJob{bi.x0, bi.y0, bi.bx(), bi.by(), 1, whole(bi) ? 1 : 0, hstride(bi, lcols),
+                     lcols, 0, 0, 0, 0};
     if (S.sweeps > 0) {
       const Box& pb = M.pboxes[i];
-      P.pj = FactorJob{pb.x0, pb.y0, pb.bx(), pb.by(), 0, whole(pb) ? 1 : 0, qstride(pb), 0,
-                       0, 0, -1, -1};
+      P.pj = FactorJob{pb.x0, pb.y0, pb.bx(), pb.by(), 0, whole(pb) ? 1 : 0,
+                       hstride(pb, pcols), pcols, 0, 0, -1, -1};
     }
     P.oj = FactorJob{oi.x0, oi.y0, oi.bx(), oi.by(), 1, whole(oi) ? 1 : 0, 0, 0, -1, -1, 0, 0};
     SubJob& sj = P.sj;

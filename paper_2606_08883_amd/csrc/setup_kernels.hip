@@ -126,11 +126,17 @@ __global__ void __launch_bounds__(64)
     if (J.d64 >= 0)
       for (int e = lane; e < n * n; e += 64) d64[J.d64 + (long long)j * n * n + e] = D[e];
     if (J.doffS >= 0) {
-      // quad layout: word (q n + r) 4 + i holds D(4 q + i, r), zero past the block
-      const int nq = (n + 3) >> 2;
-      for (int w = lane; w < J.bs; w += 64) {
-        const int q = w / (4 * n), r = (w >> 2) % n, row = 4 * q + (w & 3);
-        dS[J.doffS + (long long)j * J.bs + w] = (q < nq && row < n) ? (S)D[row * n + r] : S(0);
+      // half-block layout (setup_jobs.h): row k of lane r is D(r, (r + k) mod
+      // n) for k <= n / 2, halved for k = n / 2 when n is even, zero beyond
+      const int rows = half_rows(J.cols), h = n / 2;
+      for (int w = lane; w < rows * n; w += 64) {
+        const int k = w / n, r = w - k * n;
+        double v = 0.0;
+        if (k <= h) {
+          v = D[r * n + (r + k) % n];
+          if (2 * k == n) v *= 0.5;
+        }
+        dS[J.doffS + (long long)j * J.bs + half_word(k, r, n, J.cols)] = (S)v;
       }
     }
     double* t = P;
