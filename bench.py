@@ -36,7 +36,7 @@ CSRC = os.path.join(ROOT, "paper_2606_08883_amd", "csrc")
 def kernel_source_hash() -> str:
     """First 16 hex digits of the sha256 of the kernel sources."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "device.h"):
+    for f in ("kernels.hip", "device.h", "setup_jobs.h"):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -73,22 +73,33 @@ PRECISION_NAMES = {0: "fp64", 1: "fp32 local/smoothing apply, fp64 interface + k
                    2: "fp32 factor storage with fp64 arithmetic, fp64 interface + krylov"}
 
 
+def box_cols(max_bx: int) -> int:
+    """Column width of a box launch (the library's launch widths)."""
+    for c in (16, 20, 24, 32, 36, 40, 48):
+        if max_bx <= c:
+            return c
+    return 64
+
+
 def algorithmic_bytes(cfg, maps, tw: int, sw: int) -> dict:
     """Algorithmic bytes of one launch of the local and patch kernels
     (tw: bytes of a work-vector word, sw: bytes of a stored factor word).
 
-    Local solve of subdomain i (bx x by cells): the D_j^-1 blocks (by bx^2
-    words) and couplings (by bx words) read once, r read (8 B/cell, FP64), p
-    written (tw/cell), trace-moment weights read (2 x 8 B per face of every
-    dof) and moments written (16 B per dof).
+    The factor of a box bx cells wide and by rows is stored as by half
+    blocks of rows x bx words (rows = cols / 2 + 1, cols the launch's column
+    width) plus by x bx couplings; the algorithmic count reads them once.
+    Local solve of subdomain i (bx x by cells): factor and couplings, r read
+    (8 B/cell, FP64), p written (tw/cell), trace-moment weights read (2 x 8 B
+    per face of every dof) and moments written (16 B per dof).
     Patch solve of patch i (px x py cells, owned bx x by): factor and
-    couplings read once, the residual read on the patch (tw/cell), p read
-    and written on the owned cells (2 tw/cell).
+    couplings, the residual read on the patch (tw/cell), p read and written
+    on the owned cells (2 tw/cell).
     """
     b = maps["boxes"]
     bx = (b[:, 1] - b[:, 0]).astype(np.int64)
     by = (b[:, 3] - b[:, 2]).astype(np.int64)
-    local = int(np.sum(by * bx * bx * sw + by * bx * sw + by * bx * 8 + by * bx * tw))
+    lrows = box_cols(int(bx.max())) // 2 + 1
+    local = int(np.sum(by * bx * lrows * sw + by * bx * sw + by * bx * 8 + by * bx * tw))
     dofs = maps["dof_table"]
     sides = dofs[:, 1]
     lens = np.where(sides <= 1, by[dofs[:, 0]], bx[dofs[:, 0]])
@@ -96,7 +107,8 @@ def algorithmic_bytes(cfg, maps, tw: int, sw: int) -> dict:
     p = maps["pboxes"]
     px = (p[:, 1] - p[:, 0]).astype(np.int64)
     py = (p[:, 3] - p[:, 2]).astype(np.int64)
-    patch = int(np.sum(py * px * px * sw + py * px * sw + py * px * tw + 2 * bx * by * tw))
+    prows = box_cols(int(px.max())) // 2 + 1
+    patch = int(np.sum(py * px * prows * sw + py * px * sw + py * px * tw + 2 * bx * by * tw))
     return {"local": local, "patch": patch}
 
 

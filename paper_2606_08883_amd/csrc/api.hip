@@ -313,12 +313,13 @@ void upload_coarse(mrcm_ctx* c, const mrcm::CoarseFactor& F, const mrcm::HostSet
       const auto& cn = F.nodes[t];
       if (cn.depth != d) continue;
       const int nf = (int)cn.frow.size(), nu = (int)cn.urow.size();
-      const int step = nu > 0 ? slice_rows(nu) : std::max(nf, 1);
+      if (nu == 0) continue;  // x_F = y_F, written by the forward level
+      const int step = slice_rows(nu);
       for (int r0 = 0; r0 < nf; r0 += step)
         chunks.push_back(CChunk{r0, std::min(nf, r0 + step), nf, nu, cn.yoff, cn.coff,
                                 fcol_off[t], ucol_off[t], bwd_off[t]});
     }
-    c->bwd_levels.push_back({first, (int)chunks.size() - first});
+    if ((int)chunks.size() > first) c->bwd_levels.push_back({first, (int)chunks.size() - first});
   }
   // right-hand-side sources and contribution destinations by tree position
   const int np = F.ylen;
@@ -372,7 +373,7 @@ void apply_one(mrcm_ctx* c, mrcm_ctx::Lane& L, const double* r, double* z, hipSt
     mrcm::launch_coarse_rhs(c->gsrc, c->gscale, L.mU, L.mP, L.g_nd, c->np, s);
     for (const auto& lv : c->fwd_levels)
       mrcm::launch_coarse_fwd(c->chunks + lv.first, lv.second, c->cfwd, L.g_nd, L.contrib,
-                              c->maxp, c->np, c->cdest, L.ybuf, c->max_nf, s);
+                              c->maxp, c->np, c->cdest, L.ybuf, c->cidx, L.xc, c->max_nf, s);
     for (const auto& lv : c->bwd_levels)
       mrcm::launch_coarse_bwd(c->chunks + lv.first, lv.second, c->cbwd, c->cidx, L.ybuf,
                               L.xc, c->max_nu, s);
@@ -456,7 +457,8 @@ void apply_k(mrcm_ctx* c, mrcm_ctx::Batch& B, int k, const double* const* r, dou
     mrcm::launch_coarse_rhs_k(k, c->gsrc, c->gscale, B.mU, B.mP, B.g_nd, c->np, c->nc, s);
     for (const auto& lv : c->fwd_levels)
       mrcm::launch_coarse_fwd_k(k, c->chunks + lv.first, lv.second, c->cfwd, B.g_nd, B.contrib,
-                                c->maxp, c->np, c->cdest, B.ybuf, c->max_nf, s);
+                                c->maxp, c->np, c->cdest, B.ybuf, c->cidx, B.xc, c->nc,
+                                c->max_nf, s);
     for (const auto& lv : c->bwd_levels)
       mrcm::launch_coarse_bwd_k(k, c->chunks + lv.first, lv.second, c->cbwd, c->cidx, B.ybuf,
                                 B.xc, c->max_nu, c->np, c->nc, s);

@@ -68,12 +68,13 @@ void launch_local(const BoxDesc* boxes, int m, int max_cells, int max_bx, const 
 // launch per tree level, forward levels leaves first, backward levels root
 // first.  contrib (maxp slots per tree position, slot u of position t at
 // u * np + t, zero where unused) receives the descendants' contributions at
-// cdest; max_nf / max_nu bound the LDS vector.
+// cdest; max_nf / max_nu bound the LDS vector.  A node without border rows
+// (the root) writes its x_F in its forward level and has no backward level.
 void launch_coarse_rhs(const int4* gsrc, const double* gscale, const double* mU,
                        const double* mP, double* g_nd, int np, hipStream_t s);
 void launch_coarse_fwd(const CChunk* chunks, int nchunks, const double* fwd, const double* g_nd,
                        double* contrib, int maxp, int np, const int* cdest, double* ybuf,
-                       int max_nf, hipStream_t s);
+                       const int* idx, double* x, int max_nf, hipStream_t s);
 void launch_coarse_bwd(const CChunk* chunks, int nchunks, const double* bwd, const int* idx,
                        const double* ybuf, double* x, int max_nu, hipStream_t s);
 template <typename T, typename S>
@@ -106,7 +107,8 @@ void launch_coarse_rhs_k(int k, const int4* gsrc, const double* gscale, const do
                          const double* mP, double* g_nd, int np, int nc, hipStream_t s);
 void launch_coarse_fwd_k(int k, const CChunk* chunks, int nchunks, const double* fwd,
                          const double* g_nd, double* contrib, int maxp, int np, const int* cdest,
-                         double* ybuf, int max_nf, hipStream_t s);
+                         double* ybuf, const int* idx, double* x, int nc, int max_nf,
+                         hipStream_t s);
 void launch_coarse_bwd_k(int k, const CChunk* chunks, int nchunks, const double* bwd,
                          const int* idx, const double* ybuf, double* x, int max_nu, int np, int nc,
                          hipStream_t s);

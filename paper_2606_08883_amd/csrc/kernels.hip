@@ -586,73 +586,176 @@ __device__ __forceinline__ void gemv_chunk(const double* __restrict__ M, int nco
   }
 }
 
+// Sums of N values (a power of two, 2..64) over the 64 lanes of the wave, all
+// at once: at the exchange with lane ^ off (off = 32, 16, ..., 1) a lane
+// keeps half of its values, and the sum of each kept value is its own plus
+// the partner's, so every value meets the pairs of wave_sum in the same order
+// (each result is bit-identical to wave_sum of that value) with 2N - 1 + 6 -
+// log2 N exchanges instead of 6 N.  Afterwards v[0] in lane l is the sum of
+// value butterfly_index<N>(l).
+template <int N>
+__device__ __forceinline__ int butterfly_index(int lane) {
+  int idx = 0, n = N;
+#pragma unroll
+  for (int off = 32; off > 0 && n > 1; off >>= 1) {
+    n >>= 1;
+    if (lane & off) idx += n;
+  }
+  return idx;
+}
+template <int N>
+__device__ __forceinline__ void butterfly_sum(double (&v)[N], int lane) {
+#pragma unroll
+  for (int st = 0; st < 6; ++st) {
+    const int off = 32 >> st;
+    const int n = N >> st;  // values still held (compile-time after unrolling)
+    if (n > 1) {
+      const int half = n >> 1;
+      const bool upper = (lane & off) != 0;
+#pragma unroll
+      for (int i = 0; i < N / 2; ++i)
+        if (i < half) {
+          const double send = upper ? v[i] : v[i + half];
+          const double keep = upper ? v[i + half] : v[i];
+          v[i] = keep + __shfl_xor(send, off, 64);
+        }
+    } else {
+      v[0] += __shfl_xor(v[0], off, 64);
+    }
+  }
+}
+
+// A chunk of at most 16 rows and ncol <= 128 columns taken whole by one
+// wave: lane l loads columns l and l + 64 of every row, all at once, and the
+// sixteen row sums are reduced together; afterwards lane l holds the sum of
+// row row0 + butterfly_index<16>(l).  Each lane's partial sums and the
+// reduction tree are those of gemv_chunk, so the results are the same.
+__device__ __forceinline__ void load_chunk16(double (&m)[16][2], const double* __restrict__ M,
+                                             int ncol, int row0, int row1, int lane) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int b = lane + 64 * q;
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      m[u][q] = (b < ncol && row0 + u < row1) ? M[(long long)(row0 + u) * ncol + b] : 0.0;
+  }
+}
+__device__ __forceinline__ double gemv_chunk16(const double (&m)[16][2], const double* vec,
+                                               int ncol, int lane) {
+  double x[2], s[16];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) x[q] = lane + 64 * q < ncol ? vec[lane + 64 * q] : 0.0;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) s[u] = 0.0;
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s[u] = fmat(m[u][q], x[q], s[u]);
+  butterfly_sum<16>(s, lane);
+  return s[0];
+}
+// Whether a chunk is taken whole by a one-wave workgroup.
+__device__ __forceinline__ bool whole_chunk(const CChunk& ch, int ncol) {
+  return blockDim.x == 64 && ncol <= 128 && ch.row1 - ch.row0 <= 16;
+}
+
 // Forward level: for the separator rows a of the chunk's node (tree
 // positions t = yoff + a),
 //   v[a] = g_nd[t] - (contributions of the descendants, in slot order),
 // with the contributions by destination in contrib[u * np + t] (slot u,
-// zero where unused).  Then rows of [W; E] v: y_F into ybuf, each c_n row
-// into its destination slot cdest[coff + row - nf].
+// zero where unused).  Then rows of [W; E] v: y_F into ybuf (straight into
+// x through idx for a node without border rows, whose x_F = y_F), each c_n
+// row into its destination slot cdest[coff + row - nf].
 __global__ void __launch_bounds__(kVecThreads)
     k_coarse_fwd(const CChunk* __restrict__ chunks, const double* __restrict__ fwd,
                  const double* __restrict__ g_nd, double* __restrict__ contrib, int maxp, int np,
-                 const int* __restrict__ cdest, double* __restrict__ ybuf) {
+                 const int* __restrict__ cdest, double* __restrict__ ybuf,
+                 const int* __restrict__ idx, double* __restrict__ x) {
   extern __shared__ double v[];
   const CChunk ch = chunks[blockIdx.x];
-  const int nf = ch.nf;
+  const int nf = ch.nf, lane = threadIdx.x & 63;
   const double* M = fwd + ch.mat;
   const int yoff = ch.yoff, coff = ch.coff;
   int dst = -1;
+  auto gather = [&]() {
+    for (int a = threadIdx.x; a < nf; a += blockDim.x) {
+      const long long t = (long long)yoff + a;
+      double s = g_nd[t];
+      for (int u0 = 0; u0 < maxp; u0 += 8) {
+        double c[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          c[k] = u0 + k < maxp ? contrib[(long long)(u0 + k) * np + t] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (u0 + k < maxp) s -= c[k];
+      }
+      v[a] = s;
+    }
+    __syncthreads();
+  };
+  auto emit = [&](int row, double val) {
+    if (row >= nf)
+      contrib[dst] = val;
+    else if (ch.nu == 0)
+      x[idx[ch.fcol + row]] = val;  // a node without border rows: x_F = y_F
+    else
+      ybuf[yoff + row] = val;
+  };
+  if (whole_chunk(ch, nf)) {
+    double m[16][2];
+    load_chunk16(m, M, nf, ch.row0, ch.row1, lane);
+    const int row = ch.row0 + butterfly_index<16>(lane);
+    dst = (row >= nf && row < ch.row1) ? cdest[coff + row - nf] : -1;
+    gather();
+    const double val = gemv_chunk16(m, v, nf, lane);
+    if ((lane & 3) == 0 && row < ch.row1) emit(row, val);
+    return;
+  }
   auto pre = [&](int r) {
-    const int lane = threadIdx.x & 63, row = r + lane;
+    const int row = r + lane;
     dst = (lane < 4 && row >= nf && row < ch.row1) ? cdest[coff + row - nf] : -1;
   };
   double m[4][8];
   const int rw = ch.row0 + 4 * (threadIdx.x >> 6);
-  load_tile(m, M, nf, rw, ch.row1, threadIdx.x & 63);
+  load_tile(m, M, nf, rw, ch.row1, lane);
   pre(rw);
-  for (int a = threadIdx.x; a < nf; a += blockDim.x) {
-    const long long t = (long long)yoff + a;
-    double s = g_nd[t];
-    for (int u0 = 0; u0 < maxp; u0 += 8) {
-      double c[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k)
-        c[k] = u0 + k < maxp ? contrib[(long long)(u0 + k) * np + t] : 0.0;
-#pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (u0 + k < maxp) s -= c[k];
-    }
-    v[a] = s;
-  }
-  __syncthreads();
-  gemv_chunk(M, nf, ch.row0, ch.row1, v, m, pre, [&](int row, double val) {
-    if (row < nf)
-      ybuf[yoff + row] = val;
-    else
-      contrib[dst] = val;
-  });
+  gather();
+  gemv_chunk(M, nf, ch.row0, ch.row1, v, m, pre, emit);
 }
 
 // Backward level: x_F = y_F - G x_U for the chunk's rows (x_U gathered
-// through idx[ucol ..], x_F scattered through idx[fcol ..]).
+// through idx[ucol ..], x_F scattered through idx[fcol ..]; nu > 0).
 __global__ void __launch_bounds__(kVecThreads)
     k_coarse_bwd(const CChunk* __restrict__ chunks, const double* __restrict__ bwd,
                  const int* __restrict__ idx, const double* __restrict__ ybuf,
                  double* __restrict__ x) {
   extern __shared__ double xu[];
   const CChunk ch = chunks[blockIdx.x];
-  const int nu = ch.nu;
+  const int nu = ch.nu, lane = threadIdx.x & 63;
   const double* M = bwd + ch.mat;
   const int yoff = ch.yoff, fcol = ch.fcol;
-  if (nu == 0) {
-    for (int row = ch.row0 + threadIdx.x; row < ch.row1; row += blockDim.x)
-      x[idx[fcol + row]] = ybuf[yoff + row];
-    return;
-  }
   int dst = 0;
   double y = 0.0;
+  auto gather = [&]() {
+    for (int b = threadIdx.x; b < nu; b += blockDim.x) xu[b] = x[idx[ch.ucol + b]];
+    __syncthreads();
+  };
+  if (whole_chunk(ch, nu)) {
+    double m[16][2];
+    load_chunk16(m, M, nu, ch.row0, ch.row1, lane);
+    const int row = ch.row0 + butterfly_index<16>(lane);
+    if (row < ch.row1) {
+      dst = idx[fcol + row];
+      y = ybuf[yoff + row];
+    }
+    gather();
+    const double val = gemv_chunk16(m, xu, nu, lane);
+    if ((lane & 3) == 0 && row < ch.row1) x[dst] = y - val;
+    return;
+  }
   auto pre = [&](int r) {
-    const int lane = threadIdx.x & 63, row = r + lane;
+    const int row = r + lane;
     if (lane < 4 && row < ch.row1) {
       dst = idx[fcol + row];
       y = ybuf[yoff + row];
@@ -660,10 +763,9 @@ __global__ void __launch_bounds__(kVecThreads)
   };
   double m[4][8];
   const int rw = ch.row0 + 4 * (threadIdx.x >> 6);
-  load_tile(m, M, nu, rw, ch.row1, threadIdx.x & 63);
+  load_tile(m, M, nu, rw, ch.row1, lane);
   pre(rw);
-  for (int b = threadIdx.x; b < nu; b += blockDim.x) xu[b] = x[idx[ch.ucol + b]];
-  __syncthreads();
+  gather();
   gemv_chunk(M, nu, ch.row0, ch.row1, xu, m, pre, [&](int, double val) { x[dst] = y - val; });
 }
 
@@ -1340,45 +1442,6 @@ __device__ __forceinline__ void fma_tile_k(double (&s)[4][K], const double (&m)[
   }
 }
 
-// Sums of N values (a power of two, 2..64) over the 64 lanes of the wave, all
-// at once: at the exchange with lane ^ off (off = 32, 16, ..., 1) a lane
-// keeps half of its values, and the sum of each kept value is its own plus
-// the partner's, so every value meets the pairs of wave_sum in the same order
-// (each result is bit-identical to wave_sum of that value) with 2N - 1 + 6 -
-// log2 N exchanges instead of 6 N.  Afterwards v[0] in lane l is the sum of
-// value butterfly_index<N>(l).
-template <int N>
-__device__ __forceinline__ int butterfly_index(int lane) {
-  int idx = 0, n = N;
-#pragma unroll
-  for (int off = 32; off > 0 && n > 1; off >>= 1) {
-    n >>= 1;
-    if (lane & off) idx += n;
-  }
-  return idx;
-}
-template <int N>
-__device__ __forceinline__ void butterfly_sum(double (&v)[N], int lane) {
-#pragma unroll
-  for (int st = 0; st < 6; ++st) {
-    const int off = 32 >> st;
-    const int n = N >> st;  // values still held (compile-time after unrolling)
-    if (n > 1) {
-      const int half = n >> 1;
-      const bool upper = (lane & off) != 0;
-#pragma unroll
-      for (int i = 0; i < N / 2; ++i)
-        if (i < half) {
-          const double send = upper ? v[i] : v[i + half];
-          const double keep = upper ? v[i + half] : v[i];
-          v[i] = keep + __shfl_xor(send, off, 64);
-        }
-    } else {
-      v[0] += __shfl_xor(v[0], off, 64);
-    }
-  }
-}
-
 // gemv_chunk for K columns of the LDS matrix vec (column k at vec + k * ld).
 // After the butterfly, lane l holds output (row r + u_l, column k_l) with
 // u_l * K + k_l = butterfly_index(l); pre(row, k) runs in every lane for its
@@ -1417,13 +1480,14 @@ __device__ __forceinline__ void gemv_chunk_k(const double* __restrict__ M, int n
   }
 }
 
-// k_coarse_fwd for K columns (column k of g_nd, contrib and ybuf at offsets
-// k * np, k * maxp * np and k * np).
+// k_coarse_fwd for K columns (column k of g_nd, contrib, ybuf and x at
+// offsets k * np, k * maxp * np, k * np and k * nc).
 template <int K>
 __global__ void __launch_bounds__(kVecThreads)
     k_coarse_fwd_k(const CChunk* __restrict__ chunks, const double* __restrict__ fwd,
                    const double* __restrict__ g_nd, double* __restrict__ contrib, int maxp,
-                   int np, const int* __restrict__ cdest, double* __restrict__ ybuf) {
+                   int np, const int* __restrict__ cdest, double* __restrict__ ybuf,
+                   const int* __restrict__ idx, double* __restrict__ x, int nc) {
   extern __shared__ double v[];
   const CChunk ch = chunks[blockIdx.x];
   const int nf = ch.nf;
@@ -1458,10 +1522,12 @@ __global__ void __launch_bounds__(kVecThreads)
   }
   __syncthreads();
   gemv_chunk_k<K>(M, nf, ch.row0, ch.row1, v, nf, m, pre, [&](int row, int k, double val) {
-    if (row < nf)
-      ybuf[(long long)k * np + yoff + row] = val;
-    else
+    if (row >= nf)
       contrib[k * cstride + dst] = val;
+    else if (ch.nu == 0)
+      x[(long long)k * nc + idx[ch.fcol + row]] = val;
+    else
+      ybuf[(long long)k * np + yoff + row] = val;
   });
 }
 
@@ -1477,13 +1543,6 @@ __global__ void __launch_bounds__(kVecThreads)
   const int nu = ch.nu;
   const double* M = bwd + ch.mat;
   const int yoff = ch.yoff, fcol = ch.fcol;
-  if (nu == 0) {
-    for (int e = threadIdx.x; e < (ch.row1 - ch.row0) * K; e += blockDim.x) {
-      const int k = e / (ch.row1 - ch.row0), row = ch.row0 + e - k * (ch.row1 - ch.row0);
-      x[(long long)k * nc + idx[fcol + row]] = ybuf[(long long)k * np + yoff + row];
-    }
-    return;
-  }
   int dst = 0;
   double y = 0.0;
   auto pre = [&](int row, int k) {
@@ -1700,19 +1759,20 @@ void launch_coarse_rhs(const int4* gsrc, const double* gscale, const double* mU,
   hipLaunchKernelGGL(k_coarse_rhs, dim3((np + 255) / 256), dim3(256), 0, s, gsrc, gscale, mU, mP,
                      g_nd, np);
 }
-// Threads per chunk of an interface level: levels with many chunks (the
-// lower ones, small fronts) take one wave per chunk, so that about a dozen
-// chunks are resident per compute unit and the level runs in one round;
-// levels with few, large chunks take four waves per chunk.
-static int coarse_threads(int nchunks) { return nchunks >= 1024 ? 64 : kVecThreads; }
+// Threads per chunk of an interface level: levels with very many chunks
+// (the leaves: small fronts) take one wave per chunk, which takes its chunk
+// whole, so that every chunk of the level is resident at once; the other
+// levels take four waves per chunk (a sweep of the threshold over 0, 1024,
+// 2048 and never found 2048 best at 1024^2 and 4096^2).
+static int coarse_threads(int nchunks) { return nchunks >= 2048 ? 64 : kVecThreads; }
 
 void launch_coarse_fwd(const CChunk* chunks, int nchunks, const double* fwd, const double* g_nd,
                        double* contrib, int maxp, int np, const int* cdest, double* ybuf,
-                       int max_nf, hipStream_t s) {
+                       const int* idx, double* x, int max_nf, hipStream_t s) {
   if (nchunks <= 0) return;
   hipLaunchKernelGGL(k_coarse_fwd, dim3(nchunks), dim3(coarse_threads(nchunks)),
                      sizeof(double) * (size_t)(max_nf > 0 ? max_nf : 1), s, chunks, fwd, g_nd,
-                     contrib, maxp, np, cdest, ybuf);
+                     contrib, maxp, np, cdest, ybuf, idx, x);
 }
 void launch_coarse_bwd(const CChunk* chunks, int nchunks, const double* bwd, const int* idx,
                        const double* ybuf, double* x, int max_nu, hipStream_t s) {
@@ -1858,7 +1918,8 @@ static int coarse_width(int k, int max_dim) {
 
 void launch_coarse_fwd_k(int k, const CChunk* chunks, int nchunks, const double* fwd,
                          const double* g_nd, double* contrib, int maxp, int np, const int* cdest,
-                         double* ybuf, int max_nf, hipStream_t s) {
+                         double* ybuf, const int* idx, double* x, int nc, int max_nf,
+                         hipStream_t s) {
   check_k(k);
   if (nchunks <= 0) return;
   const int w = coarse_width(k, max_nf);
@@ -1866,16 +1927,18 @@ void launch_coarse_fwd_k(int k, const CChunk* chunks, int nchunks, const double*
     const double* g = g_nd + (long long)k0 * np;
     double* c = contrib + (long long)k0 * maxp * np;
     double* y = ybuf + (long long)k0 * np;
+    double* xk = x + (long long)k0 * nc;
     const size_t shm = sizeof(double) * (size_t)w * (max_nf > 0 ? max_nf : 1);
     const dim3 grid(nchunks), block(coarse_threads(nchunks));
     if (w == 1)
-      hipLaunchKernelGGL(k_coarse_fwd, grid, block, shm, s, chunks, fwd, g, c, maxp, np, cdest, y);
+      hipLaunchKernelGGL(k_coarse_fwd, grid, block, shm, s, chunks, fwd, g, c, maxp, np, cdest, y,
+                         idx, xk);
     else if (w == 2)
       hipLaunchKernelGGL(k_coarse_fwd_k<2>, grid, block, shm, s, chunks, fwd, g, c, maxp, np, cdest,
-                         y);
+                         y, idx, xk, nc);
     else
       hipLaunchKernelGGL(k_coarse_fwd_k<4>, grid, block, shm, s, chunks, fwd, g, c, maxp, np, cdest,
-                         y);
+                         y, idx, xk, nc);
   }
 }
 

@@ -79,3 +79,25 @@ def test_multi_rhs_apply_timing_phases(dev):
     assert all(ph[name][1] == 1 for name in ("local", "coarse", "reconstruct", "residual",
                                              "patch", "finalize"))
     ctx.close()
+
+
+def test_multi_rhs_apply_equals_columns_fullsize(dev):
+    """At 1024^2 the leaf levels of the interface solve have thousands of
+    chunks and run as one-wave workgroups that take their chunk whole; the
+    multi-column kernels must still reproduce them bit for bit."""
+    from paper_2606_08883_amd.configs import WORKLOADS
+    w = WORKLOADS["batched"]
+    K = torch.tensor(w.permeability(), dtype=torch.float64, device=dev)
+    ctx = B.Context(w.binding_config(), K)
+    n = w.nx * w.ny
+    r = torch.tensor(np.stack([wl.random_vector(n, 400 + k, zero_mean=True) for k in range(3)]),
+                     dtype=torch.float64, device=dev).contiguous()
+    z = torch.full_like(r, np.nan)
+    ctx.apply(r, z)
+    zc = torch.full_like(r, np.nan)
+    for k in range(3):
+        ctx.apply(r[k].contiguous(), zc[k])
+    torch.cuda.synchronize()
+    assert torch.isfinite(z).all()
+    assert torch.equal(z, zc)
+    ctx.close()
