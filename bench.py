@@ -112,6 +112,19 @@ def algorithmic_bytes(cfg, maps, tw: int, sw: int) -> dict:
     return {"local": local, "patch": patch}
 
 
+def interface_solve(ctx, phases) -> dict:
+    """The interface solve (right-hand side, forward and backward levels),
+    reported beside the roofline: its levels are latency-bound (each a
+    dependent launch reading a few MB), so its effective bandwidth, the
+    factor bytes per apply over its time per apply, sits far below the HBM
+    peak."""
+    ms = phases["coarse"][0] / max(1, phases["coarse"][1])
+    nbytes = ctx.query("coarse_bytes")
+    return {"bound": "latency", "launches_per_apply": int(ctx.query("coarse_launches")) + 1,
+            "factor_bytes_per_apply": nbytes, "ms_per_apply": ms,
+            "effective_GB_s": nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None}
+
+
 def cpu_baseline(workload_name: str, gpu_iterations: int, budget_s: float = 25.0) -> dict:
     """Time the oracle (as it stands) on the host: its setup for the same
     workload, then GMRES inner steps until the budget is spent; the solve
@@ -195,7 +208,8 @@ def apply_only(args, w, ctx, b, setup_s) -> int:
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                         "traffic": recorded_traffic(f"k_{dom}", f"{w.name}{w.nx}",
                                                     w.precision),
-                        "traffic_unit": "bytes per launch", "avg_launch_ms": avg_ms}}
+                        "traffic_unit": "bytes per launch", "avg_launch_ms": avg_ms},
+           "interface_solve": interface_solve(ctx, phases)}
     print(json.dumps(out), flush=True)
     ctx.close()
     return 0
@@ -428,6 +442,7 @@ def main() -> int:
                      "traffic_unit": "bytes per launch",
                      "algorithmic_bytes_per_launch": abytes[dom],
                      "avg_launch_ms": avg_ms},
+        "interface_solve": interface_solve(ctx, phases),
     }
     if multi:
         out["multi_rhs"] = multi

@@ -232,13 +232,19 @@ int mrcm_timing_read(mrcm_ctx* ctx, double* ms, int64_t* counts);
  *  MRCM_Q_COARSE_PIVOT    smallest |pivot| / max|row| met while factorising the
  *                         row-equilibrated interface system (its conditioning);
  *  MRCM_Q_COARSE_LEVELS   levels of the nested-dissection interface solve;
- *  MRCM_Q_COARSE_DOFS     interface unknowns nc. */
+ *  MRCM_Q_COARSE_DOFS     interface unknowns nc;
+ *  MRCM_Q_COARSE_BYTES    bytes of the interface factor one solve reads (the
+ *                         forward and backward matrices of every tree node);
+ *  MRCM_Q_COARSE_LAUNCHES kernel launches of one interface solve (its levels,
+ *                         forward and backward). */
 enum {
   MRCM_Q_SETUP_SECONDS = 0,
   MRCM_Q_DEVICE_BYTES = 1,
   MRCM_Q_COARSE_PIVOT = 2,
   MRCM_Q_COARSE_LEVELS = 3,
-  MRCM_Q_COARSE_DOFS = 4
+  MRCM_Q_COARSE_DOFS = 4,
+  MRCM_Q_COARSE_BYTES = 5,
+  MRCM_Q_COARSE_LAUNCHES = 6
 };
 int mrcm_query(mrcm_ctx* ctx, int32_t what, double* value);
 

@@ -27,7 +27,7 @@ EXPORTED = ["mrcm_map_sizes", "mrcm_maps", "mrcm_setup", "mrcm_apply", "mrcm_app
             "mrcm_destroy",
             "mrcm_last_error"]
 QUERIES = {"setup_seconds": 0, "device_bytes": 1, "coarse_pivot": 2, "coarse_levels": 3,
-           "coarse_dofs": 4}
+           "coarse_dofs": 4, "coarse_bytes": 5, "coarse_launches": 6}
 PHASES = ["local", "coarse", "reconstruct", "residual", "patch", "finalize"]
 TEST_EXPORTED = ["mrcm_test_coarse_sizes", "mrcm_test_coarse_matrix", "mrcm_test_host_apply"]
 
@@ -315,7 +315,8 @@ class Context:
         return t.numel() // self.n
 
     def query(self, what: str) -> float:
-        """mrcm_query: setup_seconds, device_bytes, coarse_pivot, coarse_levels, coarse_dofs."""
+        """mrcm_query: setup_seconds, device_bytes, coarse_pivot, coarse_levels, coarse_dofs,
+        coarse_bytes, coarse_launches."""
         v = ctypes.c_double()
         _check(lib().mrcm_query(self._ptr, QUERIES[what], ctypes.byref(v)))
         return v.value

@@ -88,6 +88,7 @@ struct mrcm_ctx {
   double setup_seconds = 0.0;
   double coarse_pivot = 1.0;
   int coarse_levels = 0;
+  double coarse_bytes = 0.0;  // interface factor bytes read per solve
   size_t device_bytes = 0;
   // per-phase event timing
   static constexpr int kPhases = 6;
@@ -335,6 +336,7 @@ void upload_coarse(mrcm_ctx* c, const mrcm::CoarseFactor& F, const mrcm::HostSet
       const int q = F.slots[(size_t)t * F.maxp + u];
       if (q >= 0) cdest[q] = u * np + t;
     }
+  c->coarse_bytes = 8.0 * ((double)fwd.size() + (double)bwd.size());
   c->cfwd = c->upload(fwd, s);
   c->cbwd = c->upload(bwd, s);
   c->cidx = c->upload(idx, s);
@@ -1357,6 +1359,10 @@ int mrcm_query(mrcm_ctx* c, int32_t what, double* value) {
       case MRCM_Q_COARSE_PIVOT: *value = c->coarse_pivot; break;
       case MRCM_Q_COARSE_LEVELS: *value = c->coarse_levels; break;
       case MRCM_Q_COARSE_DOFS: *value = c->nc; break;
+      case MRCM_Q_COARSE_BYTES: *value = c->coarse_bytes; break;
+      case MRCM_Q_COARSE_LAUNCHES:
+        *value = (double)(c->fwd_levels.size() + c->bwd_levels.size());
+        break;
       default: throw mrcm::Error(MRCM_EINVAL, "unknown query");
     }
     return MRCM_OK;
