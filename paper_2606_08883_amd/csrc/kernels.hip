@@ -278,7 +278,8 @@ __device__ __forceinline__ int wave_max(int v) {
 // up to a multiple of DEPTH); a group's steps past its own nsteps re-load its
 // last block and are told valid = false.  No load is conditional, so the
 // compiler counts the loads in flight exactly and waits only for the block
-// a step uses.
+// a step uses (an early exit from the unrolled steps instead of the rounding
+// made the compiler wait for more loads and was slower).
 template <typename S, int NB, int DEPTH, typename Blk, typename Step>
 __device__ __forceinline__ void pipelined_sweep(int nsteps, int nmax, Blk blk, Step step,
                                                 const S* __restrict__ Dinv, int bstride,
@@ -381,26 +382,33 @@ __device__ __forceinline__ void box_solve(T* us, T* vv, const S* cp, const S* __
       Dinv, bstride, bx, rc);
 }
 
-// Copy rows [0, by) of a box (bx cells wide, lane r: column r) from a global
-// grid vector into LDS, eight rows of loads in flight at a time.  Loads are
-// unconditional (row and column clamped into the box); the wave runs the
-// rows of its tallest box.
-template <typename T, typename G>
-__device__ __forceinline__ void rows_to_lds(T* dst, const G* __restrict__ src, long long origin,
-                                            int nx, int bx, int by, int lane, bool live) {
+// Stage a box for its solve: rows [0, by) of a grid vector (bx cells wide,
+// lane r: column r) and the box's couplings (by rows of bx words) into LDS,
+// sixteen rows of both in flight at a time, so that a box of up to sixteen
+// rows costs one memory latency.  Loads are unconditional (row and column
+// clamped into the box); the wave runs the rows of its tallest box.
+template <typename T, typename G, typename S>
+__device__ __forceinline__ void stage_box(T* dst, const G* __restrict__ src, long long origin,
+                                          int nx, S* cdst, const S* __restrict__ csrc, int bx,
+                                          int by, int lane, bool live) {
   const int rows = wave_max(live ? by : 0);
   const int col = lane < bx ? lane : bx - 1;
   const bool act = live && lane < bx;
-  for (int j0 = 0; j0 < rows; j0 += 8) {
-    G v[8];
+  for (int j0 = 0; j0 < rows; j0 += 16) {
+    G v[16];
+    S c[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 16; ++u) {
       const int j = j0 + u < by ? j0 + u : by - 1;
       v[u] = src[origin + (long long)j * nx + col];
+      c[u] = csrc[j * bx + col];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (act && j0 + u < by) dst[(j0 + u) * bx + lane] = (T)v[u];
+    for (int u = 0; u < 16; ++u)
+      if (act && j0 + u < by) {
+        dst[(j0 + u) * bx + lane] = (T)v[u];
+        cdst[(j0 + u) * bx + lane] = c[u];
+      }
   }
 }
 
@@ -466,8 +474,7 @@ __global__ void __launch_bounds__(kBoxThreads)
   const int bx = d.bx, by = d.by;
   const bool act = live && lane < bx;
   const long long origin = (long long)d.y0 * nx + d.x0;
-  rows_to_lds(L.us, r, origin, nx, bx, by, lane, live);
-  words_to_lds<S, GS>(L.cp, coup + d.coff, bx * by, lane, live);
+  stage_box(L.us, r, origin, nx, L.cp, coup + d.coff, bx, by, lane, live);
   zero_slots<T, GS>(L.vv, vec_words<NB, GS>(), lane);
   wave_sync();
   if (live && d.pin && lane == 0) L.us[0] = T(0);
@@ -484,16 +491,16 @@ __global__ void __launch_bounds__(kBoxThreads)
     const double* wu = wU + w_off[k];
     const double* wp = wP + w_off[k];
     double su = 0.0, sp = 0.0;
-    for (int j0 = 0; j0 < len; j0 += 8) {
-      double a[8], b[8];
+    for (int j0 = 0; j0 < len; j0 += 16) {
+      double a[16], b[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 16; ++u) {
         const int jf = j0 + u < len ? j0 + u : len - 1;
         a[u] = wu[jf];
         b[u] = wp[jf];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 16; ++u) {
         const int jf = j0 + u;
         if (jf < len) {
           const int cell = side == 0 ? jf * bx
@@ -822,8 +829,7 @@ __global__ void __launch_bounds__(kBoxThreads)
   const BoxDesc d = boxes[i];
   const int bx = d.bx, by = d.by;
   const long long origin = (long long)d.y0 * nx + d.x0;
-  rows_to_lds(L.us, rho, origin, nx, bx, by, lane, live);
-  words_to_lds<S, GS>(L.cp, coup + d.coff, bx * by, lane, live);
+  stage_box(L.us, rho, origin, nx, L.cp, coup + d.coff, bx, by, lane, live);
   zero_slots<T, GS>(L.vv, vec_words<NB, GS>(), lane);
   wave_sync();
   if (live && d.pin && lane == 0) L.us[0] = T(0);
@@ -831,20 +837,20 @@ __global__ void __launch_bounds__(kBoxThreads)
   box_solve<T, S, NB, GS>(L.us, L.vv, L.cp, dinv + d.doff, bx, by, d.bs, lane,
                          (threadIdx.x & 63) - lane, live);
   wave_sync();
-  // p += e on the owned cells, eight rows of read-modify-write in flight
+  // p += e on the owned cells, sixteen rows of read-modify-write in flight
   const bool own = live && lane >= d.ox && lane < d.ox + d.obx;
   const int col = own ? lane : d.ox;
   const long long o2 = origin + (long long)d.oy * nx;
   const int rows = wave_max(live ? d.oby : 0);
-  for (int j0 = 0; j0 < rows; j0 += 8) {
-    T v[8];
+  for (int j0 = 0; j0 < rows; j0 += 16) {
+    T v[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 16; ++u) {
       const int j = j0 + u < d.oby ? j0 + u : d.oby - 1;
       v[u] = p[o2 + (long long)j * nx + col];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < 16; ++u)
       if (own && j0 + u < d.oby)
         p[o2 + (long long)(j0 + u) * nx + lane] = v[u] + L.us[(d.oy + j0 + u) * bx + lane];
   }
