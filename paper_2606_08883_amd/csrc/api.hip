@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -52,6 +53,55 @@ int host_threads() {
 // pair it was created with, so its memory is always freed by the matching
 // function.
 std::mutex g_alloc_mutex;
+
+// Host-to-device copies of large host buffers go through two pinned staging
+// buffers (allocated on first use and kept until the process ends): the host
+// threads copy one piece into a buffer while the previous piece is on its way
+// to the device, so the transfer runs at DMA speed instead of the speed of
+// pageable copies.  Copies from different threads take turns.
+struct Stager {
+  static constexpr size_t kPiece = size_t(16) << 20;
+  std::mutex mu;
+  int device = -1;
+  char* buf[2] = {nullptr, nullptr};
+  hipEvent_t done[2] = {nullptr, nullptr};
+};
+Stager g_stager;
+
+void staged_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lock(g_stager.mu);
+  if (g_stager.device < 0) {
+    for (int k = 0; k < 2; ++k) {
+      hip_check(hipHostMalloc((void**)&g_stager.buf[k], Stager::kPiece, hipHostMallocDefault),
+                "hipHostMalloc");
+      hip_check(hipEventCreateWithFlags(&g_stager.done[k], hipEventDisableTiming),
+                "hipEventCreate");
+    }
+    g_stager.device = dev;
+  }
+  if (dev != g_stager.device) {  // events belong to the first device: copy directly
+    hip_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    return;
+  }
+  const int nth = host_threads();
+  int k = 0;
+  for (size_t off = 0; off < bytes; off += Stager::kPiece, k ^= 1) {
+    const size_t len = std::min(Stager::kPiece, bytes - off);
+    hip_check(hipEventSynchronize(g_stager.done[k]), "hipEventSynchronize");
+    const size_t part = (len + nth - 1) / nth;
+#pragma omp parallel for num_threads(nth) schedule(static)
+    for (int t = 0; t < nth; ++t) {
+      const size_t a = std::min(len, (size_t)t * part), b = std::min(len, a + part);
+      if (b > a) std::memcpy(g_stager.buf[k] + a, static_cast<const char*>(src) + off + a, b - a);
+    }
+    hip_check(hipMemcpyAsync(static_cast<char*>(dst) + off, g_stager.buf[k], len,
+                             hipMemcpyHostToDevice, s),
+              "hipMemcpyAsync");
+    hip_check(hipEventRecord(g_stager.done[k], s), "hipEventRecord");
+  }
+}
 mrcm_alloc_fn g_alloc = nullptr;
 mrcm_free_fn g_free = nullptr;
 
@@ -177,12 +227,18 @@ struct mrcm_ctx {
       (void)hipFree(p);
   }
   template <typename X>
-  X* upload(const std::vector<X>& v, hipStream_t s) {
-    X* d = alloc<X>(v.size());
-    if (!v.empty())
-      hip_check(hipMemcpyAsync(d, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice, s),
-                "hipMemcpyAsync");
+  X* upload(const X* v, size_t count, hipStream_t s) {
+    X* d = alloc<X>(count);
+    const size_t bytes = count * sizeof(X);
+    if (bytes >= (size_t(1) << 20))
+      staged_copy(d, v, bytes, s);
+    else if (bytes > 0)
+      hip_check(hipMemcpyAsync(d, v, bytes, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
     return d;
+  }
+  template <typename X>
+  X* upload(const std::vector<X>& v, hipStream_t s) {
+    return upload(v.data(), v.size(), s);
   }
   // Record an event on stream s (a graph node while capturing).
   hipEvent_t mark(hipStream_t s) {
@@ -270,23 +326,33 @@ std::vector<T> narrow(const std::vector<double>& v) {
 void upload_coarse(mrcm_ctx* c, const mrcm::CoarseFactor& F, const mrcm::HostSetup& S,
                    hipStream_t s) {
   const int nn = (int)F.nodes.size();
-  std::vector<double> fwd, bwd;
   std::vector<int> idx;
   std::vector<long long> fwd_off(nn), bwd_off(nn);
   std::vector<int> fcol_off(nn), ucol_off(nn);
   int max_nf = 1, max_nu = 1;
+  long long fwd_len = 0, bwd_len = 0;
   for (int t = 0; t < nn; ++t) {
     const auto& cn = F.nodes[t];
     fcol_off[t] = (int)idx.size();
     idx.insert(idx.end(), cn.fcol.begin(), cn.fcol.end());
     ucol_off[t] = (int)idx.size();
     idx.insert(idx.end(), cn.ucol.begin(), cn.ucol.end());
-    fwd_off[t] = (long long)fwd.size();
-    fwd.insert(fwd.end(), cn.fwd.begin(), cn.fwd.end());
-    bwd_off[t] = (long long)bwd.size();
-    bwd.insert(bwd.end(), cn.bwd.begin(), cn.bwd.end());
+    fwd_off[t] = fwd_len;
+    fwd_len += (long long)cn.fwd.size();
+    bwd_off[t] = bwd_len;
+    bwd_len += (long long)cn.bwd.size();
     max_nf = std::max(max_nf, (int)cn.frow.size());
     max_nu = std::max(max_nu, (int)cn.urow.size());
+  }
+  // the node matrices, concatenated by the host threads (uninitialised
+  // storage: every element is written)
+  std::unique_ptr<double[]> fwd(new double[std::max(fwd_len, 1LL)]);
+  std::unique_ptr<double[]> bwd(new double[std::max(bwd_len, 1LL)]);
+#pragma omp parallel for schedule(dynamic, 4) num_threads(host_threads())
+  for (int t = 0; t < nn; ++t) {
+    const auto& cn = F.nodes[t];
+    std::copy(cn.fwd.begin(), cn.fwd.end(), fwd.get() + fwd_off[t]);
+    std::copy(cn.bwd.begin(), cn.bwd.end(), bwd.get() + bwd_off[t]);
   }
   if (max_nf > 6144 || max_nu > 6144)
     throw mrcm::Error(MRCM_EINVAL, "interface separator too large for one workgroup");
@@ -336,9 +402,9 @@ void upload_coarse(mrcm_ctx* c, const mrcm::CoarseFactor& F, const mrcm::HostSet
       const int q = F.slots[(size_t)t * F.maxp + u];
       if (q >= 0) cdest[q] = u * np + t;
     }
-  c->coarse_bytes = 8.0 * ((double)fwd.size() + (double)bwd.size());
-  c->cfwd = c->upload(fwd, s);
-  c->cbwd = c->upload(bwd, s);
+  c->coarse_bytes = 8.0 * ((double)fwd_len + (double)bwd_len);
+  c->cfwd = c->upload(fwd.get(), (size_t)fwd_len, s);
+  c->cbwd = c->upload(bwd.get(), (size_t)bwd_len, s);
   c->cidx = c->upload(idx, s);
   c->gsrc = c->upload(gsrc, s);
   c->gscale = c->upload(F.nd_scale, s);

@@ -83,6 +83,9 @@ HOST_CASES = [
                                                   alpha=10.0, beta_len=0, sweeps=2)),
     ("degree-2", WORKLOADS["small"].with_(nx=40, ny=24, s=8, degree=2, oversample=0)),
     ("one-subdomain", WORKLOADS["small"].with_(nx=24, ny=20, s=24, oversample=0)),
+    # 256 subdomains: interface fronts past 64 rows take the blocked dense
+    # kernels and the column-parallel inverse of the interface factorisation
+    ("256-subdomains", WORKLOADS["small"].with_(nx=128, ny=128, s=8, oversample=2)),
 ]
 
 
