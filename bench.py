@@ -303,6 +303,53 @@ def multi_rhs(args, w, ctx) -> dict:
     return out
 
 
+INCLUSION_ROWS = [("MRCM", 0, 0), ("2h", 2, 0), ("4h", 4, 0), ("2h,2S", 2, 2), ("2h,4S", 2, 4),
+                  ("4h,2S", 4, 2), ("4h,4S", 4, 4)]
+
+
+def inclusions(args) -> int:
+    """GMRES(10) on the thin-inclusion fields (the stand-ins for the paper's
+    inclusion experiments): every row of the paper's tables (oversampling 0,
+    2 or 4 cells, 0, 2 or 4 smoothing sweeps) under 4 x 4 and 8 x 8
+    partitions, FP64, relative tolerance 1e-8.  Prints one JSON line with
+    the inner steps, restart cycles and final true residual of each run."""
+    import torch
+
+    from paper_2606_08883_amd import binding as B
+    from paper_2606_08883_amd.configs import WORKLOADS
+
+    dev = torch.device("cuda:0")
+    results = []
+    for kind in ("high", "low", "both"):
+        w0 = WORKLOADS[f"incl-{kind}"]
+        K = torch.tensor(w0.permeability(), dtype=torch.float64, device=dev)
+        f, g = w0.boundary_data()
+        ft = torch.tensor(f, dtype=torch.float64, device=dev)
+        gt = torch.tensor(g, dtype=torch.float64, device=dev)
+        for s in (40, 20):
+            for name, l, k in INCLUSION_ROWS:
+                w = w0.with_(s=s, oversample=l, sweeps=k)
+                print(f"bench: inclusions {kind} {160 // s}x{160 // s} {name}", file=sys.stderr,
+                      flush=True)
+                ctx = B.Context(w.binding_config(), K)
+                b = torch.empty(w.cells, dtype=torch.float64, device=dev)
+                ctx.rhs(ft, gt, 1.0 / w.nx, b)
+                p = torch.zeros_like(b)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = ctx.gmres(b, p, rtol=1e-8, restart=10, maxit=300, raise_on_noconv=False)
+                torch.cuda.synchronize()
+                results.append({"field": kind, "partition": f"{160 // s}x{160 // s}", "row": name,
+                                "iterations": st.iterations, "cycles": st.cycles,
+                                "converged": bool(st.converged), "final_relres": st.final_relres,
+                                "solve_ms": 1e3 * (time.perf_counter() - t0)})
+                ctx.close()
+    print(json.dumps({"metric": "GMRES(10) inner steps and restart cycles to rel.res 1e-8",
+                      "data": "synthetic thin-inclusion fields, 160x160, Dirichlet left/right",
+                      "dtype": "f64", "results": results}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +367,9 @@ def main() -> int:
                     help="serving workload: a Poisson stream of requests of mixed grid sizes "
                          "(128^2 .. 1024^2), each with its own log-normal field and 8 "
                          "injector/producer right-hand sides, served with continuous batching")
+    ap.add_argument("--inclusions", action="store_true",
+                    help="GMRES steps and cycles on the thin-inclusion fields for every "
+                         "oversampling / smoothing row of the paper's inclusion tables")
     ap.add_argument("--requests", type=int, default=48, help="requests of the serving run")
     ap.add_argument("--max-active", type=int, default=8, help="serving slots")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -349,6 +399,8 @@ def main() -> int:
 
     if args.serve:
         return serve(args)
+    if args.inclusions:
+        return inclusions(args)
 
     from paper_2606_08883_amd import binding as B
     from paper_2606_08883_amd.configs import WORKLOADS

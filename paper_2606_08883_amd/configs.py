@@ -20,6 +20,13 @@ restart 10 and relative tolerance 1e-8, interface degree 1, smoothing overlap
           contrast 1e8 (seeds 5, 6), 16384 subdomains of 32 x 32, oversampling
           4, two sweeps, alpha 10, L = H; FP32-stored factors with FP64
           arithmetic (FP64 and FP32 apply for comparison).
+* incl-high, incl-low, incl-both
+          160 x 160 thin inclusions (seed 11): 24 segments of K = 1e4, of
+          K = 1e-4, or both (contrast 1e8) on K = 1, the stand-ins for the
+          paper's inclusion experiments (Section 4.3).  Unlike the others:
+          pressure 1 on the left side and 0 on the right, no flow on the
+          others, no source; 8 x 8 subdomains of 20 x 20 (4 x 4 of 40 x 40
+          for comparison), oversampling 2, two sweeps, alpha 10, L = H; FP64.
 """
 from __future__ import annotations
 
@@ -55,10 +62,18 @@ class Workload:
             return wl.lognormal_K(self.nx, self.ny, 3.0, 16.0, 3)
         if self.field == "large":
             return wl.mixture_K(self.nx, self.ny, 5, 6)
+        if self.field.startswith("incl-"):
+            return wl.inclusions_K(self.nx, self.ny, self.field[5:], 11)
         raise ValueError(self.field)
 
     def rhs(self) -> np.ndarray:
+        """Algebraic right-hand side of the no-flow workloads."""
         return wl.corner_sources(self.nx, self.ny)
+
+    def boundary_data(self):
+        """(f, g) of the Dirichlet left/right workloads (the right-hand side
+        is assembled from them by each implementation)."""
+        return wl.dirichlet_left_right(self.nx, self.ny)
 
     def with_(self, **kw) -> "Workload":
         return replace(self, **kw)
@@ -87,3 +102,6 @@ WORKLOADS = {
     "batched": Workload("batched", 1024, 1024, 16, 4, 10.0, 0, 1, 2, 1, 2, "batched"),
     "large": Workload("large", 4096, 4096, 32, 4, 10.0, 0, 2, 2, 1, 2, "large"),
 }
+for _kind in ("high", "low", "both"):
+    WORKLOADS[f"incl-{_kind}"] = Workload(f"incl-{_kind}", 160, 160, 20, 2, 10.0, 0, 2, 2, 1, 0,
+                                          f"incl-{_kind}", (1, 1, 0, 0))

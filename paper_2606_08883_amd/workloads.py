@@ -18,6 +18,13 @@ and inclusion geometries are not reproduced):
 * Channel facies: chi = [G(ell_x, ell_y) > 0]; K = k_hi on chi, k_lo elsewhere.
 * Mixture (contrast 1e8): K_raw = exp(G2) * (chi + 1e-8 (1 - chi)),
   K = max(K_raw, 1e-8 * max(K_raw)).
+* Thin inclusions (stand-in for the paper's inclusion fields, Section 4.3):
+  background K = 1 with straight segments one cell thick, horizontal or
+  vertical with equal probability, lengths uniform in [0.15, 0.45] of the
+  grid side, start cells uniform (``Generator(PCG64(seed))``).  High
+  inclusions have K = contrast, low ones 1 / contrast; the combined field
+  draws the high segments first and the low ones after them (written over
+  any crossing), so its contrast ratio is contrast^2.
 """
 from __future__ import annotations
 
@@ -66,6 +73,47 @@ def mixture_K(nx: int, ny: int, seed_channels: int, seed_lognormal: int,
     g2 = gaussian_field(nx, ny, 32.0, 32.0, seed_lognormal)
     raw = np.exp(g2) * (chi + (1.0 / contrast) * (1.0 - chi))
     return np.maximum(raw, raw.max() / contrast).ravel()
+
+
+def _segments(rng: np.random.Generator, nx: int, ny: int, count: int) -> list:
+    """count thin straight segments as lists of cell ids."""
+    out = []
+    for _ in range(count):
+        horizontal = rng.random() < 0.5
+        side = nx if horizontal else ny
+        length = int(rng.integers(int(0.15 * side), int(0.45 * side) + 1))
+        if horizontal:
+            x0, y = int(rng.integers(0, nx - length + 1)), int(rng.integers(0, ny))
+            out.append([y * nx + x for x in range(x0, x0 + length)])
+        else:
+            x, y0 = int(rng.integers(0, nx)), int(rng.integers(0, ny - length + 1))
+            out.append([y * nx + x for y in range(y0, y0 + length)])
+    return out
+
+
+def inclusions_K(nx: int, ny: int, kind: str, seed: int, count: int = 24,
+                 contrast: float = 1e4) -> np.ndarray:
+    """Thin high ('high'), low ('low') or both kinds ('both') of inclusions on
+    a background K = 1, count segments per kind."""
+    if kind not in ("high", "low", "both"):
+        raise ValueError(kind)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    K = np.ones(nx * ny)
+    if kind in ("high", "both"):
+        for seg in _segments(rng, nx, ny, count):
+            K[seg] = contrast
+    if kind in ("low", "both"):
+        for seg in _segments(rng, nx, ny, count):
+            K[seg] = 1.0 / contrast
+    return K
+
+
+def dirichlet_left_right(nx: int, ny: int, left: float = 1.0, right: float = 0.0):
+    """Boundary data of the paper's Dirichlet left/right problems (pressure
+    `left` at x = 0, `right` at x = 1, no flow on the other sides, no source):
+    (f, g) with g the W, E, S, N face values in the order of the ABI."""
+    g = np.concatenate([np.full(ny, left), np.full(ny, right), np.zeros(nx), np.zeros(nx)])
+    return np.zeros(nx * ny), g
 
 
 def corner_sources(nx: int, ny: int) -> np.ndarray:
