@@ -1,0 +1,31 @@
+"""The seeded input generators (no method arithmetic): the thin-inclusion
+fields and the Dirichlet left/right boundary data."""
+import numpy as np
+
+from paper_2606_08883_amd import workloads as wl
+from paper_2606_08883_amd.configs import WORKLOADS
+
+
+def test_inclusions_are_seeded_thin_and_of_the_stated_contrast():
+    for kind, values in (("high", {1.0, 1e4}), ("low", {1.0, 1e-4}), ("both", {1.0, 1e4, 1e-4})):
+        K = wl.inclusions_K(160, 160, kind, 11)
+        assert np.array_equal(K, wl.inclusions_K(160, 160, kind, 11))
+        assert not np.array_equal(K, wl.inclusions_K(160, 160, kind, 12))
+        assert set(np.unique(K)) == values
+        frac = np.mean(K != 1.0)
+        assert 0.01 < frac < 0.2  # thin: a few percent of the cells
+    Kb = wl.inclusions_K(160, 160, "both", 11)
+    assert Kb.max() / Kb.min() == 1e8
+    # 24 segments one cell thick and at most 0.45 of the side long per kind
+    for kind in ("high", "low"):
+        assert np.count_nonzero(wl.inclusions_K(160, 160, kind, 11) != 1.0) <= 24 * 72
+
+
+def test_dirichlet_left_right_data():
+    f, g = wl.dirichlet_left_right(40, 30)
+    assert f.shape == (1200,) and not f.any()
+    assert np.array_equal(g[:30], np.ones(30)) and not g[30:].any()
+    w = WORKLOADS["incl-low"]
+    assert w.bc == (1, 1, 0, 0) and w.field == "incl-low"
+    f2, g2 = w.boundary_data()
+    assert g2.shape == (2 * w.ny + 2 * w.nx,)
