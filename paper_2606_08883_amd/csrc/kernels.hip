@@ -177,14 +177,19 @@ struct HalfRow {
   }
 };
 
-// Blocks in flight per lane: as many as about 48 VGPRs of rows hold, between
-// 2 and 6 (more would cost waves per SIMD: a sweep over 48, 64, 80 and 96
-// found 48 and 64 equal, 96 a third slower on 36-wide patches).
+// The largest power of two <= d, between 2 and 8.  A sweep runs its step
+// count rounded up to a multiple of the depth, and powers of two divide the
+// common box heights (16, 20, 32, 36 rows), where a depth of 5 would run 20
+// steps for 16 rows.
+constexpr int pow2_depth(int d) { return d >= 8 ? 8 : d >= 4 ? 4 : 2; }
+
+// Blocks in flight per lane: as many as about 48 VGPRs of rows hold (more
+// would cost waves per SIMD: a sweep over 48, 64, 80 and 96 found 48 and 64
+// equal, 96 a third slower on 36-wide patches).
 template <typename S, int NB>
 constexpr int reg_depth() {
   constexpr int per_block = half_rows(NB) * (int)sizeof(S) / 4;
-  constexpr int d = 48 / per_block;
-  return d < 2 ? 2 : d > 6 ? 6 : d;
+  return pow2_depth(48 / per_block);
 }
 
 // Lane rc's rows of one block of a box n cells wide: the quads at words
@@ -1115,12 +1120,12 @@ struct RhsPtrs {
 };
 
 // Blocks in flight per lane for K right-hand sides: about 64 VGPRs of rows
-// (the K columns need their own registers), between 2 and 4.
+// (the K columns need their own registers), 2 or 4.
 template <typename S, int NB, int K>
 constexpr int reg_depth_k() {
   constexpr int per_block = half_rows(NB) * (int)sizeof(S) / 4;
-  constexpr int d = (K == 1 ? 96 : 64) / per_block;
-  return d < 2 ? 2 : d > 4 ? 4 : d;
+  constexpr int d = pow2_depth((K == 1 ? 96 : 64) / per_block);
+  return d > 4 ? 4 : d;
 }
 
 // acc[k] = sum_c D(rc, c) v_k[c] for the K vectors of the group (column k's
