@@ -21,6 +21,26 @@ __device__ __forceinline__ void wsync() { __builtin_amdgcn_wave_barrier(); }
 // stores are visible to the wave (workgroup scope: waits only).
 __device__ __forceinline__ void wfence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
 
+// Row i and column b of the flat index e = lane + 64 t of an array with n
+// columns, stepped from one t to the next without a division (64 = dq n + dr).
+struct FlatIndex {
+  int i, b, dq, dr, n;
+  __device__ FlatIndex(int lane, int n_) : n(n_) {
+    i = lane / n;
+    b = lane - i * n;
+    dq = 64 / n;
+    dr = 64 - dq * n;
+  }
+  __device__ void next() {
+    i += dq;
+    b += dr;
+    if (b >= n) {
+      b -= n;
+      ++i;
+    }
+  }
+};
+
 // Robin conductance of a face leaving a cell box: 1 / (1 / (2 K_c) + b_f),
 // b_f = alpha L / t_f.
 __device__ __forceinline__ double robin(double Kc, double t, double aL) {
@@ -58,6 +78,7 @@ __global__ void __launch_bounds__(64)
   extern __shared__ double sm[];
   const FactorJob J = jobs[blockIdx.x];
   const int n = J.bx, lane = threadIdx.x;
+  const FlatIndex at0(lane, n);
   double* D = sm;
   double* P = sm + (long long)maxn * maxn;
   double* C = sm + 2LL * maxn * maxn;
@@ -100,10 +121,8 @@ __global__ void __launch_bounds__(64)
       wsync();
     }
     if (j > 0) {
-      for (int e = lane; e < n * n; e += 64) {
-        const int a = e / n, b = e - a * n;
-        D[e] -= T[a] * P[e] * T[b];
-      }
+      FlatIndex f = at0;
+      for (int e = lane; e < n * n; e += 64, f.next()) D[e] -= T[f.i] * P[e] * T[f.b];
       wsync();
     }
     for (int k = 0; k < n; ++k) {
@@ -117,10 +136,9 @@ __global__ void __launch_bounds__(64)
       const double inv = 1.0 / p;
       for (int b = lane; b < n; b += 64) D[k * n + b] = b == k ? inv : D[k * n + b] * inv;
       wsync();
-      for (int e = lane; e < n * n; e += 64) {
-        const int i = e / n, b = e - i * n;
-        if (i != k) D[e] = b == k ? -C[i] * inv : D[e] - C[i] * D[k * n + b];
-      }
+      FlatIndex f = at0;
+      for (int e = lane; e < n * n; e += 64, f.next())
+        if (f.i != k) D[e] = f.b == k ? -C[f.i] * inv : D[e] - C[f.i] * D[k * n + f.b];
       wsync();
     }
     if (J.d64 >= 0)
@@ -129,11 +147,12 @@ __global__ void __launch_bounds__(64)
       // half-block layout (setup_jobs.h): row k of lane r is D(r, (r + k) mod
       // n) for k <= n / 2, halved for k = n / 2 when n is even, zero beyond
       const int rows = half_rows(J.cols), h = n / 2;
-      for (int w = lane; w < rows * n; w += 64) {
-        const int k = w / n, r = w - k * n;
+      FlatIndex f = at0;
+      for (int w = lane; w < rows * n; w += 64, f.next()) {
+        const int k = f.i, r = f.b;
         double v = 0.0;
         if (k <= h) {
-          v = D[r * n + (r + k) % n];
+          v = D[r * n + (r + k >= n ? r + k - n : r + k)];
           if (2 * k == n) v *= 0.5;
         }
         dS[J.doffS + (long long)j * J.bs + half_word(k, r, n, J.cols)] = (S)v;
@@ -145,34 +164,70 @@ __global__ void __launch_bounds__(64)
   }
 }
 
-// x = A_box^-1 x for one box with its FP64 factor (row-major inverse blocks
-// and couplings), lane r owning column r; ys is an LDS vector of 64.
-__device__ void box_solve64(double* x, int bx, int by, const double* __restrict__ Dinv,
-                            const double* __restrict__ coup, int pin, int lane, double* ys) {
+// x_k = A_box^-1 x_k for the vectors x_k = X + k * ncell, k < nrhs <= kSolveRhs,
+// of one box (FP64 factor, lane r owning column r): the rows of each block
+// are read once for all the vectors, and every vector sums its terms in
+// column order.  ys: LDS, kSolveRhs x 64.
+constexpr int kSolveRhs = 8;
+__device__ void box_solve64_multi(double* X, int nrhs, long long ncell, int bx, int by,
+                                  const double* __restrict__ Dinv,
+                                  const double* __restrict__ coup, int pin, int lane,
+                                  double (*ys)[64]) {
   const bool act = lane < bx;
-  if (pin && lane == 0) x[0] = 0.0;
+  if (pin && lane == 0)
+    for (int k = 0; k < nrhs; ++k) X[k * ncell] = 0.0;
   wfence();
   for (int j = 0; j < by; ++j) {
-    if (act)
-      ys[lane] = x[(long long)j * bx + lane] +
-                 (j > 0 ? coup[(long long)j * bx + lane] * x[(long long)(j - 1) * bx + lane] : 0.0);
+    if (act) {
+      const double cj = j > 0 ? coup[(long long)j * bx + lane] : 0.0;
+#pragma unroll
+      for (int k = 0; k < kSolveRhs; ++k)
+        if (k < nrhs) {
+          const double* x = X + k * ncell;
+          ys[k][lane] = x[(long long)j * bx + lane] +
+                        (j > 0 ? cj * x[(long long)(j - 1) * bx + lane] : 0.0);
+        }
+    }
     wsync();
     if (act) {
       const double* Di = Dinv + (long long)j * bx * bx + (long long)lane * bx;
-      double s = 0.0;
-      for (int c = 0; c < bx; ++c) s += Di[c] * ys[c];
-      x[(long long)j * bx + lane] = s;
+      double acc[kSolveRhs];
+#pragma unroll
+      for (int k = 0; k < kSolveRhs; ++k) acc[k] = 0.0;
+      for (int c = 0; c < bx; ++c) {
+        const double d = Di[c];
+#pragma unroll
+        for (int k = 0; k < kSolveRhs; ++k)
+          if (k < nrhs) acc[k] += d * ys[k][c];
+      }
+#pragma unroll
+      for (int k = 0; k < kSolveRhs; ++k)
+        if (k < nrhs) X[k * ncell + (long long)j * bx + lane] = acc[k];
     }
     wsync();
   }
   for (int j = by - 2; j >= 0; --j) {
-    if (act) ys[lane] = coup[(long long)(j + 1) * bx + lane] * x[(long long)(j + 1) * bx + lane];
+    if (act) {
+      const double cn = coup[(long long)(j + 1) * bx + lane];
+#pragma unroll
+      for (int k = 0; k < kSolveRhs; ++k)
+        if (k < nrhs) ys[k][lane] = cn * X[k * ncell + (long long)(j + 1) * bx + lane];
+    }
     wsync();
     if (act) {
       const double* Di = Dinv + (long long)j * bx * bx + (long long)lane * bx;
-      double s = 0.0;
-      for (int c = 0; c < bx; ++c) s += Di[c] * ys[c];
-      x[(long long)j * bx + lane] += s;
+      double acc[kSolveRhs];
+#pragma unroll
+      for (int k = 0; k < kSolveRhs; ++k) acc[k] = 0.0;
+      for (int c = 0; c < bx; ++c) {
+        const double d = Di[c];
+#pragma unroll
+        for (int k = 0; k < kSolveRhs; ++k)
+          if (k < nrhs) acc[k] += d * ys[k][c];
+      }
+#pragma unroll
+      for (int k = 0; k < kSolveRhs; ++k)
+        if (k < nrhs) X[k * ncell + (long long)j * bx + lane] += acc[k];
     }
     wsync();
   }
@@ -189,7 +244,7 @@ __global__ void __launch_bounds__(64)
     k_over_phi(const SubJob* __restrict__ subs, const OverRhs* __restrict__ rhs,
                const GamFace* __restrict__ gam, const int* __restrict__ dof_side,
                const int* __restrict__ dof_q, int over0, double* __restrict__ buf) {
-  __shared__ double ys[64];
+  __shared__ double ys[kSolveRhs][64];
   const SubJob J = subs[blockIdx.x];
   const int lane = threadIdx.x;
   const int ncell = J.obx * J.oby;
@@ -201,9 +256,9 @@ __global__ void __launch_bounds__(64)
     X[(long long)R.k * ncell + R.cell] += R.val;
   }
   wfence();
-  for (int k = 0; k < J.ni; ++k)
-    box_solve64(X + (long long)k * ncell, J.obx, J.oby, buf + J.o64, buf + J.oc64, J.opin, lane,
-                ys);
+  for (int k0 = 0; k0 < J.ni; k0 += kSolveRhs)
+    box_solve64_multi(X + (long long)k0 * ncell, J.ni - k0 < kSolveRhs ? J.ni - k0 : kSolveRhs,
+                      ncell, J.obx, J.oby, buf + J.o64, buf + J.oc64, J.opin, lane, ys);
   const int ng = J.gam1 - J.gam0;
   for (int e = lane; e < J.ni * ng; e += 64) {
     const int k = e / ng, f = e - k * ng;
@@ -234,7 +289,7 @@ __global__ void __launch_bounds__(64)
     k_mbf(const SubJob* __restrict__ subs, const GamFace* __restrict__ gam, int nb,
           double* __restrict__ buf, S* __restrict__ mbf, double* __restrict__ colU,
           double* __restrict__ colP) {
-  __shared__ double ys[64];
+  __shared__ double ys[kSolveRhs][64];
   const SubJob J = subs[blockIdx.x];
   const int lane = threadIdx.x;
   const int ncell = J.lbx * J.lby, ng = J.gam1 - J.gam0;
@@ -248,9 +303,9 @@ __global__ void __launch_bounds__(64)
       X[(long long)k * ncell + G.lcin] += G.rho * buf[J.phi + (long long)k * ng + f];
     }
   wfence();
-  for (int k = 0; k < J.ni; ++k)
-    box_solve64(X + (long long)k * ncell, J.lbx, J.lby, buf + J.l64, buf + J.lc64, J.lpin, lane,
-                ys);
+  for (int k0 = 0; k0 < J.ni; k0 += kSolveRhs)
+    box_solve64_multi(X + (long long)k0 * ncell, J.ni - k0 < kSolveRhs ? J.ni - k0 : kSolveRhs,
+                      ncell, J.lbx, J.lby, buf + J.l64, buf + J.lc64, J.lpin, lane, ys);
   for (long long e = lane; e < (long long)J.ni * ncell; e += 64) mbf[J.mbf + e] = (S)X[e];
   const int nt = J.ni * J.nsides * nb;
   for (int e = lane; e < nt; e += 64) {
