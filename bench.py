@@ -200,6 +200,7 @@ def apply_only(args, w, ctx, b, setup_s) -> int:
            "dtype": DTYPES[w.precision], "data": "synthetic",
            "config": {"workload": w.name, "cells": w.cells, "subdomains": int(maps["boxes"].shape[0])},
            "setup_s": setup_s,
+           "autotune": {"ms": ctx.query("tune_ms"), "changes": ctx.query("tune_changes")},
            "device_gb": ctx.query("device_bytes") / 1e9,
            "coarse_min_pivot_ratio": ctx.query("coarse_pivot"),
            "phase_ms_per_launch": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in phases.items()},
@@ -485,6 +486,7 @@ def main() -> int:
         "iterations_per_solve": float(np.mean(its)),
         "final_relres_max": float(np.max(relres)),
         "setup_s": setup_s,
+        "autotune": {"ms": ctx.query("tune_ms"), "changes": ctx.query("tune_changes")},
         "solves_per_s_incl_setup": 1.0 / (setup_s + elapsed / args.steps),
         "apply_ms": apply_ms,
         "phase_ms_per_launch": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in phases.items()},

@@ -236,7 +236,16 @@ int mrcm_timing_read(mrcm_ctx* ctx, double* ms, int64_t* counts);
  *  MRCM_Q_COARSE_BYTES    bytes of the interface factor one solve reads (the
  *                         forward and backward matrices of every tree node);
  *  MRCM_Q_COARSE_LAUNCHES kernel launches of one interface solve (its levels,
- *                         forward and backward). */
+ *                         forward and backward);
+ *  MRCM_Q_TUNE_MS         milliseconds mrcm_setup spent timing workgroup shapes
+ *                         of the one-column launches.  The timing runs only
+ *                         with MRCM_TUNE=1 in the environment, once per shape
+ *                         and process (0 otherwise: the defaults are kept);
+ *                         with MRCM_TUNE=alt every choice takes its last
+ *                         option, untimed and uncached;
+ *  MRCM_Q_TUNE_CHANGES    workgroup shapes the set-up timing changed from the
+ *                         defaults (interface levels, local and patch solves).
+ *                         Every shape gives the same results bit for bit. */
 enum {
   MRCM_Q_SETUP_SECONDS = 0,
   MRCM_Q_DEVICE_BYTES = 1,
@@ -244,7 +253,9 @@ enum {
   MRCM_Q_COARSE_LEVELS = 3,
   MRCM_Q_COARSE_DOFS = 4,
   MRCM_Q_COARSE_BYTES = 5,
-  MRCM_Q_COARSE_LAUNCHES = 6
+  MRCM_Q_COARSE_LAUNCHES = 6,
+  MRCM_Q_TUNE_MS = 7,
+  MRCM_Q_TUNE_CHANGES = 8
 };
 int mrcm_query(mrcm_ctx* ctx, int32_t what, double* value);
 

@@ -27,7 +27,8 @@ EXPORTED = ["mrcm_map_sizes", "mrcm_maps", "mrcm_setup", "mrcm_apply", "mrcm_app
             "mrcm_destroy",
             "mrcm_last_error"]
 QUERIES = {"setup_seconds": 0, "device_bytes": 1, "coarse_pivot": 2, "coarse_levels": 3,
-           "coarse_dofs": 4, "coarse_bytes": 5, "coarse_launches": 6}
+           "coarse_dofs": 4, "coarse_bytes": 5, "coarse_launches": 6, "tune_ms": 7,
+           "tune_changes": 8}
 PHASES = ["local", "coarse", "reconstruct", "residual", "patch", "finalize"]
 TEST_EXPORTED = ["mrcm_test_coarse_sizes", "mrcm_test_coarse_matrix", "mrcm_test_host_apply"]
 

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -134,6 +135,13 @@ struct mrcm_ctx {
   int maxp = 4, np = 0;
   mrcm::CChunk* chunks = nullptr;
   std::vector<std::pair<int, int>> fwd_levels, bwd_levels;  // (first chunk, count)
+  // Workgroup shapes picked by the autotuner for the one-column launches:
+  // threads per chunk of each interface level (0: the default rule), lane
+  // groups per workgroup of the box kernels (0: the most that fit).
+  std::vector<int> fwd_threads, bwd_threads;
+  int local_groups = 0, patch_groups = 0;
+  double tune_ms = 0.0;   // time the autotuner spent in this set-up
+  int tune_changes = 0;   // choices that differ from the defaults
   size_t tsize = 8;  // bytes of the arithmetic / work-vector type
   double setup_seconds = 0.0;
   double coarse_pivot = 1.0;
@@ -417,6 +425,188 @@ void upload_coarse(mrcm_ctx* c, const mrcm::CoarseFactor& F, const mrcm::HostSet
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
+// Interface level i of the forward (backward) sweep on lane L's buffers.
+void launch_fwd_level(mrcm_ctx* c, mrcm_ctx::Lane& L, size_t i, hipStream_t s, int threads) {
+  const auto& lv = c->fwd_levels[i];
+  mrcm::launch_coarse_fwd(c->chunks + lv.first, lv.second, c->cfwd, L.g_nd, L.contrib, c->maxp,
+                          c->np, c->cdest, L.ybuf, c->cidx, L.xc, c->max_nf, s, threads);
+}
+void launch_bwd_level(mrcm_ctx* c, mrcm_ctx::Lane& L, size_t i, hipStream_t s, int threads) {
+  const auto& lv = c->bwd_levels[i];
+  mrcm::launch_coarse_bwd(c->chunks + lv.first, lv.second, c->cbwd, c->cidx, L.ybuf, L.xc,
+                          c->max_nu, s, threads);
+}
+
+// ---- autotuner --------------------------------------------------------------
+// The one-column launches have two free workgroup shapes: threads per chunk
+// of every interface level (one wave, which takes a small chunk whole, or
+// four waves), and lane groups per workgroup of the local and patch solves
+// (the most that fit in 64 KB of LDS, half or a quarter of that).  Every
+// option computes the same results bit for bit, so the choice is by time
+// alone.  With MRCM_TUNE=1 in the environment, each option's launch is
+// timed at set-up with HIP events on the context's own buffers with zero
+// data: the mean of kTuneReps launches after a warm-up, or one launch when
+// the warm-up took over 0.25 ms, the smaller of two such rounds over all
+// options.  The fastest is kept; a default is replaced only when an option
+// beats it by more than 5%.  Choices are cached per shape for the process,
+// so contexts of a shape already seen skip the timing.  Without MRCM_TUNE=1
+// the set-up keeps the defaults, which sweeps of these shapes found fastest:
+// timed choices depend on the conditions of the measurement (under a
+// kernel-tracing profiler they differ from an unprofiled run).  MRCM_TUNE=alt
+// takes the last option of every choice without timing (and caches
+// nothing), so that a test can run every shape.
+struct Tuning {
+  std::vector<int> fwd, bwd;
+  int local = 0, patch = 0;
+};
+std::mutex g_tune_mutex;
+std::map<std::string, Tuning> g_tune_cache;
+constexpr int kTuneReps = 5;
+
+std::string tune_key(const mrcm_ctx* c) {
+  std::string k = std::to_string(c->nx) + "x" + std::to_string(c->ny) + "/p" +
+                  std::to_string(c->precision) + "/m" + std::to_string(c->m) + "/l" +
+                  std::to_string(c->max_bx_local) + "," + std::to_string(c->max_cells_local) +
+                  "/s" + std::to_string(c->max_bx_patch) + "," +
+                  std::to_string(c->max_cells_patch) + "," + std::to_string(c->sweeps) + "/c" +
+                  std::to_string(c->nc) + "," + std::to_string(c->max_nf) + "," +
+                  std::to_string(c->max_nu);
+  for (const auto& lv : c->fwd_levels) k += "/f" + std::to_string(lv.second);
+  for (const auto& lv : c->bwd_levels) k += "/b" + std::to_string(lv.second);
+  return k;
+}
+
+template <typename T, typename S>
+void autotune(mrcm_ctx* c, hipStream_t s) {
+  const char* env = std::getenv("MRCM_TUNE");
+  const bool alt = env && std::strcmp(env, "alt") == 0;
+  if (!alt && !(env && std::strcmp(env, "1") == 0)) return;
+  const std::string key = tune_key(c);
+  if (!alt) {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      c->fwd_threads = it->second.fwd;
+      c->bwd_threads = it->second.bwd;
+      c->local_groups = it->second.local;
+      c->patch_groups = it->second.patch;
+      return;
+    }
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  mrcm_ctx::Lane& L = c->lanes[0];
+  const size_t nc = std::max(c->nc, 1), np = std::max(c->np, 1);
+  double* r0 = c->alloc<double>(c->n);
+  hip_check(hipMemsetAsync(r0, 0, sizeof(double) * c->n, s), "hipMemsetAsync");
+  hip_check(hipMemsetAsync(L.pT, 0, c->tsize * c->n, s), "hipMemsetAsync");
+  hip_check(hipMemsetAsync(L.rhoT, 0, c->tsize * c->n, s), "hipMemsetAsync");
+  hip_check(hipMemsetAsync(L.xc, 0, sizeof(double) * nc, s), "hipMemsetAsync");
+  hip_check(hipMemsetAsync(L.g_nd, 0, sizeof(double) * np, s), "hipMemsetAsync");
+  hip_check(hipMemsetAsync(L.ybuf, 0, sizeof(double) * np, s), "hipMemsetAsync");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hip_check(hipEventCreate(&e0), "hipEventCreate");
+  hip_check(hipEventCreate(&e1), "hipEventCreate");
+  Tuning out;
+  int changes = 0;
+  try {
+    // time of one launch: the mean over kTuneReps after a warm-up, or a
+    // single timed launch when the warm-up took over 0.25 ms
+    auto timed = [&](const auto& launch, int reps) {
+      hip_check(hipEventRecord(e0, s), "hipEventRecord");
+      for (int k = 0; k < reps; ++k) launch();
+      hip_check(hipEventRecord(e1, s), "hipEventRecord");
+      hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+      hip_check(hipGetLastError(), "autotuner launch");
+      float ms = 0.0f;
+      hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+      return (double)ms / reps;
+    };
+    auto time_of = [&](const auto& launch) {
+      const double warm = timed(launch, 1);
+      return timed(launch, warm > 0.25 ? 1 : kTuneReps);
+    };
+    // the fastest option by the smaller of two rounds over all options; the
+    // default (first) unless another is more than 5% faster
+    auto pick = [&](const std::vector<int>& opts, const auto& launch_with) {
+      if (alt) {
+        if (opts.back() != opts[0]) ++changes;
+        return opts.back();
+      }
+      std::vector<double> t(opts.size(), 1e30);
+      for (int round = 0; round < 2; ++round)
+        for (size_t o = 0; o < opts.size(); ++o)
+          t[o] = std::min(t[o], time_of([&] { launch_with(opts[o]); }));
+      int best = opts[0];
+      double tbest = t[0];
+      for (size_t o = 1; o < opts.size(); ++o)
+        if (t[o] < 0.95 * tbest) {
+          tbest = t[o];
+          best = opts[o];
+        }
+      if (best != opts[0]) ++changes;
+      return best;
+    };
+    auto group_opts = [&](int max_bx, int max_cells) {
+      const int g = mrcm::box_groups(max_bx, max_cells, sizeof(T), sizeof(S));
+      std::vector<int> o{g};
+      for (int h = g / 2; h >= 1 && (int)o.size() < 3; h /= 2) o.push_back(h);
+      return o;
+    };
+    if (c->m > 0) {
+      out.local = pick(group_opts(c->max_bx_local, c->max_cells_local), [&](int g) {
+        mrcm::launch_local<T, S>(c->lbox, c->m, c->max_cells_local, c->max_bx_local,
+                                 static_cast<const S*>(c->ldinv),
+                                 static_cast<const S*>(c->lcoup), r0,
+                                 static_cast<T*>(L.pT), c->nx, c->dof_off, c->dof_side,
+                                 c->w_off, c->wU, c->wP, L.mU, L.mP, s, g);
+      });
+      if (c->sweeps > 0)
+        out.patch = pick(group_opts(c->max_bx_patch, c->max_cells_patch), [&](int g) {
+          mrcm::launch_patch<T, S>(c->pbox, c->m, c->max_cells_patch, c->max_bx_patch,
+                                   static_cast<const S*>(c->pdinv),
+                                   static_cast<const S*>(c->pcoup),
+                                   static_cast<const T*>(L.rhoT), static_cast<T*>(L.pT), c->nx,
+                                   s, g);
+        });
+    }
+    if (c->nc > 0) {
+      for (size_t i = 0; i < c->fwd_levels.size(); ++i) {
+        const int d = mrcm::coarse_threads(c->fwd_levels[i].second);
+        out.fwd.push_back(pick({d, d == 64 ? mrcm::kVecThreads : 64},
+                               [&](int t) { launch_fwd_level(c, L, i, s, t); }));
+      }
+      for (size_t i = 0; i < c->bwd_levels.size(); ++i) {
+        const int d = mrcm::coarse_threads(c->bwd_levels[i].second);
+        out.bwd.push_back(pick({d, d == 64 ? mrcm::kVecThreads : 64},
+                               [&](int t) { launch_bwd_level(c, L, i, s, t); }));
+      }
+      // the contribution slots start at zero for every application
+      hip_check(hipMemsetAsync(L.contrib, 0, sizeof(double) * np * c->maxp, s),
+                "hipMemsetAsync");
+    }
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->release(r0, sizeof(double) * c->n);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->release(r0, sizeof(double) * c->n);
+  c->fwd_threads = out.fwd;
+  c->bwd_threads = out.bwd;
+  c->local_groups = out.local;
+  c->patch_groups = out.patch;
+  c->tune_changes = changes;
+  c->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                   .count();
+  if (alt) return;
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  g_tune_cache.emplace(key, out);
+}
+
 // One application of T with arithmetic / work-vector type T and factor
 // storage type S.
 template <typename T, typename S>
@@ -434,17 +624,16 @@ void apply_one(mrcm_ctx* c, mrcm_ctx::Lane& L, const double* r, double* z, hipSt
   mrcm::launch_local<T, S>(c->lbox, c->m, c->max_cells_local, c->max_bx_local,
                            static_cast<const S*>(c->ldinv),
                            static_cast<const S*>(c->lcoup), r, p, c->nx, c->dof_off,
-                           c->dof_side, c->w_off, c->wU, c->wP, L.mU, L.mP, s);
+                           c->dof_side, c->w_off, c->wU, c->wP, L.mU, L.mP, s,
+                           c->local_groups);
   end(0);
   if (c->nc > 0) {
     begin();
     mrcm::launch_coarse_rhs(c->gsrc, c->gscale, L.mU, L.mP, L.g_nd, c->np, s);
-    for (const auto& lv : c->fwd_levels)
-      mrcm::launch_coarse_fwd(c->chunks + lv.first, lv.second, c->cfwd, L.g_nd, L.contrib,
-                              c->maxp, c->np, c->cdest, L.ybuf, c->cidx, L.xc, c->max_nf, s);
-    for (const auto& lv : c->bwd_levels)
-      mrcm::launch_coarse_bwd(c->chunks + lv.first, lv.second, c->cbwd, c->cidx, L.ybuf,
-                              L.xc, c->max_nu, s);
+    for (size_t i = 0; i < c->fwd_levels.size(); ++i)
+      launch_fwd_level(c, L, i, s, i < c->fwd_threads.size() ? c->fwd_threads[i] : 0);
+    for (size_t i = 0; i < c->bwd_levels.size(); ++i)
+      launch_bwd_level(c, L, i, s, i < c->bwd_threads.size() ? c->bwd_threads[i] : 0);
     end(1);
     begin();
     mrcm::launch_reconstruct<T, S>(c->lbox, c->m, static_cast<const S*>(c->mbf), c->mbf_off,
@@ -459,7 +648,8 @@ void apply_one(mrcm_ctx* c, mrcm_ctx::Lane& L, const double* r, double* z, hipSt
     begin();
     mrcm::launch_patch<T, S>(c->pbox, c->m, c->max_cells_patch, c->max_bx_patch,
                              static_cast<const S*>(c->pdinv),
-                             static_cast<const S*>(c->pcoup), rho, p, c->nx, s);
+                             static_cast<const S*>(c->pcoup), rho, p, c->nx, s,
+                             c->patch_groups);
     end(4);
   }
   begin();
@@ -947,6 +1137,12 @@ int mrcm_setup(const mrcm_grid* grid, const mrcm_params* params, const double* K
     make_lane(c, c->lanes[0], s);
     hip_check(hipEventCreateWithFlags(&c->ws_in, hipEventDisableTiming), "hipEventCreate");
     hip_check(hipEventCreateWithFlags(&c->ws_out, hipEventDisableTiming), "hipEventCreate");
+    if (c->precision == 1)
+      autotune<float, float>(c, s);
+    else if (c->precision == 2)
+      autotune<double, float>(c, s);
+    else
+      autotune<double, double>(c, s);
     const char* ge = std::getenv("MRCM_GRAPHS");
     c->use_graphs = !(ge && ge[0] == '0');
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
@@ -1429,6 +1625,8 @@ int mrcm_query(mrcm_ctx* c, int32_t what, double* value) {
       case MRCM_Q_COARSE_LAUNCHES:
         *value = (double)(c->fwd_levels.size() + c->bwd_levels.size());
         break;
+      case MRCM_Q_TUNE_MS: *value = c->tune_ms; break;
+      case MRCM_Q_TUNE_CHANGES: *value = c->tune_changes; break;
       default: throw mrcm::Error(MRCM_EINVAL, "unknown query");
     }
     return MRCM_OK;

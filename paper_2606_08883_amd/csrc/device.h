@@ -57,11 +57,14 @@ void launch_rhs(const double* tx, const double* ty, int nx, int ny, const int* b
 // single group exceeds 64 KB).  t, w: bytes of the arithmetic type T and of
 // the factor storage type S.
 size_t box_lds_bytes(int max_bx, int max_cells, size_t t, size_t w);
+// Lane groups per workgroup of the box kernels (the most that fit; a launch
+// may take fewer, groups_cap > 0, which changes no result).
+int box_groups(int max_bx, int max_cells, size_t t, size_t w);
 template <typename T, typename S>
 void launch_local(const BoxDesc* boxes, int m, int max_cells, int max_bx, const S* dinv,
                   const S* coup, const double* r, T* p, int nx, const int* dof_off,
                   const int* dof_side, const int* w_off, const double* wU, const double* wP,
-                  double* mU, double* mP, hipStream_t s);
+                  double* mU, double* mP, hipStream_t s, int groups_cap = 0);
 // Interface solve: the right-hand side g_nd in tree order (np positions;
 // gsrc[t] = {L, R, kind, 0} names the trace moments of the row at tree
 // position t and its kind, gscale[t] its equilibration scale), then one
@@ -70,13 +73,17 @@ void launch_local(const BoxDesc* boxes, int m, int max_cells, int max_bx, const 
 // u * np + t, zero where unused) receives the descendants' contributions at
 // cdest; max_nf / max_nu bound the LDS vector.  A node without border rows
 // (the root) writes its x_F in its forward level and has no backward level.
+// threads: 64 (one wave per chunk) or 256 per workgroup, 0 for the default
+// of the level's chunk count; the choice changes no result.
 void launch_coarse_rhs(const int4* gsrc, const double* gscale, const double* mU,
                        const double* mP, double* g_nd, int np, hipStream_t s);
 void launch_coarse_fwd(const CChunk* chunks, int nchunks, const double* fwd, const double* g_nd,
                        double* contrib, int maxp, int np, const int* cdest, double* ybuf,
-                       const int* idx, double* x, int max_nf, hipStream_t s);
+                       const int* idx, double* x, int max_nf, hipStream_t s, int threads = 0);
 void launch_coarse_bwd(const CChunk* chunks, int nchunks, const double* bwd, const int* idx,
-                       const double* ybuf, double* x, int max_nu, hipStream_t s);
+                       const double* ybuf, double* x, int max_nu, hipStream_t s,
+                       int threads = 0);
+int coarse_threads(int nchunks);
 template <typename T, typename S>
 void launch_reconstruct(const BoxDesc* boxes, int m, const S* mbf, const long long* mbf_off,
                         const int* dof_off, const double* xc, T* p, int nx, hipStream_t s);
@@ -85,7 +92,7 @@ void launch_residual(const T* tx, const T* ty, int nx, int ny, const double* r, 
                      T* rho, hipStream_t s);
 template <typename T, typename S>
 void launch_patch(const BoxDesc* boxes, int m, int max_cells, int max_bx, const S* dinv,
-                  const S* coup, const T* rho, T* p, int nx, hipStream_t s);
+                  const S* coup, const T* rho, T* p, int nx, hipStream_t s, int groups_cap = 0);
 template <typename T>
 void launch_finalize(const T* p, long long n, int noflow, double* z, double* partials,
                      hipStream_t s);

@@ -1754,10 +1754,11 @@ template <typename T, typename S>
 void launch_local(const BoxDesc* boxes, int m, int max_cells, int max_bx, const S* dinv,
                   const S* coup, const double* r, T* p, int nx, const int* dof_off,
                   const int* dof_side, const int* w_off, const double* wU, const double* wP,
-                  double* mU, double* mP, hipStream_t s) {
-  const int groups = box_groups(max_bx, max_cells, sizeof(T), sizeof(S));
-  const size_t shm = box_lds_bytes(max_bx, max_cells, sizeof(T), sizeof(S));
+                  double* mU, double* mP, hipStream_t s, int groups_cap) {
+  int groups = box_groups(max_bx, max_cells, sizeof(T), sizeof(S));
+  if (groups_cap > 0 && groups_cap < groups) groups = groups_cap;
   const int gb = (int)group_bytes(max_bx, max_cells, sizeof(T), sizeof(S));
+  const size_t shm = (size_t)groups * gb;
   const int cp_words = round16(max_cells, sizeof(S));
   const dim3 grid((m + groups - 1) / groups), block(groups * group_size(max_bx));
   MRCM_BOX_DISPATCH(k_local, T, S, max_bx, grid, block, shm, s, boxes, m, gb, cp_words,
@@ -1775,20 +1776,22 @@ void launch_coarse_rhs(const int4* gsrc, const double* gscale, const double* mU,
 // whole, so that every chunk of the level is resident at once; the other
 // levels take four waves per chunk (a sweep of the threshold over 0, 1024,
 // 2048 and never found 2048 best at 1024^2 and 4096^2).
-static int coarse_threads(int nchunks) { return nchunks >= 2048 ? 64 : kVecThreads; }
+int coarse_threads(int nchunks) { return nchunks >= 2048 ? 64 : kVecThreads; }
 
 void launch_coarse_fwd(const CChunk* chunks, int nchunks, const double* fwd, const double* g_nd,
                        double* contrib, int maxp, int np, const int* cdest, double* ybuf,
-                       const int* idx, double* x, int max_nf, hipStream_t s) {
+                       const int* idx, double* x, int max_nf, hipStream_t s, int threads) {
   if (nchunks <= 0) return;
-  hipLaunchKernelGGL(k_coarse_fwd, dim3(nchunks), dim3(coarse_threads(nchunks)),
+  if (threads != 64 && threads != kVecThreads) threads = coarse_threads(nchunks);
+  hipLaunchKernelGGL(k_coarse_fwd, dim3(nchunks), dim3(threads),
                      sizeof(double) * (size_t)(max_nf > 0 ? max_nf : 1), s, chunks, fwd, g_nd,
                      contrib, maxp, np, cdest, ybuf, idx, x);
 }
 void launch_coarse_bwd(const CChunk* chunks, int nchunks, const double* bwd, const int* idx,
-                       const double* ybuf, double* x, int max_nu, hipStream_t s) {
+                       const double* ybuf, double* x, int max_nu, hipStream_t s, int threads) {
   if (nchunks <= 0) return;
-  hipLaunchKernelGGL(k_coarse_bwd, dim3(nchunks), dim3(coarse_threads(nchunks)),
+  if (threads != 64 && threads != kVecThreads) threads = coarse_threads(nchunks);
+  hipLaunchKernelGGL(k_coarse_bwd, dim3(nchunks), dim3(threads),
                      sizeof(double) * (size_t)(max_nu > 0 ? max_nu : 1), s, chunks, bwd, idx,
                      ybuf, x);
 }
@@ -1809,10 +1812,11 @@ void launch_residual(const T* tx, const T* ty, int nx, int ny, const double* r, 
 
 template <typename T, typename S>
 void launch_patch(const BoxDesc* boxes, int m, int max_cells, int max_bx, const S* dinv,
-                  const S* coup, const T* rho, T* p, int nx, hipStream_t s) {
-  const int groups = box_groups(max_bx, max_cells, sizeof(T), sizeof(S));
-  const size_t shm = box_lds_bytes(max_bx, max_cells, sizeof(T), sizeof(S));
+                  const S* coup, const T* rho, T* p, int nx, hipStream_t s, int groups_cap) {
+  int groups = box_groups(max_bx, max_cells, sizeof(T), sizeof(S));
+  if (groups_cap > 0 && groups_cap < groups) groups = groups_cap;
   const int gb = (int)group_bytes(max_bx, max_cells, sizeof(T), sizeof(S));
+  const size_t shm = (size_t)groups * gb;
   const int cp_words = round16(max_cells, sizeof(S));
   const dim3 grid((m + groups - 1) / groups), block(groups * group_size(max_bx));
   MRCM_BOX_DISPATCH(k_patch, T, S, max_bx, grid, block, shm, s, boxes, m, gb, cp_words,
@@ -2082,11 +2086,12 @@ void launch_sumsq(const double* x, long long n, double* partials, int nb, hipStr
 #define MRCM_INSTANTIATE_TS(T, S)                                                              \
   template void launch_local<T, S>(const BoxDesc*, int, int, int, const S*, const S*,          \
                                    const double*, T*, int, const int*, const int*, const int*,   \
-                                   const double*, const double*, double*, double*, hipStream_t); \
+                                   const double*, const double*, double*, double*, hipStream_t, \
+                                   int);                                                        \
   template void launch_reconstruct<T, S>(const BoxDesc*, int, const S*, const long long*,       \
                                          const int*, const double*, T*, int, hipStream_t);      \
   template void launch_patch<T, S>(const BoxDesc*, int, int, int, const S*, const S*,          \
-                                   const T*, T*, int, hipStream_t);                              \
+                                   const T*, T*, int, hipStream_t, int);                         \
   template void launch_local_k<T, S>(int, const BoxDesc*, int, int, int, const S*, const S*,    \
                                      const double* const*, T* const*, int, const int*,          \
                                      const int*, const int*, const double*, const double*,      \
