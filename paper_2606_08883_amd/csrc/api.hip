@@ -497,18 +497,18 @@ void autotune(mrcm_ctx* c, hipStream_t s) {
   mrcm_ctx::Lane& L = c->lanes[0];
   const size_t nc = std::max(c->nc, 1), np = std::max(c->np, 1);
   double* r0 = c->alloc<double>(c->n);
-  hip_check(hipMemsetAsync(r0, 0, sizeof(double) * c->n, s), "hipMemsetAsync");
-  hip_check(hipMemsetAsync(L.pT, 0, c->tsize * c->n, s), "hipMemsetAsync");
-  hip_check(hipMemsetAsync(L.rhoT, 0, c->tsize * c->n, s), "hipMemsetAsync");
-  hip_check(hipMemsetAsync(L.xc, 0, sizeof(double) * nc, s), "hipMemsetAsync");
-  hip_check(hipMemsetAsync(L.g_nd, 0, sizeof(double) * np, s), "hipMemsetAsync");
-  hip_check(hipMemsetAsync(L.ybuf, 0, sizeof(double) * np, s), "hipMemsetAsync");
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  hip_check(hipEventCreate(&e0), "hipEventCreate");
-  hip_check(hipEventCreate(&e1), "hipEventCreate");
   Tuning out;
   int changes = 0;
   try {
+    hip_check(hipMemsetAsync(r0, 0, sizeof(double) * c->n, s), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(L.pT, 0, c->tsize * c->n, s), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(L.rhoT, 0, c->tsize * c->n, s), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(L.xc, 0, sizeof(double) * nc, s), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(L.g_nd, 0, sizeof(double) * np, s), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(L.ybuf, 0, sizeof(double) * np, s), "hipMemsetAsync");
+    hip_check(hipEventCreate(&e0), "hipEventCreate");
+    hip_check(hipEventCreate(&e1), "hipEventCreate");
     // time of one launch: the mean over kTuneReps after a warm-up, or a
     // single timed launch when the warm-up took over 0.25 ms
     auto timed = [&](const auto& launch, int reps) {
@@ -587,8 +587,8 @@ void autotune(mrcm_ctx* c, hipStream_t s) {
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
   } catch (...) {
     (void)hipStreamSynchronize(s);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     c->release(r0, sizeof(double) * c->n);
     throw;
   }
