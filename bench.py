@@ -371,7 +371,7 @@ def main() -> int:
     ap.add_argument("--inclusions", action="store_true",
                     help="GMRES steps and cycles on the thin-inclusion fields for every "
                          "oversampling / smoothing row of the paper's inclusion tables")
-    ap.add_argument("--requests", type=int, default=48, help="requests of the serving run")
+    ap.add_argument("--requests", type=int, default=512, help="requests of the serving run")
     ap.add_argument("--max-active", type=int, default=8, help="serving slots")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB, as a runtime copy and "
