@@ -5,7 +5,9 @@
   term, exact divergence) and condenses the velocity densely.
 * ``monolithic_mrcm`` solves the MRCM-O equations (11)-(14) with all local
   pressures and all multiplier coefficients as unknowns of one sparse system,
-  without multiscale basis functions.
+  without multiscale basis functions (the multiplier of subdomain i is
+  phi_{i,r} + sum_k x_{i,k} phi_{i,k}, phi_{i,r} the trace of its source-driven
+  oversampled solution).
 * ``dense_operator`` applies an operator to every unit vector.
 * ``krylov_lstsq_residuals`` computes GMRES residuals from an explicit Krylov
   basis and a dense least-squares solve.
@@ -94,11 +96,14 @@ def rt0_vertex_quadrature_system(K, nx: int, ny: int, bc, h: float,
 
 def monolithic_mrcm(mr, r: np.ndarray) -> np.ndarray:
     """Solve the MRCM-O system directly: unknowns are every local pressure of
-    every subdomain followed by every multiplier coefficient x_{i,k}
-    (lambda_i = sum_k x_{i,k} phi_{i,k}); equations are the local Robin
-    problems with source r, then the flux rows and pressure rows of every edge
-    (with the same no-flow row replacement as the coarse system)."""
+    every subdomain followed by every multiplier coefficient x_{i,k}; the
+    Robin data on Gamma_i is lambda_i = phi_{i,r} + sum_k x_{i,k} phi_{i,k};
+    equations are the local Robin problems on Omega_i with source r, then the
+    flux rows and pressure rows of every edge (with the same no-flow row
+    replacement as the coarse system).  Face traces: U = rho (p_c - lambda),
+    pi = lambda + b U."""
     P = mr.part
+    lam0 = mr.source_multiplier(r)
     offs = [0]
     cellsets = []
     for i in range(P.m):
@@ -121,9 +126,12 @@ def monolithic_mrcm(mr, r: np.ndarray) -> np.ndarray:
         for a, b, v in zip(Ai.row, Ai.col, Ai.data):
             M[o + a, o + b] += v
         rhs[o:o + cellsets[i].size] = r[cellsets[i]]
+        loc = {int(c): j for j, c in enumerate(cellsets[i])}
+        for g in mr.gamma[i]:
+            for c, rho, l0 in zip(g.inside, g.rho, lam0[i][g.side]):
+                rhs[o + loc[int(c)]] += rho * l0
         if mr._is_whole_noflow(P.boxes[i]):
             rhs[o] = 0.0
-        loc = {int(c): j for j, c in enumerate(cellsets[i])}
         for k, phi_k in enumerate(mr.phi[i]):
             col = nloc + P.dof_offset[i] + k
             for g in mr.gamma[i]:
@@ -140,11 +148,14 @@ def monolithic_mrcm(mr, r: np.ndarray) -> np.ndarray:
             loc = {int(c): j for j, c in enumerate(cellsets[sub])}
             for jf, c in enumerate(g.inside):
                 pc_col = offs[sub] + loc[int(c)]
-                # U = rho (p_c - lambda), pi = lambda + b U
+                l0 = lam0[sub][sd][jf]
                 for q in range(nb):
                     w = Bq[q, jf]
                     M[r0 + q, pc_col] += w * g.rho[jf]
                     M[r0 + nb + q, pc_col] += sign * w * g.b[jf] * g.rho[jf]
+                    # the known part phi_{i,r} of lambda moves to the right-hand side
+                    rhs[r0 + q] -= -w * g.rho[jf] * l0
+                    rhs[r0 + nb + q] -= sign * w * (l0 - g.b[jf] * g.rho[jf] * l0)
                     for k, phi_k in enumerate(mr.phi[sub]):
                         col = nloc + P.dof_offset[sub] + k
                         lam = phi_k[sd][jf]

@@ -16,6 +16,15 @@ Paper passages followed:
 * Section 3, the modified MRCM-O used as preconditioner: homogeneous boundary
   conditions and source r (the current Krylov vector); T r is the resulting
   pressure.
+* Section 2.1, oversampling builds every multiscale basis function on the
+  extended region while the compatibility conditions stay on the
+  non-overlapping interfaces.  Reading: this includes the source-driven basis
+  function.  The local solution on Omega_i is the restriction of the solution
+  on hat-Omega_i with source r and Robin data sum_k x_k lambda^k on the part of
+  its boundary inside the domain; on Gamma_i its Robin trace is phi_{i,r} +
+  sum_k x_k phi_i^k, where phi_{i,r} is the trace of the zero-data oversampled
+  solution with source r.  Without oversampling (l = 0) this is the plain MRCM
+  particular solution with zero multiplier.
 
 Discrete readings (all plain statements of how a face-based quantity is
 evaluated on the lumped RT0 / two-point-flux discretisation; see
@@ -35,6 +44,10 @@ evaluated on the lumped RT0 / two-point-flux discretisation; see
   rho = r - A p, solves on every patch S_i (Omega_i grown by delta and clipped)
   with the principal submatrix A[S_i] (zero Dirichlet data at the neighbouring
   cell centres), and adds the solution restricted to Omega_i.
+* The interface system is solved by sparse LU followed by iterative
+  refinement whose residuals g - C x are formed in extended precision
+  (numpy.longdouble), so the oracle's interface solution is accurate to
+  about the FP64 rounding of the exact one even where C is ill-conditioned.
 * No-flow on all sides: the coarse system has a one-dimensional null space
   (a uniform pressure shift) and its constant-mode flux rows sum to the total
   source; the flux row F_{e0,0} of the first edge is replaced by a unit row on
@@ -118,6 +131,9 @@ class MRCM:
         P = self.part
         self.gamma = [[SideFaces(self, P.boxes[i], s) for s in P.sides[i]] for i in range(P.m)]
         self.local = [self._box_solver(P.boxes[i], robin=True) for i in range(P.m)]
+        self.over = [self._box_solver(P.oboxes[i], robin=True) for i in range(P.m)]
+        self.ocells = [self.box_cells(P.oboxes[i]) for i in range(P.m)]
+        self.oloc = [{int(c): j for j, c in enumerate(oc)} for oc in self.ocells]
         self.phi = [self._informed_space(i) for i in range(P.m)]
         self.mbf = []
         self.mbf_U = []
@@ -191,34 +207,44 @@ class MRCM:
         lo, hi = P.dof_offset[i], P.dof_offset[i + 1]
         return [(int(s), int(q)) for (_, s, q) in P.dof_table[lo:hi]]
 
+    def oversampled_traces(self, i: int, ph: np.ndarray, lam=None):
+        """Flux U and pressure pi of an oversampled solution ph (values on the
+        cells of hat-Omega_i) across every face of Gamma_i, per side.
+
+        With l = 0 the faces of Gamma_i are Robin faces of hat-Omega_i = Omega_i
+        and ``lam`` (side -> Robin data on those faces, absent = 0) enters:
+        U = rho (p_c - lambda), pi = lambda + b U.  With l > 0 the faces are
+        inside hat-Omega_i: U = t (p_c - p_c') and the flux-continuous face
+        pressure pi = (K_c p_c + K_c' p_c') / (K_c + K_c')."""
+        oloc = self.oloc[i]
+        out = {}
+        for g in self.gamma[i]:
+            pc = ph[[oloc[int(c)] for c in g.inside]]
+            if self.part.oversample == 0:
+                lam_f = lam[g.side] if lam is not None and g.side in lam else np.zeros(g.inside.size)
+                U = g.rho * (pc - lam_f)
+                pi = lam_f + g.b * U
+            else:
+                pn = ph[[oloc[int(c)] for c in g.outside]]
+                U = g.t * (pc - pn)
+                pi = (g.K_in * pc + g.K_out * pn) / (g.K_in + g.K_out)
+            out[g.side] = (U, pi)
+        return out
+
     def _informed_space(self, i: int):
         """phi_{i,k} on the faces of Gamma_i, one dict side -> values per k."""
         P = self.part
         obox = P.oboxes[i]
-        osolver = self._box_solver(obox, robin=True)
-        ocells = self.box_cells(obox)
-        oloc = {int(c): j for j, c in enumerate(ocells)}
         oside = {s: SideFaces(self, obox, s) for s in P.sides[i]}
         phis = []
         for (s, q) in self.coarse_functions(i):
             sf = oside[s]
             lam = side_basis(sf.inside.size, self.degree)[q]
-            rhs = np.zeros(ocells.size)
-            np.add.at(rhs, [oloc[int(c)] for c in sf.inside], sf.rho * lam)
-            ph = osolver.solve(rhs)
-            phi_k = {}
-            for g in self.gamma[i]:
-                pc = ph[[oloc[int(c)] for c in g.inside]]
-                if P.oversample == 0:
-                    lam_f = lam if g.side == s else np.zeros(g.inside.size)
-                    U = g.rho * (pc - lam_f)
-                    pi = lam_f + g.b * U
-                else:
-                    pn = ph[[oloc[int(c)] for c in g.outside]]
-                    U = g.t * (pc - pn)
-                    pi = (g.K_in * pc + g.K_out * pn) / (g.K_in + g.K_out)
-                phi_k[g.side] = pi - g.b * U
-            phis.append(phi_k)
+            rhs = np.zeros(self.ocells[i].size)
+            np.add.at(rhs, [self.oloc[i][int(c)] for c in sf.inside], sf.rho * lam)
+            ph = self.over[i].solve(rhs)
+            tr = self.oversampled_traces(i, ph, {s: lam})
+            phis.append({sd: pi - self._gamma_of(i, sd).b * U for sd, (U, pi) in tr.items()})
         return phis
 
     # ---- multiscale basis functions (setup) ------------------------------
@@ -283,35 +309,60 @@ class MRCM:
             C[self.pin_row, col] = 1.0
         self.C = sp.csc_matrix(C)
         self.C_lu = spla.splu(self.C) if nc > 0 else None
+        self.C_ext = sp.csr_matrix(self.C).astype(np.longdouble) if nc > 0 else None
+
+    def coarse_solve(self, g: np.ndarray) -> np.ndarray:
+        """x = C^-1 g: LU solve, then refinement steps x += C^-1 (g - C x) with
+        the residual and the accumulated x in extended precision, until the
+        correction stops changing x (at most ten steps)."""
+        if self.part.nc == 0:
+            return np.zeros(0)
+        gl = np.asarray(g, dtype=np.longdouble)
+        x = self.C_lu.solve(np.asarray(g, dtype=np.float64)).astype(np.longdouble)
+        for _ in range(10):
+            res = gl - self.C_ext @ x
+            dx = self.C_lu.solve(np.asarray(res, dtype=np.float64))
+            x = x + dx.astype(np.longdouble)
+            if np.abs(dx).max() <= 1e-18 * float(np.abs(x).max()):
+                break
+        return np.asarray(x, dtype=np.float64)
 
     # ---- application of T (per Krylov step) ------------------------------
     def particular(self, r: np.ndarray):
-        """Local particular solutions p_{i,r} = A_i^{-1} r[Omega_i]."""
+        """Source-driven basis functions: the oversampled problem on hat-Omega_i
+        with source r and zero Robin data, solved whole (values on the cells of
+        hat-Omega_i).  Its restriction to Omega_i is the local particular
+        solution p_{i,r}."""
+        return [self.over[i].solve(r[self.ocells[i]]) for i in range(self.part.m)]
+
+    def restrict(self, i: int, ph: np.ndarray) -> np.ndarray:
+        """Values of an oversampled solution on the cells of Omega_i."""
+        return ph[[self.oloc[i][int(c)] for c in self.box_cells(self.part.boxes[i])]]
+
+    def source_multiplier(self, r: np.ndarray):
+        """phi_{i,r}: the Robin trace -b U + pi on Gamma_i of the source-driven
+        oversampled solution (zero for l = 0), per subdomain and side."""
         out = []
-        for i in range(self.part.m):
-            cells = self.box_cells(self.part.boxes[i])
-            out.append(self.local[i].solve(r[cells]))
+        for i, ph in enumerate(self.particular(r)):
+            tr = self.oversampled_traces(i, ph)
+            out.append({sd: pi - self._gamma_of(i, sd).b * U for sd, (U, pi) in tr.items()})
         return out
 
-    def coarse_rhs(self, ploc) -> np.ndarray:
-        """g = minus the flux and pressure row functionals of the particular
-        traces U_{i,r} = rho_f p_{i,r,c}, pi_{i,r} = b_f U_{i,r}."""
+    def coarse_rhs(self, pover) -> np.ndarray:
+        """g = minus the flux and pressure row functionals of the traces of the
+        source-driven oversampled solutions."""
         P = self.part
         g = np.zeros(P.nc)
+        traces = [self.oversampled_traces(i, pover[i]) for i in range(P.m)]
         for e, (L, R, o, st, ln) in enumerate(P.edges):
             sL, sR = edge_sides(int(o))
             B = side_basis(int(ln), self.degree)
             nb = B.shape[0]
-            tr = []
-            for (sub, sd) in ((int(L), sL), (int(R), sR)):
-                gf = self._gamma_of(sub, sd)
-                cells = self.box_cells(P.boxes[sub])
-                loc = {int(c): j for j, c in enumerate(cells)}
-                U = gf.rho * ploc[sub][[loc[int(c)] for c in gf.inside]]
-                tr.append((U, gf.b * U))
+            UL, piL = traces[int(L)][sL]
+            UR, piR = traces[int(R)][sR]
             r0 = self.row_offset[e]
-            g[r0:r0 + nb] = -(B @ (tr[0][0] + tr[1][0]))
-            g[r0 + nb:r0 + 2 * nb] = -(B @ (tr[0][1] - tr[1][1]))
+            g[r0:r0 + nb] = -(B @ (UL + UR))
+            g[r0 + nb:r0 + 2 * nb] = -(B @ (piL - piR))
         if self.pin_row >= 0:
             g[self.pin_row] = 0.0
         return g
@@ -320,12 +371,12 @@ class MRCM:
         """MRCM-O solution with source r and homogeneous boundary data
         (optionally also the multiplier coefficients x)."""
         P = self.part
-        ploc = self.particular(r)
+        pover = self.particular(r)
         p = np.zeros(self.nx * self.ny)
-        x = self.C_lu.solve(self.coarse_rhs(ploc)) if P.nc > 0 else np.zeros(0)
+        x = self.coarse_solve(self.coarse_rhs(pover))
         for i in range(P.m):
             cells = self.box_cells(P.boxes[i])
-            p[cells] = ploc[i] + self.mbf[i] @ x[P.dof_offset[i]:P.dof_offset[i + 1]]
+            p[cells] = self.restrict(i, pover[i]) + self.mbf[i] @ x[P.dof_offset[i]:P.dof_offset[i + 1]]
         return (p, x) if return_coarse else p
 
     def smooth(self, r: np.ndarray, p: np.ndarray) -> np.ndarray:

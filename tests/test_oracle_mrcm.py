@@ -6,6 +6,10 @@
 * FULL interface space with l = 0: weak continuity becomes face-wise flux and
   pressure continuity, so the MRCM solve is the exact fine solve A^-1 r.
 * The MBF-reduced solve equals the monolithic solve of eqs. (11)-(14).
+* The source-driven oversampled solution restricted to Omega_i solves the
+  local Robin problem on Omega_i with source r and its own trace phi_{i,r} as
+  Robin data (so every local solution of T satisfies (11)-(12) on Omega_i);
+  with l = 0 that trace is zero.
 * One subdomain covering the grid: T = A^-1 and GMRES converges in one step.
 * Smoothing: an exact solution is a fixed point; a patch covering the whole
   grid gives A^-1 r in one sweep.
@@ -69,6 +73,28 @@ def test_basis_functions_reproduce_oversampled_solutions(l):
                 rhs[int(np.flatnonzero(ocells == c)[0])] += rho * lv
             ph = np.linalg.solve(A, rhs)
             assert np.linalg.norm(mr.mbf[i][:, k] - ph[pos]) <= 1e-11 * np.linalg.norm(ph[pos])
+
+
+@pytest.mark.parametrize("l,bc", [(0, (1, 1, 0, 0)), (2, (1, 1, 0, 0)), (3, (0, 0, 0, 0)),
+                                  (1, (1, 0, 1, 0))])
+def test_source_driven_solution_solves_the_local_problem(l, bc):
+    mr = _setup(l=l, nx=30, ny=26, s=10, bc=bc)
+    P = mr.part
+    r = wl.random_vector(mr.nx * mr.ny, 21)
+    pover = mr.particular(r)
+    lam0 = mr.source_multiplier(r)
+    for i in range(P.m):
+        cells = mr.box_cells(P.boxes[i])
+        pos = {int(c): j for j, c in enumerate(cells)}
+        rhs = r[cells].copy()
+        for g in mr.gamma[i]:
+            for c, rho, l0 in zip(g.inside, g.rho, lam0[i][g.side]):
+                rhs[pos[int(c)]] += rho * l0
+            if l == 0:
+                assert np.abs(lam0[i][g.side]).max() == 0.0
+        ref = np.linalg.solve(mr.box_matrix(P.boxes[i], True).toarray(), rhs)
+        got = mr.restrict(i, pover[i])
+        assert np.linalg.norm(got - ref) <= 1e-11 * np.linalg.norm(ref)
 
 
 @pytest.mark.parametrize("bc", [(1, 1, 0, 0), (0, 0, 0, 0), (1, 0, 1, 0)])
@@ -152,9 +178,10 @@ def test_subdomain_mass_balance_and_weak_continuity(l):
     P = mr.part
     r = wl.random_vector(mr.nx * mr.ny, 12)
     p, x = mr.mrcm_solve(r, return_coarse=True)
+    lam0 = mr.source_multiplier(r)
     U, PI = {}, {}
     for i in range(P.m):
-        lam = {g.side: np.zeros(g.inside.size) for g in mr.gamma[i]}
+        lam = {g.side: lam0[i][g.side].copy() for g in mr.gamma[i]}
         for k in range(P.dof_offset[i + 1] - P.dof_offset[i]):
             for g in mr.gamma[i]:
                 lam[g.side] += x[P.dof_offset[i] + k] * mr.phi[i][k][g.side]
@@ -194,3 +221,31 @@ def test_rejects_bad_permeability():
         MRCM(np.r_[np.ones(15), 0.0], 4, 4, (1, 1, 0, 0), 2, 2, 0, 10.0)
     with pytest.raises(ValueError):
         MRCM(np.r_[np.ones(15), np.nan], 4, 4, (1, 1, 0, 0), 2, 2, 0, 10.0)
+
+
+def test_refined_interface_solve_matches_exact_rational_solve():
+    """The oracle's interface solve (LU + refinement with extended-precision
+    residuals) against Gaussian elimination in exact rational arithmetic on
+    the same FP64 matrix and right-hand side, for an interface system of a
+    1e6-contrast channel field (condition number far above 1e8)."""
+    from fractions import Fraction
+    K = wl.channel_K(40, 20, 10.0, 3.0, 2)
+    mr = MRCM(K, 40, 20, (1, 1, 0, 0), 10, 10, 2, 10.0, "H", 0, 2, 1)
+    C = mr.C.toarray()
+    n = C.shape[0]
+    assert np.linalg.cond(C) > 1e8
+    g = wl.random_vector(n, 31)
+    M = [[Fraction(float(C[i, j])) for j in range(n)] + [Fraction(float(g[i]))] for i in range(n)]
+    for c in range(n):
+        piv = max(range(c, n), key=lambda r: abs(M[r][c]))
+        M[c], M[piv] = M[piv], M[c]
+        for r in range(c + 1, n):
+            if M[r][c] != 0:
+                f = M[r][c] / M[c][c]
+                M[r] = [a - f * b for a, b in zip(M[r], M[c])]
+    x = [Fraction(0)] * n
+    for i in range(n - 1, -1, -1):
+        x[i] = (M[i][n] - sum(M[i][j] * x[j] for j in range(i + 1, n))) / M[i][i]
+    exact = np.array([float(v) for v in x])
+    got = mr.coarse_solve(g)
+    assert np.linalg.norm(got - exact) <= 4e-16 * np.linalg.norm(exact)
