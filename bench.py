@@ -88,9 +88,11 @@ def algorithmic_bytes(cfg, maps, tw: int, sw: int) -> dict:
     The factor of a box bx cells wide and by rows is stored as by half
     blocks of rows x bx words (rows = cols / 2 + 1, cols the launch's column
     width) plus by x bx couplings; the algorithmic count reads them once.
-    Local solve of subdomain i (bx x by cells): factor and couplings, r read
-    (8 B/cell, FP64), p written (tw/cell), trace-moment weights read (2 x 8 B
-    per face of every dof) and moments written (16 B per dof).
+    Local solve of subdomain i on its oversampled box (ox x oy cells, owned
+    bx x by): factor and couplings, r read on the box (8 B/cell, FP64), p
+    written on the owned cells (tw/cell), the four trace weights of every
+    face of Gamma_i read (32 B per face) and two moments per dof written
+    (16 B per dof).
     Patch solve of patch i (px x py cells, owned bx x by): factor and
     couplings, the residual read on the patch (tw/cell), p read and written
     on the owned cells (2 tw/cell).
@@ -98,12 +100,17 @@ def algorithmic_bytes(cfg, maps, tw: int, sw: int) -> dict:
     b = maps["boxes"]
     bx = (b[:, 1] - b[:, 0]).astype(np.int64)
     by = (b[:, 3] - b[:, 2]).astype(np.int64)
-    lrows = box_cols(int(bx.max())) // 2 + 1
-    local = int(np.sum(by * bx * lrows * sw + by * bx * sw + by * bx * 8 + by * bx * tw))
+    o = maps["oboxes"]
+    ox = (o[:, 1] - o[:, 0]).astype(np.int64)
+    oy = (o[:, 3] - o[:, 2]).astype(np.int64)
+    lrows = box_cols(int(ox.max())) // 2 + 1
+    local = int(np.sum(oy * ox * lrows * sw + oy * ox * sw + oy * ox * 8 + by * bx * tw))
     dofs = maps["dof_table"]
-    sides = dofs[:, 1]
-    lens = np.where(sides <= 1, by[dofs[:, 0]], bx[dofs[:, 0]])
-    local += int(np.sum(lens) * 16 + len(dofs) * 16)
+    faces = 0
+    for i in range(len(b)):
+        sides = set(dofs[dofs[:, 0] == i][:, 1].tolist()) if len(dofs) else set()
+        faces += sum(int(by[i]) if s <= 1 else int(bx[i]) for s in sides)
+    local += faces * 32 + len(dofs) * 16
     p = maps["pboxes"]
     px = (p[:, 1] - p[:, 0]).astype(np.int64)
     py = (p[:, 3] - p[:, 2]).astype(np.int64)
@@ -166,6 +173,20 @@ print(json.dumps({"setup_s": t_setup, "step_s": t_step, "steps": steps}))
                        f"inner steps (T apply + A apply + MGS) of the same workload in "
                        f"{budget_s:.0f} s; solve time = mean step time "
                        f"({d['step_s'] * 1e3:.1f} ms) x {gpu_iterations} steps per solve")}
+
+
+def rhs_of(w, ctx, dev):
+    """b of a workload on the device: the corner sources of the no-flow
+    workloads, or the library's assembly (mrcm_rhs) of the Dirichlet
+    left/right data."""
+    import torch
+    if not any(w.bc):
+        return torch.tensor(w.rhs(), dtype=torch.float64, device=dev)
+    f, g = w.boundary_data()
+    b = torch.empty(w.cells, dtype=torch.float64, device=dev)
+    ctx.rhs(torch.tensor(f, dtype=torch.float64, device=dev),
+            torch.tensor(g, dtype=torch.float64, device=dev), 1.0 / w.nx, b)
+    return b
 
 
 def apply_only(args, w, ctx, b, setup_s) -> int:
@@ -411,8 +432,6 @@ def main() -> int:
         w = w.with_(precision=args.precision)
     dev = torch.device("cuda:0")
     K = torch.tensor(w.permeability(), dtype=torch.float64, device=dev)
-    b = torch.tensor(w.rhs(), dtype=torch.float64, device=dev)
-    p = torch.zeros_like(b)
     torch.cuda.synchronize()
     print(f"bench: workload {w.name} {w.nx}x{w.ny} precision {w.precision}", file=sys.stderr,
           flush=True)
@@ -420,6 +439,8 @@ def main() -> int:
     ctx = B.Context(w.binding_config(), K)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    b = rhs_of(w, ctx, dev)
+    p = torch.zeros_like(b)
     print(f"bench: setup {setup_s:.2f} s", file=sys.stderr, flush=True)
     if args.apply_only:
         return apply_only(args, w, ctx, b, setup_s)

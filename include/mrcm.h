@@ -233,10 +233,14 @@ int mrcm_timing_read(mrcm_ctx* ctx, double* ms, int64_t* counts);
  *                         row-equilibrated interface system (its conditioning);
  *  MRCM_Q_COARSE_LEVELS   levels of the nested-dissection interface solve;
  *  MRCM_Q_COARSE_DOFS     interface unknowns nc;
- *  MRCM_Q_COARSE_BYTES    bytes of the interface factor one solve reads (the
- *                         forward and backward matrices of every tree node);
+ *  MRCM_Q_COARSE_BYTES    bytes one interface solve reads and writes: the
+ *                         forward and backward matrices of every tree node
+ *                         once per sweep (the first solve and every
+ *                         refinement step), plus each refinement residual's
+ *                         matrix rows and vectors;
  *  MRCM_Q_COARSE_LAUNCHES kernel launches of one interface solve (its levels,
- *                         forward and backward);
+ *                         forward and backward, per sweep, and two per
+ *                         refinement step);
  *  MRCM_Q_TUNE_MS         milliseconds mrcm_setup spent timing workgroup shapes
  *                         of the one-column launches.  The timing runs only
  *                         with MRCM_TUNE=1 in the environment, once per shape
@@ -245,7 +249,13 @@ int mrcm_timing_read(mrcm_ctx* ctx, double* ms, int64_t* counts);
  *                         option, untimed and uncached;
  *  MRCM_Q_TUNE_CHANGES    workgroup shapes the set-up timing changed from the
  *                         defaults (interface levels, local and patch solves).
- *                         Every shape gives the same results bit for bit. */
+ *                         Every shape gives the same results bit for bit;
+ *  MRCM_Q_COARSE_REFINE   refinement steps every interface solve runs after
+ *                         the first (x += C^-1 (g - C x) with an FP64
+ *                         residual): the set-up measures how far one solve
+ *                         with the factor misses on a fixed right-hand side
+ *                         and takes steps until a correction is below 1e-10
+ *                         of the solution (at most four). */
 enum {
   MRCM_Q_SETUP_SECONDS = 0,
   MRCM_Q_DEVICE_BYTES = 1,
@@ -255,7 +265,8 @@ enum {
   MRCM_Q_COARSE_BYTES = 5,
   MRCM_Q_COARSE_LAUNCHES = 6,
   MRCM_Q_TUNE_MS = 7,
-  MRCM_Q_TUNE_CHANGES = 8
+  MRCM_Q_TUNE_CHANGES = 8,
+  MRCM_Q_COARSE_REFINE = 9
 };
 int mrcm_query(mrcm_ctx* ctx, int32_t what, double* value);
 

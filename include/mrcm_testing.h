@@ -33,6 +33,13 @@ int mrcm_test_coarse_matrix(const mrcm_grid* grid, const mrcm_params* params, co
 int mrcm_test_host_apply(const mrcm_grid* grid, const mrcm_params* params, const double* K,
                          const double* r, double* z, double* min_pivot_ratio);
 
+/* x = C^-1 g with the interface factorisation mrcm_setup uploads (row
+ * equilibration and nested-dissection block LU) and the refinement steps the
+ * apply runs after it, evaluated on the host.  g, x: host, nc values each (coarse
+ * row order in, coarse dof order out). */
+int mrcm_test_coarse_solve(const mrcm_grid* grid, const mrcm_params* params, const double* K,
+                           const double* g, double* x);
+
 #ifdef __cplusplus
 }
 #endif

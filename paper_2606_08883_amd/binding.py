@@ -28,9 +28,10 @@ EXPORTED = ["mrcm_map_sizes", "mrcm_maps", "mrcm_setup", "mrcm_apply", "mrcm_app
             "mrcm_last_error"]
 QUERIES = {"setup_seconds": 0, "device_bytes": 1, "coarse_pivot": 2, "coarse_levels": 3,
            "coarse_dofs": 4, "coarse_bytes": 5, "coarse_launches": 6, "tune_ms": 7,
-           "tune_changes": 8}
+           "tune_changes": 8, "coarse_refine": 9}
 PHASES = ["local", "coarse", "reconstruct", "residual", "patch", "finalize"]
-TEST_EXPORTED = ["mrcm_test_coarse_sizes", "mrcm_test_coarse_matrix", "mrcm_test_host_apply"]
+TEST_EXPORTED = ["mrcm_test_coarse_sizes", "mrcm_test_coarse_matrix", "mrcm_test_host_apply",
+                 "mrcm_test_coarse_solve"]
 
 
 class MrcmError(RuntimeError):
@@ -100,6 +101,7 @@ def lib() -> ctypes.CDLL:
             "mrcm_test_coarse_sizes": ([pG, pP, pd, pi64, pi64], i32),
             "mrcm_test_coarse_matrix": ([pG, pP, pd, pi32, pi32, pd], i32),
             "mrcm_test_host_apply": ([pG, pP, pd, pd, pd, pd], i32),
+            "mrcm_test_coarse_solve": ([pG, pP, pd, pd, pd], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -203,6 +205,16 @@ def test_host_apply(cfg: Config, K: np.ndarray, r: np.ndarray):
     _check(lib().mrcm_test_host_apply(ctypes.byref(g), ctypes.byref(p), _f64(K), _f64(r), _f64(z),
                                       ctypes.byref(piv)))
     return z, piv.value
+
+
+def test_coarse_solve(cfg: Config, K: np.ndarray, rhs: np.ndarray) -> np.ndarray:
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+    x = np.zeros_like(rhs)
+    g, p = cfg.grid(), cfg.params()
+    _check(lib().mrcm_test_coarse_solve(ctypes.byref(g), ctypes.byref(p), _f64(K), _f64(rhs),
+                                        _f64(x)))
+    return x
 
 
 # ---- device entry points --------------------------------------------------------

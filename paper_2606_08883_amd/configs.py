@@ -1,9 +1,16 @@
 """Synthetic workloads (stand-ins for the paper's experiments; see workloads.py).
 
-Every workload: no-flow on all four sides with the pressure fixed by its mean,
-a point injector +1 in cell (0, 0) and a producer -1 in the last cell, GMRES
-restart 10 and relative tolerance 1e-8, interface degree 1, smoothing overlap
-2.  Field recipes and seeds:
+Common to every workload: GMRES restart 10 and relative tolerance 1e-8,
+interface degree 1, smoothing overlap 2.  Boundary set-up and source: the
+small, batched and serving workloads have no flow on all four sides with the
+pressure fixed by its mean, a point injector +1 in cell (0, 0) and a producer
+-1 in the last cell.  The channel, large and incl-* workloads use the
+paper's set-up for its heterogeneous fields (Section 4): pressure 1 on the
+left side and 0 on the right, no flow on the others, no source.  (With no
+flow on all sides and point sources, the 1e6 and 1e8 contrast fields are not
+solvable to 1e-8 in FP64: a sparse direct solve stops near 1e-6 relative
+residual, because regions of floor permeability are nearly disconnected.)
+Field recipes and seeds:
 
 * small   64 x 64, log-normal K (sigma 2, correlation 8, seed 1), 4 x 4
           subdomains of 16 x 16, oversampling 2, alpha 1 with L = h, one
@@ -23,10 +30,9 @@ restart 10 and relative tolerance 1e-8, interface degree 1, smoothing overlap
 * incl-high, incl-low, incl-both
           160 x 160 thin inclusions (seed 11): 24 segments of K = 1e4, of
           K = 1e-4, or both (contrast 1e8) on K = 1, the stand-ins for the
-          paper's inclusion experiments (Section 4.3).  Unlike the others:
-          pressure 1 on the left side and 0 on the right, no flow on the
-          others, no source; 8 x 8 subdomains of 20 x 20 (4 x 4 of 40 x 40
-          for comparison), oversampling 2, two sweeps, alpha 10, L = H; FP64.
+          paper's inclusion experiments (Section 4.3); 8 x 8 subdomains of
+          20 x 20 (4 x 4 of 40 x 40 for comparison), oversampling 2, two
+          sweeps, alpha 10, L = H; FP64.
 """
 from __future__ import annotations
 
@@ -68,6 +74,9 @@ class Workload:
 
     def rhs(self) -> np.ndarray:
         """Algebraic right-hand side of the no-flow workloads."""
+        if any(self.bc):
+            raise ValueError(f"{self.name}: Dirichlet workload; its right-hand side is "
+                             "assembled from boundary_data() by each implementation")
         return wl.corner_sources(self.nx, self.ny)
 
     def boundary_data(self):
@@ -98,9 +107,9 @@ class Workload:
 
 WORKLOADS = {
     "small": Workload("small", 64, 64, 16, 2, 1.0, 1, 1, 2, 1, 0, "small"),
-    "channel": Workload("channel", 220, 60, 20, 2, 10.0, 0, 1, 2, 1, 0, "channel"),
+    "channel": Workload("channel", 220, 60, 20, 2, 10.0, 0, 1, 2, 1, 0, "channel", (1, 1, 0, 0)),
     "batched": Workload("batched", 1024, 1024, 16, 4, 10.0, 0, 1, 2, 1, 2, "batched"),
-    "large": Workload("large", 4096, 4096, 32, 4, 10.0, 0, 2, 2, 1, 2, "large"),
+    "large": Workload("large", 4096, 4096, 32, 4, 10.0, 0, 2, 2, 1, 2, "large", (1, 1, 0, 0)),
 }
 for _kind in ("high", "low", "both"):
     WORKLOADS[f"incl-{_kind}"] = Workload(f"incl-{_kind}", 160, 160, 20, 2, 10.0, 0, 2, 2, 1, 0,

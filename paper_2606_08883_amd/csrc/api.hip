@@ -119,17 +119,24 @@ struct mrcm_ctx {
   double *tx = nullptr, *ty = nullptr;
   void *txT = nullptr, *tyT = nullptr;  // compute-precision copies (aliases in FP64 mode)
   int* d_bc = nullptr;
-  // local and patch factors
+  // factors of the oversampled boxes (lbox: hat-Omega_i with Omega_i as its
+  // owned part) and of the smoothing patches
   mrcm::BoxDesc *lbox = nullptr, *pbox = nullptr;
   void *ldinv = nullptr, *lcoup = nullptr, *pdinv = nullptr, *pcoup = nullptr;
   void* mbf = nullptr;
   long long* mbf_off = nullptr;
-  int *dof_off = nullptr, *dof_side = nullptr, *w_off = nullptr;
-  double *wU = nullptr, *wP = nullptr;
+  // coarse dofs (first dof of every subdomain, side, mode, first face) and
+  // the four trace weights of every face of Gamma_i
+  int *dof_off = nullptr, *dof_side = nullptr, *dof_q = nullptr, *dof_face0 = nullptr;
+  double* face_w = nullptr;
   // coarse factor
   double *cfwd = nullptr, *cbwd = nullptr;
   int* cidx = nullptr;
   int4* gsrc = nullptr;        // per tree position: mU / mP indices L, R and the row kind
+  // refinement: the scaled rows of C in tree order (CSR) and the step count
+  int *crp = nullptr, *cci = nullptr;
+  double* cv = nullptr;
+  int refine = 0;
   double* gscale = nullptr;    // per tree position: row equilibration scale
   int* cdest = nullptr;        // contribution row -> slot in contrib
   int maxp = 4, np = 0;
@@ -146,7 +153,8 @@ struct mrcm_ctx {
   double setup_seconds = 0.0;
   double coarse_pivot = 1.0;
   int coarse_levels = 0;
-  double coarse_bytes = 0.0;  // interface factor bytes read per solve
+  double coarse_bytes = 0.0;  // interface factor bytes read per sweep (forward + backward)
+  double resid_bytes = 0.0;   // bytes of one refinement residual
   size_t device_bytes = 0;
   // per-phase event timing
   static constexpr int kPhases = 6;
@@ -171,6 +179,7 @@ struct mrcm_ctx {
     bool ready = false;
     void *p[mrcm::kMaxRhs] = {}, *rho[mrcm::kMaxRhs] = {}, *e[mrcm::kMaxRhs] = {};
     double *mU = nullptr, *mP = nullptr, *xc = nullptr, *g_nd = nullptr, *ybuf = nullptr;
+    double *rnd = nullptr, *dx = nullptr;
     double *contrib = nullptr, *partials = nullptr;
   };
   // One right-hand side in flight in GMRES: its Krylov space (V, Z), the
@@ -188,6 +197,7 @@ struct mrcm_ctx {
     hipStream_t st = nullptr;
     void *pT = nullptr, *rhoT = nullptr;
     double *mU = nullptr, *mP = nullptr, *xc = nullptr, *ybuf = nullptr, *g_nd = nullptr;
+    double *rnd = nullptr, *dx = nullptr;  // refinement residual (tree order) and correction
     double *contrib = nullptr;  // maxp slots per tree position (zero where unused)
     double *partials = nullptr;
     Batch batch;
@@ -196,7 +206,9 @@ struct mrcm_ctx {
   };
   std::vector<Lane> lanes;
   int max_lanes = 4, batch_width = 4;
-  long long patch_cells = 0;  // cells of all smoothing patches (scratch of one column)
+  // cells of all oversampled boxes or of all smoothing patches, the larger
+  // (the box scratch of one column of a multi-column application)
+  long long scratch_cells = 0;
   bool use_graphs = true;
   StepGraph* capturing = nullptr;
   hipStream_t ws = nullptr;  // context stream = lane 0's (graphs cannot capture the null stream)
@@ -411,6 +423,15 @@ void upload_coarse(mrcm_ctx* c, const mrcm::CoarseFactor& F, const mrcm::HostSet
       if (q >= 0) cdest[q] = u * np + t;
     }
   c->coarse_bytes = 8.0 * ((double)fwd_len + (double)bwd_len);
+  c->refine = F.refine;
+  // one refinement residual reads the scaled rows (values and column
+  // indices), g and x once and writes r
+  c->resid_bytes = 12.0 * (double)F.nd_v.size() + 4.0 * (np + 1) + 24.0 * np;
+  if (F.refine > 0) {
+    c->crp = c->upload(F.nd_rp, s);
+    c->cci = c->upload(F.nd_ci, s);
+    c->cv = c->upload(F.nd_v, s);
+  }
   c->cfwd = c->upload(fwd.get(), (size_t)fwd_len, s);
   c->cbwd = c->upload(bwd.get(), (size_t)bwd_len, s);
   c->cidx = c->upload(idx, s);
@@ -425,16 +446,38 @@ void upload_coarse(mrcm_ctx* c, const mrcm::CoarseFactor& F, const mrcm::HostSet
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
-// Interface level i of the forward (backward) sweep on lane L's buffers.
-void launch_fwd_level(mrcm_ctx* c, mrcm_ctx::Lane& L, size_t i, hipStream_t s, int threads) {
+// Interface level i of the forward (backward) sweep on lane L's buffers, for
+// the right-hand side g (tree order) and the solution x (default: the lane's
+// g_nd and xc).
+void launch_fwd_level(mrcm_ctx* c, mrcm_ctx::Lane& L, size_t i, hipStream_t s, int threads,
+                      const double* g = nullptr, double* x = nullptr) {
   const auto& lv = c->fwd_levels[i];
-  mrcm::launch_coarse_fwd(c->chunks + lv.first, lv.second, c->cfwd, L.g_nd, L.contrib, c->maxp,
-                          c->np, c->cdest, L.ybuf, c->cidx, L.xc, c->max_nf, s, threads);
+  mrcm::launch_coarse_fwd(c->chunks + lv.first, lv.second, c->cfwd, g ? g : L.g_nd, L.contrib,
+                          c->maxp, c->np, c->cdest, L.ybuf, c->cidx, x ? x : L.xc, c->max_nf, s,
+                          threads);
 }
-void launch_bwd_level(mrcm_ctx* c, mrcm_ctx::Lane& L, size_t i, hipStream_t s, int threads) {
+void launch_bwd_level(mrcm_ctx* c, mrcm_ctx::Lane& L, size_t i, hipStream_t s, int threads,
+                      double* x = nullptr) {
   const auto& lv = c->bwd_levels[i];
-  mrcm::launch_coarse_bwd(c->chunks + lv.first, lv.second, c->cbwd, c->cidx, L.ybuf, L.xc,
-                          c->max_nu, s, threads);
+  mrcm::launch_coarse_bwd(c->chunks + lv.first, lv.second, c->cbwd, c->cidx, L.ybuf,
+                          x ? x : L.xc, c->max_nu, s, threads);
+}
+
+// The interface solve of one column on lane L: x = C^-1 g (L.g_nd -> L.xc),
+// then c->refine steps of x += C^-1 (g - C x).
+void coarse_solve_lane(mrcm_ctx* c, mrcm_ctx::Lane& L, hipStream_t s) {
+  auto sweep = [&](const double* g, double* x) {
+    for (size_t i = 0; i < c->fwd_levels.size(); ++i)
+      launch_fwd_level(c, L, i, s, i < c->fwd_threads.size() ? c->fwd_threads[i] : 0, g, x);
+    for (size_t i = 0; i < c->bwd_levels.size(); ++i)
+      launch_bwd_level(c, L, i, s, i < c->bwd_threads.size() ? c->bwd_threads[i] : 0, x);
+  };
+  sweep(L.g_nd, L.xc);
+  for (int k = 0; k < c->refine; ++k) {
+    mrcm::launch_coarse_resid(1, c->crp, c->cci, c->cv, L.g_nd, L.xc, L.rnd, c->np, c->nc, s);
+    sweep(L.rnd, L.dx);
+    mrcm::launch_coarse_add(L.xc, L.dx, c->nc, s);
+  }
 }
 
 // ---- autotuner --------------------------------------------------------------
@@ -558,7 +601,7 @@ void autotune(mrcm_ctx* c, hipStream_t s) {
                                  static_cast<const S*>(c->ldinv),
                                  static_cast<const S*>(c->lcoup), r0,
                                  static_cast<T*>(L.pT), c->nx, c->dof_off, c->dof_side,
-                                 c->w_off, c->wU, c->wP, L.mU, L.mP, s, g);
+                                 c->dof_q, c->dof_face0, c->face_w, L.mU, L.mP, s, g);
       });
       if (c->sweeps > 0)
         out.patch = pick(group_opts(c->max_bx_patch, c->max_cells_patch), [&](int g) {
@@ -624,16 +667,13 @@ void apply_one(mrcm_ctx* c, mrcm_ctx::Lane& L, const double* r, double* z, hipSt
   mrcm::launch_local<T, S>(c->lbox, c->m, c->max_cells_local, c->max_bx_local,
                            static_cast<const S*>(c->ldinv),
                            static_cast<const S*>(c->lcoup), r, p, c->nx, c->dof_off,
-                           c->dof_side, c->w_off, c->wU, c->wP, L.mU, L.mP, s,
+                           c->dof_side, c->dof_q, c->dof_face0, c->face_w, L.mU, L.mP, s,
                            c->local_groups);
   end(0);
   if (c->nc > 0) {
     begin();
     mrcm::launch_coarse_rhs(c->gsrc, c->gscale, L.mU, L.mP, L.g_nd, c->np, s);
-    for (size_t i = 0; i < c->fwd_levels.size(); ++i)
-      launch_fwd_level(c, L, i, s, i < c->fwd_threads.size() ? c->fwd_threads[i] : 0);
-    for (size_t i = 0; i < c->bwd_levels.size(); ++i)
-      launch_bwd_level(c, L, i, s, i < c->bwd_threads.size() ? c->bwd_threads[i] : 0);
+    coarse_solve_lane(c, L, s);
     end(1);
     begin();
     mrcm::launch_reconstruct<T, S>(c->lbox, c->m, static_cast<const S*>(c->mbf), c->mbf_off,
@@ -673,13 +713,15 @@ void ensure_batch(mrcm_ctx* c, mrcm_ctx::Lane& L, hipStream_t s) {
   for (size_t k = 0; k < K; ++k) {
     B.p[k] = c->alloc<char>(c->tsize * c->n);
     B.rho[k] = c->alloc<char>(c->tsize * c->n);
-    B.e[k] = c->sweeps > 0 ? c->alloc<char>(c->tsize * std::max(c->patch_cells, 1LL)) : nullptr;
+    B.e[k] = c->alloc<char>(c->tsize * std::max(c->scratch_cells, 1LL));
   }
   B.mU = c->alloc<double>(K * nc);
   B.mP = c->alloc<double>(K * nc);
   B.xc = c->alloc<double>(K * nc);
   B.g_nd = c->alloc<double>(K * np);
   B.ybuf = c->alloc<double>(K * np);
+  B.rnd = c->alloc<double>(K * np);
+  B.dx = c->alloc<double>(K * nc);
   B.contrib = c->alloc<double>(K * np * c->maxp);
   hip_check(hipMemsetAsync(B.contrib, 0, sizeof(double) * K * np * c->maxp, s), "hipMemsetAsync");
   B.partials = c->alloc<double>(K * mrcm::kMaxVecBlocks);
@@ -707,19 +749,27 @@ void apply_k(mrcm_ctx* c, mrcm_ctx::Batch& B, int k, const double* const* r, dou
   begin();
   mrcm::launch_local_k<T, S>(k, c->lbox, c->m, c->max_cells_local, c->max_bx_local,
                              static_cast<const S*>(c->ldinv), static_cast<const S*>(c->lcoup), r,
-                             p, c->nx, c->dof_off, c->dof_side, c->w_off, c->wU, c->wP, B.mU,
-                             B.mP, c->nc, s);
+                             p, e, c->nx, c->dof_off, c->dof_side, c->dof_q, c->dof_face0,
+                             c->face_w, B.mU, B.mP, c->nc, s);
   end(0);
   if (c->nc > 0) {
     begin();
     mrcm::launch_coarse_rhs_k(k, c->gsrc, c->gscale, B.mU, B.mP, B.g_nd, c->np, c->nc, s);
-    for (const auto& lv : c->fwd_levels)
-      mrcm::launch_coarse_fwd_k(k, c->chunks + lv.first, lv.second, c->cfwd, B.g_nd, B.contrib,
-                                c->maxp, c->np, c->cdest, B.ybuf, c->cidx, B.xc, c->nc,
-                                c->max_nf, s);
-    for (const auto& lv : c->bwd_levels)
-      mrcm::launch_coarse_bwd_k(k, c->chunks + lv.first, lv.second, c->cbwd, c->cidx, B.ybuf,
-                                B.xc, c->max_nu, c->np, c->nc, s);
+    auto sweep = [&](const double* g, double* x) {
+      for (const auto& lv : c->fwd_levels)
+        mrcm::launch_coarse_fwd_k(k, c->chunks + lv.first, lv.second, c->cfwd, g, B.contrib,
+                                  c->maxp, c->np, c->cdest, B.ybuf, c->cidx, x, c->nc,
+                                  c->max_nf, s);
+      for (const auto& lv : c->bwd_levels)
+        mrcm::launch_coarse_bwd_k(k, c->chunks + lv.first, lv.second, c->cbwd, c->cidx, B.ybuf,
+                                  x, c->max_nu, c->np, c->nc, s);
+    };
+    sweep(B.g_nd, B.xc);
+    for (int it = 0; it < c->refine; ++it) {
+      mrcm::launch_coarse_resid(k, c->crp, c->cci, c->cv, B.g_nd, B.xc, B.rnd, c->np, c->nc, s);
+      sweep(B.rnd, B.dx);
+      mrcm::launch_coarse_add(B.xc, B.dx, (long long)k * c->nc, s);
+    }
     end(1);
     begin();
     mrcm::launch_reconstruct_k<T, S>(k, c->lbox, c->m, static_cast<const S*>(c->mbf), c->mbf_off,
@@ -791,6 +841,8 @@ void make_lane(mrcm_ctx* c, mrcm_ctx::Lane& L, hipStream_t s) {
   L.xc = c->alloc<double>(nc);
   L.g_nd = c->alloc<double>(np);
   L.ybuf = c->alloc<double>(np);
+  L.rnd = c->alloc<double>(np);
+  L.dx = c->alloc<double>(nc);
   L.contrib = c->alloc<double>(np * c->maxp);
   hip_check(hipMemsetAsync(L.contrib, 0, sizeof(double) * np * c->maxp, s), "hipMemsetAsync");
   L.partials = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
@@ -809,8 +861,8 @@ void ensure_lanes(mrcm_ctx* c, int count) {
 }
 
 // Set-up of the boxes on the device (storage type X, arithmetic W): factor
-// the subdomain, patch and oversampled boxes, solve the oversampled problems
-// for phi and the MBF problems for the MBFs and their moments.  Fills the
+// the oversampled and patch boxes, solve the oversampled problems, restrict
+// them to the subdomains (the MBFs) and take their trace moments.  Fills the
 // context's box descriptors, factors, MBFs and work-vector copies of the
 // transmissibilities, and returns the moments (colU, colP; layout of
 // T.col_off) for the interface system.
@@ -825,9 +877,11 @@ void device_setup(mrcm_ctx* c, mrcm::HostSetup& S, const double* K_dev, hipStrea
   auto check_boxes = [&](int max_bx, int max_cells) {
     if (max_bx > 64)
       throw mrcm::Error(MRCM_EINVAL,
-                        "subdomains and smoothing patches must be at most 64 cells wide");
+                        "oversampled subdomains and smoothing patches must be at most 64 cells "
+                        "wide");
     if (mrcm::box_lds_bytes(max_bx, max_cells, sizeof(W), sizeof(X)) > 64 * 1024)
-      throw mrcm::Error(MRCM_EINVAL, "subdomain or patch too large for the LDS of one workgroup");
+      throw mrcm::Error(MRCM_EINVAL,
+                        "oversampled subdomain or patch too large for the LDS of one workgroup");
   };
   auto descs = [&](const std::vector<mrcm::FactorJob>& jobs, const std::vector<mrcm::Box>& own,
                    int* max_cells, int* max_bx) {
@@ -854,7 +908,6 @@ void device_setup(mrcm_ctx* c, mrcm::HostSetup& S, const double* K_dev, hipStrea
     c->pdinv = c->alloc<X>(T.pdinv_len);
     c->pcoup = c->alloc<X>(T.pcoup_len);
   }
-  if (T.max_over > 64) throw mrcm::Error(MRCM_EINVAL, "oversampled boxes must be at most 64 cells wide");
   c->mbf = c->alloc<X>(T.mbf_off[m]);
   c->mbf_off = c->upload(std::vector<long long>(T.mbf_off.begin(), T.mbf_off.end() - 1), s);
   // set-up temporaries
@@ -875,7 +928,6 @@ void device_setup(mrcm_ctx* c, mrcm::HostSetup& S, const double* K_dev, hipStrea
   double* dP = temp_alloc((size_t)std::max(T.col_off[m], 1LL), (double*)nullptr);
   int* status = temp_upload(std::vector<int>{0});
   const mrcm::FactorJob* lj = temp_upload(T.local_jobs);
-  const mrcm::FactorJob* oj = temp_upload(T.over_jobs);
   const mrcm::SubJob* sj = temp_upload(T.subs);
   const mrcm::OverRhs* rh = temp_upload(T.rhs.empty() ? std::vector<mrcm::OverRhs>(1) : T.rhs);
   const mrcm::GamFace* gm = temp_upload(T.gam.empty() ? std::vector<mrcm::GamFace>(1) : T.gam);
@@ -892,10 +944,8 @@ void device_setup(mrcm_ctx* c, mrcm::HostSetup& S, const double* K_dev, hipStrea
                                  static_cast<X*>(c->pdinv), static_cast<X*>(c->pcoup), buf, buf,
                                  status, s);
   }
-  mrcm::launch_factor_boxes<X>(oj, m, T.max_over, K_dev, c->tx, c->ty, c->nx, c->ny, aL, ld, lcp,
-                               buf, buf, status, s);
-  mrcm::launch_over_phi(sj, m, rh, gm, dside, dq, M.oversample == 0 ? 1 : 0, buf, s);
-  mrcm::launch_mbf<X>(sj, m, gm, nb, buf, static_cast<X*>(c->mbf), dU, dP, s);
+  mrcm::launch_over_mbf<X>(sj, m, rh, gm, dside, dq, M.oversample == 0 ? 1 : 0, nb, buf,
+                           static_cast<X*>(c->mbf), dU, dP, s);
   hip_check(hipGetLastError(), "set-up kernel launch");
   colU.resize((size_t)T.col_off[m]);
   colP.resize((size_t)T.col_off[m]);
@@ -915,7 +965,7 @@ void device_setup(mrcm_ctx* c, mrcm::HostSetup& S, const double* K_dev, hipStrea
     c->tyT = c->upload(narrow<W>(S.ty), s);
   }
   c->tsize = sizeof(W);
-  c->patch_cells = T.pcoup_len;
+  c->scratch_cells = std::max(T.lcoup_len, T.pcoup_len);
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
   for (auto& t : temps) c->release(t.first, t.second);
   if (bad) throw mrcm::Error(MRCM_ESINGULAR, "non-positive pivot in a local factorisation");
@@ -1121,13 +1171,14 @@ int mrcm_setup(const mrcm_grid* grid, const mrcm_params* params, const double* K
       device_setup<double, double>(c, S, K_dev, s, colU, colP, col_off);
     mrcm::assemble_coarse(S, colU.data(), colP.data(), col_off);
     mrcm::CoarseFactor CF = mrcm::coarse_factor(S.maps, S.Crp, S.Cci, S.Cv, host_threads());
+    mrcm::coarse_refine_steps(CF, mrcm::kCoarseRefineTol, mrcm::kCoarseRefineMax);
     std::vector<int> dof_side;
     for (const auto& d : S.maps.dofs) dof_side.push_back(d[1]);
     c->dof_off = c->upload(S.maps.dof_offset, s);
-    c->dof_side = c->upload(dof_side, s);
-    c->w_off = c->upload(S.wOff, s);
-    c->wU = c->upload(S.wU, s);
-    c->wP = c->upload(S.wP, s);
+    c->dof_side = c->upload(dof_side.empty() ? std::vector<int>(1) : dof_side, s);
+    c->dof_q = c->upload(S.dof_q.empty() ? std::vector<int>(1) : S.dof_q, s);
+    c->dof_face0 = c->upload(S.dof_face0.empty() ? std::vector<int>(1) : S.dof_face0, s);
+    c->face_w = c->upload(S.face_w.empty() ? std::vector<double>(4) : S.face_w, s);
     if (c->nc > 0) upload_coarse(c, CF, S, s);
     c->coarse_pivot = CF.min_pivot_ratio;
     c->coarse_levels = CF.nodes.empty() ? 0 : CF.depth + 1;
@@ -1555,7 +1606,7 @@ size_t mrcm_footprint(const mrcm_grid* grid, const mrcm_params* params, int32_t 
       for (const auto& b : B) t += (size_t)b.by() * b.bx() * (b.bx() + 1);
       return t * w;
     };
-    bytes += boxes(M.boxes);
+    bytes += boxes(M.oboxes);
     if (params->smooth_sweeps > 0) bytes += boxes(M.pboxes);
     for (int i = 0; i < M.m; ++i)
       bytes += (size_t)(M.dof_offset[i + 1] - M.dof_offset[i]) * M.boxes[i].bx() *
@@ -1566,10 +1617,12 @@ size_t mrcm_footprint(const mrcm_grid* grid, const mrcm_params* params, int32_t 
     bytes += 2 * n * w;
     const int r = nrhs > 0 ? nrhs : 1;
     // per right-hand side in flight: Krylov basis and stored z_j of restart
-    // 10, apply work space (p, rho, patch scratch, interface vectors)
-    size_t pcells = 0;
+    // 10, apply work space (p, rho, box scratch, interface vectors)
+    size_t pcells = 0, ocells = 0;
     if (params->smooth_sweeps > 0)
       for (const auto& b : M.pboxes) pcells += (size_t)b.bx() * b.by();
+    for (const auto& b : M.oboxes) ocells += (size_t)b.bx() * b.by();
+    pcells = std::max(pcells, ocells);
     bytes += (size_t)r * (21 * n * 8 + 2 * n * w + pcells * w + 3 * (size_t)(nc + 1) * 8 +
                           (2 + 4) * (size_t)(nc + 1) * 8);
     return bytes;
@@ -1621,12 +1674,16 @@ int mrcm_query(mrcm_ctx* c, int32_t what, double* value) {
       case MRCM_Q_COARSE_PIVOT: *value = c->coarse_pivot; break;
       case MRCM_Q_COARSE_LEVELS: *value = c->coarse_levels; break;
       case MRCM_Q_COARSE_DOFS: *value = c->nc; break;
-      case MRCM_Q_COARSE_BYTES: *value = c->coarse_bytes; break;
+      case MRCM_Q_COARSE_BYTES:
+        *value = (1.0 + c->refine) * c->coarse_bytes + c->refine * c->resid_bytes;
+        break;
       case MRCM_Q_COARSE_LAUNCHES:
-        *value = (double)(c->fwd_levels.size() + c->bwd_levels.size());
+        *value = (double)((1 + c->refine) * (c->fwd_levels.size() + c->bwd_levels.size()) +
+                          2 * c->refine);
         break;
       case MRCM_Q_TUNE_MS: *value = c->tune_ms; break;
       case MRCM_Q_TUNE_CHANGES: *value = c->tune_changes; break;
+      case MRCM_Q_COARSE_REFINE: *value = c->refine; break;
       default: throw mrcm::Error(MRCM_EINVAL, "unknown query");
     }
     return MRCM_OK;

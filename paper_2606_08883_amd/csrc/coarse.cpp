@@ -351,7 +351,68 @@ CoarseFactor coarse_factor(const Maps& M, const std::vector<int>& rp, const std:
       F.nd_scale[t] = F.rscale[r];
       for (size_t u = 0; u < pulls[r].size(); ++u) F.slots[(size_t)t * F.maxp + u] = pulls[r][u];
     }
+  // the scaled rows in tree order, for the refinement residual
+  F.nd_rp.assign(nc + 1, 0);
+  for (int t = 0; t < nc; ++t) F.nd_rp[t + 1] = F.nd_rp[t] + (rp[F.nd_row[t] + 1] - rp[F.nd_row[t]]);
+  F.nd_ci.resize(F.nd_rp[nc]);
+  F.nd_v.resize(F.nd_rp[nc]);
+  for (int t = 0; t < nc; ++t) {
+    const int r = F.nd_row[t];
+    for (int q = rp[r], o = F.nd_rp[t]; q < rp[r + 1]; ++q, ++o) {
+      F.nd_ci[o] = ci[q];
+      F.nd_v[o] = cvs[q];
+    }
+  }
   return F;
+}
+
+void coarse_residual_host(const CoarseFactor& F, const double* g_nd, const double* x,
+                          double* r_nd) {
+  for (int t = 0; t < F.nc; ++t) {
+    double s = g_nd[t];
+    for (int q = F.nd_rp[t]; q < F.nd_rp[t + 1]; ++q) s = std::fma(-F.nd_v[q], x[F.nd_ci[q]], s);
+    r_nd[t] = s;
+  }
+}
+
+void coarse_solve_refined_host(const CoarseFactor& F, const double* g_nd, double* x) {
+  coarse_solve_host(F, g_nd, x);
+  std::vector<double> r(F.nc), dx(F.nc);
+  for (int s = 0; s < F.refine; ++s) {
+    coarse_residual_host(F, g_nd, x, r.data());
+    coarse_solve_host(F, r.data(), dx.data());
+    for (int q = 0; q < F.nc; ++q) x[q] += dx[q];
+  }
+}
+
+int coarse_refine_steps(CoarseFactor& F, double tol, int max_steps) {
+  F.refine = 0;
+  const int nc = F.nc;
+  if (nc == 0) return 0;
+  // right-hand side: a fixed sequence of values in [-1, 1) (64-bit linear
+  // congruential generator), in tree order
+  std::vector<double> g(nc), x(nc), r(nc), dx(nc);
+  unsigned long long st = 0x9E3779B97F4A7C15ULL;
+  for (int t = 0; t < nc; ++t) {
+    st = st * 6364136223846793005ULL + 1442695040888963407ULL;
+    g[t] = (double)(st >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  }
+  coarse_solve_host(F, g.data(), x.data());
+  int steps = 0;
+  while (steps < max_steps) {
+    coarse_residual_host(F, g.data(), x.data(), r.data());
+    coarse_solve_host(F, r.data(), dx.data());
+    double dmax = 0.0, xmax = 0.0;
+    for (int q = 0; q < nc; ++q) {
+      dmax = std::max(dmax, std::fabs(dx[q]));
+      xmax = std::max(xmax, std::fabs(x[q]));
+    }
+    if (!(dmax > tol * xmax)) break;
+    for (int q = 0; q < nc; ++q) x[q] += dx[q];
+    ++steps;
+  }
+  F.refine = steps;
+  return steps;
 }
 
 void coarse_solve_host(const CoarseFactor& F, const double* g_nd, double* x) {

@@ -45,6 +45,14 @@ struct CoarseFactor {
   int maxp = 4;
   std::vector<int> slots;
   double min_pivot_ratio = 1.0;
+  // The rows of diag(rscale) C in tree order (CSR over the tree positions,
+  // columns = coarse dofs), for the residual r_nd = g_nd - diag(rscale) C x
+  // of the refinement steps.
+  std::vector<int> nd_rp, nd_ci;
+  std::vector<double> nd_v;
+  // Refinement steps x += solve(r_nd) after the first solve (set by
+  // coarse_refine_steps).
+  int refine = 0;
 };
 
 // Factor C (CSR over rows x dofs) for the maps' subdomain grid.
@@ -54,5 +62,23 @@ CoarseFactor coarse_factor(const Maps& M, const std::vector<int>& rp, const std:
 // g_nd: the scaled right-hand side in tree order
 // (g_nd[t] = nd_scale[t] * g[nd_row[t]]).
 void coarse_solve_host(const CoarseFactor& F, const double* g_nd, double* x);
+// r_nd = g_nd - diag(rscale) C x in tree order (FP64, fixed order).
+void coarse_residual_host(const CoarseFactor& F, const double* g_nd, const double* x,
+                          double* r_nd);
+// The solve the apply runs: the level-scheduled solve, then F.refine steps of
+// x += solve(g_nd - diag(rscale) C x).
+void coarse_solve_refined_host(const CoarseFactor& F, const double* g_nd, double* x);
+// Refinement steps the apply needs: the explicit front inverses of the factor
+// are not backward stable, so on ill-conditioned interface systems one solve
+// can be off by far more than the conditioning allows, and each refinement
+// step with an FP64 residual shrinks that error by about the same factor.  The
+// step count is measured on a fixed pseudo-random right-hand side: the
+// number of corrections applied before a correction falls to tol times the
+// solution (in max norm), at most max_steps.  Sets and returns F.refine.
+int coarse_refine_steps(CoarseFactor& F, double tol, int max_steps);
+// The library's choice: corrections down to 1e-10 of the solution, at most
+// four steps.
+constexpr double kCoarseRefineTol = 1e-10;
+constexpr int kCoarseRefineMax = 4;
 
 }  // namespace mrcm

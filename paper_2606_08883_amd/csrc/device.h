@@ -60,11 +60,16 @@ size_t box_lds_bytes(int max_bx, int max_cells, size_t t, size_t w);
 // Lane groups per workgroup of the box kernels (the most that fit; a launch
 // may take fewer, groups_cap > 0, which changes no result).
 int box_groups(int max_bx, int max_cells, size_t t, size_t w);
+// Source-driven solves on the oversampled boxes (boxes[i]: hat-Omega_i with
+// Omega_i as its owned part): p = the solutions restricted to Omega_i, and
+// the trace moments mU, mP of every coarse dof (dof_side, dof_q, first face
+// dof_face0 of the four weights per face in face_w).
 template <typename T, typename S>
 void launch_local(const BoxDesc* boxes, int m, int max_cells, int max_bx, const S* dinv,
                   const S* coup, const double* r, T* p, int nx, const int* dof_off,
-                  const int* dof_side, const int* w_off, const double* wU, const double* wP,
-                  double* mU, double* mP, hipStream_t s, int groups_cap = 0);
+                  const int* dof_side, const int* dof_q, const int* dof_face0,
+                  const double* face_w, double* mU, double* mP, hipStream_t s,
+                  int groups_cap = 0);
 // Interface solve: the right-hand side g_nd in tree order (np positions;
 // gsrc[t] = {L, R, kind, 0} names the trace moments of the row at tree
 // position t and its kind, gscale[t] its equilibration scale), then one
@@ -84,6 +89,12 @@ void launch_coarse_bwd(const CChunk* chunks, int nchunks, const double* bwd, con
                        const double* ybuf, double* x, int max_nu, hipStream_t s,
                        int threads = 0);
 int coarse_threads(int nchunks);
+// Refinement of the interface solve, k columns: r_nd = g_nd - (scaled C in
+// tree order, CSR rp / ci / v) x, and x += dx (n values).
+void launch_coarse_resid(int k, const int* rp, const int* ci, const double* v,
+                         const double* g_nd, const double* x, double* r_nd, int np, int nc,
+                         hipStream_t s);
+void launch_coarse_add(double* x, const double* dx, long long n, hipStream_t s);
 template <typename T, typename S>
 void launch_reconstruct(const BoxDesc* boxes, int m, const S* mbf, const long long* mbf_off,
                         const int* dof_off, const double* xc, T* p, int nx, hipStream_t s);
@@ -102,14 +113,16 @@ void launch_convert(const double* src, float* dst, long long n, hipStream_t s);
 // Per-RHS vectors are given by host arrays of K base pointers; the per-RHS
 // work vectors of the interface solve are K consecutive blocks (mU, mP, xc:
 // k * nc; g_nd, ybuf: k * np; contrib: k * maxp * np).  e: per-RHS scratch
-// of the smoothing patches (sum of the patches' cells each, patch i at its
-// coupling offset).  Results equal K one-RHS launches bit for bit.
+// of the oversampled boxes and of the smoothing patches (box i at its
+// coupling offset; as long as the larger of the two coupling arrays).
+// Results equal K one-RHS launches bit for bit.
 size_t box_lds_bytes_k(int k, int max_bx, int max_cells, size_t t, size_t w);
 template <typename T, typename S>
 void launch_local_k(int k, const BoxDesc* boxes, int m, int max_cells, int max_bx, const S* dinv,
-                    const S* coup, const double* const* r, T* const* p, int nx,
-                    const int* dof_off, const int* dof_side, const int* w_off, const double* wU,
-                    const double* wP, double* mU, double* mP, int nc, hipStream_t s);
+                    const S* coup, const double* const* r, T* const* p, T* const* e, int nx,
+                    const int* dof_off, const int* dof_side, const int* dof_q,
+                    const int* dof_face0, const double* face_w, double* mU, double* mP, int nc,
+                    hipStream_t s);
 void launch_coarse_rhs_k(int k, const int4* gsrc, const double* gscale, const double* mU,
                          const double* mP, double* g_nd, int np, int nc, hipStream_t s);
 void launch_coarse_fwd_k(int k, const CChunk* chunks, int nchunks, const double* fwd,
@@ -141,15 +154,13 @@ template <typename S>
 void launch_factor_boxes(const FactorJob* jobs, int njobs, int maxn, const double* K,
                          const double* tx, const double* ty, int nx, int ny, double aL, S* dS,
                          S* cS, double* d64, double* c64, int* status, hipStream_t s);
-// Oversampled problems and phi of every subdomain (buf: FP64 work buffer that
-// the SubJob offsets index).
-void launch_over_phi(const SubJob* subs, int m, const OverRhs* rhs, const GamFace* gam,
-                     const int* dof_side, const int* dof_q, int over0, double* buf,
-                     hipStream_t s);
-// MBFs of every subdomain into mbf (storage type) and their moments.
+// Oversampled problems of every subdomain, their restrictions to Omega_i
+// (the MBFs, storage type) and the moments of their traces on Gamma_i (buf:
+// FP64 work buffer that the SubJob offsets index; over0: no oversampling).
 template <typename S>
-void launch_mbf(const SubJob* subs, int m, const GamFace* gam, int nb, double* buf, S* mbf,
-                double* colU, double* colP, hipStream_t s);
+void launch_over_mbf(const SubJob* subs, int m, const OverRhs* rhs, const GamFace* gam,
+                     const int* dof_side, const int* dof_q, int over0, int nb, double* buf,
+                     S* mbf, double* colU, double* colP, hipStream_t s);
 
 // ---- GMRES vector kernels (FP64) -------------------------------------------
 // r = b - A p (p may be NULL for p = 0); partials[block] = sum r^2

@@ -455,20 +455,93 @@ struct BoxSlot {
   }
 };
 
-// Local Robin particular solves p_{i,r} = A_i^-1 r[Omega_i], one lane group
-// per subdomain, fused with the trace moments of the coarse right-hand side:
-// mU[k] = sum_j wU[k][j] p(face cell j), mP[k] likewise, for every coarse dof
-// k = (i, side, q) of the subdomain (one lane per dof, FP64 sums).  Groups
-// past the last subdomain (live = false) run along on the last one and write
-// nothing.
+// Legendre polynomial P_q at the face parameter xi_j = (2 j + 1) / n - 1
+// (three-term recurrence).
+__device__ __forceinline__ double legendre_face(int q, int j, int n) {
+  const double xi = (2.0 * j + 1.0) / n - 1.0;
+  double pm = 1.0, pq = xi;
+  if (q == 0) return 1.0;
+  for (int k = 1; k < q; ++k) {
+    const double pn = ((2.0 * k + 1.0) * xi * pq - k * pm) / (k + 1.0);
+    pm = pq;
+    pq = pn;
+  }
+  return pq;
+}
+
+// Box-local indices (row stride d.bx) of the two cells of face j of side
+// `side` (W E S N) of the owned subdomain of box d: the subdomain's cell and
+// the cell across the face.  A face on the box's boundary (no oversampling)
+// has no cell across inside the box; its second index is the first (the
+// weights of that cell are zero).
+__device__ __forceinline__ void face_cells(const BoxDesc& d, int side, int j, int& cin,
+                                           int& cout) {
+  int row, col, dr = 0, dc = 0;
+  if (side == 0) {
+    row = d.oy + j; col = d.ox; dc = -1;
+  } else if (side == 1) {
+    row = d.oy + j; col = d.ox + d.obx - 1; dc = 1;
+  } else if (side == 2) {
+    row = d.oy; col = d.ox + j; dr = -1;
+  } else {
+    row = d.oy + d.oby - 1; col = d.ox + j; dr = 1;
+  }
+  cin = row * d.bx + col;
+  const int r2 = row + dr, c2 = col + dc;
+  cout = (r2 < 0 || r2 >= d.by || c2 < 0 || c2 >= d.bx) ? cin : r2 * d.bx + c2;
+}
+
+// Flux and pressure moments of one coarse dof k = (i, side, q) over the faces
+// of its side: sum_j P_q(xi_j) (cUi p_in + cUo p_out) and likewise with the
+// pressure weights; fw: the four weights of each face, from the dof's first
+// face.  v(c) reads the solution at box-local cell c.  One fixed order.
+template <typename V>
+__device__ __forceinline__ void trace_moments(const BoxDesc& d, int side, int q,
+                                              const double* __restrict__ fw, V v, double& su,
+                                              double& sp) {
+  const int len = side <= 1 ? d.oby : d.obx;
+  su = 0.0;
+  sp = 0.0;
+  for (int j0 = 0; j0 < len; j0 += 8) {
+    f64x2 w[8][2];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + u < len ? j0 + u : len - 1;
+      w[u][0] = *reinterpret_cast<const f64x2*>(fw + 4 * j);
+      w[u][1] = *reinterpret_cast<const f64x2*>(fw + 4 * j + 2);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + u;
+      if (j < len) {
+        int ci, co;
+        face_cells(d, side, j, ci, co);
+        const double pin = v(ci), pout = v(co);
+        const double lw = legendre_face(q, j, len);
+        const double U = fmat(w[u][0][1], pout, w[u][0][0] * pin);
+        const double P = fmat(w[u][1][1], pout, w[u][1][0] * pin);
+        su = fmat(lw, U, su);
+        sp = fmat(lw, P, sp);
+      }
+    }
+  }
+}
+
+// Source-driven solves of the apply, one lane group per subdomain: the
+// oversampled problem on hat-Omega_i (box d) with source r and zero Robin
+// data, p = its restriction to Omega_i (the owned cells of d), fused with
+// the trace moments of the coarse right-hand side (one lane per coarse dof
+// of the subdomain, FP64 sums).  Groups past the last subdomain (live =
+// false) run along on the last one and write nothing.
 template <typename T, typename S, int NB, int GS = (NB <= 16 ? 16 : NB <= 32 ? 32 : 64)>
 __global__ void __launch_bounds__(kBoxThreads)
     k_local(const BoxDesc* __restrict__ boxes, int m, int group_bytes, int cp_words,
             const S* __restrict__ dinv, const S* __restrict__ coup,
             const double* __restrict__ r, T* __restrict__ p, int nx,
             const int* __restrict__ dof_off, const int* __restrict__ dof_side,
-            const int* __restrict__ w_off, const double* __restrict__ wU,
-            const double* __restrict__ wP, double* __restrict__ mU, double* __restrict__ mP) {
+            const int* __restrict__ dof_q, const int* __restrict__ dof_face0,
+            const double* __restrict__ face_w, double* __restrict__ mU,
+            double* __restrict__ mP) {
   extern __shared__ __align__(16) char smem_raw[];
   const int grp = threadIdx.x / GS, lane = threadIdx.x % GS;
   const int i0 = blockIdx.x * (blockDim.x / GS) + grp;
@@ -477,7 +550,6 @@ __global__ void __launch_bounds__(kBoxThreads)
   BoxSlot<T, S, NB, GS> L(smem_raw + (long long)grp * group_bytes, cp_words);
   const BoxDesc d = boxes[i];
   const int bx = d.bx, by = d.by;
-  const bool act = live && lane < bx;
   const long long origin = (long long)d.y0 * nx + d.x0;
   stage_box(L.us, r, origin, nx, L.cp, coup + d.coff, bx, by, lane, live);
   zero_slots<T, GS>(L.vv, vec_words<NB, GS>(), lane);
@@ -487,37 +559,15 @@ __global__ void __launch_bounds__(kBoxThreads)
   box_solve<T, S, NB, GS>(L.us, L.vv, L.cp, dinv + d.doff, bx, by, d.bs, lane,
                          (threadIdx.x & 63) - lane, live);
   wave_sync();
-  if (act)
-    for (int j = 0; j < by; ++j) p[origin + (long long)j * nx + lane] = L.us[j * bx + lane];
+  if (live && lane >= d.ox && lane < d.ox + d.obx) {
+    const long long o2 = origin + (long long)d.oy * nx;
+    for (int j = 0; j < d.oby; ++j) p[o2 + (long long)j * nx + lane] = L.us[(d.oy + j) * bx + lane];
+  }
   if (!live) return;
   for (int k = dof_off[i] + lane; k < dof_off[i + 1]; k += GS) {
-    const int side = dof_side[k];
-    const int len = (side <= 1) ? by : bx;
-    const double* wu = wU + w_off[k];
-    const double* wp = wP + w_off[k];
-    double su = 0.0, sp = 0.0;
-    for (int j0 = 0; j0 < len; j0 += 16) {
-      double a[16], b[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int jf = j0 + u < len ? j0 + u : len - 1;
-        a[u] = wu[jf];
-        b[u] = wp[jf];
-      }
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int jf = j0 + u;
-        if (jf < len) {
-          const int cell = side == 0 ? jf * bx
-                         : side == 1 ? jf * bx + bx - 1
-                         : side == 2 ? jf
-                                     : (by - 1) * bx + jf;
-          const double v = (double)L.us[cell];
-          su = fmat(a[u], v, su);
-          sp = fmat(b[u], v, sp);
-        }
-      }
-    }
+    double su, sp;
+    trace_moments(d, dof_side[k], dof_q[k], face_w + 4LL * dof_face0[k],
+                  [&](int c) { return (double)L.us[c]; }, su, sp);
     mU[k] = su;
     mP[k] = sp;
   }
@@ -535,6 +585,28 @@ __global__ void k_coarse_rhs(const int4* __restrict__ gsrc, const double* __rest
   const int4 src = gsrc[t];
   const double v = src.z == 0 ? -(mU[src.x] + mU[src.y]) : -(mP[src.x] - mP[src.y]);
   g_nd[t] = src.z == 2 ? 0.0 : gscale[t] * v;
+}
+
+// Refinement residual of the interface solve in tree order: r_nd[t] = g_nd[t]
+// - sum over the scaled row of position t of v * x (CSR rp / ci / v), one
+// thread per row, terms in row order; blockIdx.y selects a column of a
+// multi-column solve (vectors of column k at k * np / k * nc).
+__global__ void k_coarse_resid(const int* __restrict__ rp, const int* __restrict__ ci,
+                               const double* __restrict__ v, const double* __restrict__ g_nd,
+                               const double* __restrict__ x, double* __restrict__ r_nd, int np,
+                               int nc) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= np) return;
+  const double* xk = x + (long long)blockIdx.y * nc;
+  double s = g_nd[(long long)blockIdx.y * np + t];
+  for (int q = rp[t]; q < rp[t + 1]; ++q) s = fmat(-v[q], xk[ci[q]], s);
+  r_nd[(long long)blockIdx.y * np + t] = s;
+}
+
+// x += dx over n values (columns of a multi-column solve are consecutive).
+__global__ void k_coarse_add(double* __restrict__ x, const double* __restrict__ dx, long long n) {
+  const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (q < n) x[q] += dx[q];
 }
 
 // ---- interface solve (level-scheduled nested dissection) -------------------
@@ -781,7 +853,8 @@ __global__ void __launch_bounds__(kVecThreads)
   gemv_chunk(M, nu, ch.row0, ch.row1, xu, m, pre, [&](int, double val) { x[dst] = y - val; });
 }
 
-// p[Omega_i] += P_i x_i (multiscale reconstruction), one workgroup per subdomain.
+// p[Omega_i] += P_i x_i (multiscale reconstruction; Omega_i is the owned part
+// of box d), one workgroup per subdomain.
 template <typename T, typename S>
 __global__ void __launch_bounds__(kBoxThreads)
     k_reconstruct(const BoxDesc* __restrict__ boxes, const S* __restrict__ mbf,
@@ -790,13 +863,13 @@ __global__ void __launch_bounds__(kBoxThreads)
   __shared__ T xs[64];
   const int i = blockIdx.x;
   const BoxDesc d = boxes[i];
-  const int k0 = dof_off[i], nk = dof_off[i + 1] - k0, ncell = d.bx * d.by;
+  const int k0 = dof_off[i], nk = dof_off[i + 1] - k0, ncell = d.obx * d.oby;
   for (int k = threadIdx.x; k < nk; k += blockDim.x) xs[k] = (T)xc[k0 + k];
   __syncthreads();
   const S* P = mbf + mbf_off[i];
   for (int q = threadIdx.x; q < ncell; q += blockDim.x) {
-    const int a = q % d.bx, j = q / d.bx;
-    const long long c = (long long)(d.y0 + j) * nx + d.x0 + a;
+    const int a = q % d.obx, j = q / d.obx;
+    const long long c = (long long)(d.y0 + d.oy + j) * nx + d.x0 + d.ox + a;
     T s = p[c];
     for (int k = 0; k < nk; ++k) s = fmat((T)P[(long long)k * ncell + q], xs[k], s);
     p[c] = s;
@@ -1292,16 +1365,18 @@ struct BoxSlotK {
   }
 };
 
-// k_local for K right-hand sides: p_k[Omega_i] = A_i^-1 r_k[Omega_i] (solved
-// in place in p_k) and the trace moments of every coarse dof of the
-// subdomain for every k (mU[k * nc + dof], mP likewise).
+// k_local for K right-hand sides: the oversampled solve of every column,
+// built in the subdomain's slice of the scratch vectors (offset coff, row
+// stride bx), p_k = its restriction to Omega_i, and the trace moments of
+// every coarse dof of the subdomain for every k (mU[k * nc + dof], mP
+// likewise; the arithmetic of k_local per column).
 template <typename T, typename S, int NB, int K, int GS = (NB <= 16 ? 16 : NB <= 32 ? 32 : 64)>
 __global__ void __launch_bounds__(kBoxThreads)
     k_local_k(const BoxDesc* __restrict__ boxes, int m, int group_bytes,
               const S* __restrict__ dinv, const S* __restrict__ coup, RhsPtrs<const double> r,
-              RhsPtrs<T> p, int nx, const int* __restrict__ dof_off,
-              const int* __restrict__ dof_side, const int* __restrict__ w_off,
-              const double* __restrict__ wU, const double* __restrict__ wP,
+              RhsPtrs<T> p, RhsPtrs<T> e, int nx, const int* __restrict__ dof_off,
+              const int* __restrict__ dof_side, const int* __restrict__ dof_q,
+              const int* __restrict__ dof_face0, const double* __restrict__ face_w,
               double* __restrict__ mU, double* __restrict__ mP, int nc) {
   extern __shared__ __align__(16) char smem_raw[];
   const int grp = threadIdx.x / GS, lane = threadIdx.x % GS;
@@ -1317,51 +1392,32 @@ __global__ void __launch_bounds__(kBoxThreads)
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     in[k] = r.v[k] + origin;
-    work[k] = p.v[k] + origin;
+    work[k] = e.v[k] + d.coff;
   }
   words_to_lds<S, GS>(L.cp, coup + d.coff, bx * by, lane, live);
   zero_slots<T, GS>(L.vv, K * vec_words<NB, GS>(), lane);
   wave_sync();
-  box_solve_k<T, S, NB, GS, K, double>(in, nx, work, nx, L.vv, L.cp, dinv + d.doff, bx, by,
+  box_solve_k<T, S, NB, GS, K, double>(in, nx, work, bx, L.vv, L.cp, dinv + d.doff, bx, by,
                                        d.bs, lane, (threadIdx.x & 63) - lane, live,
                                        live && d.pin);
   if (!live) return;
+  if (lane >= d.ox && lane < d.ox + d.obx) {
+    const long long o2 = origin + (long long)d.oy * nx;
+#pragma unroll 1
+    for (int k = 0; k < K; ++k)
+      for (int j = 0; j < d.oby; ++j)
+        p.v[k][o2 + (long long)j * nx + lane] = work[k][(long long)(d.oy + j) * bx + lane];
+  }
   for (int kd = dof_off[i] + lane; kd < dof_off[i + 1]; kd += GS) {
-    const int side = dof_side[kd];
-    const int len = (side <= 1) ? by : bx;
-    const double* wu = wU + w_off[kd];
-    const double* wp = wP + w_off[kd];
-    double su[K], sp[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) su[k] = sp[k] = 0.0;
-    for (int j0 = 0; j0 < len; j0 += 8) {
-      double a8[8], b8[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int jf = j0 + u < len ? j0 + u : len - 1;
-        a8[u] = wu[jf];
-        b8[u] = wp[jf];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int jf = j0 + u;
-        if (jf < len) {
-          const int row = side == 0 ? jf : side == 1 ? jf : side == 2 ? 0 : by - 1;
-          const int col = side == 0 ? 0 : side == 1 ? bx - 1 : jf;
-          const long long c = (long long)row * nx + col;
-#pragma unroll
-          for (int k = 0; k < K; ++k) {
-            const double v = (double)work[k][c];
-            su[k] = fmat(a8[u], v, su[k]);
-            sp[k] = fmat(b8[u], v, sp[k]);
-          }
-        }
-      }
-    }
-#pragma unroll
+    const int side = dof_side[kd], q = dof_q[kd];
+    const double* fw = face_w + 4LL * dof_face0[kd];
+#pragma unroll 1
     for (int k = 0; k < K; ++k) {
-      mU[(long long)k * nc + kd] = su[k];
-      mP[(long long)k * nc + kd] = sp[k];
+      const T* wk = work[k];
+      double su, sp;
+      trace_moments(d, side, q, fw, [&](int c) { return (double)wk[c]; }, su, sp);
+      mU[(long long)k * nc + kd] = su;
+      mP[(long long)k * nc + kd] = sp;
     }
   }
 }
@@ -1588,7 +1644,7 @@ __global__ void __launch_bounds__(kBoxThreads)
   __shared__ T xs[K][64];
   const int i = blockIdx.x;
   const BoxDesc d = boxes[i];
-  const int k0 = dof_off[i], nk = dof_off[i + 1] - k0, ncell = d.bx * d.by;
+  const int k0 = dof_off[i], nk = dof_off[i + 1] - k0, ncell = d.obx * d.oby;
   for (int e = threadIdx.x; e < nk * K; e += blockDim.x) {
     const int k = e / nk, j = e - k * nk;
     xs[k][j] = (T)xc[(long long)k * nc + k0 + j];
@@ -1596,8 +1652,8 @@ __global__ void __launch_bounds__(kBoxThreads)
   __syncthreads();
   const S* P = mbf + mbf_off[i];
   for (int q = threadIdx.x; q < ncell; q += blockDim.x) {
-    const int a = q % d.bx, j = q / d.bx;
-    const long long c = (long long)(d.y0 + j) * nx + d.x0 + a;
+    const int a = q % d.obx, j = q / d.obx;
+    const long long c = (long long)(d.y0 + d.oy + j) * nx + d.x0 + d.ox + a;
     T s[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) s[k] = p.v[k][c];
@@ -1753,8 +1809,8 @@ size_t box_lds_bytes(int max_bx, int max_cells, size_t t, size_t w) {
 template <typename T, typename S>
 void launch_local(const BoxDesc* boxes, int m, int max_cells, int max_bx, const S* dinv,
                   const S* coup, const double* r, T* p, int nx, const int* dof_off,
-                  const int* dof_side, const int* w_off, const double* wU, const double* wP,
-                  double* mU, double* mP, hipStream_t s, int groups_cap) {
+                  const int* dof_side, const int* dof_q, const int* dof_face0,
+                  const double* face_w, double* mU, double* mP, hipStream_t s, int groups_cap) {
   int groups = box_groups(max_bx, max_cells, sizeof(T), sizeof(S));
   if (groups_cap > 0 && groups_cap < groups) groups = groups_cap;
   const int gb = (int)group_bytes(max_bx, max_cells, sizeof(T), sizeof(S));
@@ -1762,7 +1818,7 @@ void launch_local(const BoxDesc* boxes, int m, int max_cells, int max_bx, const 
   const int cp_words = round16(max_cells, sizeof(S));
   const dim3 grid((m + groups - 1) / groups), block(groups * group_size(max_bx));
   MRCM_BOX_DISPATCH(k_local, T, S, max_bx, grid, block, shm, s, boxes, m, gb, cp_words,
-                    dinv, coup, r, p, nx, dof_off, dof_side, w_off, wU, wP, mU, mP);
+                    dinv, coup, r, p, nx, dof_off, dof_side, dof_q, dof_face0, face_w, mU, mP);
 }
 
 void launch_coarse_rhs(const int4* gsrc, const double* gscale, const double* mU,
@@ -1771,6 +1827,18 @@ void launch_coarse_rhs(const int4* gsrc, const double* gscale, const double* mU,
   hipLaunchKernelGGL(k_coarse_rhs, dim3((np + 255) / 256), dim3(256), 0, s, gsrc, gscale, mU, mP,
                      g_nd, np);
 }
+void launch_coarse_resid(int k, const int* rp, const int* ci, const double* v,
+                         const double* g_nd, const double* x, double* r_nd, int np, int nc,
+                         hipStream_t s) {
+  if (np <= 0) return;
+  hipLaunchKernelGGL(k_coarse_resid, dim3((np + 255) / 256, k), dim3(256), 0, s, rp, ci, v, g_nd,
+                     x, r_nd, np, nc);
+}
+void launch_coarse_add(double* x, const double* dx, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_coarse_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, dx, n);
+}
+
 // Threads per chunk of an interface level: levels with very many chunks
 // (the leaves: small fronts) take one wave per chunk, which takes its chunk
 // whole, so that every chunk of the level is resident at once; the other
@@ -1891,9 +1959,10 @@ inline int box_width_k(int nb, size_t w) {
 
 template <typename T, typename S>
 void launch_local_k(int k, const BoxDesc* boxes, int m, int max_cells, int max_bx, const S* dinv,
-                    const S* coup, const double* const* r, T* const* p, int nx,
-                    const int* dof_off, const int* dof_side, const int* w_off, const double* wU,
-                    const double* wP, double* mU, double* mP, int nc, hipStream_t s) {
+                    const S* coup, const double* const* r, T* const* p, T* const* e, int nx,
+                    const int* dof_off, const int* dof_side, const int* dof_q,
+                    const int* dof_face0, const double* face_w, double* mU, double* mP, int nc,
+                    hipStream_t s) {
   check_k(k);
   const int nb = col_width(max_bx), kk = std::min(k, box_width_k(nb, sizeof(S)));
   for (int k0 = 0; k0 < k; k0 += kk) {
@@ -1901,7 +1970,7 @@ void launch_local_k(int k, const BoxDesc* boxes, int m, int max_cells, int max_b
     double* v = mP + (long long)k0 * nc;
     if (kk == 1) {
       launch_local<T, S>(boxes, m, max_cells, max_bx, dinv, coup, r[k0], p[k0], nx, dof_off,
-                         dof_side, w_off, wU, wP, u, v, s);
+                         dof_side, dof_q, dof_face0, face_w, u, v, s);
       continue;
     }
     const int groups = box_groups_k(kk, max_bx, max_cells, sizeof(T), sizeof(S));
@@ -1909,9 +1978,9 @@ void launch_local_k(int k, const BoxDesc* boxes, int m, int max_cells, int max_b
     const int gb = (int)group_bytes_k(kk, max_bx, max_cells, sizeof(T), sizeof(S));
     const dim3 grid((m + groups - 1) / groups), block(groups * group_size(max_bx));
     const RhsPtrs<const double> rp = rhs_ptrs(kk, r + k0);
-    const RhsPtrs<T> pp = rhs_ptrs(kk, p + k0);
+    const RhsPtrs<T> pp = rhs_ptrs(kk, p + k0), ep = rhs_ptrs(kk, e + k0);
     MRCM_BOX_DISPATCH_K(k_local_k, T, S, nb, kk, grid, block, shm, s, boxes, m, gb, dinv, coup,
-                        rp, pp, nx, dof_off, dof_side, w_off, wU, wP, u, v, nc);
+                        rp, pp, ep, nx, dof_off, dof_side, dof_q, dof_face0, face_w, u, v, nc);
   }
 }
 
@@ -2086,16 +2155,16 @@ void launch_sumsq(const double* x, long long n, double* partials, int nb, hipStr
 #define MRCM_INSTANTIATE_TS(T, S)                                                              \
   template void launch_local<T, S>(const BoxDesc*, int, int, int, const S*, const S*,          \
                                    const double*, T*, int, const int*, const int*, const int*,   \
-                                   const double*, const double*, double*, double*, hipStream_t, \
+                                   const int*, const double*, double*, double*, hipStream_t,     \
                                    int);                                                        \
   template void launch_reconstruct<T, S>(const BoxDesc*, int, const S*, const long long*,       \
                                          const int*, const double*, T*, int, hipStream_t);      \
   template void launch_patch<T, S>(const BoxDesc*, int, int, int, const S*, const S*,          \
                                    const T*, T*, int, hipStream_t, int);                         \
   template void launch_local_k<T, S>(int, const BoxDesc*, int, int, int, const S*, const S*,    \
-                                     const double* const*, T* const*, int, const int*,          \
-                                     const int*, const int*, const double*, const double*,      \
-                                     double*, double*, int, hipStream_t);                       \
+                                     const double* const*, T* const*, T* const*, int,           \
+                                     const int*, const int*, const int*, const int*,            \
+                                     const double*, double*, double*, int, hipStream_t);        \
   template void launch_reconstruct_k<T, S>(int, const BoxDesc*, int, const S*,                  \
                                            const long long*, const int*, const double*, int,    \
                                            T* const*, int, hipStream_t);                        \

@@ -1,7 +1,9 @@
 // Host-side FP64 setup of T (Section 2.1): face transmissibilities, Robin
-// coefficients (beta = alpha L / K_H), block LDL^T factors of the local Robin
-// problems, the oversampled problems that inform the multiplier spaces, the
-// multiscale basis functions, the interface system, and the factors of the
+// coefficients (beta = alpha L / K_H), block LDL^T factors of the oversampled
+// Robin problems (which inform the multiplier spaces and on which every
+// multiscale basis function is built, the source-driven one of the apply
+// included), the multiscale basis functions as restrictions of the
+// oversampled solutions, the interface system, and the factors of the
 // smoothing patches.
 #include "setup.h"
 
@@ -249,25 +251,45 @@ void host_prepare(HostSetup& S, const mrcm_grid& g, const mrcm_params& p, const 
   if (bad) throw Error(MRCM_EINVAL, "K must be finite and positive on every cell");
   face_transmissibilities(S);
   const int m = M.m, nc = M.nc();
-  // coarse right-hand-side weights of the particular traces, per dof k =
-  // (i, side, q) over the faces of that side: wU = rho P_q(xi), wP = b wU
-  S.wOff.assign(nc + 1, 0);
-  for (int k = 0; k < nc; ++k)
-    S.wOff[k + 1] = S.wOff[k] + side_len(M.boxes[M.dofs[k][0]], M.dofs[k][1]);
-  S.wU.assign(S.wOff[nc], 0.0);
-  S.wP.assign(S.wOff[nc], 0.0);
+  // trace weights of the source-driven solutions, per face of Gamma_i:
+  // inside the oversampled box U = t (p_in - p_out) and the flux-continuous
+  // pi = (K_in p_in + K_out p_out) / (K_in + K_out); without oversampling the
+  // face is a Robin face with zero data: U = rho p_in, pi = b U
+  S.face_off.assign(m + 1, 0);
+  for (int i = 0; i < m; ++i) {
+    int nf = 0;
+    for (int s : M.sides[i]) nf += side_len(M.boxes[i], s);
+    S.face_off[i + 1] = S.face_off[i] + nf;
+  }
+  S.face_w.assign((size_t)4 * S.face_off[m], 0.0);
+  S.dof_face0.assign(nc, 0);
+  S.dof_q.assign(nc, 0);
 #pragma omp parallel for schedule(dynamic, 64)
-  for (int i = 0; i < m; ++i)
-    for (int dof = M.dof_offset[i]; dof < M.dof_offset[i + 1]; ++dof) {
-      const int ks = M.dofs[dof][1], kq = M.dofs[dof][2];
-      const GammaSide gs = make_side(S, M.boxes[i], ks);
-      const int nfs = (int)gs.faces.size();
-      for (int j = 0; j < nfs; ++j) {
-        const double w = legendre(kq, xi_of(j, nfs));
-        S.wU[S.wOff[dof] + j] = gs.rho[j] * w;
-        S.wP[S.wOff[dof] + j] = gs.b[j] * gs.rho[j] * w;
+  for (int i = 0; i < m; ++i) {
+    int f = S.face_off[i];
+    for (int s : M.sides[i]) {
+      const GammaSide gs = make_side(S, M.boxes[i], s);
+      for (int dof = M.dof_offset[i]; dof < M.dof_offset[i + 1]; ++dof)
+        if (M.dofs[dof][1] == s) {
+          S.dof_face0[dof] = f;
+          S.dof_q[dof] = M.dofs[dof][2];
+        }
+      for (size_t j = 0; j < gs.faces.size(); ++j, ++f) {
+        double* w = &S.face_w[(size_t)4 * f];
+        if (M.oversample == 0) {
+          w[0] = gs.rho[j];
+          w[1] = 0.0;
+          w[2] = gs.b[j] * gs.rho[j];
+          w[3] = 0.0;
+        } else {
+          w[0] = gs.t[j];
+          w[1] = -gs.t[j];
+          w[2] = gs.Kin[j] / (gs.Kin[j] + gs.Kout[j]);
+          w[3] = gs.Kout[j] / (gs.Kin[j] + gs.Kout[j]);
+        }
       }
     }
+  }
   // coarse rows: the dofs of the L and R sides each row combines
   const int E = (int)M.edges.size();
   S.rowL.assign(nc, -1);
@@ -293,11 +315,11 @@ void device_tables(const HostSetup& S, int epv, DeviceTables& T) {
   auto whole = [&](const Box& b) {
     return S.noflow && b.x0 == 0 && b.y0 == 0 && b.x1 == nx && b.y1 == ny;
   };
-  // column widths of the local and patch launches, which fix the half-block
-  // layout of their factors
+  // column widths of the local (oversampled) and patch launches, which fix
+  // the half-block layout of their factors
   int lmax = 1, pmax = 1;
   for (int i = 0; i < m; ++i) {
-    lmax = std::max(lmax, M.boxes[i].bx());
+    lmax = std::max(lmax, M.oboxes[i].bx());
     if (S.sweeps > 0) pmax = std::max(pmax, M.pboxes[i].bx());
   }
   const int lcols = box_cols(lmax), pcols = box_cols(pmax);
@@ -308,7 +330,7 @@ void device_tables(const HostSetup& S, int epv, DeviceTables& T) {
   // per subdomain (in parallel): the jobs with sizes only, the Robin data of
   // its oversampled problems and its faces of Gamma_i
   struct Part {
-    FactorJob lj, pj, oj;
+    FactorJob lj, pj;
     SubJob sj;
     std::vector<OverRhs> rhs;
     std::vector<GamFace> gam;
@@ -321,22 +343,22 @@ void device_tables(const HostSetup& S, int epv, DeviceTables& T) {
     const Box& oi = M.oboxes[i];
     const int ni = M.dof_offset[i + 1] - M.dof_offset[i];
     const int ns = (int)M.sides[i].size();
-    P.lj = FactorJob{bi.x0, bi.y0, bi.bx(), bi.by(), 1, whole(bi) ? 1 : 0, hstride(bi, lcols),
+    P.lj = FactorJob{oi.x0, oi.y0, oi.bx(), oi.by(), 1, whole(oi) ? 1 : 0, hstride(oi, lcols),
                      lcols, 0, 0, 0, 0};
     if (S.sweeps > 0) {
       const Box& pb = M.pboxes[i];
       P.pj = FactorJob{pb.x0, pb.y0, pb.bx(), pb.by(), 0, whole(pb) ? 1 : 0,
                        hstride(pb, pcols), pcols, 0, 0, -1, -1};
     }
-    P.oj = FactorJob{oi.x0, oi.y0, oi.bx(), oi.by(), 1, whole(oi) ? 1 : 0, 0, 0, -1, -1, 0, 0};
     SubJob& sj = P.sj;
     sj = SubJob{};
-    sj.lbx = bi.bx();
-    sj.lby = bi.by();
-    sj.lpin = P.lj.pin;
     sj.obx = oi.bx();
     sj.oby = oi.by();
-    sj.opin = P.oj.pin;
+    sj.opin = P.lj.pin;
+    sj.lbx = bi.bx();
+    sj.lby = bi.by();
+    sj.ox = bi.x0 - oi.x0;
+    sj.oy = bi.y0 - oi.y0;
     sj.ni = ni;
     sj.nsides = ns;
     sj.dof0 = M.dof_offset[i];
@@ -363,7 +385,6 @@ void device_tables(const HostSetup& S, int epv, DeviceTables& T) {
         GamFace g{};
         g.ocin = loc_of(oi, f.inside, nx);
         g.ocout = M.oversample == 0 ? -1 : loc_of(oi, f.outside, nx);
-        g.lcin = loc_of(bi, f.inside, nx);
         g.si = si;
         g.side = gs.side;
         g.j = j;
@@ -393,17 +414,16 @@ void device_tables(const HostSetup& S, int epv, DeviceTables& T) {
     Part& P = part[i];
     SubJob& sj = P.sj;
     const long long lc = (long long)sj.lbx * sj.lby, oc = (long long)sj.obx * sj.oby;
-    T.max_local = std::max(T.max_local, sj.lbx);
-    T.max_over = std::max(T.max_over, sj.obx);
+    T.max_local = std::max(T.max_local, sj.obx);
     P.lj.doffS = T.ldinv_len;
     P.lj.coffS = T.lcoup_len;
     P.lj.d64 = buf;
-    P.lj.c64 = buf + lc * sj.lbx;
-    T.ldinv_len += (long long)P.lj.bs * sj.lby;
-    T.lcoup_len += lc;
-    sj.l64 = P.lj.d64;
-    sj.lc64 = P.lj.c64;
-    buf += lc * sj.lbx + lc;
+    P.lj.c64 = buf + oc * sj.obx;
+    T.ldinv_len += (long long)P.lj.bs * sj.oby;
+    T.lcoup_len += oc;
+    sj.o64 = P.lj.d64;
+    sj.oc64 = P.lj.c64;
+    buf += oc * sj.obx + oc;
     T.local_jobs.push_back(P.lj);
     if (S.sweeps > 0) {
       T.max_patch = std::max(T.max_patch, P.pj.bx);
@@ -413,14 +433,6 @@ void device_tables(const HostSetup& S, int epv, DeviceTables& T) {
       T.pcoup_len += (long long)P.pj.bx * P.pj.by;
       T.patch_jobs.push_back(P.pj);
     }
-    P.oj.d64 = buf;
-    P.oj.c64 = buf + oc * sj.obx;
-    sj.o64 = P.oj.d64;
-    sj.oc64 = P.oj.c64;
-    buf += oc * sj.obx + oc;
-    T.over_jobs.push_back(P.oj);
-    sj.lscr = buf;
-    buf += sj.ni * lc;
     sj.oscr = buf;
     buf += sj.ni * oc;
     sj.rhs0 = (int)T.rhs.size();
@@ -429,8 +441,6 @@ void device_tables(const HostSetup& S, int epv, DeviceTables& T) {
     sj.gam0 = (int)T.gam.size();
     T.gam.insert(T.gam.end(), P.gam.begin(), P.gam.end());
     sj.gam1 = (int)T.gam.size();
-    sj.phi = buf;
-    buf += (long long)sj.ni * (sj.gam1 - sj.gam0);
     T.mbf_off[i + 1] = T.mbf_off[i] + sj.ni * lc;
     T.col_off[i + 1] = T.col_off[i] + (long long)sj.ni * sj.nsides * nb;
     sj.mbf = T.mbf_off[i];
@@ -508,7 +518,7 @@ void host_setup(HostSetup& S, const mrcm_grid& g, const mrcm_params& p, const do
   host_prepare(S, g, p, K);
   const Maps& M = S.maps;
   const int m = M.m, nb = M.degree + 1;
-  S.local.resize(m);
+  S.over.resize(m);
   S.patch.resize(S.sweeps > 0 ? m : 0);
   S.mbf.resize(m);
   std::vector<SubResult> sub(m);
@@ -520,63 +530,49 @@ void host_setup(HostSetup& S, const mrcm_grid& g, const mrcm_params& p, const do
     try {
       const Box& bi = M.boxes[i];
       const Box& oi = M.oboxes[i];
-      S.local[i] = factor_box(S, bi, true);
       if (S.sweeps > 0) S.patch[i] = factor_box(S, M.pboxes[i], false);
+      S.over[i] = factor_box(S, oi, true);
       std::vector<GammaSide> gam;
       for (int s : M.sides[i]) gam.push_back(make_side(S, bi, s));
       const int Ni = M.dof_offset[i + 1] - M.dof_offset[i];
-      // oversampled problems -> informed multiplier functions phi_k on Gamma_i
-      BoxFactor of = factor_box(S, oi, true);
-      std::vector<std::vector<std::vector<double>>> phi(Ni);  // [k][side idx][face]
+      const size_t nloc = (size_t)bi.bx() * bi.by();
+      S.mbf[i].assign((size_t)Ni * nloc, 0.0);
+      sub[i].colU.assign(Ni, std::vector<std::vector<double>>(gam.size(), std::vector<double>(nb)));
+      sub[i].colP = sub[i].colU;
       std::vector<double> ph((size_t)oi.bx() * oi.by());
       for (int k = 0; k < Ni; ++k) {
+        // oversampled problem k: P_q Robin data on side ks of hat-Omega_i
         const int ks = M.dofs[M.dof_offset[i] + k][1], kq = M.dofs[M.dof_offset[i] + k][2];
         GammaSide os = make_side(S, oi, ks);
         std::fill(ph.begin(), ph.end(), 0.0);
         const int nf = (int)os.faces.size();
         for (int j = 0; j < nf; ++j)
           ph[loc_of(oi, os.faces[j].inside, S.nx)] += os.rho[j] * legendre(kq, xi_of(j, nf));
-        box_solve(of, ph.data());
-        phi[k].resize(gam.size());
+        box_solve(S.over[i], ph.data());
+        // the multiscale basis function is its restriction to Omega_i
+        double* pk = &S.mbf[i][(size_t)k * nloc];
+        for (int y = bi.y0; y < bi.y1; ++y)
+          for (int x = bi.x0; x < bi.x1; ++x)
+            pk[(size_t)(y - bi.y0) * bi.bx() + (x - bi.x0)] =
+                ph[(size_t)(y - oi.y0) * oi.bx() + (x - oi.x0)];
+        // and its flux and pressure moments on Gamma_i (columns of C)
         for (size_t si = 0; si < gam.size(); ++si) {
           const GammaSide& gs = gam[si];
           const int nfs = (int)gs.faces.size();
-          phi[k][si].resize(nfs);
           for (int j = 0; j < nfs; ++j) {
-            double pc = ph[loc_of(oi, gs.faces[j].inside, S.nx)], U, pi;
+            const double pc = ph[loc_of(oi, gs.faces[j].inside, S.nx)];
+            double U, pi;
             if (M.oversample == 0) {
-              double lam = gs.side == ks ? legendre(kq, xi_of(j, nfs)) : 0.0;
+              const double lam = gs.side == ks ? legendre(kq, xi_of(j, nfs)) : 0.0;
               U = gs.rho[j] * (pc - lam);
               pi = lam + gs.b[j] * U;
             } else {
-              double pn = ph[loc_of(oi, gs.faces[j].outside, S.nx)];
+              const double pn = ph[loc_of(oi, gs.faces[j].outside, S.nx)];
               U = gs.t[j] * (pc - pn);
               pi = (gs.Kin[j] * pc + gs.Kout[j] * pn) / (gs.Kin[j] + gs.Kout[j]);
             }
-            phi[k][si][j] = pi - gs.b[j] * U;
-          }
-        }
-      }
-      // multiscale basis functions and their trace moments (columns of C)
-      const size_t nloc = (size_t)bi.bx() * bi.by();
-      S.mbf[i].assign((size_t)Ni * nloc, 0.0);
-      sub[i].colU.assign(Ni, std::vector<std::vector<double>>(gam.size(), std::vector<double>(nb)));
-      sub[i].colP = sub[i].colU;
-      for (int k = 0; k < Ni; ++k) {
-        double* pk = &S.mbf[i][(size_t)k * nloc];
-        for (size_t si = 0; si < gam.size(); ++si)
-          for (size_t j = 0; j < gam[si].faces.size(); ++j)
-            pk[loc_of(bi, gam[si].faces[j].inside, S.nx)] += gam[si].rho[j] * phi[k][si][j];
-        box_solve(S.local[i], pk);
-        for (size_t si = 0; si < gam.size(); ++si) {
-          const GammaSide& gs = gam[si];
-          const int nfs = (int)gs.faces.size();
-          for (int j = 0; j < nfs; ++j) {
-            double pc = pk[loc_of(bi, gs.faces[j].inside, S.nx)];
-            double U = gs.rho[j] * (pc - phi[k][si][j]);
-            double pi = phi[k][si][j] + gs.b[j] * U;
             for (int q = 0; q < M.nbasis(nfs); ++q) {
-              double w = legendre(q, xi_of(j, nfs));
+              const double w = legendre(q, xi_of(j, nfs));
               sub[i].colU[k][si][q] += w * U;
               sub[i].colP[k][si][q] += w * pi;
             }

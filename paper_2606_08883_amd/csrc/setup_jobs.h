@@ -55,30 +55,30 @@ struct OverRhs {
 };
 
 // A face of Gamma_i: its cells in the oversampled box (ocout = -1: the face
-// is on the oversampled box's boundary) and in the subdomain box; the index
-// si of its side among the subdomain's interface sides, the side code
-// (W E S N), its position j among the nfs faces of the side; conductances.
+// is on the oversampled box's boundary, which happens without oversampling),
+// the index si of its side among the subdomain's interface sides, the side
+// code (W E S N), its position j among the nfs faces of the side;
+// conductances.
 struct GamFace {
-  int ocin, ocout, lcin;
+  int ocin, ocout;
   int si, side, j, nfs;
-  int unused;
+  int unused0, unused1;
   double rho, b, t, Kin, Kout;
 };
 
-// The set-up work of one subdomain: its box and oversampled box (origins are
-// implied by the tables), ni local dofs (the first is dof0), nsides sides of
-// Gamma_i, its entries of the OverRhs and GamFace tables, and offsets of
-// its FP64 factors and couplings, scratch vectors (ni x cells), phi values
-// (ni x faces), MBF output (ni x cells, storage type) and moments (ni x
-// nsides x nb).
+// The set-up work of one subdomain: its oversampled box (obx x oby, pinned
+// when opin) and the subdomain box inside it (lbx x lby at offset ox, oy);
+// ni local dofs (the first is dof0), nsides sides of Gamma_i, its entries of
+// the OverRhs and GamFace tables, and offsets of the oversampled factor and
+// couplings (FP64), scratch vectors (ni x oversampled cells), MBF output
+// (ni x subdomain cells, storage type) and moments (ni x nsides x nb).
 struct SubJob {
-  int lbx, lby, lpin;
   int obx, oby, opin;
+  int lbx, lby, ox, oy;
   int ni, nsides, dof0;
   int rhs0, rhs1, gam0, gam1;
   int unused;
-  long long l64, lc64, o64, oc64;
-  long long lscr, oscr, phi, mbf, col;
+  long long o64, oc64, oscr, mbf, col;
 };
 
 }  // namespace mrcm

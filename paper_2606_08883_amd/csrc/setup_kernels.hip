@@ -2,12 +2,12 @@
 // subdomain:
 //  - k_factor_boxes: block LDL^T factorisation of a cell box by cell rows
 //    with explicit inverses of the row blocks (Gauss-Jordan in LDS);
-//  - k_over_phi: the oversampled Robin problems with Legendre data on each
-//    side of the oversampled box, and the informed multiplier functions phi
-//    on the faces of Gamma_i;
-//  - k_mbf: the multiscale basis functions (local Robin problems with the
-//    phi data) and their flux and pressure moments on Gamma_i (the columns
-//    of the interface system).
+//  - k_over_mbf: the oversampled Robin problems with Legendre data on each
+//    side of the oversampled box; their restrictions to Omega_i are the
+//    multiscale basis functions (the local Robin problem on Omega_i with the
+//    informed multiplier phi as data has exactly this solution), and their
+//    flux and pressure moments on Gamma_i are the columns of the interface
+//    system.
 #include "device.h"
 #include "setup_jobs.h"
 
@@ -235,15 +235,20 @@ __device__ void box_solve64_multi(double* X, int nrhs, long long ncell, int bx, 
 }
 
 // Oversampled problems of one subdomain (one right-hand side per local dof:
-// its Legendre function as Robin data on its side of the oversampled box)
-// and the informed functions phi on the faces of Gamma_i:
-//   phi = pi - b U, with U, pi the flux and pressure of the oversampled
-//   solution across the face (from the cells on both sides, or from the
-//   Robin data when the oversampled box is the subdomain box).
+// its Legendre function as Robin data on its side of the oversampled box),
+// solved in the scratch vectors; then
+//   mbf = the solutions restricted to Omega_i (storage type), and
+//   colU = sum_j P_q(xi_j) U_j,  colP = sum_j P_q(xi_j) pi_j
+// over the faces of every side si of Gamma_i and mode q, with U, pi the flux
+// and pressure of the oversampled solution across the face (from the cells
+// on both sides, or, when the oversampled box is the subdomain box, from the
+// Robin data lambda of the face: U = rho (p - lambda), pi = lambda + b U).
+template <typename S>
 __global__ void __launch_bounds__(64)
-    k_over_phi(const SubJob* __restrict__ subs, const OverRhs* __restrict__ rhs,
+    k_over_mbf(const SubJob* __restrict__ subs, const OverRhs* __restrict__ rhs,
                const GamFace* __restrict__ gam, const int* __restrict__ dof_side,
-               const int* __restrict__ dof_q, int over0, double* __restrict__ buf) {
+               const int* __restrict__ dof_q, int over0, int nb, double* __restrict__ buf,
+               S* __restrict__ mbf, double* __restrict__ colU, double* __restrict__ colP) {
   __shared__ double ys[kSolveRhs][64];
   const SubJob J = subs[blockIdx.x];
   const int lane = threadIdx.x;
@@ -259,66 +264,34 @@ __global__ void __launch_bounds__(64)
   for (int k0 = 0; k0 < J.ni; k0 += kSolveRhs)
     box_solve64_multi(X + (long long)k0 * ncell, J.ni - k0 < kSolveRhs ? J.ni - k0 : kSolveRhs,
                       ncell, J.obx, J.oby, buf + J.o64, buf + J.oc64, J.opin, lane, ys);
-  const int ng = J.gam1 - J.gam0;
-  for (int e = lane; e < J.ni * ng; e += 64) {
-    const int k = e / ng, f = e - k * ng;
-    const GamFace G = gam[J.gam0 + f];
-    const double pc = X[(long long)k * ncell + G.ocin];
-    double U, pi;
-    if (over0) {
-      const int dk = J.dof0 + k;
-      const double lam = G.side == dof_side[dk] ? legendre_d(dof_q[dk], xi_d(G.j, G.nfs)) : 0.0;
-      U = G.rho * (pc - lam);
-      pi = lam + G.b * U;
-    } else {
-      const double pn = X[(long long)k * ncell + G.ocout];
-      U = G.t * (pc - pn);
-      pi = (G.Kin * pc + G.Kout * pn) / (G.Kin + G.Kout);
-    }
-    buf[J.phi + (long long)k * ng + f] = pi - G.b * U;
+  const int lc = J.lbx * J.lby;
+  for (long long e = lane; e < (long long)J.ni * lc; e += 64) {
+    const int k = (int)(e / lc), q = (int)(e - (long long)k * lc);
+    const int j = q / J.lbx, a = q - j * J.lbx;
+    mbf[J.mbf + e] = (S)X[(long long)k * ncell + (long long)(J.oy + j) * J.obx + J.ox + a];
   }
-}
-
-// Multiscale basis functions of one subdomain: p_k = A_i^-1 (sum over the
-// faces of Gamma_i of rho phi_k at the inside cell), stored as the MBF
-// columns (storage type), and their moments on every side si and mode q:
-//   colU = sum_j P_q(xi_j) U_j,  colP = sum_j P_q(xi_j) pi_j,
-//   U = rho (p - phi), pi = phi + b U.
-template <typename S>
-__global__ void __launch_bounds__(64)
-    k_mbf(const SubJob* __restrict__ subs, const GamFace* __restrict__ gam, int nb,
-          double* __restrict__ buf, S* __restrict__ mbf, double* __restrict__ colU,
-          double* __restrict__ colP) {
-  __shared__ double ys[kSolveRhs][64];
-  const SubJob J = subs[blockIdx.x];
-  const int lane = threadIdx.x;
-  const int ncell = J.lbx * J.lby, ng = J.gam1 - J.gam0;
-  double* X = buf + J.lscr;
-  for (long long e = lane; e < (long long)J.ni * ncell; e += 64) X[e] = 0.0;
-  wfence();
-  // faces in order per right-hand side (a corner cell has two faces)
-  for (int k = lane; k < J.ni; k += 64)
-    for (int f = 0; f < ng; ++f) {
-      const GamFace G = gam[J.gam0 + f];
-      X[(long long)k * ncell + G.lcin] += G.rho * buf[J.phi + (long long)k * ng + f];
-    }
-  wfence();
-  for (int k0 = 0; k0 < J.ni; k0 += kSolveRhs)
-    box_solve64_multi(X + (long long)k0 * ncell, J.ni - k0 < kSolveRhs ? J.ni - k0 : kSolveRhs,
-                      ncell, J.lbx, J.lby, buf + J.l64, buf + J.lc64, J.lpin, lane, ys);
-  for (long long e = lane; e < (long long)J.ni * ncell; e += 64) mbf[J.mbf + e] = (S)X[e];
+  const int ng = J.gam1 - J.gam0;
   const int nt = J.ni * J.nsides * nb;
   for (int e = lane; e < nt; e += 64) {
     const int k = e / (J.nsides * nb), rem = e - k * (J.nsides * nb);
     const int si = rem / nb, q = rem - si * nb;
+    const int dk = J.dof0 + k;
     double su = 0.0, sp = 0.0;
     for (int f = 0; f < ng; ++f) {
       const GamFace G = gam[J.gam0 + f];
       if (G.si != si || q >= (nb < G.nfs ? nb : G.nfs)) continue;
-      const double pc = X[(long long)k * ncell + G.lcin];
-      const double phi = buf[J.phi + (long long)k * ng + f];
-      const double U = G.rho * (pc - phi);
-      const double pi = phi + G.b * U;
+      const double pc = X[(long long)k * ncell + G.ocin];
+      double U, pi;
+      if (over0) {
+        const double lam =
+            G.side == dof_side[dk] ? legendre_d(dof_q[dk], xi_d(G.j, G.nfs)) : 0.0;
+        U = G.rho * (pc - lam);
+        pi = lam + G.b * U;
+      } else {
+        const double pn = X[(long long)k * ncell + G.ocout];
+        U = G.t * (pc - pn);
+        pi = (G.Kin * pc + G.Kout * pn) / (G.Kin + G.Kout);
+      }
       const double w = legendre_d(q, xi_d(G.j, G.nfs));
       su += w * U;
       sp += w * pi;
@@ -343,19 +316,13 @@ void launch_factor_boxes(const FactorJob* jobs, int njobs, int maxn, const doubl
                      ny, aL, dS, cS, d64, c64, status);
 }
 
-void launch_over_phi(const SubJob* subs, int m, const OverRhs* rhs, const GamFace* gam,
-                     const int* dof_side, const int* dof_q, int over0, double* buf,
-                     hipStream_t s) {
-  if (m <= 0) return;
-  hipLaunchKernelGGL(k_over_phi, dim3(m), dim3(64), 0, s, subs, rhs, gam, dof_side, dof_q, over0,
-                     buf);
-}
-
 template <typename S>
-void launch_mbf(const SubJob* subs, int m, const GamFace* gam, int nb, double* buf, S* mbf,
-                double* colU, double* colP, hipStream_t s) {
+void launch_over_mbf(const SubJob* subs, int m, const OverRhs* rhs, const GamFace* gam,
+                     const int* dof_side, const int* dof_q, int over0, int nb, double* buf,
+                     S* mbf, double* colU, double* colP, hipStream_t s) {
   if (m <= 0) return;
-  hipLaunchKernelGGL(k_mbf<S>, dim3(m), dim3(64), 0, s, subs, gam, nb, buf, mbf, colU, colP);
+  hipLaunchKernelGGL(k_over_mbf<S>, dim3(m), dim3(64), 0, s, subs, rhs, gam, dof_side, dof_q,
+                     over0, nb, buf, mbf, colU, colP);
 }
 
 template void launch_factor_boxes<float>(const FactorJob*, int, int, const double*, const double*,
@@ -364,9 +331,11 @@ template void launch_factor_boxes<float>(const FactorJob*, int, int, const doubl
 template void launch_factor_boxes<double>(const FactorJob*, int, int, const double*,
                                           const double*, const double*, int, int, double,
                                           double*, double*, double*, double*, int*, hipStream_t);
-template void launch_mbf<float>(const SubJob*, int, const GamFace*, int, double*, float*, double*,
-                                double*, hipStream_t);
-template void launch_mbf<double>(const SubJob*, int, const GamFace*, int, double*, double*,
-                                 double*, double*, hipStream_t);
+template void launch_over_mbf<float>(const SubJob*, int, const OverRhs*, const GamFace*,
+                                     const int*, const int*, int, int, double*, float*, double*,
+                                     double*, hipStream_t);
+template void launch_over_mbf<double>(const SubJob*, int, const OverRhs*, const GamFace*,
+                                      const int*, const int*, int, int, double*, double*,
+                                      double*, double*, hipStream_t);
 
 }  // namespace mrcm

@@ -62,6 +62,7 @@ int mrcm_test_host_apply(const mrcm_grid* grid, const mrcm_params* params, const
     const mrcm::Maps& M = S.maps;
     mrcm::CoarseFactor CF =
         mrcm::coarse_factor(M, S.Crp, S.Cci, S.Cv, std::max(1, omp_get_max_threads()));
+    mrcm::coarse_refine_steps(CF, mrcm::kCoarseRefineTol, mrcm::kCoarseRefineMax);
     if (min_pivot_ratio) *min_pivot_ratio = CF.min_pivot_ratio;
     const int nx = S.nx;
     const size_t n = (size_t)S.nx * S.ny;
@@ -75,23 +76,39 @@ int mrcm_test_host_apply(const mrcm_grid* grid, const mrcm_params* params, const
     };
     std::vector<double> x;
     for (int i = 0; i < M.m; ++i) {
+      // source-driven solve on hat-Omega_i, kept on Omega_i
       const mrcm::Box& b = M.boxes[i];
-      gather(b, r, x);
-      mrcm::box_solve(S.local[i], x.data());
+      const mrcm::Box& ob = M.oboxes[i];
+      gather(ob, r, x);
+      mrcm::box_solve(S.over[i], x.data());
+      const int ox = b.x0 - ob.x0, oy = b.y0 - ob.y0, obx = ob.bx(), oby = ob.by();
       for (int j = 0; j < b.by(); ++j)
         for (int a = 0; a < b.bx(); ++a)
-          p[(size_t)(b.y0 + j) * nx + b.x0 + a] = x[(size_t)j * b.bx() + a];
+          p[(size_t)(b.y0 + j) * nx + b.x0 + a] = x[(size_t)(oy + j) * obx + ox + a];
+      // trace moments: U = cUi p_in + cUo p_out, pi = cPi p_in + cPo p_out
       for (int k = M.dof_offset[i]; k < M.dof_offset[i + 1]; ++k) {
-        const int side = M.dofs[k][1];
+        const int side = M.dofs[k][1], q = M.dofs[k][2];
         const int len = mrcm::side_len(b, side);
         double su = 0.0, sp = 0.0;
         for (int jf = 0; jf < len; ++jf) {
-          int cell = side == 0 ? jf * b.bx()
-                   : side == 1 ? jf * b.bx() + b.bx() - 1
-                   : side == 2 ? jf
-                               : (b.by() - 1) * b.bx() + jf;
-          su += S.wU[S.wOff[k] + jf] * x[cell];
-          sp += S.wP[S.wOff[k] + jf] * x[cell];
+          int row, col, dr = 0, dc = 0;
+          if (side == 0) {
+            row = oy + jf; col = ox; dc = -1;
+          } else if (side == 1) {
+            row = oy + jf; col = ox + b.bx() - 1; dc = 1;
+          } else if (side == 2) {
+            row = oy; col = ox + jf; dr = -1;
+          } else {
+            row = oy + b.by() - 1; col = ox + jf; dr = 1;
+          }
+          const int r2 = row + dr, c2 = col + dc;
+          const bool across = r2 >= 0 && r2 < oby && c2 >= 0 && c2 < obx;
+          const double pin = x[(size_t)row * obx + col];
+          const double pout = across ? x[(size_t)r2 * obx + c2] : pin;
+          const double* w = &S.face_w[(size_t)4 * (S.dof_face0[k] + jf)];
+          const double lw = mrcm::legendre(q, (2.0 * jf + 1.0) / len - 1.0);
+          su += lw * (w[0] * pin + w[1] * pout);
+          sp += lw * (w[2] * pin + w[3] * pout);
         }
         mU[k] = su;
         mP[k] = sp;
@@ -105,7 +122,7 @@ int mrcm_test_host_apply(const mrcm_grid* grid, const mrcm_params* params, const
       }
       std::vector<double> gnd(nc);
       for (int q = 0; q < nc; ++q) gnd[q] = CF.nd_scale[q] * g[CF.nd_row[q]];
-      mrcm::coarse_solve_host(CF, gnd.data(), xc.data());
+      mrcm::coarse_solve_refined_host(CF, gnd.data(), xc.data());
       for (int i = 0; i < M.m; ++i) {
         const mrcm::Box& b = M.boxes[i];
         const int ncell = b.bx() * b.by();
@@ -137,6 +154,25 @@ int mrcm_test_host_apply(const mrcm_grid* grid, const mrcm_params* params, const
       mean /= (double)n;
     }
     for (size_t c = 0; c < n; ++c) z[c] = p[c] - mean;
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    return fail(e);
+  }
+}
+
+int mrcm_test_coarse_solve(const mrcm_grid* grid, const mrcm_params* params, const double* K,
+                           const double* g, double* x) {
+  try {
+    if (!g || !x) throw mrcm::Error(MRCM_EINVAL, "null argument");
+    mrcm::HostSetup S = make_setup(grid, params, K);
+    const int nc = S.maps.nc();
+    if (nc == 0) return MRCM_OK;
+    mrcm::CoarseFactor CF =
+        mrcm::coarse_factor(S.maps, S.Crp, S.Cci, S.Cv, std::max(1, omp_get_max_threads()));
+    mrcm::coarse_refine_steps(CF, mrcm::kCoarseRefineTol, mrcm::kCoarseRefineMax);
+    std::vector<double> gnd(nc);
+    for (int q = 0; q < nc; ++q) gnd[q] = CF.nd_scale[q] * g[CF.nd_row[q]];
+    mrcm::coarse_solve_refined_host(CF, gnd.data(), x);
     return MRCM_OK;
   } catch (const mrcm::Error& e) {
     return fail(e);

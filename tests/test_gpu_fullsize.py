@@ -2,14 +2,19 @@
 
 * 1024 x 1024 log-normal workload (4096 subdomains), precision modes 2 (the
   benchmark's) and 0: T r and the GMRES solution element by element against
-  the oracle, iteration counts within +-1 (mode 0) / +2 (mode 2).  The
-  interface system of this field has cond_1(C) ~ 4e10, so the FP64 gate is
-  the forward-error bound cond(C) * 2^-53 (tests/_gates.py), not 1e-10.
-* 4096 x 4096 mixture workload (16384 subdomains, contrast 1e8), precision
-  mode 2: the oracle's MRCM setup takes minutes there, so the check uses
-  what holds at any size: A x element by element against the oracle's sparse
-  A, zero mean and run-to-run bit identity of T r, and the true residual
-  the library reports for a GMRES cycle recomputed with the oracle's A.
+  the oracle.  Mode 0: the FP64 gate (tests/_gates.py: 1e-10, or the
+  interface system's forward-error bound where that is larger) and
+  iterations within +-1.  Mode 2: T within 1e-7, iterations within +-1, and
+  the solution within 1e-7 for solutions driven to relative residual 1e-10.
+* The 4096 x 4096 workload's kernels (32 x 32 subdomains grown by 4 cells,
+  36-cell-wide smoothing patches, two sweeps, the channel / log-normal
+  mixture with contrast 1e8, Dirichlet left/right data) on grids the oracle
+  sets up in minutes (512 x 512 and 1024 x 1024), modes 0 and 2, against the
+  oracle: T r, GMRES iterations and the solution at the same step.
+* 4096 x 4096 itself, precision mode 2: what holds at any size -- A x
+  element by element against the oracle's sparse A, run-to-run bit identity
+  of T r, a converged GMRES solve whose true residual, recomputed with the
+  oracle's A, meets the tolerance and matches the one the library reports.
 """
 import numpy as np
 import pytest
@@ -20,7 +25,7 @@ from oracle.mrcm import MRCM
 from paper_2606_08883_amd import binding as B
 from paper_2606_08883_amd import workloads as wl
 from paper_2606_08883_amd.configs import WORKLOADS
-from tests._gates import t_gate
+from tests._gates import MIXED_GATE, t_gate
 
 pytestmark = pytest.mark.gpu
 
@@ -71,6 +76,12 @@ def batched_oracle():
     return w, K, mr, b, r, Tr, ref, gate
 
 
+def oracle_at(mr, b, iterations):
+    """The oracle's GMRES run to exactly `iterations` steps (no early stop)."""
+    return gmres(lambda x: mr.A @ x, mr.apply, b, rtol=0.0, restart=10, maxit=iterations,
+                 atol=0.0)
+
+
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("precision", [2, 0])
 def test_batched_fullsize(dev, batched_oracle, precision):
@@ -78,33 +89,92 @@ def test_batched_fullsize(dev, batched_oracle, precision):
     w = w.with_(precision=precision)
     print(f"batched {w.nx}x{w.ny} precision {precision}", flush=True)
     ctx = B.Context(w.binding_config(), T(K, dev))
+    print(f"  interface refinement steps {ctx.query('coarse_refine'):.0f}", flush=True)
     z = torch.empty(w.cells, dtype=torch.float64, device=dev)
     ctx.apply(T(r, dev), z)
     errT = np.linalg.norm(z.cpu().numpy() - Tr) / np.linalg.norm(Tr)
     p = torch.zeros(w.cells, dtype=torch.float64, device=dev)
     st = ctx.gmres(T(b, dev), p, rtol=1e-8, restart=10, maxit=300)
     pg = p.cpu().numpy()
-    err = np.linalg.norm(pg - ref.p) / np.linalg.norm(ref.p)
     relres = np.linalg.norm(b - mr.A @ pg) / np.linalg.norm(b)
     print(f"  T rel L2 {errT:.2e}; its gpu {st.iterations} oracle {ref.iterations}; "
-          f"p rel L2 {err:.2e}; relres (oracle A) {relres:.2e} reported {st.final_relres:.2e}",
-          flush=True)
-    ctx.close()
+          f"relres (oracle A) {relres:.2e} reported {st.final_relres:.2e}", flush=True)
     gate = residual_gate(mr.A, pg, b)
     print(f"  residual rounding bound {gate:.2e}", flush=True)
     assert st.converged and relres <= 1e-8 + gate
     assert abs(relres - st.final_relres) <= gate
+    assert abs(st.iterations - ref.iterations) <= 1
     if precision == 0:
-        # FP64: the interface system's forward-error bound (cond(C) * 2^-53)
+        same = oracle_at(mr, b, st.iterations)
+        err = np.linalg.norm(pg - same.p) / np.linalg.norm(same.p)
+        print(f"  p rel L2 at the same step {err:.2e} (gate {tg:.2e})", flush=True)
         assert errT <= tg
-        assert abs(st.iterations - ref.iterations) <= 1
         assert err <= tg
     else:
         # FP32-stored factors: T differs by the FP32 rounding of the factors;
-        # the solutions agree to the tolerance both were driven to.
-        assert errT <= 1e-4
-        assert st.iterations <= ref.iterations + 2
-        assert err <= 1e-6
+        # solutions are compared where both are driven to 1e-10
+        ref10 = gmres(lambda x: mr.A @ x, mr.apply, b, rtol=1e-10, restart=10, maxit=300)
+        p10 = torch.zeros_like(p)
+        st10 = ctx.gmres(T(b, dev), p10, rtol=1e-10, restart=10, maxit=300)
+        err = np.linalg.norm(p10.cpu().numpy() - ref10.p) / np.linalg.norm(ref10.p)
+        print(f"  p rel L2 at relres 1e-10: {err:.2e}", flush=True)
+        assert errT <= MIXED_GATE
+        assert st10.converged and err <= MIXED_GATE
+    ctx.close()
+
+
+def _dirichlet(w, K, ctx, dev):
+    from oracle.discretization import rhs
+    f, g = w.boundary_data()
+    ref = rhs(K, w.nx, w.ny, w.bc, f, {0: g[:w.ny], 1: g[w.ny:2 * w.ny]}, 1.0 / w.nx)
+    bd = torch.empty(w.cells, dtype=torch.float64, device=dev)
+    ctx.rhs(T(f, dev), T(g, dev), 1.0 / w.nx, bd)
+    torch.cuda.synchronize()
+    assert np.linalg.norm(bd.cpu().numpy() - ref) <= 1e-14 * np.linalg.norm(ref)
+    return ref, bd
+
+
+@pytest.fixture(scope="module", params=[512, 1024], ids=["mixture-512", "mixture-1024"])
+def mixture_oracle(request):
+    n = request.param
+    w = WORKLOADS["large"].with_(nx=n, ny=n)
+    print(f"oracle setup: the 4096^2 workload's method on a {n}x{n} mixture field", flush=True)
+    K = wl.mixture_K(n, n, 5, 6)
+    mr = MRCM(K, **w.oracle_args())
+    r = wl.random_vector(w.cells, 14)
+    Tr = mr.apply(r)
+    return w, K, mr, r, Tr, t_gate(mr)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision", [2, 0])
+def test_large_kernels_against_oracle(dev, mixture_oracle, precision):
+    w, K, mr, r, Tr, tg = mixture_oracle
+    w = w.with_(precision=precision)
+    print(f"mixture {w.nx}x{w.ny} s={w.s} l={w.oversample} k={w.sweeps} precision {precision}",
+          flush=True)
+    ctx = B.Context(w.binding_config(), T(K, dev))
+    z = torch.empty(w.cells, dtype=torch.float64, device=dev)
+    ctx.apply(T(r, dev), z)
+    errT = np.linalg.norm(z.cpu().numpy() - Tr) / np.linalg.norm(Tr)
+    b, bd = _dirichlet(w, K, ctx, dev)
+    ref = gmres(lambda x: mr.A @ x, mr.apply, b, rtol=1e-8, restart=10, maxit=300)
+    p = torch.zeros(w.cells, dtype=torch.float64, device=dev)
+    st = ctx.gmres(bd, p, rtol=1e-8, restart=10, maxit=300)
+    pg = p.cpu().numpy()
+    same = oracle_at(mr, b, st.iterations)
+    err = np.linalg.norm(pg - same.p) / np.linalg.norm(same.p)
+    relres = np.linalg.norm(b - mr.A @ pg) / np.linalg.norm(b)
+    gate = tg if precision == 0 else MIXED_GATE
+    print(f"  refinement steps {ctx.query('coarse_refine'):.0f}; T rel L2 {errT:.2e} "
+          f"(gate {gate:.2e}); its gpu {st.iterations} oracle {ref.iterations}; p rel L2 at "
+          f"the same step {err:.2e}; relres {relres:.2e}", flush=True)
+    ctx.close()
+    assert ref.converged and st.converged
+    assert abs(st.iterations - ref.iterations) <= 1
+    assert relres <= 1e-8 + residual_gate(mr.A, pg, b)
+    assert errT <= gate
+    assert err <= gate
 
 
 @pytest.mark.timeout(900)
@@ -123,26 +193,25 @@ def test_large_fullsize_properties(dev):
     print(f"  op_apply rel L2 {errA:.2e}", flush=True)
     assert errA <= 1e-13
 
-    r = T(wl.random_vector(w.cells, 13, zero_mean=True), dev)
+    r = T(wl.random_vector(w.cells, 13), dev)
     z1 = torch.empty_like(r)
     z2 = torch.empty_like(r)
     ctx.apply(r, z1)
     ctx.apply(r, z2)
     zc = z1.cpu().numpy()
-    mean_rel = abs(zc.mean()) / np.abs(zc).max()
-    print(f"  T r: |mean| / max {mean_rel:.2e}; bit-identical repeat "
-          f"{bool(torch.equal(z1, z2))}", flush=True)
+    print(f"  T r bit-identical repeat {bool(torch.equal(z1, z2))}", flush=True)
     assert torch.equal(z1, z2)
-    assert mean_rel <= 1e-12 and np.all(np.isfinite(zc))
+    assert np.all(np.isfinite(zc))
 
-    b = w.rhs()
+    b, bd = _dirichlet(w, K, ctx, dev)
     p = torch.zeros(w.cells, dtype=torch.float64, device=dev)
-    st = ctx.gmres(T(b, dev), p, rtol=1e-8, restart=10, maxit=10, raise_on_noconv=False)
+    st = ctx.gmres(bd, p, rtol=1e-8, restart=10, maxit=100)
     pg = p.cpu().numpy()
     relres = np.linalg.norm(b - A @ pg) / np.linalg.norm(b)
-    print(f"  one GMRES cycle: {st.iterations} its, relres (oracle A) {relres:.3e} "
+    print(f"  GMRES: {st.iterations} its, relres (oracle A) {relres:.3e} "
           f"reported {st.final_relres:.3e}", flush=True)
     ctx.close()
-    assert st.iterations == 10
-    assert abs(relres - st.final_relres) <= residual_gate(A, pg, b)
-    assert relres <= 1.0 + 1e-12  # GMRES never increases the residual from p_0 = 0
+    gate = residual_gate(A, pg, b)
+    assert st.converged
+    assert relres <= 1e-8 + gate
+    assert abs(relres - st.final_relres) <= gate
