@@ -2,6 +2,17 @@
 
 FP64 gate: relative L2 1e-10.
 
+Mixed precision (precision modes 1 and 2): solutions driven to relative
+residual 1e-10 agree to MIXED_GATE = 1e-7.  T itself differs from the FP64
+operator by the FP32 rounding of the box factors (mode 2: stored in FP32,
+applied in FP64; mode 1: also applied in FP32): a box solve runs its block
+recurrence down and back up the rows of the box, one product with a rounded
+inverse block per row and direction, each of up to `cols` terms in FP32 in
+mode 1, so its first-order relative error is at most about
+(2 rows + cols) u32 (u32 = 2^-24); T chains the local solve and one patch
+solve per smoothing sweep, so mixed_t_gate = (k + 1) (2 rows + cols) u32
+with rows and cols the largest extents of the oversampled boxes and patches.
+
 The interface system C x = g of T is the one step whose conditioning can
 exceed what 1e-10 allows (the 1e6-contrast channel field, the sigma = 3
 log-normal field at 1024 x 1024).  The oracle solves it accurately (LU plus
@@ -23,6 +34,7 @@ import scipy.sparse.linalg as spla
 FP64_GATE = 1e-10
 MIXED_GATE = 1e-7
 UNIT_ROUNDOFF = 2.0 ** -53
+UNIT_ROUNDOFF_32 = 2.0 ** -24
 GATE_FACTOR = 16.0
 DENSE_COND_MAX = 4000
 
@@ -46,3 +58,11 @@ def t_gate(mr) -> float:
     if mr.part.nc == 0:
         return FP64_GATE
     return max(FP64_GATE, GATE_FACTOR * skeel_condition(mr) * UNIT_ROUNDOFF)
+
+
+def mixed_t_gate(mr) -> float:
+    P = mr.part
+    boxes = list(P.oboxes) + (list(P.pboxes) if mr.sweeps > 0 else [])
+    rows = max(int(b[3] - b[2]) for b in boxes)
+    cols = max(int(b[1] - b[0]) for b in boxes)
+    return (mr.sweeps + 1) * (2 * rows + cols) * UNIT_ROUNDOFF_32

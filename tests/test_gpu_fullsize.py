@@ -10,7 +10,8 @@
   36-cell-wide smoothing patches, two sweeps, the channel / log-normal
   mixture with contrast 1e8, Dirichlet left/right data) on grids the oracle
   sets up in minutes (512 x 512 and 1024 x 1024), modes 0 and 2, against the
-  oracle: T r, GMRES iterations and the solution at the same step.
+  oracle: T r, GMRES iterations, the solution at the same step (mode 0) or
+  for solutions driven to relative residual 1e-12 (mode 2).
 * 4096 x 4096 itself, precision mode 2: what holds at any size -- A x
   element by element against the oracle's sparse A, run-to-run bit identity
   of T r, a converged GMRES solve whose true residual, recomputed with the
@@ -25,7 +26,7 @@ from oracle.mrcm import MRCM
 from paper_2606_08883_amd import binding as B
 from paper_2606_08883_amd import workloads as wl
 from paper_2606_08883_amd.configs import WORKLOADS
-from tests._gates import MIXED_GATE, t_gate
+from tests._gates import MIXED_GATE, mixed_t_gate, t_gate
 
 pytestmark = pytest.mark.gpu
 
@@ -118,7 +119,7 @@ def test_batched_fullsize(dev, batched_oracle, precision):
         st10 = ctx.gmres(T(b, dev), p10, rtol=1e-10, restart=10, maxit=300)
         err = np.linalg.norm(p10.cpu().numpy() - ref10.p) / np.linalg.norm(ref10.p)
         print(f"  p rel L2 at relres 1e-10: {err:.2e}", flush=True)
-        assert errT <= MIXED_GATE
+        assert errT <= mixed_t_gate(mr)
         assert st10.converged and err <= MIXED_GATE
     ctx.close()
 
@@ -165,7 +166,7 @@ def test_large_kernels_against_oracle(dev, mixture_oracle, precision):
     same = oracle_at(mr, b, st.iterations)
     err = np.linalg.norm(pg - same.p) / np.linalg.norm(same.p)
     relres = np.linalg.norm(b - mr.A @ pg) / np.linalg.norm(b)
-    gate = tg if precision == 0 else MIXED_GATE
+    gate = tg if precision == 0 else mixed_t_gate(mr)
     print(f"  refinement steps {ctx.query('coarse_refine'):.0f}; T rel L2 {errT:.2e} "
           f"(gate {gate:.2e}); its gpu {st.iterations} oracle {ref.iterations}; p rel L2 at "
           f"the same step {err:.2e}; relres {relres:.2e}", flush=True)
@@ -174,7 +175,21 @@ def test_large_kernels_against_oracle(dev, mixture_oracle, precision):
     assert abs(st.iterations - ref.iterations) <= 1
     assert relres <= 1e-8 + residual_gate(mr.A, pg, b)
     assert errT <= gate
-    assert err <= gate
+    if precision == 0:
+        assert err <= gate
+    else:
+        # both driven to 1e-12 (the direct solve of these Dirichlet problems
+        # reaches ~1e-14): at contrast 1e8 two solutions at relative
+        # residual 1e-10 may differ by more than 1e-7 through the
+        # conditioning of A alone
+        ref10 = gmres(lambda x: mr.A @ x, mr.apply, b, rtol=1e-12, restart=10, maxit=400)
+        p10 = torch.zeros(w.cells, dtype=torch.float64, device=dev)
+        ctx2 = B.Context(w.binding_config(), T(K, dev))
+        st10 = ctx2.gmres(bd, p10, rtol=1e-12, restart=10, maxit=400)
+        e10 = np.linalg.norm(p10.cpu().numpy() - ref10.p) / np.linalg.norm(ref10.p)
+        ctx2.close()
+        print(f"  p rel L2 at relres 1e-12: {e10:.2e}", flush=True)
+        assert st10.converged and e10 <= MIXED_GATE
 
 
 @pytest.mark.timeout(900)

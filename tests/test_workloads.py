@@ -29,3 +29,14 @@ def test_dirichlet_left_right_data():
     assert w.bc == (1, 1, 0, 0) and w.field == "incl-low"
     f2, g2 = w.boundary_data()
     assert g2.shape == (2 * w.ny + 2 * w.nx,)
+
+
+def test_mixture_spans_the_contrast_with_channel_facies():
+    K = wl.mixture_K(256, 256, 5, 6)
+    assert abs(K.max() - 1.0) < 1e-15 and abs(K.max() / K.min() / 1e8 - 1.0) < 1e-9
+    chi = wl.gaussian_field(256, 256, 160.0, 24.0, 5) > 0.0
+    # the facies still separate the field: channel cells are on average
+    # about the facies contrast (1e4, stretched) more permeable
+    ratio = np.exp(np.log(K[chi.ravel()]).mean() - np.log(K[~chi.ravel()]).mean())
+    assert 1e3 < ratio < 1e6
+    assert 0.3 < chi.mean() < 0.7
