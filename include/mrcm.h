@@ -136,6 +136,20 @@ int mrcm_setup(const mrcm_grid* grid, const mrcm_params* params, const double* K
  * then the smoothing sweeps).  r, z: device [nrhs][n]; may not alias. */
 int mrcm_apply(mrcm_ctx* ctx, const double* r, double* z, int32_t nrhs, void* stream);
 
+/* z = T r for nrhs vectors, as mrcm_apply, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  This call allocates nothing: its work
+ * space (two cell vectors and the interface-solve vectors of one column) is
+ * a static array of the library, 256 MiB per device, held from the first
+ * call on a device until the process ends; a context whose work space does
+ * not fit (more than about 16 M cells in FP64 work vectors) is rejected with
+ * MRCM_EINVAL.  The columns run one after the other with the one-column
+ * kernels, so z equals mrcm_apply's one-column result bit for bit.  Every
+ * call on a device shares that device's array and leaves its contents
+ * behind: calls that overlap on one device (other streams or threads) race
+ * and must be ordered by the caller.  Per-phase timing is not recorded. */
+int mrcm_apply_noalloc(mrcm_ctx* ctx, const double* r, double* z, int32_t nrhs, void* stream);
+
 /* z_i = T_i r_i for n set-up contexts at once (Section 3, as mrcm_apply,
  * for several permeability fields or grids): every context's applications
  * run on its own stream after the work already queued on `stream`, so the

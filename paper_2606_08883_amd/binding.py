@@ -20,7 +20,8 @@ MRCM_OK, MRCM_EINVAL, MRCM_ENOMEM, MRCM_ESINGULAR, MRCM_ENOCONV, MRCM_EDEVICE = 
 _NAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "ESINGULAR", -4: "ENOCONV", -5: "EDEVICE"}
 
 # Every symbol the headers declare (checked by the test suite).
-EXPORTED = ["mrcm_map_sizes", "mrcm_maps", "mrcm_setup", "mrcm_apply", "mrcm_apply_many",
+EXPORTED = ["mrcm_map_sizes", "mrcm_maps", "mrcm_setup", "mrcm_apply", "mrcm_apply_noalloc",
+            "mrcm_apply_many",
             "op_apply", "gmres_solve", "mrcm_rhs", "mrcm_footprint", "mrcm_timing_enable",
             "mrcm_timing_read", "mrcm_query", "mrcm_set_allocator", "mrcm_set_lanes", "mrcm_set_batch",
             "mrcm_set_host_threads",
@@ -83,6 +84,7 @@ def lib() -> ctypes.CDLL:
             "mrcm_maps": ([pG, pP] + [pi32] * 8, i32),
             "mrcm_setup": ([pG, pP, P, P, ctypes.POINTER(P)], i32),
             "mrcm_apply": ([P, P, P, i32, P], i32),
+            "mrcm_apply_noalloc": ([P, P, P, i32, P], i32),
             "mrcm_apply_many": ([ctypes.POINTER(P), i32, ctypes.POINTER(P), ctypes.POINTER(P),
                                  pi32, P], i32),
             "mrcm_set_allocator": ([ALLOC_FN, FREE_FN], None),
@@ -349,6 +351,12 @@ class Context:
         """z = T r (mrcm_apply)."""
         k = self._nrhs(r)
         _check(lib().mrcm_apply(self._ptr, _dptr(r), _dptr(z, r.numel()), k, _stream(stream)))
+
+    def apply_noalloc(self, r, z, stream=None):
+        """z = T r with the library's static work space (mrcm_apply_noalloc)."""
+        k = self._nrhs(r)
+        _check(lib().mrcm_apply_noalloc(self._ptr, _dptr(r), _dptr(z, r.numel()), k,
+                                        _stream(stream)))
 
     def op(self, x, y, stream=None):
         """y = A x (op_apply)."""

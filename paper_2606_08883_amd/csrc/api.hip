@@ -1216,6 +1216,103 @@ int mrcm_setup(const mrcm_grid* grid, const mrcm_params* params, const double* K
   }
 }
 
+}  // extern "C"
+
+// ---- applications that allocate nothing ------------------------------------
+// The work space of mrcm_apply_noalloc: one array per device, held from the
+// library's load until the process ends.  Host code never passes `scratch`
+// itself (in host code the name is a host-side stand-in, not a device
+// address): its device address is looked up once per device with
+// hipGetSymbolAddress and kept in g_scratch_ptr.
+namespace {
+
+constexpr size_t kScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mutex;
+std::map<int, void*> g_scratch_ptr;
+
+// Device address of this device's `scratch` (looked up on the first call on
+// the device, with the device current).
+void* scratch_ptr() {
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+  if (!ptr) throw mrcm::Error(MRCM_EDEVICE, "hipGetSymbolAddress returned no address");
+  g_scratch_ptr[dev] = ptr;
+  return ptr;
+}
+
+// A lane whose one-column work space (the vectors apply_one uses) is carved
+// from `base`; returns the bytes it takes (256-byte aligned pieces).
+size_t carve_lane(const mrcm_ctx* c, char* base, mrcm_ctx::Lane& L) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+    return p;
+  };
+  const size_t nc = std::max(c->nc, 1), np = std::max(c->np, 1);
+  L.pT = take(c->tsize * (size_t)c->n);
+  L.rhoT = take(c->tsize * (size_t)c->n);
+  L.mU = reinterpret_cast<double*>(take(8 * nc));
+  L.mP = reinterpret_cast<double*>(take(8 * nc));
+  L.xc = reinterpret_cast<double*>(take(8 * nc));
+  L.dx = reinterpret_cast<double*>(take(8 * nc));
+  L.g_nd = reinterpret_cast<double*>(take(8 * np));
+  L.ybuf = reinterpret_cast<double*>(take(8 * np));
+  L.rnd = reinterpret_cast<double*>(take(8 * np));
+  L.contrib = reinterpret_cast<double*>(take(8 * np * (size_t)c->maxp));
+  L.partials = reinterpret_cast<double*>(take(8 * 2 * (size_t)mrcm::kMaxVecBlocks));
+  return off;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mrcm_apply_noalloc(mrcm_ctx* c, const double* r, double* z, int32_t nrhs, void* stream) {
+  try {
+    if (!c || nrhs < 0) throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+    if (nrhs == 0) return MRCM_OK;
+    if (!r || !z) throw mrcm::Error(MRCM_EINVAL, "null vector");
+    mrcm_ctx::Lane L;
+    const size_t need = carve_lane(c, nullptr, L);
+    if (need > kScratchBytes)
+      throw mrcm::Error(MRCM_EINVAL, "mrcm_apply_noalloc: the context needs " +
+                                         std::to_string(need) + " bytes of work space, more "
+                                         "than the " + std::to_string(kScratchBytes) +
+                                         " bytes of the library's static array");
+    char* base = static_cast<char*>(scratch_ptr());
+    carve_lane(c, base, L);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    L.st = s;
+    // the array keeps the last call's contents: unused contribution slots
+    // must read zero
+    mrcm::launch_zero(L.contrib, (long long)std::max(c->np, 1) * c->maxp, s);
+    // no event timing here (its events are created on demand)
+    const bool timing = c->timing;
+    c->timing = false;
+    try {
+      for (int k = 0; k < nrhs; ++k)
+        apply_dispatch(c, L, r + (size_t)k * c->n, z + (size_t)k * c->n, s);
+    } catch (...) {
+      c->timing = timing;
+      throw;
+    }
+    c->timing = timing;
+    check_launch();
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    set_error(e.what());
+    return e.code;
+  }
+}
+
 int mrcm_apply(mrcm_ctx* c, const double* r, double* z, int32_t nrhs, void* stream) {
   try {
     if (!c || nrhs < 0) throw mrcm::Error(MRCM_EINVAL, "invalid argument");

@@ -168,6 +168,8 @@ void launch_resid_norm(const double* tx, const double* ty, int nx, int ny, const
                        const double* p, double* r, double* partials, int nb, hipStream_t s);
 // v = alpha * v
 void launch_scale(double* v, long long n, double alpha, hipStream_t s);
+// v = 0 (a kernel, so that it can be captured in a graph)
+void launch_zero(double* v, long long n, hipStream_t s);
 // w = A z, partials = w . v0
 void launch_arnoldi_start(const double* tx, const double* ty, int nx, int ny, const double* z,
                           double* w, const double* v0, double* partials, int nb, hipStream_t s);

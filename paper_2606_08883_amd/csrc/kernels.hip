@@ -1024,6 +1024,12 @@ __global__ void __launch_bounds__(kVecThreads)
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+__global__ void k_zero(double* __restrict__ v, long long n) {
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
+       c += (long long)gridDim.x * blockDim.x)
+    v[c] = 0.0;
+}
+
 __global__ void k_scale(double* __restrict__ v, long long n, double alpha) {
   for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
        c += (long long)gridDim.x * blockDim.x)
@@ -2116,6 +2122,11 @@ void launch_resid_norm(const double* tx, const double* ty, int nx, int ny, const
                        const double* p, double* r, double* partials, int nb, hipStream_t s) {
   hipLaunchKernelGGL(k_resid_norm, dim3(nb), dim3(kVecThreads), 0, s, tx, ty, nx, ny, b, p, r,
                      partials);
+}
+
+void launch_zero(double* v, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_zero, dim3(grid_for(n)), dim3(kVecThreads), 0, s, v, n);
 }
 
 void launch_scale(double* v, long long n, double alpha, hipStream_t s) {
