@@ -3,16 +3,24 @@
 A step is one solve of A p = b to a true FP64 relative residual of 1e-8 with
 right-preconditioned GMRES(10) and the MRCM-OS operator, the operator's
 factorisations resident in HBM (setup excluded from the timed region and
-reported separately).  Every step runs the whole hot path: local Robin
-solves with trace moments, interface solve, reconstruction, smoothing
-residual and patch solves, output projection, the fine operator, Gram-Schmidt
+reported separately).  Every step runs the whole hot path: local solves on
+the oversampled boxes with trace moments, interface solve, reconstruction,
+smoothing residual and patch solves, output, the fine operator, Gram-Schmidt
 and the solution update.
 
-Prints one JSON line (rank 0).  Besides the contract keys it carries the
-roofline of the dominant kernel (measured live with HIP events on the
-library's stream), the oracle timed on the host cores on a bounded sample,
-cell-DOF/s, p50/p99 latency of the timed solves and setup-inclusive
-throughput.
+The default workload is the largest single-GPU configuration: 4096 x 4096
+cells, the channel / log-normal mixture of contrast 1e8, 32 x 32 subdomains
+grown by 4 cells, two smoothing sweeps, pressure 1 on the left side and 0 on
+the right.  Prints one JSON line.  Besides the contract keys it carries:
+  roofline         the dominant phase of the preconditioner apply (largest
+                   device time), algorithmic bytes over its HIP-event
+                   duration on the library's stream;
+  phases           the same for every phase of the apply;
+  precisions       solves/s of the same workload with FP64, FP32 and
+                   FP32-stored factors;
+  batched_1024     the 1024 x 1024 log-normal workload (4096 subdomains);
+  serving          a short Poisson stream of mixed-size requests (p50/p99);
+  cpu_baseline     the oracle timed on the host cores on a bounded sample.
 """
 from __future__ import annotations
 
@@ -20,6 +28,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import subprocess
 import sys
 import time
@@ -31,6 +40,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 CSRC = os.path.join(ROOT, "paper_2606_08883_amd", "csrc")
+METRIC = "GMRES+MRCM-OS solves/s & cell-DOF/s at rel.res 1e-8; p50/p99 solve latency"
 
 
 def kernel_source_hash() -> str:
@@ -81,22 +91,31 @@ def box_cols(max_bx: int) -> int:
     return 64
 
 
-def algorithmic_bytes(cfg, maps, tw: int, sw: int) -> dict:
-    """Algorithmic bytes of one launch of the local and patch kernels
-    (tw: bytes of a work-vector word, sw: bytes of a stored factor word).
+def algorithmic_bytes(w, maps, ctx) -> dict:
+    """Algorithmic bytes of one instance of every phase of the apply (tw:
+    bytes of a work-vector word, sw: of a stored factor word).
 
-    The factor of a box bx cells wide and by rows is stored as by half
-    blocks of rows x bx words (rows = cols / 2 + 1, cols the launch's column
-    width) plus by x bx couplings; the algorithmic count reads them once.
-    Local solve of subdomain i on its oversampled box (ox x oy cells, owned
-    bx x by): factor and couplings, r read on the box (8 B/cell, FP64), p
-    written on the owned cells (tw/cell), the four trace weights of every
-    face of Gamma_i read (32 B per face) and two moments per dof written
-    (16 B per dof).
-    Patch solve of patch i (px x py cells, owned bx x by): factor and
-    couplings, the residual read on the patch (tw/cell), p read and written
-    on the owned cells (2 tw/cell).
+    The factor of a box bx cells wide and by rows is stored as by half blocks
+    of rows x bx words (rows = cols / 2 + 1, cols the launch's column width)
+    plus by x bx couplings; the algorithmic count reads them once.
+      local       per subdomain, on its oversampled box (ox x oy, owned
+                  bx x by): factor and couplings, r read on the box (8 B/cell),
+                  p written on the owned cells (tw), the four trace weights of
+                  every face of Gamma_i (32 B) and two moments per dof (16 B);
+      coarse      the interface solve: its factor matrices once per sweep and
+                  the refinement residuals (mrcm_query's count);
+      reconstruct the MBFs (sw per entry), the interface solution (8 B per
+                  dof) and p read and written (2 tw per cell);
+      residual    tx and ty (tw per face), r (8 B) and p (tw) read, rho
+                  written (tw), per cell;
+      patch       per patch (px x py, owned bx x by): factor and couplings, the
+                  residual on the patch (tw), p read and written on the owned
+                  cells (2 tw);
+      finalize    p read (tw, twice with the zero-mean projection) and z
+                  written (8 B) per cell.
     """
+    tw, sw = words(w.precision)
+    n = w.nx * w.ny
     b = maps["boxes"]
     bx = (b[:, 1] - b[:, 0]).astype(np.int64)
     by = (b[:, 3] - b[:, 2]).astype(np.int64)
@@ -106,73 +125,61 @@ def algorithmic_bytes(cfg, maps, tw: int, sw: int) -> dict:
     lrows = box_cols(int(ox.max())) // 2 + 1
     local = int(np.sum(oy * ox * lrows * sw + oy * ox * sw + oy * ox * 8 + by * bx * tw))
     dofs = maps["dof_table"]
+    nc = len(dofs)
     faces = 0
-    for i in range(len(b)):
-        sides = set(dofs[dofs[:, 0] == i][:, 1].tolist()) if len(dofs) else set()
-        faces += sum(int(by[i]) if s <= 1 else int(bx[i]) for s in sides)
-    local += faces * 32 + len(dofs) * 16
+    if nc:
+        sides = np.unique(dofs[:, :2], axis=0)
+        lens = np.where(sides[:, 1] <= 1, by[sides[:, 0]], bx[sides[:, 0]])
+        faces = int(lens.sum())
+    local += faces * 32 + nc * 16
+    per_sub = np.bincount(dofs[:, 0], minlength=len(b)) if nc else np.zeros(len(b), np.int64)
+    recon = int(np.sum(per_sub * bx * by) * sw + nc * 8 + 2 * n * tw)
     p = maps["pboxes"]
     px = (p[:, 1] - p[:, 0]).astype(np.int64)
     py = (p[:, 3] - p[:, 2]).astype(np.int64)
     prows = box_cols(int(px.max())) // 2 + 1
     patch = int(np.sum(py * px * prows * sw + py * px * sw + py * px * tw + 2 * bx * by * tw))
-    return {"local": local, "patch": patch}
+    faces_all = w.ny * (w.nx + 1) + (w.ny + 1) * w.nx
+    residual = faces_all * tw + n * (8 + 2 * tw)
+    finalize = n * ((2 if not any(w.bc) else 1) * tw + 8)
+    return {"local": local, "coarse": int(ctx.query("coarse_bytes")), "reconstruct": recon,
+            "residual": residual, "patch": patch, "finalize": finalize}
 
 
-def interface_solve(ctx, phases) -> dict:
-    """The interface solve (right-hand side, forward and backward levels),
-    reported beside the roofline: its levels are latency-bound (each a
-    dependent launch reading a few MB), so its effective bandwidth, the
-    factor bytes per apply over its time per apply, sits far below the HBM
-    peak."""
-    ms = phases["coarse"][0] / max(1, phases["coarse"][1])
-    nbytes = ctx.query("coarse_bytes")
-    return {"bound": "latency", "launches_per_apply": int(ctx.query("coarse_launches")) + 1,
-            "factor_bytes_per_apply": nbytes, "ms_per_apply": ms,
-            "effective_GB_s": nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None}
+PHASE_KERNELS = {"local": "k_local", "coarse": "interface solve (k_coarse_rhs, k_coarse_fwd "
+                 "and k_coarse_bwd per level, k_coarse_resid and k_coarse_add per refinement)",
+                 "reconstruct": "k_reconstruct", "residual": "k_residual", "patch": "k_patch",
+                 "finalize": "k_sum + k_finalize"}
 
 
-def cpu_baseline(workload_name: str, gpu_iterations: int, budget_s: float = 25.0) -> dict:
-    """Time the oracle (as it stands) on the host: its setup for the same
-    workload, then GMRES inner steps until the budget is spent; the solve
-    time is the mean inner-step time times the iterations of one solve."""
-    code = r"""
-import json, sys, time
-import numpy as np
-sys.path.insert(0, %r)
-from oracle.mrcm import MRCM
-from oracle.gmres import gmres
-from paper_2606_08883_amd.configs import WORKLOADS
-w = WORKLOADS[%r]
-K = w.permeability()
-t0 = time.perf_counter()
-mr = MRCM(K, **w.oracle_args())
-t_setup = time.perf_counter() - t0
-b = w.rhs()
-steps = 0
-t0 = time.perf_counter()
-while True:
-    res = gmres(lambda x: mr.A @ x, mr.apply, b, rtol=1e-8, restart=10, maxit=2)
-    steps += res.iterations
-    if time.perf_counter() - t0 > %f:
-        break
-t_step = (time.perf_counter() - t0) / steps
-print(json.dumps({"setup_s": t_setup, "step_s": t_step, "steps": steps}))
-""" % (ROOT, workload_name, budget_s)
-    env = dict(os.environ)
-    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
-        env[k] = "1"
-    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
-                         timeout=900)
-    if out.returncode != 0:
-        raise RuntimeError(out.stderr[-2000:])
-    d = json.loads(out.stdout.strip().splitlines()[-1])
-    solve_s = d["step_s"] * gpu_iterations
-    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle setup ({d['setup_s']:.1f} s, excluded) then {d['steps']} GMRES "
-                       f"inner steps (T apply + A apply + MGS) of the same workload in "
-                       f"{budget_s:.0f} s; solve time = mean step time "
-                       f"({d['step_s'] * 1e3:.1f} ms) x {gpu_iterations} steps per solve")}
+def phase_table(w, maps, ctx, phases) -> dict:
+    """Per phase: device ms per instance (HIP events on the library's
+    stream), algorithmic bytes per instance, achieved GB/s and fraction of
+    the HBM peak."""
+    ab = algorithmic_bytes(w, maps, ctx)
+    out = {}
+    napply = max(1, phases["local"][1])
+    for k, (ms, cnt) in phases.items():
+        if cnt == 0:
+            continue
+        avg = ms / cnt
+        gbs = ab[k] / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
+        out[k] = {"kernel": PHASE_KERNELS[k], "ms": avg, "per_apply": cnt / napply,
+                  "algorithmic_bytes": ab[k], "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS}
+    return out
+
+
+def roofline_of(table: dict, w) -> dict:
+    """The roofline entry of the phase with the largest device time per
+    apply."""
+    dom = max(table, key=lambda k: table[k]["ms"] * table[k]["per_apply"])
+    t = table[dom]
+    kernel = "k_" + dom if dom not in ("coarse", "finalize") else t["kernel"]
+    return {"bound": "hbm", "kernel": kernel, "phase": dom, "achieved": t["GB_s"],
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": t["frac"],
+            "traffic": recorded_traffic(kernel, f"{w.name}{w.nx}", w.precision),
+            "traffic_unit": "bytes per launch",
+            "algorithmic_bytes_per_launch": t["algorithmic_bytes"], "avg_launch_ms": t["ms"]}
 
 
 def rhs_of(w, ctx, dev):
@@ -187,6 +194,208 @@ def rhs_of(w, ctx, dev):
     ctx.rhs(torch.tensor(f, dtype=torch.float64, device=dev),
             torch.tensor(g, dtype=torch.float64, device=dev), 1.0 / w.nx, b)
     return b
+
+
+def timed_solves(ctx, b, steps: int, warmup: int) -> dict:
+    """`warmup` untimed solves, then `steps` timed ones between device
+    synchronisations; per-solve latency, iterations and true residuals."""
+    import torch
+    p = torch.zeros_like(b)
+    for _ in range(warmup):
+        ctx.gmres(b, p, rtol=1e-8, restart=10, maxit=500)
+    torch.cuda.synchronize()
+    lat, its, rel = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        st = ctx.gmres(b, p, rtol=1e-8, restart=10, maxit=500)
+        lat.append(time.perf_counter() - t1)
+        its.append(st.iterations)
+        rel.append(st.final_relres)
+        if not st.converged:
+            raise RuntimeError("GMRES did not converge")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    return {"elapsed": elapsed, "value": steps / elapsed, "ms": 1e3 * elapsed / steps,
+            "p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
+            "iterations": float(np.mean(its)), "relres_max": float(np.max(rel))}
+
+
+def phase_timing(ctx, b, steps: int) -> dict:
+    """The same solves again with HIP events around every phase of every
+    apply, on the library's stream (eager launches; the kernels are those of
+    the captured graphs of the timed region)."""
+    import torch
+    p = torch.zeros_like(b)
+    ctx.timing(True)
+    for _ in range(steps):
+        ctx.gmres(b, p, rtol=1e-8, restart=10, maxit=500)
+    torch.cuda.synchronize()
+    phases = ctx.timing_read()
+    ctx.timing(False)
+    return phases
+
+
+def workload_line(w) -> str:
+    bcs = "Dirichlet left/right" if any(w.bc) else "no-flow, corner sources"
+    return (f"{w.name}: {w.nx}x{w.ny} cells, subdomains of {w.s}x{w.s}, oversampling "
+            f"{w.oversample}, {w.sweeps} smoothing sweep(s), overlap {w.overlap}, alpha {w.alpha}, "
+            f"field {w.field}, {bcs}")
+
+
+def precisions(w, K, steps: int) -> dict:
+    """Solves/s of the same workload in every precision mode (setup, one
+    warm-up solve, `steps` timed solves)."""
+    import torch
+
+    from paper_2606_08883_amd import binding as B
+    out = {}
+    for prec in (0, 1, 2):
+        wp = w.with_(precision=prec)
+        ctx = B.Context(wp.binding_config(), K)
+        b = rhs_of(wp, ctx, K.device)
+        try:
+            r = timed_solves(ctx, b, steps, 1)
+            out[DTYPES[prec]] = {"solves_per_s": r["value"], "iterations": r["iterations"],
+                                 "relres_max": r["relres_max"]}
+        except RuntimeError as e:
+            out[DTYPES[prec]] = {"error": str(e)}
+        ctx.close()
+        torch.cuda.synchronize()
+        print(f"bench: precision {prec}: {out[DTYPES[prec]]}", file=sys.stderr, flush=True)
+    return out
+
+
+def batched_leg(steps: int) -> dict:
+    """The 1024 x 1024 log-normal workload (4096 subdomains): solves/s in
+    every precision mode."""
+    import torch
+
+    from paper_2606_08883_amd import binding as B
+    from paper_2606_08883_amd.configs import WORKLOADS
+    w = WORKLOADS["batched"]
+    dev = torch.device("cuda:0")
+    K = torch.tensor(w.permeability(), dtype=torch.float64, device=dev)
+    out = {"workload": workload_line(w)}
+    for prec in (2, 1, 0):
+        wp = w.with_(precision=prec)
+        ctx = B.Context(wp.binding_config(), K)
+        b = rhs_of(wp, ctx, dev)
+        r = timed_solves(ctx, b, steps, 2)
+        out[DTYPES[prec]] = {"solves_per_s": r["value"], "cell_dof_per_s": r["value"] * w.cells,
+                             "latency_ms": {"p50": r["p50"], "p99": r["p99"]},
+                             "iterations": r["iterations"]}
+        ctx.close()
+        print(f"bench: batched precision {prec}: {r['value']:.1f} solves/s", file=sys.stderr,
+              flush=True)
+    return out
+
+
+def serving_leg(requests: int, max_active: int) -> dict:
+    """A short Poisson stream of mixed-size requests (each with its own
+    field and 8 right-hand sides) at 0.8 of the closed-loop capacity."""
+    from paper_2606_08883_amd import serving as S
+    solver = S.gpu_solver(None, keep=False)
+    S.Server(solver, max_active=1).run([S.make_payload(S.Request(0, 128, 2.0, 999, 1999, 2, 0.0))],
+                                       realtime=False)
+    burst = [S.make_payload(r) for r in S.make_requests(max(4, requests // 2), rate=None, seed=5)]
+    t0 = time.perf_counter()
+    res = S.Server(solver, max_active=max_active, footprint=S.footprint_of).run(burst,
+                                                                                realtime=False)
+    cap = len(res) / (time.perf_counter() - t0)
+    rate = 0.8 * cap
+    reqs = [S.make_payload(r) for r in S.make_requests(requests, rate=rate, seed=4)]
+    server = S.Server(solver, max_active=max_active, footprint=S.footprint_of)
+    t0 = time.perf_counter()
+    res = server.run(reqs)
+    wall = time.perf_counter() - t0
+    sm = S.summary(res, wall)
+    return {"requests": requests, "grids": sorted({r.n for r in reqs}),
+            "arrival_rate_per_s": rate, "solves_per_s": sm["solves_per_s"],
+            "latency_ms": sm["latency_ms"], "all_converged": sm["all_converged"],
+            "setup_s_mean": sm["setup_s_mean"], "solve_s_mean": sm["solve_s_mean"],
+            "peak_active": server.peak_active}
+
+
+def cpu_baseline(w, gpu_iterations: float, window: int = 512) -> dict:
+    """The oracle as it stands, on the host cores, on a bounded sample of the
+    workload: the bottom-left window x window cells of the same field with
+    the same method parameters and boundary set-up, solved whole (setup,
+    then GMRES to 1e-8), once on one core and then as independent copies on
+    every core the box gives this run (at most 16).  The solve time per
+    GMRES step scales with the cell count (one box solve per subdomain and
+    sweep), so the estimate for the workload is the sample's time per step
+    times the cell ratio times the GPU's iterations per solve."""
+    code = r"""
+import json, sys, time
+import numpy as np
+sys.path.insert(0, %r)
+from oracle.discretization import rhs
+from oracle.gmres import gmres
+from oracle.mrcm import MRCM
+from paper_2606_08883_amd.configs import WORKLOADS
+w0 = WORKLOADS[%r]
+n = %d
+w = w0.with_(nx=n, ny=n)
+K = w0.permeability().reshape(w0.ny, w0.nx)[:n, :n].ravel().copy()
+t0 = time.perf_counter()
+mr = MRCM(K, **w.oracle_args())
+t_setup = time.perf_counter() - t0
+if any(w.bc):
+    f, g = w.boundary_data()
+    b = rhs(K, n, n, w.bc, f, {0: g[:n], 1: g[n:2 * n]}, 1.0 / n)
+else:
+    b = w.rhs()
+t0 = time.perf_counter()
+res = gmres(lambda x: mr.A @ x, mr.apply, b, rtol=1e-8, restart=10, maxit=300)
+t_solve = time.perf_counter() - t0
+print(json.dumps({"setup_s": t_setup, "solve_s": t_solve, "its": res.iterations,
+                  "converged": res.converged}))
+""" % (ROOT, w.name, window)
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        env[k] = "1"
+
+    def run(copies: int) -> list:
+        procs = [subprocess.Popen([sys.executable, "-c", code], stdout=subprocess.PIPE,
+                                  stderr=subprocess.PIPE, text=True, env=env)
+                 for _ in range(copies)]
+        out = []
+        for pr in procs:
+            so, se = pr.communicate(timeout=900)
+            if pr.returncode != 0:
+                raise RuntimeError(se[-2000:])
+            out.append(json.loads(so.strip().splitlines()[-1]))
+        return out
+
+    one = run(1)[0]
+    cores = max(1, min(os.cpu_count() or 1, 16))
+    t0 = time.perf_counter()
+    many = run(cores)
+    wall = time.perf_counter() - t0
+    scale = (w.nx * w.ny) / float(window * window)
+    step_1 = one["solve_s"] / one["its"]
+    solve_est_1 = step_1 * scale * gpu_iterations
+    # all cores: the copies solve at once; their combined steps per second,
+    # scaled the same way
+    step_rate_all = sum(m["its"] / m["solve_s"] for m in many)
+    solve_est_all = scale * gpu_iterations / step_rate_all
+    try:
+        model = [ln.split(":", 1)[1].strip() for ln in
+                 subprocess.run(["lscpu"], capture_output=True, text=True).stdout.splitlines()
+                 if ln.startswith("Model name")][0]
+    except Exception:
+        model = platform.processor() or "unknown"
+    return {"value": 1.0 / solve_est_all, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "single_core_solves_per_s": 1.0 / solve_est_1,
+            "cpu_model": model, "nproc": os.cpu_count(),
+            "sample": (f"the oracle (NumPy/SciPy FP64, one thread per process) on the "
+                       f"{window}x{window} bottom-left window of the same field and method "
+                       f"parameters, solved whole: setup {one['setup_s']:.1f} s, GMRES "
+                       f"{one['its']} steps in {one['solve_s']:.1f} s on one core; {cores} "
+                       f"independent copies at once took {wall:.1f} s wall.  Solve time of the "
+                       f"workload = time per step x cell ratio ({scale:.0f}) x the GPU's "
+                       f"{gpu_iterations:.1f} steps per solve; value = all {cores} cores")}
 
 
 def apply_only(args, w, ctx, b, setup_s) -> int:
@@ -211,27 +420,15 @@ def apply_only(args, w, ctx, b, setup_s) -> int:
     phases = ctx.timing_read()
     ctx.timing(False)
     maps = B.maps(w.binding_config())
-    abytes = algorithmic_bytes(w, maps, *words(w.precision))
-    dom = max(("local", "patch"), key=lambda k: phases[k][0])
-    avg_ms = phases[dom][0] / max(1, phases[dom][1])
-    achieved = abytes[dom] / (avg_ms * 1e-3) / 1e9
+    table = phase_table(w, maps, ctx, phases)
     out = {"metric": "MRCM-OS preconditioner applications/s", "value": args.steps / elapsed,
            "unit": "applies/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
            "dtype": DTYPES[w.precision], "data": "synthetic",
-           "config": {"workload": w.name, "cells": w.cells, "subdomains": int(maps["boxes"].shape[0])},
-           "setup_s": setup_s,
-           "autotune": {"ms": ctx.query("tune_ms"), "changes": ctx.query("tune_changes")},
-           "device_gb": ctx.query("device_bytes") / 1e9,
-           "coarse_min_pivot_ratio": ctx.query("coarse_pivot"),
-           "phase_ms_per_launch": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in phases.items()},
-           "algorithmic_bytes_per_launch": abytes,
-           "roofline": {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved,
-                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                        "traffic": recorded_traffic(f"k_{dom}", f"{w.name}{w.nx}",
-                                                    w.precision),
-                        "traffic_unit": "bytes per launch", "avg_launch_ms": avg_ms},
-           "interface_solve": interface_solve(ctx, phases)}
+           "config": {"workload": workload_line(w), "cells": w.cells,
+                      "subdomains": int(maps["boxes"].shape[0])},
+           "setup_s": setup_s, "device_gb": ctx.query("device_bytes") / 1e9,
+           "roofline": roofline_of(table, w), "phases": table}
     print(json.dumps(out), flush=True)
     ctx.close()
     return 0
@@ -245,7 +442,6 @@ def serve(args) -> int:
     params = None if args.precision is None else dict(precision=args.precision)
     prec = S.SERVE_PARAMS["precision"] if args.precision is None else args.precision
     fp = (lambda r: S.footprint_of(r, params))
-    # a set-up takes the host cores divided among the set-ups in progress
     B = S.gpu_solver(params, keep=False)
     warm = S.make_payload(S.Request(0, 128, 2.0, 999, 1999, 2, 0.0))
     S.Server(B, max_active=1).run([warm], realtime=False)
@@ -267,10 +463,10 @@ def serve(args) -> int:
     if not sm["all_converged"]:
         raise RuntimeError("a served request did not converge")
     sizes = sorted({r.n for r in reqs})
-    out = {"metric": "GMRES+MRCM-OS solves/s & cell-DOF/s at rel.res 1e-8; p50/p99 solve latency",
-           "value": sm["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": len(reqs),
-           "warmup": 1, "ms_per_step": 1e3 * wall / len(reqs), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": DTYPES[prec], "data": "synthetic",
+    out = {"metric": METRIC, "value": sm["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+           "steps": len(reqs), "warmup": 1, "ms_per_step": 1e3 * wall / len(reqs),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": DTYPES[prec], "data": "synthetic",
            "config": {"workload": f"serving: {len(reqs)} requests, grids {sizes} (uniform), "
                                   f"log-normal sigma U[1,3] corr. 16, 8 injector/producer "
                                   f"pairs each, Poisson arrivals at 0.8 x closed-loop capacity "
@@ -283,46 +479,6 @@ def serve(args) -> int:
            "peak_footprint_gb": server.peak_bytes / 1e9}
     print(json.dumps(out), flush=True)
     return 0
-
-
-def multi_rhs(args, w, ctx) -> dict:
-    """Throughput of one gmres call on nrhs injector/producer right-hand sides
-    (seeded cell pairs) on the same context, one at a time and with several in
-    flight: lanes (streams) x width (right-hand sides sharing one
-    multi-column application of T per step).  Each right-hand side's solution
-    is the same bit for bit in every arrangement (checked here)."""
-    import torch
-
-    from paper_2606_08883_amd import workloads as wl
-
-    b = torch.tensor(wl.random_pairs(w.nx, w.ny, args.nrhs, 2024), dtype=torch.float64,
-                     device="cuda:0").contiguous()
-    out = {"nrhs": args.nrhs, "rhs": "injector/producer cell pairs, seed 2024"}
-    ref = None
-    for lanes, width in ((1, 1), (4, 1), (1, 8), (2, 4)):
-        ctx.set_lanes(lanes)
-        ctx.set_batch(width)
-        p = torch.zeros_like(b)
-        ctx.gmres(b, p, rtol=1e-8, restart=10, maxit=500)  # warm-up: lanes, graphs
-        torch.cuda.synchronize()
-        reps = 2
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            st = ctx.gmres(b, p, rtol=1e-8, restart=10, maxit=500)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
-        if ref is None:
-            ref = p.clone()
-        elif not torch.equal(ref, p):
-            raise RuntimeError("lanes or batch width changed a solution")
-        out[f"lanes_{lanes}_width_{width}"] = {
-            "solves_per_s": args.nrhs / dt, "ms_per_call": 1e3 * dt,
-            "iterations_per_solve": st.iterations / args.nrhs}
-        print(f"bench: {args.nrhs} rhs on {lanes} lane(s) of width {width}: "
-              f"{args.nrhs / dt:.1f} solves/s", file=sys.stderr, flush=True)
-    ctx.set_lanes(4)
-    ctx.set_batch(4)
-    return out
 
 
 INCLUSION_ROWS = [("MRCM", 0, 0), ("2h", 2, 0), ("4h", 4, 0), ("2h,2S", 2, 2), ("2h,4S", 2, 4),
@@ -345,17 +501,13 @@ def inclusions(args) -> int:
     for kind in ("high", "low", "both"):
         w0 = WORKLOADS[f"incl-{kind}"]
         K = torch.tensor(w0.permeability(), dtype=torch.float64, device=dev)
-        f, g = w0.boundary_data()
-        ft = torch.tensor(f, dtype=torch.float64, device=dev)
-        gt = torch.tensor(g, dtype=torch.float64, device=dev)
         for s in (40, 20):
             for name, l, k in INCLUSION_ROWS:
                 w = w0.with_(s=s, oversample=l, sweeps=k)
                 print(f"bench: inclusions {kind} {160 // s}x{160 // s} {name}", file=sys.stderr,
                       flush=True)
                 ctx = B.Context(w.binding_config(), K)
-                b = torch.empty(w.cells, dtype=torch.float64, device=dev)
-                ctx.rhs(ft, gt, 1.0 / w.nx, b)
+                b = rhs_of(w, ctx, dev)
                 p = torch.zeros_like(b)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
@@ -377,12 +529,13 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batched",
+    ap.add_argument("--workload", default="large",
                     choices=["small", "channel", "batched", "large"])
-    ap.add_argument("--precision", type=int, default=None, help="0 FP64 apply, 1 FP32 apply, 2 FP32-stored factors with FP64 arithmetic")
+    ap.add_argument("--precision", type=int, default=None,
+                    help="0 FP64 apply, 1 FP32 apply, 2 FP32-stored factors with FP64 arithmetic")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--nrhs", type=int, default=8,
-                    help="right-hand sides of the extra multi-RHS measurement (0: skip)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the precision comparison, the 1024^2 workload and the serving leg")
     ap.add_argument("--apply-only", action="store_true",
                     help="time preconditioner applications T r instead of solves")
     ap.add_argument("--serve", action="store_true",
@@ -431,101 +584,68 @@ def main() -> int:
     if args.precision is not None:
         w = w.with_(precision=args.precision)
     dev = torch.device("cuda:0")
+    print(f"bench: workload {w.name} {w.nx}x{w.ny} precision {w.precision}: field",
+          file=sys.stderr, flush=True)
     K = torch.tensor(w.permeability(), dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
-    print(f"bench: workload {w.name} {w.nx}x{w.ny} precision {w.precision}", file=sys.stderr,
-          flush=True)
     t0 = time.perf_counter()
     ctx = B.Context(w.binding_config(), K)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    b = rhs_of(w, ctx, dev)
-    p = torch.zeros_like(b)
     print(f"bench: setup {setup_s:.2f} s", file=sys.stderr, flush=True)
+    b = rhs_of(w, ctx, dev)
     if args.apply_only:
         return apply_only(args, w, ctx, b, setup_s)
-    for _ in range(args.warmup):
-        st = ctx.gmres(b, p, rtol=1e-8, restart=10, maxit=500)
-    torch.cuda.synchronize()
-    lat = []
-    its = []
-    relres = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        t1 = time.perf_counter()
-        st = ctx.gmres(b, p, rtol=1e-8, restart=10, maxit=500)
-        lat.append(time.perf_counter() - t1)
-        its.append(st.iterations)
-        relres.append(st.final_relres)
-        if not st.converged:
-            raise RuntimeError("GMRES did not converge")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    # Kernel durations: the same solves again with HIP events recorded around
-    # every phase on the library's stream (eager launches; kernels are the
-    # same as in the captured graphs of the timed region).
-    ctx.timing(True)
-    for _ in range(args.steps):
-        ctx.gmres(b, p, rtol=1e-8, restart=10, maxit=500)
-    torch.cuda.synchronize()
-    phases = ctx.timing_read()
-    ctx.timing(False)
-    multi = multi_rhs(args, w, ctx) if args.nrhs > 0 else None
-    n = w.cells
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = args.steps / elapsed
+    r = timed_solves(ctx, b, args.steps, args.warmup)
+    print(f"bench: {r['value']:.2f} solves/s, {r['iterations']:.1f} iterations", file=sys.stderr,
+          flush=True)
+    phases = phase_timing(ctx, b, max(1, min(args.steps, 5)))
     maps = B.maps(w.binding_config())
-    abytes = algorithmic_bytes(w, maps, *words(w.precision))
-    # dominant kernel = the phase with the largest accumulated device time
-    dom = max(("local", "patch"), key=lambda k: phases[k][0])
-    avg_ms = phases[dom][0] / max(1, phases[dom][1])
-    achieved = abytes[dom] / (avg_ms * 1e-3) / 1e9
+    table = phase_table(w, maps, ctx, phases)
     apply_ms = sum(v[0] for v in phases.values()) / max(1, phases["local"][1])
     out = {
-        "metric": "GMRES+MRCM-OS solves/s & cell-DOF/s at rel.res 1e-8; p50/p99 solve latency",
-        "value": value,
+        "metric": METRIC,
+        "value": r["value"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": r["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": DTYPES[w.precision],
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: {w.nx}x{w.ny} cells, {maps['boxes'].shape[0]} "
-                               f"subdomains of {w.s}x{w.s}, oversampling {w.oversample}, "
-                               f"{w.sweeps} smoothing sweep(s), overlap {w.overlap}, "
-                               f"alpha {w.alpha}, field {w.field}, no-flow, corner sources",
-                   "cells": n, "precision": PRECISION_NAMES[w.precision],
-                   "rtol": 1e-8, "restart": 10, "parallelism": "single GPU"},
-        "cell_dof_per_s": value * n,
-        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
-                       "p99": float(np.percentile(lat, 99) * 1e3)},
-        "iterations_per_solve": float(np.mean(its)),
-        "final_relres_max": float(np.max(relres)),
+        "config": {"workload": workload_line(w), "cells": w.cells,
+                   "precision": PRECISION_NAMES[w.precision], "rtol": 1e-8, "restart": 10,
+                   "parallelism": "single GPU"},
+        "cell_dof_per_s": r["value"] * w.cells,
+        "latency_ms": {"p50": r["p50"], "p99": r["p99"]},
+        "iterations_per_solve": r["iterations"],
+        "final_relres_max": r["relres_max"],
         "setup_s": setup_s,
-        "autotune": {"ms": ctx.query("tune_ms"), "changes": ctx.query("tune_changes")},
-        "solves_per_s_incl_setup": 1.0 / (setup_s + elapsed / args.steps),
+        "solves_per_s_incl_setup": 1.0 / (setup_s + r["elapsed"] / args.steps),
+        "device_gb": ctx.query("device_bytes") / 1e9,
+        "interface_refinement_steps": ctx.query("coarse_refine"),
         "apply_ms": apply_ms,
-        "phase_ms_per_launch": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in phases.items()},
-        "roofline": {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": recorded_traffic(f"k_{dom}", f"{w.name}{w.nx}", w.precision),
-                     "traffic_unit": "bytes per launch",
-                     "algorithmic_bytes_per_launch": abytes[dom],
-                     "avg_launch_ms": avg_ms},
-        "interface_solve": interface_solve(ctx, phases),
+        "roofline": roofline_of(table, w),
+        "phases": table,
     }
-    if multi:
-        out["multi_rhs"] = multi
+    ctx.close()
+    torch.cuda.synchronize()
+    if not args.no_extras:
+        print("bench: precision modes", file=sys.stderr, flush=True)
+        out["precisions"] = precisions(w, K, max(2, args.steps // 4))
+        del K
+        torch.cuda.empty_cache()
+        print("bench: 1024^2 workload", file=sys.stderr, flush=True)
+        out["batched_1024"] = batched_leg(max(5, args.steps // 2))
+        print("bench: serving leg", file=sys.stderr, flush=True)
+        out["serving"] = serving_leg(32, 8)
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w.name, int(round(np.mean(its))))
+        out["cpu_baseline"] = cpu_baseline(w, r["iterations"])
     print(json.dumps(out), flush=True)
-    ctx.close()
     return 0
 
 

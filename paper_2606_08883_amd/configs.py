@@ -25,8 +25,9 @@ Field recipes and seeds:
           arithmetic, FP64 factorisation, interface solve and GMRES.
 * large   4096 x 4096 (16.8 M cells), channel / log-normal mixture with
           contrast 1e8 (seeds 5, 6), 16384 subdomains of 32 x 32, oversampling
-          4, two sweeps, alpha 10, L = H; FP32-stored factors with FP64
-          arithmetic (FP64 and FP32 apply for comparison).
+          4, two sweeps, alpha 10, L = H; local and smoothing solves applied
+          in FP32 (factors computed in FP64), FP64 interface solve and GMRES
+          (FP64 and FP32-stored factors for comparison).
 * incl-high, incl-low, incl-both
           160 x 160 thin inclusions (seed 11): 24 segments of K = 1e4, of
           K = 1e-4, or both (contrast 1e8) on K = 1, the stand-ins for the
@@ -109,7 +110,7 @@ WORKLOADS = {
     "small": Workload("small", 64, 64, 16, 2, 1.0, 1, 1, 2, 1, 0, "small"),
     "channel": Workload("channel", 220, 60, 20, 2, 10.0, 0, 1, 2, 1, 0, "channel", (1, 1, 0, 0)),
     "batched": Workload("batched", 1024, 1024, 16, 4, 10.0, 0, 1, 2, 1, 2, "batched"),
-    "large": Workload("large", 4096, 4096, 32, 4, 10.0, 0, 2, 2, 1, 2, "large", (1, 1, 0, 0)),
+    "large": Workload("large", 4096, 4096, 32, 4, 10.0, 0, 2, 2, 1, 1, "large", (1, 1, 0, 0)),
 }
 for _kind in ("high", "low", "both"):
     WORKLOADS[f"incl-{_kind}"] = Workload(f"incl-{_kind}", 160, 160, 20, 2, 10.0, 0, 2, 2, 1, 0,

@@ -1171,7 +1171,8 @@ int mrcm_setup(const mrcm_grid* grid, const mrcm_params* params, const double* K
       device_setup<double, double>(c, S, K_dev, s, colU, colP, col_off);
     mrcm::assemble_coarse(S, colU.data(), colP.data(), col_off);
     mrcm::CoarseFactor CF = mrcm::coarse_factor(S.maps, S.Crp, S.Cci, S.Cv, host_threads());
-    mrcm::coarse_refine_steps(CF, mrcm::kCoarseRefineTol, mrcm::kCoarseRefineMax);
+    mrcm::coarse_refine_steps(CF, mrcm::coarse_refine_tol(params->precision),
+                              mrcm::kCoarseRefineMax);
     std::vector<int> dof_side;
     for (const auto& d : S.maps.dofs) dof_side.push_back(d[1]);
     c->dof_off = c->upload(S.maps.dof_offset, s);

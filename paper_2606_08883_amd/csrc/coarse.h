@@ -76,9 +76,15 @@ void coarse_solve_refined_host(const CoarseFactor& F, const double* g_nd, double
 // number of corrections applied before a correction falls to tol times the
 // solution (in max norm), at most max_steps.  Sets and returns F.refine.
 int coarse_refine_steps(CoarseFactor& F, double tol, int max_steps);
-// The library's choice: corrections down to 1e-10 of the solution, at most
-// four steps.
+// The library's choice: corrections down to 1e-10 of the solution in the
+// FP64 mode, at most four steps.  In the modes with FP32 box factors the
+// interface solve needs only to stay below the factors' own FP32 rounding
+// (whose effect on T is of order 1e-7 to 1e-6): corrections down to 1e-7.
 constexpr double kCoarseRefineTol = 1e-10;
+constexpr double kCoarseRefineTolMixed = 1e-7;
 constexpr int kCoarseRefineMax = 4;
+inline double coarse_refine_tol(int precision) {
+  return precision == 0 ? kCoarseRefineTol : kCoarseRefineTolMixed;
+}
 
 }  // namespace mrcm

@@ -62,7 +62,8 @@ int mrcm_test_host_apply(const mrcm_grid* grid, const mrcm_params* params, const
     const mrcm::Maps& M = S.maps;
     mrcm::CoarseFactor CF =
         mrcm::coarse_factor(M, S.Crp, S.Cci, S.Cv, std::max(1, omp_get_max_threads()));
-    mrcm::coarse_refine_steps(CF, mrcm::kCoarseRefineTol, mrcm::kCoarseRefineMax);
+    mrcm::coarse_refine_steps(CF, mrcm::coarse_refine_tol(params->precision),
+                              mrcm::kCoarseRefineMax);
     if (min_pivot_ratio) *min_pivot_ratio = CF.min_pivot_ratio;
     const int nx = S.nx;
     const size_t n = (size_t)S.nx * S.ny;
@@ -169,7 +170,8 @@ int mrcm_test_coarse_solve(const mrcm_grid* grid, const mrcm_params* params, con
     if (nc == 0) return MRCM_OK;
     mrcm::CoarseFactor CF =
         mrcm::coarse_factor(S.maps, S.Crp, S.Cci, S.Cv, std::max(1, omp_get_max_threads()));
-    mrcm::coarse_refine_steps(CF, mrcm::kCoarseRefineTol, mrcm::kCoarseRefineMax);
+    mrcm::coarse_refine_steps(CF, mrcm::coarse_refine_tol(params->precision),
+                              mrcm::kCoarseRefineMax);
     std::vector<double> gnd(nc);
     for (int q = 0; q < nc; ++q) gnd[q] = CF.nd_scale[q] * g[CF.nd_row[q]];
     mrcm::coarse_solve_refined_host(CF, gnd.data(), x);

@@ -9,9 +9,9 @@
 * The 4096 x 4096 workload's kernels (32 x 32 subdomains grown by 4 cells,
   36-cell-wide smoothing patches, two sweeps, the channel / log-normal
   mixture with contrast 1e8, Dirichlet left/right data) on grids the oracle
-  sets up in minutes (512 x 512 and 1024 x 1024), modes 0 and 2, against the
+  sets up in minutes (512 x 512 and 1024 x 1024), modes 0, 1 and 2, against the
   oracle: T r, GMRES iterations, the solution at the same step (mode 0) or
-  for solutions driven to relative residual 1e-12 (mode 2).
+  for solutions driven to relative residual 1e-12 (modes 1 and 2).
 * 4096 x 4096 itself, precision mode 2: what holds at any size -- A x
   element by element against the oracle's sparse A, run-to-run bit identity
   of T r, a converged GMRES solve whose true residual, recomputed with the
@@ -148,7 +148,7 @@ def mixture_oracle(request):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("precision", [2, 0])
+@pytest.mark.parametrize("precision", [1, 2, 0])
 def test_large_kernels_against_oracle(dev, mixture_oracle, precision):
     w, K, mr, r, Tr, tg = mixture_oracle
     w = w.with_(precision=precision)
