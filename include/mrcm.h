@@ -269,7 +269,7 @@ int mrcm_timing_read(mrcm_ctx* ctx, double* ms, int64_t* counts);
  *                         residual): the set-up measures how far one solve
  *                         with the factor misses on a fixed right-hand side
  *                         and takes steps until a correction is below 1e-10
- *                         of the solution in precision mode 0, 1e-7 in modes
+ *                         of the solution in precision mode 0, 1e-6 in modes
  *                         1 and 2 (at most four). */
 enum {
   MRCM_Q_SETUP_SECONDS = 0,

@@ -1,6 +1,11 @@
 // Nested-dissection multifrontal factorisation of the interface system and a
 // host reference of its level-scheduled solve (the GPU solve is in
-// kernels.hip).  See coarse.h for the structure.
+// kernels.hip).  See coarse.h for the structure.  The dissection is four-way:
+// a region of the subdomain grid is split by a cross of subdomains into four
+// quadrants (by a line into two halves when it is thinner than three
+// subdomains), so the tree has about half the levels of a two-way dissection
+// and the solve half the dependent launches, at the price of larger fronts
+// near the root (bytes, which cost less than launch latency there).
 #include "coarse.h"
 
 #include <omp.h>
@@ -182,6 +187,19 @@ CoarseFactor coarse_factor(const Maps& M, const std::vector<int>& rp, const std:
     if ((x1 - x0) * (y1 - y0) <= kLeafArea) {
       for (int y = y0; y < y1; ++y)
         for (int x = x0; x < x1; ++x) nd.fsub.push_back(y * M.mx + x);
+    } else if (x1 - x0 >= 3 && y1 - y0 >= 3) {
+      // a cross of subdomains (one column and one row) splits the region
+      // into four quadrants, which couple only through it (the interface
+      // system has the five-point pattern of the subdomain grid)
+      const int xm = (x0 + x1) / 2, ym = (y0 + y1) / 2;
+      for (int k = 0; k < 4; ++k) {
+        const int c = build(k & 1 ? xm + 1 : x0, k & 1 ? x1 : xm, k & 2 ? ym + 1 : y0,
+                            k & 2 ? y1 : ym, depth + 1);
+        if (c >= 0) nd.children.push_back(c);
+      }
+      for (int y = y0; y < y1; ++y) nd.fsub.push_back(y * M.mx + xm);
+      for (int x = x0; x < x1; ++x)
+        if (x != xm) nd.fsub.push_back(ym * M.mx + x);
     } else if (x1 - x0 >= y1 - y0) {
       const int xm = (x0 + x1) / 2;
       int a = build(x0, xm, y0, y1, depth + 1), b = build(xm + 1, x1, y0, y1, depth + 1);

@@ -4,7 +4,7 @@
 // Every coarse row is owned by one subdomain (the flux rows of an edge by its
 // left/lower subdomain, the pressure rows by its right/upper one), so every
 // subdomain owns as many rows as it has dofs and C has the block five-point
-// pattern of the subdomain grid.  A nested-dissection tree of line separators
+// pattern of the subdomain grid.  A nested-dissection tree of cross (and line) separators
 // on that grid gives a multifrontal block elimination: every node eliminates
 // the dofs of its separator F against the dofs U of the subdomains bordering
 // its region, storing
@@ -78,10 +78,11 @@ void coarse_solve_refined_host(const CoarseFactor& F, const double* g_nd, double
 int coarse_refine_steps(CoarseFactor& F, double tol, int max_steps);
 // The library's choice: corrections down to 1e-10 of the solution in the
 // FP64 mode, at most four steps.  In the modes with FP32 box factors the
-// interface solve needs only to stay below the factors' own FP32 rounding
-// (whose effect on T is of order 1e-7 to 1e-6): corrections down to 1e-7.
+// interface solve needs only to stay below the effect of the factors' own
+// FP32 rounding on T (1e-7 to 1e-5 on the workloads, bounded by the
+// recurrence length times 2^-24): corrections down to 1e-6.
 constexpr double kCoarseRefineTol = 1e-10;
-constexpr double kCoarseRefineTolMixed = 1e-7;
+constexpr double kCoarseRefineTolMixed = 1e-6;
 constexpr int kCoarseRefineMax = 4;
 inline double coarse_refine_tol(int precision) {
   return precision == 0 ? kCoarseRefineTol : kCoarseRefineTolMixed;
