@@ -114,7 +114,7 @@ class MRCM:
 
     def __init__(self, K, nx: int, ny: int, bc, sx: int, sy: int, oversample: int,
                  alpha: float, beta_len: str = "H", sweeps: int = 0, overlap: int = 2,
-                 degree: int = 1, pin_edge: int = 0):
+                 degree: int = 1, pin_edge: int = 0, schwarz: str = "additive"):
         self.K = np.asarray(K, dtype=np.float64).ravel()
         if self.K.size != nx * ny or not np.all(np.isfinite(self.K)) or np.any(self.K <= 0):
             raise ValueError("K must be finite and positive on every cell")
@@ -123,6 +123,9 @@ class MRCM:
         self.L_cells = float(max(sx, sy)) if beta_len == "H" else 1.0
         self.sweeps, self.overlap, self.degree = int(sweeps), int(overlap), int(degree)
         self.pin_edge = int(pin_edge)
+        if schwarz not in ("additive", "multiplicative"):
+            raise ValueError("schwarz must be 'additive' or 'multiplicative'")
+        self.schwarz = schwarz
         self.part = build_partition(nx, ny, sx, sy, oversample, overlap, degree)
         self.tx, self.ty = face_transmissibilities(self.K, nx, ny, self.bc)
         self.A = assemble(self.K, nx, ny, self.bc)
@@ -380,7 +383,21 @@ class MRCM:
         return (p, x) if return_coarse else p
 
     def smooth(self, r: np.ndarray, p: np.ndarray) -> np.ndarray:
+        """Smoothing sweeps on A p = r (Section 2.1, the Schwarz-type
+        smoothing step).  Additive (the default): one residual per sweep, every
+        patch solved from it, each correction kept on the patch's own
+        subdomain (restricted additive Schwarz).  Multiplicative (calibration
+        only): patches in subdomain order, each solved from the residual left
+        by the ones before it, its correction added on the whole patch."""
         P = self.part
+        if self.schwarz == "multiplicative":
+            for _ in range(self.sweeps):
+                for i in range(P.m):
+                    pcells = self.box_cells(P.pboxes[i])
+                    rho = r - self.A @ p
+                    p = p.copy()
+                    p[pcells] += self.patch[i].solve(rho[pcells])
+            return p
         for _ in range(self.sweeps):
             rho = r - self.A @ p
             corr = np.zeros_like(p)

@@ -142,6 +142,41 @@ def test_smoothing_fixed_point_and_whole_grid_patch():
     assert np.linalg.norm(one - exact) <= 1e-12 * np.linalg.norm(exact)
 
 
+def test_multiplicative_smoothing_is_the_product_of_patch_projections():
+    """Multiplicative Schwarz (the calibration variant of the smoothing
+    step): one sweep maps the error e = x - p to prod_i (I - R_i^T
+    A_{S_i}^-1 R_i A) e, patches in subdomain order (the last factor
+    applied first), written out densely here."""
+    mr = _setup(k=1, l=2, schwarz="multiplicative")
+    n = mr.nx * mr.ny
+    r = wl.random_vector(n, 7)
+    exact = direct_solve(mr.A, r, mr.bc)
+    assert np.linalg.norm(mr.smooth(r, exact) - exact) <= 1e-12 * np.linalg.norm(exact)
+    p0 = wl.random_vector(n, 8)
+    A = mr.A.toarray()
+    E = np.eye(n)
+    for i in range(mr.part.m):
+        cells = mr.box_cells(mr.part.pboxes[i])
+        R = np.zeros((len(cells), n))
+        R[np.arange(len(cells)), cells] = 1.0
+        Pi = R.T @ np.linalg.solve(A[np.ix_(cells, cells)], R @ A)
+        E = (np.eye(n) - Pi) @ E
+    want = exact - E @ (exact - p0)
+    got = mr.smooth(r, p0)
+    assert np.linalg.norm(got - want) <= 1e-10 * np.linalg.norm(want)
+    with pytest.raises(ValueError):
+        _setup(schwarz="jacobi")
+
+
+def test_calibration_script_runs_a_paper_case():
+    """The calibration script's set-up of Table 2 gives the printed count
+    within one cycle for a cheap case (8 x 8, 2h,2S, multiplicative)."""
+    from oracle import calibrate_tables as ct
+    job = ("msm", 2, 8, "2h,2S")
+    got = ct.cycles(job)[1]
+    assert got is not None and abs(got - ct.paper_counts()[(2, "2h,2S")][8]) <= 1
+
+
 def test_principal_submatrix_patches():
     mr = _setup(k=1, l=2)
     for i in range(mr.part.m):
