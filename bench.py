@@ -295,7 +295,7 @@ def serving_leg(requests: int, max_active: int) -> dict:
     """A short Poisson stream of mixed-size requests (each with its own
     field and 8 right-hand sides) at 0.8 of the closed-loop capacity."""
     from paper_2606_08883_amd import serving as S
-    solver = S.gpu_solver(None, keep=False)
+    solver = S.GpuBackend(None, keep=False)
     S.Server(solver, max_active=1).run([S.make_payload(S.Request(0, 128, 2.0, 999, 1999, 2, 0.0))],
                                        realtime=False)
     burst = [S.make_payload(r) for r in S.make_requests(max(4, requests // 2), rate=None, seed=5)]
@@ -314,7 +314,9 @@ def serving_leg(requests: int, max_active: int) -> dict:
             "arrival_rate_per_s": rate, "solves_per_s": sm["solves_per_s"],
             "latency_ms": sm["latency_ms"], "all_converged": sm["all_converged"],
             "setup_s_mean": sm["setup_s_mean"], "solve_s_mean": sm["solve_s_mean"],
-            "peak_active": server.peak_active}
+            "peak_active": server.peak_active, "ticks": server.ticks,
+            "driver": "one batched GMRES advanced in ticks (gmres_batch_tick), set-ups on "
+                      "worker threads"}
 
 
 def cpu_baseline(w, gpu_iterations: float, window: int = 512) -> dict:
@@ -442,7 +444,7 @@ def serve(args) -> int:
     params = None if args.precision is None else dict(precision=args.precision)
     prec = S.SERVE_PARAMS["precision"] if args.precision is None else args.precision
     fp = (lambda r: S.footprint_of(r, params))
-    B = S.gpu_solver(params, keep=False)
+    B = S.GpuBackend(params, keep=False)
     warm = S.make_payload(S.Request(0, 128, 2.0, 999, 1999, 2, 0.0))
     S.Server(B, max_active=1).run([warm], realtime=False)
     burst = [S.make_payload(r) for r in S.make_requests(max(4, args.requests // 2), rate=None,
@@ -471,11 +473,13 @@ def serve(args) -> int:
                                   f"log-normal sigma U[1,3] corr. 16, 8 injector/producer "
                                   f"pairs each, Poisson arrivals at 0.8 x closed-loop capacity "
                                   f"({rate:.2f}/s), {args.max_active} slots",
-                      "parallelism": "single GPU, requests in flight on separate streams"},
+                      "parallelism": "single GPU, the right-hand sides of all requests in "
+                                     "flight advanced together in ticks of one batched GMRES"},
            "cell_dof_per_s": sm["cell_dof_per_s"], "latency_ms": sm["latency_ms"],
            "requests_per_s": sm["requests_per_s"], "capacity_requests_per_s": cap,
            "setup_s_mean": sm["setup_s_mean"], "solve_s_mean": sm["solve_s_mean"],
            "iterations_per_solve": sm["iterations_mean"], "peak_active": server.peak_active,
+           "ticks": server.ticks,
            "peak_footprint_gb": server.peak_bytes / 1e9}
     print(json.dumps(out), flush=True)
     return 0

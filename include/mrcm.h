@@ -151,12 +151,20 @@ int mrcm_apply(mrcm_ctx* ctx, const double* r, double* z, int32_t nrhs, void* st
 int mrcm_apply_noalloc(mrcm_ctx* ctx, const double* r, double* z, int32_t nrhs, void* stream);
 
 /* z_i = T_i r_i for n set-up contexts at once (Section 3, as mrcm_apply,
- * for several permeability fields or grids): every context's applications
- * run on its own stream after the work already queued on `stream`, so the
- * contexts' kernels overlap on the device, and `stream` waits for all of
- * them.  ctx[i], r[i], z[i], nrhs[i]: host arrays of n entries; r[i], z[i]:
- * device [nrhs[i]][n_i] of context i.  A context may appear once per call.
- * Results are those of mrcm_apply, bit for bit. */
+ * for several permeability fields or grids).  Every column of every context
+ * is one work item, and each phase of T (local solves, every level of the
+ * interface solve, reconstruction, each smoothing sweep, the projection) is
+ * one launch over the (column, subdomain) items of all of them, for contexts
+ * of one family (precision mode and box column widths; families run one
+ * after the other).  ctx[i], r[i], z[i], nrhs[i]: host arrays of n entries;
+ * r[i], z[i]: device [nrhs[i]][n_i] of context i; a context may appear once
+ * per call (MRCM_EINVAL otherwise).  Runs on `stream`.  Column k of a
+ * context uses that context's k-th column work space (allocated on first
+ * use and kept until mrcm_destroy); the launch tables live with the first
+ * context of the call, and a call waits on the host until the launches of
+ * the previous call led by the same context have read them.  Calls that
+ * share a context must not overlap.  Results are those of mrcm_apply, bit
+ * for bit.  Per-phase timing is not recorded. */
 int mrcm_apply_many(mrcm_ctx* const* ctx, int32_t n, const double* const* r, double* const* z,
                     const int32_t* nrhs, void* stream);
 
@@ -195,6 +203,42 @@ int op_apply(mrcm_ctx* ctx, const double* x, double* y, int32_t nrhs, void* stre
 int gmres_solve(mrcm_ctx* ctx, const double* b, double* p, int32_t nrhs, double rtol,
                 int32_t restart, int32_t maxit, mrcm_stats* st, void* stream);
 
+/* Batched GMRES over several contexts (Algorithm 1 for every right-hand
+ * side of every member; continuous batching): right-hand sides of any
+ * number of set-up contexts, added and removed at any time, advance together
+ * in ticks.  A tick consumes the scalars fetched by the previous tick (norms
+ * and Hessenberg columns), advances every right-hand side on the host as
+ * gmres_solve does, runs the Arnoldi steps of all stepping right-hand sides
+ * as one launch per phase of T and of the Arnoldi tail over all of them (as
+ * mrcm_apply_many), and copies the scalars the host needs next in one
+ * transfer.  Each right-hand side runs gmres_solve's kernels in the same
+ * order, so its iterates equal gmres_solve's bit for bit (p_0 = 0, modified
+ * Gram-Schmidt, the estimated residual tested after every step, the true
+ * FP64 residual at every cycle end).  The batch has its own stream; calls
+ * on one batch must come from one thread at a time. */
+typedef struct mrcm_batch mrcm_batch;
+/* A batch with Krylov dimension `restart` (1..200). */
+int gmres_batch_create(int32_t restart, mrcm_batch** out);
+/* Add the nrhs right-hand sides b of a context (device [nrhs][n]); their
+ * solutions are written to p (device [nrhs][n]) as they progress.  b, the
+ * context and p are used after the work `stream` holds when the call is
+ * made.  The batch allocates each right-hand side's Krylov space and work
+ * space from the context (released by mrcm_destroy); the context must
+ * outlive the tag.  *tag receives the handle of the group. */
+int gmres_batch_add(mrcm_batch* batch, mrcm_ctx* ctx, const double* b, double* p,
+                    int32_t nrhs, double rtol, int32_t maxit, void* stream, int32_t* tag);
+/* One tick; *active receives the right-hand sides not yet finished. */
+int gmres_batch_tick(mrcm_batch* batch, int32_t* active);
+/* *done = 1 when every right-hand side of the tag has finished (converged
+ * or maxit reached); p is then final.  st (host, may be NULL) receives the
+ * sums of iterations and cycles over the tag, converged, and the largest
+ * true relative residual; no histories. */
+int gmres_batch_poll(mrcm_batch* batch, int32_t tag, int32_t* done, mrcm_stats* st);
+/* Drop a tag's right-hand sides (finished or not) after the batch's device
+ * work has ended; p keeps what was written. */
+int gmres_batch_remove(mrcm_batch* batch, int32_t tag);
+/* Drain and free the batch (its tags' contexts are not touched). */
+void gmres_batch_destroy(mrcm_batch* batch);
 /* Lanes (streams) gmres_solve may use at once on this context (1..64; 4
  * after mrcm_setup).  Lanes beyond the first are created, with their
  * streams and device work space, by the first solve that uses them and kept

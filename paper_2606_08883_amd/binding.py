@@ -25,6 +25,8 @@ EXPORTED = ["mrcm_map_sizes", "mrcm_maps", "mrcm_setup", "mrcm_apply", "mrcm_app
             "op_apply", "gmres_solve", "mrcm_rhs", "mrcm_footprint", "mrcm_timing_enable",
             "mrcm_timing_read", "mrcm_query", "mrcm_set_allocator", "mrcm_set_lanes", "mrcm_set_batch",
             "mrcm_set_host_threads",
+            "gmres_batch_create", "gmres_batch_add", "gmres_batch_tick", "gmres_batch_poll",
+            "gmres_batch_remove", "gmres_batch_destroy",
             "mrcm_destroy",
             "mrcm_last_error"]
 QUERIES = {"setup_seconds": 0, "device_bytes": 1, "coarse_pivot": 2, "coarse_levels": 3,
@@ -99,6 +101,12 @@ def lib() -> ctypes.CDLL:
             "mrcm_timing_read": ([P, pd, pi64], i32),
             "mrcm_query": ([P, i32, pd], i32),
             "mrcm_destroy": ([P], None),
+            "gmres_batch_create": ([i32, ctypes.POINTER(P)], i32),
+            "gmres_batch_add": ([P, P, P, P, i32, dbl, i32, P, pi32], i32),
+            "gmres_batch_tick": ([P, pi32], i32),
+            "gmres_batch_poll": ([P, i32, pi32, ctypes.POINTER(Stats)], i32),
+            "gmres_batch_remove": ([P, i32], i32),
+            "gmres_batch_destroy": ([P], None),
             "mrcm_last_error": ([], ctypes.c_char_p),
             "mrcm_test_coarse_sizes": ([pG, pP, pd, pi64, pi64], i32),
             "mrcm_test_coarse_matrix": ([pG, pP, pd, pi32, pi32, pd], i32),
@@ -276,6 +284,52 @@ def apply_many(contexts, rs, zs, stream=None):
     zp = (P * n)(*[_dptr(z, r.numel()) for r, z in zip(rs, zs)])
     k = (ctypes.c_int32 * n)(*[c._nrhs(r) for c, r in zip(contexts, rs)])
     _check(lib().mrcm_apply_many(ctx, n, rp, zp, k, _stream(stream)))
+class Batch:
+    """Batched GMRES over several contexts in ticks (gmres_batch_*)."""
+
+    def __init__(self, restart: int = 10):
+        self._ptr = ctypes.c_void_p()
+        _check(lib().gmres_batch_create(restart, ctypes.byref(self._ptr)))
+
+    def add(self, ctx: "Context", b, p, rtol: float = 1e-8, maxit: int = 300,
+            stream=None) -> int:
+        """Add the right-hand sides b of a context (solutions into p); returns the tag."""
+        tag = ctypes.c_int32()
+        _check(lib().gmres_batch_add(self._ptr, ctx._ptr, _dptr(b), _dptr(p, b.numel()),
+                                     ctx._nrhs(b), rtol, maxit, _stream(stream),
+                                     ctypes.byref(tag)))
+        return tag.value
+
+    def tick(self) -> int:
+        """One tick; returns the right-hand sides still running."""
+        active = ctypes.c_int32()
+        _check(lib().gmres_batch_tick(self._ptr, ctypes.byref(active)))
+        return active.value
+
+    def poll(self, tag: int):
+        """None while the tag runs, else its SolveStats."""
+        done = ctypes.c_int32()
+        st = Stats(0, 0, 0, 0, 0, 0, 0.0, None, None)
+        _check(lib().gmres_batch_poll(self._ptr, tag, ctypes.byref(done), ctypes.byref(st)))
+        if not done.value:
+            return None
+        return SolveStats(st.iterations, st.cycles, bool(st.converged), st.final_relres, [], [])
+
+    def remove(self, tag: int) -> None:
+        _check(lib().gmres_batch_remove(self._ptr, tag))
+
+    def close(self):
+        if self._ptr:
+            lib().gmres_batch_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def _stream(stream):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream

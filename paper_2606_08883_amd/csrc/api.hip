@@ -106,6 +106,53 @@ void staged_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
 mrcm_alloc_fn g_alloc = nullptr;
 mrcm_free_fn g_free = nullptr;
 
+// Column descriptors and workgroup ranges of launches over several contexts:
+// device tables filled from pinned host copies, one upload per call.  The
+// tables are rewritten only after the launches that read them have ended.
+struct ManyTables {
+  mrcm::ManyCol *d_cols = nullptr, *h_cols = nullptr;
+  int *d_ints = nullptr, *h_ints = nullptr;
+  size_t cap_cols = 0, cap_ints = 0;
+  hipEvent_t used = nullptr;  // recorded after the last launch that read them
+  void reserve(size_t ncols, size_t nints) {
+    if (used) hip_check(hipEventSynchronize(used), "hipEventSynchronize");
+    if (ncols > cap_cols) {
+      release_cols();
+      cap_cols = std::max(ncols, 2 * cap_cols);
+      hip_check(hipMalloc(&d_cols, cap_cols * sizeof(mrcm::ManyCol)), "hipMalloc");
+      hip_check(hipHostMalloc((void**)&h_cols, cap_cols * sizeof(mrcm::ManyCol),
+                              hipHostMallocDefault),
+                "hipHostMalloc");
+    }
+    if (nints > cap_ints) {
+      release_ints();
+      cap_ints = std::max(nints, 2 * cap_ints);
+      hip_check(hipMalloc(&d_ints, cap_ints * sizeof(int)), "hipMalloc");
+      hip_check(hipHostMalloc((void**)&h_ints, cap_ints * sizeof(int), hipHostMallocDefault),
+                "hipHostMalloc");
+    }
+    if (!used) hip_check(hipEventCreateWithFlags(&used, hipEventDisableTiming), "hipEventCreate");
+  }
+  void release_cols() {
+    if (d_cols) (void)hipFree(d_cols);
+    if (h_cols) (void)hipHostFree(h_cols);
+    d_cols = h_cols = nullptr;
+  }
+  void release_ints() {
+    if (d_ints) (void)hipFree(d_ints);
+    if (h_ints) (void)hipHostFree(h_ints);
+    d_ints = h_ints = nullptr;
+  }
+  ~ManyTables() {
+    if (used) {
+      (void)hipEventSynchronize(used);
+      (void)hipEventDestroy(used);
+    }
+    release_cols();
+    release_ints();
+  }
+};
+
 }  // namespace
 
 struct mrcm_ctx {
@@ -206,6 +253,16 @@ struct mrcm_ctx {
   };
   std::vector<Lane> lanes;
   int max_lanes = 4, batch_width = 4;
+  // One-column work space of the columns of launches over several contexts
+  // (mrcm_apply_many: column k of this context uses columns[k]).
+  struct Column {
+    void *pT = nullptr, *rhoT = nullptr;
+    double *mU = nullptr, *mP = nullptr, *xc = nullptr, *ybuf = nullptr, *g_nd = nullptr;
+    double *rnd = nullptr, *dx = nullptr, *contrib = nullptr, *partials = nullptr;
+  };
+  std::vector<Column> columns;
+  // Column tables of the mrcm_apply_many calls this context leads.
+  std::unique_ptr<ManyTables> many;
   // cells of all oversampled boxes or of all smoothing patches, the larger
   // (the box scratch of one column of a multi-column application)
   long long scratch_cells = 0;
@@ -1064,6 +1121,275 @@ double host_sum(const double* v, int nb) {
 
 void check_launch() { hip_check(hipGetLastError(), "kernel launch"); }
 
+// ---- launches over several contexts ----------------------------------------
+
+// Work space of one column of a launch over several contexts: the
+// one-column vectors of apply_one (contrib zeroed once, as in make_lane).
+mrcm_ctx::Column make_column(mrcm_ctx* c, hipStream_t s) {
+  mrcm_ctx::Column w;
+  const size_t nc = std::max(c->nc, 1), np = std::max(c->np, 1);
+  w.pT = c->alloc<char>(c->tsize * c->n);
+  w.rhoT = c->alloc<char>(c->tsize * c->n);
+  w.mU = c->alloc<double>(nc);
+  w.mP = c->alloc<double>(nc);
+  w.xc = c->alloc<double>(nc);
+  w.g_nd = c->alloc<double>(np);
+  w.ybuf = c->alloc<double>(np);
+  w.rnd = c->alloc<double>(np);
+  w.dx = c->alloc<double>(nc);
+  w.contrib = c->alloc<double>(np * c->maxp);
+  mrcm::launch_zero(w.contrib, (long long)(np * c->maxp), s);
+  w.partials = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
+  return w;
+}
+
+void ensure_columns(mrcm_ctx* c, int count, hipStream_t s) {
+  while ((int)c->columns.size() < count) c->columns.push_back(make_column(c, s));
+}
+
+// A column of a launch over several contexts: the context, its work space,
+// T's input r and output z; for batched GMRES also its Krylov space and step.
+struct ManyRef {
+  mrcm_ctx* c = nullptr;
+  const mrcm_ctx::Column* w = nullptr;
+  const double* r = nullptr;
+  double* z = nullptr;
+  double *V = nullptr, *Z = nullptr, *parts = nullptr, *hcol = nullptr;
+  int j = 0;
+};
+
+// Contexts whose columns can share launches: precision and the column
+// widths of the box kernels' templates.
+long long family_of(const mrcm_ctx* c) {
+  return (long long)c->precision * 10000 + mrcm::box_cols(c->max_bx_local) * 100 +
+         (c->sweeps > 0 ? mrcm::box_cols(c->max_bx_patch) : 0);
+}
+
+mrcm::ManyCol many_col_of(const ManyRef& f) {
+  const mrcm_ctx* c = f.c;
+  const mrcm_ctx::Column* w = f.w;
+  mrcm::ManyCol a{};
+  a.lbox = c->lbox;
+  a.pbox = c->pbox;
+  a.ldinv = c->ldinv;
+  a.lcoup = c->lcoup;
+  a.pdinv = c->pdinv;
+  a.pcoup = c->pcoup;
+  a.mbf = c->mbf;
+  a.mbf_off = c->mbf_off;
+  a.dof_off = c->dof_off;
+  a.dof_side = c->dof_side;
+  a.dof_q = c->dof_q;
+  a.dof_face0 = c->dof_face0;
+  a.face_w = c->face_w;
+  a.gsrc = c->gsrc;
+  a.gscale = c->gscale;
+  a.cfwd = c->cfwd;
+  a.cbwd = c->cbwd;
+  a.cidx = c->cidx;
+  a.cdest = c->cdest;
+  a.chunks = c->chunks;
+  a.crp = c->crp;
+  a.cci = c->cci;
+  a.cv = c->cv;
+  a.txT = c->txT;
+  a.tyT = c->tyT;
+  a.tx = c->tx;
+  a.ty = c->ty;
+  a.nx = c->nx;
+  a.ny = c->ny;
+  a.m = c->m;
+  a.nc = c->nc;
+  a.np = c->np;
+  a.maxp = c->maxp;
+  a.noflow = c->noflow;
+  a.nb = mrcm::vec_blocks(c->n);
+  a.n = c->n;
+  a.r = f.r;
+  a.z = f.z;
+  a.p = w->pT;
+  a.rho = w->rhoT;
+  a.mU = w->mU;
+  a.mP = w->mP;
+  a.xc = w->xc;
+  a.g_nd = w->g_nd;
+  a.ybuf = w->ybuf;
+  a.rnd = w->rnd;
+  a.dx = w->dx;
+  a.contrib = w->contrib;
+  a.partials = w->partials;
+  a.V = f.V;
+  a.Z = f.Z;
+  a.parts = f.parts;
+  a.hcol = f.hcol;
+  a.j = f.j;
+  return a;
+}
+
+inline int grid_blocks(long long n) {
+  long long b = (n + mrcm::kVecThreads - 1) / mrcm::kVecThreads;
+  return (int)std::max(1LL, std::min(4096LL, b));
+}
+
+// z = T r for every column of one family, each phase one launch over all
+// columns (the steps and per-column arithmetic of apply_one); with tails
+// also the Arnoldi tail of every column at its step j (w = A z_j,
+// Gram-Schmidt, normalisation; the work of arnoldi_tail).
+template <typename T, typename S>
+void apply_family(const std::vector<ManyRef>& refs, ManyTables& tb, hipStream_t s,
+                  bool tails) {
+  const int nc = (int)refs.size();
+  if (nc == 0) return;
+  int mcl = 0, mbl = 0, mcp = 0, mbp = 0, mnf = 0, mnu = 0, nfwd = 0, nbwd = 0, nref = 0,
+      nsw = 0, maxj = 0;
+  for (const ManyRef& f : refs) {
+    const mrcm_ctx* c = f.c;
+    mcl = std::max(mcl, c->max_cells_local);
+    mbl = std::max(mbl, c->max_bx_local);
+    if (c->sweeps > 0) {
+      mcp = std::max(mcp, c->max_cells_patch);
+      mbp = std::max(mbp, c->max_bx_patch);
+    }
+    mnf = std::max(mnf, c->max_nf);
+    mnu = std::max(mnu, c->max_nu);
+    if (c->nc > 0) {
+      nfwd = std::max(nfwd, (int)c->fwd_levels.size());
+      nbwd = std::max(nbwd, (int)c->bwd_levels.size());
+      nref = std::max(nref, c->refine);
+    }
+    nsw = std::max(nsw, c->sweeps);
+    maxj = std::max(maxj, f.j);
+  }
+  const int gl = mrcm::box_groups(mbl, mcl, sizeof(T), sizeof(S));
+  const int gp = nsw > 0 ? mrcm::box_groups(mbp, mcp, sizeof(T), sizeof(S)) : 1;
+  if (gl <= 0 || gp <= 0)
+    throw mrcm::Error(MRCM_EINVAL, "boxes too large for a launch over several contexts");
+  // workgroup ranges: prefix sums of per-column counts (and first chunks)
+  std::vector<int> ints;
+  struct Seg {
+    size_t pre = 0, first = 0;
+    int blocks = 0;
+  };
+  auto seg = [&](auto count, auto first) {
+    Seg g;
+    g.pre = ints.size();
+    int acc = 0;
+    ints.push_back(0);
+    for (int i = 0; i < nc; ++i) {
+      acc += count(refs[i].c, i);
+      ints.push_back(acc);
+    }
+    g.blocks = acc;
+    g.first = ints.size();
+    for (int i = 0; i < nc; ++i) ints.push_back(first(refs[i].c));
+    return g;
+  };
+  auto none = [](const mrcm_ctx*) { return 0; };
+  const Seg local = seg([&](const mrcm_ctx* c, int) { return (c->m + gl - 1) / gl; }, none);
+  const Seg crhs = seg([](const mrcm_ctx* c, int) { return c->nc > 0 ? (c->np + 255) / 256 : 0; },
+                       none);
+  auto level = [&](const std::vector<std::pair<int, int>> mrcm_ctx::*lv, int l, int it) {
+    return seg(
+        [&](const mrcm_ctx* c, int) {
+          return c->nc > 0 && it < (it < 0 ? 1 : c->refine) && l < (int)(c->*lv).size()
+                     ? (c->*lv)[l].second
+                     : 0;
+        },
+        [&](const mrcm_ctx* c) {
+          return c->nc > 0 && l < (int)(c->*lv).size() ? (c->*lv)[l].first : 0;
+        });
+  };
+  // it = -1: the first solve; it >= 0: refinement step it
+  std::vector<std::vector<Seg>> fwd(nref + 1), bwd(nref + 1);
+  std::vector<Seg> resid(nref), add(nref);
+  for (int it = -1; it < nref; ++it) {
+    if (it >= 0)
+      resid[it] = seg([&](const mrcm_ctx* c, int) {
+        return c->nc > 0 && it < c->refine ? (c->np + 255) / 256 : 0;
+      }, none);
+    for (int l = 0; l < nfwd; ++l) fwd[it + 1].push_back(level(&mrcm_ctx::fwd_levels, l, it));
+    for (int l = 0; l < nbwd; ++l) bwd[it + 1].push_back(level(&mrcm_ctx::bwd_levels, l, it));
+    if (it >= 0)
+      add[it] = seg([&](const mrcm_ctx* c, int) {
+        return c->nc > 0 && it < c->refine ? (c->nc + 255) / 256 : 0;
+      }, none);
+  }
+  const Seg recon = seg([](const mrcm_ctx* c, int) { return c->nc > 0 ? c->m : 0; }, none);
+  std::vector<Seg> resd(nsw), patch(nsw);
+  for (int sw = 0; sw < nsw; ++sw) {
+    resd[sw] = seg([&](const mrcm_ctx* c, int) { return sw < c->sweeps ? grid_blocks(c->n) : 0; },
+                   none);
+    patch[sw] = seg([&](const mrcm_ctx* c, int) {
+      return sw < c->sweeps ? (c->m + gp - 1) / gp : 0;
+    }, none);
+  }
+  const Seg sum = seg([](const mrcm_ctx* c, int) { return c->noflow ? mrcm::vec_blocks(c->n) : 0; },
+                      none);
+  const Seg fin = seg([](const mrcm_ctx* c, int) { return mrcm::vec_blocks(c->n); }, none);
+  Seg astart, nscale;
+  std::vector<Seg> mgs;
+  if (tails) {
+    astart = seg([](const mrcm_ctx* c, int) { return mrcm::vec_blocks(c->n); }, none);
+    for (int i = 0; i <= maxj; ++i)
+      mgs.push_back(seg([&](const mrcm_ctx* c, int q) {
+        return refs[q].j >= i ? mrcm::vec_blocks(c->n) : 0;
+      }, none));
+    nscale = seg([](const mrcm_ctx* c, int) { return mrcm::vec_blocks(c->n); }, none);
+  }
+  // upload the tables
+  tb.reserve(nc, ints.size());
+  for (int i = 0; i < nc; ++i) tb.h_cols[i] = many_col_of(refs[i]);
+  std::memcpy(tb.h_ints, ints.data(), ints.size() * sizeof(int));
+  hip_check(hipMemcpyAsync(tb.d_cols, tb.h_cols, nc * sizeof(mrcm::ManyCol),
+                           hipMemcpyHostToDevice, s),
+            "hipMemcpyAsync");
+  hip_check(hipMemcpyAsync(tb.d_ints, tb.h_ints, ints.size() * sizeof(int),
+                           hipMemcpyHostToDevice, s),
+            "hipMemcpyAsync");
+  const mrcm::ManyCol* C = tb.d_cols;
+  const int* I = tb.d_ints;
+  // the phases of apply_one
+  mrcm::launch_local_many<T, S>(C, I + local.pre, nc, local.blocks, mcl, mbl, s);
+  mrcm::launch_coarse_rhs_many(C, I + crhs.pre, nc, crhs.blocks, s);
+  for (int it = -1; it < nref; ++it) {
+    if (it >= 0) mrcm::launch_coarse_resid_many(C, I + resid[it].pre, nc, resid[it].blocks, s);
+    for (const Seg& g : fwd[it + 1])
+      mrcm::launch_coarse_fwd_many(C, I + g.pre, I + g.first, nc, g.blocks, it >= 0, mnf, s);
+    for (const Seg& g : bwd[it + 1])
+      mrcm::launch_coarse_bwd_many(C, I + g.pre, I + g.first, nc, g.blocks, it >= 0, mnu, s);
+    if (it >= 0) mrcm::launch_coarse_add_many(C, I + add[it].pre, nc, add[it].blocks, s);
+  }
+  mrcm::launch_reconstruct_many<T, S>(C, I + recon.pre, nc, recon.blocks, s);
+  for (int sw = 0; sw < nsw; ++sw) {
+    mrcm::launch_residual_many<T>(C, I + resd[sw].pre, nc, resd[sw].blocks, s);
+    mrcm::launch_patch_many<T, S>(C, I + patch[sw].pre, nc, patch[sw].blocks, mcp, mbp, s);
+  }
+  mrcm::launch_sum_many<T>(C, I + sum.pre, nc, sum.blocks, s);
+  mrcm::launch_finalize_many<T>(C, I + fin.pre, nc, fin.blocks, s);
+  if (tails) {
+    mrcm::launch_arnoldi_start_many(C, I + astart.pre, nc, astart.blocks, s);
+    for (int i = 0; i <= maxj; ++i)
+      mrcm::launch_mgs_step_many(C, I + mgs[i].pre, nc, mgs[i].blocks, i, s);
+    mrcm::launch_norm_scale_many(C, I + nscale.pre, nc, nscale.blocks, s);
+  }
+  hip_check(hipEventRecord(tb.used, s), "hipEventRecord");
+}
+
+// Columns of every family, one family after the other.
+void apply_families(std::vector<ManyRef>& refs, ManyTables& tb, hipStream_t s, bool tails) {
+  std::map<long long, std::vector<ManyRef>> fam;
+  for (const ManyRef& f : refs) fam[family_of(f.c)].push_back(f);
+  for (auto& kv : fam) {
+    const int prec = kv.second[0].c->precision;
+    if (prec == 1)
+      apply_family<float, float>(kv.second, tb, s, tails);
+    else if (prec == 2)
+      apply_family<double, float>(kv.second, tb, s, tails);
+    else
+      apply_family<double, double>(kv.second, tb, s, tails);
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -1344,28 +1670,31 @@ int mrcm_apply_many(mrcm_ctx* const* ctx, int32_t n, const double* const* r, dou
     for (int i = 0; i < n; ++i) {
       if (!ctx[i] || nrhs[i] < 0) throw mrcm::Error(MRCM_EINVAL, "invalid argument");
       if (nrhs[i] > 0 && (!r[i] || !z[i])) throw mrcm::Error(MRCM_EINVAL, "null vector");
+      for (int q = 0; q < i; ++q)
+        if (ctx[q] == ctx[i]) throw mrcm::Error(MRCM_EINVAL, "a context appears twice");
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    // every context's applications run on its own stream after the work the
-    // caller's stream holds, and the caller's stream waits for all of them
+    // every column of every context: one launch per phase over all of them
+    // (per family of kernel templates)
+    std::vector<ManyRef> refs;
+    mrcm_ctx* lead = nullptr;
     for (int i = 0; i < n; ++i) {
       mrcm_ctx* c = ctx[i];
       if (nrhs[i] == 0) continue;
-      hip_check(hipEventRecord(c->ws_in, s), "hipEventRecord");
-      hip_check(hipStreamWaitEvent(c->ws, c->ws_in, 0), "hipStreamWaitEvent");
-      std::vector<const double*> rk(nrhs[i]);
-      std::vector<double*> zk(nrhs[i]);
+      if (!lead) lead = c;
+      ensure_columns(c, nrhs[i], s);
       for (int k = 0; k < nrhs[i]; ++k) {
-        rk[k] = r[i] + (size_t)k * c->n;
-        zk[k] = z[i] + (size_t)k * c->n;
+        ManyRef f;
+        f.c = c;
+        f.w = &c->columns[k];
+        f.r = r[i] + (size_t)k * c->n;
+        f.z = z[i] + (size_t)k * c->n;
+        refs.push_back(f);
       }
-      apply_columns(c, c->lanes[0], rk.data(), zk.data(), nrhs[i], c->ws);
-      hip_check(hipEventRecord(c->ws_out, c->ws), "hipEventRecord");
     }
-    for (int i = 0; i < n; ++i)
-      if (nrhs[i] > 0) hip_check(hipStreamWaitEvent(s, ctx[i]->ws_out, 0), "hipStreamWaitEvent");
-    for (int i = 0; i < n; ++i)
-      if (ctx[i]->timing && ctx[i]->ev_used > 4096) ctx[i]->fold_timing();
+    if (!lead) return MRCM_OK;
+    if (!lead->many) lead->many.reset(new ManyTables());
+    apply_families(refs, *lead->many, s, false);
     check_launch();
     return MRCM_OK;
   } catch (const mrcm::Error& e) {
@@ -1660,6 +1989,379 @@ int gmres_solve(mrcm_ctx* c, const double* b, double* p, int32_t nrhs, double rt
   }
 }
 
+}  // extern "C"
+
+// ---- batched GMRES over several contexts -----------------------------------
+// Right-hand sides of any number of contexts advance together in ticks.  A
+// tick consumes the scalars the previous tick fetched (norms, Hessenberg
+// columns), advances every right-hand side on the host exactly as
+// gmres_solve does (Givens rotations, cycle ends, restarts), launches the
+// Arnoldi steps of all of them at once (one launch per phase of T and of the
+// Arnoldi tail over every stepping column, per family of kernel templates),
+// gathers the scalars the host needs next into one staging vector and copies
+// it to the host with one transfer.  Each right-hand side runs the kernels
+// and arithmetic of gmres_solve in the same order, so its iterates are the
+// same bit for bit.
+struct mrcm_batch {
+  int restart = 10;
+  hipStream_t st = nullptr;
+  hipEvent_t ev_in = nullptr;
+  ManyTables tables;
+  mrcm::GatherItem *d_items = nullptr, *h_items = nullptr;
+  size_t cap_items = 0;
+  double *d_stage = nullptr, *h_stage = nullptr;
+  size_t cap_stage = 0;
+  enum Phase { kNew, kNormB, kBeta, kStep, kDone };
+  struct Run {
+    mrcm_ctx* c = nullptr;
+    int tag = 0;
+    const double* b = nullptr;
+    double* p = nullptr;
+    mrcm_ctx::Column w;
+    double *V = nullptr, *Z = nullptr, *hcol = nullptr, *parts = nullptr, *yd = nullptr;
+    double* h_y = nullptr;  // pinned
+    Phase phase = kNew;
+    bool step = false;
+    double rtol = 0.0, bnorm = 0.0, tol = 0.0, relres = 1.0;
+    int maxit = 0, it = 0, j = 0, cycles = 0, nb = 1;
+    bool conv = false;
+    std::vector<double> H, cs, sn, gv, y;
+    const double* fsrc = nullptr;  // scalars to fetch this tick
+    int fcnt = 0;
+    long long foff = 0;  // their place in the staging vector
+  };
+  struct Tag {
+    std::vector<Run*> runs;
+    int remaining = 0;
+  };
+  std::vector<std::unique_ptr<Run>> runs;
+  std::map<int, Tag> tags;
+  int next_tag = 1;
+  ~mrcm_batch() {
+    if (st) (void)hipStreamSynchronize(st);
+    for (auto& R : runs)
+      if (R->h_y) (void)hipHostFree(R->h_y);
+    if (d_items) (void)hipFree(d_items);
+    if (h_items) (void)hipHostFree(h_items);
+    if (d_stage) (void)hipFree(d_stage);
+    if (h_stage) (void)hipHostFree(h_stage);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (st) (void)hipStreamDestroy(st);
+  }
+};
+
+namespace {
+
+using Run = mrcm_batch::Run;
+
+void batch_fetch(Run& R, const double* src, int cnt) {
+  R.fsrc = src;
+  R.fcnt = cnt;
+}
+
+void batch_finish(mrcm_batch* B, Run& R) {
+  R.phase = mrcm_batch::kDone;
+  R.step = false;
+  R.fcnt = 0;
+  B->tags[R.tag].remaining -= 1;
+}
+
+void batch_start(mrcm_batch* B, Run& R) {
+  const long long n = R.c->n;
+  R.H.assign((size_t)(B->restart + 1) * B->restart, 0.0);
+  R.cs.assign(B->restart, 0.0);
+  R.sn.assign(B->restart, 0.0);
+  R.gv.assign(B->restart + 1, 0.0);
+  R.y.assign(B->restart, 0.0);
+  mrcm::launch_zero(R.p, n, B->st);
+  mrcm::launch_sumsq(R.b, n, R.parts, R.nb, B->st);
+  batch_fetch(R, R.parts, R.nb);
+  R.phase = mrcm_batch::kNormB;
+}
+
+// The host part of a tick for one right-hand side (gmres_solve's advance).
+void batch_advance(mrcm_batch* B, Run& R, const double* hh) {
+  mrcm_ctx* c = R.c;
+  const long long n = c->n;
+  const int restart = B->restart;
+  hipStream_t s = B->st;
+  R.fcnt = 0;
+  if (R.phase == mrcm_batch::kNormB) {
+    R.bnorm = std::sqrt(host_sum(hh, R.nb));
+    if (R.bnorm == 0.0) {  // p = 0 is exact
+      R.conv = true;
+      R.relres = 0.0;
+      batch_finish(B, R);
+      return;
+    }
+    R.tol = R.rtol * R.bnorm;
+    mrcm::launch_resid_norm(c->tx, c->ty, c->nx, c->ny, R.b, nullptr, R.V, R.parts, R.nb, s);
+    batch_fetch(R, R.parts, R.nb);
+    R.phase = mrcm_batch::kBeta;
+    return;
+  }
+  if (R.phase == mrcm_batch::kBeta) {
+    const double beta = std::sqrt(host_sum(hh, R.nb));
+    R.relres = beta / R.bnorm;
+    if (beta <= R.tol) {
+      R.conv = true;
+      batch_finish(B, R);
+      return;
+    }
+    if (R.it >= R.maxit) {
+      batch_finish(B, R);
+      return;
+    }
+    ++R.cycles;
+    mrcm::launch_scale(R.V, n, 1.0 / beta, s);
+    std::fill(R.H.begin(), R.H.end(), 0.0);
+    std::fill(R.gv.begin(), R.gv.end(), 0.0);
+    R.gv[0] = beta;
+    R.j = 0;
+    R.step = true;
+    R.phase = mrcm_batch::kStep;
+    return;
+  }
+  // kStep: Givens rotation of the new Hessenberg column (Algorithm 1)
+  const int j = R.j;
+  std::vector<double>& H = R.H;
+  ++R.it;
+  for (int i = 0; i <= j + 1; ++i) H[(size_t)i * restart + j] = hh[i];
+  const double hnext = hh[j + 1];
+  for (int i = 0; i < j; ++i) {
+    const double a = H[(size_t)i * restart + j], bb = H[(size_t)(i + 1) * restart + j];
+    H[(size_t)i * restart + j] = R.cs[i] * a + R.sn[i] * bb;
+    H[(size_t)(i + 1) * restart + j] = -R.sn[i] * a + R.cs[i] * bb;
+  }
+  const double a = H[(size_t)j * restart + j], bb = H[(size_t)(j + 1) * restart + j];
+  const double rr = std::hypot(a, bb);
+  R.cs[j] = a / rr;
+  R.sn[j] = bb / rr;
+  H[(size_t)j * restart + j] = rr;
+  H[(size_t)(j + 1) * restart + j] = 0.0;
+  R.gv[j + 1] = -R.sn[j] * R.gv[j];
+  R.gv[j] = R.cs[j] * R.gv[j];
+  const int jj = j + 1;
+  if (!(hnext == 0.0 || std::fabs(R.gv[j + 1]) <= R.tol || R.it >= R.maxit || jj == restart)) {
+    R.j = jj;
+    R.step = true;
+    return;
+  }
+  // end of the cycle: y = H^-1 g, p += Z y, true residual
+  for (int i = jj - 1; i >= 0; --i) {
+    double sum = R.gv[i];
+    for (int q = i + 1; q < jj; ++q) sum -= H[(size_t)i * restart + q] * R.y[q];
+    R.y[i] = sum / H[(size_t)i * restart + i];
+  }
+  std::memcpy(R.h_y, R.y.data(), sizeof(double) * jj);
+  hip_check(hipMemcpyAsync(R.yd, R.h_y, sizeof(double) * jj, hipMemcpyHostToDevice, s),
+            "hipMemcpyAsync");
+  mrcm::launch_update(R.p, R.Z, R.yd, jj, n, s);
+  mrcm::launch_resid_norm(c->tx, c->ty, c->nx, c->ny, R.b, R.p, R.V, R.parts, R.nb, s);
+  batch_fetch(R, R.parts, R.nb);
+  R.phase = mrcm_batch::kBeta;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gmres_batch_create(int32_t restart, mrcm_batch** out) {
+  try {
+    if (!out || restart < 1 || restart > 200) throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+    std::unique_ptr<mrcm_batch> B(new mrcm_batch());
+    B->restart = restart;
+    hip_check(hipStreamCreateWithFlags(&B->st, hipStreamNonBlocking), "hipStreamCreate");
+    hip_check(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming), "hipEventCreate");
+    *out = B.release();
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    set_error(e.what());
+    return e.code;
+  }
+}
+
+int gmres_batch_add(mrcm_batch* B, mrcm_ctx* c, const double* b, double* p, int32_t nrhs,
+                    double rtol, int32_t maxit, void* stream, int32_t* tag) {
+  try {
+    if (!B || !c || nrhs < 1 || !b || !p || !tag || maxit < 0 || !(rtol >= 0.0))
+      throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+    // the runs read b and the context's data after the work `stream` holds
+    hip_check(hipEventRecord(B->ev_in, static_cast<hipStream_t>(stream)), "hipEventRecord");
+    hip_check(hipStreamWaitEvent(B->st, B->ev_in, 0), "hipStreamWaitEvent");
+    const int id = B->next_tag++;
+    mrcm_batch::Tag& T = B->tags[id];
+    const long long n = c->n;
+    for (int k = 0; k < nrhs; ++k) {
+      std::unique_ptr<Run> R(new Run());
+      R->c = c;
+      R->tag = id;
+      R->b = b + (size_t)k * n;
+      R->p = p + (size_t)k * n;
+      R->w = make_column(c, B->st);
+      R->V = c->alloc<double>((size_t)(B->restart + 1) * n);
+      R->Z = c->alloc<double>((size_t)B->restart * n);
+      R->hcol = c->alloc<double>(B->restart + 2);
+      R->parts = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
+      R->yd = c->alloc<double>(B->restart + 1);
+      hip_check(hipHostMalloc((void**)&R->h_y, sizeof(double) * (B->restart + 1),
+                              hipHostMallocDefault),
+                "hipHostMalloc");
+      R->rtol = rtol;
+      R->maxit = maxit;
+      R->nb = mrcm::vec_blocks(n);
+      T.runs.push_back(R.get());
+      B->runs.push_back(std::move(R));
+    }
+    T.remaining = nrhs;
+    *tag = id;
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    set_error(e.what());
+    return e.code;
+  }
+}
+
+int gmres_batch_tick(mrcm_batch* B, int32_t* active) {
+  try {
+    if (!B) throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+    hip_check(hipStreamSynchronize(B->st), "hipStreamSynchronize");
+    // consume the fetched scalars; start the new right-hand sides
+    for (auto& up : B->runs) {
+      Run& R = *up;
+      if (R.phase == mrcm_batch::kDone) continue;
+      if (R.phase == mrcm_batch::kNew) {
+        batch_start(B, R);
+        continue;
+      }
+      batch_advance(B, R, B->h_stage + R.foff);
+    }
+    // the Arnoldi steps of every stepping right-hand side
+    std::vector<ManyRef> refs;
+    for (auto& up : B->runs) {
+      Run& R = *up;
+      if (!R.step) continue;
+      ManyRef f;
+      f.c = R.c;
+      f.w = &R.w;
+      f.r = R.V + (size_t)R.j * R.c->n;
+      f.z = R.Z + (size_t)R.j * R.c->n;
+      f.V = R.V;
+      f.Z = R.Z;
+      f.parts = R.parts;
+      f.hcol = R.hcol;
+      f.j = R.j;
+      refs.push_back(f);
+      batch_fetch(R, R.hcol, R.j + 2);
+      R.step = false;
+    }
+    if (!refs.empty()) apply_families(refs, B->tables, B->st, true);
+    // gather the scalars of every right-hand side and copy them to the host
+    std::vector<mrcm::GatherItem> items;
+    long long total = 0;
+    int live = 0;
+    for (auto& up : B->runs) {
+      Run& R = *up;
+      if (R.phase == mrcm_batch::kDone) continue;
+      ++live;
+      if (R.fcnt <= 0) continue;
+      R.foff = total;
+      items.push_back(mrcm::GatherItem{R.fsrc, total, R.fcnt, 0});
+      total += R.fcnt;
+    }
+    if (!items.empty()) {
+      if (items.size() > B->cap_items) {
+        if (B->d_items) (void)hipFree(B->d_items);
+        if (B->h_items) (void)hipHostFree(B->h_items);
+        B->cap_items = std::max(items.size(), 2 * B->cap_items);
+        hip_check(hipMalloc(&B->d_items, B->cap_items * sizeof(mrcm::GatherItem)), "hipMalloc");
+        hip_check(hipHostMalloc((void**)&B->h_items, B->cap_items * sizeof(mrcm::GatherItem),
+                                hipHostMallocDefault),
+                  "hipHostMalloc");
+      }
+      if ((size_t)total > B->cap_stage) {
+        if (B->d_stage) (void)hipFree(B->d_stage);
+        if (B->h_stage) (void)hipHostFree(B->h_stage);
+        B->cap_stage = std::max((size_t)total, 2 * B->cap_stage);
+        hip_check(hipMalloc(&B->d_stage, B->cap_stage * sizeof(double)), "hipMalloc");
+        hip_check(hipHostMalloc((void**)&B->h_stage, B->cap_stage * sizeof(double),
+                                hipHostMallocDefault),
+                  "hipHostMalloc");
+      }
+      std::memcpy(B->h_items, items.data(), items.size() * sizeof(mrcm::GatherItem));
+      hip_check(hipMemcpyAsync(B->d_items, B->h_items, items.size() * sizeof(mrcm::GatherItem),
+                               hipMemcpyHostToDevice, B->st),
+                "hipMemcpyAsync");
+      mrcm::launch_gather(B->d_items, (int)items.size(), B->d_stage, B->st);
+      hip_check(hipMemcpyAsync(B->h_stage, B->d_stage, total * sizeof(double),
+                               hipMemcpyDeviceToHost, B->st),
+                "hipMemcpyAsync");
+    }
+    check_launch();
+    if (active) *active = live;
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    set_error(e.what());
+    return e.code;
+  }
+}
+
+int gmres_batch_poll(mrcm_batch* B, int32_t tag, int32_t* done, mrcm_stats* st) {
+  try {
+    if (!B || !done) throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+    auto it = B->tags.find(tag);
+    if (it == B->tags.end()) throw mrcm::Error(MRCM_EINVAL, "unknown tag");
+    const mrcm_batch::Tag& T = it->second;
+    *done = T.remaining == 0 ? 1 : 0;
+    if (st) {
+      int iters = 0, cycles = 0, conv = 1;
+      double worst = 0.0;
+      for (const Run* R : T.runs) {
+        iters += R->it;
+        cycles += R->cycles;
+        conv &= R->conv ? 1 : 0;
+        worst = std::max(worst, R->relres);
+      }
+      st->iterations = iters;
+      st->cycles = cycles;
+      st->converged = conv;
+      st->hist_len = st->true_len = 0;
+      st->final_relres = worst;
+    }
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    set_error(e.what());
+    return e.code;
+  }
+}
+
+int gmres_batch_remove(mrcm_batch* B, int32_t tag) {
+  try {
+    if (!B) throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+    auto it = B->tags.find(tag);
+    if (it == B->tags.end()) throw mrcm::Error(MRCM_EINVAL, "unknown tag");
+    // no launch of the engine may still use the runs' buffers
+    hip_check(hipStreamSynchronize(B->st), "hipStreamSynchronize");
+    auto& runs = B->runs;
+    for (auto r = runs.begin(); r != runs.end();) {
+      if ((*r)->tag == tag) {
+        if ((*r)->h_y) (void)hipHostFree((*r)->h_y);
+        r = runs.erase(r);
+      } else {
+        ++r;
+      }
+    }
+    B->tags.erase(it);
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    set_error(e.what());
+    return e.code;
+  }
+}
+
+void gmres_batch_destroy(mrcm_batch* B) { delete B; }
+
+
 int mrcm_set_host_threads(int32_t threads) {
   if (threads < 0) {
     set_error("invalid argument");
@@ -1721,8 +2423,9 @@ size_t mrcm_footprint(const mrcm_grid* grid, const mrcm_params* params, int32_t 
       for (const auto& b : M.pboxes) pcells += (size_t)b.bx() * b.by();
     for (const auto& b : M.oboxes) ocells += (size_t)b.bx() * b.by();
     pcells = std::max(pcells, ocells);
-    bytes += (size_t)r * (21 * n * 8 + 2 * n * w + pcells * w + 3 * (size_t)(nc + 1) * 8 +
-                          (2 + 4) * (size_t)(nc + 1) * 8);
+    const size_t t = params->precision == 1 ? 4 : 8;  // work-vector words
+    bytes += (size_t)r * (21 * n * 8 + 2 * n * t + pcells * w + 3 * (size_t)(nc + 1) * 8 +
+                          (2 + 4 + 4) * (size_t)(nc + 1) * 8);
     return bytes;
   } catch (...) {
     return 0;

@@ -147,6 +147,86 @@ template <typename T>
 void launch_finalize_k(int k, const T* const* p, long long n, int noflow, double* const* z,
                        double* partials, hipStream_t s);
 
+// ---- launches over several contexts ----------------------------------------
+// One column of a launch over several contexts: one right-hand side of one
+// context, with the context's tables and factors and the column's own work
+// vectors (the factor and work-vector pointers are typed by the launch's S
+// and T).  A launch gives column c the workgroups [pre[c], pre[c + 1]) of its
+// grid; workgroup pre[c] + b runs as block b of the column's own launch, so
+// every column gets the results of its one-context launch bit for bit.
+struct ManyCol {
+  const BoxDesc *lbox, *pbox;
+  const void *ldinv, *lcoup, *pdinv, *pcoup, *mbf;
+  const long long* mbf_off;
+  const int *dof_off, *dof_side, *dof_q, *dof_face0;
+  const double* face_w;
+  const int4* gsrc;
+  const double* gscale;
+  const double *cfwd, *cbwd;
+  const int *cidx, *cdest;
+  const CChunk* chunks;
+  const int *crp, *cci;
+  const double* cv;
+  const void *txT, *tyT;
+  const double *tx, *ty;
+  int nx, ny, m, nc, np, maxp, noflow, nb;  // nb: blocks of the column's vector reductions
+  long long n;
+  const double* r;  // T is applied to r and written to z
+  double* z;
+  void *p, *rho;
+  double *mU, *mP, *xc, *g_nd, *ybuf, *rnd, *dx, *contrib, *partials;
+  // GMRES state of the column (batched solves): the Krylov basis V (restart
+  // + 1 vectors), Z, the two halves of the reduction partials, the
+  // Hessenberg column and the step j.
+  double *V, *Z, *parts, *hcol;
+  int j, pad;
+};
+// A copy of count doubles from src into a staging vector at dst.
+struct GatherItem {
+  const double* src;
+  long long dst;
+  int count, pad;
+};
+template <typename T, typename S>
+void launch_local_many(const ManyCol* cols, const int* pre, int ncol, int blocks, int max_cells,
+                       int max_bx, hipStream_t s);
+void launch_coarse_rhs_many(const ManyCol* cols, const int* pre, int ncol, int blocks,
+                            hipStream_t s);
+// Level of the interface solve: column c's chunks first[c] .. of its own
+// chunk table; refine selects the refinement vectors (rnd, dx) instead of
+// (g_nd, xc).
+void launch_coarse_fwd_many(const ManyCol* cols, const int* pre, const int* first, int ncol,
+                            int blocks, int refine, int max_nf, hipStream_t s);
+void launch_coarse_bwd_many(const ManyCol* cols, const int* pre, const int* first, int ncol,
+                            int blocks, int refine, int max_nu, hipStream_t s);
+void launch_coarse_resid_many(const ManyCol* cols, const int* pre, int ncol, int blocks,
+                              hipStream_t s);
+void launch_coarse_add_many(const ManyCol* cols, const int* pre, int ncol, int blocks,
+                            hipStream_t s);
+template <typename T, typename S>
+void launch_reconstruct_many(const ManyCol* cols, const int* pre, int ncol, int blocks,
+                             hipStream_t s);
+template <typename T>
+void launch_residual_many(const ManyCol* cols, const int* pre, int ncol, int blocks,
+                          hipStream_t s);
+template <typename T, typename S>
+void launch_patch_many(const ManyCol* cols, const int* pre, int ncol, int blocks, int max_cells,
+                       int max_bx, hipStream_t s);
+template <typename T>
+void launch_sum_many(const ManyCol* cols, const int* pre, int ncol, int blocks, hipStream_t s);
+template <typename T>
+void launch_finalize_many(const ManyCol* cols, const int* pre, int ncol, int blocks,
+                          hipStream_t s);
+// The Arnoldi tail of every column at its step j: w = A Z_j with w . v_0,
+// modified Gram-Schmidt step i (columns with j >= i), normalisation.
+void launch_arnoldi_start_many(const ManyCol* cols, const int* pre, int ncol, int blocks,
+                               hipStream_t s);
+void launch_mgs_step_many(const ManyCol* cols, const int* pre, int ncol, int blocks, int i,
+                          hipStream_t s);
+void launch_norm_scale_many(const ManyCol* cols, const int* pre, int ncol, int blocks,
+                            hipStream_t s);
+void launch_gather(const GatherItem* items, int count, double* stage, hipStream_t s);
+
 // ---- set-up on the device (FP64; one wave per box or subdomain) ------------
 // Factor the boxes of `jobs` (LDS: two maxn x maxn blocks); status[0] = 1
 // after a non-positive pivot.

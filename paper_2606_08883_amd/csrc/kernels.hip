@@ -103,6 +103,16 @@ __global__ void k_rhs(const double* __restrict__ tx, const double* __restrict__ 
   }
 }
 
+// Virtual block of a launch: its index and the block count of its grid.  A
+// launch over one context uses the hardware grid; a launch over several
+// contexts gives every column its own range of workgroups, each of which
+// runs as block `id` of a grid of `n`, so that every column's arithmetic and
+// reduction order are those of its own launch.
+struct Blk {
+  int id, n;
+};
+__device__ __forceinline__ Blk hw_blk() { return Blk{(int)blockIdx.x, (int)gridDim.x}; }
+
 // ---- batched box solves ---------------------------------------------------
 // One lane group of GS lanes (GS = 16, 32 or 64 >= the box width bx, 64 / GS
 // boxes per wave) solves one cell box with the block LDL^T factor of its cell
@@ -533,18 +543,17 @@ __device__ __forceinline__ void trace_moments(const BoxDesc& d, int side, int q,
 // the trace moments of the coarse right-hand side (one lane per coarse dof
 // of the subdomain, FP64 sums).  Groups past the last subdomain (live =
 // false) run along on the last one and write nothing.
-template <typename T, typename S, int NB, int GS = (NB <= 16 ? 16 : NB <= 32 ? 32 : 64)>
-__global__ void __launch_bounds__(kBoxThreads)
-    k_local(const BoxDesc* __restrict__ boxes, int m, int group_bytes, int cp_words,
-            const S* __restrict__ dinv, const S* __restrict__ coup,
-            const double* __restrict__ r, T* __restrict__ p, int nx,
-            const int* __restrict__ dof_off, const int* __restrict__ dof_side,
-            const int* __restrict__ dof_q, const int* __restrict__ dof_face0,
-            const double* __restrict__ face_w, double* __restrict__ mU,
-            double* __restrict__ mP) {
+template <typename T, typename S, int NB, int GS>
+__device__ __forceinline__ void local_body(
+    const Blk blk, const BoxDesc* __restrict__ boxes, int m, int group_bytes, int cp_words,
+    const S* __restrict__ dinv, const S* __restrict__ coup, const double* __restrict__ r,
+    T* __restrict__ p, int nx, const int* __restrict__ dof_off,
+    const int* __restrict__ dof_side, const int* __restrict__ dof_q,
+    const int* __restrict__ dof_face0, const double* __restrict__ face_w,
+    double* __restrict__ mU, double* __restrict__ mP) {
   extern __shared__ __align__(16) char smem_raw[];
   const int grp = threadIdx.x / GS, lane = threadIdx.x % GS;
-  const int i0 = blockIdx.x * (blockDim.x / GS) + grp;
+  const int i0 = blk.id * (blockDim.x / GS) + grp;
   const bool live = i0 < m;
   const int i = live ? i0 : m - 1;
   BoxSlot<T, S, NB, GS> L(smem_raw + (long long)grp * group_bytes, cp_words);
@@ -572,41 +581,73 @@ __global__ void __launch_bounds__(kBoxThreads)
     mP[k] = sp;
   }
 }
+template <typename T, typename S, int NB, int GS = (NB <= 16 ? 16 : NB <= 32 ? 32 : 64)>
+__global__ void __launch_bounds__(kBoxThreads)
+    k_local(const BoxDesc* __restrict__ boxes, int m, int group_bytes, int cp_words,
+            const S* __restrict__ dinv, const S* __restrict__ coup,
+            const double* __restrict__ r, T* __restrict__ p, int nx,
+            const int* __restrict__ dof_off, const int* __restrict__ dof_side,
+            const int* __restrict__ dof_q, const int* __restrict__ dof_face0,
+            const double* __restrict__ face_w, double* __restrict__ mU,
+            double* __restrict__ mP) {
+  local_body<T, S, NB, GS>(hw_blk(), boxes, m, group_bytes, cp_words, dinv, coup, r, p, nx,
+                           dof_off, dof_side, dof_q, dof_face0, face_w, mU, mP);
+}
 
 // Interface right-hand side in tree order: for tree position t, gsrc[t] =
 // {L, R, kind}: kind 0 a flux row, g = -(mU[L] + mU[R]); 1 a pressure row,
 // g = -(mP[L] - mP[R]); 2 the replaced row of an all-no-flow grid, g = 0;
 // times the row's equilibration scale gscale[t].
-__global__ void k_coarse_rhs(const int4* __restrict__ gsrc, const double* __restrict__ gscale,
-                             const double* __restrict__ mU, const double* __restrict__ mP,
-                             double* __restrict__ g_nd, int np) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void coarse_rhs_body(const Blk blk, const int4* __restrict__ gsrc,
+                                                const double* __restrict__ gscale,
+                                                const double* __restrict__ mU,
+                                                const double* __restrict__ mP,
+                                                double* __restrict__ g_nd, int np) {
+  const int t = blk.id * blockDim.x + threadIdx.x;
   if (t >= np) return;
   const int4 src = gsrc[t];
   const double v = src.z == 0 ? -(mU[src.x] + mU[src.y]) : -(mP[src.x] - mP[src.y]);
   g_nd[t] = src.z == 2 ? 0.0 : gscale[t] * v;
+}
+__global__ void k_coarse_rhs(const int4* __restrict__ gsrc, const double* __restrict__ gscale,
+                             const double* __restrict__ mU, const double* __restrict__ mP,
+                             double* __restrict__ g_nd, int np) {
+  coarse_rhs_body(hw_blk(), gsrc, gscale, mU, mP, g_nd, np);
 }
 
 // Refinement residual of the interface solve in tree order: r_nd[t] = g_nd[t]
 // - sum over the scaled row of position t of v * x (CSR rp / ci / v), one
 // thread per row, terms in row order; blockIdx.y selects a column of a
 // multi-column solve (vectors of column k at k * np / k * nc).
+__device__ __forceinline__ void coarse_resid_body(const Blk blk, int col,
+                                                  const int* __restrict__ rp,
+                                                  const int* __restrict__ ci,
+                                                  const double* __restrict__ v,
+                                                  const double* __restrict__ g_nd,
+                                                  const double* __restrict__ x,
+                                                  double* __restrict__ r_nd, int np, int nc) {
+  const int t = blk.id * blockDim.x + threadIdx.x;
+  if (t >= np) return;
+  const double* xk = x + (long long)col * nc;
+  double s = g_nd[(long long)col * np + t];
+  for (int q = rp[t]; q < rp[t + 1]; ++q) s = fmat(-v[q], xk[ci[q]], s);
+  r_nd[(long long)col * np + t] = s;
+}
 __global__ void k_coarse_resid(const int* __restrict__ rp, const int* __restrict__ ci,
                                const double* __restrict__ v, const double* __restrict__ g_nd,
                                const double* __restrict__ x, double* __restrict__ r_nd, int np,
                                int nc) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= np) return;
-  const double* xk = x + (long long)blockIdx.y * nc;
-  double s = g_nd[(long long)blockIdx.y * np + t];
-  for (int q = rp[t]; q < rp[t + 1]; ++q) s = fmat(-v[q], xk[ci[q]], s);
-  r_nd[(long long)blockIdx.y * np + t] = s;
+  coarse_resid_body(hw_blk(), blockIdx.y, rp, ci, v, g_nd, x, r_nd, np, nc);
 }
 
 // x += dx over n values (columns of a multi-column solve are consecutive).
-__global__ void k_coarse_add(double* __restrict__ x, const double* __restrict__ dx, long long n) {
-  const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+__device__ __forceinline__ void coarse_add_body(const Blk blk, double* __restrict__ x,
+                                                const double* __restrict__ dx, long long n) {
+  const long long q = blk.id * (long long)blockDim.x + threadIdx.x;
   if (q < n) x[q] += dx[q];
+}
+__global__ void k_coarse_add(double* __restrict__ x, const double* __restrict__ dx, long long n) {
+  coarse_add_body(hw_blk(), x, dx, n);
 }
 
 // ---- interface solve (level-scheduled nested dissection) -------------------
@@ -750,13 +791,11 @@ __device__ __forceinline__ bool whole_chunk(const CChunk& ch, int ncol) {
 // zero where unused).  Then rows of [W; E] v: y_F into ybuf (straight into
 // x through idx for a node without border rows, whose x_F = y_F), each c_n
 // row into its destination slot cdest[coff + row - nf].
-__global__ void __launch_bounds__(kVecThreads)
-    k_coarse_fwd(const CChunk* __restrict__ chunks, const double* __restrict__ fwd,
-                 const double* __restrict__ g_nd, double* __restrict__ contrib, int maxp, int np,
-                 const int* __restrict__ cdest, double* __restrict__ ybuf,
-                 const int* __restrict__ idx, double* __restrict__ x) {
+__device__ __forceinline__ void coarse_fwd_body(
+    const CChunk ch, const double* __restrict__ fwd, const double* __restrict__ g_nd,
+    double* __restrict__ contrib, int maxp, int np, const int* __restrict__ cdest,
+    double* __restrict__ ybuf, const int* __restrict__ idx, double* __restrict__ x) {
   extern __shared__ double v[];
-  const CChunk ch = chunks[blockIdx.x];
   const int nf = ch.nf, lane = threadIdx.x & 63;
   const double* M = fwd + ch.mat;
   const int yoff = ch.yoff, coff = ch.coff;
@@ -807,15 +846,21 @@ __global__ void __launch_bounds__(kVecThreads)
   gather();
   gemv_chunk(M, nf, ch.row0, ch.row1, v, m, pre, emit);
 }
+__global__ void __launch_bounds__(kVecThreads)
+    k_coarse_fwd(const CChunk* __restrict__ chunks, const double* __restrict__ fwd,
+                 const double* __restrict__ g_nd, double* __restrict__ contrib, int maxp, int np,
+                 const int* __restrict__ cdest, double* __restrict__ ybuf,
+                 const int* __restrict__ idx, double* __restrict__ x) {
+  coarse_fwd_body(chunks[blockIdx.x], fwd, g_nd, contrib, maxp, np, cdest, ybuf, idx, x);
+}
 
 // Backward level: x_F = y_F - G x_U for the chunk's rows (x_U gathered
 // through idx[ucol ..], x_F scattered through idx[fcol ..]; nu > 0).
-__global__ void __launch_bounds__(kVecThreads)
-    k_coarse_bwd(const CChunk* __restrict__ chunks, const double* __restrict__ bwd,
-                 const int* __restrict__ idx, const double* __restrict__ ybuf,
-                 double* __restrict__ x) {
+__device__ __forceinline__ void coarse_bwd_body(const CChunk ch, const double* __restrict__ bwd,
+                                                const int* __restrict__ idx,
+                                                const double* __restrict__ ybuf,
+                                                double* __restrict__ x) {
   extern __shared__ double xu[];
-  const CChunk ch = chunks[blockIdx.x];
   const int nu = ch.nu, lane = threadIdx.x & 63;
   const double* M = bwd + ch.mat;
   const int yoff = ch.yoff, fcol = ch.fcol;
@@ -852,16 +897,24 @@ __global__ void __launch_bounds__(kVecThreads)
   gather();
   gemv_chunk(M, nu, ch.row0, ch.row1, xu, m, pre, [&](int, double val) { x[dst] = y - val; });
 }
+__global__ void __launch_bounds__(kVecThreads)
+    k_coarse_bwd(const CChunk* __restrict__ chunks, const double* __restrict__ bwd,
+                 const int* __restrict__ idx, const double* __restrict__ ybuf,
+                 double* __restrict__ x) {
+  coarse_bwd_body(chunks[blockIdx.x], bwd, idx, ybuf, x);
+}
 
 // p[Omega_i] += P_i x_i (multiscale reconstruction; Omega_i is the owned part
 // of box d), one workgroup per subdomain.
 template <typename T, typename S>
-__global__ void __launch_bounds__(kBoxThreads)
-    k_reconstruct(const BoxDesc* __restrict__ boxes, const S* __restrict__ mbf,
-                  const long long* __restrict__ mbf_off, const int* __restrict__ dof_off,
-                  const double* __restrict__ xc, T* __restrict__ p, int nx) {
+__device__ __forceinline__ void reconstruct_body(const Blk blk, const BoxDesc* __restrict__ boxes,
+                                                 const S* __restrict__ mbf,
+                                                 const long long* __restrict__ mbf_off,
+                                                 const int* __restrict__ dof_off,
+                                                 const double* __restrict__ xc,
+                                                 T* __restrict__ p, int nx) {
   __shared__ T xs[64];
-  const int i = blockIdx.x;
+  const int i = blk.id;
   const BoxDesc d = boxes[i];
   const int k0 = dof_off[i], nk = dof_off[i + 1] - k0, ncell = d.obx * d.oby;
   for (int k = threadIdx.x; k < nk; k += blockDim.x) xs[k] = (T)xc[k0 + k];
@@ -875,32 +928,48 @@ __global__ void __launch_bounds__(kBoxThreads)
     p[c] = s;
   }
 }
+template <typename T, typename S>
+__global__ void __launch_bounds__(kBoxThreads)
+    k_reconstruct(const BoxDesc* __restrict__ boxes, const S* __restrict__ mbf,
+                  const long long* __restrict__ mbf_off, const int* __restrict__ dof_off,
+                  const double* __restrict__ xc, T* __restrict__ p, int nx) {
+  reconstruct_body<T, S>(hw_blk(), boxes, mbf, mbf_off, dof_off, xc, p, nx);
+}
 
 // Smoothing residual rho = r - A p.
+template <typename T>
+__device__ __forceinline__ void residual_body(const Blk blk, const T* __restrict__ tx,
+                                              const T* __restrict__ ty, int nx, int ny,
+                                              const double* __restrict__ r,
+                                              const T* __restrict__ p, T* __restrict__ rho) {
+  const long long n = (long long)nx * ny;
+  for (long long c = blk.id * (long long)blockDim.x + threadIdx.x; c < n;
+       c += (long long)blk.n * blockDim.x) {
+    const int iy = (int)(c / nx), ix = (int)(c - (long long)iy * nx);
+    rho[c] = (T)r[c] - stencil(tx, ty, nx, ny, ix, iy, p);
+  }
+}
 template <typename T>
 __global__ void __launch_bounds__(kVecThreads)
     k_residual(const T* __restrict__ tx, const T* __restrict__ ty, int nx, int ny,
                const double* __restrict__ r, const T* __restrict__ p, T* __restrict__ rho) {
-  const long long n = (long long)nx * ny;
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
-       c += (long long)gridDim.x * blockDim.x) {
-    const int iy = (int)(c / nx), ix = (int)(c - (long long)iy * nx);
-    rho[c] = (T)r[c] - stencil(tx, ty, nx, ny, ix, iy, p);
-  }
+  residual_body<T>(hw_blk(), tx, ty, nx, ny, r, p, rho);
 }
 
 // Restricted additive Schwarz: solve A[S_i] e = rho[S_i] on patch i (one
 // lane group per patch) and add e on the owned subdomain Omega_i (each cell
 // is written by one patch only).  Groups past the last patch run along on
 // the last one and write nothing.
-template <typename T, typename S, int NB, int GS = (NB <= 16 ? 16 : NB <= 32 ? 32 : 64)>
-__global__ void __launch_bounds__(kBoxThreads)
-    k_patch(const BoxDesc* __restrict__ boxes, int m, int group_bytes, int cp_words,
-            const S* __restrict__ dinv, const S* __restrict__ coup, const T* __restrict__ rho,
-            T* __restrict__ p, int nx) {
+template <typename T, typename S, int NB, int GS>
+__device__ __forceinline__ void patch_body(const Blk blk, const BoxDesc* __restrict__ boxes,
+                                           int m, int group_bytes, int cp_words,
+                                           const S* __restrict__ dinv,
+                                           const S* __restrict__ coup,
+                                           const T* __restrict__ rho, T* __restrict__ p,
+                                           int nx) {
   extern __shared__ __align__(16) char smem_raw[];
   const int grp = threadIdx.x / GS, lane = threadIdx.x % GS;
-  const int i0 = blockIdx.x * (blockDim.x / GS) + grp;
+  const int i0 = blk.id * (blockDim.x / GS) + grp;
   const bool live = i0 < m;
   const int i = live ? i0 : m - 1;
   BoxSlot<T, S, NB, GS> L(smem_raw + (long long)grp * group_bytes, cp_words);
@@ -933,14 +1002,21 @@ __global__ void __launch_bounds__(kBoxThreads)
         p[o2 + (long long)(j0 + u) * nx + lane] = v[u] + L.us[(d.oy + j0 + u) * bx + lane];
   }
 }
+template <typename T, typename S, int NB, int GS = (NB <= 16 ? 16 : NB <= 32 ? 32 : 64)>
+__global__ void __launch_bounds__(kBoxThreads)
+    k_patch(const BoxDesc* __restrict__ boxes, int m, int group_bytes, int cp_words,
+            const S* __restrict__ dinv, const S* __restrict__ coup, const T* __restrict__ rho,
+            T* __restrict__ p, int nx) {
+  patch_body<T, S, NB, GS>(hw_blk(), boxes, m, group_bytes, cp_words, dinv, coup, rho, p, nx);
+}
 
 template <typename T>
-__global__ void __launch_bounds__(kVecThreads)
-    k_sum(const T* __restrict__ p, long long n, double* __restrict__ partials) {
+__device__ __forceinline__ void sum_body(const Blk blk, const T* __restrict__ p, long long n,
+                                         double* __restrict__ partials) {
   __shared__ double red[kVecThreads / 64];
-  const long long st = (long long)gridDim.x * blockDim.x;
+  const long long st = (long long)blk.n * blockDim.x;
   double s = 0.0;
-  for (long long c0 = blockIdx.x * (long long)blockDim.x + threadIdx.x; c0 < n;
+  for (long long c0 = blk.id * (long long)blockDim.x + threadIdx.x; c0 < n;
        c0 += kRound * st) {
     T a[kRound];
 #pragma unroll
@@ -953,17 +1029,22 @@ __global__ void __launch_bounds__(kVecThreads)
       if (c0 + u * st < n) s += (double)a[u];
   }
   s = block_sum(s, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (threadIdx.x == 0) partials[blk.id] = s;
+}
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+    k_sum(const T* __restrict__ p, long long n, double* __restrict__ partials) {
+  sum_body<T>(hw_blk(), p, n, partials);
 }
 
 // z = p - mean(p) (no-flow) or z = p, in FP64.  First round loaded before
 // the reduction, as in k_mgs_step.
 template <typename T>
-__global__ void __launch_bounds__(kVecThreads)
-    k_finalize(const T* __restrict__ p, long long n, const double* __restrict__ partials, int nb,
-               double* __restrict__ z) {
+__device__ __forceinline__ void finalize_body(const Blk blk, const T* __restrict__ p, long long n,
+                                              const double* __restrict__ partials, int nb,
+                                              double* __restrict__ z) {
   __shared__ double red[kVecThreads / 64];
-  const long long st = (long long)gridDim.x * blockDim.x;
+  const long long st = (long long)blk.n * blockDim.x;
   T a[kRound];
   auto load = [&](long long c0) {
 #pragma unroll
@@ -972,7 +1053,7 @@ __global__ void __launch_bounds__(kVecThreads)
       a[u] = p[c < n ? c : n - 1];
     }
   };
-  const long long start = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long start = blk.id * (long long)blockDim.x + threadIdx.x;
   load(start);
   const double mean = partials ? reduce_partials(partials, nb, red) / (double)n : 0.0;
   for (long long c0 = start; c0 < n; c0 += kRound * st) {
@@ -983,6 +1064,12 @@ __global__ void __launch_bounds__(kVecThreads)
       if (c < n) z[c] = (double)a[u] - mean;
     }
   }
+}
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+    k_finalize(const T* __restrict__ p, long long n, const double* __restrict__ partials, int nb,
+               double* __restrict__ z) {
+  finalize_body<T>(hw_blk(), p, n, partials, nb, z);
 }
 
 __global__ void k_convert(const double* __restrict__ s, float* __restrict__ d, long long n) {
@@ -1037,14 +1124,16 @@ __global__ void k_scale(double* __restrict__ v, long long n, double alpha) {
 }
 
 // w = A z, partial sums of w . v0.
-__global__ void __launch_bounds__(kVecThreads)
-    k_arnoldi_start(const double* __restrict__ tx, const double* __restrict__ ty, int nx, int ny,
-                    const double* __restrict__ z, double* __restrict__ w,
-                    const double* __restrict__ v0, double* __restrict__ partials) {
+__device__ __forceinline__ void arnoldi_start_body(const Blk blk, const double* __restrict__ tx,
+                                                   const double* __restrict__ ty, int nx, int ny,
+                                                   const double* __restrict__ z,
+                                                   double* __restrict__ w,
+                                                   const double* __restrict__ v0,
+                                                   double* __restrict__ partials) {
   __shared__ double red[kVecThreads / 64];
-  const long long n = (long long)nx * ny, st = (long long)gridDim.x * blockDim.x;
+  const long long n = (long long)nx * ny, st = (long long)blk.n * blockDim.x;
   double s = 0.0;
-  for (long long c0 = blockIdx.x * (long long)blockDim.x + threadIdx.x; c0 < n;
+  for (long long c0 = blk.id * (long long)blockDim.x + threadIdx.x; c0 < n;
        c0 += kRound * st) {
     double v[kRound], o[kRound];
 #pragma unroll
@@ -1064,7 +1153,13 @@ __global__ void __launch_bounds__(kVecThreads)
     }
   }
   s = block_sum(s, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (threadIdx.x == 0) partials[blk.id] = s;
+}
+__global__ void __launch_bounds__(kVecThreads)
+    k_arnoldi_start(const double* __restrict__ tx, const double* __restrict__ ty, int nx, int ny,
+                    const double* __restrict__ z, double* __restrict__ w,
+                    const double* __restrict__ v0, double* __restrict__ partials) {
+  arnoldi_start_body(hw_blk(), tx, ty, nx, ny, z, w, v0, partials);
 }
 
 // h = sum(part_in) (= w . v_i); hcol[i] = h; w -= h v_i; partial sums of
@@ -1072,14 +1167,16 @@ __global__ void __launch_bounds__(kVecThreads)
 // depend on h: every thread issues its first round before the reduction
 // that forms h (outside any loop, so its barriers are met by all threads),
 // then finishes its remaining rounds.
-__global__ void __launch_bounds__(kVecThreads)
-    k_mgs_step(const double* __restrict__ part_in, double* __restrict__ part_out, int nb,
-               double* __restrict__ hcol, int i, double* __restrict__ w,
-               const double* __restrict__ vi, const double* __restrict__ vnext, long long n) {
+__device__ __forceinline__ void mgs_step_body(const Blk blk, const double* __restrict__ part_in,
+                                              double* __restrict__ part_out, int nb,
+                                              double* __restrict__ hcol, int i,
+                                              double* __restrict__ w,
+                                              const double* __restrict__ vi,
+                                              const double* __restrict__ vnext, long long n) {
   __shared__ double red[kVecThreads / 64];
   const bool self = vnext == nullptr;
   const double* vn = self ? vi : vnext;
-  const long long st = (long long)gridDim.x * blockDim.x;
+  const long long st = (long long)blk.n * blockDim.x;
   double a[kRound], b[kRound], d[kRound];
   auto load = [&](long long c0) {
 #pragma unroll
@@ -1102,26 +1199,32 @@ __global__ void __launch_bounds__(kVecThreads)
       }
     }
   };
-  const long long start = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long start = blk.id * (long long)blockDim.x + threadIdx.x;
   load(start);
   h = reduce_partials(part_in, nb, red);
-  if (blockIdx.x == 0 && threadIdx.x == 0) hcol[i] = h;
+  if (blk.id == 0 && threadIdx.x == 0) hcol[i] = h;
   use(start);
   for (long long c0 = start + kRound * st; c0 < n; c0 += kRound * st) {
     load(c0);
     use(c0);
   }
   s = block_sum(s, red);
-  if (threadIdx.x == 0) part_out[blockIdx.x] = s;
+  if (threadIdx.x == 0) part_out[blk.id] = s;
+}
+__global__ void __launch_bounds__(kVecThreads)
+    k_mgs_step(const double* __restrict__ part_in, double* __restrict__ part_out, int nb,
+               double* __restrict__ hcol, int i, double* __restrict__ w,
+               const double* __restrict__ vi, const double* __restrict__ vnext, long long n) {
+  mgs_step_body(hw_blk(), part_in, part_out, nb, hcol, i, w, vi, vnext, n);
 }
 
 // hn = sqrt(sum(part_in)); hcol[j] = hn; w /= hn (if hn > 0).  First round
 // loaded before the reduction, as in k_mgs_step.
-__global__ void __launch_bounds__(kVecThreads)
-    k_norm_scale(const double* __restrict__ part_in, int nb, double* __restrict__ hcol, int j,
-                 double* __restrict__ w, long long n) {
+__device__ __forceinline__ void norm_scale_body(const Blk blk, const double* __restrict__ part_in,
+                                                int nb, double* __restrict__ hcol, int j,
+                                                double* __restrict__ w, long long n) {
   __shared__ double red[kVecThreads / 64];
-  const long long st = (long long)gridDim.x * blockDim.x;
+  const long long st = (long long)blk.n * blockDim.x;
   double a[kRound];
   auto load = [&](long long c0) {
 #pragma unroll
@@ -1130,10 +1233,10 @@ __global__ void __launch_bounds__(kVecThreads)
       a[u] = w[c < n ? c : n - 1];
     }
   };
-  const long long start = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long start = blk.id * (long long)blockDim.x + threadIdx.x;
   load(start);
   const double hn = sqrt(reduce_partials(part_in, nb, red));
-  if (blockIdx.x == 0 && threadIdx.x == 0) hcol[j] = hn;
+  if (blk.id == 0 && threadIdx.x == 0) hcol[j] = hn;
   if (!(hn > 0.0)) return;
   const double inv = 1.0 / hn;
   for (long long c0 = start; c0 < n; c0 += kRound * st) {
@@ -1144,6 +1247,11 @@ __global__ void __launch_bounds__(kVecThreads)
       if (c < n) w[c] = a[u] * inv;
     }
   }
+}
+__global__ void __launch_bounds__(kVecThreads)
+    k_norm_scale(const double* __restrict__ part_in, int nb, double* __restrict__ hcol, int j,
+                 double* __restrict__ w, long long n) {
+  norm_scale_body(hw_blk(), part_in, nb, hcol, j, w, n);
 }
 
 // p += sum_{i < k} y_i Z_i (k <= kMaxUpdate per launch).
@@ -2163,6 +2271,253 @@ void launch_sumsq(const double* x, long long n, double* partials, int nb, hipStr
   hipLaunchKernelGGL(k_sumsq, dim3(nb), dim3(kVecThreads), 0, s, x, n, partials);
 }
 
+// ---- launches over several contexts ----------------------------------------
+namespace {
+
+// The column whose workgroup range [pre[c], pre[c + 1]) holds workgroup b
+// (the largest c with pre[c] <= b; empty ranges are skipped).
+__device__ __forceinline__ int many_col(const int* __restrict__ pre, int ncol, int b) {
+  int lo = 0, hi = ncol - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+__device__ __forceinline__ Blk many_blk(const int* __restrict__ pre, int c) {
+  return Blk{(int)blockIdx.x - pre[c], pre[c + 1] - pre[c]};
+}
+
+template <typename T, typename S, int NB, int GS = (NB <= 16 ? 16 : NB <= 32 ? 32 : 64)>
+__global__ void __launch_bounds__(kBoxThreads)
+    k_local_many(const ManyCol* __restrict__ cols, const int* __restrict__ pre, int ncol,
+                 int group_bytes, int cp_words) {
+  const int c = many_col(pre, ncol, blockIdx.x);
+  const ManyCol& a = cols[c];
+  local_body<T, S, NB, GS>(many_blk(pre, c), a.lbox, a.m, group_bytes, cp_words,
+                           static_cast<const S*>(a.ldinv), static_cast<const S*>(a.lcoup), a.r,
+                           static_cast<T*>(a.p), a.nx, a.dof_off, a.dof_side, a.dof_q,
+                           a.dof_face0, a.face_w, a.mU, a.mP);
+}
+
+__global__ void k_coarse_rhs_many(const ManyCol* __restrict__ cols, const int* __restrict__ pre,
+                                  int ncol) {
+  const int c = many_col(pre, ncol, blockIdx.x);
+  const ManyCol& a = cols[c];
+  coarse_rhs_body(many_blk(pre, c), a.gsrc, a.gscale, a.mU, a.mP, a.g_nd, a.np);
+}
+
+__global__ void __launch_bounds__(kVecThreads)
+    k_coarse_fwd_many(const ManyCol* __restrict__ cols, const int* __restrict__ pre,
+                      const int* __restrict__ first, int ncol, int refine) {
+  const int c = many_col(pre, ncol, blockIdx.x);
+  const ManyCol& a = cols[c];
+  const int q = first[c] + (int)blockIdx.x - pre[c];
+  coarse_fwd_body(a.chunks[q], a.cfwd, refine ? a.rnd : a.g_nd, a.contrib, a.maxp, a.np,
+                  a.cdest, a.ybuf, a.cidx, refine ? a.dx : a.xc);
+}
+
+__global__ void __launch_bounds__(kVecThreads)
+    k_coarse_bwd_many(const ManyCol* __restrict__ cols, const int* __restrict__ pre,
+                      const int* __restrict__ first, int ncol, int refine) {
+  const int c = many_col(pre, ncol, blockIdx.x);
+  const ManyCol& a = cols[c];
+  const int q = first[c] + (int)blockIdx.x - pre[c];
+  coarse_bwd_body(a.chunks[q], a.cbwd, a.cidx, a.ybuf, refine ? a.dx : a.xc);
+}
+
+__global__ void k_coarse_resid_many(const ManyCol* __restrict__ cols,
+                                    const int* __restrict__ pre, int ncol) {
+  const int c = many_col(pre, ncol, blockIdx.x);
+  const ManyCol& a = cols[c];
+  coarse_resid_body(many_blk(pre, c), 0, a.crp, a.cci, a.cv, a.g_nd, a.xc, a.rnd, a.np, a.nc);
+}
+
+__global__ void k_coarse_add_many(const ManyCol* __restrict__ cols, const int* __restrict__ pre,
+                                  int ncol) {
+  const int c = many_col(pre, ncol, blockIdx.x);
+  const ManyCol& a = cols[c];
+  coarse_add_body(many_blk(pre, c), a.xc, a.dx, a.nc);
+}
+
+template <typename T, typename S>
+__global__ void __launch_bounds__(kBoxThreads)
+    k_reconstruct_many(const ManyCol* __restrict__ cols, const int* __restrict__ pre, int ncol) {
+  const int c = many_col(pre, ncol, blockIdx.x);
+  const ManyCol& a = cols[c];
+  reconstruct_body<T, S>(many_blk(pre, c), a.lbox, static_cast<const S*>(a.mbf), a.mbf_off,
+                         a.dof_off, a.xc, static_cast<T*>(a.p), a.nx);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+    k_residual_many(const ManyCol* __restrict__ cols, const int* __restrict__ pre, int ncol) {
+  const int c = many_col(pre, ncol, blockIdx.x);
+  const ManyCol& a = cols[c];
+  residual_body<T>(many_blk(pre, c), static_cast<const T*>(a.txT), static_cast<const T*>(a.tyT),
+                   a.nx, a.ny, a.r, static_cast<const T*>(a.p), static_cast<T*>(a.rho));
+}
+
+template <typename T, typename S, int NB, int GS = (NB <= 16 ? 16 : NB <= 32 ? 32 : 64)>
+__global__ void __launch_bounds__(kBoxThreads)
+    k_patch_many(const ManyCol* __restrict__ cols, const int* __restrict__ pre, int ncol,
+                 int group_bytes, int cp_words) {
+  const int c = many_col(pre, ncol, blockIdx.x);
+  const ManyCol& a = cols[c];
+  patch_body<T, S, NB, GS>(many_blk(pre, c), a.pbox, a.m, group_bytes, cp_words,
+                           static_cast<const S*>(a.pdinv), static_cast<const S*>(a.pcoup),
+                           static_cast<const T*>(a.rho), static_cast<T*>(a.p), a.nx);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+    k_sum_many(const ManyCol* __restrict__ cols, const int* __restrict__ pre, int ncol) {
+  const int c = many_col(pre, ncol, blockIdx.x);
+  const ManyCol& a = cols[c];
+  sum_body<T>(many_blk(pre, c), static_cast<const T*>(a.p), a.n, a.partials);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+    k_finalize_many(const ManyCol* __restrict__ cols, const int* __restrict__ pre, int ncol) {
+  const int c = many_col(pre, ncol, blockIdx.x);
+  const ManyCol& a = cols[c];
+  finalize_body<T>(many_blk(pre, c), static_cast<const T*>(a.p), a.n,
+                   a.noflow ? a.partials : (const double*)nullptr, a.nb, a.z);
+}
+
+__global__ void __launch_bounds__(kVecThreads)
+    k_arnoldi_start_many(const ManyCol* __restrict__ cols, const int* __restrict__ pre,
+                         int ncol) {
+  const int c = many_col(pre, ncol, blockIdx.x);
+  const ManyCol& a = cols[c];
+  arnoldi_start_body(many_blk(pre, c), a.tx, a.ty, a.nx, a.ny, a.Z + (long long)a.j * a.n,
+                     a.V + (long long)(a.j + 1) * a.n, a.V, a.parts);
+}
+
+__global__ void __launch_bounds__(kVecThreads)
+    k_mgs_step_many(const ManyCol* __restrict__ cols, const int* __restrict__ pre, int ncol,
+                    int i) {
+  const int c = many_col(pre, ncol, blockIdx.x);
+  const ManyCol& a = cols[c];
+  const long long n = a.n;
+  mgs_step_body(many_blk(pre, c), a.parts + (i % 2) * kMaxVecBlocks,
+                a.parts + ((i + 1) % 2) * kMaxVecBlocks, a.nb, a.hcol, i,
+                a.V + (long long)(a.j + 1) * n, a.V + (long long)i * n,
+                i < a.j ? a.V + (long long)(i + 1) * n : (const double*)nullptr, n);
+}
+
+__global__ void __launch_bounds__(kVecThreads)
+    k_norm_scale_many(const ManyCol* __restrict__ cols, const int* __restrict__ pre, int ncol) {
+  const int c = many_col(pre, ncol, blockIdx.x);
+  const ManyCol& a = cols[c];
+  norm_scale_body(many_blk(pre, c), a.parts + ((a.j + 1) % 2) * kMaxVecBlocks, a.nb, a.hcol,
+                  a.j + 1, a.V + (long long)(a.j + 1) * a.n, a.n);
+}
+
+// One workgroup per item.
+__global__ void k_gather(const GatherItem* __restrict__ items, double* __restrict__ stage) {
+  const GatherItem g = items[blockIdx.x];
+  for (int e = threadIdx.x; e < g.count; e += blockDim.x) stage[g.dst + e] = g.src[e];
+}
+
+}  // namespace
+
+template <typename T, typename S>
+void launch_local_many(const ManyCol* cols, const int* pre, int ncol, int blocks, int max_cells,
+                       int max_bx, hipStream_t s) {
+  if (blocks <= 0) return;
+  const int groups = box_groups(max_bx, max_cells, sizeof(T), sizeof(S));
+  const int gb = (int)group_bytes(max_bx, max_cells, sizeof(T), sizeof(S));
+  const int cp_words = round16(max_cells, sizeof(S));
+  MRCM_BOX_DISPATCH(k_local_many, T, S, max_bx, dim3(blocks), dim3(groups * group_size(max_bx)),
+                    (size_t)groups * gb, s, cols, pre, ncol, gb, cp_words);
+}
+void launch_coarse_rhs_many(const ManyCol* cols, const int* pre, int ncol, int blocks,
+                            hipStream_t s) {
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL(k_coarse_rhs_many, dim3(blocks), dim3(256), 0, s, cols, pre, ncol);
+}
+void launch_coarse_fwd_many(const ManyCol* cols, const int* pre, const int* first, int ncol,
+                            int blocks, int refine, int max_nf, hipStream_t s) {
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL(k_coarse_fwd_many, dim3(blocks), dim3(coarse_threads(blocks)),
+                     sizeof(double) * (size_t)(max_nf > 0 ? max_nf : 1), s, cols, pre, first,
+                     ncol, refine);
+}
+void launch_coarse_bwd_many(const ManyCol* cols, const int* pre, const int* first, int ncol,
+                            int blocks, int refine, int max_nu, hipStream_t s) {
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL(k_coarse_bwd_many, dim3(blocks), dim3(coarse_threads(blocks)),
+                     sizeof(double) * (size_t)(max_nu > 0 ? max_nu : 1), s, cols, pre, first,
+                     ncol, refine);
+}
+void launch_coarse_resid_many(const ManyCol* cols, const int* pre, int ncol, int blocks,
+                              hipStream_t s) {
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL(k_coarse_resid_many, dim3(blocks), dim3(256), 0, s, cols, pre, ncol);
+}
+void launch_coarse_add_many(const ManyCol* cols, const int* pre, int ncol, int blocks,
+                            hipStream_t s) {
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL(k_coarse_add_many, dim3(blocks), dim3(256), 0, s, cols, pre, ncol);
+}
+template <typename T, typename S>
+void launch_reconstruct_many(const ManyCol* cols, const int* pre, int ncol, int blocks,
+                             hipStream_t s) {
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL((k_reconstruct_many<T, S>), dim3(blocks), dim3(kBoxThreads), 0, s, cols,
+                     pre, ncol);
+}
+template <typename T>
+void launch_residual_many(const ManyCol* cols, const int* pre, int ncol, int blocks,
+                          hipStream_t s) {
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL(k_residual_many<T>, dim3(blocks), dim3(kVecThreads), 0, s, cols, pre, ncol);
+}
+template <typename T, typename S>
+void launch_patch_many(const ManyCol* cols, const int* pre, int ncol, int blocks, int max_cells,
+                       int max_bx, hipStream_t s) {
+  if (blocks <= 0) return;
+  const int groups = box_groups(max_bx, max_cells, sizeof(T), sizeof(S));
+  const int gb = (int)group_bytes(max_bx, max_cells, sizeof(T), sizeof(S));
+  const int cp_words = round16(max_cells, sizeof(S));
+  MRCM_BOX_DISPATCH(k_patch_many, T, S, max_bx, dim3(blocks), dim3(groups * group_size(max_bx)),
+                    (size_t)groups * gb, s, cols, pre, ncol, gb, cp_words);
+}
+template <typename T>
+void launch_sum_many(const ManyCol* cols, const int* pre, int ncol, int blocks, hipStream_t s) {
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL(k_sum_many<T>, dim3(blocks), dim3(kVecThreads), 0, s, cols, pre, ncol);
+}
+template <typename T>
+void launch_finalize_many(const ManyCol* cols, const int* pre, int ncol, int blocks,
+                          hipStream_t s) {
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL(k_finalize_many<T>, dim3(blocks), dim3(kVecThreads), 0, s, cols, pre, ncol);
+}
+void launch_arnoldi_start_many(const ManyCol* cols, const int* pre, int ncol, int blocks,
+                               hipStream_t s) {
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL(k_arnoldi_start_many, dim3(blocks), dim3(kVecThreads), 0, s, cols, pre,
+                     ncol);
+}
+void launch_mgs_step_many(const ManyCol* cols, const int* pre, int ncol, int blocks, int i,
+                          hipStream_t s) {
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL(k_mgs_step_many, dim3(blocks), dim3(kVecThreads), 0, s, cols, pre, ncol, i);
+}
+void launch_norm_scale_many(const ManyCol* cols, const int* pre, int ncol, int blocks,
+                            hipStream_t s) {
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL(k_norm_scale_many, dim3(blocks), dim3(kVecThreads), 0, s, cols, pre, ncol);
+}
+void launch_gather(const GatherItem* items, int count, double* stage, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_gather, dim3(count), dim3(64), 0, s, items, stage);
+}
+
 #define MRCM_INSTANTIATE_TS(T, S)                                                              \
   template void launch_local<T, S>(const BoxDesc*, int, int, int, const S*, const S*,          \
                                    const double*, T*, int, const int*, const int*, const int*,   \
@@ -2180,7 +2535,12 @@ void launch_sumsq(const double* x, long long n, double* partials, int nb, hipStr
                                            const long long*, const int*, const double*, int,    \
                                            T* const*, int, hipStream_t);                        \
   template void launch_patch_k<T, S>(int, const BoxDesc*, int, int, int, const S*, const S*,    \
-                                     const T* const*, T* const*, T* const*, int, hipStream_t);
+                                     const T* const*, T* const*, T* const*, int, hipStream_t); \
+  template void launch_local_many<T, S>(const ManyCol*, const int*, int, int, int, int,         \
+                                        hipStream_t);                                           \
+  template void launch_reconstruct_many<T, S>(const ManyCol*, const int*, int, int, hipStream_t); \
+  template void launch_patch_many<T, S>(const ManyCol*, const int*, int, int, int, int,         \
+                                        hipStream_t);
 #define MRCM_INSTANTIATE_T(T)                                                                  \
   template void launch_residual<T>(const T*, const T*, int, int, const double*, const T*, T*,   \
                                    hipStream_t);                                                \
@@ -2188,7 +2548,10 @@ void launch_sumsq(const double* x, long long n, double* partials, int nb, hipStr
   template void launch_residual_k<T>(int, const T*, const T*, int, int, const double* const*,   \
                                      const T* const*, T* const*, hipStream_t);                  \
   template void launch_finalize_k<T>(int, const T* const*, long long, int, double* const*,      \
-                                     double*, hipStream_t);
+                                     double*, hipStream_t);                                     \
+  template void launch_residual_many<T>(const ManyCol*, const int*, int, int, hipStream_t);     \
+  template void launch_sum_many<T>(const ManyCol*, const int*, int, int, hipStream_t);          \
+  template void launch_finalize_many<T>(const ManyCol*, const int*, int, int, hipStream_t);
 
 MRCM_INSTANTIATE_TS(double, double)
 MRCM_INSTANTIATE_TS(float, float)

@@ -7,19 +7,20 @@ GMRES(10) with MRCM-OS to the relative tolerance.
 
 Requests arrive over time.  The server admits an arrived request as soon as
 one of its slots is free and the request's device footprint (mrcm_footprint:
-factorisations, basis functions, interface factor, Krylov space of its right-
-hand sides) fits under the memory budget beside the requests in flight.  An
-admitted request is set up on its own stream (its factorisations stay
-resident in device memory while it is in flight) and solved while the others
-are in flight, so their kernels overlap on the device; its slot and memory are
-released when its answer is complete, and the next arrived request takes
-them.  Nothing is shared between requests and every kernel's arithmetic and
-reduction order is fixed, so each answer is bit-identical to the same request
-solved alone.
+factorisations, basis functions, interface factor, Krylov spaces of its
+right-hand sides) fits under the memory budget beside the requests in flight.
+An admitted request is set up by a worker thread on its own stream (its
+factorisations stay resident in device memory while it is in flight); when
+its set-up ends, its right-hand sides join the batched GMRES that the serving
+thread advances in ticks: every tick runs one Arnoldi step of every right-hand
+side in flight, of every request, with one launch per phase of T over all of
+them (gmres_batch_tick).  A request's slot and memory are released when its
+answer is complete, and the next arrived request takes them.  Every kernel's
+arithmetic and reduction order is fixed per right-hand side, so each answer
+is bit-identical to the same request solved alone (and to gmres_solve).
 
-The scheduling is host logic and takes the solve function as an argument (the
-tests drive it with stand-ins on the CPU); `gpu_solver` is the solve function
-of the library.
+The scheduling is host logic and takes the backend as an argument (the tests
+drive it with stand-ins on the CPU); `GpuBackend` is the library's.
 """
 from __future__ import annotations
 
@@ -104,12 +105,11 @@ def config_for(n: int, params: dict | None = None):
                   p["sweeps"], p["overlap"], p["degree"], p["precision"])
 
 
-LANES, WIDTH = 4, 4  # lanes and right-hand sides per lane of a request (mrcm_set_lanes/_batch)
 
 
 def footprint_of(req: Request, params: dict | None = None) -> int:
     from .binding import footprint
-    return footprint(config_for(req.n, params), min(req.nrhs, LANES * WIDTH))
+    return footprint(config_for(req.n, params), req.nrhs)
 
 
 def host_cores() -> int:
@@ -121,77 +121,97 @@ def host_cores() -> int:
         return max(1, os.cpu_count() or 1)
 
 
-def gpu_solver(params: dict | None = None, rtol: float = 1e-8, restart: int = 10,
-               maxit: int = 500, keep: bool = True, device: int = 0,
-               setup_threads: int | None = None):
-    """Solve function of the library: set up the request's context on its
-    own stream, solve its right-hand sides, copy the answer to the host and
-    release everything.  setup_threads: host threads of each set-up; None
-    (the default) divides the host cores among the set-ups in progress when
-    a set-up starts (all of them when it runs alone); 0 = all cores always."""
-    import torch
+class GpuBackend:
+    """The library behind the server: a request is set up on its own stream
+    by a worker thread (its factorisations stay resident while it is in
+    flight), then its right-hand sides join one batched GMRES (gmres_batch_*)
+    that the server ticks; its answer is copied to the host and its context
+    released when all of them have finished.
 
-    from .binding import Context, set_host_threads
+    setup_threads: host threads of each set-up; None (the default) divides
+    the host cores among the set-ups in progress when a set-up starts (all
+    of them when it runs alone); 0 = all cores always."""
 
-    cores = host_cores()
-    lock = threading.Lock()
-    setups = [0]  # set-ups in progress
+    def __init__(self, params: dict | None = None, rtol: float = 1e-8, restart: int = 10,
+                 maxit: int = 500, keep: bool = True, device: int = 0,
+                 setup_threads: int | None = None):
+        self.params, self.rtol, self.restart, self.maxit = params, rtol, restart, maxit
+        self.keep, self.device, self.setup_threads = keep, device, setup_threads
+        self.cores = host_cores()
+        self.lock = threading.Lock()
+        self.setups = 0
+        self.batch = None
 
-    def solve(req: Request) -> dict:
-        with lock:
-            setups[0] += 1
-            share = max(1, cores // setups[0])
-        set_host_threads(share if setup_threads is None else setup_threads)
-        in_setup = True
+    def setup(self, req: Request) -> dict:
+        import torch
+
+        from .binding import Context, set_host_threads
+        with self.lock:
+            self.setups += 1
+            share = max(1, self.cores // self.setups)
+        set_host_threads(share if self.setup_threads is None else self.setup_threads)
         try:
-            dev = torch.device("cuda", device)
+            dev = torch.device("cuda", self.device)
             stream = torch.cuda.Stream(device=dev)
             with torch.cuda.stream(stream):
                 K = torch.tensor(req.K, dtype=torch.float64, device=dev)
                 B = torch.tensor(req.B, dtype=torch.float64, device=dev).contiguous()
                 t0 = time.perf_counter()
-                ctx = Context(config_for(req.n, params), K, stream=stream)
-                ctx.set_lanes(LANES)
-                ctx.set_batch(WIDTH)
+                ctx = Context(config_for(req.n, self.params), K, stream=stream)
+                P = torch.zeros_like(B)
                 stream.synchronize()
                 t1 = time.perf_counter()
-                with lock:
-                    setups[0] -= 1
-                in_setup = False
-                P = torch.zeros_like(B)
-                st = ctx.gmres(B, P, rtol=rtol, restart=restart, maxit=maxit, stream=stream,
-                               raise_on_noconv=False)
-                stream.synchronize()
-                t2 = time.perf_counter()
-                p = P.cpu().numpy() if keep else None
-                ctx.close()
         finally:
-            if in_setup:
-                with lock:
-                    setups[0] -= 1
-        return dict(iterations=st.iterations, converged=st.converged,
-                    final_relres=st.final_relres, setup_s=t1 - t0, solve_s=t2 - t1, p=p)
+            with self.lock:
+                self.setups -= 1
+        return dict(ctx=ctx, B=B, P=P, K=K, stream=stream, setup_s=t1 - t0)
 
-    return solve
+    def add(self, h: dict) -> None:
+        from .binding import Batch
+        if self.batch is None:
+            self.batch = Batch(self.restart)
+        h["tag"] = self.batch.add(h["ctx"], h["B"], h["P"], rtol=self.rtol, maxit=self.maxit,
+                                  stream=h["stream"])
+        h["t_add"] = time.perf_counter()
+
+    def tick(self) -> int:
+        return self.batch.tick() if self.batch is not None else 0
+
+    def poll(self, h: dict):
+        st = self.batch.poll(h["tag"])
+        if st is None:
+            return None
+        t2 = time.perf_counter()
+        self.batch.remove(h["tag"])
+        p = h["P"].cpu().numpy() if self.keep else None
+        h["ctx"].close()
+        return dict(iterations=st.iterations, converged=st.converged,
+                    final_relres=st.final_relres, setup_s=h["setup_s"],
+                    solve_s=t2 - h["t_add"], p=p)
 
 
 class Server:
     """Admission and continuous batching of requests (see the module text).
 
-    max_active: requests in flight at once; mem_budget: bytes their
-    footprints may total; footprint(req) -> bytes; solve(req) -> dict of
-    Result fields."""
+    backend: setup(req) -> handle, run on worker threads; add(handle),
+    tick() -> right-hand sides still running, poll(handle) -> None or a dict
+    of Result fields (the request is then finished and released), run on the
+    serving thread.  max_active: requests in flight at once (set up or
+    solving); mem_budget: bytes their footprints may total; footprint(req)
+    -> bytes; setup_workers: set-ups in progress at once."""
 
-    def __init__(self, solve, max_active: int = 8, mem_budget: int = 200 << 30,
-                 footprint=footprint_of):
+    def __init__(self, backend, max_active: int = 8, mem_budget: int = 200 << 30,
+                 footprint=footprint_of, setup_workers: int = 4):
         if max_active < 1:
             raise ValueError("max_active must be at least 1")
-        self.solve = solve
+        self.backend = backend
         self.max_active = max_active
         self.mem_budget = mem_budget
         self.footprint = footprint
+        self.setup_workers = max(1, setup_workers)
         self.peak_active = 0
         self.peak_bytes = 0
+        self.ticks = 0
         self.events = []   # (time, "admit" | "done", rid), in order
 
     def run(self, requests, realtime: bool = True) -> list:
@@ -202,55 +222,62 @@ class Server:
         for r in reqs:
             if self.footprint(r) > self.mem_budget:
                 raise ValueError(f"request {r.rid} needs more memory than the whole budget")
-        lock = threading.Lock()
         results = {}
         start = time.perf_counter()
         clock = lambda: time.perf_counter() - start  # noqa: E731
         pending = list(reqs)
-        inflight = {}  # future -> (request, bytes)
+        setting_up = {}   # future -> (request, bytes, admitted)
+        solving = []      # (request, bytes, admitted, handle)
         used = 0
-        with ThreadPoolExecutor(max_workers=self.max_active) as pool:
-            while pending or inflight:
+        with ThreadPoolExecutor(max_workers=self.setup_workers) as pool:
+            while pending or setting_up or solving:
                 now = clock()
                 # admit, in arrival order, what has arrived and fits
                 while pending:
                     r = pending[0]
                     arrived = (r.arrival <= now) if realtime else True
                     need = self.footprint(r)
-                    if not arrived or len(inflight) >= self.max_active or used + need > self.mem_budget:
+                    inflight = len(setting_up) + len(solving)
+                    if not arrived or inflight >= self.max_active or used + need > self.mem_budget:
                         break
                     pending.pop(0)
                     used += need
                     t_adm = clock()
-                    with lock:
-                        self.events.append((t_adm, "admit", r.rid))
-                    fut = pool.submit(self._serve_one, r, t_adm, clock, results, lock)
-                    inflight[fut] = (r, need)
-                    self.peak_active = max(self.peak_active, len(inflight))
+                    self.events.append((t_adm, "admit", r.rid))
+                    setting_up[pool.submit(self.backend.setup, r)] = (r, need, t_adm)
+                    self.peak_active = max(self.peak_active, len(setting_up) + len(solving))
                     self.peak_bytes = max(self.peak_bytes, used)
-                if not inflight:
-                    # nothing running: sleep until the next arrival
-                    time.sleep(max(0.0, pending[0].arrival - clock()) if realtime else 0.0)
+                # requests whose set-up ended join the batch
+                for f in [f for f in setting_up if f.done()]:
+                    r, need, t_adm = setting_up.pop(f)
+                    h = f.result()  # re-raise a failed set-up here
+                    self.backend.add(h)
+                    solving.append((r, need, t_adm, h))
+                if solving:
+                    self.backend.tick()
+                    self.ticks += 1
+                    still = []
+                    for r, need, t_adm, h in solving:
+                        out = self.backend.poll(h)
+                        if out is None:
+                            still.append((r, need, t_adm, h))
+                            continue
+                        t_done = clock()
+                        used -= need
+                        self.events.append((t_done, "done", r.rid))
+                        results[r.rid] = Result(r.rid, r.n, r.nrhs, r.arrival, t_adm, t_done,
+                                                footprint=need, **out)
+                    solving = still
                     continue
+                # nothing to tick: wait for a set-up or the next arrival
                 timeout = None
                 if pending and realtime and pending[0].arrival > clock():
                     timeout = pending[0].arrival - clock()
-                done, _ = wait(list(inflight), timeout=timeout, return_when=FIRST_COMPLETED)
-                for f in done:
-                    r, need = inflight.pop(f)
-                    used -= need
-                    f.result()  # re-raise a failed solve here
+                if setting_up:
+                    wait(list(setting_up), timeout=timeout, return_when=FIRST_COMPLETED)
+                elif timeout is not None:
+                    time.sleep(timeout)
         return [results[r.rid] for r in sorted(requests, key=lambda r: r.rid)]
-
-    def _serve_one(self, r: Request, t_adm: float, clock, results: dict, lock):
-        out = self.solve(r)
-        t_done = clock()
-        res = Result(r.rid, r.n, r.nrhs, r.arrival, t_adm, t_done, footprint=self.footprint(r),
-                     **out)
-        with lock:
-            self.events.append((t_done, "done", r.rid))
-            results[r.rid] = res
-        return res
 
 
 def summary(results, wall: float) -> dict:

@@ -1,11 +1,21 @@
 """GPU tests of the serving path and of the batch and allocator entry points.
 
-* Requests of mixed grid sizes served together (in flight at once, each on
-  its own stream) give answers bit-identical to the same requests served one
-  at a time, and every answer meets the tolerance on the true residual.
+* Requests of mixed grid sizes served together (their right-hand sides in
+  one batched GMRES, advanced in shared ticks) give answers bit-identical to
+  the same requests served one at a time, and every answer meets the
+  tolerance on the true residual.
 * A served request in FP64 (precision 0) matches the oracle's GMRES solution
-  (iterations within +-1, solution within the FP64 gate).
-* mrcm_apply_many over several contexts equals mrcm_apply on each, bit for bit.
+  (iterations within +-1, solution within the FP64 gate); served 512^2 and
+  1024^2 requests in the serving mode (FP32 factor storage, FP64 arithmetic)
+  equal gmres_solve bit for bit, the 512^2 one also matches the oracle's
+  iterations (+-1 per right-hand side) and, driven to 1e-10, the direct
+  solve within 1e-7; the 1024^2 answers meet the tolerance on the oracle's
+  own A.
+* mrcm_apply_many over contexts of several sizes, boundary types and
+  precision modes (one launch per phase over all their columns) equals
+  mrcm_apply on each, bit for bit.
+* The batched GMRES (gmres_batch_*) over contexts of several families, with
+  right-hand sides joining while others run, equals gmres_solve bit for bit.
 * Contexts set up with a caller allocator (torch's caching allocator through
   mrcm_set_allocator) allocate through it and compute the same T r.
 * gmres_solve advancing several right-hand sides at once (lanes, and
@@ -16,7 +26,7 @@
 import numpy as np
 import pytest
 
-from oracle.discretization import assemble
+from oracle.discretization import assemble, direct_solve
 from oracle.gmres import gmres
 from oracle.mrcm import MRCM
 from paper_2606_08883_amd import binding as B
@@ -45,8 +55,8 @@ def _requests():
 def test_mix_equals_alone(dev):
     print("serving: 4 requests alone, then together", flush=True)
     reqs = _requests()
-    alone = S.Server(S.gpu_solver(), max_active=1).run(reqs, realtime=False)
-    mix_server = S.Server(S.gpu_solver(), max_active=4)
+    alone = S.Server(S.GpuBackend(), max_active=1).run(reqs, realtime=False)
+    mix_server = S.Server(S.GpuBackend(), max_active=4)
     mix = mix_server.run(reqs, realtime=False)
     assert mix_server.peak_active >= 2
     for a, m, r in zip(alone, mix, reqs):
@@ -63,7 +73,7 @@ def test_mix_equals_alone(dev):
 def test_served_request_matches_oracle(dev):
     r = S.make_payload(S.Request(0, 128, 2.0, 1000, 2000, 2, 0.0))
     params = dict(precision=0)
-    res = S.Server(S.gpu_solver(params), max_active=1).run([r], realtime=False)[0]
+    res = S.Server(S.GpuBackend(params), max_active=1).run([r], realtime=False)[0]
     p = dict(S.SERVE_PARAMS, **params)
     mr = MRCM(r.K, nx=r.n, ny=r.n, bc=(0, 0, 0, 0), sx=p["s"], sy=p["s"],
               oversample=p["oversample"], alpha=p["alpha"],
@@ -81,23 +91,124 @@ def test_served_request_matches_oracle(dev):
     assert abs(res.iterations - its) <= r.nrhs
 
 
-def test_apply_many_equals_apply(dev):
-    cfgs = [S.config_for(128), S.config_for(256), S.config_for(128, dict(precision=0))]
+def _mixed_contexts(dev):
+    """Contexts of several sizes, boundary types and precision modes: two
+    families share the serving parameters, the others differ in box widths,
+    sweeps or precision."""
+    cfgs = [S.config_for(128), S.config_for(256), S.config_for(128, dict(precision=0)),
+            B.Config(100, 76, (1, 1, 0, 0), 12, 12, 2, 10.0, 0, 2, 2, 1, 2),
+            S.config_for(192, dict(precision=1)), S.config_for(64)]
     Ks = [wl.lognormal_K(c.nx, c.ny, 2.0, 16.0, 40 + i) for i, c in enumerate(cfgs)]
     ctxs = [B.Context(c, torch.tensor(K, dtype=torch.float64, device=dev)) for c, K in zip(cfgs, Ks)]
-    rs = [torch.tensor(np.stack([wl.random_vector(c.nx * c.ny, 50 + i + 7 * k, zero_mean=True)
-                                 for k in range(2)]), dtype=torch.float64, device=dev).contiguous()
-          for i, c in enumerate(cfgs)]
-    zs = [torch.empty_like(r) for r in rs]
-    B.apply_many(ctxs, rs, zs)
-    torch.cuda.synchronize()
-    for c, r, z in zip(ctxs, rs, zs):
-        z1 = torch.empty_like(r)
-        c.apply(r, z1)
+    return cfgs, ctxs
+
+
+def _rhs(c, nrhs, seed, dev):
+    noflow = not any(c.bc)
+    return torch.tensor(np.stack([wl.random_vector(c.nx * c.ny, seed + 7 * k, zero_mean=noflow)
+                                  for k in range(nrhs)]), dtype=torch.float64,
+                        device=dev).contiguous()
+
+
+def test_apply_many_equals_apply(dev):
+    print("apply_many: six contexts, four families, 1..3 columns each", flush=True)
+    cfgs, ctxs = _mixed_contexts(dev)
+    rs = [_rhs(c, 1 + i % 3, 50 + i, dev) for i, c in enumerate(cfgs)]
+    for rep in range(2):   # the second call reuses the column work spaces and tables
+        zs = [torch.full_like(r, 3.0) for r in rs]
+        B.apply_many(ctxs, rs, zs)
         torch.cuda.synchronize()
-        assert torch.equal(z, z1)
+        for c, r, z in zip(ctxs, rs, zs):
+            z1 = torch.empty_like(r)
+            c.apply(r, z1)
+            torch.cuda.synchronize()
+            assert torch.equal(z, z1)
+    with pytest.raises(B.MrcmError):
+        B.apply_many([ctxs[0], ctxs[0]], [rs[0], rs[0]], [zs[0], zs[0]])
     for c in ctxs:
         c.close()
+
+
+def test_batch_equals_gmres_solve(dev):
+    print("batched GMRES: six contexts, right-hand sides joining while others run", flush=True)
+    cfgs, ctxs = _mixed_contexts(dev)
+    bs = [_rhs(c, 1 + (i + 1) % 3, 90 + i, dev) for i, c in enumerate(cfgs)]
+    ps = [torch.full_like(b, 5.0) for b in bs]
+    batch = B.Batch(10)
+    tags = {}
+    ticks = 0
+    for i in range(len(ctxs)):   # one more context joins every third tick
+        tags[i] = batch.add(ctxs[i], bs[i], ps[i], rtol=1e-8, maxit=400)
+        for _ in range(3):
+            batch.tick()
+            ticks += 1
+    while batch.tick() > 0:
+        ticks += 1
+    stats = {i: batch.poll(t) for i, t in tags.items()}
+    print(f"  {ticks} ticks", flush=True)
+    for i, c in enumerate(ctxs):
+        st = stats[i]
+        assert st is not None and st.converged
+        c.set_lanes(1)
+        p1 = torch.zeros_like(bs[i])
+        s1 = c.gmres(bs[i], p1, rtol=1e-8, restart=10, maxit=400)
+        torch.cuda.synchronize()
+        print(f"  context {i} ({cfgs[i].nx}x{cfgs[i].ny}, precision {cfgs[i].precision}): "
+              f"iterations {st.iterations} / {s1.iterations}, identical "
+              f"{torch.equal(p1, ps[i])}", flush=True)
+        assert (st.iterations, st.cycles) == (s1.iterations, s1.cycles)
+        assert st.final_relres == s1.final_relres
+        assert torch.equal(p1, ps[i])
+        batch.remove(tags[i])
+    with pytest.raises(B.MrcmError):
+        batch.poll(tags[0])
+    batch.close()
+    for c in ctxs:
+        c.close()
+
+
+def test_served_large_requests_in_the_serving_mode(dev):
+    """512^2 and 1024^2 requests (precision 2) served together."""
+    reqs = [S.make_payload(S.Request(0, 512, 2.5, 1100, 2100, 2, 0.0)),
+            S.make_payload(S.Request(1, 1024, 2.0, 1101, 2101, 2, 0.0))]
+    print("serving: 512^2 and 1024^2 requests together, precision 2", flush=True)
+    served = S.Server(S.GpuBackend(), max_active=2).run(reqs, realtime=False)
+    for r, res in zip(reqs, served):
+        ctx = B.Context(S.config_for(r.n), torch.tensor(r.K, dtype=torch.float64, device=dev))
+        b = torch.tensor(r.B, dtype=torch.float64, device=dev).contiguous()
+        p1 = torch.zeros_like(b)
+        s1 = ctx.gmres(b, p1, rtol=1e-8, restart=10, maxit=500)
+        torch.cuda.synchronize()
+        A = assemble(r.K, r.n, r.n, (0, 0, 0, 0))
+        rel = [np.linalg.norm(r.B[k] - A @ res.p[k]) / np.linalg.norm(r.B[k])
+               for k in range(r.nrhs)]
+        print(f"  {r.n}^2: iterations {res.iterations} / gmres_solve {s1.iterations}, "
+              f"max relres (oracle A) {max(rel):.2e}", flush=True)
+        assert res.converged and res.iterations == s1.iterations
+        assert np.array_equal(res.p, p1.cpu().numpy())
+        assert max(rel) <= 1e-8 * (1 + 1e-6)
+        ctx.close()
+    # 512^2 against the oracle: its GMRES counts, and the direct solve at 1e-10
+    r = reqs[0]
+    p = S.SERVE_PARAMS
+    mr = MRCM(r.K, nx=r.n, ny=r.n, bc=(0, 0, 0, 0), sx=p["s"], sy=p["s"],
+              oversample=p["oversample"], alpha=p["alpha"], beta_len="H", sweeps=p["sweeps"],
+              overlap=p["overlap"], degree=p["degree"])
+    its = []
+    for k in range(r.nrhs):
+        ref = gmres(lambda x: mr.A @ x, mr.apply, r.B[k], rtol=1e-8, restart=10, maxit=500)
+        its.append(ref.iterations)
+    print(f"  512^2 oracle iterations {its} (served total {served[0].iterations})", flush=True)
+    assert abs(served[0].iterations - sum(its)) <= r.nrhs
+    tight = S.Server(S.GpuBackend(rtol=1e-10, maxit=800), max_active=1).run([r],
+                                                                             realtime=False)[0]
+    assert tight.converged
+    for k in range(r.nrhs):
+        exact = direct_solve(mr.A, r.B[k], (0, 0, 0, 0))
+        got = tight.p[k] - tight.p[k].mean()
+        err = np.linalg.norm(got - exact) / np.linalg.norm(exact)
+        print(f"  512^2 rhs {k} at 1e-10: rel L2 to the direct solve {err:.2e}", flush=True)
+        assert err <= 1e-7
 
 
 def test_caller_allocator(dev):

@@ -1,10 +1,12 @@
 """Admission and continuous batching of the request loop, on the CPU.
 
-The solve function is a stand-in that sleeps for a time set by the request's
-size, so the scheduling rules can be checked without a GPU: slots and the
-memory budget are never exceeded, requests are admitted in arrival order and
-no earlier than their arrival, and a request that arrives while a long one is
-in flight starts as soon as a slot frees, without waiting for the long one.
+The backend is a stand-in: its set-up sleeps, and every tick advances each
+request in the batch by the tick's time until the request's work (set by its
+size) is done, so the scheduling rules can be checked without a GPU: slots
+and the memory budget are never exceeded, requests are admitted in arrival
+order and no earlier than their arrival, and a request that arrives while a
+long one is in flight joins the batch and finishes without waiting for the
+long one.
 """
 import time
 
@@ -13,12 +15,35 @@ import pytest
 from paper_2606_08883_amd.serving import Request, Server, make_requests, summary
 
 
-def fake_solve(unit=0.02):
-    def solve(req):
-        time.sleep(unit * req.n / 128)
-        return dict(iterations=3 * req.nrhs, converged=True, final_relres=1e-9, setup_s=0.0,
-                    solve_s=unit * req.n / 128, p=None)
-    return solve
+class FakeBackend:
+    """Set-up sleeps setup_s; a request needs unit * n / 128 seconds of
+    ticks; a tick takes tick_s and advances every request in the batch."""
+
+    def __init__(self, unit=0.02, tick_s=0.002, setup_s=0.002):
+        self.unit, self.tick_s, self.setup_s = unit, tick_s, setup_s
+        self.active = []
+
+    def setup(self, req):
+        time.sleep(self.setup_s)
+        return {"req": req, "left": self.unit * req.n / 128, "ticks": 0}
+
+    def add(self, h):
+        self.active.append(h)
+
+    def tick(self):
+        time.sleep(self.tick_s)
+        for h in self.active:
+            h["left"] -= self.tick_s
+            h["ticks"] += 1
+        return len(self.active)
+
+    def poll(self, h):
+        if h["left"] > 1e-12:
+            return None
+        self.active.remove(h)
+        r = h["req"]
+        return dict(iterations=3 * r.nrhs, converged=True, final_relres=1e-9,
+                    setup_s=self.setup_s, solve_s=h["ticks"] * self.tick_s, p=None)
 
 
 def fp(req):
@@ -44,7 +69,7 @@ def _check_log(server, results, max_active, budget):
 def test_slots_budget_and_order():
     reqs = [Request(i, 128 * (1 + i % 3), 2.0, 0, 0, 2, 0.01 * i) for i in range(10)]
     budget = fp(reqs[2]) + fp(reqs[1])  # at most one 384^2 and one 256^2 together
-    s = Server(fake_solve(), max_active=3, mem_budget=budget, footprint=fp)
+    s = Server(FakeBackend(), max_active=3, mem_budget=budget, footprint=fp)
     res = s.run(reqs)
     assert [r.rid for r in res] == list(range(10))
     _check_log(s, res, 3, budget)
@@ -56,19 +81,21 @@ def test_slots_budget_and_order():
 def test_late_arrival_overtakes_a_long_request():
     long_req = Request(0, 1024, 2.0, 0, 0, 1, 0.0)      # 0.16 s
     shorts = [Request(i, 128, 2.0, 0, 0, 1, 0.03 * i) for i in range(1, 4)]  # 0.02 s each
-    s = Server(fake_solve(), max_active=2, mem_budget=1 << 40, footprint=fp)
+    s = Server(FakeBackend(), max_active=2, mem_budget=1 << 40, footprint=fp)
     res = s.run([long_req] + shorts)
     done0 = res[0].done
     # every short request was admitted and finished while the long one ran
     for r in res[1:]:
         assert r.admitted < done0 and r.done < done0
     assert s.peak_active == 2
+    # the short requests shared ticks with the long one
+    assert s.ticks < sum(round(0.02 * r.n / 128 / 0.002) for r in [long_req] + shorts)
 
 
 def test_closed_loop_and_summary():
     reqs = make_requests(6, sizes=(128, 256), rate=None, nrhs=2, seed=1)
     assert all(r.arrival == 0.0 for r in reqs)
-    s = Server(fake_solve(0.005), max_active=4, footprint=fp)
+    s = Server(FakeBackend(0.005), max_active=4, footprint=fp)
     t0 = time.perf_counter()
     res = s.run(reqs, realtime=False)
     wall = time.perf_counter() - t0
@@ -87,6 +114,6 @@ def test_poisson_stream_is_seeded():
 
 
 def test_request_larger_than_budget_is_rejected():
-    s = Server(fake_solve(), max_active=2, mem_budget=10, footprint=fp)
+    s = Server(FakeBackend(), max_active=2, mem_budget=10, footprint=fp)
     with pytest.raises(ValueError):
         s.run([Request(0, 128, 2.0, 0, 0, 1, 0.0)])
