@@ -485,6 +485,58 @@ def serve(args) -> int:
     return 0
 
 
+def mfma_ab(args) -> int:
+    """8-column applications of T with the reconstruction on the vector FMA
+    kernel (the default) and on the matrix cores (MRCM_MFMA_RECON=mfma, and
+    bf16 in FP32 mode): apply time and reconstruct phase time per variant,
+    1024^2 cells, subdomains of 16^2, log-normal sigma 2."""
+    import os
+
+    import torch
+
+    from paper_2606_08883_amd import binding as B
+    from paper_2606_08883_amd import workloads as wl
+    dev = torch.device("cuda", 0)
+    n, sub = 1024, 16
+    K = torch.tensor(wl.lognormal_K(n, n, 2.0, 16.0, 5), dtype=torch.float64, device=dev)
+    R = torch.tensor(np.stack([wl.random_vector(n * n, 10 + k, zero_mean=True) for k in range(8)]),
+                     dtype=torch.float64, device=dev).contiguous()
+    out = {}
+    for prec in (2, 1, 0):
+        for mode in ([None, "mfma", "bf16"] if prec == 1 else [None, "mfma"]):
+            if mode:
+                os.environ["MRCM_MFMA_RECON"] = mode
+            else:
+                os.environ.pop("MRCM_MFMA_RECON", None)
+            ctx = B.Context(B.Config(n, n, (0, 0, 0, 0), sub, sub, 4, 10.0, 0, 1, 2, 1, prec), K)
+            Z = torch.empty_like(R)
+            for _ in range(args.warmup):
+                ctx.apply(R, Z)
+            torch.cuda.synchronize()
+            ctx.timing(True)
+            for _ in range(args.steps):
+                ctx.apply(R, Z)
+            torch.cuda.synchronize()
+            ph = ctx.timing_read()
+            ctx.timing(False)
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                ctx.apply(R, Z)
+            torch.cuda.synchronize()
+            key = f"{DTYPES[prec]} {mode or 'fma'}"
+            out[key] = {"apply_ms": 1e3 * (time.perf_counter() - t0) / args.steps,
+                        "reconstruct_ms": ph["reconstruct"][0] / max(1, ph["reconstruct"][1]),
+                        "mfma_recon": ctx.query("mfma_recon")}
+            print(f"bench: {key}: {out[key]}", file=sys.stderr, flush=True)
+            ctx.close()
+    os.environ.pop("MRCM_MFMA_RECON", None)
+    print(json.dumps({"metric": "8-column applications of T, reconstruction FMA vs MFMA",
+                      "config": {"workload": "1024x1024 cells, subdomains of 16x16, oversampling "
+                                             "4, one sweep, log-normal sigma 2, 8 columns"},
+                      "variants": out}), flush=True)
+    return 0
+
+
 INCLUSION_ROWS = [("MRCM", 0, 0), ("2h", 2, 0), ("4h", 4, 0), ("2h,2S", 2, 2), ("2h,4S", 2, 4),
                   ("4h,2S", 4, 2), ("4h,4S", 4, 4)]
 
@@ -551,6 +603,9 @@ def main() -> int:
                          "oversampling / smoothing row of the paper's inclusion tables")
     ap.add_argument("--requests", type=int, default=512, help="requests of the serving run")
     ap.add_argument("--max-active", type=int, default=8, help="serving slots")
+    ap.add_argument("--mfma-ab", action="store_true",
+                    help="time 8-column applications with the reconstruction on the FMA kernel "
+                         "and on the matrix cores")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB, as a runtime copy and "
                          "as an elementwise kernel (known-size kernels that scale the "
@@ -578,6 +633,8 @@ def main() -> int:
 
     if args.serve:
         return serve(args)
+    if args.mfma_ab:
+        return mfma_ab(args)
     if args.inclusions:
         return inclusions(args)
 

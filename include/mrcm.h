@@ -314,7 +314,16 @@ int mrcm_timing_read(mrcm_ctx* ctx, double* ms, int64_t* counts);
  *                         with the factor misses on a fixed right-hand side
  *                         and takes steps until a correction is below 1e-10
  *                         of the solution in precision mode 0, 1e-6 in modes
- *                         1 and 2 (at most four). */
+ *                         1 and 2 (at most four);
+ *  MRCM_Q_MFMA_RECON      1 when the reconstruction of 8-column applications
+ *                         runs on the matrix cores in the arithmetic type, 2
+ *                         with BF16 inputs and FP32 accumulation, 0 with the
+ *                         vector FMA kernel (the default).  Set at mrcm_setup
+ *                         from MRCM_MFMA_RECON=mfma|bf16 in the environment
+ *                         (interface degree <= 1; bf16 needs precision mode
+ *                         1, else mfma is used); its sums round differently,
+ *                         so 8-column results then differ from one-column
+ *                         results in rounding. */
 enum {
   MRCM_Q_SETUP_SECONDS = 0,
   MRCM_Q_DEVICE_BYTES = 1,
@@ -325,7 +334,8 @@ enum {
   MRCM_Q_COARSE_LAUNCHES = 6,
   MRCM_Q_TUNE_MS = 7,
   MRCM_Q_TUNE_CHANGES = 8,
-  MRCM_Q_COARSE_REFINE = 9
+  MRCM_Q_COARSE_REFINE = 9,
+  MRCM_Q_MFMA_RECON = 10
 };
 int mrcm_query(mrcm_ctx* ctx, int32_t what, double* value);
 

@@ -31,7 +31,7 @@ EXPORTED = ["mrcm_map_sizes", "mrcm_maps", "mrcm_setup", "mrcm_apply", "mrcm_app
             "mrcm_last_error"]
 QUERIES = {"setup_seconds": 0, "device_bytes": 1, "coarse_pivot": 2, "coarse_levels": 3,
            "coarse_dofs": 4, "coarse_bytes": 5, "coarse_launches": 6, "tune_ms": 7,
-           "tune_changes": 8, "coarse_refine": 9}
+           "tune_changes": 8, "coarse_refine": 9, "mfma_recon": 10}
 PHASES = ["local", "coarse", "reconstruct", "residual", "patch", "finalize"]
 TEST_EXPORTED = ["mrcm_test_coarse_sizes", "mrcm_test_coarse_matrix", "mrcm_test_host_apply",
                  "mrcm_test_coarse_solve"]

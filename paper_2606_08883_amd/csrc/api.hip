@@ -194,6 +194,10 @@ struct mrcm_ctx {
   // groups per workgroup of the box kernels (0: the most that fit).
   std::vector<int> fwd_threads, bwd_threads;
   int local_groups = 0, patch_groups = 0;
+  // Reconstruction of 8-column applications on the matrix cores (0: the
+  // FMA kernel; 1: MFMA of the arithmetic type; 2: BF16 MFMA, FP32
+  // arithmetic only), from MRCM_MFMA_RECON=mfma|bf16 at set-up.
+  int mfma_recon = 0;
   double tune_ms = 0.0;   // time the autotuner spent in this set-up
   int tune_changes = 0;   // choices that differ from the defaults
   size_t tsize = 8;  // bytes of the arithmetic / work-vector type
@@ -829,6 +833,11 @@ void apply_k(mrcm_ctx* c, mrcm_ctx::Batch& B, int k, const double* const* r, dou
     }
     end(1);
     begin();
+    if (c->mfma_recon && k == 8)
+      mrcm::launch_reconstruct_mfma<T, S>(c->mfma_recon, c->lbox, c->m,
+                                          static_cast<const S*>(c->mbf), c->mbf_off, c->dof_off,
+                                          B.xc, c->nc, p, c->nx, s);
+    else
     mrcm::launch_reconstruct_k<T, S>(k, c->lbox, c->m, static_cast<const S*>(c->mbf), c->mbf_off,
                                      c->dof_off, B.xc, c->nc, p, c->nx, s);
     end(2);
@@ -1479,6 +1488,13 @@ int mrcm_setup(const mrcm_grid* grid, const mrcm_params* params, const double* K
     c->noflow = S.noflow ? 1 : 0;
     c->precision = params->precision;
     c->sweeps = params->smooth_sweeps;
+    if (const char* mf = std::getenv("MRCM_MFMA_RECON")) {
+      // at most 8 basis functions per subdomain (degree <= 1)
+      if (params->iface_degree <= 1 && params->iface_degree >= 0) {
+        if (std::strcmp(mf, "mfma") == 0) c->mfma_recon = 1;
+        if (std::strcmp(mf, "bf16") == 0) c->mfma_recon = params->precision == 1 ? 2 : 1;
+      }
+    }
     c->m = S.maps.m;
     c->nc = S.maps.nc();
     c->n = (long long)n;
@@ -2485,6 +2501,7 @@ int mrcm_query(mrcm_ctx* c, int32_t what, double* value) {
       case MRCM_Q_TUNE_MS: *value = c->tune_ms; break;
       case MRCM_Q_TUNE_CHANGES: *value = c->tune_changes; break;
       case MRCM_Q_COARSE_REFINE: *value = c->refine; break;
+      case MRCM_Q_MFMA_RECON: *value = c->mfma_recon; break;
       default: throw mrcm::Error(MRCM_EINVAL, "unknown query");
     }
     return MRCM_OK;

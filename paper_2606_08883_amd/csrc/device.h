@@ -136,6 +136,14 @@ template <typename T, typename S>
 void launch_reconstruct_k(int k, const BoxDesc* boxes, int m, const S* mbf,
                           const long long* mbf_off, const int* dof_off, const double* xc, int nc,
                           T* const* p, int nx, hipStream_t s);
+// The reconstruction of 8 right-hand sides on the matrix cores (mode 1:
+// the MFMA of the arithmetic type, FP32 or FP64; mode 2: BF16 inputs with
+// FP32 accumulation, FP32 arithmetic only); rounding differs from
+// launch_reconstruct_k.
+template <typename T, typename S>
+void launch_reconstruct_mfma(int mode, const BoxDesc* boxes, int m, const S* mbf,
+                             const long long* mbf_off, const int* dof_off, const double* xc,
+                             int nc, T* const* p, int nx, hipStream_t s);
 template <typename T>
 void launch_residual_k(int k, const T* tx, const T* ty, int nx, int ny, const double* const* r,
                        const T* const* p, T* const* rho, hipStream_t s);

@@ -1781,6 +1781,93 @@ __global__ void __launch_bounds__(kBoxThreads)
   }
 }
 
+// k_reconstruct_k for 8 right-hand sides on the matrix cores: per
+// subdomain, P_i^T (cells x nk, nk <= 8 basis functions) times X (nk x 8
+// columns) is added to the 8 columns of p[Omega_i] in tiles of 16 cells, one
+// wave per tile, as a 16 x 16 x 8 product (columns 8..15 and basis functions
+// past nk are zero).  MfmaRecon selects the instruction: 0 the FP32 or FP64
+// 16x16x4 MFMA of the arithmetic type (two steps of four basis functions);
+// 1 the BF16 16x16x16 MFMA with FP32 accumulation (P and X rounded to BF16,
+// nearest even; FP32 arithmetic only).  The sums are those of the MFMA, not
+// of k_reconstruct_k's FMA chain, so results differ from it in rounding.
+// MFMA 16 x 16 operand layout: lane l holds A[l % 16][l / 16] (cells x
+// basis functions), B[l / 16][l % 16] (basis functions x columns), and in
+// accumulator register r row 4 (l / 16) + r of column l % 16 (FP32 and
+// BF16 forms) or row 4 r + l / 16 (FP64 form); the BF16 form holds four
+// consecutive k per lane (k = 4 (l / 16) .. + 3).
+typedef float mfma_f32x4 __attribute__((ext_vector_type(4)));
+typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
+typedef short mfma_s16x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ short bf16_rne(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+template <typename T, int MODE> struct MfmaAcc;
+template <> struct MfmaAcc<float, 0> { typedef mfma_f32x4 type; };
+template <> struct MfmaAcc<float, 1> { typedef mfma_f32x4 type; };
+template <> struct MfmaAcc<double, 0> { typedef mfma_f64x4 type; };
+
+template <typename T, typename S, int MODE>
+__global__ void __launch_bounds__(kBoxThreads)
+    k_reconstruct_mfma(const BoxDesc* __restrict__ boxes, const S* __restrict__ mbf,
+                       const long long* __restrict__ mbf_off, const int* __restrict__ dof_off,
+                       const double* __restrict__ xc, int nc, RhsPtrs<T> p, int nx) {
+  typedef typename MfmaAcc<T, MODE>::type Acc;
+  __shared__ T xs[16][16];
+  const int i = blockIdx.x;
+  const BoxDesc d = boxes[i];
+  const int k0 = dof_off[i], nk = dof_off[i + 1] - k0, ncell = d.obx * d.oby;
+  for (int e = threadIdx.x; e < 16 * 16; e += blockDim.x) {
+    const int k = e / 16, j = e % 16;
+    xs[k][j] = (k < nk && k < 8 && j < 8) ? (T)xc[(long long)j * nc + k0 + k] : T(0);
+  }
+  __syncthreads();
+  const S* P = mbf + mbf_off[i];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  T* pj = p.v[li < 8 ? li : 0];
+  const long long base = (long long)(d.y0 + d.oy) * nx + d.x0 + d.ox;
+  for (int t = wid; t * 16 < ncell; t += nw) {
+    const int q = 16 * t + li;
+    long long addr[4];
+    bool ok[4];
+    Acc c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int qq = 16 * t + (sizeof(T) == 8 ? 4 * r + lk : 4 * lk + r);
+      ok[r] = li < 8 && qq < ncell;
+      const int qc = qq < ncell ? qq : 0;
+      const int row = qc / d.obx, col = qc - row * d.obx;
+      addr[r] = base + (long long)row * nx + col;
+      c[r] = ok[r] ? pj[addr[r]] : T(0);
+    }
+    if constexpr (MODE == 0) {
+#pragma unroll
+      for (int s4 = 0; s4 < 2; ++s4) {
+        const int k = 4 * s4 + lk;
+        const T a = (k < nk && q < ncell) ? (T)P[(long long)k * ncell + q] : T(0);
+        const T b = xs[k][li];
+        if constexpr (sizeof(T) == 4)
+          c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+        else
+          c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+      }
+    } else {
+      mfma_s16x4 a, b;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = 4 * lk + u;
+        a[u] = bf16_rne((k < nk && q < ncell) ? (float)P[(long long)k * ncell + q] : 0.0f);
+        b[u] = bf16_rne((float)xs[k][li]);
+      }
+      c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (ok[r]) pj[addr[r]] = c[r];
+  }
+}
+
 // Smoothing residuals rho_k = r_k - A p_k (blockIdx.y = k).
 template <typename T>
 __global__ void __launch_bounds__(kVecThreads)
@@ -2170,6 +2257,22 @@ void launch_reconstruct_k(int k, const BoxDesc* boxes, int m, const S* mbf,
                                         s, boxes, mbf, mbf_off, dof_off, xc, nc, pp, nx));
 }
 
+template <typename T, typename S>
+void launch_reconstruct_mfma(int mode, const BoxDesc* boxes, int m, const S* mbf,
+                             const long long* mbf_off, const int* dof_off, const double* xc,
+                             int nc, T* const* p, int nx, hipStream_t s) {
+  const RhsPtrs<T> pp = rhs_ptrs(8, p);
+  if constexpr (sizeof(T) == 4) {
+    if (mode == 2) {
+      hipLaunchKernelGGL((k_reconstruct_mfma<T, S, 1>), dim3(m), dim3(kBoxThreads), 0, s, boxes,
+                         mbf, mbf_off, dof_off, xc, nc, pp, nx);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_reconstruct_mfma<T, S, 0>), dim3(m), dim3(kBoxThreads), 0, s, boxes, mbf,
+                     mbf_off, dof_off, xc, nc, pp, nx);
+}
+
 template <typename T>
 void launch_residual_k(int k, const T* tx, const T* ty, int nx, int ny, const double* const* r,
                        const T* const* p, T* const* rho, hipStream_t s) {
@@ -2534,6 +2637,9 @@ void launch_gather(const GatherItem* items, int count, double* stage, hipStream_
   template void launch_reconstruct_k<T, S>(int, const BoxDesc*, int, const S*,                  \
                                            const long long*, const int*, const double*, int,    \
                                            T* const*, int, hipStream_t);                        \
+  template void launch_reconstruct_mfma<T, S>(int, const BoxDesc*, int, const S*,               \
+                                              const long long*, const int*, const double*, int, \
+                                              T* const*, int, hipStream_t);                     \
   template void launch_patch_k<T, S>(int, const BoxDesc*, int, int, int, const S*, const S*,    \
                                      const T* const*, T* const*, T* const*, int, hipStream_t); \
   template void launch_local_many<T, S>(const ManyCol*, const int*, int, int, int, int,         \
