@@ -332,7 +332,7 @@ def cpu_baseline(w, gpu_iterations: float, window: int = 512) -> dict:
 import json, sys, time
 import numpy as np
 sys.path.insert(0, %r)
-from oracle.discretization import rhs
+from oracle.discretization import direct_solve, rhs
 from oracle.gmres import gmres
 from oracle.mrcm import MRCM
 from paper_2606_08883_amd.configs import WORKLOADS
@@ -351,8 +351,11 @@ else:
 t0 = time.perf_counter()
 res = gmres(lambda x: mr.A @ x, mr.apply, b, rtol=1e-8, restart=10, maxit=300)
 t_solve = time.perf_counter() - t0
+t0 = time.perf_counter()
+direct_solve(mr.A, b, w.bc)
+t_splu = time.perf_counter() - t0
 print(json.dumps({"setup_s": t_setup, "solve_s": t_solve, "its": res.iterations,
-                  "converged": res.converged}))
+                  "converged": res.converged, "splu_s": t_splu}))
 """ % (ROOT, w.name, window)
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
@@ -390,6 +393,11 @@ print(json.dumps({"setup_s": t_setup, "solve_s": t_solve, "its": res.iterations,
         model = platform.processor() or "unknown"
     return {"value": 1.0 / solve_est_all, "unit": "solves/s", "cores": cores, "kind": "oracle",
             "single_core_solves_per_s": 1.0 / solve_est_1,
+            "splu_window_s": one["splu_s"],
+            "splu_note": (f"scipy splu (SuperLU, COLAMD ordering) direct solve of the same "
+                          f"{window}x{window} window on one core, for reference: "
+                          f"{one['splu_s']:.2f} s; its fill grows faster than the cell count, "
+                          f"so it is not scaled to the workload"),
             "cpu_model": model, "nproc": os.cpu_count(),
             "sample": (f"the oracle (NumPy/SciPy FP64, one thread per process) on the "
                        f"{window}x{window} bottom-left window of the same field and method "

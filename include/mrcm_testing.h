@@ -40,6 +40,15 @@ int mrcm_test_host_apply(const mrcm_grid* grid, const mrcm_params* params, const
 int mrcm_test_coarse_solve(const mrcm_grid* grid, const mrcm_params* params, const double* K,
                            const double* g, double* x);
 
+/* Failure injection for MRCM_ESINGULAR: validate K as
+ * mrcm_setup does, then set K = 0 on one cell and factor every local and
+ * patch box on the host (Section 2.1, the local problems).  A cell with
+ * K = 0 has no conductance on any face, so its box matrix has a zero row and
+ * the block LDL^T meets a zero pivot: MRCM_ESINGULAR.  Returns MRCM_OK when
+ * every factorisation succeeds, MRCM_EINVAL for a bad cell index. */
+int mrcm_test_zero_cell_setup(const mrcm_grid* grid, const mrcm_params* params,
+                              const double* K, int64_t cell);
+
 #ifdef __cplusplus
 }
 #endif

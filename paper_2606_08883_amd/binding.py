@@ -34,7 +34,7 @@ QUERIES = {"setup_seconds": 0, "device_bytes": 1, "coarse_pivot": 2, "coarse_lev
            "tune_changes": 8, "coarse_refine": 9, "mfma_recon": 10}
 PHASES = ["local", "coarse", "reconstruct", "residual", "patch", "finalize"]
 TEST_EXPORTED = ["mrcm_test_coarse_sizes", "mrcm_test_coarse_matrix", "mrcm_test_host_apply",
-                 "mrcm_test_coarse_solve"]
+                 "mrcm_test_coarse_solve", "mrcm_test_zero_cell_setup"]
 
 
 class MrcmError(RuntimeError):
@@ -112,6 +112,7 @@ def lib() -> ctypes.CDLL:
             "mrcm_test_coarse_matrix": ([pG, pP, pd, pi32, pi32, pd], i32),
             "mrcm_test_host_apply": ([pG, pP, pd, pd, pd, pd], i32),
             "mrcm_test_coarse_solve": ([pG, pP, pd, pd, pd], i32),
+            "mrcm_test_zero_cell_setup": ([pG, pP, pd, i64], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -229,6 +230,13 @@ def test_coarse_solve(cfg: Config, K: np.ndarray, rhs: np.ndarray) -> np.ndarray
 
 # ---- device entry points --------------------------------------------------------
 _allocator = None  # the callback objects in use (kept alive while installed)
+
+
+def test_zero_cell_setup(cfg: Config, K: np.ndarray, cell: int) -> None:
+    """Host set-up with K = 0 on one cell after validation (failure injection)."""
+    g, p = cfg.grid(), cfg.params()
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    _check(lib().mrcm_test_zero_cell_setup(ctypes.byref(g), ctypes.byref(p), _f64(K), cell))
 
 
 def set_allocator(alloc=None, release=None):

@@ -30,6 +30,27 @@ mrcm::HostSetup make_setup(const mrcm_grid* g, const mrcm_params* p, const doubl
 
 extern "C" {
 
+int mrcm_test_zero_cell_setup(const mrcm_grid* grid, const mrcm_params* params,
+                              const double* K, int64_t cell) {
+  try {
+    if (!grid || !params || !K) throw mrcm::Error(MRCM_EINVAL, "null argument");
+    if (cell < 0 || cell >= (int64_t)grid->nx * grid->ny)
+      throw mrcm::Error(MRCM_EINVAL, "cell out of range");
+    mrcm::HostSetup S;
+    mrcm::host_prepare(S, *grid, *params, K);  // validates K
+    S.K[(size_t)cell] = 0.0;                    // the degenerate cell, after validation
+    mrcm::face_transmissibilities(S);
+    const mrcm::Maps& M = S.maps;
+    for (int i = 0; i < M.m; ++i) {
+      if (S.sweeps > 0) (void)mrcm::factor_box(S, M.pboxes[i], false);
+      (void)mrcm::factor_box(S, M.oboxes[i], true);
+    }
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    return fail(e);
+  }
+}
+
 int mrcm_test_coarse_sizes(const mrcm_grid* grid, const mrcm_params* params, const double* K,
                            int64_t* nc, int64_t* nnz) {
   try {

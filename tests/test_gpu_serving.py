@@ -254,6 +254,39 @@ def test_caller_allocator(dev):
     assert torch.equal(z0, z1)
 
 
+def test_failing_allocator_reports_enomem(dev):
+    """Failure injection: a caller allocator that returns NULL part-way
+    through the set-up makes mrcm_setup fail with MRCM_ENOMEM, and every
+    allocation it had made is returned."""
+    cfg = S.config_for(128)
+    K = torch.tensor(wl.lognormal_K(128, 128, 2.0, 16.0, 62), dtype=torch.float64, device=dev)
+    ta, tf = B.torch_allocator(0)
+    calls = {"alloc": 0, "ok": 0, "free": 0}
+
+    def alloc(nbytes, stream):
+        calls["alloc"] += 1
+        if calls["alloc"] > 6:
+            return None
+        calls["ok"] += 1
+        return ta(nbytes, stream)
+
+    def release(ptr, stream):
+        calls["free"] += 1
+        tf(ptr, stream)
+
+    B.set_allocator(alloc, release)
+    try:
+        with pytest.raises(B.MrcmError) as e:
+            B.Context(cfg, K)
+    finally:
+        B.set_allocator(None, None)
+    print(f"  allocator calls {calls}", flush=True)
+    assert e.value.code == B.MRCM_ENOMEM
+    assert calls["ok"] == 6 and calls["free"] == calls["ok"]
+    ctx = B.Context(cfg, K)   # the library is usable afterwards
+    ctx.close()
+
+
 @pytest.mark.parametrize("precision,n,nrhs,lanes,width",
                          [(2, 256, 6, 4, 1), (0, 128, 3, 2, 1), (2, 256, 7, 1, 8), (2, 256, 9, 2, 4),
                           (1, 128, 5, 2, 2), (0, 128, 4, 1, 4)])

@@ -123,6 +123,22 @@ def test_host_setup_rejects_bad_permeability():
         B.test_host_apply(cfg, K, np.zeros(256))
 
 
+@pytest.mark.parametrize("cell", [20 * 48 + 25, 0, 48 * 40 - 1])
+def test_zero_permeability_cell_is_a_singular_local_problem(cell):
+    """Failure injection: K = 0 on one cell (after validation) leaves its
+    row of the local matrix empty, and the factorisation reports
+    MRCM_ESINGULAR (interior cell, corner cells)."""
+    cfg = B.Config(48, 40, (1, 1, 0, 0), 12, 12, 2, 10.0, 0, 1, 2, 1, 0)
+    K = wl.lognormal_K(48, 40, 1.0, 4.0, 3)
+    with pytest.raises(B.MrcmError) as e:
+        B.test_zero_cell_setup(cfg, K, cell)
+    assert e.value.code == B.MRCM_ESINGULAR
+    assert "pivot" in str(e.value)
+    with pytest.raises(B.MrcmError) as e:
+        B.test_zero_cell_setup(cfg, K, 48 * 40)
+    assert e.value.code == B.MRCM_EINVAL
+
+
 def test_set_host_threads():
     """mrcm_set_host_threads is per calling thread and rejects negative counts
     (host only; no device is touched)."""
