@@ -222,9 +222,10 @@ int gmres_batch_create(int32_t restart, mrcm_batch** out);
 /* Add the nrhs right-hand sides b of a context (device [nrhs][n]); their
  * solutions are written to p (device [nrhs][n]) as they progress.  b, the
  * context and p are used after the work `stream` holds when the call is
- * made.  The batch allocates each right-hand side's Krylov space and work
- * space from the context (released by mrcm_destroy); the context must
- * outlive the tag.  *tag receives the handle of the group. */
+ * made.  Each right-hand side's Krylov space and work space come from the
+ * context: buffers of the context's removed tags with the same restart
+ * length are reused, others are allocated (all released by mrcm_destroy).
+ * The context must outlive the tag.  *tag receives the handle of the group. */
 int gmres_batch_add(mrcm_batch* batch, mrcm_ctx* ctx, const double* b, double* p,
                     int32_t nrhs, double rtol, int32_t maxit, void* stream, int32_t* tag);
 /* One tick; *active receives the right-hand sides not yet finished. */

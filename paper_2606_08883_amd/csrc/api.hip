@@ -265,6 +265,15 @@ struct mrcm_ctx {
     double *rnd = nullptr, *dx = nullptr, *contrib = nullptr, *partials = nullptr;
   };
   std::vector<Column> columns;
+  // Work space of batched-GMRES right-hand sides of removed tags, kept for
+  // the next tags of this context: the column, the Krylov space of the
+  // batch's restart length and the small vectors.
+  struct RunSpace {
+    Column w;
+    int restart = 0;
+    double *V = nullptr, *Z = nullptr, *hcol = nullptr, *parts = nullptr, *yd = nullptr;
+  };
+  std::vector<RunSpace> run_pool;
   // Column tables of the mrcm_apply_many calls this context leads.
   std::unique_ptr<ManyTables> many;
   // cells of all oversampled boxes or of all smoothing patches, the larger
@@ -2214,12 +2223,24 @@ int gmres_batch_add(mrcm_batch* B, mrcm_ctx* c, const double* b, double* p, int3
       R->tag = id;
       R->b = b + (size_t)k * n;
       R->p = p + (size_t)k * n;
-      R->w = make_column(c, B->st);
-      R->V = c->alloc<double>((size_t)(B->restart + 1) * n);
-      R->Z = c->alloc<double>((size_t)B->restart * n);
-      R->hcol = c->alloc<double>(B->restart + 2);
-      R->parts = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
-      R->yd = c->alloc<double>(B->restart + 1);
+      auto pooled = std::find_if(c->run_pool.begin(), c->run_pool.end(),
+                                 [&](const mrcm_ctx::RunSpace& q) { return q.restart == B->restart; });
+      if (pooled != c->run_pool.end()) {
+        R->w = pooled->w;
+        R->V = pooled->V;
+        R->Z = pooled->Z;
+        R->hcol = pooled->hcol;
+        R->parts = pooled->parts;
+        R->yd = pooled->yd;
+        c->run_pool.erase(pooled);
+      } else {
+        R->w = make_column(c, B->st);
+        R->V = c->alloc<double>((size_t)(B->restart + 1) * n);
+        R->Z = c->alloc<double>((size_t)B->restart * n);
+        R->hcol = c->alloc<double>(B->restart + 2);
+        R->parts = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
+        R->yd = c->alloc<double>(B->restart + 1);
+      }
       hip_check(hipHostMalloc((void**)&R->h_y, sizeof(double) * (B->restart + 1),
                               hipHostMallocDefault),
                 "hipHostMalloc");
@@ -2361,7 +2382,18 @@ int gmres_batch_remove(mrcm_batch* B, int32_t tag) {
     auto& runs = B->runs;
     for (auto r = runs.begin(); r != runs.end();) {
       if ((*r)->tag == tag) {
-        if ((*r)->h_y) (void)hipHostFree((*r)->h_y);
+        Run& R = **r;
+        if (R.h_y) (void)hipHostFree(R.h_y);
+        // the buffers go back to the context for its next tags
+        mrcm_ctx::RunSpace q;
+        q.w = R.w;
+        q.restart = B->restart;
+        q.V = R.V;
+        q.Z = R.Z;
+        q.hcol = R.hcol;
+        q.parts = R.parts;
+        q.yd = R.yd;
+        R.c->run_pool.push_back(q);
         r = runs.erase(r);
       } else {
         ++r;

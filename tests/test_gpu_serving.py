@@ -162,6 +162,22 @@ def test_batch_equals_gmres_solve(dev):
         batch.remove(tags[i])
     with pytest.raises(B.MrcmError):
         batch.poll(tags[0])
+    # a second round on the same contexts reuses the removed tags' buffers
+    held = [c.query("device_bytes") for c in ctxs]
+    again = {}
+    for i in (0, 3, 4):
+        ps[i].fill_(-2.0)
+        again[i] = batch.add(ctxs[i], bs[i], ps[i], rtol=1e-8, maxit=400)
+    while batch.tick() > 0:
+        pass
+    for i, t in again.items():
+        st = batch.poll(t)
+        p1 = torch.zeros_like(bs[i])
+        s1 = ctxs[i].gmres(bs[i], p1, rtol=1e-8, restart=10, maxit=400)
+        torch.cuda.synchronize()
+        assert st.iterations == s1.iterations and torch.equal(p1, ps[i])
+        batch.remove(t)
+    assert [c.query("device_bytes") for c in ctxs] == held
     batch.close()
     for c in ctxs:
         c.close()
