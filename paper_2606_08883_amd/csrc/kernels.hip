@@ -338,16 +338,17 @@ __device__ __forceinline__ void zero_slots(T* v, int count, int lane) {
 }
 
 // Block LDL^T solve of one box by a group; us holds b on entry and x on exit
-// (by rows of bx words, LDS); cp holds the couplings T_j (LDS); vv is the
-// group's vector slot (vec_words, zeroed); g0 the group's first lane in the
-// wave.  S is the storage type of the factors, T the arithmetic and vector
+// in rows stop .. by - 1 (by rows of bx words, LDS; the backward pass ends at
+// row stop, the first row the caller reads, and rows below it keep their
+// forward values); cp holds the couplings T_j (LDS); vv is the group's vector
+// slot (vec_words, zeroed); g0 the group's first lane in the wave.  S is the storage type of the factors, T the arithmetic and vector
 // type (FP32 factors may be applied in FP64 arithmetic).  Lanes at or past
 // bx (and whole groups with live = false) take part in every step but read
 // only inside the box and write nothing outside their slot.
 template <typename T, typename S, int NB, int GS>
 __device__ __forceinline__ void box_solve(T* us, T* vv, const S* cp, const S* __restrict__ Dinv,
                                           int bx, int by, int bstride, int r, int g0,
-                                          bool live) {
+                                          bool live, int stop) {
   constexpr int H = Half<NB>::H;
   constexpr int DEPTH = reg_depth<S, NB>();
   const bool act = live && r < bx;
@@ -374,8 +375,8 @@ __device__ __forceinline__ void box_solve(T* us, T* vv, const S* cp, const S* __
         carry = w ? acc : carry;
       },
       Dinv, bstride, bx, rc);
-  // carry = x_{by-1} = u_{by-1}
-  const int nb = live && by > 1 ? by - 1 : 0;
+  // carry = x_{by-1} = u_{by-1}; rows by - 2 down to stop
+  const int nb = live && by - 1 - stop > 0 ? by - 1 - stop : 0;
   pipelined_sweep<S, NB, DEPTH>(
       nb, wave_steps<DEPTH>(nb), [by](int s) { return by - 2 - s; },
       [&](int s, const HalfRow<S, NB>& d, bool valid) {
@@ -565,8 +566,9 @@ __device__ __forceinline__ void local_body(
   wave_sync();
   if (live && d.pin && lane == 0) L.us[0] = T(0);
   wave_sync();
+  // rows from the one across Omega_i's south side (its traces) upward
   box_solve<T, S, NB, GS>(L.us, L.vv, L.cp, dinv + d.doff, bx, by, d.bs, lane,
-                         (threadIdx.x & 63) - lane, live);
+                         (threadIdx.x & 63) - lane, live, d.oy > 0 ? d.oy - 1 : 0);
   wave_sync();
   if (live && lane >= d.ox && lane < d.ox + d.obx) {
     const long long o2 = origin + (long long)d.oy * nx;
@@ -981,8 +983,9 @@ __device__ __forceinline__ void patch_body(const Blk blk, const BoxDesc* __restr
   wave_sync();
   if (live && d.pin && lane == 0) L.us[0] = T(0);
   wave_sync();
+  // the owned rows upward
   box_solve<T, S, NB, GS>(L.us, L.vv, L.cp, dinv + d.doff, bx, by, d.bs, lane,
-                         (threadIdx.x & 63) - lane, live);
+                         (threadIdx.x & 63) - lane, live, d.oy);
   wave_sync();
   // p += e on the owned cells, sixteen rows of read-modify-write in flight
   const bool own = live && lane >= d.ox && lane < d.ox + d.obx;
@@ -1371,13 +1374,14 @@ __device__ __forceinline__ void group_fence() {
 // the backward pass overwrites it with x_j.  The next step's rows are loaded
 // one step ahead.  vv holds the group's K vector slots (vec_words each,
 // zeroed), cp the couplings (LDS); g0 is the group's first lane in the wave;
-// pin zeroes b_0 in column 0 (a box fixed at its first cell).
+// pin zeroes b_0 in column 0 (a box fixed at its first cell); the backward
+// pass ends at row stop, as in box_solve.
 template <typename T, typename S, int NB, int GS, int K, typename In>
 __device__ __forceinline__ void box_solve_k(const In* const (&in)[K], long long istride,
                                             T* const (&work)[K], long long wstride, T* vv,
                                             const S* cp, const S* __restrict__ Dinv, int bx,
                                             int by, int bstride, int r, int g0, bool live,
-                                            bool pin) {
+                                            bool pin, int stop) {
   constexpr int H = Half<NB>::H, VW = vec_words<NB, GS>();
   constexpr int DEPTH = reg_depth_k<S, NB, K>();
   const bool act = live && r < bx;
@@ -1425,8 +1429,8 @@ __device__ __forceinline__ void box_solve_k(const In* const (&in)[K], long long 
       },
       Dinv, bstride, bx, rc);
   group_fence();
-  // carry = x_{by-1} = u_{by-1}
-  const int nb = live && by > 1 ? by - 1 : 0;
+  // carry = x_{by-1} = u_{by-1}; rows by - 2 down to stop
+  const int nb = live && by - 1 - stop > 0 ? by - 1 - stop : 0;
   auto u_row = [&](int s) {
     int j = by - 2 - s;
     j = j < 0 ? 0 : j;
@@ -1513,7 +1517,7 @@ __global__ void __launch_bounds__(kBoxThreads)
   wave_sync();
   box_solve_k<T, S, NB, GS, K, double>(in, nx, work, bx, L.vv, L.cp, dinv + d.doff, bx, by,
                                        d.bs, lane, (threadIdx.x & 63) - lane, live,
-                                       live && d.pin);
+                                       live && d.pin, d.oy > 0 ? d.oy - 1 : 0);
   if (!live) return;
   if (lane >= d.ox && lane < d.ox + d.obx) {
     const long long o2 = origin + (long long)d.oy * nx;
@@ -1564,7 +1568,7 @@ __global__ void __launch_bounds__(kBoxThreads)
   zero_slots<T, GS>(L.vv, K * vec_words<NB, GS>(), lane);
   wave_sync();
   box_solve_k<T, S, NB, GS, K, T>(in, nx, work, bx, L.vv, L.cp, dinv + d.doff, bx, by, d.bs,
-                                  lane, (threadIdx.x & 63) - lane, live, live && d.pin);
+                                  lane, (threadIdx.x & 63) - lane, live, live && d.pin, d.oy);
   // p += e on the owned cells, eight rows of read-modify-write in flight
   const bool own = live && lane >= d.ox && lane < d.ox + d.obx;
   const int col = own ? lane : d.ox;
