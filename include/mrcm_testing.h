@@ -12,6 +12,7 @@
 #include <stdint.h>
 
 #include "mrcm.h"
+#include "mrcm3d.h"
 
 #ifdef __cplusplus
 extern "C" {
@@ -48,6 +49,14 @@ int mrcm_test_coarse_solve(const mrcm_grid* grid, const mrcm_params* params, con
  * every factorisation succeeds, MRCM_EINVAL for a bad cell index. */
 int mrcm_test_zero_cell_setup(const mrcm_grid* grid, const mrcm_params* params,
                               const double* K, int64_t cell);
+
+/* z = T r on a 3-D grid (include/mrcm3d.h) evaluated on the host from the
+ * tables mrcm3d_setup uploads, in the order the device applies them (plane-
+ * block local solves, trace moments, the dense interface inverse with one
+ * refinement step, reconstruction, smoothing, projection).  K, r, z: host, n
+ * values; *nc (may be NULL) receives the interface unknowns. */
+int mrcm3d_test_host_apply(const mrcm3d_grid* grid, const mrcm3d_params* params,
+                           const double* K, const double* r, double* z, int64_t* nc);
 
 #ifdef __cplusplus
 }

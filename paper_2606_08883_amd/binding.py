@@ -27,6 +27,8 @@ EXPORTED = ["mrcm_map_sizes", "mrcm_maps", "mrcm_setup", "mrcm_apply", "mrcm_app
             "mrcm_set_host_threads",
             "gmres_batch_create", "gmres_batch_add", "gmres_batch_tick", "gmres_batch_poll",
             "gmres_batch_remove", "gmres_batch_destroy",
+            "mrcm3d_setup", "mrcm3d_apply", "mrcm3d_op_apply", "mrcm3d_gmres_solve",
+            "mrcm3d_timing_enable", "mrcm3d_timing_read", "mrcm3d_query", "mrcm3d_destroy",
             "mrcm_destroy",
             "mrcm_last_error"]
 QUERIES = {"setup_seconds": 0, "device_bytes": 1, "coarse_pivot": 2, "coarse_levels": 3,
@@ -34,7 +36,7 @@ QUERIES = {"setup_seconds": 0, "device_bytes": 1, "coarse_pivot": 2, "coarse_lev
            "tune_changes": 8, "coarse_refine": 9, "mfma_recon": 10}
 PHASES = ["local", "coarse", "reconstruct", "residual", "patch", "finalize"]
 TEST_EXPORTED = ["mrcm_test_coarse_sizes", "mrcm_test_coarse_matrix", "mrcm_test_host_apply",
-                 "mrcm_test_coarse_solve", "mrcm_test_zero_cell_setup"]
+                 "mrcm_test_coarse_solve", "mrcm_test_zero_cell_setup", "mrcm3d_test_host_apply"]
 
 
 class MrcmError(RuntimeError):
@@ -56,6 +58,18 @@ class Params(ctypes.Structure):
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Grid3(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("bc", ctypes.c_int32 * 6)]
+
+
+class Params3(ctypes.Structure):
+    _fields_ = [("sx", ctypes.c_int32), ("sy", ctypes.c_int32), ("sz", ctypes.c_int32),
+                ("oversample", ctypes.c_int32), ("alpha", ctypes.c_double),
+                ("beta_len", ctypes.c_int32), ("smooth_sweeps", ctypes.c_int32),
+                ("smooth_overlap", ctypes.c_int32), ("iface_degree", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -102,6 +116,17 @@ def lib() -> ctypes.CDLL:
             "mrcm_query": ([P, i32, pd], i32),
             "mrcm_destroy": ([P], None),
             "gmres_batch_create": ([i32, ctypes.POINTER(P)], i32),
+            "mrcm3d_setup": ([ctypes.POINTER(Grid3), ctypes.POINTER(Params3), P, P,
+                              ctypes.POINTER(P)], i32),
+            "mrcm3d_apply": ([P, P, P, P], i32),
+            "mrcm3d_op_apply": ([P, P, P, P], i32),
+            "mrcm3d_gmres_solve": ([P, P, P, dbl, i32, i32, ctypes.POINTER(Stats), P], i32),
+            "mrcm3d_timing_enable": ([P, i32], i32),
+            "mrcm3d_timing_read": ([P, pd, pi64], i32),
+            "mrcm3d_query": ([P, i32, pd], i32),
+            "mrcm3d_destroy": ([P], None),
+            "mrcm3d_test_host_apply": ([ctypes.POINTER(Grid3), ctypes.POINTER(Params3), pd, pd,
+                                        pd, pi64], i32),
             "gmres_batch_add": ([P, P, P, P, i32, dbl, i32, P, pi32], i32),
             "gmres_batch_tick": ([P, pi32], i32),
             "gmres_batch_poll": ([P, i32, pi32, ctypes.POINTER(Stats)], i32),
@@ -237,6 +262,103 @@ def test_zero_cell_setup(cfg: Config, K: np.ndarray, cell: int) -> None:
     g, p = cfg.grid(), cfg.params()
     K = np.ascontiguousarray(K, dtype=np.float64)
     _check(lib().mrcm_test_zero_cell_setup(ctypes.byref(g), ctypes.byref(p), _f64(K), cell))
+
+
+@dataclass
+class Config3:
+    """A 3-D grid and the method parameters (include/mrcm3d.h)."""
+    nx: int
+    ny: int
+    nz: int
+    bc: tuple
+    sx: int
+    sy: int
+    sz: int
+    oversample: int
+    alpha: float = 10.0
+    beta_len: int = 0
+    sweeps: int = 1
+    overlap: int = 2
+    degree: int = 1
+
+    def grid(self) -> Grid3:
+        return Grid3(self.nx, self.ny, self.nz, (ctypes.c_int32 * 6)(*self.bc))
+
+    def params(self) -> Params3:
+        return Params3(self.sx, self.sy, self.sz, self.oversample, self.alpha, self.beta_len,
+                       self.sweeps, self.overlap, self.degree)
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+def test3d_host_apply(cfg: Config3, K: np.ndarray, r: np.ndarray) -> tuple:
+    """z = T r on a 3-D grid from the host tables of mrcm3d_setup; (z, nc)."""
+    g, p = cfg.grid(), cfg.params()
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    z = np.empty(cfg.n)
+    nc = ctypes.c_int64()
+    _check(lib().mrcm3d_test_host_apply(ctypes.byref(g), ctypes.byref(p), _f64(K), _f64(r),
+                                        _f64(z), ctypes.byref(nc)))
+    return z, nc.value
+
+
+class Context3:
+    """A set-up 3-D MRCM-OS operator (mrcm3d_setup)."""
+
+    def __init__(self, cfg: Config3, K, stream=None):
+        self.cfg = cfg
+        self.n = cfg.n
+        self._ptr = ctypes.c_void_p()
+        self._g, self._p = cfg.grid(), cfg.params()
+        _check(lib().mrcm3d_setup(ctypes.byref(self._g), ctypes.byref(self._p),
+                                  _dptr(K, self.n), _stream(stream), ctypes.byref(self._ptr)))
+
+    def close(self):
+        if self._ptr:
+            lib().mrcm3d_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply(self, r, z, stream=None):
+        _check(lib().mrcm3d_apply(self._ptr, _dptr(r, self.n), _dptr(z, self.n), _stream(stream)))
+
+    def op(self, x, y, stream=None):
+        _check(lib().mrcm3d_op_apply(self._ptr, _dptr(x, self.n), _dptr(y, self.n),
+                                     _stream(stream)))
+
+    def gmres(self, b, p, rtol: float = 1e-8, restart: int = 10, maxit: int = 300,
+              stream=None, raise_on_noconv: bool = True) -> SolveStats:
+        st = Stats(0, 0, 0, 0, 0, 0, 0.0, None, None)
+        code = lib().mrcm3d_gmres_solve(self._ptr, _dptr(b, self.n), _dptr(p, self.n), rtol,
+                                        restart, maxit, ctypes.byref(st), _stream(stream))
+        if code != MRCM_OK and (code != MRCM_ENOCONV or raise_on_noconv):
+            _check(code)
+        return SolveStats(st.iterations, st.cycles, bool(st.converged), st.final_relres, [], [])
+
+    def timing(self, on: bool):
+        _check(lib().mrcm3d_timing_enable(self._ptr, 1 if on else 0))
+
+    def timing_read(self) -> dict:
+        ms = (ctypes.c_double * 6)()
+        cnt = (ctypes.c_int64 * 6)()
+        _check(lib().mrcm3d_timing_read(self._ptr, ms, cnt))
+        return {PHASES[k]: (ms[k], cnt[k]) for k in range(6)}
+
+    def query(self, what: str) -> float:
+        """setup_seconds, device_bytes, coarse_dofs, factor_bytes, cinv_bytes."""
+        idx = {"setup_seconds": 0, "device_bytes": 1, "coarse_dofs": 2, "factor_bytes": 3,
+               "cinv_bytes": 4}[what]
+        v = ctypes.c_double()
+        _check(lib().mrcm3d_query(self._ptr, idx, ctypes.byref(v)))
+        return v.value
 
 
 def set_allocator(alloc=None, release=None):

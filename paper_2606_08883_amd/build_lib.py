@@ -13,8 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmrcm.so")
-SOURCES = ["maps.cpp", "setup.cpp", "coarse.cpp", "testing.cpp", "kernels.hip", "setup_kernels.hip",
-           "api.hip"]
+SOURCES = ["maps.cpp", "setup.cpp", "coarse.cpp", "setup3d.cpp", "testing.cpp", "kernels.hip",
+           "setup_kernels.hip", "kernels3d.hip", "api.hip", "api3d.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CXX = os.environ.get("MRCM_CXX", "/opt/rocm/bin/amdclang++")

@@ -1,0 +1,518 @@
+// C ABI of the 3-D path (include/mrcm3d.h): set-up (host FP64 tables
+// uploaded to HBM), the preconditioner apply, the fine operator, and the
+// host-driven GMRES loop of Algorithm 1 with device-resident Krylov vectors
+// (the vector kernels of the 2-D path: Gram-Schmidt, normalisation, update,
+// norms, projection).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "device3d.h"
+#include "setup3d.h"
+
+namespace {
+
+void check3(hipError_t e, const char* what) {
+  if (e != hipSuccess)
+    throw mrcm::Error(e == hipErrorOutOfMemory ? MRCM_ENOMEM : MRCM_EDEVICE,
+                      std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+struct mrcm3d_ctx {
+  int nx = 0, ny = 0, nz = 0, m = 0, nc = 0, sweeps = 0, noflow = 0;
+  long long n = 0;
+  std::vector<void*> allocs;
+  size_t device_bytes = 0;
+  double setup_seconds = 0.0, factor_bytes = 0.0, cinv_bytes = 0.0;
+  double *tx = nullptr, *ty = nullptr, *tz = nullptr;
+  mrcm3d::Box3 *lbox = nullptr, *pbox = nullptr;
+  double *ldinv = nullptr, *lcoup = nullptr, *pdinv = nullptr, *pcoup = nullptr;
+  double* mbf = nullptr;
+  long long* mbf_off = nullptr;
+  int* dof_off = nullptr;
+  mrcm3d::Dof3* dofs = nullptr;
+  int *fin = nullptr, *fout = nullptr;
+  double* fw = nullptr;
+  int *rowL = nullptr, *rowR = nullptr, *rowKind = nullptr;
+  double* Cinv = nullptr;
+  int *crp = nullptr, *cci = nullptr;
+  double* cv = nullptr;
+  // work space of one application and of GMRES
+  double *p = nullptr, *rho = nullptr, *mU = nullptr, *mP = nullptr, *g = nullptr, *x = nullptr;
+  double *res = nullptr, *dx = nullptr, *partials = nullptr;
+  int krylov_cap = 0;
+  double *V = nullptr, *Z = nullptr, *hcol = nullptr, *parts = nullptr, *yd = nullptr;
+  double *h_fetch = nullptr, *h_y = nullptr;  // pinned
+  hipStream_t st = nullptr;
+  hipEvent_t ev_in = nullptr;
+  // per-phase timing: (phase, start, end)
+  bool timing = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+  double phase_ms[6] = {0, 0, 0, 0, 0, 0};
+  long long phase_n[6] = {0, 0, 0, 0, 0, 0};
+
+  template <typename X>
+  X* alloc(size_t count) {
+    void* q = nullptr;
+    const size_t bytes = ((count ? count : 1) * sizeof(X) + 255) / 256 * 256;
+    check3(hipMalloc(&q, bytes), "hipMalloc");
+    allocs.push_back(q);
+    device_bytes += bytes;
+    return static_cast<X*>(q);
+  }
+  template <typename X>
+  X* upload(const std::vector<X>& v) {
+    X* d = alloc<X>(v.size());
+    if (!v.empty())
+      check3(hipMemcpyAsync(d, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice, st),
+             "hipMemcpyAsync");
+    return d;
+  }
+  void fold() {
+    for (auto& mk : marks) {
+      float ms = 0.0f;
+      check3(hipEventSynchronize(mk.second.second), "hipEventSynchronize");
+      check3(hipEventElapsedTime(&ms, mk.second.first, mk.second.second), "hipEventElapsedTime");
+      phase_ms[mk.first] += ms;
+      phase_n[mk.first] += 1;
+      (void)hipEventDestroy(mk.second.first);
+      (void)hipEventDestroy(mk.second.second);
+    }
+    marks.clear();
+  }
+  ~mrcm3d_ctx() {
+    if (st) (void)hipStreamSynchronize(st);
+    for (auto& mk : marks) {
+      (void)hipEventDestroy(mk.second.first);
+      (void)hipEventDestroy(mk.second.second);
+    }
+    for (void* q : allocs) (void)hipFree(q);
+    if (h_fetch) (void)hipHostFree(h_fetch);
+    if (h_y) (void)hipHostFree(h_y);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (st) (void)hipStreamDestroy(st);
+  }
+};
+
+namespace {
+
+thread_local std::string g_err3;
+
+int fail3(const mrcm::Error& e) {
+  g_err3 = e.what();
+  mrcm::set_last_error(g_err3);
+  return e.code;
+}
+
+// Box descriptors and the concatenated factors of a list of boxes.
+void upload_boxes(mrcm3d_ctx* c, const mrcm3d::Setup& S, const std::vector<mrcm3d::Box>& boxes,
+                  const std::vector<mrcm3d::PlaneFactor>& F, mrcm3d::Box3*& dbox, double*& ddinv,
+                  double*& dcoup) {
+  std::vector<mrcm3d::Box3> desc(boxes.size());
+  std::vector<double> dinv, coup;
+  for (size_t i = 0; i < boxes.size(); ++i) {
+    const mrcm3d::Box& b = boxes[i];
+    const mrcm3d::Box& own = S.boxes[i];
+    mrcm3d::Box3& d = desc[i];
+    for (int a = 0; a < 3; ++a) {
+      d.lo[a] = b.lo[a];
+      d.n[a] = b.n(a);
+      d.olo[a] = own.lo[a] - b.lo[a];
+      d.on[a] = own.n(a);
+    }
+    d.P = b.plane();
+    d.pin = F[i].pin;
+    if (d.P > mrcm3d::kBox3Threads || b.cells() > mrcm3d::kMaxBox3Cells)
+      throw mrcm::Error(MRCM_EINVAL, "3-D box too large (at most 256 cells per z-plane and 4096 cells)");
+    d.doff = (long long)dinv.size();
+    d.coff = (long long)coup.size();
+    dinv.insert(dinv.end(), F[i].dinv.begin(), F[i].dinv.end());
+    coup.insert(coup.end(), F[i].coup.begin(), F[i].coup.end());
+  }
+  c->factor_bytes += 2.0 * 8.0 * (double)dinv.size();
+  dbox = c->upload(desc);
+  ddinv = c->upload(dinv);
+  dcoup = c->upload(coup);
+}
+
+void mark(mrcm3d_ctx* c, int phase, hipEvent_t a) {
+  hipEvent_t b;
+  check3(hipEventCreate(&b), "hipEventCreate");
+  check3(hipEventRecord(b, c->st), "hipEventRecord");
+  c->marks.push_back({phase, {a, b}});
+}
+hipEvent_t start_mark(mrcm3d_ctx* c) {
+  if (!c->timing) return nullptr;
+  hipEvent_t a;
+  check3(hipEventCreate(&a), "hipEventCreate");
+  check3(hipEventRecord(a, c->st), "hipEventRecord");
+  return a;
+}
+
+// z = T r on the context stream.
+void apply3(mrcm3d_ctx* c, const double* r, double* z) {
+  hipStream_t s = c->st;
+  hipEvent_t e = start_mark(c);
+  mrcm3d::launch_local3(c->lbox, c->m, c->ldinv, c->lcoup, r, c->p, c->nx, c->ny, c->dof_off,
+                        c->dofs, c->fin, c->fout, c->fw, c->mU, c->mP, s);
+  if (e) mark(c, 0, e);
+  if (c->nc > 0) {
+    e = start_mark(c);
+    mrcm3d::launch_coarse_rhs3(c->rowL, c->rowR, c->rowKind, c->mU, c->mP, c->g, c->nc, s);
+    mrcm3d::launch_gemv3(c->Cinv, c->g, c->x, c->nc, s);
+    mrcm3d::launch_csr_resid3(c->crp, c->cci, c->cv, c->g, c->x, c->res, c->nc, s);
+    mrcm3d::launch_gemv3(c->Cinv, c->res, c->dx, c->nc, s);
+    mrcm3d::launch_axpy3(c->x, c->dx, c->nc, s);
+    if (e) mark(c, 1, e);
+    e = start_mark(c);
+    mrcm3d::launch_reconstruct3(c->lbox, c->m, c->mbf, c->mbf_off, c->dof_off, c->x, c->p, c->nx,
+                                c->ny, s);
+    if (e) mark(c, 2, e);
+  }
+  for (int k = 0; k < c->sweeps; ++k) {
+    e = start_mark(c);
+    mrcm3d::launch_residual3(c->tx, c->ty, c->tz, c->nx, c->ny, c->nz, r, c->p, c->rho, s);
+    if (e) mark(c, 3, e);
+    e = start_mark(c);
+    mrcm3d::launch_patch3(c->pbox, c->m, c->pdinv, c->pcoup, c->rho, c->p, c->nx, c->ny, s);
+    if (e) mark(c, 4, e);
+  }
+  e = start_mark(c);
+  mrcm::launch_finalize<double>(c->p, c->n, c->noflow, z, c->partials, s);
+  if (e) mark(c, 5, e);
+}
+
+double host_sum3(const double* v, int nb) {
+  double s = 0.0;
+  for (int k = 0; k < nb; ++k) s += v[k];
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mrcm3d_setup(const mrcm3d_grid* grid, const mrcm3d_params* params, const double* K_dev,
+                 void* stream, mrcm3d_ctx** out) {
+  mrcm3d_ctx* c = nullptr;
+  try {
+    if (!grid || !params || !K_dev || !out) throw mrcm::Error(MRCM_EINVAL, "null argument");
+    const auto t0 = std::chrono::steady_clock::now();
+    const long long n = (long long)grid->nx * grid->ny * grid->nz;
+    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1)
+      throw mrcm::Error(MRCM_EINVAL, "invalid grid");
+    c = new mrcm3d_ctx();
+    check3(hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking), "hipStreamCreate");
+    check3(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming), "hipEventCreate");
+    std::vector<double> K((size_t)n);
+    hipStream_t cs = static_cast<hipStream_t>(stream);
+    check3(hipMemcpyAsync(K.data(), K_dev, sizeof(double) * n, hipMemcpyDeviceToHost, cs),
+           "hipMemcpyAsync");
+    check3(hipStreamSynchronize(cs), "hipStreamSynchronize");
+    mrcm3d::Setup S;
+    mrcm3d::host_setup(S, *grid, *params, K.data());
+    c->nx = S.nx;
+    c->ny = S.ny;
+    c->nz = S.nz;
+    c->n = S.n;
+    c->m = S.m;
+    c->nc = S.nc;
+    c->sweeps = S.sweeps;
+    c->noflow = S.noflow ? 1 : 0;
+    c->tx = c->upload(S.tx);
+    c->ty = c->upload(S.ty);
+    c->tz = c->upload(S.tz);
+    upload_boxes(c, S, S.oboxes, S.over, c->lbox, c->ldinv, c->lcoup);
+    if (S.sweeps > 0) upload_boxes(c, S, S.pboxes, S.patch, c->pbox, c->pdinv, c->pcoup);
+    // multiscale basis functions
+    std::vector<double> mbf;
+    std::vector<long long> mbf_off(S.m);
+    for (int i = 0; i < S.m; ++i) {
+      mbf_off[i] = (long long)mbf.size();
+      mbf.insert(mbf.end(), S.mbf[i].begin(), S.mbf[i].end());
+    }
+    c->mbf = c->upload(mbf);
+    c->mbf_off = c->upload(mbf_off);
+    c->dof_off = c->upload(S.dof_off);
+    // trace tables: the faces of every side of Gamma_i, box-local in hat-Omega_i
+    std::vector<mrcm3d::Dof3> dofs(S.nc);
+    std::vector<int> fin, fout;
+    std::vector<double> fw;
+    for (int i = 0; i < S.m; ++i) {
+      const mrcm3d::Box& oi = S.oboxes[i];
+      auto local = [&](long long cell) {
+        const int x = (int)(cell % S.nx), y = (int)((cell / S.nx) % S.ny),
+                  z = (int)(cell / ((long long)S.nx * S.ny));
+        return ((z - oi.lo[2]) * oi.n(1) + (y - oi.lo[1])) * oi.n(0) + (x - oi.lo[0]);
+      };
+      for (const mrcm3d::SideData& d : S.gam[i]) {
+        const int f0 = (int)fin.size();
+        for (size_t f = 0; f < d.in.size(); ++f) {
+          fin.push_back(local(d.in[f]));
+          fout.push_back(S.oversample > 0 ? local(d.out[f]) : local(d.in[f]));
+          for (int w = 0; w < 4; ++w) fw.push_back(d.w[f][w]);
+        }
+        for (int k = S.dof_off[i]; k < S.dof_off[i + 1]; ++k)
+          if (S.dofs[k][1] == d.side)
+            dofs[k] = mrcm3d::Dof3{f0, (int)d.in.size(), d.n0, d.n1, S.dofs[k][3], S.dofs[k][4], 0, 0};
+      }
+    }
+    c->dofs = c->upload(dofs);
+    c->fin = c->upload(fin);
+    c->fout = c->upload(fout);
+    c->fw = c->upload(fw);
+    c->rowL = c->upload(S.rowL);
+    c->rowR = c->upload(S.rowR);
+    c->rowKind = c->upload(S.rowKind);
+    c->Cinv = c->upload(S.Cinv);
+    c->cinv_bytes = 8.0 * (double)S.Cinv.size();
+    std::vector<int> rp(S.nc + 1, 0), ci;
+    std::vector<double> cv;
+    for (int a = 0; a < S.nc; ++a) {
+      for (int b = 0; b < S.nc; ++b) {
+        const double v = S.C[(size_t)a * S.nc + b];
+        if (v != 0.0) {
+          ci.push_back(b);
+          cv.push_back(v);
+        }
+      }
+      rp[a + 1] = (int)ci.size();
+    }
+    c->crp = c->upload(rp);
+    c->cci = c->upload(ci);
+    c->cv = c->upload(cv);
+    const size_t nc = std::max(S.nc, 1);
+    c->p = c->alloc<double>(S.n);
+    c->rho = c->alloc<double>(S.n);
+    c->mU = c->alloc<double>(nc);
+    c->mP = c->alloc<double>(nc);
+    c->g = c->alloc<double>(nc);
+    c->x = c->alloc<double>(nc);
+    c->res = c->alloc<double>(nc);
+    c->dx = c->alloc<double>(nc);
+    c->partials = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
+    c->parts = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
+    check3(hipHostMalloc((void**)&c->h_fetch, sizeof(double) * (mrcm::kMaxVecBlocks + 256),
+                         hipHostMallocDefault),
+           "hipHostMalloc");
+    check3(hipHostMalloc((void**)&c->h_y, sizeof(double) * 256, hipHostMallocDefault),
+           "hipHostMalloc");
+    check3(hipStreamSynchronize(c->st), "hipStreamSynchronize");
+    c->setup_seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = c;
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    delete c;
+    return fail3(e);
+  } catch (const std::bad_alloc&) {
+    delete c;
+    return fail3(mrcm::Error(MRCM_ENOMEM, "host allocation failed"));
+  }
+}
+
+int mrcm3d_apply(mrcm3d_ctx* c, const double* r, double* z, void* stream) {
+  try {
+    if (!c || !r || !z) throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    check3(hipEventRecord(c->ev_in, s), "hipEventRecord");
+    check3(hipStreamWaitEvent(c->st, c->ev_in, 0), "hipStreamWaitEvent");
+    apply3(c, r, z);
+    check3(hipEventRecord(c->ev_in, c->st), "hipEventRecord");
+    check3(hipStreamWaitEvent(s, c->ev_in, 0), "hipStreamWaitEvent");
+    check3(hipGetLastError(), "kernel launch");
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    return fail3(e);
+  }
+}
+
+int mrcm3d_op_apply(mrcm3d_ctx* c, const double* x, double* y, void* stream) {
+  try {
+    if (!c || !x || !y) throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+    mrcm3d::launch_op3(c->tx, c->ty, c->tz, c->nx, c->ny, c->nz, x, y,
+                       static_cast<hipStream_t>(stream));
+    check3(hipGetLastError(), "kernel launch");
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    return fail3(e);
+  }
+}
+
+int mrcm3d_gmres_solve(mrcm3d_ctx* c, const double* b, double* p, double rtol, int32_t restart,
+                       int32_t maxit, mrcm_stats* st, void* stream) {
+  try {
+    if (!c || !b || !p || restart < 1 || restart > 200 || maxit < 0 || !(rtol >= 0.0))
+      throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+    hipStream_t s = c->st;
+    check3(hipEventRecord(c->ev_in, static_cast<hipStream_t>(stream)), "hipEventRecord");
+    check3(hipStreamWaitEvent(s, c->ev_in, 0), "hipStreamWaitEvent");
+    const long long n = c->n;
+    if (restart > c->krylov_cap) {
+      c->V = c->alloc<double>((size_t)(restart + 1) * n);
+      c->Z = c->alloc<double>((size_t)restart * n);
+      c->hcol = c->alloc<double>(restart + 2);
+      c->yd = c->alloc<double>(restart + 1);
+      c->krylov_cap = restart;
+    }
+    const int nb = mrcm::vec_blocks(n);
+    auto fetch = [&](const double* src, int cnt) {
+      check3(hipMemcpyAsync(c->h_fetch, src, sizeof(double) * cnt, hipMemcpyDeviceToHost, s),
+             "hipMemcpyAsync");
+      check3(hipStreamSynchronize(s), "hipStreamSynchronize");
+      if (c->timing) c->fold();
+    };
+    std::vector<double> H((size_t)(restart + 1) * restart), cs(restart), sn(restart),
+        gv(restart + 1), y(restart);
+    int it = 0, cycles = 0;
+    bool conv = false;
+    double relres = 1.0;
+    mrcm::launch_zero(p, n, s);
+    mrcm::launch_sumsq(b, n, c->parts, nb, s);
+    fetch(c->parts, nb);
+    const double bnorm = std::sqrt(host_sum3(c->h_fetch, nb));
+    if (bnorm == 0.0) {
+      conv = true;
+      relres = 0.0;
+    } else {
+      const double tol = rtol * bnorm;
+      bool first = true;
+      for (;;) {
+        mrcm3d::launch_resid_norm3(c->tx, c->ty, c->tz, c->nx, c->ny, c->nz, b,
+                                   first ? nullptr : p, c->V, c->parts, nb, s);
+        first = false;
+        fetch(c->parts, nb);
+        const double beta = std::sqrt(host_sum3(c->h_fetch, nb));
+        relres = beta / bnorm;
+        if (beta <= tol) {
+          conv = true;
+          break;
+        }
+        if (it >= maxit) break;
+        ++cycles;
+        mrcm::launch_scale(c->V, n, 1.0 / beta, s);
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = beta;
+        int j = 0;
+        for (;;) {
+          double* vj = c->V + (size_t)j * n;
+          double* zj = c->Z + (size_t)j * n;
+          double* w = c->V + (size_t)(j + 1) * n;
+          apply3(c, vj, zj);
+          mrcm3d::launch_arnoldi_start3(c->tx, c->ty, c->tz, c->nx, c->ny, c->nz, zj, w, c->V,
+                                        c->parts, nb, s);
+          for (int i = 0; i <= j; ++i)
+            mrcm::launch_mgs_step(c->parts + (i % 2) * mrcm::kMaxVecBlocks,
+                                  c->parts + ((i + 1) % 2) * mrcm::kMaxVecBlocks, nb, c->hcol, i,
+                                  w, c->V + (size_t)i * n,
+                                  i < j ? c->V + (size_t)(i + 1) * n : nullptr, n, s);
+          mrcm::launch_norm_scale(c->parts + ((j + 1) % 2) * mrcm::kMaxVecBlocks, nb, c->hcol,
+                                  j + 1, w, n, s);
+          fetch(c->hcol, j + 2);
+          const double* hh = c->h_fetch;
+          ++it;
+          for (int i = 0; i <= j + 1; ++i) H[(size_t)i * restart + j] = hh[i];
+          const double hnext = hh[j + 1];
+          for (int i = 0; i < j; ++i) {
+            const double a = H[(size_t)i * restart + j], bb = H[(size_t)(i + 1) * restart + j];
+            H[(size_t)i * restart + j] = cs[i] * a + sn[i] * bb;
+            H[(size_t)(i + 1) * restart + j] = -sn[i] * a + cs[i] * bb;
+          }
+          const double a = H[(size_t)j * restart + j], bb = H[(size_t)(j + 1) * restart + j];
+          const double rr = std::hypot(a, bb);
+          cs[j] = a / rr;
+          sn[j] = bb / rr;
+          H[(size_t)j * restart + j] = rr;
+          H[(size_t)(j + 1) * restart + j] = 0.0;
+          gv[j + 1] = -sn[j] * gv[j];
+          gv[j] = cs[j] * gv[j];
+          const int jj = j + 1;
+          if (!(hnext == 0.0 || std::fabs(gv[j + 1]) <= tol || it >= maxit || jj == restart)) {
+            j = jj;
+            continue;
+          }
+          for (int i = jj - 1; i >= 0; --i) {
+            double sum = gv[i];
+            for (int q = i + 1; q < jj; ++q) sum -= H[(size_t)i * restart + q] * y[q];
+            y[i] = sum / H[(size_t)i * restart + i];
+          }
+          std::memcpy(c->h_y, y.data(), sizeof(double) * jj);
+          check3(hipMemcpyAsync(c->yd, c->h_y, sizeof(double) * jj, hipMemcpyHostToDevice, s),
+                 "hipMemcpyAsync");
+          mrcm::launch_update(p, c->Z, c->yd, jj, n, s);
+          break;
+        }
+      }
+    }
+    check3(hipEventRecord(c->ev_in, s), "hipEventRecord");
+    check3(hipStreamWaitEvent(static_cast<hipStream_t>(stream), c->ev_in, 0), "hipStreamWaitEvent");
+    check3(hipGetLastError(), "kernel launch");
+    if (st) {
+      st->iterations = it;
+      st->cycles = cycles;
+      st->converged = conv ? 1 : 0;
+      st->hist_len = st->true_len = 0;
+      st->final_relres = relres;
+    }
+    if (!conv) throw mrcm::Error(MRCM_ENOCONV, "GMRES reached maxit");
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    return fail3(e);
+  }
+}
+
+int mrcm3d_timing_enable(mrcm3d_ctx* c, int32_t on) {
+  try {
+    if (!c) throw mrcm::Error(MRCM_EINVAL, "null context");
+    check3(hipStreamSynchronize(c->st), "hipStreamSynchronize");
+    c->fold();
+    for (int k = 0; k < 6; ++k) {
+      c->phase_ms[k] = 0.0;
+      c->phase_n[k] = 0;
+    }
+    c->timing = on != 0;
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    return fail3(e);
+  }
+}
+
+int mrcm3d_timing_read(mrcm3d_ctx* c, double* ms, int64_t* counts) {
+  try {
+    if (!c || !ms || !counts) throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+    check3(hipStreamSynchronize(c->st), "hipStreamSynchronize");
+    c->fold();
+    for (int k = 0; k < 6; ++k) {
+      ms[k] = c->phase_ms[k];
+      counts[k] = c->phase_n[k];
+    }
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    return fail3(e);
+  }
+}
+
+int mrcm3d_query(mrcm3d_ctx* c, int32_t what, double* value) {
+  if (!c || !value) return MRCM_EINVAL;
+  switch (what) {
+    case 0: *value = c->setup_seconds; break;
+    case 1: *value = (double)c->device_bytes; break;
+    case 2: *value = c->nc; break;
+    case 3: *value = c->factor_bytes; break;
+    case 4: *value = c->cinv_bytes; break;
+    default: return MRCM_EINVAL;
+  }
+  return MRCM_OK;
+}
+
+void mrcm3d_destroy(mrcm3d_ctx* c) { delete c; }
+
+}  // extern "C"

@@ -1,0 +1,351 @@
+// HIP kernels of the 3-D path (include/mrcm3d.h), FP64: plane-block LDL^T
+// box solves (one workgroup per box, one thread per cell of a plane), trace
+// moments with tensor Legendre test functions, the interface solve through a
+// dense inverse with one refinement step, reconstruction, and the
+// seven-point operator in its forms for smoothing and GMRES.  Every
+// reduction has a fixed order.
+#include "device3d.h"
+
+namespace mrcm3d {
+
+namespace {
+
+constexpr int kVec3Threads = 256;
+
+__device__ __forceinline__ double legendre_face3(int q, int j, int n) {
+  const double xi = (2.0 * j + 1.0) / n - 1.0;
+  if (q == 0) return 1.0;
+  double pm = 1.0, pq = xi;
+  for (int k = 1; k < q; ++k) {
+    const double pn = ((2.0 * k + 1.0) * xi * pq - k * pm) / (k + 1.0);
+    pm = pq;
+    pq = pn;
+  }
+  return pq;
+}
+
+// Global cell of box-local cell q (x fastest, then y, then z).
+__device__ __forceinline__ long long global_cell(const Box3& d, int q, int nx, int ny) {
+  const int x = q % d.n[0], y = (q / d.n[0]) % d.n[1], z = q / (d.n[0] * d.n[1]);
+  return ((long long)(d.lo[2] + z) * ny + (d.lo[1] + y)) * nx + (d.lo[0] + x);
+}
+
+// acc = sum_k D(t, k) v[k] with D symmetric (column t read, consecutive
+// threads reading consecutive words), four partial sums in a fixed order.
+__device__ __forceinline__ double plane_dot(const double* __restrict__ D, const double* v, int P,
+                                            int t) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int k = 0;
+  for (; k + 4 <= P; k += 4) {
+    a0 = fma(D[(long long)k * P + t], v[k], a0);
+    a1 = fma(D[(long long)(k + 1) * P + t], v[k + 1], a1);
+    a2 = fma(D[(long long)(k + 2) * P + t], v[k + 2], a2);
+    a3 = fma(D[(long long)(k + 3) * P + t], v[k + 3], a3);
+  }
+  for (; k < P; ++k) a0 = fma(D[(long long)k * P + t], v[k], a0);
+  return (a0 + a1) + (a2 + a3);
+}
+
+// Block LDL^T solve of the box in LDS: us holds b on entry and x on exit in
+// planes stop .. bz - 1 (planes below keep their forward values).
+__device__ __forceinline__ void plane_solve(double* us, double* v, const Box3& d,
+                                            const double* __restrict__ dinv,
+                                            const double* __restrict__ coup, int stop) {
+  const int P = d.P, bz = d.n[2], t = threadIdx.x;
+  const double* D = dinv + d.doff;
+  const double* T = coup + d.coff;
+  for (int j = 0; j < bz; ++j) {
+    if (t < P) v[t] = j > 0 ? fma(T[(long long)j * P + t], us[(j - 1) * P + t], us[j * P + t])
+                            : us[j * P + t];
+    __syncthreads();
+    if (t < P) us[j * P + t] = plane_dot(D + (long long)j * P * P, v, P, t);
+    __syncthreads();
+  }
+  for (int j = bz - 2; j >= stop; --j) {
+    if (t < P) v[t] = T[(long long)(j + 1) * P + t] * us[(j + 1) * P + t];
+    __syncthreads();
+    if (t < P) us[j * P + t] += plane_dot(D + (long long)j * P * P, v, P, t);
+    __syncthreads();
+  }
+}
+
+// LDS: us[cells] | v[P].
+__global__ void __launch_bounds__(kBox3Threads)
+    k_local3(const Box3* __restrict__ boxes, const double* __restrict__ dinv,
+             const double* __restrict__ coup, const double* __restrict__ r,
+             double* __restrict__ p, int nx, int ny, const int* __restrict__ dof_off,
+             const Dof3* __restrict__ dofs, const int* __restrict__ fin,
+             const int* __restrict__ fout, const double* __restrict__ fw,
+             double* __restrict__ mU, double* __restrict__ mP) {
+  extern __shared__ double sm3[];
+  const int i = blockIdx.x;
+  const Box3 d = boxes[i];
+  const int cells = d.P * d.n[2];
+  double* us = sm3;
+  double* v = sm3 + cells;
+  for (int q = threadIdx.x; q < cells; q += blockDim.x) us[q] = r[global_cell(d, q, nx, ny)];
+  __syncthreads();
+  if (d.pin && threadIdx.x == 0) us[0] = 0.0;
+  __syncthreads();
+  plane_solve(us, v, d, dinv, coup, d.olo[2] > 0 ? d.olo[2] - 1 : 0);
+  // p on the owned cells
+  const int oc = d.on[0] * d.on[1] * d.on[2];
+  for (int q = threadIdx.x; q < oc; q += blockDim.x) {
+    const int x = q % d.on[0], y = (q / d.on[0]) % d.on[1], z = q / (d.on[0] * d.on[1]);
+    const int lq = ((d.olo[2] + z) * d.n[1] + d.olo[1] + y) * d.n[0] + d.olo[0] + x;
+    p[global_cell(d, lq, nx, ny)] = us[lq];
+  }
+  // trace moments of every dof of the subdomain
+  for (int k = dof_off[i] + threadIdx.x; k < dof_off[i + 1]; k += blockDim.x) {
+    const Dof3 q = dofs[k];
+    double su = 0.0, sp = 0.0;
+    for (int f = 0; f < q.nf; ++f) {
+      const int ff = q.f0 + f;
+      const double pin = us[fin[ff]], pout = us[fout[ff]];
+      const double bv = legendre_face3(q.a, f % q.n0, q.n0) * legendre_face3(q.b, f / q.n0, q.n1);
+      const double U = fma(fw[4LL * ff + 1], pout, fw[4LL * ff] * pin);
+      const double Pi = fma(fw[4LL * ff + 3], pout, fw[4LL * ff + 2] * pin);
+      su = fma(bv, U, su);
+      sp = fma(bv, Pi, sp);
+    }
+    mU[k] = su;
+    mP[k] = sp;
+  }
+}
+
+__global__ void __launch_bounds__(kBox3Threads)
+    k_patch3(const Box3* __restrict__ boxes, const double* __restrict__ dinv,
+             const double* __restrict__ coup, const double* __restrict__ rho,
+             double* __restrict__ p, int nx, int ny) {
+  extern __shared__ double sm3[];
+  const Box3 d = boxes[blockIdx.x];
+  const int cells = d.P * d.n[2];
+  double* us = sm3;
+  double* v = sm3 + cells;
+  for (int q = threadIdx.x; q < cells; q += blockDim.x) us[q] = rho[global_cell(d, q, nx, ny)];
+  __syncthreads();
+  if (d.pin && threadIdx.x == 0) us[0] = 0.0;
+  __syncthreads();
+  plane_solve(us, v, d, dinv, coup, d.olo[2]);
+  const int oc = d.on[0] * d.on[1] * d.on[2];
+  for (int q = threadIdx.x; q < oc; q += blockDim.x) {
+    const int x = q % d.on[0], y = (q / d.on[0]) % d.on[1], z = q / (d.on[0] * d.on[1]);
+    const int lq = ((d.olo[2] + z) * d.n[1] + d.olo[1] + y) * d.n[0] + d.olo[0] + x;
+    const long long c = global_cell(d, lq, nx, ny);
+    p[c] += us[lq];
+  }
+}
+
+__global__ void k_coarse_rhs3(const int* __restrict__ rowL, const int* __restrict__ rowR,
+                              const int* __restrict__ kind, const double* __restrict__ mU,
+                              const double* __restrict__ mP, double* __restrict__ g, int nc) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nc) return;
+  const int k = kind[t], L = rowL[t], R = rowR[t];
+  g[t] = k == 2 ? 0.0 : k == 0 ? -(mU[L] + mU[R]) : -(mP[L] - mP[R]);
+}
+
+__device__ __forceinline__ double wave_sum3(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// One wave per row; lanes take columns lane, lane + 64, ... in order.
+__global__ void __launch_bounds__(kVec3Threads)
+    k_gemv3(const double* __restrict__ M, const double* __restrict__ x, double* __restrict__ y,
+            int n) {
+  const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const double* Mr = M + (long long)row * n;
+  double a0 = 0.0, a1 = 0.0;
+  int c = lane;
+  for (; c + 64 < n; c += 128) {
+    a0 = fma(Mr[c], x[c], a0);
+    a1 = fma(Mr[c + 64], x[c + 64], a1);
+  }
+  if (c < n) a0 = fma(Mr[c], x[c], a0);
+  const double s = wave_sum3(a0 + a1);
+  if (lane == 0) y[row] = s;
+}
+
+__global__ void k_csr_resid3(const int* __restrict__ rp, const int* __restrict__ ci,
+                             const double* __restrict__ v, const double* __restrict__ g,
+                             const double* __restrict__ x, double* __restrict__ r, int n) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double s = g[t];
+  for (int q = rp[t]; q < rp[t + 1]; ++q) s = fma(-v[q], x[ci[q]], s);
+  r[t] = s;
+}
+
+__global__ void k_axpy3(double* __restrict__ x, const double* __restrict__ dx, int n) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) x[t] += dx[t];
+}
+
+__global__ void __launch_bounds__(kBox3Threads)
+    k_reconstruct3(const Box3* __restrict__ boxes, const double* __restrict__ mbf,
+                   const long long* __restrict__ mbf_off, const int* __restrict__ dof_off,
+                   const double* __restrict__ x, double* __restrict__ p, int nx, int ny) {
+  const int i = blockIdx.x;
+  const Box3 d = boxes[i];
+  const int k0 = dof_off[i], nk = dof_off[i + 1] - k0;
+  const int oc = d.on[0] * d.on[1] * d.on[2];
+  const double* Pm = mbf + mbf_off[i];
+  for (int q = threadIdx.x; q < oc; q += blockDim.x) {
+    const int xx = q % d.on[0], y = (q / d.on[0]) % d.on[1], z = q / (d.on[0] * d.on[1]);
+    const int lq = ((d.olo[2] + z) * d.n[1] + d.olo[1] + y) * d.n[0] + d.olo[0] + xx;
+    const long long c = global_cell(d, lq, nx, ny);
+    double s = p[c];
+    for (int k = 0; k < nk; ++k) s = fma(Pm[(long long)k * oc + q], x[k0 + k], s);
+    p[c] = s;
+  }
+}
+
+// The seven-point stencil at cell c: sum over the faces of t_f (x_c - x_c'),
+// boundary faces coupled to zero.
+__device__ __forceinline__ double stencil3(const double* __restrict__ tx,
+                                           const double* __restrict__ ty,
+                                           const double* __restrict__ tz, int nx, int ny, int nz,
+                                           long long c, const double* __restrict__ x) {
+  const int ix = (int)(c % nx), iy = (int)((c / nx) % ny), iz = (int)(c / ((long long)nx * ny));
+  const long long fx = ((long long)iz * ny + iy) * (nx + 1) + ix;
+  const long long fy = ((long long)iz * (ny + 1) + iy) * nx + ix;
+  const long long fz = ((long long)iz * ny + iy) * nx + ix;
+  const double tW = tx[fx], tE = tx[fx + 1], tS = ty[fy], tN = ty[fy + nx], tB = tz[fz],
+               tT = tz[fz + (long long)nx * ny];
+  const double xc = x[c];
+  double v = (tW + tE + tS + tN + tB + tT) * xc;
+  if (ix > 0) v -= tW * x[c - 1];
+  if (ix + 1 < nx) v -= tE * x[c + 1];
+  if (iy > 0) v -= tS * x[c - nx];
+  if (iy + 1 < ny) v -= tN * x[c + nx];
+  if (iz > 0) v -= tB * x[c - (long long)nx * ny];
+  if (iz + 1 < nz) v -= tT * x[c + (long long)nx * ny];
+  return v;
+}
+
+__global__ void __launch_bounds__(kVec3Threads)
+    k_op3(const double* __restrict__ tx, const double* __restrict__ ty,
+          const double* __restrict__ tz, int nx, int ny, int nz, const double* __restrict__ x,
+          double* __restrict__ y, const double* __restrict__ r, int mode) {
+  const long long n = (long long)nx * ny * nz;
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
+       c += (long long)gridDim.x * blockDim.x) {
+    const double a = stencil3(tx, ty, tz, nx, ny, nz, c, x);
+    y[c] = mode == 0 ? a : r[c] - a;
+  }
+}
+
+__device__ __forceinline__ double block_sum3(double v, double* red) {
+  v = wave_sum3(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k];
+  return s;
+}
+
+// mode 0: w = A z, partials of w . v0 (v0 = aux); mode 1: r = b - A p (b when
+// p is NULL; b = aux), partials of r^2.
+__global__ void __launch_bounds__(kVec3Threads)
+    k_op_reduce3(const double* __restrict__ tx, const double* __restrict__ ty,
+                 const double* __restrict__ tz, int nx, int ny, int nz,
+                 const double* __restrict__ x, double* __restrict__ out,
+                 const double* __restrict__ aux, double* __restrict__ partials, int mode) {
+  __shared__ double red[kVec3Threads / 64];
+  const long long n = (long long)nx * ny * nz;
+  double s = 0.0;
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
+       c += (long long)gridDim.x * blockDim.x) {
+    if (mode == 0) {
+      const double w = stencil3(tx, ty, tz, nx, ny, nz, c, x);
+      out[c] = w;
+      s = fma(w, aux[c], s);
+    } else {
+      const double rr = x ? aux[c] - stencil3(tx, ty, tz, nx, ny, nz, c, x) : aux[c];
+      out[c] = rr;
+      s = fma(rr, rr, s);
+    }
+  }
+  s = block_sum3(s, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+inline int grid3(long long n) {
+  long long b = (n + kVec3Threads - 1) / kVec3Threads;
+  return (int)(b < 1 ? 1 : b > 4096 ? 4096 : b);
+}
+
+}  // namespace
+
+void launch_local3(const Box3* boxes, int m, const double* dinv, const double* coup,
+                   const double* r, double* p, int nx, int ny, const int* dof_off,
+                   const Dof3* dofs, const int* fin, const int* fout, const double* fw,
+                   double* mU, double* mP, hipStream_t s) {
+  if (m <= 0) return;
+  const size_t shm = sizeof(double) * (kMaxBox3Cells + kBox3Threads);
+  hipLaunchKernelGGL(k_local3, dim3(m), dim3(kBox3Threads), shm, s, boxes, dinv, coup, r, p, nx,
+                     ny, dof_off, dofs, fin, fout, fw, mU, mP);
+}
+void launch_patch3(const Box3* boxes, int m, const double* dinv, const double* coup,
+                   const double* rho, double* p, int nx, int ny, hipStream_t s) {
+  if (m <= 0) return;
+  const size_t shm = sizeof(double) * (kMaxBox3Cells + kBox3Threads);
+  hipLaunchKernelGGL(k_patch3, dim3(m), dim3(kBox3Threads), shm, s, boxes, dinv, coup, rho, p,
+                     nx, ny);
+}
+void launch_coarse_rhs3(const int* rowL, const int* rowR, const int* kind, const double* mU,
+                        const double* mP, double* g, int nc, hipStream_t s) {
+  if (nc <= 0) return;
+  hipLaunchKernelGGL(k_coarse_rhs3, dim3((nc + 255) / 256), dim3(256), 0, s, rowL, rowR, kind, mU,
+                     mP, g, nc);
+}
+void launch_gemv3(const double* M, const double* x, double* y, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_gemv3, dim3((n + 3) / 4), dim3(kVec3Threads), 0, s, M, x, y, n);
+}
+void launch_csr_resid3(const int* rp, const int* ci, const double* v, const double* g,
+                       const double* x, double* r, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_csr_resid3, dim3((n + 255) / 256), dim3(256), 0, s, rp, ci, v, g, x, r, n);
+}
+void launch_axpy3(double* x, const double* dx, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_axpy3, dim3((n + 255) / 256), dim3(256), 0, s, x, dx, n);
+}
+void launch_reconstruct3(const Box3* boxes, int m, const double* mbf, const long long* mbf_off,
+                         const int* dof_off, const double* x, double* p, int nx, int ny,
+                         hipStream_t s) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_reconstruct3, dim3(m), dim3(kBox3Threads), 0, s, boxes, mbf, mbf_off,
+                     dof_off, x, p, nx, ny);
+}
+void launch_op3(const double* tx, const double* ty, const double* tz, int nx, int ny, int nz,
+                const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_op3, dim3(grid3((long long)nx * ny * nz)), dim3(kVec3Threads), 0, s, tx,
+                     ty, tz, nx, ny, nz, x, y, (const double*)nullptr, 0);
+}
+void launch_residual3(const double* tx, const double* ty, const double* tz, int nx, int ny,
+                      int nz, const double* r, const double* p, double* rho, hipStream_t s) {
+  hipLaunchKernelGGL(k_op3, dim3(grid3((long long)nx * ny * nz)), dim3(kVec3Threads), 0, s, tx,
+                     ty, tz, nx, ny, nz, p, rho, r, 1);
+}
+void launch_arnoldi_start3(const double* tx, const double* ty, const double* tz, int nx, int ny,
+                           int nz, const double* z, double* w, const double* v0,
+                           double* partials, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_op_reduce3, dim3(nb), dim3(kVec3Threads), 0, s, tx, ty, tz, nx, ny, nz, z,
+                     w, v0, partials, 0);
+}
+void launch_resid_norm3(const double* tx, const double* ty, const double* tz, int nx, int ny,
+                        int nz, const double* b, const double* p, double* r, double* partials,
+                        int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_op_reduce3, dim3(nb), dim3(kVec3Threads), 0, s, tx, ty, tz, nx, ny, nz, p,
+                     r, b, partials, 1);
+}
+
+}  // namespace mrcm3d

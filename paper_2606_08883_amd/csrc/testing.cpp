@@ -11,6 +11,7 @@
 
 #include "coarse.h"
 #include "setup.h"
+#include "setup3d.h"
 
 namespace {
 
@@ -29,6 +30,20 @@ mrcm::HostSetup make_setup(const mrcm_grid* g, const mrcm_params* p, const doubl
 }  // namespace
 
 extern "C" {
+
+int mrcm3d_test_host_apply(const mrcm3d_grid* grid, const mrcm3d_params* params,
+                           const double* K, const double* r, double* z, int64_t* nc) {
+  try {
+    if (!grid || !params || !K || !r || !z) throw mrcm::Error(MRCM_EINVAL, "null argument");
+    mrcm3d::Setup S;
+    mrcm3d::host_setup(S, *grid, *params, K);
+    mrcm3d::host_apply(S, r, z);
+    if (nc) *nc = S.nc;
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    return fail(e);
+  }
+}
 
 int mrcm_test_zero_cell_setup(const mrcm_grid* grid, const mrcm_params* params,
                               const double* K, int64_t cell) {
