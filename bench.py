@@ -20,6 +20,8 @@ the right.  Prints one JSON line.  Besides the contract keys it carries:
                    FP32-stored factors;
   batched_1024     the 1024 x 1024 log-normal workload (4096 subdomains);
   serving          a short Poisson stream of mixed-size requests (p50/p99);
+  cube_3d          the 3-D workload (96^3 cells, seven-point stencil): solves/s,
+                   phases and the roofline entry of its dominant phase;
   cpu_baseline     the oracle timed on the host cores on a bounded sample.
 """
 from __future__ import annotations
@@ -319,6 +321,138 @@ def serving_leg(requests: int, max_active: int) -> dict:
                       "worker threads"}
 
 
+def boxes3(w, grow: int) -> np.ndarray:
+    """Subdomain boxes of a 3-D workload grown by `grow` cells and clipped to
+    the grid, rows (x0, x1, y0, y1, z0, z1); layers of w.s cells per axis,
+    the last one ragged."""
+    dims = (w.nx, w.ny, w.nz)
+    m = [-(-d // w.s) for d in dims]
+    out = []
+    for L in range(m[2]):
+        for J in range(m[1]):
+            for I in range(m[0]):
+                b = []
+                for a, q in enumerate((I, J, L)):
+                    b += [max(0, q * w.s - grow), min(dims[a], (q + 1) * w.s + grow)]
+                out.append(b)
+    return np.array(out, dtype=np.int64)
+
+
+def algorithmic_bytes3(w, coarse_bytes: float) -> dict:
+    """Algorithmic bytes of one instance of every phase of the 3-D apply
+    (FP64 throughout).  A box of bx x by x bz cells (plane P = bx by) stores
+    bz symmetric P x P plane blocks in full and bz x P couplings; the count
+    reads them once.
+      local       per subdomain on its oversampled box: factor and couplings,
+                  r on the box, p written on the owned cells; per trace face
+                  its two box-local cells (8 B) and four weights (32 B); per
+                  interface dof its 32 B table entry and two moments (16 B);
+      coarse      the interface solve: the factor matrices of its dissection
+                  once per sweep and the refinement residuals (mrcm3d_query's
+                  count);
+      reconstruct the MBFs (N_i words per owned cell), the interface solution
+                  and p read and written;
+      residual    tx, ty, tz once, r and p read, rho written;
+      patch       per patch: factor and couplings, rho on the patch, p read
+                  and written on the owned cells;
+      finalize    p read twice (zero-mean projection) and z written."""
+    n = w.cells
+    own = boxes3(w, 0)
+    dims = (w.nx, w.ny, w.nz)
+
+    def ext(b):
+        return (b[:, 1] - b[:, 0]), (b[:, 3] - b[:, 2]), (b[:, 5] - b[:, 4])
+
+    def factor(b):
+        bx, by, bz = ext(b)
+        P = bx * by
+        return int(np.sum(bz * P * P * 8 + bz * P * 8))
+
+    ox, oy, oz = ext(own)
+    cells_own = ox * oy * oz
+    ob = boxes3(w, w.oversample)
+    obx, oby, obz = ext(ob)
+    tang = {0: (oy, oz), 1: (ox, oz), 2: (ox, oy)}
+    faces, ndof = 0, np.zeros(len(own), dtype=np.int64)
+    for a in range(3):
+        t0, t1 = tang[a]
+        nb = np.minimum(w.degree + 1, t0) * np.minimum(w.degree + 1, t1)
+        for lo in (True, False):
+            inner = own[:, 2 * a] > 0 if lo else own[:, 2 * a + 1] < dims[a]
+            faces += int(np.sum((t0 * t1)[inner]))
+            ndof += np.where(inner, nb, 0)
+    nc = int(ndof.sum())
+    local = factor(ob) + int(np.sum(obx * oby * obz)) * 8 + n * 8 + faces * 40 + nc * 48
+    coarse = int(coarse_bytes)
+    recon = int(np.sum(ndof * cells_own)) * 8 + nc * 8 + 16 * n
+    faces_all = (w.nx + 1) * w.ny * w.nz + w.nx * (w.ny + 1) * w.nz + w.nx * w.ny * (w.nz + 1)
+    residual = faces_all * 8 + 24 * n
+    pb = boxes3(w, w.overlap)
+    px, py, pz = ext(pb)
+    patch = factor(pb) + int(np.sum(px * py * pz)) * 8 + 16 * n
+    finalize = n * ((2 if not any(w.bc) else 1) * 8 + 8)
+    return {"local": local, "coarse": coarse, "reconstruct": recon, "residual": residual,
+            "patch": patch, "finalize": finalize, "nc": nc}
+
+
+PHASE_KERNELS3 = {"local": "k_local3", "coarse": "interface solve (k_coarse_rhs, k_coarse_fwd "
+                  "and k_coarse_bwd per level, k_coarse_resid and k_coarse_add per refinement)",
+                  "reconstruct": "k_reconstruct3", "residual": "k_op3 (residual form)",
+                  "patch": "k_patch3", "finalize": "k_sum + k_finalize"}
+
+
+def cube_leg(steps: int) -> dict:
+    """The 3-D cube workload (96^3 cells, 1728 subdomains): solves/s, phase
+    table and the roofline entry of its dominant phase."""
+    import torch
+
+    from paper_2606_08883_amd import binding as B
+    from paper_2606_08883_amd.configs import WORKLOADS3
+    w = WORKLOADS3["cube"]
+    dev = torch.device("cuda:0")
+    K = torch.tensor(w.permeability(), dtype=torch.float64, device=dev)
+    b = torch.tensor(w.rhs(), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx = B.Context3(w.binding_config(), K)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    r = timed_solves(ctx, b, steps, 2)
+    phases = phase_timing(ctx, b, max(1, min(steps, 5)))
+    ab = algorithmic_bytes3(w, ctx.query("coarse_bytes"))
+    napply = max(1, phases["local"][1])
+    table = {}
+    for k, (ms, cnt) in phases.items():
+        if cnt == 0:
+            continue
+        avg = ms / cnt
+        gbs = ab[k] / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
+        table[k] = {"kernel": PHASE_KERNELS3[k], "ms": avg, "per_apply": cnt / napply,
+                    "algorithmic_bytes": ab[k], "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS}
+    dom = max(table, key=lambda k: table[k]["ms"] * table[k]["per_apply"])
+    t = table[dom]
+    out = {"workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz} cells, subdomains of {w.s}^3, "
+                       f"oversampling {w.oversample}, degree {w.degree}, {w.sweeps} smoothing "
+                       f"sweep(s), overlap {w.overlap}, alpha {w.alpha}, log-normal sigma "
+                       f"{w.sigma} correlation {w.ell}, no-flow, corner sources",
+           "solves_per_s": r["value"], "cell_dof_per_s": r["value"] * w.cells,
+           "latency_ms": {"p50": r["p50"], "p99": r["p99"]}, "iterations": r["iterations"],
+           "final_relres_max": r["relres_max"], "setup_s": setup_s,
+           "interface_dofs": int(ctx.query("coarse_dofs")),
+           "interface_refinement_steps": int(ctx.query("coarse_refine")),
+           "interface_levels_per_sweep": int(ctx.query("coarse_levels")),
+           "device_gb": ctx.query("device_bytes") / 1e9,
+           "apply_ms": sum(v[0] for v in phases.values()) / napply,
+           "roofline": {"bound": "hbm", "kernel": t["kernel"], "phase": dom,
+                        "achieved": t["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": t["frac"], "algorithmic_bytes_per_launch": t["algorithmic_bytes"],
+                        "avg_launch_ms": t["ms"]},
+           "phases": table}
+    assert out["interface_dofs"] == ab["nc"]
+    ctx.close()
+    return out
+
+
 def cpu_baseline(w, gpu_iterations: float, window: int = 512) -> dict:
     """The oracle as it stands, on the host cores, on a bounded sample of the
     workload: the bottom-left window x window cells of the same field with
@@ -611,6 +745,8 @@ def main() -> int:
                          "oversampling / smoothing row of the paper's inclusion tables")
     ap.add_argument("--requests", type=int, default=512, help="requests of the serving run")
     ap.add_argument("--max-active", type=int, default=8, help="serving slots")
+    ap.add_argument("--cube", action="store_true",
+                    help="only the 3-D cube workload (96^3 cells): one JSON line")
     ap.add_argument("--mfma-ab", action="store_true",
                     help="time 8-column applications with the reconstruction on the FMA kernel "
                          "and on the matrix cores")
@@ -643,6 +779,9 @@ def main() -> int:
         return serve(args)
     if args.mfma_ab:
         return mfma_ab(args)
+    if args.cube:
+        print(json.dumps(cube_leg(args.steps)), flush=True)
+        return 0
     if args.inclusions:
         return inclusions(args)
 
@@ -711,6 +850,8 @@ def main() -> int:
         out["batched_1024"] = batched_leg(max(5, args.steps // 2))
         print("bench: serving leg", file=sys.stderr, flush=True)
         out["serving"] = serving_leg(32, 8)
+        print("bench: 3-D cube workload", file=sys.stderr, flush=True)
+        out["cube_3d"] = cube_leg(max(5, args.steps // 2))
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, r["iterations"])

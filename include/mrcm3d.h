@@ -15,10 +15,12 @@
  * Schwarz smoothing; FP64 throughout.  Vectors are FP64 device pointers of
  * nx ny nz values, cell (ix, iy, iz) at (iz ny + iy) nx + ix.
  *
- * Error codes and stats as in mrcm.h.  Limits of this first 3-D path: every
- * oversampled box and patch has at most 256 cells per z-plane (bx by <= 256)
- * and 4096 cells, and the interface system has at most 16384 unknowns (its
- * inverse is kept dense); larger configurations get MRCM_EINVAL.
+ * Error codes and stats as in mrcm.h.  Limits: every oversampled box and
+ * patch has at most 256 cells per z-plane (bx by <= 256) and 4096 cells, and
+ * every separator of the interface solve (a plane of subdomains across the
+ * longest axis of a region, halved recursively down to regions of at most
+ * eight subdomains) and every border has at most 6144 interface rows;
+ * larger configurations get MRCM_EINVAL.
  */
 #ifndef MRCM3D_H
 #define MRCM3D_H
@@ -52,8 +54,12 @@ typedef struct mrcm3d_ctx mrcm3d_ctx;
 /* Set up T for the permeability K_dev (device, n values, finite and > 0):
  * the host computes the maps, the plane-block LDL^T factors of every
  * oversampled box and patch, the informed spaces, the multiscale basis
- * functions and the interface system with its dense inverse (FP64), and
- * uploads them.  The context owns all device memory. */
+ * functions and the interface system, which it factors over a dissection of
+ * the subdomain grid into planes (row-equilibrated block elimination with
+ * partial pivoting in every separator, FP64, as the 2-D path), with the
+ * number of FP64 refinement steps each interface solve runs set so that a
+ * correction falls below 1e-10 of the solution (at most four), and uploads
+ * them.  The context owns all device memory. */
 int mrcm3d_setup(const mrcm3d_grid* grid, const mrcm3d_params* params, const double* K_dev,
                  void* stream, mrcm3d_ctx** out);
 
@@ -80,7 +86,10 @@ int mrcm3d_timing_read(mrcm3d_ctx* ctx, double* ms, int64_t* counts);
 
 /* Queries: 0 set-up seconds, 1 device bytes, 2 interface unknowns, 3 bytes
  * one application reads from the box factors (local and patch, each read
- * twice), 4 bytes of the dense interface inverse. */
+ * twice), 4 bytes one interface solve reads and writes (its factor matrices
+ * once per sweep and the refinement residuals), 5 refinement steps of every
+ * interface solve, 6 level launches of one sweep of the interface solve.
+ * MRCM_EINVAL for another code. */
 int mrcm3d_query(mrcm3d_ctx* ctx, int32_t what, double* value);
 
 /* Release a context (NULL is ignored). */

@@ -52,11 +52,24 @@ int mrcm_test_zero_cell_setup(const mrcm_grid* grid, const mrcm_params* params,
 
 /* z = T r on a 3-D grid (include/mrcm3d.h) evaluated on the host from the
  * tables mrcm3d_setup uploads, in the order the device applies them (plane-
- * block local solves, trace moments, the dense interface inverse with one
- * refinement step, reconstruction, smoothing, projection).  K, r, z: host, n
- * values; *nc (may be NULL) receives the interface unknowns. */
+ * block local solves, trace moments, the interface solve through the
+ * dissection factor with its refinement steps, reconstruction, smoothing,
+ * projection).  K, r, z: host, n values; *nc (may be NULL) receives the
+ * interface unknowns. */
 int mrcm3d_test_host_apply(const mrcm3d_grid* grid, const mrcm3d_params* params,
                            const double* K, const double* r, double* z, int64_t* nc);
+
+/* The dissection tree of the 3-D interface solve on an mx x my x mz grid of
+ * subdomains (subdomain (I, J, L) at (L my + J) mx + I), nodes in post-order:
+ * elim[s] the node that eliminates subdomain s (m values); parent[t] (-1 for
+ * the root) and depth[t] per node; the border of node t in
+ * border[border_ptr[t] .. border_ptr[t + 1]) (sorted).  Capacities: max_nodes
+ * nodes (parent, depth: max_nodes; border_ptr: max_nodes + 1) and max_border
+ * border entries; *nodes receives the node count.  MRCM_EINVAL when a
+ * capacity is too small. */
+int mrcm3d_test_dissection(int32_t mx, int32_t my, int32_t mz, int32_t* elim, int32_t* parent,
+                           int32_t* depth, int32_t* border_ptr, int32_t* border,
+                           int32_t max_nodes, int32_t max_border, int32_t* nodes);
 
 #ifdef __cplusplus
 }

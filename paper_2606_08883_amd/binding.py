@@ -36,7 +36,8 @@ QUERIES = {"setup_seconds": 0, "device_bytes": 1, "coarse_pivot": 2, "coarse_lev
            "tune_changes": 8, "coarse_refine": 9, "mfma_recon": 10}
 PHASES = ["local", "coarse", "reconstruct", "residual", "patch", "finalize"]
 TEST_EXPORTED = ["mrcm_test_coarse_sizes", "mrcm_test_coarse_matrix", "mrcm_test_host_apply",
-                 "mrcm_test_coarse_solve", "mrcm_test_zero_cell_setup", "mrcm3d_test_host_apply"]
+                 "mrcm_test_coarse_solve", "mrcm_test_zero_cell_setup", "mrcm3d_test_host_apply",
+                 "mrcm3d_test_dissection"]
 
 
 class MrcmError(RuntimeError):
@@ -127,6 +128,8 @@ def lib() -> ctypes.CDLL:
             "mrcm3d_destroy": ([P], None),
             "mrcm3d_test_host_apply": ([ctypes.POINTER(Grid3), ctypes.POINTER(Params3), pd, pd,
                                         pd, pi64], i32),
+            "mrcm3d_test_dissection": ([i32, i32, i32, pi32, pi32, pi32, pi32, pi32, i32, i32,
+                                        pi32], i32),
             "gmres_batch_add": ([P, P, P, P, i32, dbl, i32, P, pi32], i32),
             "gmres_batch_tick": ([P, pi32], i32),
             "gmres_batch_poll": ([P, i32, pi32, ctypes.POINTER(Stats)], i32),
@@ -305,6 +308,25 @@ def test3d_host_apply(cfg: Config3, K: np.ndarray, r: np.ndarray) -> tuple:
     return z, nc.value
 
 
+def test3d_dissection(mx: int, my: int, mz: int) -> dict:
+    """The 3-D interface solve's dissection tree: elim (per subdomain), parent,
+    depth and border lists per node (post-order)."""
+    m = mx * my * mz
+    cap = 4 * m + 8
+    elim = np.full(m, -1, dtype=np.int32)
+    parent = np.empty(cap, dtype=np.int32)
+    depth = np.empty(cap, dtype=np.int32)
+    bptr = np.empty(cap + 1, dtype=np.int32)
+    border = np.empty(6 * m * cap // 4 + 64, dtype=np.int32)
+    nn = ctypes.c_int32()
+    p32 = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
+    _check(lib().mrcm3d_test_dissection(mx, my, mz, p32(elim), p32(parent), p32(depth), p32(bptr),
+                                        p32(border), cap, len(border), ctypes.byref(nn)))
+    k = nn.value
+    return {"elim": elim, "parent": parent[:k].copy(), "depth": depth[:k].copy(),
+            "border": [border[bptr[t]:bptr[t + 1]].copy() for t in range(k)]}
+
+
 class Context3:
     """A set-up 3-D MRCM-OS operator (mrcm3d_setup)."""
 
@@ -353,9 +375,10 @@ class Context3:
         return {PHASES[k]: (ms[k], cnt[k]) for k in range(6)}
 
     def query(self, what: str) -> float:
-        """setup_seconds, device_bytes, coarse_dofs, factor_bytes, cinv_bytes."""
+        """setup_seconds, device_bytes, coarse_dofs, factor_bytes, coarse_bytes,
+        coarse_refine, coarse_levels."""
         idx = {"setup_seconds": 0, "device_bytes": 1, "coarse_dofs": 2, "factor_bytes": 3,
-               "cinv_bytes": 4}[what]
+               "coarse_bytes": 4, "coarse_refine": 5, "coarse_levels": 6}[what]
         v = ctypes.c_double()
         _check(lib().mrcm3d_query(self._ptr, idx, ctypes.byref(v)))
         return v.value

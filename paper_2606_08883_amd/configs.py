@@ -34,6 +34,17 @@ Field recipes and seeds:
           paper's inclusion experiments (Section 4.3); 8 x 8 subdomains of
           20 x 20 (4 x 4 of 40 x 40 for comparison), oversampling 2, two
           sweeps, alpha 10, L = H; FP64.
+
+3-D (the model problem of Section 2 with d = 3; the paper reports no 3-D
+experiment, so this workload is a stand-in of the same construction):
+
+* cube    96 x 96 x 96 (884 736 cells), log-normal K (sigma 2, correlation
+          6, seed 21), 12 x 12 x 12 subdomains of 8 x 8 x 8, oversampling 2
+          (12 x 12 x 12 boxes), tensor Legendre degree 1 on every face (4
+          functions per face and unknown, 38 016 interface dofs), one
+          smoothing sweep with overlap 2, alpha 10, L = H; no flow on all six
+          sides with the pressure fixed by its mean, injector +1 in cell
+          (0, 0, 0) and producer -1 in the opposite corner; FP64.
 """
 from __future__ import annotations
 
@@ -115,3 +126,43 @@ WORKLOADS = {
 for _kind in ("high", "low", "both"):
     WORKLOADS[f"incl-{_kind}"] = Workload(f"incl-{_kind}", 160, 160, 20, 2, 10.0, 0, 2, 2, 1, 0,
                                           f"incl-{_kind}", (1, 1, 0, 0))
+
+
+@dataclass(frozen=True)
+class Workload3:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    s: int
+    oversample: int
+    alpha: float
+    beta_len: int
+    sweeps: int
+    overlap: int
+    degree: int
+    sigma: float
+    ell: float
+    seed: int
+    bc: tuple = (0, 0, 0, 0, 0, 0)
+
+    def permeability(self) -> np.ndarray:
+        return wl.lognormal_K3(self.nx, self.ny, self.nz, self.sigma, self.ell, self.seed)
+
+    def rhs(self) -> np.ndarray:
+        return wl.corner_sources3(self.nx, self.ny, self.nz)
+
+    def binding_config(self):
+        from .binding import Config3
+        return Config3(self.nx, self.ny, self.nz, tuple(self.bc), self.s, self.s, self.s,
+                       self.oversample, self.alpha, self.beta_len, self.sweeps, self.overlap,
+                       self.degree)
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+WORKLOADS3 = {
+    "cube": Workload3("cube", 96, 96, 96, 8, 2, 10.0, 0, 1, 2, 1, 2.0, 6.0, 21),
+}

@@ -415,83 +415,15 @@ std::vector<T> narrow(const std::vector<double>& v) {
 // node reads its rows' contributions in slot order with coalesced loads).
 void upload_coarse(mrcm_ctx* c, const mrcm::CoarseFactor& F, const mrcm::HostSetup& S,
                    hipStream_t s) {
-  const int nn = (int)F.nodes.size();
-  std::vector<int> idx;
-  std::vector<long long> fwd_off(nn), bwd_off(nn);
-  std::vector<int> fcol_off(nn), ucol_off(nn);
-  int max_nf = 1, max_nu = 1;
-  long long fwd_len = 0, bwd_len = 0;
-  for (int t = 0; t < nn; ++t) {
-    const auto& cn = F.nodes[t];
-    fcol_off[t] = (int)idx.size();
-    idx.insert(idx.end(), cn.fcol.begin(), cn.fcol.end());
-    ucol_off[t] = (int)idx.size();
-    idx.insert(idx.end(), cn.ucol.begin(), cn.ucol.end());
-    fwd_off[t] = fwd_len;
-    fwd_len += (long long)cn.fwd.size();
-    bwd_off[t] = bwd_len;
-    bwd_len += (long long)cn.bwd.size();
-    max_nf = std::max(max_nf, (int)cn.frow.size());
-    max_nu = std::max(max_nu, (int)cn.urow.size());
-  }
-  // the node matrices, concatenated by the host threads (uninitialised
-  // storage: every element is written)
-  std::unique_ptr<double[]> fwd(new double[std::max(fwd_len, 1LL)]);
-  std::unique_ptr<double[]> bwd(new double[std::max(bwd_len, 1LL)]);
-#pragma omp parallel for schedule(dynamic, 4) num_threads(host_threads())
-  for (int t = 0; t < nn; ++t) {
-    const auto& cn = F.nodes[t];
-    std::copy(cn.fwd.begin(), cn.fwd.end(), fwd.get() + fwd_off[t]);
-    std::copy(cn.bwd.begin(), cn.bwd.end(), bwd.get() + bwd_off[t]);
-  }
-  if (max_nf > 6144 || max_nu > 6144)
-    throw mrcm::Error(MRCM_EINVAL, "interface separator too large for one workgroup");
-  // 16 rows per chunk: one group of four rows per wave
-  auto slice_rows = [](int) { return 16; };
-  std::vector<CChunk> chunks;
-  c->fwd_levels.clear();
-  c->bwd_levels.clear();
-  for (int d = F.depth; d >= 0; --d) {
-    const int first = (int)chunks.size();
-    for (int t = 0; t < nn; ++t) {
-      const auto& cn = F.nodes[t];
-      if (cn.depth != d) continue;
-      const int nf = (int)cn.frow.size(), nu = (int)cn.urow.size(), rows = nf + nu;
-      const int step = slice_rows(nf);
-      for (int r0 = 0; r0 < rows; r0 += step)
-        chunks.push_back(CChunk{r0, std::min(rows, r0 + step), nf, nu, cn.yoff, cn.coff,
-                                fcol_off[t], ucol_off[t], fwd_off[t]});
-    }
-    c->fwd_levels.push_back({first, (int)chunks.size() - first});
-  }
-  for (int d = 0; d <= F.depth; ++d) {
-    const int first = (int)chunks.size();
-    for (int t = 0; t < nn; ++t) {
-      const auto& cn = F.nodes[t];
-      if (cn.depth != d) continue;
-      const int nf = (int)cn.frow.size(), nu = (int)cn.urow.size();
-      if (nu == 0) continue;  // x_F = y_F, written by the forward level
-      const int step = slice_rows(nu);
-      for (int r0 = 0; r0 < nf; r0 += step)
-        chunks.push_back(CChunk{r0, std::min(nf, r0 + step), nf, nu, cn.yoff, cn.coff,
-                                fcol_off[t], ucol_off[t], bwd_off[t]});
-    }
-    if ((int)chunks.size() > first) c->bwd_levels.push_back({first, (int)chunks.size() - first});
-  }
-  // right-hand-side sources and contribution destinations by tree position
+  mrcm::CoarseTables T = mrcm::coarse_tables(F, S.rowL.data(), S.rowR.data(), S.rowKind.data(),
+                                             S.pin_row, host_threads());
+  const long long fwd_len = T.fwd_len, bwd_len = T.bwd_len;
   const int np = F.ylen;
+  c->fwd_levels = T.fwd_levels;
+  c->bwd_levels = T.bwd_levels;
+  static_assert(sizeof(int4) == sizeof(std::array<int, 4>), "gsrc layout");
   std::vector<int4> gsrc(np);
-  for (int t = 0; t < np; ++t) {
-    const int row = F.nd_row[t];
-    const int kind = row == S.pin_row ? 2 : S.rowKind[row];
-    gsrc[t] = make_int4(S.rowL[row], S.rowR[row], kind, 0);
-  }
-  std::vector<int> cdest(std::max(F.clen, 1), 0);
-  for (int t = 0; t < np; ++t)
-    for (int u = 0; u < F.maxp; ++u) {
-      const int q = F.slots[(size_t)t * F.maxp + u];
-      if (q >= 0) cdest[q] = u * np + t;
-    }
+  std::memcpy(gsrc.data(), T.gsrc.data(), sizeof(int4) * (size_t)np);
   c->coarse_bytes = 8.0 * ((double)fwd_len + (double)bwd_len);
   c->refine = F.refine;
   // one refinement residual reads the scaled rows (values and column
@@ -502,17 +434,17 @@ void upload_coarse(mrcm_ctx* c, const mrcm::CoarseFactor& F, const mrcm::HostSet
     c->cci = c->upload(F.nd_ci, s);
     c->cv = c->upload(F.nd_v, s);
   }
-  c->cfwd = c->upload(fwd.get(), (size_t)fwd_len, s);
-  c->cbwd = c->upload(bwd.get(), (size_t)bwd_len, s);
-  c->cidx = c->upload(idx, s);
+  c->cfwd = c->upload(T.fwd.get(), (size_t)fwd_len, s);
+  c->cbwd = c->upload(T.bwd.get(), (size_t)bwd_len, s);
+  c->cidx = c->upload(T.idx, s);
   c->gsrc = c->upload(gsrc, s);
   c->gscale = c->upload(F.nd_scale, s);
-  c->cdest = c->upload(cdest, s);
+  c->cdest = c->upload(T.cdest, s);
   c->maxp = F.maxp;
   c->np = np;
-  c->chunks = c->upload(chunks, s);
-  c->max_nf = max_nf;
-  c->max_nu = max_nu;
+  c->chunks = c->upload(T.chunks, s);
+  c->max_nf = T.max_nf;
+  c->max_nu = T.max_nu;
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 

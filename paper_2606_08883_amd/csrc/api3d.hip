@@ -4,7 +4,10 @@
 // (the vector kernels of the 2-D path: Gram-Schmidt, normalisation, update,
 // norms, projection).
 #include <hip/hip_runtime.h>
+#include <omp.h>
 
+#include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -30,7 +33,7 @@ struct mrcm3d_ctx {
   long long n = 0;
   std::vector<void*> allocs;
   size_t device_bytes = 0;
-  double setup_seconds = 0.0, factor_bytes = 0.0, cinv_bytes = 0.0;
+  double setup_seconds = 0.0, factor_bytes = 0.0, coarse_bytes = 0.0, resid_bytes = 0.0;
   double *tx = nullptr, *ty = nullptr, *tz = nullptr;
   mrcm3d::Box3 *lbox = nullptr, *pbox = nullptr;
   double *ldinv = nullptr, *lcoup = nullptr, *pdinv = nullptr, *pcoup = nullptr;
@@ -40,13 +43,22 @@ struct mrcm3d_ctx {
   mrcm3d::Dof3* dofs = nullptr;
   int *fin = nullptr, *fout = nullptr;
   double* fw = nullptr;
-  int *rowL = nullptr, *rowR = nullptr, *rowKind = nullptr;
-  double* Cinv = nullptr;
+  // the interface solve: the nested-dissection factor and its level lists,
+  // right-hand-side sources and scales by tree position, the scaled rows of C
+  // in tree order for the refinement residual
+  int4* gsrc = nullptr;
+  double* gscale = nullptr;
+  mrcm::CChunk* chunks = nullptr;
+  double *cfwd = nullptr, *cbwd = nullptr;
+  int *cidx = nullptr, *cdest = nullptr;
+  std::vector<std::pair<int, int>> fwd_levels, bwd_levels;
+  int maxp = 4, np = 0, max_nf = 1, max_nu = 1, refine = 0;
   int *crp = nullptr, *cci = nullptr;
   double* cv = nullptr;
-  // work space of one application and of GMRES
-  double *p = nullptr, *rho = nullptr, *mU = nullptr, *mP = nullptr, *g = nullptr, *x = nullptr;
-  double *res = nullptr, *dx = nullptr, *partials = nullptr;
+  // work space of one application and of GMRES (contrib: zero where unused)
+  double *p = nullptr, *rho = nullptr, *mU = nullptr, *mP = nullptr, *g_nd = nullptr;
+  double *x = nullptr, *rnd = nullptr, *dx = nullptr, *ybuf = nullptr, *contrib = nullptr;
+  double* partials = nullptr;
   int krylov_cap = 0;
   double *V = nullptr, *Z = nullptr, *hcol = nullptr, *parts = nullptr, *yd = nullptr;
   double *h_fetch = nullptr, *h_y = nullptr;  // pinned
@@ -68,12 +80,16 @@ struct mrcm3d_ctx {
     return static_cast<X*>(q);
   }
   template <typename X>
-  X* upload(const std::vector<X>& v) {
-    X* d = alloc<X>(v.size());
-    if (!v.empty())
-      check3(hipMemcpyAsync(d, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice, st),
+  X* upload(const X* v, size_t count) {
+    X* d = alloc<X>(count);
+    if (count)
+      check3(hipMemcpyAsync(d, v, count * sizeof(X), hipMemcpyHostToDevice, st),
              "hipMemcpyAsync");
     return d;
+  }
+  template <typename X>
+  X* upload(const std::vector<X>& v) {
+    return upload(v.data(), v.size());
   }
   void fold() {
     for (auto& mk : marks) {
@@ -156,6 +172,17 @@ hipEvent_t start_mark(mrcm3d_ctx* c) {
   return a;
 }
 
+// x = C^-1 g by the level-scheduled solve of the factor (g in tree order,
+// x by dof): forward levels leaves first, backward levels root first.
+void coarse_sweep(mrcm3d_ctx* c, const double* g, double* x, hipStream_t s) {
+  for (const auto& lv : c->fwd_levels)
+    mrcm::launch_coarse_fwd(c->chunks + lv.first, lv.second, c->cfwd, g, c->contrib, c->maxp,
+                            c->np, c->cdest, c->ybuf, c->cidx, x, c->max_nf, s);
+  for (const auto& lv : c->bwd_levels)
+    mrcm::launch_coarse_bwd(c->chunks + lv.first, lv.second, c->cbwd, c->cidx, c->ybuf, x,
+                            c->max_nu, s);
+}
+
 // z = T r on the context stream.
 void apply3(mrcm3d_ctx* c, const double* r, double* z) {
   hipStream_t s = c->st;
@@ -165,11 +192,13 @@ void apply3(mrcm3d_ctx* c, const double* r, double* z) {
   if (e) mark(c, 0, e);
   if (c->nc > 0) {
     e = start_mark(c);
-    mrcm3d::launch_coarse_rhs3(c->rowL, c->rowR, c->rowKind, c->mU, c->mP, c->g, c->nc, s);
-    mrcm3d::launch_gemv3(c->Cinv, c->g, c->x, c->nc, s);
-    mrcm3d::launch_csr_resid3(c->crp, c->cci, c->cv, c->g, c->x, c->res, c->nc, s);
-    mrcm3d::launch_gemv3(c->Cinv, c->res, c->dx, c->nc, s);
-    mrcm3d::launch_axpy3(c->x, c->dx, c->nc, s);
+    mrcm::launch_coarse_rhs(c->gsrc, c->gscale, c->mU, c->mP, c->g_nd, c->np, s);
+    coarse_sweep(c, c->g_nd, c->x, s);
+    for (int k = 0; k < c->refine; ++k) {
+      mrcm::launch_coarse_resid(1, c->crp, c->cci, c->cv, c->g_nd, c->x, c->rnd, c->np, c->nc, s);
+      coarse_sweep(c, c->rnd, c->dx, s);
+      mrcm::launch_coarse_add(c->x, c->dx, c->nc, s);
+    }
     if (e) mark(c, 1, e);
     e = start_mark(c);
     mrcm3d::launch_reconstruct3(c->lbox, c->m, c->mbf, c->mbf_off, c->dof_off, c->x, c->p, c->nx,
@@ -268,35 +297,47 @@ int mrcm3d_setup(const mrcm3d_grid* grid, const mrcm3d_params* params, const dou
     c->fin = c->upload(fin);
     c->fout = c->upload(fout);
     c->fw = c->upload(fw);
-    c->rowL = c->upload(S.rowL);
-    c->rowR = c->upload(S.rowR);
-    c->rowKind = c->upload(S.rowKind);
-    c->Cinv = c->upload(S.Cinv);
-    c->cinv_bytes = 8.0 * (double)S.Cinv.size();
-    std::vector<int> rp(S.nc + 1, 0), ci;
-    std::vector<double> cv;
-    for (int a = 0; a < S.nc; ++a) {
-      for (int b = 0; b < S.nc; ++b) {
-        const double v = S.C[(size_t)a * S.nc + b];
-        if (v != 0.0) {
-          ci.push_back(b);
-          cv.push_back(v);
-        }
-      }
-      rp[a + 1] = (int)ci.size();
+    if (S.nc > 0) {
+      const mrcm::CoarseFactor& F = S.CF;
+      mrcm::CoarseTables T = mrcm::coarse_tables(F, S.rowL.data(), S.rowR.data(),
+                                                 S.rowKind.data(), S.pin_row,
+                                                 std::max(1, omp_get_max_threads()));
+      static_assert(sizeof(int4) == sizeof(std::array<int, 4>), "gsrc layout");
+      c->gsrc = reinterpret_cast<int4*>(c->upload(&T.gsrc[0][0], 4 * T.gsrc.size()));
+      c->gscale = c->upload(F.nd_scale);
+      c->chunks = c->upload(T.chunks);
+      c->cfwd = c->upload(T.fwd.get(), (size_t)T.fwd_len);
+      c->cbwd = c->upload(T.bwd.get(), (size_t)T.bwd_len);
+      c->cidx = c->upload(T.idx);
+      c->cdest = c->upload(T.cdest);
+      c->fwd_levels = T.fwd_levels;
+      c->bwd_levels = T.bwd_levels;
+      c->maxp = F.maxp;
+      c->np = F.ylen;
+      c->max_nf = T.max_nf;
+      c->max_nu = T.max_nu;
+      c->refine = F.refine;
+      c->crp = c->upload(F.nd_rp);
+      c->cci = c->upload(F.nd_ci);
+      c->cv = c->upload(F.nd_v);
+      c->coarse_bytes = 8.0 * ((double)T.fwd_len + (double)T.bwd_len);
+      c->resid_bytes = 12.0 * (double)F.nd_v.size() + 4.0 * (c->np + 1) + 24.0 * c->np;
+      // the upload reads the host tables: finish it before they go
+      check3(hipStreamSynchronize(c->st), "hipStreamSynchronize");
     }
-    c->crp = c->upload(rp);
-    c->cci = c->upload(ci);
-    c->cv = c->upload(cv);
     const size_t nc = std::max(S.nc, 1);
     c->p = c->alloc<double>(S.n);
     c->rho = c->alloc<double>(S.n);
     c->mU = c->alloc<double>(nc);
     c->mP = c->alloc<double>(nc);
-    c->g = c->alloc<double>(nc);
+    c->g_nd = c->alloc<double>(nc);
     c->x = c->alloc<double>(nc);
-    c->res = c->alloc<double>(nc);
+    c->rnd = c->alloc<double>(nc);
     c->dx = c->alloc<double>(nc);
+    c->ybuf = c->alloc<double>(nc);
+    c->contrib = c->alloc<double>(nc * (size_t)c->maxp);
+    check3(hipMemsetAsync(c->contrib, 0, sizeof(double) * nc * (size_t)c->maxp, c->st),
+           "hipMemsetAsync");
     c->partials = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
     c->parts = c->alloc<double>(2 * mrcm::kMaxVecBlocks);
     check3(hipHostMalloc((void**)&c->h_fetch, sizeof(double) * (mrcm::kMaxVecBlocks + 256),
@@ -507,7 +548,9 @@ int mrcm3d_query(mrcm3d_ctx* c, int32_t what, double* value) {
     case 1: *value = (double)c->device_bytes; break;
     case 2: *value = c->nc; break;
     case 3: *value = c->factor_bytes; break;
-    case 4: *value = c->cinv_bytes; break;
+    case 4: *value = (1.0 + c->refine) * c->coarse_bytes + c->refine * c->resid_bytes; break;
+    case 5: *value = c->refine; break;
+    case 6: *value = (double)(c->fwd_levels.size() + c->bwd_levels.size()); break;
     default: return MRCM_EINVAL;
   }
   return MRCM_OK;

@@ -20,11 +20,6 @@ namespace {
 
 constexpr int kLeafArea = 16;  // boxes of at most this many subdomains are eliminated whole
 
-struct TreeNode {
-  std::vector<int> fsub, usub;
-  int depth;
-  std::vector<int> children;
-};
 
 // C rows [i0, i1) = alpha * A * B + beta * C (row-major, k inner terms).  A 4 x 16
 // tile of C is held in registers across the whole sum; every element adds its
@@ -164,25 +159,23 @@ double lu_inverse(std::vector<double>& A, int n, std::vector<double>& inv, int n
 
 CoarseFactor coarse_factor(const Maps& M, const std::vector<int>& rp, const std::vector<int>& ci,
                            const std::vector<double>& cv, int nthreads) {
-  CoarseFactor F;
   const int nc = M.nc();
-  F.nc = nc;
-  if (nc == 0) return F;
+  if (nc == 0) {
+    CoarseFactor F;
+    return F;
+  }
   // rows owned by each subdomain: flux rows -> L, pressure rows -> R
   std::vector<std::vector<int>> rows_of(M.m);
   for (int r = 0; r < nc; ++r) {
     const auto& e = M.edges[M.rows[r][0]];
     rows_of[M.rows[r][1] == 0 ? e[0] : e[1]].push_back(r);
   }
-  for (int i = 0; i < M.m; ++i)
-    if ((int)rows_of[i].size() != M.dof_offset[i + 1] - M.dof_offset[i])
-      throw Error(MRCM_EINVAL, "coarse row ownership is not square");
   // nested dissection on the mx x my subdomain grid
-  std::vector<TreeNode> tree;
+  std::vector<DissectionNode> tree;
   std::function<int(int, int, int, int, int)> build = [&](int x0, int x1, int y0, int y1,
                                                           int depth) -> int {
     if (x0 >= x1 || y0 >= y1) return -1;
-    TreeNode nd;
+    DissectionNode nd;
     nd.depth = depth;
     if ((x1 - x0) * (y1 - y0) <= kLeafArea) {
       for (int y = y0; y < y1; ++y)
@@ -226,6 +219,21 @@ CoarseFactor coarse_factor(const Maps& M, const std::vector<int>& rp, const std:
     return (int)tree.size() - 1;
   };
   build(0, M.mx, 0, M.my, 0);
+  return coarse_factor_tree(tree, rows_of, M.dof_offset, rp, ci, cv, nthreads);
+}
+
+CoarseFactor coarse_factor_tree(const std::vector<DissectionNode>& tree,
+                                const std::vector<std::vector<int>>& rows_of,
+                                const std::vector<int32_t>& dof_offset,
+                                const std::vector<int>& rp, const std::vector<int>& ci,
+                                const std::vector<double>& cv, int nthreads) {
+  CoarseFactor F;
+  const int nc = dof_offset.empty() ? 0 : dof_offset.back();
+  F.nc = nc;
+  if (nc == 0) return F;
+  for (size_t i = 0; i + 1 < dof_offset.size(); ++i)
+    if ((int)rows_of[i].size() != dof_offset[i + 1] - dof_offset[i])
+      throw Error(MRCM_EINVAL, "coarse row ownership is not square");
   const int nn = (int)tree.size();
   F.nodes.resize(nn);
   int maxdepth = 0;
@@ -235,11 +243,11 @@ CoarseFactor coarse_factor(const Maps& M, const std::vector<int>& rp, const std:
     maxdepth = std::max(maxdepth, cn.depth);
     for (int s : tree[t].fsub) {
       cn.frow.insert(cn.frow.end(), rows_of[s].begin(), rows_of[s].end());
-      for (int k = M.dof_offset[s]; k < M.dof_offset[s + 1]; ++k) cn.fcol.push_back(k);
+      for (int k = dof_offset[s]; k < dof_offset[s + 1]; ++k) cn.fcol.push_back(k);
     }
     for (int s : tree[t].usub) {
       cn.urow.insert(cn.urow.end(), rows_of[s].begin(), rows_of[s].end());
-      for (int k = M.dof_offset[s]; k < M.dof_offset[s + 1]; ++k) cn.ucol.push_back(k);
+      for (int k = dof_offset[s]; k < dof_offset[s + 1]; ++k) cn.ucol.push_back(k);
     }
   }
   F.depth = maxdepth;
@@ -382,6 +390,81 @@ CoarseFactor coarse_factor(const Maps& M, const std::vector<int>& rp, const std:
     }
   }
   return F;
+}
+
+CoarseTables coarse_tables(const CoarseFactor& F, const int32_t* rowL, const int32_t* rowR,
+                           const int32_t* rowKind, int pin_row, int nthreads) {
+  CoarseTables T;
+  const int nn = (int)F.nodes.size();
+  std::vector<long long> fwd_off(nn), bwd_off(nn);
+  std::vector<int> fcol_off(nn), ucol_off(nn);
+  for (int t = 0; t < nn; ++t) {
+    const auto& cn = F.nodes[t];
+    fcol_off[t] = (int)T.idx.size();
+    T.idx.insert(T.idx.end(), cn.fcol.begin(), cn.fcol.end());
+    ucol_off[t] = (int)T.idx.size();
+    T.idx.insert(T.idx.end(), cn.ucol.begin(), cn.ucol.end());
+    fwd_off[t] = T.fwd_len;
+    T.fwd_len += (long long)cn.fwd.size();
+    bwd_off[t] = T.bwd_len;
+    T.bwd_len += (long long)cn.bwd.size();
+    T.max_nf = std::max(T.max_nf, (int)cn.frow.size());
+    T.max_nu = std::max(T.max_nu, (int)cn.urow.size());
+  }
+  if (T.max_nf > kMaxCoarseFront || T.max_nu > kMaxCoarseFront)
+    throw Error(MRCM_EINVAL, "interface separator too large for one workgroup");
+  // the node matrices, concatenated by the host threads (uninitialised
+  // storage: every element is written)
+  T.fwd.reset(new double[std::max(T.fwd_len, 1LL)]);
+  T.bwd.reset(new double[std::max(T.bwd_len, 1LL)]);
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
+  for (int t = 0; t < nn; ++t) {
+    const auto& cn = F.nodes[t];
+    std::copy(cn.fwd.begin(), cn.fwd.end(), T.fwd.get() + fwd_off[t]);
+    std::copy(cn.bwd.begin(), cn.bwd.end(), T.bwd.get() + bwd_off[t]);
+  }
+  // 16 rows per chunk: one group of four rows per wave
+  constexpr int step = 16;
+  for (int d = F.depth; d >= 0; --d) {
+    const int first = (int)T.chunks.size();
+    for (int t = 0; t < nn; ++t) {
+      const auto& cn = F.nodes[t];
+      if (cn.depth != d) continue;
+      const int nf = (int)cn.frow.size(), nu = (int)cn.urow.size(), rows = nf + nu;
+      for (int r0 = 0; r0 < rows; r0 += step)
+        T.chunks.push_back(CChunk{r0, std::min(rows, r0 + step), nf, nu, cn.yoff, cn.coff,
+                                  fcol_off[t], ucol_off[t], fwd_off[t]});
+    }
+    T.fwd_levels.push_back({first, (int)T.chunks.size() - first});
+  }
+  for (int d = 0; d <= F.depth; ++d) {
+    const int first = (int)T.chunks.size();
+    for (int t = 0; t < nn; ++t) {
+      const auto& cn = F.nodes[t];
+      if (cn.depth != d) continue;
+      const int nf = (int)cn.frow.size(), nu = (int)cn.urow.size();
+      if (nu == 0) continue;  // x_F = y_F, written by the forward level
+      for (int r0 = 0; r0 < nf; r0 += step)
+        T.chunks.push_back(CChunk{r0, std::min(nf, r0 + step), nf, nu, cn.yoff, cn.coff,
+                                  fcol_off[t], ucol_off[t], bwd_off[t]});
+    }
+    if ((int)T.chunks.size() > first) T.bwd_levels.push_back({first, (int)T.chunks.size() - first});
+  }
+  // right-hand-side sources and contribution destinations by tree position
+  const int np = F.ylen;
+  T.gsrc.resize(np);
+  for (int t = 0; t < np; ++t) {
+    const int row = F.nd_row[t];
+    const int kind = row == pin_row ? 2 : rowKind[row];
+    T.gsrc[t] = {rowL[row], rowR[row], kind, 0};
+  }
+  T.cdest.assign(std::max(F.clen, 1), 0);
+  for (int t = 0; t < np; ++t)
+    for (int u = 0; u < F.maxp; ++u) {
+      const int q = F.slots[(size_t)t * F.maxp + u];
+      if (q >= 0) T.cdest[q] = u * np + t;
+    }
+  return T;
 }
 
 void coarse_residual_host(const CoarseFactor& F, const double* g_nd, const double* x,

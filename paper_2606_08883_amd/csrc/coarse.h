@@ -17,6 +17,8 @@
 //   backward, root to leaves: x_F = y_F - G x_U.
 #pragma once
 
+#include <memory>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -55,9 +57,72 @@ struct CoarseFactor {
   int refine = 0;
 };
 
+// A chunk of one level of the interface solve: rows [row0, row1) of one
+// node's forward ([W; E], (nf + nu) x nf) or backward (G, nf x nu) matrix,
+// with the node's sizes and offsets copied in so that a workgroup needs one
+// descriptor load: mat, the matrix offset; yoff, the node's first tree
+// position (its y_F rows); coff, its first contribution row; fcol, ucol,
+// offsets of its separator and border dof lists in the index array.
+struct CChunk {
+  int row0, row1, nf, nu;
+  int yoff, coff, fcol, ucol;
+  long long mat;
+};
+
+// The tables of the level-scheduled GPU solve of a factor, built on the host
+// and uploaded as they are:
+//   idx            separator and border dof lists of every node, concatenated;
+//   fwd, bwd       the node matrices, concatenated (fwd_len, bwd_len words);
+//   chunks         16 rows each, forward levels leaves first (fwd_levels:
+//                  first chunk and count per level), then backward levels
+//                  root first (bwd_levels); a node without border rows has
+//                  no backward chunk;
+//   gsrc           per tree position t: the two dofs of its row, its kind
+//                  (0 flux, 1 pressure, 2 pinned) and 0;
+//   cdest          per contribution row q: the slot u * np + t it adds to;
+//   max_nf, max_nu the largest separator and border of a node.
+struct CoarseTables {
+  std::vector<int> idx;
+  std::unique_ptr<double[]> fwd, bwd;
+  long long fwd_len = 0, bwd_len = 0;
+  std::vector<CChunk> chunks;
+  std::vector<std::pair<int, int>> fwd_levels, bwd_levels;
+  std::vector<std::array<int, 4>> gsrc;
+  std::vector<int> cdest;
+  int max_nf = 1, max_nu = 1;
+};
+// rowL, rowR, rowKind: per interface row, the dofs whose trace moments it
+// combines and its kind; pin_row (or -1) takes kind 2.  Separators or borders
+// above kMaxCoarseFront rows are rejected (MRCM_EINVAL): the solve holds a
+// node's vector in LDS.
+constexpr int kMaxCoarseFront = 6144;
+CoarseTables coarse_tables(const CoarseFactor& F, const int32_t* rowL, const int32_t* rowR,
+                           const int32_t* rowKind, int pin_row, int nthreads);
+
 // Factor C (CSR over rows x dofs) for the maps' subdomain grid.
 CoarseFactor coarse_factor(const Maps& M, const std::vector<int>& rp, const std::vector<int>& ci,
                            const std::vector<double>& cv, int nthreads);
+
+// A node of a dissection tree over the subdomains: the subdomains whose rows
+// and dofs it eliminates (fsub), those bordering its region (usub, sorted),
+// its depth (root 0) and children.  Rows of a subdomain couple only to dofs of
+// itself and its face neighbours, so a region's interior and the rest of the
+// grid meet only through its border.
+struct DissectionNode {
+  std::vector<int> fsub, usub;
+  int depth = 0;
+  std::vector<int> children;
+};
+
+// Factor C for a given tree (post-order: children before their parent).
+// rows_of[i] lists the coarse rows owned by subdomain i, as many as its dofs
+// dof_offset[i] .. dof_offset[i + 1] - 1.  Any grid of subdomains (2-D or
+// 3-D) with such a tree; coarse_factor builds the 2-D one.
+CoarseFactor coarse_factor_tree(const std::vector<DissectionNode>& tree,
+                                const std::vector<std::vector<int>>& rows_of,
+                                const std::vector<int32_t>& dof_offset,
+                                const std::vector<int>& rp, const std::vector<int>& ci,
+                                const std::vector<double>& cv, int nthreads);
 // Host reference of the level-scheduled solve (used to check the factor).
 // g_nd: the scaled right-hand side in tree order
 // (g_nd[t] = nd_scale[t] * g[nd_row[t]]).

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 
+#include "coarse.h"
 #include "setup_jobs.h"
 
 namespace mrcm {
@@ -19,18 +20,6 @@ struct BoxDesc {
   int bs;          // stride between D_j^-1 blocks (words, a multiple of 16 bytes)
   long long doff;  // offset of the first D_j^-1 block (elements, 16-byte aligned)
   long long coff;  // offset of the couplings T_j (elements)
-};
-
-// A chunk of one level of the interface solve: rows [row0, row1) of one
-// node's forward ([W; E], (nf + nu) x nf) or backward (G, nf x nu) matrix,
-// with the node's sizes and offsets copied in so that a workgroup needs one
-// descriptor load: mat, the matrix offset; yoff, the node's first tree
-// position (its y_F rows); coff, its first contribution row; fcol, ucol,
-// offsets of its separator and border dof lists in the index array.
-struct CChunk {
-  int row0, row1, nf, nu;
-  int yoff, coff, fcol, ucol;
-  long long mat;
 };
 
 constexpr int kBoxThreads = 256;

@@ -37,16 +37,6 @@ void launch_local3(const Box3* boxes, int m, const double* dinv, const double* c
 // Patch solves of the smoothing sweep: p += A[S_i]^-1 rho[S_i] on the owned cells.
 void launch_patch3(const Box3* boxes, int m, const double* dinv, const double* coup,
                    const double* rho, double* p, int nx, int ny, hipStream_t s);
-// Interface right-hand side: g[t] = -(mU[L] + mU[R]) (flux rows), -(mP[L] -
-// mP[R]) (pressure rows), 0 for the pinned row.
-void launch_coarse_rhs3(const int* rowL, const int* rowR, const int* kind, const double* mU,
-                        const double* mP, double* g, int nc, hipStream_t s);
-// y = M x, M dense row-major n x n (one wave per row).
-void launch_gemv3(const double* M, const double* x, double* y, int n, hipStream_t s);
-// r = g - C x with C in CSR (one thread per row).
-void launch_csr_resid3(const int* rp, const int* ci, const double* v, const double* g,
-                       const double* x, double* r, int n, hipStream_t s);
-void launch_axpy3(double* x, const double* dx, int n, hipStream_t s);
 // p[Omega_i] += P_i x_i (one workgroup per subdomain; mbf_off per subdomain).
 void launch_reconstruct3(const Box3* boxes, int m, const double* mbf, const long long* mbf_off,
                          const int* dof_off, const double* x, double* p, int nx, int ny,

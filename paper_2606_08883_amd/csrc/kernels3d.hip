@@ -1,8 +1,8 @@
 // HIP kernels of the 3-D path (include/mrcm3d.h), FP64: plane-block LDL^T
 // box solves (one workgroup per box, one thread per cell of a plane), trace
-// moments with tensor Legendre test functions, the interface solve through a
-// dense inverse with one refinement step, reconstruction, and the
-// seven-point operator in its forms for smoothing and GMRES.  Every
+// moments with tensor Legendre test functions, reconstruction, and the
+// seven-point operator in its forms for smoothing and GMRES (the interface
+// solve runs the level kernels of the 2-D path on the 3-D factor).  Every
 // reduction has a fixed order.
 #include "device3d.h"
 
@@ -136,53 +136,10 @@ __global__ void __launch_bounds__(kBox3Threads)
   }
 }
 
-__global__ void k_coarse_rhs3(const int* __restrict__ rowL, const int* __restrict__ rowR,
-                              const int* __restrict__ kind, const double* __restrict__ mU,
-                              const double* __restrict__ mP, double* __restrict__ g, int nc) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nc) return;
-  const int k = kind[t], L = rowL[t], R = rowR[t];
-  g[t] = k == 2 ? 0.0 : k == 0 ? -(mU[L] + mU[R]) : -(mP[L] - mP[R]);
-}
-
 __device__ __forceinline__ double wave_sum3(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
-}
-
-// One wave per row; lanes take columns lane, lane + 64, ... in order.
-__global__ void __launch_bounds__(kVec3Threads)
-    k_gemv3(const double* __restrict__ M, const double* __restrict__ x, double* __restrict__ y,
-            int n) {
-  const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (row >= n) return;
-  const double* Mr = M + (long long)row * n;
-  double a0 = 0.0, a1 = 0.0;
-  int c = lane;
-  for (; c + 64 < n; c += 128) {
-    a0 = fma(Mr[c], x[c], a0);
-    a1 = fma(Mr[c + 64], x[c + 64], a1);
-  }
-  if (c < n) a0 = fma(Mr[c], x[c], a0);
-  const double s = wave_sum3(a0 + a1);
-  if (lane == 0) y[row] = s;
-}
-
-__global__ void k_csr_resid3(const int* __restrict__ rp, const int* __restrict__ ci,
-                             const double* __restrict__ v, const double* __restrict__ g,
-                             const double* __restrict__ x, double* __restrict__ r, int n) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  double s = g[t];
-  for (int q = rp[t]; q < rp[t + 1]; ++q) s = fma(-v[q], x[ci[q]], s);
-  r[t] = s;
-}
-
-__global__ void k_axpy3(double* __restrict__ x, const double* __restrict__ dx, int n) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) x[t] += dx[t];
 }
 
 __global__ void __launch_bounds__(kBox3Threads)
@@ -298,25 +255,6 @@ void launch_patch3(const Box3* boxes, int m, const double* dinv, const double* c
   const size_t shm = sizeof(double) * (kMaxBox3Cells + kBox3Threads);
   hipLaunchKernelGGL(k_patch3, dim3(m), dim3(kBox3Threads), shm, s, boxes, dinv, coup, rho, p,
                      nx, ny);
-}
-void launch_coarse_rhs3(const int* rowL, const int* rowR, const int* kind, const double* mU,
-                        const double* mP, double* g, int nc, hipStream_t s) {
-  if (nc <= 0) return;
-  hipLaunchKernelGGL(k_coarse_rhs3, dim3((nc + 255) / 256), dim3(256), 0, s, rowL, rowR, kind, mU,
-                     mP, g, nc);
-}
-void launch_gemv3(const double* M, const double* x, double* y, int n, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_gemv3, dim3((n + 3) / 4), dim3(kVec3Threads), 0, s, M, x, y, n);
-}
-void launch_csr_resid3(const int* rp, const int* ci, const double* v, const double* g,
-                       const double* x, double* r, int n, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_csr_resid3, dim3((n + 255) / 256), dim3(256), 0, s, rp, ci, v, g, x, r, n);
-}
-void launch_axpy3(double* x, const double* dx, int n, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_axpy3, dim3((n + 255) / 256), dim3(256), 0, s, x, dx, n);
 }
 void launch_reconstruct3(const Box3* boxes, int m, const double* mbf, const long long* mbf_off,
                          const int* dof_off, const double* x, double* p, int nx, int ny,

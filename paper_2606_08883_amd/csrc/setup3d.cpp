@@ -13,6 +13,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
+#include <tuple>
 
 namespace mrcm3d {
 
@@ -255,54 +257,6 @@ PlaneFactor factor_box(const Setup& S, const Box& b, bool robin) {
   return F;
 }
 
-// Dense inverse of an n x n row-major matrix by LU with partial pivoting.
-void dense_inverse(const std::vector<double>& A, int n, std::vector<double>& Ainv) {
-  std::vector<double> M(A);
-  std::vector<int> perm(n);
-  for (int i = 0; i < n; ++i) perm[i] = i;
-  for (int k = 0; k < n; ++k) {
-    int piv = k;
-    double best = std::fabs(M[(size_t)k * n + k]);
-    for (int i = k + 1; i < n; ++i)
-      if (std::fabs(M[(size_t)i * n + k]) > best) {
-        best = std::fabs(M[(size_t)i * n + k]);
-        piv = i;
-      }
-    if (!(best > 0.0) || !std::isfinite(best))
-      throw Error(MRCM_ESINGULAR, "singular interface system");
-    if (piv != k) {
-      for (int c = 0; c < n; ++c) std::swap(M[(size_t)k * n + c], M[(size_t)piv * n + c]);
-      std::swap(perm[k], perm[piv]);
-    }
-    const double inv = 1.0 / M[(size_t)k * n + k];
-#pragma omp parallel for schedule(static)
-    for (int i = k + 1; i < n; ++i) {
-      const double f = M[(size_t)i * n + k] * inv;
-      M[(size_t)i * n + k] = f;
-      if (f != 0.0)
-        for (int c = k + 1; c < n; ++c) M[(size_t)i * n + c] -= f * M[(size_t)k * n + c];
-    }
-  }
-  // columns of the inverse: solve L U x = e_perm
-  Ainv.assign((size_t)n * n, 0.0);
-#pragma omp parallel for schedule(dynamic, 16)
-  for (int col = 0; col < n; ++col) {
-    std::vector<double> x(n, 0.0);
-    for (int i = 0; i < n; ++i) x[i] = perm[i] == col ? 1.0 : 0.0;
-    for (int i = 0; i < n; ++i) {
-      double s = x[i];
-      for (int k = 0; k < i; ++k) s -= M[(size_t)i * n + k] * x[k];
-      x[i] = s;
-    }
-    for (int i = n - 1; i >= 0; --i) {
-      double s = x[i];
-      for (int k = i + 1; k < n; ++k) s -= M[(size_t)i * n + k] * x[k];
-      x[i] = s / M[(size_t)i * n + i];
-    }
-    for (int i = 0; i < n; ++i) Ainv[(size_t)i * n + col] = x[i];
-  }
-}
-
 // Values of a box-local solution at a global cell.
 inline double at(const Box& b, const double* v, long long cell, const Setup& S) {
   const int x = (int)(cell % S.nx), y = (int)((cell / S.nx) % S.ny), z = (int)(cell / ((long long)S.nx * S.ny));
@@ -470,7 +424,6 @@ void host_setup(Setup& S, const mrcm3d_grid& g, const mrcm3d_params& p, const do
     face_at[(size_t)L * 6 + 2 * a + 1] = (int)f;
     face_at[(size_t)R * 6 + 2 * a] = (int)f;
   }
-  if (S.nc > 16384) throw Error(MRCM_EINVAL, "interface system too large for its dense inverse");
   // face data of every side of Gamma_i: weights of the traces of a solution
   // with zero Robin data
   S.gam.resize(S.m);
@@ -491,7 +444,8 @@ void host_setup(Setup& S, const mrcm3d_grid& g, const mrcm3d_params& p, const do
   S.over.resize(S.m);
   S.patch.resize(S.sweeps > 0 ? S.m : 0);
   S.mbf.resize(S.m);
-  S.C.assign((size_t)S.nc * S.nc, 0.0);
+  // entries of C by column owner: (row, column, value), each written once
+  std::vector<std::vector<std::tuple<int, int, double>>> centries(S.m);
   int err = 0;
   std::string msg;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -554,8 +508,8 @@ void host_setup(Setup& S, const mrcm3d_grid& g, const mrcm3d_params& p, const do
               const int r0 = S.row_off[fidx];
               const int nbf = (S.row_off[fidx + 1] - r0) / 2;
               const double sign = d.side % 2 == 1 ? 1.0 : -1.0;
-              S.C[(size_t)(r0 + q) * S.nc + col] += su;
-              S.C[(size_t)(r0 + nbf + q) * S.nc + col] += sign * sp;
+              centries[i].emplace_back(r0 + q, col, su);
+              centries[i].emplace_back(r0 + nbf + q, col, sign * sp);
             }
         }
       }
@@ -568,15 +522,95 @@ void host_setup(Setup& S, const mrcm3d_grid& g, const mrcm3d_params& p, const do
     }
   }
   if (err) throw Error(err, msg);
+  // C in CSR; with no flow on every side the first flux row of the first
+  // interface is replaced by the pin of its lower subdomain's first dof
+  int pin_col = -1;
   if (S.noflow && !S.faces.empty()) {
     const int L0 = S.faces[0][0], a0 = S.faces[0][2];
-    const int col = dof_of(L0, 2 * a0 + 1, 0);
+    pin_col = dof_of(L0, 2 * a0 + 1, 0);
     S.pin_row = 0;
-    std::fill(S.C.begin(), S.C.begin() + S.nc, 0.0);
-    S.C[(size_t)col] = 1.0;
     S.rowKind[0] = 2;
   }
-  if (S.nc > 0) dense_inverse(S.C, S.nc, S.Cinv);
+  std::vector<std::vector<std::pair<int, double>>> rows(S.nc);
+  for (int i = 0; i < S.m; ++i)
+    for (const auto& e : centries[i])
+      if (std::get<0>(e) != S.pin_row) rows[std::get<0>(e)].push_back({std::get<1>(e), std::get<2>(e)});
+  if (S.pin_row >= 0) rows[S.pin_row].push_back({pin_col, 1.0});
+  S.Crp.assign(S.nc + 1, 0);
+  for (int r = 0; r < S.nc; ++r) {
+    std::sort(rows[r].begin(), rows[r].end());
+    for (const auto& e : rows[r]) {
+      S.Cci.push_back(e.first);
+      S.Cv.push_back(e.second);
+    }
+    S.Crp[r + 1] = (int)S.Cci.size();
+  }
+  if (S.nc > 0) {
+    // rows owned by each subdomain: flux rows by the lower one, pressure rows
+    // by the upper one (as many as its dofs)
+    std::vector<std::vector<int>> rows_of(S.m);
+    for (int r = 0; r < S.nc; ++r) {
+      const int f = (int)(std::upper_bound(S.row_off.begin(), S.row_off.end(), r) -
+                          S.row_off.begin()) - 1;
+      const int nbf = (S.row_off[f + 1] - S.row_off[f]) / 2;
+      rows_of[r - S.row_off[f] < nbf ? S.faces[f][0] : S.faces[f][1]].push_back(r);
+    }
+    S.CF = mrcm::coarse_factor_tree(dissection3(S.mdims[0], S.mdims[1], S.mdims[2]), rows_of,
+                                    S.dof_off, S.Crp, S.Cci, S.Cv,
+                                    std::max(1, omp_get_max_threads()));
+    mrcm::coarse_refine_steps(S.CF, mrcm::kCoarseRefineTol, mrcm::kCoarseRefineMax);
+  }
+}
+
+std::vector<mrcm::DissectionNode> dissection3(int mx, int my, int mz) {
+  std::vector<mrcm::DissectionNode> tree;
+  const int dims[3] = {mx, my, mz};
+  auto id = [&](int x, int y, int z) { return (z * my + y) * mx + x; };
+  std::function<int(std::array<int, 3>, std::array<int, 3>, int)> build =
+      [&](std::array<int, 3> lo, std::array<int, 3> hi, int depth) -> int {
+    for (int a = 0; a < 3; ++a)
+      if (lo[a] >= hi[a]) return -1;
+    mrcm::DissectionNode nd;
+    nd.depth = depth;
+    const int ext[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
+    auto add_region = [&](std::array<int, 3> l, std::array<int, 3> h, std::vector<int>& out) {
+      for (int z = l[2]; z < h[2]; ++z)
+        for (int y = l[1]; y < h[1]; ++y)
+          for (int x = l[0]; x < h[0]; ++x) out.push_back(id(x, y, z));
+    };
+    if (ext[0] * ext[1] * ext[2] <= 8) {
+      add_region(lo, hi, nd.fsub);
+    } else {
+      int ax = 0;
+      for (int a = 1; a < 3; ++a)
+        if (ext[a] > ext[ax]) ax = a;
+      const int mid = (lo[ax] + hi[ax]) / 2;
+      std::array<int, 3> h1 = hi, l2 = lo, pl = lo, ph = hi;
+      h1[ax] = mid;
+      l2[ax] = mid + 1;
+      pl[ax] = mid;
+      ph[ax] = mid + 1;
+      const int c1 = build(lo, h1, depth + 1), c2 = build(l2, hi, depth + 1);
+      if (c1 >= 0) nd.children.push_back(c1);
+      if (c2 >= 0) nd.children.push_back(c2);
+      add_region(pl, ph, nd.fsub);
+    }
+    // the border: the face neighbours of the region outside it
+    for (int a = 0; a < 3; ++a)
+      for (int side = 0; side < 2; ++side) {
+        const int at = side == 0 ? lo[a] - 1 : hi[a];
+        if (at < 0 || at >= dims[a]) continue;
+        std::array<int, 3> l = lo, h = hi;
+        l[a] = at;
+        h[a] = at + 1;
+        add_region(l, h, nd.usub);
+      }
+    std::sort(nd.usub.begin(), nd.usub.end());
+    tree.push_back(nd);
+    return (int)tree.size() - 1;
+  };
+  build({0, 0, 0}, {mx, my, mz}, 0);
+  return tree;
 }
 
 void host_op_apply(const Setup& S, const double* x, double* y) {
@@ -635,24 +669,17 @@ void host_apply(const Setup& S, const double* r, double* z) {
       mP[k] = sp;
     }
   }
-  std::vector<double> g(S.nc), x(S.nc, 0.0), res(S.nc), dx(S.nc);
+  std::vector<double> g(S.nc), x(S.nc, 0.0);
   for (int t = 0; t < S.nc; ++t) {
     const int L = S.rowL[t], R = S.rowR[t];
     g[t] = S.rowKind[t] == 2 ? 0.0
            : S.rowKind[t] == 0 ? -(mU[L] + mU[R]) : -(mP[L] - mP[R]);
   }
-  auto gemv = [&](const std::vector<double>& M, const std::vector<double>& v, std::vector<double>& o) {
-    for (int a = 0; a < S.nc; ++a) {
-      double s = 0.0;
-      for (int c = 0; c < S.nc; ++c) s += M[(size_t)a * S.nc + c] * v[c];
-      o[a] = s;
-    }
-  };
-  gemv(S.Cinv, g, x);
-  gemv(S.C, x, res);
-  for (int t = 0; t < S.nc; ++t) res[t] = g[t] - res[t];
-  gemv(S.Cinv, res, dx);
-  for (int t = 0; t < S.nc; ++t) x[t] += dx[t];
+  if (S.nc > 0) {
+    std::vector<double> gnd(S.nc);
+    for (int t = 0; t < S.nc; ++t) gnd[t] = S.CF.nd_scale[t] * g[S.CF.nd_row[t]];
+    mrcm::coarse_solve_refined_host(S.CF, gnd.data(), x.data());
+  }
   for (int i = 0; i < S.m; ++i) {
     const Box& bi = S.boxes[i];
     const int Ni = S.dof_off[i + 1] - S.dof_off[i];

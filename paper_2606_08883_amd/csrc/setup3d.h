@@ -1,7 +1,7 @@
 // Host-side FP64 set-up of T on 3-D grids (include/mrcm3d.h): maps, face
 // transmissibilities, plane-block LDL^T factors of the oversampled boxes and
-// patches, multiscale basis functions, the interface system and its dense
-// inverse, and the tables the device apply reads.
+// patches, multiscale basis functions, the interface system with its
+// nested-dissection factor, and the tables the device apply reads.
 #pragma once
 
 #include <array>
@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/mrcm3d.h"
+#include "coarse.h"
 #include "internal.h"
 
 namespace mrcm3d {
@@ -65,9 +66,16 @@ struct Setup {
   int nc = 0, pin_row = -1;
   std::vector<PlaneFactor> over, patch;
   std::vector<std::vector<double>> mbf;    // per subdomain: Ni x cells of Omega_i, basis-major
-  std::vector<double> C;                   // nc x nc, row-major
-  std::vector<double> Cinv;                // nc x nc, row-major
+  std::vector<int> Crp, Cci;               // the interface matrix C in CSR (columns ascending)
+  std::vector<double> Cv;
+  mrcm::CoarseFactor CF;                   // its factor over a dissection of the subdomain grid
 };
+
+// Dissection tree of an mx x my x mz subdomain grid (post-order): a region of
+// more than eight subdomains is split across its longest axis by the plane of
+// subdomains at its middle, which becomes the node's separator; smaller
+// regions are eliminated whole.
+std::vector<mrcm::DissectionNode> dissection3(int mx, int my, int mz);
 
 long long cell_of(const Setup& S, int x, int y, int z);
 void host_setup(Setup& S, const mrcm3d_grid& g, const mrcm3d_params& p, const double* K);

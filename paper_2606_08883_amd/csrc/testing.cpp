@@ -45,6 +45,35 @@ int mrcm3d_test_host_apply(const mrcm3d_grid* grid, const mrcm3d_params* params,
   }
 }
 
+int mrcm3d_test_dissection(int32_t mx, int32_t my, int32_t mz, int32_t* elim, int32_t* parent,
+                           int32_t* depth, int32_t* border_ptr, int32_t* border,
+                           int32_t max_nodes, int32_t max_border, int32_t* nodes) {
+  try {
+    if (mx < 1 || my < 1 || mz < 1 || !elim || !parent || !depth || !border_ptr || !border ||
+        !nodes)
+      throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+    const std::vector<mrcm::DissectionNode> tree = mrcm3d::dissection3(mx, my, mz);
+    const int nn = (int)tree.size();
+    size_t nb = 0;
+    for (const auto& nd : tree) nb += nd.usub.size();
+    if (nn > max_nodes || (long long)nb > max_border)
+      throw mrcm::Error(MRCM_EINVAL, "capacity too small");
+    for (int t = 0; t < nn; ++t) parent[t] = -1;
+    border_ptr[0] = 0;
+    for (int t = 0; t < nn; ++t) {
+      depth[t] = tree[t].depth;
+      for (int c : tree[t].children) parent[c] = t;
+      for (int s : tree[t].fsub) elim[s] = t;
+      std::copy(tree[t].usub.begin(), tree[t].usub.end(), border + border_ptr[t]);
+      border_ptr[t + 1] = border_ptr[t] + (int32_t)tree[t].usub.size();
+    }
+    *nodes = nn;
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    return fail(e);
+  }
+}
+
 int mrcm_test_zero_cell_setup(const mrcm_grid* grid, const mrcm_params* params,
                               const double* K, int64_t cell) {
   try {

@@ -5,7 +5,9 @@ solves, no coupling).  It only draws or evaluates problem data, and both the
 HIP path and the oracle receive its arrays as inputs.
 
 Cell ``(ix, iy)`` of an ``nx x ny`` grid has id ``iy * nx + ix`` (x fastest);
-cell (0, 0) touches the corner x = 0, y = 0.  Arrays are float64, length n.
+cell (0, 0) touches the corner x = 0, y = 0.  On an ``nx x ny x nz`` grid cell
+``(ix, iy, iz)`` has id ``(iz * ny + iy) * nx + ix``.  Arrays are float64,
+length n.
 
 Field recipes (stand-ins for the paper's workloads; the paper's SPE10 layers
 and inclusion geometries are not reproduced):
@@ -15,6 +17,8 @@ and inclusion geometries are not reproduced):
   with the kernel exp(-2 t^2 / ell^2) normalised to unit L2 norm, then cropped.
   This gives unit variance and covariance exp(-r^2 / ell^2).
 * Log-normal K = exp(sigma * G).
+* 3-D Gaussian random field: the same recipe on an (nz, ny, nx) array, one
+  correlation length on every axis, convolved along x, then y, then z.
 * Channel facies: chi = [G(ell_x, ell_y) > 0]; K = k_hi on chi, k_lo elsewhere.
 * Mixture (contrast 1e8): channel facies chi = [G1(160, 24) > 0] at a facies
   contrast of 1e4 times a log-normal factor, K_raw = exp(G2) * (chi + 1e-4
@@ -65,6 +69,22 @@ def gaussian_field(nx: int, ny: int, ell_x: float, ell_y: float | None = None,
 
 def lognormal_K(nx: int, ny: int, sigma: float, ell: float, seed: int) -> np.ndarray:
     return np.exp(sigma * gaussian_field(nx, ny, ell, ell, seed)).ravel()
+
+
+def gaussian_field3(nx: int, ny: int, nz: int, ell: float, seed: int) -> np.ndarray:
+    """Unit-variance 3-D Gaussian field with Gaussian covariance, shape (nz, ny, nx)."""
+    pad = int(math.ceil(3.0 * ell))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w = rng.standard_normal((nz + 2 * pad, ny + 2 * pad, nx + 2 * pad))
+    k = _kernel(ell)
+    g = fftconvolve(w, k[None, None, :], mode="same", axes=2)
+    g = fftconvolve(g, k[None, :, None], mode="same", axes=1)
+    g = fftconvolve(g, k[:, None, None], mode="same", axes=0)
+    return np.ascontiguousarray(g[pad:pad + nz, pad:pad + ny, pad:pad + nx])
+
+
+def lognormal_K3(nx: int, ny: int, nz: int, sigma: float, ell: float, seed: int) -> np.ndarray:
+    return np.exp(sigma * gaussian_field3(nx, ny, nz, ell, seed)).ravel()
 
 
 def channel_K(nx: int, ny: int, ell_x: float, ell_y: float, seed: int,
@@ -128,6 +148,14 @@ def corner_sources(nx: int, ny: int) -> np.ndarray:
     b = np.zeros(nx * ny)
     b[0] = 1.0
     b[nx * ny - 1] = -1.0
+    return b
+
+
+def corner_sources3(nx: int, ny: int, nz: int) -> np.ndarray:
+    """Point injector +1 in cell (0, 0, 0) and producer -1 in the opposite corner cell."""
+    b = np.zeros(nx * ny * nz)
+    b[0] = 1.0
+    b[-1] = -1.0
     return b
 
 

@@ -130,3 +130,41 @@ def test_oversized_3d_box_rejected(dev):
     with pytest.raises(B.MrcmError) as e:   # 20 x 20 planes exceed 256 cells
         B.Context3(B.Config3(20, 20, 8, (1,) * 6, 20, 20, 8, 0), K)
     assert e.value.code == B.MRCM_EINVAL
+
+
+def test_cube_workload_on_the_device(dev):
+    """The 96^3 cube workload (1728 subdomains of 8^3, 38016 interface dofs, a
+    dissection with separators of up to 144 subdomains): T on the device
+    against the library's host evaluation of the same tables (pinned to the
+    oracle on the grids above), and GMRES to 1e-8 with the true residual
+    recomputed by the device operator."""
+    from paper_2606_08883_amd.configs import WORKLOADS3
+    w = WORKLOADS3["cube"]
+    cfg = w.binding_config()
+    n = w.cells
+    K = w.permeability()
+    print(f"3-D cube workload {w.nx}x{w.ny}x{w.nz}", flush=True)
+    ctx = B.Context3(cfg, torch.tensor(K, dtype=torch.float64, device=dev))
+    r = _vec(n, 6, True)
+    rd = torch.tensor(r, dtype=torch.float64, device=dev)
+    z = torch.full_like(rd, np.nan)
+    ctx.apply(rd, z)
+    torch.cuda.synchronize()
+    zh, nc = B.test3d_host_apply(cfg, K, r)
+    errh = np.linalg.norm(z.cpu().numpy() - zh) / np.linalg.norm(zh)
+    print(f"  nc {nc}; T rel L2 to the host evaluation {errh:.2e}; refinement steps "
+          f"{ctx.query('coarse_refine'):.0f}", flush=True)
+    assert nc == ctx.query("coarse_dofs") == 38016
+    assert errh <= 1e-10
+    b = torch.tensor(w.rhs(), dtype=torch.float64, device=dev)
+    p = torch.zeros_like(b)
+    st = ctx.gmres(b, p, rtol=1e-8, restart=10, maxit=500)
+    y = torch.empty_like(b)
+    ctx.op(p, y)
+    torch.cuda.synchronize()
+    rel = (torch.linalg.norm(b - y) / torch.linalg.norm(b)).item()
+    print(f"  GMRES {st.iterations} steps, relres {rel:.2e} (reported {st.final_relres:.2e})",
+          flush=True)
+    assert st.converged and rel <= 1e-8 * (1 + 1e-6)
+    assert abs(rel - st.final_relres) <= 1e-3 * rel
+    ctx.close()

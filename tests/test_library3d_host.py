@@ -54,3 +54,52 @@ def test_invalid_3d_configurations_rejected():
     with pytest.raises(B.MrcmError) as e:
         B.test3d_host_apply(B.Config3(14, 9, 11, (1,) * 6, 7, 9, 11, 0), K, r)
     assert e.value.code == B.MRCM_EINVAL
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 2, 2), (3, 2, 2), (5, 4, 3), (6, 6, 6), (12, 1, 7)])
+def test_dissection_tree_separates_regions(dims):
+    """Every subdomain is eliminated by one node; a node's region (its own
+    subdomains and its descendants') is a box; its border is exactly the set of
+    face neighbours of the region outside it; the subdomains of different
+    children are never face neighbours (the separator splits them); leaves hold
+    at most eight subdomains and children sit one level below their parent."""
+    mx, my, mz = dims
+    m = mx * my * mz
+    T = B.test3d_dissection(mx, my, mz)
+    nn = len(T["parent"])
+    assert np.all(T["elim"] >= 0) and np.all(T["elim"] < nn)
+    assert np.sum(T["parent"] == -1) == 1 and T["parent"][-1] == -1   # post-order: root last
+    coords = lambda s: (s % mx, (s // mx) % my, s // (mx * my))  # noqa: E731
+
+    def nbrs(s):
+        x, y, z = coords(s)
+        for d in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+            q = (x + d[0], y + d[1], z + d[2])
+            if 0 <= q[0] < mx and 0 <= q[1] < my and 0 <= q[2] < mz:
+                yield (q[2] * my + q[1]) * mx + q[0]
+
+    region = [set() for _ in range(nn)]
+    for s in range(m):
+        t = T["elim"][s]
+        while t >= 0:
+            region[t].add(s)
+            t = T["parent"][t]
+    assert region[-1] == set(range(m))
+    children = [[] for _ in range(nn)]
+    for t in range(nn):
+        if T["parent"][t] >= 0:
+            assert T["parent"][t] > t
+            assert T["depth"][t] == T["depth"][T["parent"][t]] + 1
+            children[T["parent"][t]].append(t)
+    for t in range(nn):
+        cs = np.array([coords(s) for s in region[t]])
+        assert len(region[t]) == np.prod(cs.max(0) - cs.min(0) + 1)   # a box
+        border = {q for s in region[t] for q in nbrs(s)} - region[t]
+        assert sorted(border) == list(T["border"][t])
+        own = {s for s in range(m) if T["elim"][s] == t}
+        if not children[t]:
+            assert len(own) <= 8 and own == region[t]
+        for a in children[t]:
+            for b in children[t]:
+                if a < b:
+                    assert not any(q in region[b] for s in region[a] for q in nbrs(s))

@@ -40,3 +40,28 @@ def test_mixture_spans_the_contrast_with_channel_facies():
     ratio = np.exp(np.log(K[chi.ravel()]).mean() - np.log(K[~chi.ravel()]).mean())
     assert 1e3 < ratio < 1e6
     assert 0.3 < chi.mean() < 0.7
+
+
+def test_gaussian_field3_is_seeded_unit_variance_and_correlated():
+    g = wl.gaussian_field3(48, 40, 32, 4.0, 7)
+    assert g.shape == (32, 40, 48)
+    assert np.array_equal(g, wl.gaussian_field3(48, 40, 32, 4.0, 7))
+    assert abs(g.std() - 1.0) < 0.2 and abs(g.mean()) < 0.3
+    # covariance exp(-r^2 / ell^2) along every axis at lag 2: exp(-1/4)
+    for ax in range(3):
+        a = np.moveaxis(g, ax, 0)
+        c = np.mean(a[2:] * a[:-2]) / np.mean(a * a)
+        assert abs(c - np.exp(-0.25)) < 0.1
+    K = wl.lognormal_K3(16, 12, 8, 2.0, 3.0, 5)
+    assert K.shape == (16 * 12 * 8,) and np.all(K > 0)
+    b = wl.corner_sources3(4, 3, 2)
+    assert b[0] == 1.0 and b[23] == -1.0 and np.count_nonzero(b) == 2
+
+
+def test_cube_workload():
+    from paper_2606_08883_amd.configs import WORKLOADS3
+    w = WORKLOADS3["cube"]
+    assert (w.nx, w.ny, w.nz, w.s) == (96, 96, 96, 8) and not any(w.bc)
+    cfg = w.binding_config()
+    assert (cfg.sx, cfg.oversample, cfg.degree, cfg.sweeps) == (8, 2, 1, 1)
+    assert w.permeability().shape == (w.cells,)
