@@ -341,8 +341,8 @@ def boxes3(w, grow: int) -> np.ndarray:
 def algorithmic_bytes3(w, coarse_bytes: float) -> dict:
     """Algorithmic bytes of one instance of every phase of the 3-D apply
     (FP64 throughout).  A box of bx x by x bz cells (plane P = bx by) stores
-    bz symmetric P x P plane blocks in full and bz x P couplings; the count
-    reads them once.
+    bz symmetric P x P plane blocks by their P / 2 + 1 cyclic diagonals and
+    bz x P couplings; the count reads them once.
       local       per subdomain on its oversampled box: factor and couplings,
                   r on the box, p written on the owned cells; per trace face
                   its two box-local cells (8 B) and four weights (32 B); per
@@ -366,7 +366,7 @@ def algorithmic_bytes3(w, coarse_bytes: float) -> dict:
     def factor(b):
         bx, by, bz = ext(b)
         P = bx * by
-        return int(np.sum(bz * P * P * 8 + bz * P * 8))
+        return int(np.sum(bz * (P // 2 + 1) * P * 8 + bz * P * 8))
 
     ox, oy, oz = ext(own)
     cells_own = ox * oy * oz

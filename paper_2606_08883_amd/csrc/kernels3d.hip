@@ -30,20 +30,44 @@ __device__ __forceinline__ long long global_cell(const Box3& d, int q, int nx, i
   return ((long long)(d.lo[2] + z) * ny + (d.lo[1] + y)) * nx + (d.lo[0] + x);
 }
 
-// acc = sum_k D(t, k) v[k] with D symmetric (column t read, consecutive
-// threads reading consecutive words), four partial sums in a fixed order.
+// sum_c D(t, c) v[c] for a block in cyclic-diagonal storage (word d P + t
+// holds D(t, (t + d) mod P), d < P / 2 + 1): diagonal d gives D(t, t + d)
+// v[t + d] from word d P + t and, unless 2 d = P, D(t - d, t) v[t - d] from
+// word d P + t - d, indices mod P.  Consecutive threads read consecutive
+// words of one diagonal in both terms, so each stored word comes from HBM
+// once.  Odd and even d in separate sums, added as (even up + odd up) +
+// (even down + odd down): the host solve's order.
 __device__ __forceinline__ double plane_dot(const double* __restrict__ D, const double* v, int P,
                                             int t) {
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int k = 0;
-  for (; k + 4 <= P; k += 4) {
-    a0 = fma(D[(long long)k * P + t], v[k], a0);
-    a1 = fma(D[(long long)(k + 1) * P + t], v[k + 1], a1);
-    a2 = fma(D[(long long)(k + 2) * P + t], v[k + 2], a2);
-    a3 = fma(D[(long long)(k + 3) * P + t], v[k + 3], a3);
+  const int H = P / 2 + 1;
+  double u0 = D[t] * v[t], u1 = 0.0, w0 = 0.0, w1 = 0.0;
+  int up = t, dn = t;
+  int d = 1;
+  for (; d + 1 < H; d += 2) {
+    up = up + 1 == P ? 0 : up + 1;
+    dn = dn == 0 ? P - 1 : dn - 1;
+    const double* r1 = D + (long long)d * P;
+    const double a1 = r1[t], b1 = r1[dn], x1 = v[up], y1 = v[dn];
+    const int up2 = up + 1 == P ? 0 : up + 1, dn2 = dn == 0 ? P - 1 : dn - 1;
+    const double* r2 = r1 + P;
+    const double a2 = r2[t], b2 = r2[dn2], x2 = v[up2], y2 = v[dn2];
+    u1 = fma(a1, x1, u1);
+    if (2 * d != P) w1 = fma(b1, y1, w1);
+    u0 = fma(a2, x2, u0);
+    if (2 * (d + 1) != P) w0 = fma(b2, y2, w0);
+    up = up2;
+    dn = dn2;
   }
-  for (; k < P; ++k) a0 = fma(D[(long long)k * P + t], v[k], a0);
-  return (a0 + a1) + (a2 + a3);
+  if (d < H) {
+    up = up + 1 == P ? 0 : up + 1;
+    dn = dn == 0 ? P - 1 : dn - 1;
+    const double* r1 = D + (long long)d * P;
+    double& u = d & 1 ? u1 : u0;
+    double& w = d & 1 ? w1 : w0;
+    u = fma(r1[t], v[up], u);
+    if (2 * d != P) w = fma(r1[dn], v[dn], w);
+  }
+  return (u0 + u1) + (w0 + w1);
 }
 
 // Block LDL^T solve of the box in LDS: us holds b on entry and x on exit in
@@ -52,19 +76,20 @@ __device__ __forceinline__ void plane_solve(double* us, double* v, const Box3& d
                                             const double* __restrict__ dinv,
                                             const double* __restrict__ coup, int stop) {
   const int P = d.P, bz = d.n[2], t = threadIdx.x;
+  const long long HP = (long long)(P / 2 + 1) * P;  // words of one stored block
   const double* D = dinv + d.doff;
   const double* T = coup + d.coff;
   for (int j = 0; j < bz; ++j) {
     if (t < P) v[t] = j > 0 ? fma(T[(long long)j * P + t], us[(j - 1) * P + t], us[j * P + t])
                             : us[j * P + t];
     __syncthreads();
-    if (t < P) us[j * P + t] = plane_dot(D + (long long)j * P * P, v, P, t);
+    if (t < P) us[j * P + t] = plane_dot(D + j * HP, v, P, t);
     __syncthreads();
   }
   for (int j = bz - 2; j >= stop; --j) {
     if (t < P) v[t] = T[(long long)(j + 1) * P + t] * us[(j + 1) * P + t];
     __syncthreads();
-    if (t < P) us[j * P + t] += plane_dot(D + (long long)j * P * P, v, P, t);
+    if (t < P) us[j * P + t] += plane_dot(D + j * HP, v, P, t);
     __syncthreads();
   }
 }
@@ -240,19 +265,20 @@ inline int grid3(long long n) {
 
 }  // namespace
 
-void launch_local3(const Box3* boxes, int m, const double* dinv, const double* coup,
-                   const double* r, double* p, int nx, int ny, const int* dof_off,
-                   const Dof3* dofs, const int* fin, const int* fout, const double* fw,
-                   double* mU, double* mP, hipStream_t s) {
+void launch_local3(const Box3* boxes, int m, int max_cells, const double* dinv,
+                   const double* coup, const double* r, double* p, int nx, int ny,
+                   const int* dof_off, const Dof3* dofs, const int* fin, const int* fout,
+                   const double* fw, double* mU, double* mP, hipStream_t s) {
   if (m <= 0) return;
-  const size_t shm = sizeof(double) * (kMaxBox3Cells + kBox3Threads);
+  const size_t shm = sizeof(double) * (max_cells + kBox3Threads);
   hipLaunchKernelGGL(k_local3, dim3(m), dim3(kBox3Threads), shm, s, boxes, dinv, coup, r, p, nx,
                      ny, dof_off, dofs, fin, fout, fw, mU, mP);
 }
-void launch_patch3(const Box3* boxes, int m, const double* dinv, const double* coup,
-                   const double* rho, double* p, int nx, int ny, hipStream_t s) {
+void launch_patch3(const Box3* boxes, int m, int max_cells, const double* dinv,
+                   const double* coup, const double* rho, double* p, int nx, int ny,
+                   hipStream_t s) {
   if (m <= 0) return;
-  const size_t shm = sizeof(double) * (kMaxBox3Cells + kBox3Threads);
+  const size_t shm = sizeof(double) * (max_cells + kBox3Threads);
   hipLaunchKernelGGL(k_patch3, dim3(m), dim3(kBox3Threads), shm, s, boxes, dinv, coup, rho, p,
                      nx, ny);
 }

@@ -203,9 +203,10 @@ PlaneFactor factor_box(const Setup& S, const Box& b, bool robin) {
   const int dims[3] = {S.nx, S.ny, S.nz};
   for (int a = 0; a < 3; ++a) whole = whole && b.lo[a] == 0 && b.hi[a] == dims[a];
   F.pin = S.noflow && whole ? 1 : 0;
-  F.dinv.assign((size_t)bz * P * P, 0.0);
+  const int H = half_rows(P);
+  F.dinv.assign((size_t)bz * H * P, 0.0);
   F.coup.assign((size_t)bz * P, 0.0);
-  std::vector<double> D((size_t)P * P);
+  std::vector<double> D((size_t)P * P), Dp((size_t)P * P);
   for (int j = 0; j < bz; ++j) {
     const int z = b.lo[2] + j;
     std::fill(D.begin(), D.end(), 0.0);
@@ -245,14 +246,16 @@ PlaneFactor factor_box(const Setup& S, const Box& b, bool robin) {
     }
     if (F.pin && j == 1) F.coup[(size_t)P] = 0.0;
     if (j > 0) {
-      const double* Dp = &F.dinv[(size_t)(j - 1) * P * P];
       const double* Tj = &F.coup[(size_t)j * P];
       for (int a = 0; a < P; ++a)
         for (int c = 0; c < P; ++c) D[(size_t)a * P + c] -= Tj[a] * Dp[(size_t)a * P + c] * Tj[c];
     }
     if (!spd_inverse(D.data(), P))
       throw Error(MRCM_ESINGULAR, "non-positive pivot in a local factorisation");
-    std::copy(D.begin(), D.end(), F.dinv.begin() + (size_t)j * P * P);
+    double* Dh = &F.dinv[(size_t)j * H * P];
+    for (int d = 0; d < H; ++d)
+      for (int t = 0; t < P; ++t) Dh[(size_t)d * P + t] = D[(size_t)t * P + (t + d) % P];
+    std::swap(D, Dp);
   }
   return F;
 }
@@ -287,31 +290,39 @@ long long cell_of(const Setup& S, int x, int y, int z) {
   return ((long long)z * S.ny + y) * S.nx + x;
 }
 
+double plane_dot(const double* D, const double* v, int P, int t) {
+  const int H = half_rows(P);
+  double u0 = D[t] * v[t], u1 = 0.0, w0 = 0.0, w1 = 0.0;
+  int up = t, dn = t;
+  for (int d = 1; d < H; ++d) {
+    up = up + 1 == P ? 0 : up + 1;
+    dn = dn == 0 ? P - 1 : dn - 1;
+    const double* row = D + (size_t)d * P;
+    double& u = d & 1 ? u1 : u0;
+    double& w = d & 1 ? w1 : w0;
+    u = std::fma(row[t], v[up], u);
+    if (2 * d != P) w = std::fma(row[dn], v[dn], w);
+  }
+  return (u0 + u1) + (w0 + w1);
+}
+
 void box_solve(const PlaneFactor& F, double* x) {
-  const int P = F.P, bz = F.bz;
+  const int P = F.P, bz = F.bz, H = half_rows(P);
   if (F.pin) x[0] = 0.0;
   std::vector<double> v(P);
   for (int j = 0; j < bz; ++j) {
     double* xj = x + (size_t)j * P;
     for (int c = 0; c < P; ++c)
-      v[c] = j > 0 ? xj[c] + F.coup[(size_t)j * P + c] * x[(size_t)(j - 1) * P + c] : xj[c];
-    const double* D = &F.dinv[(size_t)j * P * P];
-    for (int a = 0; a < P; ++a) {
-      double s = 0.0;
-      for (int c = 0; c < P; ++c) s += D[(size_t)a * P + c] * v[c];
-      xj[a] = s;
-    }
+      v[c] = j > 0 ? std::fma(F.coup[(size_t)j * P + c], x[(size_t)(j - 1) * P + c], xj[c]) : xj[c];
+    const double* D = &F.dinv[(size_t)j * H * P];
+    for (int a = 0; a < P; ++a) xj[a] = plane_dot(D, v.data(), P, a);
   }
   for (int j = bz - 2; j >= 0; --j) {
     double* xj = x + (size_t)j * P;
     const double* xn = x + (size_t)(j + 1) * P;
     for (int c = 0; c < P; ++c) v[c] = F.coup[(size_t)(j + 1) * P + c] * xn[c];
-    const double* D = &F.dinv[(size_t)j * P * P];
-    for (int a = 0; a < P; ++a) {
-      double s = 0.0;
-      for (int c = 0; c < P; ++c) s += D[(size_t)a * P + c] * v[c];
-      xj[a] += s;
-    }
+    const double* D = &F.dinv[(size_t)j * H * P];
+    for (int a = 0; a < P; ++a) xj[a] += plane_dot(D, v.data(), P, a);
   }
 }
 

@@ -28,12 +28,22 @@ struct Box {
 // cells of a plane, x fastest) for every plane j, and the z-couplings T_j
 // (P values: the transmissibility between plane j - 1 and plane j at each
 // cell; plane 0's are unused).  pin: the box covers an all-no-flow domain and
-// its first cell is fixed.
+// its first cell is fixed.  D_j^-1 is stored by its cyclic diagonals 0 ..
+// H - 1 (H = P / 2 + 1): word d P + t holds D(t, (t + d) mod P), which holds
+// every entry of a symmetric matrix once (twice on diagonal P / 2 when P is
+// even); plane_dot reads it back.
 struct PlaneFactor {
   int P = 0, bz = 0, pin = 0;
-  std::vector<double> dinv;  // bz x P x P
+  std::vector<double> dinv;  // bz x H x P
   std::vector<double> coup;  // bz x P
 };
+inline int half_rows(int P) { return P / 2 + 1; }
+// sum_c D(t, c) v[c] of a block in cyclic-diagonal storage: diagonal 0, then
+// for d = 1 .. H - 1 the term D(t, t + d) v[t + d] (read at d P + t) and,
+// unless 2 d = P, D(t - d, t) v[t - d] (read at d P + t - d), indices mod P;
+// the terms of odd and even d in separate sums, added last as
+// (even up + odd up) + (even down + odd down).
+double plane_dot(const double* D, const double* v, int P, int t);
 
 // The faces of one side of Omega_i with the data of the trace moments: the
 // inside and outside cell (global), and the four weights of U = w0 p_in +
