@@ -48,7 +48,7 @@ METRIC = "GMRES+MRCM-OS solves/s & cell-DOF/s at rel.res 1e-8; p50/p99 solve lat
 def kernel_source_hash() -> str:
     """First 16 hex digits of the sha256 of the kernel sources."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "device.h", "setup_jobs.h"):
+    for f in ("kernels.hip", "device.h", "coarse.h", "setup_jobs.h"):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -408,9 +408,8 @@ std::vector<T> narrow(const std::vector<double>& v) {
 }
 
 // Upload the nested-dissection factor of the interface system and the data
-// of its level-scheduled solve: chunk descriptors (16 rows each), the
-// right-hand-side sources of every
-// tree position, and the contribution slots by destination (the inverse of
+// of its level-scheduled solve: chunk descriptors (64 or 16 rows each, see
+// coarse_tables), the right-hand-side sources of every tree position, and the contribution slots by destination (the inverse of
 // the factor's slot lists; slot u of every position contiguous, so that a
 // node reads its rows' contributions in slot order with coalesced loads).
 void upload_coarse(mrcm_ctx* c, const mrcm::CoarseFactor& F, const mrcm::HostSetup& S,
@@ -484,8 +483,8 @@ void coarse_solve_lane(mrcm_ctx* c, mrcm_ctx::Lane& L, hipStream_t s) {
 
 // ---- autotuner --------------------------------------------------------------
 // The one-column launches have two free workgroup shapes: threads per chunk
-// of every interface level (one wave, which takes a small chunk whole, or
-// four waves), and lane groups per workgroup of the local and patch solves
+// of every interface level (four or one waves, see coarse_threads), and lane
+// groups per workgroup of the local and patch solves
 // (the most that fit in 64 KB of LDS, half or a quarter of that).  Every
 // option computes the same results bit for bit, so the choice is by time
 // alone.  With MRCM_TUNE=1 in the environment, each option's launch is
@@ -616,12 +615,12 @@ void autotune(mrcm_ctx* c, hipStream_t s) {
     }
     if (c->nc > 0) {
       for (size_t i = 0; i < c->fwd_levels.size(); ++i) {
-        const int d = mrcm::coarse_threads(c->fwd_levels[i].second);
+        const int d = mrcm::coarse_threads(c->fwd_levels[i].second, true);
         out.fwd.push_back(pick({d, d == 64 ? mrcm::kVecThreads : 64},
                                [&](int t) { launch_fwd_level(c, L, i, s, t); }));
       }
       for (size_t i = 0; i < c->bwd_levels.size(); ++i) {
-        const int d = mrcm::coarse_threads(c->bwd_levels[i].second);
+        const int d = mrcm::coarse_threads(c->bwd_levels[i].second, false);
         out.bwd.push_back(pick({d, d == 64 ? mrcm::kVecThreads : 64},
                                [&](int t) { launch_bwd_level(c, L, i, s, t); }));
       }

@@ -423,14 +423,20 @@ CoarseTables coarse_tables(const CoarseFactor& F, const int32_t* rowL, const int
     std::copy(cn.fwd.begin(), cn.fwd.end(), T.fwd.get() + fwd_off[t]);
     std::copy(cn.bwd.begin(), cn.bwd.end(), T.bwd.get() + bwd_off[t]);
   }
-  // 16 rows per chunk: one group of four rows per wave
-  constexpr int step = 16;
+  // Rows per forward chunk: 64 when the node's separator has at most 128
+  // rows (a 256-thread workgroup takes the chunk whole, 16 rows per wave,
+  // with one gather of the vector for all 64 rows), else 16 (four rows per
+  // wave at a time).  Backward chunks have 16 rows (a one-wave workgroup
+  // takes a chunk of at most 128 columns whole): wider backward chunks
+  // measured slower.
+  auto rows_per_chunk = [](int ncol) { return ncol <= 128 ? 64 : 16; };
   for (int d = F.depth; d >= 0; --d) {
     const int first = (int)T.chunks.size();
     for (int t = 0; t < nn; ++t) {
       const auto& cn = F.nodes[t];
       if (cn.depth != d) continue;
       const int nf = (int)cn.frow.size(), nu = (int)cn.urow.size(), rows = nf + nu;
+      const int step = rows_per_chunk(nf);
       for (int r0 = 0; r0 < rows; r0 += step)
         T.chunks.push_back(CChunk{r0, std::min(rows, r0 + step), nf, nu, cn.yoff, cn.coff,
                                   fcol_off[t], ucol_off[t], fwd_off[t]});
@@ -444,6 +450,7 @@ CoarseTables coarse_tables(const CoarseFactor& F, const int32_t* rowL, const int
       if (cn.depth != d) continue;
       const int nf = (int)cn.frow.size(), nu = (int)cn.urow.size();
       if (nu == 0) continue;  // x_F = y_F, written by the forward level
+      const int step = 16;
       for (int r0 = 0; r0 < nf; r0 += step)
         T.chunks.push_back(CChunk{r0, std::min(nf, r0 + step), nf, nu, cn.yoff, cn.coff,
                                   fcol_off[t], ucol_off[t], bwd_off[t]});

@@ -73,7 +73,9 @@ struct CChunk {
 // and uploaded as they are:
 //   idx            separator and border dof lists of every node, concatenated;
 //   fwd, bwd       the node matrices, concatenated (fwd_len, bwd_len words);
-//   chunks         16 rows each, forward levels leaves first (fwd_levels:
+//   chunks         forward: 64 rows each for a matrix of at most 128
+//                  columns, else 16; backward: 16; forward levels leaves
+//                  first (fwd_levels:
 //                  first chunk and count per level), then backward levels
 //                  root first (bwd_levels); a node without border rows has
 //                  no backward chunk;

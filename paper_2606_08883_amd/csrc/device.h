@@ -67,8 +67,11 @@ void launch_local(const BoxDesc* boxes, int m, int max_cells, int max_bx, const 
 // u * np + t, zero where unused) receives the descendants' contributions at
 // cdest; max_nf / max_nu bound the LDS vector.  A node without border rows
 // (the root) writes its x_F in its forward level and has no backward level.
-// threads: 64 (one wave per chunk) or 256 per workgroup, 0 for the default
-// of the level's chunk count; the choice changes no result.
+// threads: 64 or 256 per workgroup, 0 for the default (coarse_threads); the
+// choice changes no result.  A forward chunk of at most 128 columns is taken
+// whole, 16 rows per wave, when its rows fit the workgroup's waves; a
+// backward one when a one-wave workgroup takes its (at most 16) rows; other
+// chunks go four rows per wave at a time.
 void launch_coarse_rhs(const int4* gsrc, const double* gscale, const double* mU,
                        const double* mP, double* g_nd, int np, hipStream_t s);
 void launch_coarse_fwd(const CChunk* chunks, int nchunks, const double* fwd, const double* g_nd,
@@ -77,7 +80,9 @@ void launch_coarse_fwd(const CChunk* chunks, int nchunks, const double* fwd, con
 void launch_coarse_bwd(const CChunk* chunks, int nchunks, const double* bwd, const int* idx,
                        const double* ybuf, double* x, int max_nu, hipStream_t s,
                        int threads = 0);
-int coarse_threads(int nchunks);
+// Default threads of a level: 256 forward; backward 64 for levels of 2048
+// chunks or more, else 256.
+int coarse_threads(int nchunks, bool forward);
 // Refinement of the interface solve, k columns: r_nd = g_nd - (scaled C in
 // tree order, CSR rp / ci / v) x, and x += dx (n values).
 void launch_coarse_resid(int k, const int* rp, const int* ci, const double* v,

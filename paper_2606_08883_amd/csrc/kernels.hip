@@ -781,8 +781,14 @@ __device__ __forceinline__ double gemv_chunk16(const double (&m)[16][2], const d
   butterfly_sum<16>(s, lane);
   return s[0];
 }
-// Whether a chunk is taken whole by a one-wave workgroup.
+// Whether a forward chunk is taken whole, 16 rows per wave (wave w: rows
+// row0 + 16 w .. row0 + 16 w + 15) with every row's columns in the wave's
+// registers.
 __device__ __forceinline__ bool whole_chunk(const CChunk& ch, int ncol) {
+  return ncol <= 128 && ch.row1 - ch.row0 <= 16 * (int)(blockDim.x >> 6);
+}
+// Whether a backward chunk is taken whole by a one-wave workgroup.
+__device__ __forceinline__ bool whole_chunk_wave(const CChunk& ch, int ncol) {
   return blockDim.x == 64 && ncol <= 128 && ch.row1 - ch.row0 <= 16;
 }
 
@@ -828,9 +834,10 @@ __device__ __forceinline__ void coarse_fwd_body(
       ybuf[yoff + row] = val;
   };
   if (whole_chunk(ch, nf)) {
+    const int r0 = ch.row0 + 16 * (int)(threadIdx.x >> 6);
     double m[16][2];
-    load_chunk16(m, M, nf, ch.row0, ch.row1, lane);
-    const int row = ch.row0 + butterfly_index<16>(lane);
+    load_chunk16(m, M, nf, r0, ch.row1, lane);
+    const int row = r0 + butterfly_index<16>(lane);
     dst = (row >= nf && row < ch.row1) ? cdest[coff + row - nf] : -1;
     gather();
     const double val = gemv_chunk16(m, v, nf, lane);
@@ -872,7 +879,7 @@ __device__ __forceinline__ void coarse_bwd_body(const CChunk ch, const double* _
     for (int b = threadIdx.x; b < nu; b += blockDim.x) xu[b] = x[idx[ch.ucol + b]];
     __syncthreads();
   };
-  if (whole_chunk(ch, nu)) {
+  if (whole_chunk_wave(ch, nu)) {
     double m[16][2];
     load_chunk16(m, M, nu, ch.row0, ch.row1, lane);
     const int row = ch.row0 + butterfly_index<16>(lane);
@@ -2049,13 +2056,15 @@ void launch_coarse_add(double* x, const double* dx, long long n, hipStream_t s) 
 // whole, so that every chunk of the level is resident at once; the other
 // levels take four waves per chunk (a sweep of the threshold over 0, 1024,
 // 2048 and never found 2048 best at 1024^2 and 4096^2).
-int coarse_threads(int nchunks) { return nchunks >= 2048 ? 64 : kVecThreads; }
+int coarse_threads(int nchunks, bool forward) {
+  return forward || nchunks < 2048 ? kVecThreads : 64;
+}
 
 void launch_coarse_fwd(const CChunk* chunks, int nchunks, const double* fwd, const double* g_nd,
                        double* contrib, int maxp, int np, const int* cdest, double* ybuf,
                        const int* idx, double* x, int max_nf, hipStream_t s, int threads) {
   if (nchunks <= 0) return;
-  if (threads != 64 && threads != kVecThreads) threads = coarse_threads(nchunks);
+  if (threads != 64 && threads != kVecThreads) threads = coarse_threads(nchunks, true);
   hipLaunchKernelGGL(k_coarse_fwd, dim3(nchunks), dim3(threads),
                      sizeof(double) * (size_t)(max_nf > 0 ? max_nf : 1), s, chunks, fwd, g_nd,
                      contrib, maxp, np, cdest, ybuf, idx, x);
@@ -2063,7 +2072,7 @@ void launch_coarse_fwd(const CChunk* chunks, int nchunks, const double* fwd, con
 void launch_coarse_bwd(const CChunk* chunks, int nchunks, const double* bwd, const int* idx,
                        const double* ybuf, double* x, int max_nu, hipStream_t s, int threads) {
   if (nchunks <= 0) return;
-  if (threads != 64 && threads != kVecThreads) threads = coarse_threads(nchunks);
+  if (threads != 64 && threads != kVecThreads) threads = coarse_threads(nchunks, false);
   hipLaunchKernelGGL(k_coarse_bwd, dim3(nchunks), dim3(threads),
                      sizeof(double) * (size_t)(max_nu > 0 ? max_nu : 1), s, chunks, bwd, idx,
                      ybuf, x);
@@ -2218,7 +2227,7 @@ void launch_coarse_fwd_k(int k, const CChunk* chunks, int nchunks, const double*
     double* y = ybuf + (long long)k0 * np;
     double* xk = x + (long long)k0 * nc;
     const size_t shm = sizeof(double) * (size_t)w * (max_nf > 0 ? max_nf : 1);
-    const dim3 grid(nchunks), block(coarse_threads(nchunks));
+    const dim3 grid(nchunks), block(coarse_threads(nchunks, true));
     if (w == 1)
       hipLaunchKernelGGL(k_coarse_fwd, grid, block, shm, s, chunks, fwd, g, c, maxp, np, cdest, y,
                          idx, xk);
@@ -2241,7 +2250,7 @@ void launch_coarse_bwd_k(int k, const CChunk* chunks, int nchunks, const double*
     const double* y = ybuf + (long long)k0 * np;
     double* xk = x + (long long)k0 * nc;
     const size_t shm = sizeof(double) * (size_t)w * (max_nu > 0 ? max_nu : 1);
-    const dim3 grid(nchunks), block(coarse_threads(nchunks));
+    const dim3 grid(nchunks), block(coarse_threads(nchunks, false));
     if (w == 1)
       hipLaunchKernelGGL(k_coarse_bwd, grid, block, shm, s, chunks, bwd, idx, y, xk);
     else if (w == 2)
@@ -2549,14 +2558,14 @@ void launch_coarse_rhs_many(const ManyCol* cols, const int* pre, int ncol, int b
 void launch_coarse_fwd_many(const ManyCol* cols, const int* pre, const int* first, int ncol,
                             int blocks, int refine, int max_nf, hipStream_t s) {
   if (blocks <= 0) return;
-  hipLaunchKernelGGL(k_coarse_fwd_many, dim3(blocks), dim3(coarse_threads(blocks)),
+  hipLaunchKernelGGL(k_coarse_fwd_many, dim3(blocks), dim3(coarse_threads(blocks, true)),
                      sizeof(double) * (size_t)(max_nf > 0 ? max_nf : 1), s, cols, pre, first,
                      ncol, refine);
 }
 void launch_coarse_bwd_many(const ManyCol* cols, const int* pre, const int* first, int ncol,
                             int blocks, int refine, int max_nu, hipStream_t s) {
   if (blocks <= 0) return;
-  hipLaunchKernelGGL(k_coarse_bwd_many, dim3(blocks), dim3(coarse_threads(blocks)),
+  hipLaunchKernelGGL(k_coarse_bwd_many, dim3(blocks), dim3(coarse_threads(blocks, false)),
                      sizeof(double) * (size_t)(max_nu > 0 ? max_nu : 1), s, cols, pre, first,
                      ncol, refine);
 }
