@@ -27,7 +27,6 @@ the right.  Prints one JSON line.  Besides the contract keys it carries:
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import platform
@@ -47,11 +46,8 @@ METRIC = "GMRES+MRCM-OS solves/s & cell-DOF/s at rel.res 1e-8; p50/p99 solve lat
 
 def kernel_source_hash() -> str:
     """First 16 hex digits of the sha256 of the kernel sources."""
-    h = hashlib.sha256()
-    for f in ("kernels.hip", "device.h", "coarse.h", "setup_jobs.h"):
-        with open(os.path.join(CSRC, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_2606_08883_amd.profile_summary import kernel_source_hash as h
+    return h()
 
 
 def recorded_traffic(kernel: str, workload: str, precision: int):
