@@ -37,6 +37,7 @@ struct mrcm3d_ctx {
   double *tx = nullptr, *ty = nullptr, *tz = nullptr;
   mrcm3d::Box3 *lbox = nullptr, *pbox = nullptr;
   int lmax_cells = 1, pmax_cells = 1;  // the most cells of a box of each list
+  int lmax_plane = 1, pmax_plane = 1;  // and the most cells of a plane
   double *ldinv = nullptr, *lcoup = nullptr, *pdinv = nullptr, *pcoup = nullptr;
   double* mbf = nullptr;
   long long* mbf_off = nullptr;
@@ -131,7 +132,7 @@ int fail3(const mrcm::Error& e) {
 // Box descriptors and the concatenated factors of a list of boxes.
 void upload_boxes(mrcm3d_ctx* c, const mrcm3d::Setup& S, const std::vector<mrcm3d::Box>& boxes,
                   const std::vector<mrcm3d::PlaneFactor>& F, mrcm3d::Box3*& dbox, double*& ddinv,
-                  double*& dcoup, int& max_cells) {
+                  double*& dcoup, int& max_cells, int& max_plane) {
   std::vector<mrcm3d::Box3> desc(boxes.size());
   std::vector<double> dinv, coup;
   for (size_t i = 0; i < boxes.size(); ++i) {
@@ -149,6 +150,7 @@ void upload_boxes(mrcm3d_ctx* c, const mrcm3d::Setup& S, const std::vector<mrcm3
     if (d.P > mrcm3d::kBox3Threads || b.cells() > mrcm3d::kMaxBox3Cells)
       throw mrcm::Error(MRCM_EINVAL, "3-D box too large (at most 256 cells per z-plane and 4096 cells)");
     max_cells = std::max(max_cells, (int)b.cells());
+    max_plane = std::max(max_plane, d.P);
     d.doff = (long long)dinv.size();
     d.coff = (long long)coup.size();
     dinv.insert(dinv.end(), F[i].dinv.begin(), F[i].dinv.end());
@@ -189,8 +191,9 @@ void coarse_sweep(mrcm3d_ctx* c, const double* g, double* x, hipStream_t s) {
 void apply3(mrcm3d_ctx* c, const double* r, double* z) {
   hipStream_t s = c->st;
   hipEvent_t e = start_mark(c);
-  mrcm3d::launch_local3(c->lbox, c->m, c->lmax_cells, c->ldinv, c->lcoup, r, c->p, c->nx, c->ny,
-                        c->dof_off, c->dofs, c->fin, c->fout, c->fw, c->mU, c->mP, s);
+  mrcm3d::launch_local3(c->lbox, c->m, c->lmax_cells, c->lmax_plane, c->ldinv, c->lcoup, r, c->p,
+                        c->nx, c->ny, c->dof_off, c->dofs, c->fin, c->fout, c->fw, c->mU, c->mP,
+                        s);
   if (e) mark(c, 0, e);
   if (c->nc > 0) {
     e = start_mark(c);
@@ -212,8 +215,8 @@ void apply3(mrcm3d_ctx* c, const double* r, double* z) {
     mrcm3d::launch_residual3(c->tx, c->ty, c->tz, c->nx, c->ny, c->nz, r, c->p, c->rho, s);
     if (e) mark(c, 3, e);
     e = start_mark(c);
-    mrcm3d::launch_patch3(c->pbox, c->m, c->pmax_cells, c->pdinv, c->pcoup, c->rho, c->p, c->nx,
-                          c->ny, s);
+    mrcm3d::launch_patch3(c->pbox, c->m, c->pmax_cells, c->pmax_plane, c->pdinv, c->pcoup, c->rho,
+                          c->p, c->nx, c->ny, s);
     if (e) mark(c, 4, e);
   }
   e = start_mark(c);
@@ -261,9 +264,11 @@ int mrcm3d_setup(const mrcm3d_grid* grid, const mrcm3d_params* params, const dou
     c->tx = c->upload(S.tx);
     c->ty = c->upload(S.ty);
     c->tz = c->upload(S.tz);
-    upload_boxes(c, S, S.oboxes, S.over, c->lbox, c->ldinv, c->lcoup, c->lmax_cells);
+    upload_boxes(c, S, S.oboxes, S.over, c->lbox, c->ldinv, c->lcoup, c->lmax_cells,
+                 c->lmax_plane);
     if (S.sweeps > 0)
-      upload_boxes(c, S, S.pboxes, S.patch, c->pbox, c->pdinv, c->pcoup, c->pmax_cells);
+      upload_boxes(c, S, S.pboxes, S.patch, c->pbox, c->pdinv, c->pcoup, c->pmax_cells,
+                   c->pmax_plane);
     // multiscale basis functions
     std::vector<double> mbf;
     std::vector<long long> mbf_off(S.m);

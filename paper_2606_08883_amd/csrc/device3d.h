@@ -6,7 +6,7 @@
 
 namespace mrcm3d {
 
-constexpr int kBox3Threads = 256;  // threads per box; a box plane has at most this many cells
+constexpr int kBox3Threads = 256;  // cells of a box plane, at most (a thread per cell)
 constexpr int kMaxBox3Cells = 4096;
 
 // A cell box solved by one workgroup: origin lo and extents n (global),
@@ -29,14 +29,15 @@ struct Dof3 {
 
 // Source-driven solves on the oversampled boxes (p on the owned cells, the
 // trace moments mU, mP of every dof of the box's subdomain; face tables:
-// box-local inside and outside cell, four weights per face).  max_cells: the
-// most cells of a box of the launch (its LDS, at most kMaxBox3Cells).
-void launch_local3(const Box3* boxes, int m, int max_cells, const double* dinv,
+// box-local inside and outside cell, four weights per face).  max_cells and
+// max_plane: the most cells and plane cells of a box of the launch (its LDS
+// and threads, whole waves; at most kMaxBox3Cells and kBox3Threads).
+void launch_local3(const Box3* boxes, int m, int max_cells, int max_plane, const double* dinv,
                    const double* coup, const double* r, double* p, int nx, int ny,
                    const int* dof_off, const Dof3* dofs, const int* fin, const int* fout,
                    const double* fw, double* mU, double* mP, hipStream_t s);
 // Patch solves of the smoothing sweep: p += A[S_i]^-1 rho[S_i] on the owned cells.
-void launch_patch3(const Box3* boxes, int m, int max_cells, const double* dinv,
+void launch_patch3(const Box3* boxes, int m, int max_cells, int max_plane, const double* dinv,
                    const double* coup, const double* rho, double* p, int nx, int ny,
                    hipStream_t s);
 // p[Omega_i] += P_i x_i (one workgroup per subdomain; mbf_off per subdomain).

@@ -265,22 +265,25 @@ inline int grid3(long long n) {
 
 }  // namespace
 
-void launch_local3(const Box3* boxes, int m, int max_cells, const double* dinv,
+// Threads of a box launch: one per cell of the widest plane, whole waves.
+inline int box3_threads(int max_plane) { return (max_plane + 63) / 64 * 64; }
+
+void launch_local3(const Box3* boxes, int m, int max_cells, int max_plane, const double* dinv,
                    const double* coup, const double* r, double* p, int nx, int ny,
                    const int* dof_off, const Dof3* dofs, const int* fin, const int* fout,
                    const double* fw, double* mU, double* mP, hipStream_t s) {
   if (m <= 0) return;
-  const size_t shm = sizeof(double) * (max_cells + kBox3Threads);
-  hipLaunchKernelGGL(k_local3, dim3(m), dim3(kBox3Threads), shm, s, boxes, dinv, coup, r, p, nx,
-                     ny, dof_off, dofs, fin, fout, fw, mU, mP);
+  const size_t shm = sizeof(double) * (max_cells + max_plane);
+  hipLaunchKernelGGL(k_local3, dim3(m), dim3(box3_threads(max_plane)), shm, s, boxes, dinv, coup,
+                     r, p, nx, ny, dof_off, dofs, fin, fout, fw, mU, mP);
 }
-void launch_patch3(const Box3* boxes, int m, int max_cells, const double* dinv,
+void launch_patch3(const Box3* boxes, int m, int max_cells, int max_plane, const double* dinv,
                    const double* coup, const double* rho, double* p, int nx, int ny,
                    hipStream_t s) {
   if (m <= 0) return;
-  const size_t shm = sizeof(double) * (max_cells + kBox3Threads);
-  hipLaunchKernelGGL(k_patch3, dim3(m), dim3(kBox3Threads), shm, s, boxes, dinv, coup, rho, p,
-                     nx, ny);
+  const size_t shm = sizeof(double) * (max_cells + max_plane);
+  hipLaunchKernelGGL(k_patch3, dim3(m), dim3(box3_threads(max_plane)), shm, s, boxes, dinv, coup,
+                     rho, p, nx, ny);
 }
 void launch_reconstruct3(const Box3* boxes, int m, const double* mbf, const long long* mbf_off,
                          const int* dof_off, const double* x, double* p, int nx, int ny,
