@@ -399,53 +399,62 @@ PHASE_KERNELS3 = {"local": "k_local3", "coarse": "interface solve (k_coarse_rhs,
 
 def cube_leg(steps: int) -> dict:
     """The 3-D cube workload (96^3 cells, 1728 subdomains): solves/s, phase
-    table and the roofline entry of its dominant phase."""
+    table and the roofline entry of its dominant phase in FP64, and the same
+    with the plane blocks stored in FP32 (precision 2)."""
     import torch
 
     from paper_2606_08883_amd import binding as B
     from paper_2606_08883_amd.configs import WORKLOADS3
-    w = WORKLOADS3["cube"]
+    w0 = WORKLOADS3["cube"]
     dev = torch.device("cuda:0")
-    K = torch.tensor(w.permeability(), dtype=torch.float64, device=dev)
-    b = torch.tensor(w.rhs(), dtype=torch.float64, device=dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx = B.Context3(w.binding_config(), K)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    r = timed_solves(ctx, b, steps, 2)
-    phases = phase_timing(ctx, b, max(1, min(steps, 5)))
-    ab = algorithmic_bytes3(w, ctx.query("coarse_bytes"))
-    napply = max(1, phases["local"][1])
-    table = {}
-    for k, (ms, cnt) in phases.items():
-        if cnt == 0:
-            continue
-        avg = ms / cnt
-        gbs = ab[k] / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
-        table[k] = {"kernel": PHASE_KERNELS3[k], "ms": avg, "per_apply": cnt / napply,
-                    "algorithmic_bytes": ab[k], "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS}
-    dom = max(table, key=lambda k: table[k]["ms"] * table[k]["per_apply"])
-    t = table[dom]
-    out = {"workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz} cells, subdomains of {w.s}^3, "
-                       f"oversampling {w.oversample}, degree {w.degree}, {w.sweeps} smoothing "
-                       f"sweep(s), overlap {w.overlap}, alpha {w.alpha}, log-normal sigma "
-                       f"{w.sigma} correlation {w.ell}, no-flow, corner sources",
-           "solves_per_s": r["value"], "cell_dof_per_s": r["value"] * w.cells,
-           "latency_ms": {"p50": r["p50"], "p99": r["p99"]}, "iterations": r["iterations"],
-           "final_relres_max": r["relres_max"], "setup_s": setup_s,
-           "interface_dofs": int(ctx.query("coarse_dofs")),
-           "interface_refinement_steps": int(ctx.query("coarse_refine")),
-           "interface_levels_per_sweep": int(ctx.query("coarse_levels")),
-           "device_gb": ctx.query("device_bytes") / 1e9,
-           "apply_ms": sum(v[0] for v in phases.values()) / napply,
-           "roofline": {"bound": "hbm", "kernel": t["kernel"], "phase": dom,
-                        "achieved": t["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": t["frac"], "algorithmic_bytes_per_launch": t["algorithmic_bytes"],
-                        "avg_launch_ms": t["ms"]},
-           "phases": table}
-    assert out["interface_dofs"] == ab["nc"]
-    ctx.close()
+    K = torch.tensor(w0.permeability(), dtype=torch.float64, device=dev)
+    b = torch.tensor(w0.rhs(), dtype=torch.float64, device=dev)
+    out = None
+    for prec in (0, 2):
+        w = w0.with_(precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx = B.Context3(w.binding_config(), K)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        r = timed_solves(ctx, b, steps, 2)
+        phases = phase_timing(ctx, b, max(1, min(steps, 5)))
+        ab = algorithmic_bytes3(w, ctx.query("coarse_bytes"))
+        napply = max(1, phases["local"][1])
+        table = {}
+        for k, (ms, cnt) in phases.items():
+            if cnt == 0:
+                continue
+            avg = ms / cnt
+            gbs = ab[k] / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
+            table[k] = {"kernel": PHASE_KERNELS3[k], "ms": avg, "per_apply": cnt / napply,
+                        "algorithmic_bytes": ab[k], "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS}
+        assert int(ctx.query("coarse_dofs")) == ab["nc"]
+        refine, levels = int(ctx.query("coarse_refine")), int(ctx.query("coarse_levels"))
+        res = {"solves_per_s": r["value"], "cell_dof_per_s": r["value"] * w.cells,
+               "latency_ms": {"p50": r["p50"], "p99": r["p99"]}, "iterations": r["iterations"],
+               "final_relres_max": r["relres_max"], "setup_s": setup_s,
+               "device_gb": ctx.query("device_bytes") / 1e9,
+               "apply_ms": sum(v[0] for v in phases.values()) / napply, "phases": table}
+        ctx.close()
+        if prec == 0:
+            dom = max(table, key=lambda k: table[k]["ms"] * table[k]["per_apply"])
+            t = table[dom]
+            out = {"workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz} cells, subdomains of {w.s}^3, "
+                               f"oversampling {w.oversample}, degree {w.degree}, {w.sweeps} "
+                               f"smoothing sweep(s), overlap {w.overlap}, alpha {w.alpha}, "
+                               f"log-normal sigma {w.sigma} correlation {w.ell}, no-flow, "
+                               "corner sources",
+                   "dtype": "f64", "interface_dofs": ab["nc"],
+                   "interface_refinement_steps": refine, "interface_levels_per_sweep": levels,
+                   **res,
+                   "roofline": {"bound": "hbm", "kernel": t["kernel"], "phase": dom,
+                                "achieved": t["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": t["frac"],
+                                "algorithmic_bytes_per_launch": t["algorithmic_bytes"],
+                                "avg_launch_ms": t["ms"]}}
+        else:
+            out["f32-storage/f64-arith"] = res
     return out
 
 

@@ -12,7 +12,8 @@
  * min(degree + 1, faces in that direction); informed spaces from the
  * oversampled problems, multiscale basis functions as their restrictions,
  * the source-driven solution on the oversampled box; restricted additive
- * Schwarz smoothing; FP64 throughout.  Vectors are FP64 device pointers of
+ * Schwarz smoothing; FP64 arithmetic throughout (the box factors optionally
+ * stored in FP32: precision 2).  Vectors are FP64 device pointers of
  * nx ny nz values, cell (ix, iy, iz) at (iz ny + iy) nx + ix.
  *
  * Error codes and stats as in mrcm.h.  Limits: every oversampled box and
@@ -47,6 +48,10 @@ typedef struct {
   int32_t smooth_sweeps;  /* k */
   int32_t smooth_overlap; /* delta */
   int32_t iface_degree;   /* d >= 0 */
+  int32_t precision;      /* 0: FP64; 2: plane blocks of the box factors stored
+                             in FP32 (rounded after the FP64 factorisation and
+                             the set-up's own solves), FP64 arithmetic; 1 is not
+                             offered in 3-D (MRCM_EINVAL) */
 } mrcm3d_params;
 
 typedef struct mrcm3d_ctx mrcm3d_ctx;
@@ -58,8 +63,9 @@ typedef struct mrcm3d_ctx mrcm3d_ctx;
  * the subdomain grid into planes (row-equilibrated block elimination with
  * partial pivoting in every separator, FP64, as the 2-D path), with the
  * number of FP64 refinement steps each interface solve runs set so that a
- * correction falls below 1e-10 of the solution (at most four), and uploads
- * them.  The context owns all device memory. */
+ * correction falls below 1e-10 of the solution in precision 0 and 1e-6 in
+ * precision 2 (at most four), and uploads them.  The context owns all device
+ * memory. */
 int mrcm3d_setup(const mrcm3d_grid* grid, const mrcm3d_params* params, const double* K_dev,
                  void* stream, mrcm3d_ctx** out);
 

@@ -70,7 +70,8 @@ class Params3(ctypes.Structure):
     _fields_ = [("sx", ctypes.c_int32), ("sy", ctypes.c_int32), ("sz", ctypes.c_int32),
                 ("oversample", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("beta_len", ctypes.c_int32), ("smooth_sweeps", ctypes.c_int32),
-                ("smooth_overlap", ctypes.c_int32), ("iface_degree", ctypes.c_int32)]
+                ("smooth_overlap", ctypes.c_int32), ("iface_degree", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -283,13 +284,14 @@ class Config3:
     sweeps: int = 1
     overlap: int = 2
     degree: int = 1
+    precision: int = 0
 
     def grid(self) -> Grid3:
         return Grid3(self.nx, self.ny, self.nz, (ctypes.c_int32 * 6)(*self.bc))
 
     def params(self) -> Params3:
         return Params3(self.sx, self.sy, self.sz, self.oversample, self.alpha, self.beta_len,
-                       self.sweeps, self.overlap, self.degree)
+                       self.sweeps, self.overlap, self.degree, self.precision)
 
     @property
     def n(self) -> int:

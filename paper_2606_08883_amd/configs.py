@@ -145,9 +145,13 @@ class Workload3:
     ell: float
     seed: int
     bc: tuple = (0, 0, 0, 0, 0, 0)
+    precision: int = 0  # 0 FP64; 2 FP32-stored plane blocks, FP64 arithmetic
 
     def permeability(self) -> np.ndarray:
         return wl.lognormal_K3(self.nx, self.ny, self.nz, self.sigma, self.ell, self.seed)
+
+    def with_(self, **kw) -> "Workload3":
+        return replace(self, **kw)
 
     def rhs(self) -> np.ndarray:
         return wl.corner_sources3(self.nx, self.ny, self.nz)
@@ -156,7 +160,7 @@ class Workload3:
         from .binding import Config3
         return Config3(self.nx, self.ny, self.nz, tuple(self.bc), self.s, self.s, self.s,
                        self.oversample, self.alpha, self.beta_len, self.sweeps, self.overlap,
-                       self.degree)
+                       self.degree, self.precision)
 
     @property
     def cells(self) -> int:

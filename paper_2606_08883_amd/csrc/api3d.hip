@@ -38,7 +38,10 @@ struct mrcm3d_ctx {
   mrcm3d::Box3 *lbox = nullptr, *pbox = nullptr;
   int lmax_cells = 1, pmax_cells = 1;  // the most cells of a box of each list
   int lmax_plane = 1, pmax_plane = 1;  // and the most cells of a plane
-  double *ldinv = nullptr, *lcoup = nullptr, *pdinv = nullptr, *pcoup = nullptr;
+  // plane blocks: double, or float with precision 2
+  void *ldinv = nullptr, *pdinv = nullptr;
+  double *lcoup = nullptr, *pcoup = nullptr;
+  int precision = 0;
   double* mbf = nullptr;
   long long* mbf_off = nullptr;
   int* dof_off = nullptr;
@@ -81,12 +84,16 @@ struct mrcm3d_ctx {
     device_bytes += bytes;
     return static_cast<X*>(q);
   }
+  // A set-up upload; it returns once the host data has been read, so the
+  // caller may release it.
   template <typename X>
   X* upload(const X* v, size_t count) {
     X* d = alloc<X>(count);
-    if (count)
+    if (count) {
       check3(hipMemcpyAsync(d, v, count * sizeof(X), hipMemcpyHostToDevice, st),
              "hipMemcpyAsync");
+      check3(hipStreamSynchronize(st), "hipStreamSynchronize");
+    }
     return d;
   }
   template <typename X>
@@ -131,7 +138,7 @@ int fail3(const mrcm::Error& e) {
 
 // Box descriptors and the concatenated factors of a list of boxes.
 void upload_boxes(mrcm3d_ctx* c, const mrcm3d::Setup& S, const std::vector<mrcm3d::Box>& boxes,
-                  const std::vector<mrcm3d::PlaneFactor>& F, mrcm3d::Box3*& dbox, double*& ddinv,
+                  const std::vector<mrcm3d::PlaneFactor>& F, mrcm3d::Box3*& dbox, void*& ddinv,
                   double*& dcoup, int& max_cells, int& max_plane) {
   std::vector<mrcm3d::Box3> desc(boxes.size());
   std::vector<double> dinv, coup;
@@ -156,9 +163,15 @@ void upload_boxes(mrcm3d_ctx* c, const mrcm3d::Setup& S, const std::vector<mrcm3
     dinv.insert(dinv.end(), F[i].dinv.begin(), F[i].dinv.end());
     coup.insert(coup.end(), F[i].coup.begin(), F[i].coup.end());
   }
-  c->factor_bytes += 2.0 * 8.0 * (double)dinv.size();
+  const double word = S.precision == 2 ? 4.0 : 8.0;
+  c->factor_bytes += 2.0 * word * (double)dinv.size();
   dbox = c->upload(desc);
-  ddinv = c->upload(dinv);
+  if (S.precision == 2) {
+    const std::vector<float> f(dinv.begin(), dinv.end());
+    ddinv = c->upload(f);
+  } else {
+    ddinv = c->upload(dinv);
+  }
   dcoup = c->upload(coup);
 }
 
@@ -191,9 +204,14 @@ void coarse_sweep(mrcm3d_ctx* c, const double* g, double* x, hipStream_t s) {
 void apply3(mrcm3d_ctx* c, const double* r, double* z) {
   hipStream_t s = c->st;
   hipEvent_t e = start_mark(c);
-  mrcm3d::launch_local3(c->lbox, c->m, c->lmax_cells, c->lmax_plane, c->ldinv, c->lcoup, r, c->p,
-                        c->nx, c->ny, c->dof_off, c->dofs, c->fin, c->fout, c->fw, c->mU, c->mP,
-                        s);
+  if (c->precision == 2)
+    mrcm3d::launch_local3(c->lbox, c->m, c->lmax_cells, c->lmax_plane,
+                          static_cast<const float*>(c->ldinv), c->lcoup, r, c->p, c->nx, c->ny,
+                          c->dof_off, c->dofs, c->fin, c->fout, c->fw, c->mU, c->mP, s);
+  else
+    mrcm3d::launch_local3(c->lbox, c->m, c->lmax_cells, c->lmax_plane,
+                          static_cast<const double*>(c->ldinv), c->lcoup, r, c->p, c->nx, c->ny,
+                          c->dof_off, c->dofs, c->fin, c->fout, c->fw, c->mU, c->mP, s);
   if (e) mark(c, 0, e);
   if (c->nc > 0) {
     e = start_mark(c);
@@ -215,8 +233,14 @@ void apply3(mrcm3d_ctx* c, const double* r, double* z) {
     mrcm3d::launch_residual3(c->tx, c->ty, c->tz, c->nx, c->ny, c->nz, r, c->p, c->rho, s);
     if (e) mark(c, 3, e);
     e = start_mark(c);
-    mrcm3d::launch_patch3(c->pbox, c->m, c->pmax_cells, c->pmax_plane, c->pdinv, c->pcoup, c->rho,
-                          c->p, c->nx, c->ny, s);
+    if (c->precision == 2)
+      mrcm3d::launch_patch3(c->pbox, c->m, c->pmax_cells, c->pmax_plane,
+                            static_cast<const float*>(c->pdinv), c->pcoup, c->rho, c->p, c->nx,
+                            c->ny, s);
+    else
+      mrcm3d::launch_patch3(c->pbox, c->m, c->pmax_cells, c->pmax_plane,
+                            static_cast<const double*>(c->pdinv), c->pcoup, c->rho, c->p, c->nx,
+                            c->ny, s);
     if (e) mark(c, 4, e);
   }
   e = start_mark(c);
@@ -260,6 +284,7 @@ int mrcm3d_setup(const mrcm3d_grid* grid, const mrcm3d_params* params, const dou
     c->m = S.m;
     c->nc = S.nc;
     c->sweeps = S.sweeps;
+    c->precision = S.precision;
     c->noflow = S.noflow ? 1 : 0;
     c->tx = c->upload(S.tx);
     c->ty = c->upload(S.ty);
@@ -331,8 +356,6 @@ int mrcm3d_setup(const mrcm3d_grid* grid, const mrcm3d_params* params, const dou
       c->cv = c->upload(F.nd_v);
       c->coarse_bytes = 8.0 * ((double)T.fwd_len + (double)T.bwd_len);
       c->resid_bytes = 12.0 * (double)F.nd_v.size() + 4.0 * (c->np + 1) + 24.0 * c->np;
-      // the upload reads the host tables: finish it before they go
-      check3(hipStreamSynchronize(c->st), "hipStreamSynchronize");
     }
     const size_t nc = std::max(S.nc, 1);
     c->p = c->alloc<double>(S.n);

@@ -32,12 +32,15 @@ struct Dof3 {
 // box-local inside and outside cell, four weights per face).  max_cells and
 // max_plane: the most cells and plane cells of a box of the launch (its LDS
 // and threads, whole waves; at most kMaxBox3Cells and kBox3Threads).
-void launch_local3(const Box3* boxes, int m, int max_cells, int max_plane, const double* dinv,
+// S: the storage type of the plane blocks (double or float), FP64 arithmetic.
+template <typename S>
+void launch_local3(const Box3* boxes, int m, int max_cells, int max_plane, const S* dinv,
                    const double* coup, const double* r, double* p, int nx, int ny,
                    const int* dof_off, const Dof3* dofs, const int* fin, const int* fout,
                    const double* fw, double* mU, double* mP, hipStream_t s);
 // Patch solves of the smoothing sweep: p += A[S_i]^-1 rho[S_i] on the owned cells.
-void launch_patch3(const Box3* boxes, int m, int max_cells, int max_plane, const double* dinv,
+template <typename S>
+void launch_patch3(const Box3* boxes, int m, int max_cells, int max_plane, const S* dinv,
                    const double* coup, const double* rho, double* p, int nx, int ny,
                    hipStream_t s);
 // p[Omega_i] += P_i x_i (one workgroup per subdomain; mbf_off per subdomain).

@@ -37,19 +37,20 @@ __device__ __forceinline__ long long global_cell(const Box3& d, int q, int nx, i
 // words of one diagonal in both terms, so each stored word comes from HBM
 // once.  Odd and even d in separate sums, added as (even up + odd up) +
 // (even down + odd down): the host solve's order.
-__device__ __forceinline__ double plane_dot(const double* __restrict__ D, const double* v, int P,
+template <typename S>
+__device__ __forceinline__ double plane_dot(const S* __restrict__ D, const double* v, int P,
                                             int t) {
   const int H = P / 2 + 1;
-  double u0 = D[t] * v[t], u1 = 0.0, w0 = 0.0, w1 = 0.0;
+  double u0 = (double)D[t] * v[t], u1 = 0.0, w0 = 0.0, w1 = 0.0;
   int up = t, dn = t;
   int d = 1;
   for (; d + 1 < H; d += 2) {
     up = up + 1 == P ? 0 : up + 1;
     dn = dn == 0 ? P - 1 : dn - 1;
-    const double* r1 = D + (long long)d * P;
+    const S* r1 = D + (long long)d * P;
     const double a1 = r1[t], b1 = r1[dn], x1 = v[up], y1 = v[dn];
     const int up2 = up + 1 == P ? 0 : up + 1, dn2 = dn == 0 ? P - 1 : dn - 1;
-    const double* r2 = r1 + P;
+    const S* r2 = r1 + P;
     const double a2 = r2[t], b2 = r2[dn2], x2 = v[up2], y2 = v[dn2];
     u1 = fma(a1, x1, u1);
     if (2 * d != P) w1 = fma(b1, y1, w1);
@@ -61,23 +62,24 @@ __device__ __forceinline__ double plane_dot(const double* __restrict__ D, const 
   if (d < H) {
     up = up + 1 == P ? 0 : up + 1;
     dn = dn == 0 ? P - 1 : dn - 1;
-    const double* r1 = D + (long long)d * P;
+    const S* r1 = D + (long long)d * P;
     double& u = d & 1 ? u1 : u0;
     double& w = d & 1 ? w1 : w0;
-    u = fma(r1[t], v[up], u);
-    if (2 * d != P) w = fma(r1[dn], v[dn], w);
+    u = fma((double)r1[t], v[up], u);
+    if (2 * d != P) w = fma((double)r1[dn], v[dn], w);
   }
   return (u0 + u1) + (w0 + w1);
 }
 
 // Block LDL^T solve of the box in LDS: us holds b on entry and x on exit in
 // planes stop .. bz - 1 (planes below keep their forward values).
+template <typename S>
 __device__ __forceinline__ void plane_solve(double* us, double* v, const Box3& d,
-                                            const double* __restrict__ dinv,
+                                            const S* __restrict__ dinv,
                                             const double* __restrict__ coup, int stop) {
   const int P = d.P, bz = d.n[2], t = threadIdx.x;
   const long long HP = (long long)(P / 2 + 1) * P;  // words of one stored block
-  const double* D = dinv + d.doff;
+  const S* D = dinv + d.doff;
   const double* T = coup + d.coff;
   for (int j = 0; j < bz; ++j) {
     if (t < P) v[t] = j > 0 ? fma(T[(long long)j * P + t], us[(j - 1) * P + t], us[j * P + t])
@@ -94,9 +96,11 @@ __device__ __forceinline__ void plane_solve(double* us, double* v, const Box3& d
   }
 }
 
-// LDS: us[cells] | v[P].
+// LDS: us[cells] | v[P].  S: the storage type of the plane blocks (FP64 or
+// FP32); the arithmetic is FP64.
+template <typename S>
 __global__ void __launch_bounds__(kBox3Threads)
-    k_local3(const Box3* __restrict__ boxes, const double* __restrict__ dinv,
+    k_local3(const Box3* __restrict__ boxes, const S* __restrict__ dinv,
              const double* __restrict__ coup, const double* __restrict__ r,
              double* __restrict__ p, int nx, int ny, const int* __restrict__ dof_off,
              const Dof3* __restrict__ dofs, const int* __restrict__ fin,
@@ -138,8 +142,9 @@ __global__ void __launch_bounds__(kBox3Threads)
   }
 }
 
+template <typename S>
 __global__ void __launch_bounds__(kBox3Threads)
-    k_patch3(const Box3* __restrict__ boxes, const double* __restrict__ dinv,
+    k_patch3(const Box3* __restrict__ boxes, const S* __restrict__ dinv,
              const double* __restrict__ coup, const double* __restrict__ rho,
              double* __restrict__ p, int nx, int ny) {
   extern __shared__ double sm3[];
@@ -268,23 +273,35 @@ inline int grid3(long long n) {
 // Threads of a box launch: one per cell of the widest plane, whole waves.
 inline int box3_threads(int max_plane) { return (max_plane + 63) / 64 * 64; }
 
-void launch_local3(const Box3* boxes, int m, int max_cells, int max_plane, const double* dinv,
+template <typename S>
+void launch_local3(const Box3* boxes, int m, int max_cells, int max_plane, const S* dinv,
                    const double* coup, const double* r, double* p, int nx, int ny,
                    const int* dof_off, const Dof3* dofs, const int* fin, const int* fout,
                    const double* fw, double* mU, double* mP, hipStream_t s) {
   if (m <= 0) return;
   const size_t shm = sizeof(double) * (max_cells + max_plane);
-  hipLaunchKernelGGL(k_local3, dim3(m), dim3(box3_threads(max_plane)), shm, s, boxes, dinv, coup,
-                     r, p, nx, ny, dof_off, dofs, fin, fout, fw, mU, mP);
+  hipLaunchKernelGGL(k_local3<S>, dim3(m), dim3(box3_threads(max_plane)), shm, s, boxes, dinv,
+                     coup, r, p, nx, ny, dof_off, dofs, fin, fout, fw, mU, mP);
 }
-void launch_patch3(const Box3* boxes, int m, int max_cells, int max_plane, const double* dinv,
+template <typename S>
+void launch_patch3(const Box3* boxes, int m, int max_cells, int max_plane, const S* dinv,
                    const double* coup, const double* rho, double* p, int nx, int ny,
                    hipStream_t s) {
   if (m <= 0) return;
   const size_t shm = sizeof(double) * (max_cells + max_plane);
-  hipLaunchKernelGGL(k_patch3, dim3(m), dim3(box3_threads(max_plane)), shm, s, boxes, dinv, coup,
-                     rho, p, nx, ny);
+  hipLaunchKernelGGL(k_patch3<S>, dim3(m), dim3(box3_threads(max_plane)), shm, s, boxes, dinv,
+                     coup, rho, p, nx, ny);
 }
+#define MRCM3D_INSTANTIATE(S)                                                                  \
+  template void launch_local3<S>(const Box3*, int, int, int, const S*, const double*,          \
+                                 const double*, double*, int, int, const int*, const Dof3*,    \
+                                 const int*, const int*, const double*, double*, double*,      \
+                                 hipStream_t);                                                 \
+  template void launch_patch3<S>(const Box3*, int, int, int, const S*, const double*,          \
+                                 const double*, double*, int, int, hipStream_t);
+MRCM3D_INSTANTIATE(double)
+MRCM3D_INSTANTIATE(float)
+#undef MRCM3D_INSTANTIATE
 void launch_reconstruct3(const Box3* boxes, int m, const double* mbf, const long long* mbf_off,
                          const int* dof_off, const double* x, double* p, int nx, int ny,
                          hipStream_t s) {

@@ -328,7 +328,8 @@ void box_solve(const PlaneFactor& F, double* x) {
 
 void host_setup(Setup& S, const mrcm3d_grid& g, const mrcm3d_params& p, const double* Kin) {
   if (g.nx < 1 || g.ny < 1 || g.nz < 1 || p.sx < 1 || p.sy < 1 || p.sz < 1 || p.oversample < 0 ||
-      p.smooth_sweeps < 0 || p.smooth_overlap < 0 || p.iface_degree < 0 || !(p.alpha > 0.0))
+      p.smooth_sweeps < 0 || p.smooth_overlap < 0 || p.iface_degree < 0 || !(p.alpha > 0.0) ||
+      (p.precision != 0 && p.precision != 2))
     throw Error(MRCM_EINVAL, "invalid grid or parameters");
   S.nx = g.nx;
   S.ny = g.ny;
@@ -342,6 +343,7 @@ void host_setup(Setup& S, const mrcm3d_grid& g, const mrcm3d_params& p, const do
   S.sweeps = p.smooth_sweeps;
   S.overlap = p.smooth_overlap;
   S.degree = p.iface_degree;
+  S.precision = p.precision;
   S.alpha = p.alpha;
   S.Lcells = p.beta_len == 0 ? (double)std::max(p.sx, std::max(p.sy, p.sz)) : 1.0;
   S.n = (long long)g.nx * g.ny * g.nz;
@@ -569,8 +571,17 @@ void host_setup(Setup& S, const mrcm3d_grid& g, const mrcm3d_params& p, const do
     S.CF = mrcm::coarse_factor_tree(dissection3(S.mdims[0], S.mdims[1], S.mdims[2]), rows_of,
                                     S.dof_off, S.Crp, S.Cci, S.Cv,
                                     std::max(1, omp_get_max_threads()));
-    mrcm::coarse_refine_steps(S.CF, mrcm::kCoarseRefineTol, mrcm::kCoarseRefineMax);
+    // refinement to 1e-10 of the solution in FP64, to 1e-6 with FP32-stored
+    // blocks (below their own effect on T), as in 2-D
+    mrcm::coarse_refine_steps(S.CF, mrcm::coarse_refine_tol(S.precision),
+                              mrcm::kCoarseRefineMax);
   }
+  // precision 2: the apply reads the plane blocks rounded to FP32 (the MBFs,
+  // C and its factor above came from the FP64 blocks)
+  if (S.precision == 2)
+    for (auto* list : {&S.over, &S.patch})
+      for (PlaneFactor& F : *list)
+        for (double& x : F.dinv) x = (double)(float)x;
 }
 
 std::vector<mrcm::DissectionNode> dissection3(int mx, int my, int mz) {

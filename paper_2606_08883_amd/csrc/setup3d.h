@@ -59,6 +59,7 @@ struct SideData {
 struct Setup {
   int nx = 0, ny = 0, nz = 0, bc[6] = {0, 0, 0, 0, 0, 0};
   int sx = 0, sy = 0, sz = 0, oversample = 0, sweeps = 0, overlap = 0, degree = 1;
+  int precision = 0;  // 0 FP64, 2 FP32-stored plane blocks
   double alpha = 0.0, Lcells = 1.0;
   bool noflow = false;
   long long n = 0;

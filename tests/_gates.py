@@ -12,6 +12,9 @@ mode 1, so its first-order relative error is at most about
 (2 rows + cols) u32 (u32 = 2^-24); T chains the local solve and one patch
 solve per smoothing sweep, so mixed_t_gate = (k + 1) (2 rows + cols) u32
 with rows and cols the largest extents of the oversampled boxes and patches.
+In 3-D (precision 2) a box recurrence runs over its z-planes and each product
+has up to P = bx by terms (the plane), so mixed_t_gate3 = (k + 1)
+(2 planes + P) u32 with the largest plane count and plane size.
 
 The interface system C x = g of T is the one step whose conditioning can
 exceed what 1e-10 allows (the 1e6-contrast channel field, the sigma = 3
@@ -66,3 +69,11 @@ def mixed_t_gate(mr) -> float:
     rows = max(int(b[3] - b[2]) for b in boxes)
     cols = max(int(b[1] - b[0]) for b in boxes)
     return (mr.sweeps + 1) * (2 * rows + cols) * UNIT_ROUNDOFF_32
+
+
+def mixed_t_gate3(mr) -> float:
+    P = mr.part
+    boxes = list(P.oboxes) + (list(P.pboxes) if mr.sweeps > 0 else [])
+    planes = max(int(b[5] - b[4]) for b in boxes)
+    plane = max(int((b[1] - b[0]) * (b[3] - b[2])) for b in boxes)
+    return (mr.sweeps + 1) * (2 * planes + plane) * UNIT_ROUNDOFF_32

@@ -13,6 +13,7 @@ import pytest
 
 from oracle import mrcm3d as M3
 from paper_2606_08883_amd import binding as B
+from tests._gates import mixed_t_gate3
 
 CASES = [
     # nx, ny, nz, (sx, sy, sz), l, k, bc
@@ -103,3 +104,29 @@ def test_dissection_tree_separates_regions(dims):
             for b in children[t]:
                 if a < b:
                     assert not any(q in region[b] for s in region[a] for q in nbrs(s))
+
+
+@pytest.mark.parametrize("case", CASES[1:4], ids=[f"{c[0]}x{c[1]}x{c[2]}-l{c[4]}-k{c[5]}" for c in CASES[1:4]])
+def test_host_apply_fp32_storage(case):
+    """Precision 2 rounds the plane blocks to FP32 after the FP64 set-up: T
+    moves off the FP64 operator by at most the recurrence bound
+    (k + 1)(2 planes + P) 2^-24 and by more than FP64 rounding."""
+    nx, ny, nz, s, l, k, bc = case
+    n = nx * ny * nz
+    K = _field(n, 3)
+    r = np.random.Generator(np.random.PCG64(7)).standard_normal(n)
+    if not any(bc):
+        r -= r.mean()
+    mr = M3.MRCM3D(K, nx, ny, nz, bc, *s, l, 10.0, "H", k, 2, 1)
+    z_ref = mr.apply(r)
+    z, _ = B.test3d_host_apply(B.Config3(nx, ny, nz, bc, *s, l, 10.0, 0, k, 2, 1, 2), K, r)
+    err = np.linalg.norm(z - z_ref) / np.linalg.norm(z_ref)
+    assert 1e-12 < err <= mixed_t_gate3(mr)
+
+
+def test_fp32_arithmetic_not_offered_in_3d():
+    n = 8 * 8 * 8
+    with pytest.raises(B.MrcmError) as e:
+        B.test3d_host_apply(B.Config3(8, 8, 8, (1,) * 6, 4, 4, 4, 0, 10.0, 0, 0, 2, 1, 1),
+                            _field(n, 4), np.zeros(n))
+    assert e.value.code == B.MRCM_EINVAL
