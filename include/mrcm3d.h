@@ -76,6 +76,16 @@ int mrcm3d_apply(mrcm3d_ctx* ctx, const double* r, double* z, void* stream);
 /* y = A x (the seven-point operator).  x, y: device, may not alias. */
 int mrcm3d_op_apply(mrcm3d_ctx* ctx, const double* x, double* y, void* stream);
 
+/* Right-hand side of the fine system (Section 3, d = 3): b = f h^2 plus
+ * 2 K_c g on every Dirichlet boundary face.  f_cell: device n values or NULL
+ * (zero source); g_bc: device, the Dirichlet face values of the six sides
+ * concatenated in the order W, E (ny nz values each, face (y, z) at
+ * z ny + y), S, N (nx nz each, z nx + x), B, T (nx ny each, y nx + x), or
+ * NULL; entries of no-flow sides are ignored; h: cell size (> 0); b: device
+ * n values. */
+int mrcm3d_rhs(mrcm3d_ctx* ctx, const double* f_cell, const double* g_bc, double h, double* b,
+               void* stream);
+
 /* Right-preconditioned restarted GMRES (Algorithm 1, as gmres_solve: p_0 = 0,
  * modified Gram-Schmidt, estimated residual tested after every step, true
  * FP64 residual at every cycle end).  One right-hand side b (device); p

@@ -27,7 +27,7 @@ EXPORTED = ["mrcm_map_sizes", "mrcm_maps", "mrcm_setup", "mrcm_apply", "mrcm_app
             "mrcm_set_host_threads",
             "gmres_batch_create", "gmres_batch_add", "gmres_batch_tick", "gmres_batch_poll",
             "gmres_batch_remove", "gmres_batch_destroy",
-            "mrcm3d_setup", "mrcm3d_apply", "mrcm3d_op_apply", "mrcm3d_gmres_solve",
+            "mrcm3d_setup", "mrcm3d_apply", "mrcm3d_op_apply", "mrcm3d_rhs", "mrcm3d_gmres_solve",
             "mrcm3d_timing_enable", "mrcm3d_timing_read", "mrcm3d_query", "mrcm3d_destroy",
             "mrcm_destroy",
             "mrcm_last_error"]
@@ -122,6 +122,7 @@ def lib() -> ctypes.CDLL:
                               ctypes.POINTER(P)], i32),
             "mrcm3d_apply": ([P, P, P, P], i32),
             "mrcm3d_op_apply": ([P, P, P, P], i32),
+            "mrcm3d_rhs": ([P, P, P, dbl, P, P], i32),
             "mrcm3d_gmres_solve": ([P, P, P, dbl, i32, i32, ctypes.POINTER(Stats), P], i32),
             "mrcm3d_timing_enable": ([P, i32], i32),
             "mrcm3d_timing_read": ([P, pd, pi64], i32),
@@ -357,6 +358,14 @@ class Context3:
     def op(self, x, y, stream=None):
         _check(lib().mrcm3d_op_apply(self._ptr, _dptr(x, self.n), _dptr(y, self.n),
                                      _stream(stream)))
+
+    def rhs(self, f, g, h: float, b, stream=None):
+        """b = f h^2 + 2 K g on the Dirichlet faces (mrcm3d_rhs); f, g: device or None."""
+        c = self.cfg
+        ng = 2 * (c.ny * c.nz + c.nx * c.nz + c.nx * c.ny)
+        _check(lib().mrcm3d_rhs(self._ptr, _dptr(f, self.n) if f is not None else None,
+                                _dptr(g, ng) if g is not None else None, h,
+                                _dptr(b, self.n), _stream(stream)))
 
     def gmres(self, b, p, rtol: float = 1e-8, restart: int = 10, maxit: int = 300,
               stream=None, raise_on_noconv: bool = True) -> SolveStats:

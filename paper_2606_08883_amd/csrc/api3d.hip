@@ -30,6 +30,7 @@ void check3(hipError_t e, const char* what) {
 
 struct mrcm3d_ctx {
   int nx = 0, ny = 0, nz = 0, m = 0, nc = 0, sweeps = 0, noflow = 0;
+  int bcmask = 0;  // bit s: side s (W E S N B T) has Dirichlet data
   long long n = 0;
   std::vector<void*> allocs;
   size_t device_bytes = 0;
@@ -286,6 +287,7 @@ int mrcm3d_setup(const mrcm3d_grid* grid, const mrcm3d_params* params, const dou
     c->sweeps = S.sweeps;
     c->precision = S.precision;
     c->noflow = S.noflow ? 1 : 0;
+    for (int sd = 0; sd < 6; ++sd) c->bcmask |= S.bc[sd] ? 1 << sd : 0;
     c->tx = c->upload(S.tx);
     c->ty = c->upload(S.ty);
     c->tz = c->upload(S.tz);
@@ -412,6 +414,20 @@ int mrcm3d_op_apply(mrcm3d_ctx* c, const double* x, double* y, void* stream) {
     if (!c || !x || !y) throw mrcm::Error(MRCM_EINVAL, "invalid argument");
     mrcm3d::launch_op3(c->tx, c->ty, c->tz, c->nx, c->ny, c->nz, x, y,
                        static_cast<hipStream_t>(stream));
+    check3(hipGetLastError(), "kernel launch");
+    return MRCM_OK;
+  } catch (const mrcm::Error& e) {
+    return fail3(e);
+  }
+}
+
+int mrcm3d_rhs(mrcm3d_ctx* c, const double* f_cell, const double* g_bc, double h, double* b,
+               void* stream) {
+  try {
+    if (!c || !b || !(h > 0.0) || !std::isfinite(h))
+      throw mrcm::Error(MRCM_EINVAL, "invalid argument");
+    mrcm3d::launch_rhs3(c->tx, c->ty, c->tz, c->nx, c->ny, c->nz, c->bcmask, f_cell, g_bc, h, b,
+                        static_cast<hipStream_t>(stream));
     check3(hipGetLastError(), "kernel launch");
     return MRCM_OK;
   } catch (const mrcm::Error& e) {

@@ -53,6 +53,11 @@ void launch_op3(const double* tx, const double* ty, const double* tz, int nx, in
                 const double* x, double* y, hipStream_t s);
 void launch_residual3(const double* tx, const double* ty, const double* tz, int nx, int ny,
                       int nz, const double* r, const double* p, double* rho, hipStream_t s);
+// b = f h^2 (f may be NULL) plus 2 K_c g on the Dirichlet boundary faces
+// (bcmask bit s for side s of W, E, S, N, B, T; g may be NULL).
+void launch_rhs3(const double* tx, const double* ty, const double* tz, int nx, int ny, int nz,
+                 int bcmask, const double* f, const double* g, double h, double* b,
+                 hipStream_t s);
 void launch_arnoldi_start3(const double* tx, const double* ty, const double* tz, int nx, int ny,
                            int nz, const double* z, double* w, const double* v0,
                            double* partials, int nb, hipStream_t s);

@@ -263,6 +263,38 @@ __global__ void __launch_bounds__(kVec3Threads)
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// b = f h^2 plus t_f g_f on every Dirichlet boundary face (t_f = 2 K_c
+// there), sides in the order W, E, S, N, B, T; g: the six sides' face values
+// concatenated (W, E: z ny + y; S, N: z nx + x; B, T: y nx + x).
+__global__ void __launch_bounds__(kVec3Threads)
+    k_rhs3(const double* __restrict__ tx, const double* __restrict__ ty,
+           const double* __restrict__ tz, int nx, int ny, int nz, int bcmask,
+           const double* __restrict__ f, const double* __restrict__ g, double h,
+           double* __restrict__ b) {
+  const long long n = (long long)nx * ny * nz;
+  const long long oW = 0, oE = (long long)ny * nz, oS = 2LL * ny * nz,
+                  oN = oS + (long long)nx * nz, oB = oN + (long long)nx * nz,
+                  oT = oB + (long long)nx * ny;
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
+       c += (long long)gridDim.x * blockDim.x) {
+    const int ix = (int)(c % nx), iy = (int)((c / nx) % ny), iz = (int)(c / ((long long)nx * ny));
+    double v = f ? f[c] * h * h : 0.0;
+    if (g) {
+      const long long fx = ((long long)iz * ny + iy) * (nx + 1) + ix;
+      const long long fy = ((long long)iz * (ny + 1) + iy) * nx + ix;
+      const long long fz = ((long long)iz * ny + iy) * nx + ix;
+      if (ix == 0 && (bcmask & 1)) v += tx[fx] * g[oW + (long long)iz * ny + iy];
+      if (ix == nx - 1 && (bcmask & 2)) v += tx[fx + 1] * g[oE + (long long)iz * ny + iy];
+      if (iy == 0 && (bcmask & 4)) v += ty[fy] * g[oS + (long long)iz * nx + ix];
+      if (iy == ny - 1 && (bcmask & 8)) v += ty[fy + nx] * g[oN + (long long)iz * nx + ix];
+      if (iz == 0 && (bcmask & 16)) v += tz[fz] * g[oB + (long long)iy * nx + ix];
+      if (iz == nz - 1 && (bcmask & 32))
+        v += tz[fz + (long long)nx * ny] * g[oT + (long long)iy * nx + ix];
+    }
+    b[c] = v;
+  }
+}
+
 inline int grid3(long long n) {
   long long b = (n + kVec3Threads - 1) / kVec3Threads;
   return (int)(b < 1 ? 1 : b > 4096 ? 4096 : b);
@@ -318,6 +350,12 @@ void launch_residual3(const double* tx, const double* ty, const double* tz, int 
                       int nz, const double* r, const double* p, double* rho, hipStream_t s) {
   hipLaunchKernelGGL(k_op3, dim3(grid3((long long)nx * ny * nz)), dim3(kVec3Threads), 0, s, tx,
                      ty, tz, nx, ny, nz, p, rho, r, 1);
+}
+void launch_rhs3(const double* tx, const double* ty, const double* tz, int nx, int ny, int nz,
+                 int bcmask, const double* f, const double* g, double h, double* b,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_rhs3, dim3(grid3((long long)nx * ny * nz)), dim3(kVec3Threads), 0, s, tx,
+                     ty, tz, nx, ny, nz, bcmask, f, g, h, b);
 }
 void launch_arnoldi_start3(const double* tx, const double* ty, const double* tz, int nx, int ny,
                            int nz, const double* z, double* w, const double* v0,

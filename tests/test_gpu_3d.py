@@ -214,3 +214,37 @@ def test_fp32_storage_3d(dev, case):
     assert st.converged and abs(st.iterations - ref.iterations) <= 1
     assert rel <= 1e-8 * (1 + 1e-6)
     ctx.close()
+
+
+def test_rhs_and_dirichlet_solve_3d(dev):
+    """mrcm3d_rhs against the oracle's right-hand side (random source and face
+    values on all six sides, of which the no-flow sides' are ignored), and
+    the GMRES solution of A p = b driven to 1e-10 against the sparse direct
+    solve (the plain definition of the converged result)."""
+    case = CASES[3]   # 14 x 9 x 13, Dirichlet on E, S and T
+    print(f"3-D right-hand side and Dirichlet solve: {case}", flush=True)
+    cfg, K, ctx, mr = _setup(case, dev)
+    nx, ny, nz = cfg.nx, cfg.ny, cfg.nz
+    rng = np.random.Generator(np.random.PCG64(11))
+    f = rng.standard_normal(cfg.n)
+    shapes = [(nz, ny), (nz, ny), (nz, nx), (nz, nx), (ny, nx), (ny, nx)]
+    sides = [rng.standard_normal(sh) for sh in shapes]
+    h = 1.0 / nx
+    b_ref = M3.rhs(K, nx, ny, nz, cfg.bc, f, {sd: sides[sd] for sd in range(6)}, h)
+    T = lambda a: torch.tensor(np.ascontiguousarray(a).ravel(), dtype=torch.float64, device=dev)  # noqa: E731
+    b = torch.empty(cfg.n, dtype=torch.float64, device=dev)
+    ctx.rhs(T(f), T(np.concatenate([x.ravel() for x in sides])), h, b)
+    b0 = torch.empty_like(b)
+    ctx.rhs(None, None, h, b0)
+    torch.cuda.synchronize()
+    bg = b.cpu().numpy()
+    assert np.abs(bg - b_ref).max() <= 1e-15 * np.abs(b_ref).max()
+    assert not b0.abs().max().item()
+    p = torch.zeros_like(b)
+    st = ctx.gmres(b, p, rtol=1e-10, restart=10, maxit=300)
+    torch.cuda.synchronize()
+    p_ref = M3.direct_solve(mr.A, b_ref, cfg.bc)
+    err = np.linalg.norm(p.cpu().numpy() - p_ref) / np.linalg.norm(p_ref)
+    print(f"  GMRES {st.iterations} steps; solution against the direct solve {err:.2e}", flush=True)
+    assert st.converged and err <= 1e-7
+    ctx.close()
