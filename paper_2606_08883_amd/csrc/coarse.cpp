@@ -112,36 +112,63 @@ void lu_solve_cols(const double* __restrict__ A, int n, double* __restrict__ X, 
 
 // Inverse of a dense n x n row-major matrix by LU with partial pivoting, nth
 // OpenMP threads in its loops.  Returns the smallest |pivot| / max|A| ratio
-// (0 when singular).
+// (0 when singular).  The factorisation is blocked by panels of kPanel
+// columns: each panel is factored with row pivoting over the whole column
+// (full rows swapped), the panel's rows of U to its right are formed by the
+// unit-lower panel, and the trailing matrix takes the panel's rank-kPanel
+// update through gemm.  The pivots are those of the unblocked elimination;
+// every trailing entry receives its updates in the same order of k.
 double lu_inverse(std::vector<double>& A, int n, std::vector<double>& inv, int nth) {
+  constexpr int kPanel = 64;
   double amax = 0.0;
   for (double v : A) amax = std::max(amax, std::fabs(v));
   std::vector<int> perm(n);
   for (int i = 0; i < n; ++i) perm[i] = i;
   double ratio = 1.0;
-  for (int k = 0; k < n; ++k) {
-    int p = k;
-    double best = std::fabs(A[(size_t)k * n + k]);
-    for (int i = k + 1; i < n; ++i)
-      if (std::fabs(A[(size_t)i * n + k]) > best) {
-        best = std::fabs(A[(size_t)i * n + k]);
-        p = i;
+  for (int k0 = 0; k0 < n; k0 += kPanel) {
+    const int k1 = std::min(n, k0 + kPanel);
+    for (int k = k0; k < k1; ++k) {
+      int p = k;
+      double best = std::fabs(A[(size_t)k * n + k]);
+      for (int i = k + 1; i < n; ++i)
+        if (std::fabs(A[(size_t)i * n + k]) > best) {
+          best = std::fabs(A[(size_t)i * n + k]);
+          p = i;
+        }
+      if (!(best > 0.0) || !std::isfinite(best)) return 0.0;
+      ratio = std::min(ratio, best / amax);
+      if (p != k) {
+        for (int j = 0; j < n; ++j) std::swap(A[(size_t)k * n + j], A[(size_t)p * n + j]);
+        std::swap(perm[k], perm[p]);
       }
-    if (!(best > 0.0) || !std::isfinite(best)) return 0.0;
-    ratio = std::min(ratio, best / amax);
-    if (p != k) {
-      for (int j = 0; j < n; ++j) std::swap(A[(size_t)k * n + j], A[(size_t)p * n + j]);
-      std::swap(perm[k], perm[p]);
-    }
-    const double piv = A[(size_t)k * n + k];
-    const bool par = !omp_in_parallel() && (double)(n - k) * (n - k) > 2e5;
+      const double piv = A[(size_t)k * n + k];
+      // the multipliers of column k and the update of the panel's columns
+      const bool par = !omp_in_parallel() && (double)(n - k) * (k1 - k) > 2e5;
 #pragma omp parallel for schedule(static) num_threads(nth) if (par)
-    for (int i = k + 1; i < n; ++i) {
-      double l = A[(size_t)i * n + k] / piv;
-      A[(size_t)i * n + k] = l;
-      if (l == 0.0) continue;
-      for (int j = k + 1; j < n; ++j) A[(size_t)i * n + j] -= l * A[(size_t)k * n + j];
+      for (int i = k + 1; i < n; ++i) {
+        double l = A[(size_t)i * n + k] / piv;
+        A[(size_t)i * n + k] = l;
+        if (l == 0.0) continue;
+        for (int j = k + 1; j < k1; ++j) A[(size_t)i * n + j] -= l * A[(size_t)k * n + j];
+      }
     }
+    if (k1 == n) break;
+    // the panel's rows of U right of the panel: unit-lower panel solve
+    const int nt = n - k1;
+    const bool par = !omp_in_parallel() && (double)nt * (k1 - k0) * (k1 - k0) > 2e5;
+#pragma omp parallel for schedule(static) num_threads(nth) if (par)
+    for (int jb = 0; jb < nt; jb += 64) {
+      const int j0 = k1 + jb, j1 = std::min(n, j0 + 64);
+      for (int k = k0; k < k1; ++k)
+        for (int i = k + 1; i < k1; ++i) {
+          const double l = A[(size_t)i * n + k];
+          if (l == 0.0) continue;
+          for (int j = j0; j < j1; ++j) A[(size_t)i * n + j] -= l * A[(size_t)k * n + j];
+        }
+    }
+    // trailing update A22 -= L21 U12
+    gemm(nt, nt, k1 - k0, -1.0, &A[(size_t)k1 * n + k0], n, &A[(size_t)k0 * n + k1], n, 1.0,
+         &A[(size_t)k1 * n + k1], n, nth);
   }
   // inv = U^-1 L^-1 P: the permuted identity, solved a block of columns at a
   // time

@@ -194,7 +194,7 @@ bool spd_inverse(double* A, int n) {
 // domain-boundary faces keep the global condition, faces leaving the box
 // inside the domain carry rho_f (robin) or t_f with zero data beyond (the
 // principal submatrix of A).
-PlaneFactor factor_box(const Setup& S, const Box& b, bool robin) {
+PlaneFactor factor_box(const Setup& S, const Box& b, bool robin, bool keep_full) {
   PlaneFactor F;
   const int bx = b.n(0), by = b.n(1), bz = b.n(2), P = bx * by;
   F.P = P;
@@ -255,6 +255,7 @@ PlaneFactor factor_box(const Setup& S, const Box& b, bool robin) {
     double* Dh = &F.dinv[(size_t)j * H * P];
     for (int d = 0; d < H; ++d)
       for (int t = 0; t < P; ++t) Dh[(size_t)d * P + t] = D[(size_t)t * P + (t + d) % P];
+    if (keep_full) F.full.insert(F.full.end(), D.begin(), D.end());
     std::swap(D, Dp);
   }
   return F;
@@ -304,6 +305,30 @@ double plane_dot(const double* D, const double* v, int P, int t) {
     if (2 * d != P) w = std::fma(row[dn], v[dn], w);
   }
   return (u0 + u1) + (w0 + w1);
+}
+
+void box_solve_full(const PlaneFactor& F, double* x) {
+  const int P = F.P, bz = F.bz;
+  if (F.pin) x[0] = 0.0;
+  std::vector<double> v(P);
+  auto product = [&](const double* D, double* out, bool add) {
+    for (int a = 0; a < P; ++a) {
+      const double* row = D + (size_t)a * P;
+      double s = 0.0;
+      for (int c = 0; c < P; ++c) s += row[c] * v[c];
+      out[a] = add ? out[a] + s : s;
+    }
+  };
+  for (int j = 0; j < bz; ++j) {
+    double* xj = x + (size_t)j * P;
+    for (int c = 0; c < P; ++c)
+      v[c] = j > 0 ? xj[c] + F.coup[(size_t)j * P + c] * x[(size_t)(j - 1) * P + c] : xj[c];
+    product(&F.full[(size_t)j * P * P], xj, false);
+  }
+  for (int j = bz - 2; j >= 0; --j) {
+    for (int c = 0; c < P; ++c) v[c] = F.coup[(size_t)(j + 1) * P + c] * x[(size_t)(j + 1) * P + c];
+    product(&F.full[(size_t)j * P * P], x + (size_t)j * P, true);
+  }
 }
 
 void box_solve(const PlaneFactor& F, double* x) {
@@ -466,8 +491,8 @@ void host_setup(Setup& S, const mrcm3d_grid& g, const mrcm3d_params& p, const do
     try {
       const Box& bi = S.boxes[i];
       const Box& oi = S.oboxes[i];
-      if (S.sweeps > 0) S.patch[i] = factor_box(S, S.pboxes[i], false);
-      S.over[i] = factor_box(S, oi, true);
+      if (S.sweeps > 0) S.patch[i] = factor_box(S, S.pboxes[i], false, false);
+      S.over[i] = factor_box(S, oi, true, true);
       const int Ni = S.dof_off[i + 1] - S.dof_off[i];
       S.mbf[i].assign((size_t)Ni * bi.cells(), 0.0);
       std::vector<double> ph((size_t)oi.cells());
@@ -483,7 +508,7 @@ void host_setup(Setup& S, const mrcm3d_grid& g, const mrcm3d_params& p, const do
           ph[((size_t)(z - oi.lo[2]) * oi.n(1) + (y - oi.lo[1])) * oi.n(0) + (x - oi.lo[0])] +=
               os.rho[f] * basis_value(ka, kb, (int)f, os.n0, os.n1);
         }
-        box_solve(S.over[i], ph.data());
+        box_solve_full(S.over[i], ph.data());
         double* pk = &S.mbf[i][(size_t)k * bi.cells()];
         for (int z = bi.lo[2]; z < bi.hi[2]; ++z)
           for (int y = bi.lo[1]; y < bi.hi[1]; ++y)
@@ -526,6 +551,7 @@ void host_setup(Setup& S, const mrcm3d_grid& g, const mrcm3d_params& p, const do
             }
         }
       }
+      std::vector<double>().swap(S.over[i].full);  // the full blocks are done with
     } catch (const Error& e) {
 #pragma omp critical
       {

@@ -36,6 +36,8 @@ struct PlaneFactor {
   int P = 0, bz = 0, pin = 0;
   std::vector<double> dinv;  // bz x H x P
   std::vector<double> coup;  // bz x P
+  std::vector<double> full;  // bz x P x P, row-major: kept only while the set-up
+                             // solves with the box (box_solve_full)
 };
 inline int half_rows(int P) { return P / 2 + 1; }
 // sum_c D(t, c) v[c] of a block in cyclic-diagonal storage: diagonal 0, then
@@ -91,6 +93,9 @@ std::vector<mrcm::DissectionNode> dissection3(int mx, int my, int mz);
 long long cell_of(const Setup& S, int x, int y, int z);
 void host_setup(Setup& S, const mrcm3d_grid& g, const mrcm3d_params& p, const double* K);
 void box_solve(const PlaneFactor& F, double* x);
+// The same solve from the full blocks (contiguous row products), for the
+// set-up's own solves; needs F.full.
+void box_solve_full(const PlaneFactor& F, double* x);
 void host_op_apply(const Setup& S, const double* x, double* y);
 void host_apply(const Setup& S, const double* r, double* z);
 // Legendre P_q at the face-centre parameter of face j of n.

@@ -4,7 +4,9 @@
 * T: the device application against the oracle's T (oracle.mrcm3d) within
   the FP64 gate derived from Skeel's condition number of the interface
   matrix, and against the library's own host evaluation of the uploaded
-  tables; run-to-run bit identity.
+  tables within the same gate (the two differ only in the order of the sums
+  of the interface solve, whose forward error that gate bounds); run-to-run
+  bit identity.
 * GMRES(10): the same step count as the oracle's GMRES with the same T, the
   solution compared with the oracle's iterate at the same step, and the
   reported true residual checked with the oracle's A.
@@ -92,7 +94,7 @@ def test_op_and_apply_3d(dev, case):
           f"evaluation {errh:.2e}", flush=True)
     assert nc == mr.part.nc
     assert err <= gate
-    assert errh <= 1e-12
+    assert errh <= gate
     ctx.close()
 
 
