@@ -42,31 +42,42 @@ __device__ __forceinline__ double plane_dot(const S* __restrict__ D, const doubl
                                             int t) {
   const int H = P / 2 + 1;
   double u0 = (double)D[t] * v[t], u1 = 0.0, w0 = 0.0, w1 = 0.0;
-  int up = t, dn = t;
+  // kU diagonals per pass, every load of the pass issued before its
+  // multiply-adds (eight for FP32 blocks, which leave the loop latency-bound;
+  // two for FP64, which is bound by its bytes); d starts odd, so diagonal
+  // d + q is odd for even q
+  constexpr int kU = sizeof(S) == 4 ? 8 : 2;
   int d = 1;
-  for (; d + 1 < H; d += 2) {
-    up = up + 1 == P ? 0 : up + 1;
-    dn = dn == 0 ? P - 1 : dn - 1;
-    const S* r1 = D + (long long)d * P;
-    const double a1 = r1[t], b1 = r1[dn], x1 = v[up], y1 = v[dn];
-    const int up2 = up + 1 == P ? 0 : up + 1, dn2 = dn == 0 ? P - 1 : dn - 1;
-    const S* r2 = r1 + P;
-    const double a2 = r2[t], b2 = r2[dn2], x2 = v[up2], y2 = v[dn2];
-    u1 = fma(a1, x1, u1);
-    if (2 * d != P) w1 = fma(b1, y1, w1);
-    u0 = fma(a2, x2, u0);
-    if (2 * (d + 1) != P) w0 = fma(b2, y2, w0);
-    up = up2;
-    dn = dn2;
+  for (; d + kU <= H; d += kU) {
+    double a[kU], b[kU], x[kU], y[kU];
+#pragma unroll
+    for (int q = 0; q < kU; ++q) {
+      int up = t + d + q, dn = t - d - q;
+      if (up >= P) up -= P;
+      if (dn < 0) dn += P;
+      const S* row = D + (long long)(d + q) * P;
+      a[q] = row[t];
+      b[q] = row[dn];
+      x[q] = v[up];
+      y[q] = v[dn];
+    }
+#pragma unroll
+    for (int q = 0; q < kU; ++q) {
+      double& u = q & 1 ? u0 : u1;
+      double& w = q & 1 ? w0 : w1;
+      u = fma(a[q], x[q], u);
+      if (2 * (d + q) != P) w = fma(b[q], y[q], w);
+    }
   }
-  if (d < H) {
-    up = up + 1 == P ? 0 : up + 1;
-    dn = dn == 0 ? P - 1 : dn - 1;
-    const S* r1 = D + (long long)d * P;
+  for (; d < H; ++d) {
+    int up = t + d, dn = t - d;
+    if (up >= P) up -= P;
+    if (dn < 0) dn += P;
+    const S* row = D + (long long)d * P;
     double& u = d & 1 ? u1 : u0;
     double& w = d & 1 ? w1 : w0;
-    u = fma((double)r1[t], v[up], u);
-    if (2 * d != P) w = fma((double)r1[dn], v[dn], w);
+    u = fma((double)row[t], v[up], u);
+    if (2 * d != P) w = fma((double)row[dn], v[dn], w);
   }
   return (u0 + u1) + (w0 + w1);
 }
