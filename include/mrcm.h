@@ -324,7 +324,15 @@ int mrcm_timing_read(mrcm_ctx* ctx, double* ms, int64_t* counts);
  *                         (interface degree <= 1; bf16 needs precision mode
  *                         1, else mfma is used); its sums round differently,
  *                         so 8-column results then differ from one-column
- *                         results in rounding. */
+ *                         results in rounding;
+ *  MRCM_Q_SETUP_HOST_S    seconds of mrcm_setup in the host preparation
+ *                         (maps, transmissibilities, face weights, work
+ *                         lists);
+ *  MRCM_Q_SETUP_DEVICE_S  seconds in the device set-up (box factors,
+ *                         oversampled solves, MBFs and their moments), until
+ *                         its results are back on the host;
+ *  MRCM_Q_SETUP_COARSE_S  seconds in the interface system's assembly,
+ *                         factorisation and refinement count (host). */
 enum {
   MRCM_Q_SETUP_SECONDS = 0,
   MRCM_Q_DEVICE_BYTES = 1,
@@ -336,7 +344,10 @@ enum {
   MRCM_Q_TUNE_MS = 7,
   MRCM_Q_TUNE_CHANGES = 8,
   MRCM_Q_COARSE_REFINE = 9,
-  MRCM_Q_MFMA_RECON = 10
+  MRCM_Q_MFMA_RECON = 10,
+  MRCM_Q_SETUP_HOST_S = 11,
+  MRCM_Q_SETUP_DEVICE_S = 12,
+  MRCM_Q_SETUP_COARSE_S = 13
 };
 int mrcm_query(mrcm_ctx* ctx, int32_t what, double* value);
 

@@ -33,7 +33,8 @@ EXPORTED = ["mrcm_map_sizes", "mrcm_maps", "mrcm_setup", "mrcm_apply", "mrcm_app
             "mrcm_last_error"]
 QUERIES = {"setup_seconds": 0, "device_bytes": 1, "coarse_pivot": 2, "coarse_levels": 3,
            "coarse_dofs": 4, "coarse_bytes": 5, "coarse_launches": 6, "tune_ms": 7,
-           "tune_changes": 8, "coarse_refine": 9, "mfma_recon": 10}
+           "tune_changes": 8, "coarse_refine": 9, "mfma_recon": 10, "setup_host_s": 11,
+           "setup_device_s": 12, "setup_coarse_s": 13}
 PHASES = ["local", "coarse", "reconstruct", "residual", "patch", "finalize"]
 TEST_EXPORTED = ["mrcm_test_coarse_sizes", "mrcm_test_coarse_matrix", "mrcm_test_host_apply",
                  "mrcm_test_coarse_solve", "mrcm_test_zero_cell_setup", "mrcm3d_test_host_apply",

@@ -202,6 +202,7 @@ struct mrcm_ctx {
   int tune_changes = 0;   // choices that differ from the defaults
   size_t tsize = 8;  // bytes of the arithmetic / work-vector type
   double setup_seconds = 0.0;
+  double setup_host_s = 0.0, setup_device_s = 0.0, setup_coarse_s = 0.0;  // parts of it
   double coarse_pivot = 1.0;
   int coarse_levels = 0;
   double coarse_bytes = 0.0;  // interface factor bytes read per sweep (forward + backward)
@@ -1414,8 +1415,14 @@ int mrcm_setup(const mrcm_grid* grid, const mrcm_params* params, const double* K
               "hipMemcpyAsync K");
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     mrcm::HostSetup S;
+    auto since = [](std::chrono::steady_clock::time_point a) {
+      return std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();
+    };
+    auto ta = std::chrono::steady_clock::now();
     mrcm::host_prepare(S, *grid, *params, K.data());
+    const double t_host = since(ta);
     c = new mrcm_ctx();
+    c->setup_host_s = t_host;
     {
       std::lock_guard<std::mutex> lock(g_alloc_mutex);
       c->alloc_fn = g_alloc;
@@ -1445,16 +1452,20 @@ int mrcm_setup(const mrcm_grid* grid, const mrcm_params* params, const double* K
     // host
     std::vector<double> colU, colP;
     std::vector<long long> col_off;
+    ta = std::chrono::steady_clock::now();
     if (c->precision == 1)
       device_setup<float, float>(c, S, K_dev, s, colU, colP, col_off);
     else if (c->precision == 2)
       device_setup<double, float>(c, S, K_dev, s, colU, colP, col_off);
     else
       device_setup<double, double>(c, S, K_dev, s, colU, colP, col_off);
+    c->setup_device_s = since(ta);
+    ta = std::chrono::steady_clock::now();
     mrcm::assemble_coarse(S, colU.data(), colP.data(), col_off);
     mrcm::CoarseFactor CF = mrcm::coarse_factor(S.maps, S.Crp, S.Cci, S.Cv, host_threads());
     mrcm::coarse_refine_steps(CF, mrcm::coarse_refine_tol(params->precision),
-                              mrcm::kCoarseRefineMax);
+                              mrcm::kCoarseRefineMax, host_threads());
+    c->setup_coarse_s = since(ta);
     std::vector<int> dof_side;
     for (const auto& d : S.maps.dofs) dof_side.push_back(d[1]);
     c->dof_off = c->upload(S.maps.dof_offset, s);
@@ -2465,6 +2476,9 @@ int mrcm_query(mrcm_ctx* c, int32_t what, double* value) {
       case MRCM_Q_TUNE_CHANGES: *value = c->tune_changes; break;
       case MRCM_Q_COARSE_REFINE: *value = c->refine; break;
       case MRCM_Q_MFMA_RECON: *value = c->mfma_recon; break;
+      case MRCM_Q_SETUP_HOST_S: *value = c->setup_host_s; break;
+      case MRCM_Q_SETUP_DEVICE_S: *value = c->setup_device_s; break;
+      case MRCM_Q_SETUP_COARSE_S: *value = c->setup_coarse_s; break;
       default: throw mrcm::Error(MRCM_EINVAL, "unknown query");
     }
     return MRCM_OK;

@@ -80,33 +80,46 @@ void gemm(int m, int n, int k, double alpha, const double* A, int lda, const dou
     gemm_rows(16 * bi, std::min(m, 16 * bi + 16), n, k, alpha, A, lda, B, ldb, beta, C, ldc);
 }
 
-// Rows i of X (columns [c0, c1)) updated as X[i] -= L[i][j] X[j] for j < i
-// (unit lower triangle of A), then X[i] = (X[i] - sum_{j > i} U[i][j] X[j]) /
-// U[i][i] from the last row up: the forward and back substitutions of the LU
-// factor applied to a block of right-hand-side columns, each element summing
-// its terms in the order of the plain column-by-column substitutions.
+// X := U^-1 L^-1 X for the columns [c0, c1) of X (n x n, row-major), with L
+// the unit lower and U the upper triangle of A (the LU factor), blocked by 64
+// rows: each row block first takes the product of the rows already solved
+// through gemm_rows (columns before the block in the forward substitution,
+// after it in the backward one), then substitutes within the block.
 __attribute__((target_clones("avx512f", "avx2", "default")))
 void lu_solve_cols(const double* __restrict__ A, int n, double* __restrict__ X, int c0, int c1) {
+  constexpr int RB = 64;
   const int w = c1 - c0;
-  for (int i = 1; i < n; ++i) {
-    double* xi = X + (size_t)i * n + c0;
-    for (int j = 0; j < i; ++j) {
-      const double l = A[(size_t)i * n + j];
-      if (l == 0.0) continue;
-      const double* xj = X + (size_t)j * n + c0;
-      for (int c = 0; c < w; ++c) xi[c] = std::fma(-l, xj[c], xi[c]);
+  for (int b0 = 0; b0 < n; b0 += RB) {
+    const int b1 = std::min(n, b0 + RB);
+    if (b0 > 0)
+      gemm_rows(0, b1 - b0, w, b0, -1.0, A + (size_t)b0 * n, n, X + c0, n, 1.0,
+                X + (size_t)b0 * n + c0, n);
+    for (int i = b0 + 1; i < b1; ++i) {
+      double* xi = X + (size_t)i * n + c0;
+      for (int j = b0; j < i; ++j) {
+        const double l = A[(size_t)i * n + j];
+        if (l == 0.0) continue;
+        const double* xj = X + (size_t)j * n + c0;
+        for (int c = 0; c < w; ++c) xi[c] = std::fma(-l, xj[c], xi[c]);
+      }
     }
   }
-  for (int i = n - 1; i >= 0; --i) {
-    double* xi = X + (size_t)i * n + c0;
-    for (int j = i + 1; j < n; ++j) {
-      const double u = A[(size_t)i * n + j];
-      if (u == 0.0) continue;
-      const double* xj = X + (size_t)j * n + c0;
-      for (int c = 0; c < w; ++c) xi[c] = std::fma(-u, xj[c], xi[c]);
+  for (int b1 = n; b1 > 0; b1 -= RB) {
+    const int b0 = std::max(0, b1 - RB);
+    if (b1 < n)
+      gemm_rows(0, b1 - b0, w, n - b1, -1.0, A + (size_t)b0 * n + b1, n, X + (size_t)b1 * n + c0,
+                n, 1.0, X + (size_t)b0 * n + c0, n);
+    for (int i = b1 - 1; i >= b0; --i) {
+      double* xi = X + (size_t)i * n + c0;
+      for (int j = i + 1; j < b1; ++j) {
+        const double u = A[(size_t)i * n + j];
+        if (u == 0.0) continue;
+        const double* xj = X + (size_t)j * n + c0;
+        for (int c = 0; c < w; ++c) xi[c] = std::fma(-u, xj[c], xi[c]);
+      }
+      const double d = A[(size_t)i * n + i];
+      for (int c = 0; c < w; ++c) xi[c] /= d;
     }
-    const double d = A[(size_t)i * n + i];
-    for (int c = 0; c < w; ++c) xi[c] /= d;
   }
 }
 
@@ -502,7 +515,8 @@ CoarseTables coarse_tables(const CoarseFactor& F, const int32_t* rowL, const int
 }
 
 void coarse_residual_host(const CoarseFactor& F, const double* g_nd, const double* x,
-                          double* r_nd) {
+                          double* r_nd, int nthreads) {
+#pragma omp parallel for schedule(static) num_threads(std::max(1, nthreads)) if (nthreads > 1)
   for (int t = 0; t < F.nc; ++t) {
     double s = g_nd[t];
     for (int q = F.nd_rp[t]; q < F.nd_rp[t + 1]; ++q) s = std::fma(-F.nd_v[q], x[F.nd_ci[q]], s);
@@ -510,17 +524,18 @@ void coarse_residual_host(const CoarseFactor& F, const double* g_nd, const doubl
   }
 }
 
-void coarse_solve_refined_host(const CoarseFactor& F, const double* g_nd, double* x) {
-  coarse_solve_host(F, g_nd, x);
+void coarse_solve_refined_host(const CoarseFactor& F, const double* g_nd, double* x,
+                               int nthreads) {
+  coarse_solve_host(F, g_nd, x, nthreads);
   std::vector<double> r(F.nc), dx(F.nc);
   for (int s = 0; s < F.refine; ++s) {
-    coarse_residual_host(F, g_nd, x, r.data());
-    coarse_solve_host(F, r.data(), dx.data());
+    coarse_residual_host(F, g_nd, x, r.data(), nthreads);
+    coarse_solve_host(F, r.data(), dx.data(), nthreads);
     for (int q = 0; q < F.nc; ++q) x[q] += dx[q];
   }
 }
 
-int coarse_refine_steps(CoarseFactor& F, double tol, int max_steps) {
+int coarse_refine_steps(CoarseFactor& F, double tol, int max_steps, int nthreads) {
   F.refine = 0;
   const int nc = F.nc;
   if (nc == 0) return 0;
@@ -532,11 +547,11 @@ int coarse_refine_steps(CoarseFactor& F, double tol, int max_steps) {
     st = st * 6364136223846793005ULL + 1442695040888963407ULL;
     g[t] = (double)(st >> 11) * (2.0 / 9007199254740992.0) - 1.0;
   }
-  coarse_solve_host(F, g.data(), x.data());
+  coarse_solve_host(F, g.data(), x.data(), nthreads);
   int steps = 0;
   while (steps < max_steps) {
-    coarse_residual_host(F, g.data(), x.data(), r.data());
-    coarse_solve_host(F, r.data(), dx.data());
+    coarse_residual_host(F, g.data(), x.data(), r.data(), nthreads);
+    coarse_solve_host(F, r.data(), dx.data(), nthreads);
     double dmax = 0.0, xmax = 0.0;
     for (int q = 0; q < nc; ++q) {
       dmax = std::max(dmax, std::fabs(dx[q]));
@@ -550,41 +565,69 @@ int coarse_refine_steps(CoarseFactor& F, double tol, int max_steps) {
   return steps;
 }
 
-void coarse_solve_host(const CoarseFactor& F, const double* g_nd, double* x) {
-  std::vector<double> ybuf(F.ylen), cbuf(F.clen);
-  for (int d = F.depth; d >= 0; --d)
-    for (const auto& cn : F.nodes) {
-      if (cn.depth != d) continue;
-      const int nf = (int)cn.frow.size(), nu = (int)cn.urow.size();
-      std::vector<double> v(nf);
-      for (int a = 0; a < nf; ++a) {
+void coarse_solve_host(const CoarseFactor& F, const double* g_nd, double* x, int nthreads) {
+  constexpr int kRows = 32;  // rows of a work item
+  std::vector<double> ybuf(F.ylen), cbuf(F.clen), v(F.ylen);
+  std::vector<std::vector<int>> level(F.depth + 1);
+  for (int t = 0; t < (int)F.nodes.size(); ++t) level[F.nodes[t].depth].push_back(t);
+  const int nth = std::max(1, nthreads);
+  std::vector<std::pair<int, int>> items;  // (node, first row)
+  for (int d = F.depth; d >= 0; --d) {
+    const auto& lv = level[d];
+    // the vectors of the level's nodes (descendants' contributions in slot
+    // order), then their rows of [W; E]
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nth) if (nth > 1)
+    for (int li = 0; li < (int)lv.size(); ++li) {
+      const CoarseNode& cn = F.nodes[lv[li]];
+      for (int a = 0; a < (int)cn.frow.size(); ++a) {
         const size_t t = (size_t)cn.yoff + a;
         double s = g_nd[t];
         for (int u = 0; u < F.maxp; ++u) {
           const int q = F.slots[t * F.maxp + u];
           if (q >= 0) s -= cbuf[q];
         }
-        v[a] = s;
+        v[t] = s;
       }
-      for (int a = 0; a < nf + nu; ++a) {
+    }
+    items.clear();
+    for (int t : lv) {
+      const CoarseNode& cn = F.nodes[t];
+      for (int r0 = 0; r0 < (int)(cn.frow.size() + cn.urow.size()); r0 += kRows) items.push_back({t, r0});
+    }
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nth) if (nth > 1)
+    for (int it = 0; it < (int)items.size(); ++it) {
+      const CoarseNode& cn = F.nodes[items[it].first];
+      const int nf = (int)cn.frow.size(), nu = (int)cn.urow.size();
+      const double* vn = &v[cn.yoff];
+      const int r1 = std::min(nf + nu, items[it].second + kRows);
+      for (int a = items[it].second; a < r1; ++a) {
         double s = 0.0;
-        for (int b = 0; b < nf; ++b) s += cn.fwd[(size_t)a * nf + b] * v[b];
+        for (int b = 0; b < nf; ++b) s += cn.fwd[(size_t)a * nf + b] * vn[b];
         if (a < nf)
           ybuf[cn.yoff + a] = s;
         else
           cbuf[cn.coff + a - nf] = s;
       }
     }
-  for (int d = 0; d <= F.depth; ++d)
-    for (const auto& cn : F.nodes) {
-      if (cn.depth != d) continue;
+  }
+  for (int d = 0; d <= F.depth; ++d) {
+    items.clear();
+    for (int t : level[d]) {
+      const CoarseNode& cn = F.nodes[t];
+      for (int r0 = 0; r0 < (int)cn.frow.size(); r0 += kRows) items.push_back({t, r0});
+    }
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nth) if (nth > 1)
+    for (int it = 0; it < (int)items.size(); ++it) {
+      const CoarseNode& cn = F.nodes[items[it].first];
       const int nf = (int)cn.frow.size(), nu = (int)cn.urow.size();
-      for (int a = 0; a < nf; ++a) {
+      const int r1 = std::min(nf, items[it].second + kRows);
+      for (int a = items[it].second; a < r1; ++a) {
         double s = ybuf[cn.yoff + a];
         for (int b = 0; b < nu; ++b) s -= cn.bwd[(size_t)a * nu + b] * x[cn.ucol[b]];
         x[cn.fcol[a]] = s;
       }
     }
+  }
 }
 
 }  // namespace mrcm

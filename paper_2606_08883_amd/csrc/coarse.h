@@ -128,13 +128,16 @@ CoarseFactor coarse_factor_tree(const std::vector<DissectionNode>& tree,
 // Host reference of the level-scheduled solve (used to check the factor).
 // g_nd: the scaled right-hand side in tree order
 // (g_nd[t] = nd_scale[t] * g[nd_row[t]]).
-void coarse_solve_host(const CoarseFactor& F, const double* g_nd, double* x);
+// nthreads: host threads of the level loops (the arithmetic of every row is
+// the same for any count).
+void coarse_solve_host(const CoarseFactor& F, const double* g_nd, double* x, int nthreads = 1);
 // r_nd = g_nd - diag(rscale) C x in tree order (FP64, fixed order).
 void coarse_residual_host(const CoarseFactor& F, const double* g_nd, const double* x,
-                          double* r_nd);
+                          double* r_nd, int nthreads = 1);
 // The solve the apply runs: the level-scheduled solve, then F.refine steps of
 // x += solve(g_nd - diag(rscale) C x).
-void coarse_solve_refined_host(const CoarseFactor& F, const double* g_nd, double* x);
+void coarse_solve_refined_host(const CoarseFactor& F, const double* g_nd, double* x,
+                               int nthreads = 1);
 // Refinement steps the apply needs: the explicit front inverses of the factor
 // are not backward stable, so on ill-conditioned interface systems one solve
 // can be off by far more than the conditioning allows, and each refinement
@@ -142,7 +145,7 @@ void coarse_solve_refined_host(const CoarseFactor& F, const double* g_nd, double
 // step count is measured on a fixed pseudo-random right-hand side: the
 // number of corrections applied before a correction falls to tol times the
 // solution (in max norm), at most max_steps.  Sets and returns F.refine.
-int coarse_refine_steps(CoarseFactor& F, double tol, int max_steps);
+int coarse_refine_steps(CoarseFactor& F, double tol, int max_steps, int nthreads = 1);
 // The library's choice: corrections down to 1e-10 of the solution in the
 // FP64 mode, at most four steps.  In the modes with FP32 box factors the
 // interface solve needs only to stay below the effect of the factors' own

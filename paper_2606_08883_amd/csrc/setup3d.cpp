@@ -600,7 +600,7 @@ void host_setup(Setup& S, const mrcm3d_grid& g, const mrcm3d_params& p, const do
     // refinement to 1e-10 of the solution in FP64, to 1e-6 with FP32-stored
     // blocks (below their own effect on T), as in 2-D
     mrcm::coarse_refine_steps(S.CF, mrcm::coarse_refine_tol(S.precision),
-                              mrcm::kCoarseRefineMax);
+                              mrcm::kCoarseRefineMax, std::max(1, omp_get_max_threads()));
   }
   // precision 2: the apply reads the plane blocks rounded to FP32 (the MBFs,
   // C and its factor above came from the FP64 blocks)
@@ -726,7 +726,7 @@ void host_apply(const Setup& S, const double* r, double* z) {
   if (S.nc > 0) {
     std::vector<double> gnd(S.nc);
     for (int t = 0; t < S.nc; ++t) gnd[t] = S.CF.nd_scale[t] * g[S.CF.nd_row[t]];
-    mrcm::coarse_solve_refined_host(S.CF, gnd.data(), x.data());
+    mrcm::coarse_solve_refined_host(S.CF, gnd.data(), x.data(), std::max(1, omp_get_max_threads()));
   }
   for (int i = 0; i < S.m; ++i) {
     const Box& bi = S.boxes[i];
