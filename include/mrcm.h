@@ -168,7 +168,8 @@ int mrcm_apply_noalloc(mrcm_ctx* ctx, const double* r, double* z, int32_t nrhs, 
 int mrcm_apply_many(mrcm_ctx* const* ctx, int32_t n, const double* const* r, double* const* z,
                     const int32_t* nrhs, void* stream);
 
-/* Device allocator for the contexts set up after this call (not part of the
+/* Device allocator for the contexts (2-D, and 3-D of mrcm3d.h) set up after
+ * this call (not part of the
  * method: memory plumbing, so that a caller such as a framework's caching
  * allocator owns the device memory).  alloc(bytes, stream) returns device
  * memory of at least `bytes` bytes, 256-byte aligned, or NULL (mrcm_setup

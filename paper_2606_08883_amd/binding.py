@@ -449,6 +449,8 @@ def apply_many(contexts, rs, zs, stream=None):
     zp = (P * n)(*[_dptr(z, r.numel()) for r, z in zip(rs, zs)])
     k = (ctypes.c_int32 * n)(*[c._nrhs(r) for c, r in zip(contexts, rs)])
     _check(lib().mrcm_apply_many(ctx, n, rp, zp, k, _stream(stream)))
+
+
 class Batch:
     """Batched GMRES over several contexts in ticks (gmres_batch_*)."""
 

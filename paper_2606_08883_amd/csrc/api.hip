@@ -2493,3 +2493,11 @@ void mrcm_destroy(mrcm_ctx* c) { delete c; }
 const char* mrcm_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"
+
+namespace mrcm {
+void current_allocator(mrcm_alloc_fn* alloc, mrcm_free_fn* release) {
+  std::lock_guard<std::mutex> lock(g_alloc_mutex);
+  *alloc = g_alloc;
+  *release = g_free;
+}
+}  // namespace mrcm

@@ -76,11 +76,22 @@ struct mrcm3d_ctx {
   double phase_ms[6] = {0, 0, 0, 0, 0, 0};
   long long phase_n[6] = {0, 0, 0, 0, 0, 0};
 
+  // allocator of this context (null: hipMalloc / hipFree; mrcm_set_allocator)
+  // and the stream its callbacks are given (the set-up stream)
+  mrcm_alloc_fn alloc_fn = nullptr;
+  mrcm_free_fn free_fn = nullptr;
+  hipStream_t alloc_stream = nullptr;
+
   template <typename X>
   X* alloc(size_t count) {
     void* q = nullptr;
     const size_t bytes = ((count ? count : 1) * sizeof(X) + 255) / 256 * 256;
-    check3(hipMalloc(&q, bytes), "hipMalloc");
+    if (alloc_fn) {
+      q = alloc_fn(bytes, alloc_stream);
+      if (!q) throw mrcm::Error(MRCM_ENOMEM, "allocator callback returned NULL");
+    } else {
+      check3(hipMalloc(&q, bytes), "hipMalloc");
+    }
     allocs.push_back(q);
     device_bytes += bytes;
     return static_cast<X*>(q);
@@ -119,7 +130,13 @@ struct mrcm3d_ctx {
       (void)hipEventDestroy(mk.second.first);
       (void)hipEventDestroy(mk.second.second);
     }
-    for (void* q : allocs) (void)hipFree(q);
+    if (alloc_stream) (void)hipStreamSynchronize(alloc_stream);
+    for (void* q : allocs) {
+      if (free_fn)
+        free_fn(q, alloc_stream);
+      else
+        (void)hipFree(q);
+    }
     if (h_fetch) (void)hipHostFree(h_fetch);
     if (h_y) (void)hipHostFree(h_y);
     if (ev_in) (void)hipEventDestroy(ev_in);
@@ -269,6 +286,8 @@ int mrcm3d_setup(const mrcm3d_grid* grid, const mrcm3d_params* params, const dou
     if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1)
       throw mrcm::Error(MRCM_EINVAL, "invalid grid");
     c = new mrcm3d_ctx();
+    mrcm::current_allocator(&c->alloc_fn, &c->free_fn);
+    c->alloc_stream = static_cast<hipStream_t>(stream);
     check3(hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking), "hipStreamCreate");
     check3(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming), "hipEventCreate");
     std::vector<double> K((size_t)n);

@@ -66,4 +66,8 @@ double legendre(int q, double xi);
 // Message returned by mrcm_last_error() on the calling thread.
 void set_last_error(const std::string& msg);
 
+// The device allocator pair of mrcm_set_allocator (both null: hipMalloc /
+// hipFree), read under its lock, for contexts being set up.
+void current_allocator(mrcm_alloc_fn* alloc, mrcm_free_fn* release);
+
 }  // namespace mrcm

@@ -250,3 +250,56 @@ def test_rhs_and_dirichlet_solve_3d(dev):
     print(f"  GMRES {st.iterations} steps; solution against the direct solve {err:.2e}", flush=True)
     assert st.converged and err <= 1e-7
     ctx.close()
+
+
+def test_caller_allocator_3d(dev):
+    """3-D contexts set up while a caller allocator is installed
+    (mrcm_set_allocator) take all their device memory from it, return every
+    allocation at destroy and compute the same T r bit for bit; an allocator
+    that returns NULL part-way through the set-up gives MRCM_ENOMEM with every
+    allocation returned."""
+    cfg, K, ctx0, mr = _setup(CASES[1], dev)
+    Kd = torch.tensor(K, dtype=torch.float64, device=dev)
+    r = torch.tensor(_vec(cfg.n, 6, False), dtype=torch.float64, device=dev)
+    z0 = torch.empty_like(r)
+    ctx0.apply(r, z0)
+    torch.cuda.synchronize()
+    ctx0.close()
+    ta, tf = B.torch_allocator(0)
+    calls = {"alloc": 0, "free": 0, "live": 0, "fail_after": None}
+    sizes = {}
+
+    def alloc(nbytes, stream):
+        calls["alloc"] += 1
+        if calls["fail_after"] is not None and calls["alloc"] > calls["fail_after"]:
+            return None
+        calls["live"] += nbytes
+        ptr = ta(nbytes, stream)
+        sizes[ptr] = nbytes
+        return ptr
+
+    def release(ptr, stream):
+        calls["free"] += 1
+        calls["live"] -= sizes.pop(ptr)
+        tf(ptr, stream)
+
+    B.set_allocator(alloc, release)
+    try:
+        ctx = B.Context3(cfg, Kd)
+        z1 = torch.empty_like(r)
+        ctx.apply(r, z1)
+        torch.cuda.synchronize()
+        held, live = ctx.query("device_bytes"), calls["live"]
+        ctx.close()
+        done = dict(calls)
+        calls.update(alloc=0, free=0, fail_after=5)
+        with pytest.raises(B.MrcmError) as e:
+            B.Context3(cfg, Kd)
+    finally:
+        B.set_allocator(None, None)
+    print(f"  allocator calls {done}, context bytes {held:.0f}; failing run {calls}", flush=True)
+    assert done["alloc"] > 0 and done["alloc"] == done["free"] and done["live"] == 0
+    assert live == held
+    assert torch.equal(z0, z1)
+    assert e.value.code == B.MRCM_ENOMEM
+    assert calls["free"] == 5 and calls["live"] == 0
