@@ -837,6 +837,9 @@ def main() -> int:
         "iterations_per_solve": r["iterations"],
         "final_relres_max": r["relres_max"],
         "setup_s": setup_s,
+        "setup_stages_s": {"host_preparation": ctx.query("setup_host_s"),
+                           "device": ctx.query("setup_device_s"),
+                           "interface": ctx.query("setup_coarse_s")},
         "solves_per_s_incl_setup": 1.0 / (setup_s + r["elapsed"] / args.steps),
         "device_gb": ctx.query("device_bytes") / 1e9,
         "interface_refinement_steps": ctx.query("coarse_refine"),
