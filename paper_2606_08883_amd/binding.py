@@ -90,7 +90,7 @@ def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+            raise ImportError(f"{LIB_PATH} is not built (run python -m paper_2606_08883_amd.build_lib)")
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.c_void_p
         i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
