@@ -44,11 +44,15 @@ __device__ __forceinline__ double plane_dot(const S* __restrict__ D, const doubl
   double u0 = (double)D[t] * v[t], u1 = 0.0, w0 = 0.0, w1 = 0.0;
   // kU diagonals per pass, every load of the pass issued before its
   // multiply-adds (eight for FP32 blocks, which leave the loop latency-bound;
-  // two for FP64, which is bound by its bytes); d starts odd, so diagonal
-  // d + q is odd for even q
+  // two for FP64, where four and eight measured slower); d starts odd, so
+  // diagonal d + q is odd for even q.  Only the diagonal d = P / 2 of an
+  // even P has no second term, and it is the last: the passes stop before
+  // it, so their loop holds no branch (a branch there made every pass wait
+  // for all of its loads).
   constexpr int kU = sizeof(S) == 4 ? 8 : 2;
+  const int Hd = P % 2 == 0 ? P / 2 : H;  // diagonals 1 .. Hd - 1 have both terms
   int d = 1;
-  for (; d + kU <= H; d += kU) {
+  for (; d + kU <= Hd; d += kU) {
     double a[kU], b[kU], x[kU], y[kU];
 #pragma unroll
     for (int q = 0; q < kU; ++q) {
@@ -66,7 +70,7 @@ __device__ __forceinline__ double plane_dot(const S* __restrict__ D, const doubl
       double& u = q & 1 ? u0 : u1;
       double& w = q & 1 ? w0 : w1;
       u = fma(a[q], x[q], u);
-      if (2 * (d + q) != P) w = fma(b[q], y[q], w);
+      w = fma(b[q], y[q], w);
     }
   }
   for (; d < H; ++d) {
