@@ -3,6 +3,8 @@
 // coarse interface solve, multiscale reconstruction, Schwarz smoothing and the
 // fused Arnoldi vector kernels of GMRES.  Every reduction has a fixed order,
 // so results are bit-identical from run to run.
+#include <type_traits>
+
 #include "device.h"
 #include "internal.h"
 
@@ -660,6 +662,13 @@ __global__ void k_coarse_add(double* __restrict__ x, const double* __restrict__ 
 // loads are issued before the right-hand side is gathered, so their latency
 // overlaps the gather.
 
+// Entries of a node's vector a thread gathers into LDS at a time: a root
+// separator of more than kWideRoot rows (kGatherA), a backward border (up to
+// kGatherB, as its length needs).
+constexpr int kGatherA = 4;
+constexpr int kGatherB = 8;
+constexpr int kWideRoot = 1024;
+
 // Issue the loads of one 4 x (8 x 64) tile: rows r .. r + 3 (clipped at
 // row1), columns b0 + 64 q (clipped at ncol); missing entries read as zero.
 __device__ __forceinline__ void load_tile(double (&m)[4][8], const double* __restrict__ M,
@@ -808,23 +817,40 @@ __device__ __forceinline__ void coarse_fwd_body(
   const double* M = fwd + ch.mat;
   const int yoff = ch.yoff, coff = ch.coff;
   int dst = -1;
-  auto gather = [&]() {
-    for (int a = threadIdx.x; a < nf; a += blockDim.x) {
-      const long long t = (long long)yoff + a;
-      double s = g_nd[t];
-      for (int u0 = 0; u0 < maxp; u0 += 8) {
-        double c[8];
+  // v[a] = g_nd[t] minus the contributions in slot order; a thread takes
+  // its entries A at a time, with all their loads in flight together
+  auto gather_rows = [&](auto A) {
+    constexpr int kA = decltype(A)::value, kC = kA > 1 ? 4 : 8;
+    const int bd = blockDim.x;
+    for (int a0 = threadIdx.x; a0 < nf; a0 += kA * bd) {
+      long long t[kA];
+      double s[kA];
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
-          c[k] = u0 + k < maxp ? contrib[(long long)(u0 + k) * np + t] : 0.0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-          if (u0 + k < maxp) s -= c[k];
+      for (int i = 0; i < kA; ++i) {
+        const int a = a0 + i * bd;
+        t[i] = (long long)yoff + (a < nf ? a : nf - 1);
+        s[i] = g_nd[t[i]];
       }
-      v[a] = s;
+      for (int u0 = 0; u0 < maxp; u0 += kC) {
+        double c[kA][kC];
+#pragma unroll
+        for (int i = 0; i < kA; ++i)
+#pragma unroll
+          for (int k = 0; k < kC; ++k)
+            c[i][k] = u0 + k < maxp ? contrib[(long long)(u0 + k) * np + t[i]] : 0.0;
+#pragma unroll
+        for (int i = 0; i < kA; ++i)
+#pragma unroll
+          for (int k = 0; k < kC; ++k)
+            if (u0 + k < maxp) s[i] -= c[i][k];
+      }
+#pragma unroll
+      for (int i = 0; i < kA; ++i)
+        if (a0 + i * bd < nf) v[a0 + i * bd] = s[i];
     }
     __syncthreads();
   };
+  auto gather = [&]() { gather_rows(std::integral_constant<int, 1>()); };
   auto emit = [&](int row, double val) {
     if (row >= nf)
       contrib[dst] = val;
@@ -850,9 +876,18 @@ __device__ __forceinline__ void coarse_fwd_body(
   };
   double m[4][8];
   const int rw = ch.row0 + 4 * (threadIdx.x >> 6);
-  load_tile(m, M, nf, rw, ch.row1, lane);
-  pre(rw);
-  gather();
+  if (ch.nu == 0 && nf > kWideRoot) {
+    // the root of a large tree: few workgroups, each with a long gather,
+    // which goes first, kGatherA entries deep (the tile's registers are
+    // not live yet, so the kernel's occupancy holds)
+    gather_rows(std::integral_constant<int, kGatherA>());
+    load_tile(m, M, nf, rw, ch.row1, lane);
+    pre(rw);
+  } else {
+    load_tile(m, M, nf, rw, ch.row1, lane);
+    pre(rw);
+    gather();
+  }
   gemv_chunk(M, nf, ch.row0, ch.row1, v, m, pre, emit);
 }
 __global__ void __launch_bounds__(kVecThreads)
@@ -875,9 +910,38 @@ __device__ __forceinline__ void coarse_bwd_body(const CChunk ch, const double* _
   const int yoff = ch.yoff, fcol = ch.fcol;
   int dst = 0;
   double y = 0.0;
-  auto gather = [&]() {
-    for (int b = threadIdx.x; b < nu; b += blockDim.x) xu[b] = x[idx[ch.ucol + b]];
+  // xu[b] = x[idx[ucol + b]]: a thread takes its entries R at a time, all
+  // their loads in flight together, R being 1, 2, 4 or kGatherB as the
+  // border needs (it is the same in the whole workgroup)
+  auto gather_r = [&](auto R) {
+    constexpr int kR = decltype(R)::value;
+    const int bd = blockDim.x;
+    for (int b0 = threadIdx.x; b0 < nu; b0 += kR * bd) {
+      int k[kR];
+      double val[kR];
+#pragma unroll
+      for (int i = 0; i < kR; ++i) {
+        const int b = b0 + i * bd;
+        k[i] = idx[ch.ucol + (b < nu ? b : nu - 1)];
+      }
+#pragma unroll
+      for (int i = 0; i < kR; ++i) val[i] = x[k[i]];
+#pragma unroll
+      for (int i = 0; i < kR; ++i)
+        if (b0 + i * bd < nu) xu[b0 + i * bd] = val[i];
+    }
     __syncthreads();
+  };
+  auto gather = [&]() {
+    const int rounds = (nu + (int)blockDim.x - 1) / (int)blockDim.x;
+    if (rounds <= 1)
+      gather_r(std::integral_constant<int, 1>());
+    else if (rounds <= 2)
+      gather_r(std::integral_constant<int, 2>());
+    else if (rounds <= 4)
+      gather_r(std::integral_constant<int, 4>());
+    else
+      gather_r(std::integral_constant<int, kGatherB>());
   };
   if (whole_chunk_wave(ch, nu)) {
     double m[16][2];
