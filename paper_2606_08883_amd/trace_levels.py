@@ -37,8 +37,18 @@ def solves(trace_dir: str) -> list:
 
 
 def main(argv: list) -> int:
+    if len(argv) < 2 or argv[1].startswith("-") or (len(argv) > 2 and not argv[2].isdigit()):
+        print(__doc__.strip())
+        return 0 if len(argv) > 1 and argv[1] in ("-h", "--help") else 2
     apps = int(argv[2]) if len(argv) > 2 else 4
-    sv = solves(argv[1])
+    try:
+        sv = solves(argv[1])
+    except FileNotFoundError as e:
+        print(e, file=sys.stderr)
+        return 1
+    if not sv:
+        print(f"no interface solve in the trace under {argv[1]}", file=sys.stderr)
+        return 1
     last = sv[-apps:]
     n = min(len(a) for a in last)
     print(f"interface solves in the trace: {len(sv)}; the last {len(last)}, launch by launch (us)")

@@ -71,3 +71,13 @@ def test_profile_summary_stats_table(tmp_path, capsys):
     out = capsys.readouterr().out.splitlines()
     assert out[1].startswith("k_patch<float>") and out[1].split()[-1] == "1000.00"
     assert out[2].startswith("k_factor_boxes<float>") and out[2].split()[-1] == "-"
+
+
+def test_trace_levels_usage_and_missing_trace(tmp_path, capsys):
+    assert TL.main(["trace_levels", "--help"]) == 0
+    assert "Usage" in capsys.readouterr().out
+    assert TL.main(["trace_levels"]) == 2
+    assert TL.main(["trace_levels", str(tmp_path), "x"]) == 2
+    capsys.readouterr()
+    assert TL.main(["trace_levels", str(tmp_path)]) == 1
+    assert "no kernel_trace.csv" in capsys.readouterr().err
