@@ -91,6 +91,11 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built (run python -m paper_2606_08883_amd.build_lib)")
+        # PyTorch ships its own HIP and HSA runtimes.  Importing it first
+        # makes the library bind to those same runtimes; loaded the other way
+        # round, the process held two runtime stacks and the library's first
+        # device call found no device.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.c_void_p
         i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double

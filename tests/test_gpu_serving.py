@@ -22,6 +22,9 @@
   several slots per lane sharing multi-column applications of T) gives the
   solutions and iteration counts of one lane, bit for bit, and of each
   right-hand side solved on its own.
+* In a fresh process whose first library call is a host-only one made
+  before torch is imported, a request served from a worker thread still
+  sets up and converges (the binding loads torch's runtimes first).
 """
 import numpy as np
 import pytest
@@ -340,3 +343,26 @@ def test_lanes_equal_one_lane(dev, precision, n, nrhs, lanes, width):
     with pytest.raises(B.MrcmError):
         ctx.set_batch(9)
     ctx.close()
+
+
+def test_library_loaded_before_torch_serves_from_a_worker():
+    import os
+    import subprocess
+    import sys
+    code = (
+        "import sys\n"
+        "from paper_2606_08883_amd import serving as S\n"
+        "assert 'torch' not in sys.modules\n"
+        "from paper_2606_08883_amd.binding import footprint\n"
+        "print('footprint', footprint(S.config_for(128), 2), flush=True)\n"
+        "assert 'torch' in sys.modules\n"
+        "solver = S.GpuBackend(None, keep=True)\n"
+        "req = S.make_payload(S.Request(0, 128, 2.0, 999, 1999, 2, 0.0))\n"
+        "r = S.Server(solver, max_active=1).run([req], realtime=False)[0]\n"
+        "print('served', r.converged, r.final_relres, flush=True)\n"
+        "assert r.converged and r.final_relres <= 1e-8\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True,
+                         text=True, timeout=180)
+    print(out.stdout, out.stderr[-2000:], flush=True)
+    assert out.returncode == 0
