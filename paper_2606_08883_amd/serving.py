@@ -125,8 +125,10 @@ class GpuBackend:
     """The library behind the server: a request is set up on its own stream
     by a worker thread (its factorisations stay resident while it is in
     flight), then its right-hand sides join one batched GMRES (gmres_batch_*)
-    that the server ticks; its answer is copied to the host and its context
-    released when all of them have finished.
+    that the server ticks; its answer is copied to the host when all of them
+    have finished, and its context is released on a background thread (a
+    release frees device memory, which can wait for the device; on the
+    serving thread it held up the ticks).  flush() waits for the releases.
 
     setup_threads: host threads of each set-up; None (the default) divides
     the host cores among the set-ups in progress when a set-up starts (all
@@ -141,6 +143,8 @@ class GpuBackend:
         self.lock = threading.Lock()
         self.setups = 0
         self.batch = None
+        self.releaser = ThreadPoolExecutor(max_workers=1)
+        self.releases = []
 
     def setup(self, req: Request) -> dict:
         import torch
@@ -182,12 +186,19 @@ class GpuBackend:
         if st is None:
             return None
         t2 = time.perf_counter()
-        self.batch.remove(h["tag"])
+        self.batch.remove(h["tag"])  # returns once the batch's device work has ended
         p = h["P"].cpu().numpy() if self.keep else None
-        h["ctx"].close()
+        self.releases.append(self.releaser.submit(h["ctx"].close))
         return dict(iterations=st.iterations, converged=st.converged,
                     final_relres=st.final_relres, setup_s=h["setup_s"],
                     solve_s=t2 - h["t_add"], p=p)
+
+    def flush(self) -> None:
+        """Wait until every finished request's context is released (re-raises
+        a failed release)."""
+        done, self.releases = self.releases, []
+        for f in done:
+            f.result()
 
 
 class Server:
@@ -195,10 +206,13 @@ class Server:
 
     backend: setup(req) -> handle, run on worker threads; add(handle),
     tick() -> right-hand sides still running, poll(handle) -> None or a dict
-    of Result fields (the request is then finished and released), run on the
-    serving thread.  max_active: requests in flight at once (set up or
-    solving); mem_budget: bytes their footprints may total; footprint(req)
-    -> bytes; setup_workers: set-ups in progress at once."""
+    of Result fields (the request is then finished and its release begun),
+    run on the serving thread; optionally flush(), called at the end of
+    run(), which waits for the releases.  A finished request's footprint
+    counts as free from the moment poll() returns its answer.  max_active:
+    requests in flight at once (set up or solving); mem_budget: bytes their
+    footprints may total; footprint(req) -> bytes; setup_workers: set-ups in
+    progress at once."""
 
     def __init__(self, backend, max_active: int = 8, mem_budget: int = 200 << 30,
                  footprint=footprint_of, setup_workers: int = 4):
@@ -277,6 +291,9 @@ class Server:
                     wait(list(setting_up), timeout=timeout, return_when=FIRST_COMPLETED)
                 elif timeout is not None:
                     time.sleep(timeout)
+        flush = getattr(self.backend, "flush", None)
+        if flush is not None:
+            flush()
         return [results[r.rid] for r in sorted(requests, key=lambda r: r.rid)]
 
 
