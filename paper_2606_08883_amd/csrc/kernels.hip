@@ -660,7 +660,8 @@ __global__ void k_coarse_add(double* __restrict__ x, const double* __restrict__ 
 // of four rows (wave w: rows row0 + 4 w + 16 k); lanes stride the columns
 // eight deep, so a wave has 32 matrix loads in flight.  The first group's
 // loads are issued before the right-hand side is gathered, so their latency
-// overlaps the gather.
+// overlaps the gather (except at the root of a large tree, whose long gather
+// goes first).
 
 // Entries of a node's vector a thread gathers into LDS at a time: a root
 // separator of more than kWideRoot rows (kGatherA), a backward border (up to
