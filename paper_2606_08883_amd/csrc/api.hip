@@ -41,6 +41,18 @@ void hip_check(hipError_t e, const char* what) {
                       std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// The return code of an entry point that stopped on an exception other than
+// mrcm::Error: MRCM_ENOMEM for a failed host allocation, else MRCM_EINVAL
+// (no C++ exception leaves the C ABI).
+int fail_std(const std::exception& e) {
+  if (dynamic_cast<const std::bad_alloc*>(&e)) {
+    set_error("host allocation failed");
+    return MRCM_ENOMEM;
+  }
+  set_error(e.what());
+  return MRCM_EINVAL;
+}
+
 // Host threads of the calling thread's set-ups (mrcm_set_host_threads; 0 =
 // OpenMP's default).
 thread_local int t_host_threads = 0;
@@ -1604,6 +1616,8 @@ int mrcm_apply_noalloc(mrcm_ctx* c, const double* r, double* z, int32_t nrhs, vo
   } catch (const mrcm::Error& e) {
     set_error(e.what());
     return e.code;
+  } catch (const std::exception& e) {
+    return fail_std(e);
   }
 }
 
@@ -1626,6 +1640,8 @@ int mrcm_apply(mrcm_ctx* c, const double* r, double* z, int32_t nrhs, void* stre
   } catch (const mrcm::Error& e) {
     set_error(e.what());
     return e.code;
+  } catch (const std::exception& e) {
+    return fail_std(e);
   }
 }
 
@@ -1667,6 +1683,8 @@ int mrcm_apply_many(mrcm_ctx* const* ctx, int32_t n, const double* const* r, dou
   } catch (const mrcm::Error& e) {
     set_error(e.what());
     return e.code;
+  } catch (const std::exception& e) {
+    return fail_std(e);
   }
 }
 
@@ -1695,6 +1713,8 @@ int op_apply(mrcm_ctx* c, const double* x, double* y, int32_t nrhs, void* stream
   } catch (const mrcm::Error& e) {
     set_error(e.what());
     return e.code;
+  } catch (const std::exception& e) {
+    return fail_std(e);
   }
 }
 
@@ -1709,6 +1729,8 @@ int mrcm_rhs(mrcm_ctx* c, const double* f_cell, const double* g_bc, double h, do
   } catch (const mrcm::Error& e) {
     set_error(e.what());
     return e.code;
+  } catch (const std::exception& e) {
+    return fail_std(e);
   }
 }
 
@@ -1953,6 +1975,8 @@ int gmres_solve(mrcm_ctx* c, const double* b, double* p, int32_t nrhs, double rt
   } catch (const mrcm::Error& e) {
     set_error(e.what());
     return e.code;
+  } catch (const std::exception& e) {
+    return fail_std(e);
   }
 }
 
@@ -2145,6 +2169,8 @@ int gmres_batch_create(int32_t restart, mrcm_batch** out) {
   } catch (const mrcm::Error& e) {
     set_error(e.what());
     return e.code;
+  } catch (const std::exception& e) {
+    return fail_std(e);
   }
 }
 
@@ -2198,6 +2224,8 @@ int gmres_batch_add(mrcm_batch* B, mrcm_ctx* c, const double* b, double* p, int3
   } catch (const mrcm::Error& e) {
     set_error(e.what());
     return e.code;
+  } catch (const std::exception& e) {
+    return fail_std(e);
   }
 }
 
@@ -2282,6 +2310,8 @@ int gmres_batch_tick(mrcm_batch* B, int32_t* active) {
   } catch (const mrcm::Error& e) {
     set_error(e.what());
     return e.code;
+  } catch (const std::exception& e) {
+    return fail_std(e);
   }
 }
 
@@ -2311,6 +2341,8 @@ int gmres_batch_poll(mrcm_batch* B, int32_t tag, int32_t* done, mrcm_stats* st) 
   } catch (const mrcm::Error& e) {
     set_error(e.what());
     return e.code;
+  } catch (const std::exception& e) {
+    return fail_std(e);
   }
 }
 
@@ -2346,6 +2378,8 @@ int gmres_batch_remove(mrcm_batch* B, int32_t tag) {
   } catch (const mrcm::Error& e) {
     set_error(e.what());
     return e.code;
+  } catch (const std::exception& e) {
+    return fail_std(e);
   }
 }
 
@@ -2370,6 +2404,8 @@ int mrcm_set_batch(mrcm_ctx* c, int32_t width) {
   } catch (const mrcm::Error& e) {
     set_error(e.what());
     return e.code;
+  } catch (const std::exception& e) {
+    return fail_std(e);
   }
 }
 
@@ -2381,6 +2417,8 @@ int mrcm_set_lanes(mrcm_ctx* c, int32_t lanes) {
   } catch (const mrcm::Error& e) {
     set_error(e.what());
     return e.code;
+  } catch (const std::exception& e) {
+    return fail_std(e);
   }
 }
 
@@ -2438,6 +2476,8 @@ int mrcm_timing_enable(mrcm_ctx* c, int32_t on) {
   } catch (const mrcm::Error& e) {
     set_error(e.what());
     return e.code;
+  } catch (const std::exception& e) {
+    return fail_std(e);
   }
 }
 
@@ -2453,6 +2493,8 @@ int mrcm_timing_read(mrcm_ctx* c, double* ms, int64_t* counts) {
   } catch (const mrcm::Error& e) {
     set_error(e.what());
     return e.code;
+  } catch (const std::exception& e) {
+    return fail_std(e);
   }
 }
 
@@ -2485,6 +2527,8 @@ int mrcm_query(mrcm_ctx* c, int32_t what, double* value) {
   } catch (const mrcm::Error& e) {
     set_error(e.what());
     return e.code;
+  } catch (const std::exception& e) {
+    return fail_std(e);
   }
 }
 

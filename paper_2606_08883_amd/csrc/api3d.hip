@@ -11,6 +11,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <exception>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -152,6 +154,15 @@ int fail3(const mrcm::Error& e) {
   g_err3 = e.what();
   mrcm::set_last_error(g_err3);
   return e.code;
+}
+
+// The return code of an entry point that stopped on an exception other than
+// mrcm::Error: MRCM_ENOMEM for a failed host allocation, else MRCM_EINVAL
+// (no C++ exception leaves the C ABI).
+int fail3_std(const std::exception& e) {
+  if (dynamic_cast<const std::bad_alloc*>(&e))
+    return fail3(mrcm::Error(MRCM_ENOMEM, "host allocation failed"));
+  return fail3(mrcm::Error(MRCM_EINVAL, e.what()));
 }
 
 // Box descriptors and the concatenated factors of a list of boxes.
@@ -409,6 +420,9 @@ int mrcm3d_setup(const mrcm3d_grid* grid, const mrcm3d_params* params, const dou
   } catch (const std::bad_alloc&) {
     delete c;
     return fail3(mrcm::Error(MRCM_ENOMEM, "host allocation failed"));
+  } catch (const std::exception& e) {
+    delete c;
+    return fail3(mrcm::Error(MRCM_EINVAL, e.what()));
   }
 }
 
@@ -425,6 +439,8 @@ int mrcm3d_apply(mrcm3d_ctx* c, const double* r, double* z, void* stream) {
     return MRCM_OK;
   } catch (const mrcm::Error& e) {
     return fail3(e);
+  } catch (const std::exception& e) {
+    return fail3_std(e);
   }
 }
 
@@ -437,6 +453,8 @@ int mrcm3d_op_apply(mrcm3d_ctx* c, const double* x, double* y, void* stream) {
     return MRCM_OK;
   } catch (const mrcm::Error& e) {
     return fail3(e);
+  } catch (const std::exception& e) {
+    return fail3_std(e);
   }
 }
 
@@ -451,6 +469,8 @@ int mrcm3d_rhs(mrcm3d_ctx* c, const double* f_cell, const double* g_bc, double h
     return MRCM_OK;
   } catch (const mrcm::Error& e) {
     return fail3(e);
+  } catch (const std::exception& e) {
+    return fail3_std(e);
   }
 }
 
@@ -574,6 +594,8 @@ int mrcm3d_gmres_solve(mrcm3d_ctx* c, const double* b, double* p, double rtol, i
     return MRCM_OK;
   } catch (const mrcm::Error& e) {
     return fail3(e);
+  } catch (const std::exception& e) {
+    return fail3_std(e);
   }
 }
 
@@ -590,6 +612,8 @@ int mrcm3d_timing_enable(mrcm3d_ctx* c, int32_t on) {
     return MRCM_OK;
   } catch (const mrcm::Error& e) {
     return fail3(e);
+  } catch (const std::exception& e) {
+    return fail3_std(e);
   }
 }
 
@@ -605,6 +629,8 @@ int mrcm3d_timing_read(mrcm3d_ctx* c, double* ms, int64_t* counts) {
     return MRCM_OK;
   } catch (const mrcm::Error& e) {
     return fail3(e);
+  } catch (const std::exception& e) {
+    return fail3_std(e);
   }
 }
 
