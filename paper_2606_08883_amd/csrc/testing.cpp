@@ -6,6 +6,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <exception>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -42,6 +44,10 @@ int mrcm3d_test_host_apply(const mrcm3d_grid* grid, const mrcm3d_params* params,
     return MRCM_OK;
   } catch (const mrcm::Error& e) {
     return fail(e);
+  } catch (const std::bad_alloc&) {
+    return fail(mrcm::Error(MRCM_ENOMEM, "host allocation failed"));
+  } catch (const std::exception& e) {
+    return fail(mrcm::Error(MRCM_EINVAL, e.what()));
   }
 }
 
@@ -71,6 +77,10 @@ int mrcm3d_test_dissection(int32_t mx, int32_t my, int32_t mz, int32_t* elim, in
     return MRCM_OK;
   } catch (const mrcm::Error& e) {
     return fail(e);
+  } catch (const std::bad_alloc&) {
+    return fail(mrcm::Error(MRCM_ENOMEM, "host allocation failed"));
+  } catch (const std::exception& e) {
+    return fail(mrcm::Error(MRCM_EINVAL, e.what()));
   }
 }
 
@@ -92,6 +102,10 @@ int mrcm_test_zero_cell_setup(const mrcm_grid* grid, const mrcm_params* params,
     return MRCM_OK;
   } catch (const mrcm::Error& e) {
     return fail(e);
+  } catch (const std::bad_alloc&) {
+    return fail(mrcm::Error(MRCM_ENOMEM, "host allocation failed"));
+  } catch (const std::exception& e) {
+    return fail(mrcm::Error(MRCM_EINVAL, e.what()));
   }
 }
 
@@ -104,6 +118,10 @@ int mrcm_test_coarse_sizes(const mrcm_grid* grid, const mrcm_params* params, con
     return MRCM_OK;
   } catch (const mrcm::Error& e) {
     return fail(e);
+  } catch (const std::bad_alloc&) {
+    return fail(mrcm::Error(MRCM_ENOMEM, "host allocation failed"));
+  } catch (const std::exception& e) {
+    return fail(mrcm::Error(MRCM_EINVAL, e.what()));
   }
 }
 
@@ -117,6 +135,10 @@ int mrcm_test_coarse_matrix(const mrcm_grid* grid, const mrcm_params* params, co
     return MRCM_OK;
   } catch (const mrcm::Error& e) {
     return fail(e);
+  } catch (const std::bad_alloc&) {
+    return fail(mrcm::Error(MRCM_ENOMEM, "host allocation failed"));
+  } catch (const std::exception& e) {
+    return fail(mrcm::Error(MRCM_EINVAL, e.what()));
   }
 }
 
@@ -223,6 +245,10 @@ int mrcm_test_host_apply(const mrcm_grid* grid, const mrcm_params* params, const
     return MRCM_OK;
   } catch (const mrcm::Error& e) {
     return fail(e);
+  } catch (const std::bad_alloc&) {
+    return fail(mrcm::Error(MRCM_ENOMEM, "host allocation failed"));
+  } catch (const std::exception& e) {
+    return fail(mrcm::Error(MRCM_EINVAL, e.what()));
   }
 }
 
@@ -243,6 +269,10 @@ int mrcm_test_coarse_solve(const mrcm_grid* grid, const mrcm_params* params, con
     return MRCM_OK;
   } catch (const mrcm::Error& e) {
     return fail(e);
+  } catch (const std::bad_alloc&) {
+    return fail(mrcm::Error(MRCM_ENOMEM, "host allocation failed"));
+  } catch (const std::exception& e) {
+    return fail(mrcm::Error(MRCM_EINVAL, e.what()));
   }
 }
 
