@@ -6,7 +6,9 @@ size) is done, so the scheduling rules can be checked without a GPU: slots
 and the memory budget are never exceeded, requests are admitted in arrival
 order and no earlier than their arrival, and a request that arrives while a
 long one is in flight joins the batch and finishes without waiting for the
-long one.
+long one.  A backend that releases finished requests later (as the GPU
+backend releases its contexts on a background thread) has every release
+done when run() returns.
 """
 import time
 
@@ -117,3 +119,40 @@ def test_request_larger_than_budget_is_rejected():
     s = Server(FakeBackend(), max_active=2, mem_budget=10, footprint=fp)
     with pytest.raises(ValueError):
         s.run([Request(0, 128, 2.0, 0, 0, 1, 0.0)])
+
+
+class ReleasingBackend(FakeBackend):
+    """FakeBackend whose finished requests are released later, as the GPU
+    backend releases its contexts on a background thread: poll() only queues
+    the release, flush() performs the queued ones."""
+
+    def __init__(self):
+        super().__init__()
+        self.queued, self.released, self.flushes = [], [], 0
+
+    def poll(self, h):
+        out = super().poll(h)
+        if out is not None:
+            self.queued.append(h["req"].rid)
+        return out
+
+    def flush(self):
+        self.flushes += 1
+        self.released += self.queued
+        self.queued = []
+
+
+def test_run_waits_for_the_backends_releases():
+    backend = ReleasingBackend()
+    reqs = make_requests(6, sizes=(128, 256), rate=None, seed=3)
+    res = Server(backend, max_active=3, footprint=fp).run(reqs, realtime=False)
+    assert backend.flushes == 1
+    assert backend.queued == []
+    assert sorted(backend.released) == sorted(r.rid for r in reqs)
+    assert all(r.converged for r in res)
+
+
+def test_backend_without_flush_is_served():
+    res = Server(FakeBackend(), max_active=2, footprint=fp).run(
+        make_requests(3, sizes=(128,), rate=None, seed=1), realtime=False)
+    assert len(res) == 3
