@@ -1,4 +1,5 @@
-"""The profile summary tools on small synthetic rocprofv3 CSV files (CPU)."""
+"""The profile summary tools on small synthetic rocprofv3 CSV files, and the
+bench's lookup of recorded traffic (CPU)."""
 import csv
 import json
 
@@ -81,3 +82,24 @@ def test_trace_levels_usage_and_missing_trace(tmp_path, capsys):
     capsys.readouterr()
     assert TL.main(["trace_levels", str(tmp_path)]) == 1
     assert "no kernel_trace.csv" in capsys.readouterr().err
+
+
+def test_bench_reads_recorded_traffic_only_for_current_sources(tmp_path, monkeypatch):
+    import bench
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+
+    def write(source, precision=1):
+        (prof / "k_patch_large4096_traffic.txt").write_text(
+            "summary text\n  indented: ignored\nkernel: k_patch\nworkload: large4096\n"
+            f"precision: {precision}\nsource_sha256_16: {source}\n"
+            "traffic_bytes_per_launch: 123456\n")
+
+    assert bench.recorded_traffic("k_patch", "large4096", 1) is None  # no summary
+    write(PS.kernel_source_hash())
+    assert bench.recorded_traffic("k_patch", "large4096", 1) == 123456
+    assert bench.recorded_traffic("k_patch", "large4096", 2) is None  # other precision
+    assert bench.recorded_traffic("k_local", "large4096", 1) is None  # other kernel
+    write("0" * 16)
+    assert bench.recorded_traffic("k_patch", "large4096", 1) is None  # stale sources
